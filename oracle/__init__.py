@@ -1,0 +1,240 @@
+"""ctypes front end of the CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Plain FP64 CPU reference of the method of Laidin & Rey (arXiv 2502.02704):
+lifting and projection (Section 2.1, 3.3), IMEX upwind/BGK fine propagator
+(Section 3.1), Rusanov Euler coarse propagator (Section 3.2), optimised
+parareal (Algorithm 2) and the adjoint of the fine propagator.
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  It shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+OK = 0
+E_INVALID = -1
+E_NONPHYSICAL = -2
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"oracle {where} failed with status {code}")
+        self.code = code
+
+
+class _Problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nv", C.c_int32 * 3),
+                ("x_lo", C.c_double), ("x_hi", C.c_double),
+                ("v_lo", C.c_double * 3), ("v_hi", C.c_double * 3),
+                ("bc", C.c_int32), ("eps", C.c_double), ("cfl", C.c_double),
+                ("sound_gamma", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER(_Problem)
+        D = C.POINTER(C.c_double)
+        I = C.POINTER(C.c_int32)
+        sig = {
+            "bgk_oracle_n_steps": [P, C.c_double, I, D],
+            "bgk_oracle_lift": [P, D, D],
+            "bgk_oracle_moments": [P, D, D, D],
+            "bgk_oracle_transport": [P, D, C.c_double, D],
+            "bgk_oracle_relax": [P, D, C.c_double, D],
+            "bgk_oracle_fine_steps": [P, D, D, C.c_double, C.c_int32],
+            "bgk_oracle_fine_step": [P, D, D, C.c_double, I],
+            "bgk_oracle_fine_propagate_moments": [P, D, D, C.c_double],
+            "bgk_oracle_euler_coarse_step": [P, D, D, C.c_double, I],
+            "bgk_oracle_parareal_iterate": [P, D, C.c_int32, C.c_double, C.c_int32,
+                                            C.c_double, D, D, I],
+            "bgk_oracle_serial_fine": [P, D, C.c_int32, C.c_double, D],
+            "bgk_oracle_fine_adjoint": [P, D, C.c_int32, C.c_int32, C.c_double, D,
+                                        D, D],
+            "bgk_oracle_lift_adjoint_rho": [P, D, D, D],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.bgk_oracle_set_threads.argtypes = [C.c_int]
+        L.bgk_oracle_set_threads.restype = None
+        L.bgk_oracle_get_threads.argtypes = []
+        L.bgk_oracle_get_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _prob(p) -> _Problem:
+    s = _Problem()
+    s.nx = int(p.nx)
+    for a in range(3):
+        s.nv[a] = int(p.nv[a])
+        s.v_lo[a] = float(p.v_lo[a])
+        s.v_hi[a] = float(p.v_hi[a])
+    s.x_lo, s.x_hi = float(p.x_lo), float(p.x_hi)
+    s.bc = int(p.bc)
+    s.eps = float(p.eps)
+    s.cfl = float(p.cfl)
+    s.sound_gamma = float(p.sound_gamma)
+    return s
+
+
+def _d(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _arr(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _chk(rc, where):
+    if rc != OK:
+        raise OracleError(rc, where)
+
+
+def set_threads(n: int) -> None:
+    lib().bgk_oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().bgk_oracle_get_threads())
+
+
+def n_steps(p, t_span: float):
+    n = C.c_int32()
+    dt = C.c_double()
+    _chk(lib().bgk_oracle_n_steps(C.byref(_prob(p)), t_span, C.byref(n),
+                                  C.byref(dt)), "n_steps")
+    return n.value, dt.value
+
+
+def lift(p, W) -> np.ndarray:
+    W = _arr(W)
+    f = np.empty((p.nx, p.nv[0] * p.nv[1] * p.nv[2]))
+    _chk(lib().bgk_oracle_lift(C.byref(_prob(p)), _d(W), _d(f)), "lift")
+    return f
+
+
+def moments(p, f):
+    f = _arr(f)
+    V = np.empty((p.nx, 5))
+    W = np.empty((p.nx, 5))
+    _chk(lib().bgk_oracle_moments(C.byref(_prob(p)), _d(f), _d(V), _d(W)),
+         "moments")
+    return V, W
+
+
+def transport(p, f, dt: float) -> np.ndarray:
+    f = _arr(f)
+    out = np.empty_like(f)
+    _chk(lib().bgk_oracle_transport(C.byref(_prob(p)), _d(f), dt, _d(out)),
+         "transport")
+    return out
+
+
+def relax(p, f_star, dt: float) -> np.ndarray:
+    f_star = _arr(f_star)
+    out = np.empty_like(f_star)
+    _chk(lib().bgk_oracle_relax(C.byref(_prob(p)), _d(f_star), dt, _d(out)),
+         "relax")
+    return out
+
+
+def fine_steps(p, f, dt: float, n: int) -> np.ndarray:
+    f = _arr(f)
+    out = np.empty_like(f)
+    _chk(lib().bgk_oracle_fine_steps(C.byref(_prob(p)), _d(f), _d(out), dt, n),
+         "fine_steps")
+    return out
+
+
+def fine_step(p, f, t_span: float):
+    f = _arr(f)
+    out = np.empty_like(f)
+    n = C.c_int32()
+    _chk(lib().bgk_oracle_fine_step(C.byref(_prob(p)), _d(f), _d(out), t_span,
+                                    C.byref(n)), "fine_step")
+    return out, n.value
+
+
+def fine_propagate_moments(p, V, t_span: float) -> np.ndarray:
+    V = _arr(V)
+    out = np.empty_like(V)
+    _chk(lib().bgk_oracle_fine_propagate_moments(C.byref(_prob(p)), _d(V),
+                                                 _d(out), t_span), "PFL")
+    return out
+
+
+def euler_coarse_step(p, V, t_span: float):
+    V = _arr(V)
+    out = np.empty_like(V)
+    n = C.c_int32()
+    _chk(lib().bgk_oracle_euler_coarse_step(C.byref(_prob(p)), _d(V), _d(out),
+                                            t_span, C.byref(n)), "euler")
+    return out, n.value
+
+
+def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float):
+    W0 = _arr(W0)
+    V = np.empty((n_slices + 1, p.nx, 5))
+    err = np.zeros(max(k_max, 1))
+    kd = C.c_int32()
+    _chk(lib().bgk_oracle_parareal_iterate(C.byref(_prob(p)), _d(W0), n_slices,
+                                           T, k_max, tol, _d(V), _d(err),
+                                           C.byref(kd)), "parareal")
+    return V, err[:kd.value].copy(), kd.value
+
+
+def serial_fine(p, W0, n_slices: int, T: float) -> np.ndarray:
+    W0 = _arr(W0)
+    V = np.empty((n_slices + 1, p.nx, 5))
+    _chk(lib().bgk_oracle_serial_fine(C.byref(_prob(p)), _d(W0), n_slices, T,
+                                      _d(V)), "serial_fine")
+    return V
+
+
+def fine_adjoint(p, f_ckpt, ckpt_every: int, n: int, dt: float, fbar_T):
+    f_ckpt = _arr(f_ckpt)
+    fbar_T = _arr(fbar_T)
+    fbar0 = np.empty_like(fbar_T)
+    dle = C.c_double(0.0)
+    _chk(lib().bgk_oracle_fine_adjoint(C.byref(_prob(p)), _d(f_ckpt), ckpt_every,
+                                       n, dt, _d(fbar_T), _d(fbar0),
+                                       C.byref(dle)), "fine_adjoint")
+    return fbar0, dle.value
+
+
+def lift_adjoint_rho(p, W, fbar) -> np.ndarray:
+    W = _arr(W)
+    fbar = _arr(fbar)
+    out = np.empty(p.nx)
+    _chk(lib().bgk_oracle_lift_adjoint_rho(C.byref(_prob(p)), _d(W), _d(fbar),
+                                           _d(out)), "lift_adjoint_rho")
+    return out
+
+
+def checkpoints(p, f0, dt: float, n: int, every: int) -> np.ndarray:
+    """Forward states at steps 0, every, 2*every, ... (< n)."""
+    f = _arr(f0)
+    out = []
+    for s in range(0, n, every):
+        out.append(f.copy())
+        m = min(every, n - s)
+        f = fine_steps(p, f, dt, m)
+    return np.stack(out), f

@@ -1,0 +1,87 @@
+"""Independent vectorised numpy re-derivation of one IMEX fine step and one
+Rusanov Euler substep, used only as a brute-force cross-check of the C oracle
+on tiny grids.  Written from the paper's Section 3.1-3.3 definitions without
+looking at the oracle's loops: whole-array operations, moments by tensor
+contraction, Maxwellian by broadcasting, ghost cells by np.pad / np.roll.
+"""
+import numpy as np
+
+
+def axes(p):
+    out = []
+    for a in range(3):
+        dv = (p.v_hi[a] - p.v_lo[a]) / p.nv[a]
+        out.append(p.v_lo[a] + dv * (np.arange(p.nv[a]) + 0.5))
+    return out
+
+
+def vgrid(p):
+    vx, vy, vz = axes(p)
+    VX, VY, VZ = np.meshgrid(vx, vy, vz, indexing="ij")
+    return VX.ravel(), VY.ravel(), VZ.ravel()
+
+
+def dv3(p):
+    return np.prod([(p.v_hi[a] - p.v_lo[a]) / p.nv[a] for a in range(3)])
+
+
+def maxwell(p, rho, u, th):
+    VX, VY, VZ = vgrid(p)
+    d2 = ((VX[None] - u[:, 0:1]) ** 2 + (VY[None] - u[:, 1:2]) ** 2 +
+          (VZ[None] - u[:, 2:3]) ** 2)
+    return rho[:, None] * np.exp(-d2 / (2 * th[:, None])) / (2 * np.pi * th[:, None]) ** 1.5
+
+
+def prim(p, f):
+    VX, VY, VZ = vgrid(p)
+    w = dv3(p)
+    rho = f.sum(1) * w
+    u = np.stack([(f * VX).sum(1), (f * VY).sum(1), (f * VZ).sum(1)], 1) * w / rho[:, None]
+    c2 = ((VX[None] - u[:, 0:1]) ** 2 + (VY[None] - u[:, 1:2]) ** 2 +
+          (VZ[None] - u[:, 2:3]) ** 2)
+    th = (c2 * f).sum(1) * w / (3 * rho)
+    return rho, u, th
+
+
+def transport(p, f, dt):
+    VX, _, _ = vgrid(p)
+    if p.bc == 1:
+        fl = np.roll(f, 1, axis=0)
+        fr = np.roll(f, -1, axis=0)
+    else:
+        fp = np.pad(f, ((1, 1), (0, 0)), mode="edge")
+        fl, fr = fp[:-2], fp[2:]
+    dx = (p.x_hi - p.x_lo) / p.nx
+    up = np.where(VX > 0, VX, 0.0)[None]
+    um = np.where(VX < 0, VX, 0.0)[None]
+    flux_r = up * f + um * fr
+    flux_l = up * fl + um * f
+    return f - dt / dx * (flux_r - flux_l)
+
+
+def step(p, f, dt):
+    g = transport(p, f, dt)
+    rho, u, th = prim(p, g)
+    M = maxwell(p, rho, u, th)
+    lam = dt / p.eps
+    return (g + lam * M) / (1 + lam)
+
+
+def euler_substep(p, V, dt):
+    rho = V[:, 0]
+    u = V[:, 1:4] / rho[:, None]
+    th = (2 * V[:, 4] / rho - (u ** 2).sum(1)) / 3
+    pr = rho * th
+    h = np.stack([rho * u[:, 0], rho * u[:, 0] ** 2 + pr, rho * u[:, 0] * u[:, 1],
+                  rho * u[:, 0] * u[:, 2], u[:, 0] * (V[:, 4] + pr)], 1)
+    s = np.abs(u[:, 0]) + np.sqrt(p.sound_gamma * th)
+    if p.bc == 1:
+        idxL = np.arange(-1, p.nx) % p.nx
+        idxR = np.arange(0, p.nx + 1) % p.nx
+    else:
+        idxL = np.clip(np.arange(-1, p.nx), 0, p.nx - 1)
+        idxR = np.clip(np.arange(0, p.nx + 1), 0, p.nx - 1)
+    S = np.maximum(s[idxL], s[idxR])[:, None]
+    H = 0.5 * (h[idxL] + h[idxR]) - 0.5 * S * (V[idxR] - V[idxL])
+    dx = (p.x_hi - p.x_lo) / p.nx
+    return V - dt / dx * (H[1:] - H[:-1]), s.max()

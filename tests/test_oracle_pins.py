@@ -1,0 +1,589 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test states the fact it checks; none retypes the oracle's formula.  The
+paper prints no worked values for the E = 0 path (its figures are absent and
+its tables time the E != 0 test), so the pins are closed forms, invariants,
+special cases and brute force.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import erf
+
+import oracle
+from paper_2502_02704_amd import workloads as wl
+from tests import np_reference as npr
+from tests import riemann_exact
+
+INF = float("inf")
+
+
+def relmax(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+# ------------------------------------------------------------------ P1 ----
+class TestTransport:
+    """Upwind transport in x (Section 3.1 fluxes)."""
+
+    def test_fourier_mode_amplification(self):
+        # Periodic, no relaxation: each velocity's Fourier mode is multiplied by
+        # the upwind amplification factor 1 - nu (1 - e^{-i k dx}) for nu > 0 and
+        # 1 - nu (e^{i k dx} - 1) for nu < 0 (von Neumann analysis).
+        p = wl.small_problem(nx=32, nv=(6, 2, 2), bc=wl.BC_PERIODIC, eps=INF, L=3.0)
+        x = p.x_centres()
+        dx = 1.0 / p.nx
+        vx = npr.axes(p)[0]
+        dt = 0.4 * dx / np.max(np.abs(vx))
+        for m in (1, 3, 7):
+            kappa = 2 * np.pi * m
+            f = np.zeros((p.nx, p.nv3))
+            f[:] = np.cos(kappa * x)[:, None] + 2.0
+            out = oracle.transport(p, f, dt)
+            VX = npr.vgrid(p)[0]
+            for j in range(p.nv3):
+                nu = VX[j] * dt / dx
+                if nu > 0:
+                    g = 1 - nu * (1 - np.exp(-1j * kappa * dx))
+                else:
+                    g = 1 - nu * (np.exp(1j * kappa * dx) - 1)
+                expect = np.real(g * np.exp(1j * kappa * x)) + 2.0
+                assert np.max(np.abs(out[:, j] - expect)) < 1e-14
+
+    @pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_PERIODIC])
+    def test_courant_one_is_exact_shift(self, bc):
+        # Nv=2 on [-2,2] gives v_x = +-1; with dt = dx the Courant number is 1
+        # and the scheme is an exact one-cell shift.  Values in [1,2) make every
+        # difference exact (Sterbenz), so the shift is bitwise.
+        p = wl.Problem(nx=16, nv=(2, 1, 1), v_lo=(-2, -1, -1), v_hi=(2, 1, 1),
+                       bc=bc, eps=INF)
+        rng = np.random.default_rng(1)
+        f = rng.uniform(1.0, 2.0, size=(p.nx, 2))
+        dt = 1.0 / p.nx
+        out = oracle.transport(p, f, dt)
+        # j=0: v_x=-1 moves left; j=1: v_x=+1 moves right
+        if bc == wl.BC_PERIODIC:
+            exp_neg = np.roll(f[:, 0], -1)
+            exp_pos = np.roll(f[:, 1], 1)
+        else:
+            exp_neg = np.concatenate([f[1:, 0], f[-1:, 0]])
+            exp_pos = np.concatenate([f[:1, 1], f[:-1, 1]])
+        assert np.array_equal(out[:, 0], exp_neg)
+        assert np.array_equal(out[:, 1], exp_pos)
+
+    def test_periodic_telescoping(self):
+        p = wl.small_problem(nx=24, nv=(5, 3, 2), bc=wl.BC_PERIODIC, eps=INF)
+        f = wl.random_f(p, 7)
+        out = oracle.transport(p, f, 1e-3)
+        assert np.allclose(out.sum(0), f.sum(0), rtol=1e-14, atol=0)
+
+
+# ------------------------------------------------------------------ P2 ----
+class TestLiftMoments:
+    """Lifting (Definition 2) and projection (Definition 1) on the grid."""
+
+    def test_moments_of_resolved_maxwellian(self):
+        # Delta v = 0.5 and theta ~ 1: the Poisson-summation defect of the
+        # midpoint rule is ~exp(-2 pi^2 theta / dv^2) ~ 1e-34 and the truncation
+        # tail ~exp(-(L-|u|)^2/(2 theta)) ~ 1e-26, so the discrete moments of the
+        # discrete Maxwellian equal its parameters to roundoff.
+        p = wl.Problem(nx=3, nv=(48, 48, 48), v_lo=(-12,) * 3, v_hi=(12,) * 3)
+        W = np.array([[1.7, 0.3, -0.2, 0.1, 1.0],
+                      [0.4, -0.5, 0.0, 0.25, 1.3],
+                      [2.0, 0.0, 0.0, 0.0, 0.9]])
+        V, Wo = oracle.moments(p, oracle.lift(p, W))
+        assert np.max(np.abs(Wo - W)) < 1e-13
+        E = 0.5 * W[:, 0] * (W[:, 1:4] ** 2).sum(1) + 1.5 * W[:, 0] * W[:, 4]
+        assert np.max(np.abs(V[:, 4] - E)) < 1e-13
+
+    def test_quadrature_defect_bound_sod_right_state(self):
+        # Sod right state on 16^3 / [-8,8]^3 (Delta v = 1): the defect obeys
+        # the midpoint-rule Poisson-summation bound 2 exp(-2 pi^2 theta/dv^2)
+        # per axis (theta=0.8: 2.8e-7 relative per axis in rho).
+        p = wl.Problem(nx=2, nv=(16, 16, 16))
+        W = np.array([wl.SOD_RIGHT, wl.SOD_LEFT], dtype=float)
+        _, Wo = oracle.moments(p, oracle.lift(p, W))
+        for r in range(2):
+            bound = 3 * 2 * math.exp(-2 * math.pi ** 2 * W[r, 4] / 1.0)
+            assert abs(Wo[r, 0] / W[r, 0] - 1) < bound
+            assert abs(Wo[r, 0] / W[r, 0] - 1) > bound / 100  # it is really there
+        # and theta is off by the same exponentially small order
+        assert abs(Wo[0, 4] / W[0, 4] - 1) < 50 * 2 * math.exp(-2 * math.pi ** 2 * 0.8)
+
+    def test_two_beam_moments(self):
+        # Section 5.3 initial data M(1, +e_x, 1) + M(1, -e_x, 1): by hand its
+        # moments are rho = 2, u = 0, theta = (1/6) * 2 * (3 + 1) = 4/3.
+        p = wl.Problem(nx=2, nv=(32, 32, 32))
+        f = (oracle.lift(p, [[1, 1, 0, 0, 1]] * 2) + oracle.lift(p, [[1, -1, 0, 0, 1]] * 2))
+        _, W = oracle.moments(p, f)
+        gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden",
+                                       "two_beam_moments.txt"))
+        # truncation of the box at |v| = 8 costs ~exp(-(8-1)^2/2) ~ 2e-11
+        assert abs(W[0, 0] - gold[0]) < 1e-10
+        assert np.max(np.abs(W[0, 1:4] - gold[1:4])) < 1e-13
+        assert abs(W[0, 4] - gold[4]) < 1e-9
+
+    def test_maxwellian_peak_and_symmetry(self):
+        # At v = u the Maxwellian equals rho (2 pi theta)^{-3/2}; it is even
+        # in v - u.  u is put on a cell centre (v = 0.5 with dv = 1).
+        p = wl.Problem(nx=2, nv=(16, 16, 16))
+        rho, th = 0.7, 1.3
+        f = oracle.lift(p, [[rho, 0.5, 0.5, 0.5, th]] * 2)[0].reshape(16, 16, 16)
+        assert abs(f[8, 8, 8] - rho * (2 * math.pi * th) ** -1.5) < 1e-16
+        g = f[1:, 1:, 1:]  # symmetric window around index 8: 1..15
+        assert np.allclose(g, g[::-1, ::-1, ::-1], rtol=1e-14, atol=0)
+
+    def test_nonphysical_rejected(self):
+        p = wl.small_problem(nx=2)
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.lift(p, [[1, 0, 0, 0, 1], [0.0, 0, 0, 0, 1]])
+        assert e.value.code == oracle.E_NONPHYSICAL
+        with pytest.raises(oracle.OracleError):
+            oracle.lift(p, [[1, 0, 0, 0, -1], [1, 0, 0, 0, 1]])
+        f = wl.random_f(p, 3)
+        f[1, 5] = np.nan
+        with pytest.raises(oracle.OracleError):
+            oracle.moments(p, f)
+
+
+# ------------------------------------------------------------------ P4 ----
+def _perturbed_maxwellian(p, seed, amp=0.3):
+    rng = np.random.default_rng(seed)
+    W = np.zeros((p.nx, 5))
+    W[:, 0] = rng.uniform(0.5, 1.5, p.nx)
+    W[:, 1:4] = rng.uniform(-0.4, 0.4, (p.nx, 3))
+    W[:, 4] = rng.uniform(0.7, 1.2, p.nx)
+    f = oracle.lift(p, W)
+    return f * (1 + amp * rng.uniform(-1, 1, f.shape))
+
+
+class TestRelaxation:
+    """Implicit BGK step (Section 3.1) and the collision invariants (Section 1)."""
+
+    P = wl.Problem(nx=4, nv=(40, 40, 40), v_lo=(-10,) * 3, v_hi=(10,) * 3)
+
+    @pytest.mark.parametrize("lam", [0.01, 1.0, 100.0])
+    def test_conserves_moments(self, lam):
+        # mass, momentum, energy of f* are kept (conservation property of Q),
+        # here on a grid where the quadrature defect is below roundoff
+        p = self.P
+        fs = _perturbed_maxwellian(p, 5)
+        out = oracle.relax(p, fs, lam * p.eps)
+        V0, _ = oracle.moments(p, fs)
+        V1, _ = oracle.moments(p, out)
+        assert relmax(V1, V0) < 1e-13
+
+    def test_maxwellian_is_fixed_point(self):
+        p = self.P
+        W = np.array([[1, 0.2, 0, -0.1, 1], [0.5, 0, 0.3, 0, 0.8],
+                      [2, -0.3, 0.1, 0.1, 1.1], [1, 0, 0, 0, 1]])
+        M = oracle.lift(p, W)
+        out = oracle.relax(p, M, 1.0)
+        assert relmax(out, M) < 1e-13
+
+    def test_entropy_decreases(self):
+        # sum f log f dv is non-increasing under the relaxation (Section 1)
+        p = self.P
+        fs = _perturbed_maxwellian(p, 9, amp=0.6)
+        H = lambda f: np.sum(f * np.log(f))
+        h0 = H(fs)
+        prev = h0
+        for lam in (0.1, 1.0, 10.0):
+            h = H(oracle.relax(p, fs, lam * p.eps))
+            assert h <= h0 + 1e-12 * abs(h0)
+            assert h <= prev + 1e-12 * abs(h0)  # more relaxation, less entropy
+            prev = h
+
+    def test_infinite_eps_is_identity(self):
+        p = wl.small_problem(nx=3, eps=INF)
+        f = wl.random_f(p, 2)
+        assert np.array_equal(oracle.relax(p, f, 0.1), f)
+
+
+# ------------------------------------------------------------------ P5 ----
+class TestHomogeneous:
+    """Space-homogeneous data: transport vanishes and BGK is a linear ODE."""
+
+    P = wl.Problem(nx=2, nv=(48, 48, 48), v_lo=(-10,) * 3, v_hi=(10,) * 3,
+                   bc=wl.BC_NEUMANN, eps=1e-2)
+
+    def _two_beam(self, p):
+        a = oracle.lift(p, [[1, 1, 0, 0, 1]] * p.nx)
+        b = oracle.lift(p, [[1, -1, 0, 0, 1]] * p.nx)
+        return a + b
+
+    def test_discrete_closed_form(self):
+        # f^n = M + (f^0 - M) (1 + dt/eps)^{-n}, M = M(2, 0, 4/3)
+        p = self.P
+        f0 = self._two_beam(p)
+        M = oracle.lift(p, [[2, 0, 0, 0, 4.0 / 3.0]] * p.nx)
+        dt, n = 2.5e-3, 6
+        out = oracle.fine_steps(p, f0, dt, n)
+        expect = M + (f0 - M) * (1 + dt / p.eps) ** (-n)
+        assert relmax(out, expect) < 1e-12
+
+    def test_first_order_convergence_to_exponential(self):
+        # As dt -> 0 the scheme tends to M + (f0 - M) e^{-t/eps} at first order
+        # (Section 3.1 states first order).
+        p = self.P
+        f0 = self._two_beam(p)
+        M = oracle.lift(p, [[2, 0, 0, 0, 4.0 / 3.0]] * p.nx)
+        t = 1e-2
+        exact = M + (f0 - M) * math.exp(-t / p.eps)
+        errs = []
+        for n in (4, 8, 16):
+            errs.append(relmax(oracle.fine_steps(p, f0, t / n, n), exact))
+        r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+        assert 1.8 < r1 < 2.2 and 1.8 < r2 < 2.2
+
+    def test_transport_of_uniform_field_is_exactly_zero(self):
+        p = self.P
+        f = np.tile(wl.random_f(wl.Problem(nx=1, nv=p.nv), 4), (p.nx, 1))
+        assert np.array_equal(oracle.transport(p, f, 1e-3), f)
+
+
+# ------------------------------------------------------------------ P6 ----
+class TestFullStep:
+    def test_periodic_conservation_and_entropy(self):
+        # Periodic and resolved: total mass, momentum and energy are invariant
+        # up to roundoff and the quadrature defect (~1e-14 here); the discrete
+        # entropy does not increase.
+        wk = wl.c2_smooth_periodic(eps=1e-2, nx=16)
+        p = wk.problem
+        f = oracle.lift(p, wk.W0)
+        n, dt = oracle.n_steps(p, 0.02)
+        totals = lambda f: oracle.moments(p, f)[0].sum(0)
+        H = lambda f: np.sum(f * np.log(f))
+        t0, h0 = totals(f), H(f)
+        g = oracle.fine_steps(p, f, dt, n)
+        t1, h1 = totals(g), H(g)
+        scale = np.array([t0[0], t0[0], t0[0], t0[0], t0[4]])
+        assert np.max(np.abs(t1 - t0) / scale) < 1e-12
+        assert h1 <= h0 + 1e-12 * abs(h0)
+
+    def test_step_count_rule(self):
+        # dt_stab = cfl dx / max|v_x|; exact-integer ratios must not gain a step
+        c1 = wl.c1_sod_small()
+        assert oracle.n_steps(c1.problem, c1.T / c1.n_slices)[0] == 12
+        c3 = wl.c3_sod_large()
+        assert oracle.n_steps(c3.problem, c3.T / c3.n_slices)[0] == 188
+        c2 = wl.c2_smooth_periodic()
+        assert oracle.n_steps(c2.problem, c2.T / c2.n_slices)[0] == 25
+
+
+# ------------------------------------------------------------------ P7 ----
+class TestLimits:
+    def test_fluid_limit_is_kinetic_flux_splitting(self):
+        # eps -> 0: one step maps cellwise Maxwellians to M[P(T f)], i.e. the
+        # moments move by half-range Maxwellian fluxes.  Check (a) against the
+        # half-range fluxes by direct numpy quadrature (roundoff) and (b) those
+        # against the closed-form erf fluxes (midpoint-rule error).
+        p = wl.Problem(nx=6, nv=(48, 48, 48), v_lo=(-10,) * 3, v_hi=(10,) * 3,
+                       bc=wl.BC_PERIODIC, eps=1e-300)
+        rng = np.random.default_rng(11)
+        W = np.column_stack([rng.uniform(0.5, 1.5, 6), rng.uniform(-0.5, 0.5, 6),
+                             np.zeros(6), np.zeros(6), rng.uniform(0.6, 1.2, 6)])
+        f = oracle.lift(p, W)
+        dx = 1 / p.nx
+        dt = 0.3 * dx / 10
+        out = oracle.fine_steps(p, f, dt, 1)
+        V1, _ = oracle.moments(p, out)
+        V0, _ = oracle.moments(p, f)
+        VX, VY, VZ = npr.vgrid(p)
+        w = npr.dv3(p)
+        psi = np.stack([np.ones_like(VX), VX, VY, VZ, 0.5 * (VX**2 + VY**2 + VZ**2)])
+        pos = (VX > 0)
+        Fp = (f[:, None, :] * (VX * pos)[None, None] * psi[None]).sum(-1) * w
+        Fm = (f[:, None, :] * (VX * ~pos)[None, None] * psi[None]).sum(-1) * w
+        flux = Fp + np.roll(Fm, -1, axis=0)      # through face i+1/2
+        expect = V0 - dt / dx * (flux - np.roll(flux, 1, axis=0))
+        assert np.max(np.abs(V1 - expect)) < 1e-13
+        # closed-form half-range mass flux of a Maxwellian through a face
+        rho, ux, th = W[:, 0], W[:, 1], W[:, 4]
+        s = np.sqrt(th / 2)
+        Fp_rho = rho * (0.5 * ux * (1 + erf(ux / (np.sqrt(2) * np.sqrt(th)))) +
+                        np.sqrt(th / (2 * np.pi)) * np.exp(-ux**2 / (2 * th)))
+        Fm_rho = rho * ux - Fp_rho
+        # the half-range integrand has a kink at v_x = 0 (a cell face here), so
+        # the midpoint rule is second order there: error O(dv^2)
+        dv = 20.0 / 48
+        assert np.max(np.abs(Fp[:, 0] - Fp_rho)) < 0.05 * dv ** 2
+        assert np.max(np.abs(Fm[:, 0] - Fm_rho)) < 0.05 * dv ** 2
+        del s
+
+    def test_free_transport_limit(self):
+        # eps = inf: the fine propagator is n applications of the transport
+        p = wl.small_problem(nx=10, bc=wl.BC_PERIODIC, eps=INF)
+        f = wl.random_f(p, 12)
+        g = f
+        for _ in range(3):
+            g = oracle.transport(p, g, 1e-3)
+        assert np.array_equal(oracle.fine_steps(p, f, 1e-3, 3), g)
+
+
+# ------------------------------------------------------------------ P8 ----
+class TestCoarse:
+    """Rusanov finite volumes for the Euler equations (Section 3.2)."""
+
+    @pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_PERIODIC])
+    def test_constant_state_preserved_exactly(self, bc):
+        p = wl.small_problem(nx=16, bc=bc)
+        V = np.tile([1.3, 0.2, -0.1, 0.05, 2.1], (16, 1))
+        out, n = oracle.euler_coarse_step(p, V, 0.05)
+        assert n >= 1 and np.array_equal(out, V)
+
+    def test_periodic_totals_conserved(self):
+        p = wl.small_problem(nx=64, bc=wl.BC_PERIODIC)
+        x = p.x_centres()
+        W = np.column_stack([1 + 0.3 * np.sin(2 * np.pi * x), 0.2 * np.cos(2 * np.pi * x),
+                             0 * x, 0.1 + 0 * x, 1 + 0.2 * np.sin(4 * np.pi * x)])
+        V = np.column_stack([W[:, 0], W[:, 0] * W[:, 1], W[:, 0] * W[:, 2],
+                             W[:, 0] * W[:, 3],
+                             0.5 * W[:, 0] * (W[:, 1:4]**2).sum(1) + 1.5 * W[:, 0] * W[:, 4]])
+        out, n = oracle.euler_coarse_step(p, V, 0.1)
+        assert n > 5
+        assert np.max(np.abs(out.sum(0) - V.sum(0))) < 1e-12
+
+    def test_sod_converges_to_exact_riemann_solution(self):
+        # gamma = 5/3 is the monatomic gas of the Euler limit (E = rho|u|^2/2 +
+        # 3/2 rho theta); the first-order Rusanov solution converges in L1 to
+        # the exact Riemann solution as dx -> 0.
+        T = 0.15
+        L = (1.0, 0.0, 1.0)
+        R = (0.125, 0.0, 0.125 * 0.8)
+        errs = []
+        for nx in (100, 200, 400, 800):
+            p = wl.Problem(nx=nx, nv=(2, 2, 2), bc=wl.BC_NEUMANN,
+                           sound_gamma=5.0 / 3.0)
+            W0 = wl.riemann_W0(p, wl.SOD_LEFT, wl.SOD_RIGHT)
+            V0 = np.column_stack([W0[:, 0], 0 * W0[:, 0], 0 * W0[:, 0], 0 * W0[:, 0],
+                                  1.5 * W0[:, 0] * W0[:, 4]])
+            out, _ = oracle.euler_coarse_step(p, V0, T)
+            x = p.x_centres()
+            ex = riemann_exact.sample(L, R, 5.0 / 3.0, (x - 0.5) / T)
+            errs.append(np.mean(np.abs(out[:, 0] - ex[:, 0])))
+        assert errs[-1] < 0.01
+        assert all(errs[i + 1] < 0.8 * errs[i] for i in range(len(errs) - 1))
+
+    def test_matches_numpy_substeps(self):
+        p = wl.small_problem(nx=12, bc=wl.BC_NEUMANN)
+        W0 = wl.riemann_W0(p, wl.SOD_LEFT, wl.SOD_RIGHT)
+        V = np.column_stack([W0[:, 0], 0 * W0[:, 0], 0 * W0[:, 0], 0 * W0[:, 0],
+                             1.5 * W0[:, 0] * W0[:, 4]])
+        span = 0.03
+        out, n = oracle.euler_coarse_step(p, V, span)
+        t, Vn, cnt = 0.0, V.copy(), 0
+        dx = 1 / p.nx
+        while span - t > 1e-14 * span:
+            _, smax = npr.euler_substep(p, Vn, 0.0)
+            dt = min(p.cfl * dx / smax, span - t)
+            Vn, _ = npr.euler_substep(p, Vn, dt)
+            t += dt
+            cnt += 1
+        assert cnt == n
+        assert np.max(np.abs(out - Vn)) < 1e-14
+
+
+# ------------------------------------------------------------------ P9 ----
+class TestParareal:
+    """Algorithm 2 and its frozen-prefix property (Section 2.2)."""
+
+    @staticmethod
+    def _case():
+        p = wl.Problem(nx=12, nv=(8, 8, 8), v_lo=(-6,) * 3, v_hi=(6,) * 3,
+                       bc=wl.BC_NEUMANN, eps=1e-2)
+        return p, wl.riemann_W0(p, wl.SOD_LEFT, wl.SOD_RIGHT)
+
+    def test_k_equals_n_reproduces_serial_fine(self):
+        p, W0 = self._case()
+        N, T = 4, 0.04
+        ref = oracle.serial_fine(p, W0, N, T)
+        V, err, kd = oracle.parareal_iterate(p, W0, N, T, N, 0.0)
+        assert kd == N
+        assert np.max(np.abs(V - ref)) < 1e-13
+
+    def test_frozen_prefix_and_decreasing_error(self):
+        p, W0 = self._case()
+        N, T = 6, 0.06
+        ref = oracle.serial_fine(p, W0, N, T)
+        for k in (1, 2, 3):
+            V, err, kd = oracle.parareal_iterate(p, W0, N, T, k, 0.0)
+            assert kd == k
+            # slices 0..k are exact after k iterations
+            assert np.max(np.abs(V[:k + 1] - ref[:k + 1])) < 1e-13
+            assert np.max(np.abs(V[k + 1:] - ref[k + 1:])) > 1e-9
+        V, err, kd = oracle.parareal_iterate(p, W0, N, T, 5, 0.0)
+        assert all(err[i + 1] < err[i] for i in range(len(err) - 1))
+
+    def test_error_history_is_successive_difference(self):
+        p, W0 = self._case()
+        N, T = 5, 0.05
+        prev = None
+        Vs = []
+        for k in range(0, 4):
+            V, err, kd = oracle.parareal_iterate(p, W0, N, T, k, 0.0)
+            Vs.append(V)
+        for k in range(1, 4):
+            assert abs(err[k - 1] - np.max(np.abs(Vs[k] - Vs[k - 1]))) < 1e-15
+        del prev
+
+    def test_tolerance_stops_early(self):
+        p, W0 = self._case()
+        V, err, kd = oracle.parareal_iterate(p, W0, 6, 0.06, 6, 1e30)
+        assert kd == 1
+
+    def test_coarse_initial_guess(self):
+        p, W0 = self._case()
+        V, err, kd = oracle.parareal_iterate(p, W0, 3, 0.03, 0, 0.0)
+        V0 = V[0]
+        G1, _ = oracle.euler_coarse_step(p, V0, 0.01)
+        assert np.array_equal(V[1], G1)
+
+
+# ----------------------------------------------------------------- P10 ----
+class TestAdjoint:
+    @staticmethod
+    def _case(eps=1e-2, bc=wl.BC_PERIODIC, nx=6, nv=(4, 4, 4)):
+        p = wl.Problem(nx=nx, nv=nv, v_lo=(-5,) * 3, v_hi=(5,) * 3, bc=bc, eps=eps)
+        rng = np.random.default_rng(21)
+        W = np.column_stack([rng.uniform(0.6, 1.4, nx), rng.uniform(-0.3, 0.3, (nx, 3)),
+                             rng.uniform(0.8, 1.2, nx)])
+        f0 = oracle.lift(p, W) * (1 + 0.2 * rng.uniform(-1, 1, (nx, p.nv3)))
+        return p, f0, rng
+
+    @pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_PERIODIC])
+    def test_dot_product_vs_central_differences(self, bc):
+        # <J d, w> by central finite differences of the forward map equals
+        # <d, J^T w> from the adjoint
+        p, f0, rng = self._case(bc=bc)
+        dt, n = 2e-3, 5
+        ck, fT = oracle.checkpoints(p, f0, dt, n, 2)
+        w = rng.standard_normal(f0.shape)
+        fbar0, _ = oracle.fine_adjoint(p, ck, 2, n, dt, w)
+        for trial in range(3):
+            d = rng.standard_normal(f0.shape) * f0
+            h = 1e-4
+            jp = oracle.fine_steps(p, f0 + h * d, dt, n)
+            jm = oracle.fine_steps(p, f0 - h * d, dt, n)
+            lhs = np.sum((jp - jm) / (2 * h) * w)
+            rhs = np.sum(d * fbar0)
+            assert abs(lhs - rhs) < 1e-7 * abs(rhs) + 1e-12
+
+    def test_free_transport_adjoint_is_matrix_transpose(self):
+        # eps = inf: the step is the linear upwind map; its adjoint is the
+        # transpose of the dense matrix assembled column by column.
+        p, f0, rng = self._case(eps=INF, bc=wl.BC_NEUMANN, nx=4, nv=(2, 2, 2))
+        dt = 0.05
+        N = f0.size
+        A = np.zeros((N, N))
+        for c in range(N):
+            e = np.zeros(N)
+            e[c] = 1.0
+            A[:, c] = oracle.transport(p, e.reshape(f0.shape), dt).ravel()
+        w = rng.standard_normal(f0.shape)
+        fbar0, dle = oracle.fine_adjoint(p, f0[None], 1, 1, dt, w)
+        assert np.max(np.abs(fbar0.ravel() - A.T @ w.ravel())) < 1e-14
+        assert dle == 0.0
+
+    def test_dense_jacobian_tiny(self):
+        # Nx=4, Nv=2: every row of J^T against central differences
+        p, f0, rng = self._case(nx=4, nv=(2, 2, 2), bc=wl.BC_NEUMANN)
+        dt = 0.01
+        N = f0.size
+        J = np.zeros((N, N))
+        h = 1e-6
+        for c in range(N):
+            e = np.zeros(N)
+            e[c] = h * f0.ravel()[c]
+            jp = oracle.fine_steps(p, f0 + e.reshape(f0.shape), dt, 1)
+            jm = oracle.fine_steps(p, f0 - e.reshape(f0.shape), dt, 1)
+            J[:, c] = ((jp - jm) / (2 * e[c])).ravel()
+        for r in range(N):
+            w = np.zeros(N)
+            w[r] = 1.0
+            row, _ = oracle.fine_adjoint(p, f0[None], 1, 1, dt, w.reshape(f0.shape))
+            assert np.max(np.abs(row.ravel() - J[r])) < 1e-6 * max(1, np.max(np.abs(J[r])))
+
+    def test_log_eps_gradient_vs_central_differences(self):
+        p, f0, rng = self._case()
+        dt, n = 2e-3, 6
+        w = rng.standard_normal(f0.shape)
+        ck, _ = oracle.checkpoints(p, f0, dt, n, 4)
+        _, dle = oracle.fine_adjoint(p, ck, 4, n, dt, w)
+        h = 1e-5
+        from dataclasses import replace
+        lp = np.sum(oracle.fine_steps(replace(p, eps=p.eps * math.exp(h)), f0, dt, n) * w)
+        lm = np.sum(oracle.fine_steps(replace(p, eps=p.eps * math.exp(-h)), f0, dt, n) * w)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - dle) < 1e-6 * abs(fd)
+
+    def test_checkpoint_interval_does_not_matter(self):
+        p, f0, rng = self._case()
+        dt, n = 2e-3, 7
+        w = rng.standard_normal(f0.shape)
+        outs = []
+        for every in (1, 3, 7, 10):
+            ck, _ = oracle.checkpoints(p, f0, dt, n, every)
+            outs.append(oracle.fine_adjoint(p, ck, every, n, dt, w))
+        for fb, dle in outs[1:]:
+            assert np.array_equal(fb, outs[0][0]) and dle == outs[0][1]
+
+    def test_lift_adjoint_rho(self):
+        p, f0, rng = self._case()
+        W = np.column_stack([rng.uniform(0.6, 1.4, p.nx), np.zeros((p.nx, 3)),
+                             np.ones(p.nx)])
+        fbar = rng.standard_normal((p.nx, p.nv3))
+        rb = oracle.lift_adjoint_rho(p, W, fbar)
+        h = 1e-6
+        for i in range(p.nx):
+            Wp, Wm = W.copy(), W.copy()
+            Wp[i, 0] += h
+            Wm[i, 0] -= h
+            fd = np.sum((oracle.lift(p, Wp) - oracle.lift(p, Wm)) / (2 * h) * fbar)
+            assert abs(fd - rb[i]) < 1e-8 * max(1, abs(fd))
+
+
+# ----------------------------------------------------------------- P11 ----
+class TestBruteForce:
+    """An independent numpy implementation agrees on tiny grids."""
+
+    @pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_PERIODIC])
+    @pytest.mark.parametrize("nv", [(2, 2, 2), (4, 3, 2), (3, 4, 4)])
+    def test_fine_steps(self, bc, nv):
+        p = wl.Problem(nx=8, nv=nv, v_lo=(-3, -2, -4), v_hi=(3, 2.5, 4), bc=bc,
+                       eps=3e-3)
+        f = wl.random_f(p, 31)
+        dt = 0.01
+        g = f
+        for _ in range(4):
+            g = npr.step(p, g, dt)
+        out = oracle.fine_steps(p, f, dt, 4)
+        assert relmax(out, g) < 1e-14
+
+    def test_lift_and_moments(self):
+        p = wl.Problem(nx=5, nv=(4, 3, 4), v_lo=(-3, -2, -4), v_hi=(3, 2.5, 4))
+        rng = np.random.default_rng(8)
+        W = np.column_stack([rng.uniform(0.5, 2, 5), rng.uniform(-1, 1, (5, 3)),
+                             rng.uniform(0.5, 2, 5)])
+        f = oracle.lift(p, W)
+        assert relmax(f, npr.maxwell(p, W[:, 0], W[:, 1:4], W[:, 4])) < 1e-15
+        _, Wo = oracle.moments(p, f)
+        rho, u, th = npr.prim(p, f)
+        assert relmax(Wo[:, 0], rho) < 1e-15
+        assert np.max(np.abs(Wo[:, 1:4] - u)) < 1e-14
+        assert relmax(Wo[:, 4], th) < 1e-14
+
+
+class TestErrors:
+    def test_invalid_arguments(self):
+        from dataclasses import replace
+        p = wl.small_problem()
+        f = wl.random_f(p, 1)
+        for bad in (replace(p, nx=1), replace(p, eps=0.0), replace(p, eps=float("nan")),
+                    replace(p, cfl=1.5), replace(p, cfl=0.0), replace(p, bc=3),
+                    replace(p, v_lo=(1, 1, 1), v_hi=(1, 1, 1))):
+            with pytest.raises(oracle.OracleError) as e:
+                oracle.transport(bad, f, 1e-3)
+            assert e.value.code == oracle.E_INVALID
