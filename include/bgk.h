@@ -1,0 +1,221 @@
+/*
+ * bgk.h -- C ABI of libbgk.so, the MI355X (gfx950) fine kinetic propagator of
+ * the multiscale kinetic/fluid parareal method for the collisional Vlasov-BGK
+ * equation in the hyperbolic scaling (Laidin & Rey, arXiv 2502.02704).
+ *
+ * Model (Section 1, Section 3.1): 1D in x, 3D in v, alpha = 0, no exterior
+ * force, BGK operator relaxing at rate 1/eps (tau = 1), IMEX scheme with
+ * explicit upwind transport in x and implicit relaxation whose n+1 moments
+ * come from conservation.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers marked [device] are HIP device pointers; [host] are host
+ *    pointers.  The caller owns every array and the workspace.  The library
+ *    never allocates or frees device memory on these calls.
+ *  - Layouts are row-major with the last index fastest:
+ *      f : [nx][nv0][nv1][nv2]  FP64 phase-space cell values (v_z fastest)
+ *      W : [nx][5]  primitive moments (rho, u_x, u_y, u_z, theta)
+ *      V : [nx][5]  conserved moments (rho, rho u_x, rho u_y, rho u_z, E),
+ *                   E = rho |u|^2 / 2 + 3 rho theta / 2 (Section 1).
+ *    A batch of B arrays of one problem is stored back to back.
+ *  - Velocity points are the cell centres v_a(j) = v_lo[a] + (j + 1/2) dv_a of
+ *    a uniform truncated box (Section 3); x cells are uniform on [x_lo, x_hi].
+ *  - `stream` is a hipStream_t (NULL = default stream).  Calls are enqueued on
+ *    it and return without waiting, except where stated.
+ *  - `ws`/`ws_bytes`: caller-owned device workspace of at least
+ *    bgk_workspace_bytes(prob, op, batch) bytes, 256-byte aligned.  A
+ *    workspace may be reused by successive calls on the same stream; calls
+ *    that overlap in time on different streams need separate workspaces.
+ *  - Return value: BGK_OK or a negative status.  Arguments are validated on
+ *    the host before anything is enqueued; then nothing is launched.
+ *    Non-physical states met on the device (rho <= 0, theta <= 0, NaN) raise
+ *    a sticky flag in the workspace; bgk_status() reads and clears it.
+ */
+#ifndef BGK_H
+#define BGK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BGK_OK 0
+#define BGK_E_INVALID (-1)     /* bad argument: null, nx < 2, nv < 1, eps <= 0 or
+                                  NaN, cfl outside (0,1], empty box, aliasing */
+#define BGK_E_NONPHYSICAL (-2) /* rho <= 0, theta <= 0 or NaN met on the device */
+#define BGK_E_WORKSPACE (-3)   /* ws NULL, misaligned or smaller than required */
+#define BGK_E_HIP (-4)         /* a HIP runtime call failed; see bgk_last_error */
+
+/* Problem statement (Section 1 and Section 3): Knudsen number, spatial
+ * domain with its boundary condition, truncated velocity grid.  Must match
+ * the oracle's field order. */
+typedef struct bgk_problem {
+  int32_t nx;          /* x cells, >= 2                                        */
+  int32_t nv[3];       /* velocity cells per axis, 1..256                     */
+  double x_lo, x_hi;   /* spatial domain                                      */
+  double v_lo[3];      /* velocity box per axis                               */
+  double v_hi[3];
+  int32_t bc;          /* 0: Neumann zero-gradient ghost cells, 1: periodic   */
+  double eps;          /* Knudsen number in (0, +inf]; +inf = free transport  */
+  double cfl;          /* Courant number of both propagators, in (0, 1]       */
+  double sound_gamma;  /* coarse sound speed c = sqrt(sound_gamma * theta)    */
+} bgk_problem;
+
+/* Operation selectors for bgk_workspace_bytes. */
+#define BGK_OP_FINE_STEP 0    /* bgk_fine_step / bgk_fine_steps               */
+#define BGK_OP_MOMENTS 1      /* bgk_moments                                   */
+#define BGK_OP_LIFT 2         /* bgk_lift                                      */
+#define BGK_OP_COARSE 3       /* euler_coarse_step                             */
+#define BGK_OP_PROPAGATE 4    /* bgk_fine_propagate_moments (batch = slices)   */
+#define BGK_OP_PARAREAL 5     /* parareal_iterate / bgk_serial_fine (batch =
+                                 number of slices)                             */
+#define BGK_OP_ADJOINT 6      /* bgk_fine_adjoint (batch = ckpt_every)         */
+
+/* Workspace size in bytes for `op` on `prob` with `batch` members (>= 1).
+ * Returns 0 on invalid arguments. */
+size_t bgk_workspace_bytes(const bgk_problem* prob, int32_t op, int32_t batch);
+
+/* Fine step count for a span (Section 2.2, local step rule): dt_stab =
+ * cfl * dx / max_j |v_x(j)|, n = ceil(t_span / dt_stab - 1e-9), dt = t_span/n.
+ * Independent of the data and of eps (the relaxation is implicit).
+ * [host] n_steps, dt. */
+int bgk_n_steps(const bgk_problem* prob, double t_span, int32_t* n_steps,
+                double* dt);
+
+/* Discrete lifting (Definition 2, Section 3.3): f_ij = M[W_i](v_j), the
+ * pointwise Maxwellian rho (2 pi theta)^{-3/2} exp(-|v - u|^2 / (2 theta)).
+ * [device] W [nx][5] primitive, f [nx][nv3] output. */
+int bgk_lift(const bgk_problem* prob, const double* W, double* f, void* ws,
+             size_t ws_bytes, void* stream);
+
+/* Discrete projection (Definition 1, Section 3.3), first-order quadrature:
+ * rho = sum_j f dv^3, rho u = sum_j v f dv^3, E = sum_j |v|^2/2 f dv^3.
+ * [device] f [nx][nv3]; V [nx][5] conserved output (nullable); W [nx][5]
+ * primitive output (nullable), theta = (2E/rho - |u|^2)/3. */
+int bgk_moments(const bgk_problem* prob, const double* f, double* V, double* W,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* n_steps IMEX steps of size dt (Section 3.1):
+ *   f* = f - dt/dx (F_{i+1/2} - F_{i-1/2}),
+ *   F_{i+1/2,j} = max(v_x,0) f_ij + min(v_x,0) f_{i+1,j},
+ *   f^{n+1} = (f* + lambda M[P f*]) / (1 + lambda),  lambda = dt / eps.
+ * Ghost cells per prob->bc.  [device] f_in, f_out [nx][nv3]; they must not
+ * overlap.  n_steps >= 0 (0 copies f_in). */
+int bgk_fine_steps(const bgk_problem* prob, const double* f_in, double* f_out,
+                   double dt, int32_t n_steps, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/* Fine propagator over t_span with the step count of bgk_n_steps.
+ * [host] n_steps_out (nullable). */
+int bgk_fine_step(const bgk_problem* prob, const double* f_in, double* f_out,
+                  double t_span, int32_t* n_steps_out, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* Uneven batch of independent problems in one launch per step: instance q
+ * advances f_in[q] -> f_out[q] by t_span[q] with its own grid, eps and step
+ * count.  [host] probs[n], f_in[n], f_out[n] (arrays of [device] pointers),
+ * t_span[n], n_steps_out[n] (nullable).  ws: at least
+ * bgk_workspace_bytes_batched(probs, n). */
+size_t bgk_workspace_bytes_batched(const bgk_problem* probs, int32_t n);
+int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
+                          const double* const* f_in, double* const* f_out,
+                          const double* t_span, int32_t* n_steps_out, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* Steps 5-7 of Algorithm 2 for a batch of slices: V_out[b] =
+ * P F L(V_in[b]) over t_span (lift, fine propagation, projection), all
+ * members in one launch per step.  [device] V_in, V_out [batch][nx][5]
+ * conserved; may not overlap. */
+int bgk_fine_propagate_moments(const bgk_problem* prob, int32_t batch,
+                               const double* V_in, double* V_out, double t_span,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* Coarse propagator G (Section 3.2): Euler equations in conserved variables
+ * with Rusanov fluxes H = (h_L + h_R)/2 - S/2 (V_R - V_L), S = max(|u_x| + c),
+ * c = sqrt(sound_gamma theta), adaptive substeps dt = min(cfl dx / max(|u_x|+c),
+ * remaining span).  [device] V_in, V_out [batch][nx][5] (may alias);
+ * n_sub_out [batch] substep counts (nullable). */
+int euler_coarse_step(const bgk_problem* prob, int32_t batch, const double* V_in,
+                      double* V_out, double t_span, int32_t* n_sub_out, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Optimised parareal, Algorithm 2 (iterations counted from 0): coarse guess
+ * U^{n,0} = G(U^{n-1,0}); iteration k computes the jumps
+ * Delta^n = P F L(U^{n-1,k}) - G(U^{n-1,k}) for n = k+1..N in one batched
+ * fine launch per step, then the sequential correction
+ * U^{n,k+1} = G(U^{n-1,k+1}) + Delta^n (slices n <= k are frozen), and the
+ * successive error max_{n,i,c} |U^{n,k+1} - U^{n,k}|.  Stops after k_max
+ * iterations or when the error is below tol.
+ * [device] W0 [nx][5] primitive initial moments; V_out [n_slices+1][nx][5]
+ * conserved final iterate.  [host] err_hist [k_max], k_done.
+ * Synchronises `stream` once per iteration (error readback). */
+int parareal_iterate(const bgk_problem* prob, const double* W0,
+                     int32_t n_slices, double T, int32_t k_max, double tol,
+                     double* V_out, double* err_hist, int32_t* k_done, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* The fine reference that parareal converges to (Section 2.2: N iterations
+ * reproduce it): U^n = P F L(U^{n-1}), one slice at a time with the same
+ * kernels.  [device] W0 [nx][5]; V_out [n_slices+1][nx][5]. */
+int bgk_serial_fine(const bgk_problem* prob, const double* W0, int32_t n_slices,
+                    double T, double* V_out, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* Adjoint of n_steps IMEX steps of size dt (the transpose of the step's
+ * Jacobian: transposed upwind stencil, adjoint of moments -> Maxwellian ->
+ * relaxation).  [device] f_ckpt [ceil(n_steps/ckpt_every)][nx][nv3] forward
+ * states at steps 0, ckpt_every, ...; fbar_T [nx][nv3] dL/df(final);
+ * fbar_0 [nx][nv3] output dL/df(0) (must not overlap fbar_T);
+ * dlog_eps [1] incremented by dL/dlog(eps).  Recomputes each segment of
+ * ckpt_every forward states (ws sized with batch = ckpt_every). */
+int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
+                     int32_t ckpt_every, int32_t n_steps, double dt,
+                     const double* fbar_T, double* fbar_0, double* dlog_eps,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of the lifting in rho (Definition 2: M is linear in rho):
+ * rhobar_i = sum_j fbar_ij M[W_i](v_j) / rho_i.  [device] W [nx][5],
+ * fbar [nx][nv3], rhobar [nx]. */
+int bgk_lift_adjoint_rho(const bgk_problem* prob, const double* W,
+                         const double* fbar, double* rhobar, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* Adjoint of the density of the discrete projection (Definition 1):
+ * rho_i = sum_j f_ij dv^3, so fbar_ij = rhobar_i dv^3.
+ * [device] rhobar [nx], fbar [nx][nv3] output.  Needs no workspace. */
+int bgk_density_adjoint(const bgk_problem* prob, const double* rhobar,
+                        double* fbar, void* stream);
+
+/* Synchronises `stream`, returns and clears the sticky device status in ws
+ * (BGK_OK or BGK_E_NONPHYSICAL). */
+int bgk_status(void* ws, void* stream);
+
+const char* bgk_status_string(int status);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* bgk_last_error(void);
+
+/* Tile shape of the fused step kernel: velocity elements per lane (2, 4 or 8)
+ * and x cells per work item (1..64).  0 restores the built-in choice. */
+int bgk_set_tiles(int32_t elems_per_lane, int32_t x_chunk);
+
+/* Times candidate tile shapes on `prob` with `batch` members (uses ws of
+ * BGK_OP_PROPAGATE size; synchronises) and keeps the fastest for problems of
+ * the same grid and batch.  [host] best_elems, best_chunk (nullable). */
+int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws,
+                 size_t ws_bytes, void* stream, int32_t* best_elems,
+                 int32_t* best_chunk);
+
+/* Kernel timing of the fused step kernel: when on, every launch of it is
+ * bracketed by HIP events on its stream.  bgk_prof_read synchronises and
+ * returns the summed milliseconds, the launch count and the phase-space
+ * cells updated (all since the last bgk_prof_enable(1)). */
+int bgk_prof_enable(int32_t on);
+int bgk_prof_read(double* total_ms, int64_t* launches, double* cells);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,410 @@
+"""Thin ctypes binding of libbgk.so on torch device tensors.
+
+Every function here marshals arguments (device pointers of FP64 torch
+tensors, the current HIP stream, a cached workspace) and calls the C ABI of
+``include/bgk.h`` under the same name; all arithmetic of the path runs in the
+library's HIP kernels.  There is no CPU fallback: if ``libbgk.so`` is not
+built, or no GPU is visible, the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Dict, List, Sequence, Tuple
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbgk.so")
+
+OK, E_INVALID, E_NONPHYSICAL, E_WORKSPACE, E_HIP = 0, -1, -2, -3, -4
+OP_FINE_STEP, OP_MOMENTS, OP_LIFT, OP_COARSE, OP_PROPAGATE, OP_PARAREAL, OP_ADJOINT = range(7)
+
+EXPORTS = [
+    "bgk_workspace_bytes", "bgk_workspace_bytes_batched", "bgk_n_steps", "bgk_lift",
+    "bgk_moments", "bgk_fine_steps", "bgk_fine_step", "bgk_fine_step_batched",
+    "bgk_fine_propagate_moments", "euler_coarse_step", "parareal_iterate",
+    "bgk_serial_fine", "bgk_fine_adjoint", "bgk_lift_adjoint_rho",
+    "bgk_density_adjoint", "bgk_status", "bgk_status_string", "bgk_last_error",
+    "bgk_set_tiles", "bgk_autotune", "bgk_prof_enable", "bgk_prof_read",
+]
+
+
+class BgkError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: status {code} ({msg})")
+        self.code = code
+
+
+class _Problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nv", C.c_int32 * 3),
+                ("x_lo", C.c_double), ("x_hi", C.c_double),
+                ("v_lo", C.c_double * 3), ("v_hi", C.c_double * 3),
+                ("bc", C.c_int32), ("eps", C.c_double), ("cfl", C.c_double),
+                ("sound_gamma", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbgk.so and declare the C signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+    L = C.CDLL(path)
+    P, D, I, V = C.POINTER(_Problem), C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p
+    Z = C.c_size_t
+    sig = {
+        "bgk_workspace_bytes": (Z, [P, C.c_int32, C.c_int32]),
+        "bgk_workspace_bytes_batched": (Z, [P, C.c_int32]),
+        "bgk_n_steps": (C.c_int, [P, C.c_double, I, D]),
+        "bgk_lift": (C.c_int, [P, V, V, V, Z, V]),
+        "bgk_moments": (C.c_int, [P, V, V, V, V, Z, V]),
+        "bgk_fine_steps": (C.c_int, [P, V, V, C.c_double, C.c_int32, V, Z, V]),
+        "bgk_fine_step": (C.c_int, [P, V, V, C.c_double, I, V, Z, V]),
+        "bgk_fine_step_batched": (C.c_int, [P, C.c_int32, C.POINTER(V), C.POINTER(V),
+                                            D, I, V, Z, V]),
+        "bgk_fine_propagate_moments": (C.c_int, [P, C.c_int32, V, V, C.c_double, V, Z, V]),
+        "euler_coarse_step": (C.c_int, [P, C.c_int32, V, V, C.c_double, V, V, Z, V]),
+        "parareal_iterate": (C.c_int, [P, V, C.c_int32, C.c_double, C.c_int32, C.c_double,
+                                       V, D, I, V, Z, V]),
+        "bgk_serial_fine": (C.c_int, [P, V, C.c_int32, C.c_double, V, V, Z, V]),
+        "bgk_fine_adjoint": (C.c_int, [P, V, C.c_int32, C.c_int32, C.c_double, V, V, V,
+                                       V, Z, V]),
+        "bgk_lift_adjoint_rho": (C.c_int, [P, V, V, V, V, Z, V]),
+        "bgk_density_adjoint": (C.c_int, [P, V, V, V]),
+        "bgk_status": (C.c_int, [V, V]),
+        "bgk_status_string": (C.c_char_p, [C.c_int]),
+        "bgk_last_error": (C.c_char_p, []),
+        "bgk_set_tiles": (C.c_int, [C.c_int32, C.c_int32]),
+        "bgk_autotune": (C.c_int, [P, C.c_int32, V, Z, V, I, I]),
+        "bgk_prof_enable": (C.c_int, [C.c_int32]),
+        "bgk_prof_read": (C.c_int, [D, C.POINTER(C.c_int64), D]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _gpu_lib():
+    L = load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("libbgk needs a visible gfx950 GPU")
+    return L
+
+
+def problem_struct(p) -> _Problem:
+    s = _Problem()
+    s.nx = int(p.nx)
+    for a in range(3):
+        s.nv[a] = int(p.nv[a])
+        s.v_lo[a] = float(p.v_lo[a])
+        s.v_hi[a] = float(p.v_hi[a])
+    s.x_lo, s.x_hi = float(p.x_lo), float(p.x_hi)
+    s.bc = int(p.bc)
+    s.eps = float(p.eps)
+    s.cfl = float(p.cfl)
+    s.sound_gamma = float(p.sound_gamma)
+    return s
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        msg = load_library().bgk_last_error().decode()
+        raise BgkError(rc, where, msg or load_library().bgk_status_string(rc).decode())
+
+
+def _dev(t: torch.Tensor, name: str) -> int:
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _f64(x, device="cuda") -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()
+
+
+# ------------------------------------------------------------- workspaces --
+_ws: Dict[tuple, torch.Tensor] = {}
+_last_ws: List[torch.Tensor] = []
+
+
+def _key(p):
+    return (p.nx, tuple(p.nv), p.x_lo, p.x_hi, tuple(p.v_lo), tuple(p.v_hi))
+
+
+def workspace_bytes(p, op: int, batch: int = 1) -> int:
+    return int(load_library().bgk_workspace_bytes(C.byref(problem_struct(p)), op, batch))
+
+
+def workspace(p, op: int, batch: int = 1) -> torch.Tensor:
+    """Cached zero-initialised device workspace for (grid, op, batch)."""
+    key = (_key(p), op, batch)
+    w = _ws.get(key)
+    if w is None:
+        n = workspace_bytes(p, op, batch)
+        if n == 0:
+            raise BgkError(E_INVALID, "workspace_bytes", "invalid problem")
+        w = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        _ws[key] = w
+    _last_ws[:] = [w]
+    return w
+
+
+def free_workspaces():
+    _ws.clear()
+    _last_ws.clear()
+
+
+def status(ws: torch.Tensor | None = None) -> int:
+    """Synchronise and return/clear the sticky status of a workspace."""
+    w = ws if ws is not None else (_last_ws[0] if _last_ws else None)
+    if w is None:
+        return OK
+    return int(_gpu_lib().bgk_status(C.c_void_p(w.data_ptr()), C.c_void_p(_stream())))
+
+
+def check_status(ws: torch.Tensor | None = None):
+    _check(status(ws), "device status")
+
+
+# ------------------------------------------------------------ operations --
+def n_steps(p, t_span: float) -> Tuple[int, float]:
+    n, dt = C.c_int32(), C.c_double()
+    _check(load_library().bgk_n_steps(C.byref(problem_struct(p)), t_span, C.byref(n),
+                                      C.byref(dt)), "bgk_n_steps")
+    return n.value, dt.value
+
+
+def lift(p, W) -> torch.Tensor:
+    L = _gpu_lib()
+    W = _f64(W)
+    f = torch.empty((p.nx, p.nv[0] * p.nv[1] * p.nv[2]), dtype=torch.float64, device="cuda")
+    w = workspace(p, OP_LIFT)
+    _check(L.bgk_lift(C.byref(problem_struct(p)), _dev(W, "W"), _dev(f, "f"),
+                      w.data_ptr(), w.numel(), _stream()), "bgk_lift")
+    return f
+
+
+def moments(p, f: torch.Tensor):
+    L = _gpu_lib()
+    V = torch.empty((p.nx, 5), dtype=torch.float64, device="cuda")
+    W = torch.empty((p.nx, 5), dtype=torch.float64, device="cuda")
+    w = workspace(p, OP_MOMENTS)
+    _check(L.bgk_moments(C.byref(problem_struct(p)), _dev(f, "f"), V.data_ptr(),
+                         W.data_ptr(), w.data_ptr(), w.numel(), _stream()), "bgk_moments")
+    return V, W
+
+
+def fine_steps(p, f: torch.Tensor, dt: float, n: int, out: torch.Tensor | None = None):
+    L = _gpu_lib()
+    out = torch.empty_like(f) if out is None else out
+    w = workspace(p, OP_FINE_STEP)
+    _check(L.bgk_fine_steps(C.byref(problem_struct(p)), _dev(f, "f_in"), _dev(out, "f_out"),
+                            dt, n, w.data_ptr(), w.numel(), _stream()), "bgk_fine_steps")
+    return out
+
+
+def fine_step(p, f: torch.Tensor, t_span: float, out: torch.Tensor | None = None):
+    L = _gpu_lib()
+    out = torch.empty_like(f) if out is None else out
+    n = C.c_int32()
+    w = workspace(p, OP_FINE_STEP)
+    _check(L.bgk_fine_step(C.byref(problem_struct(p)), _dev(f, "f_in"), _dev(out, "f_out"),
+                           t_span, C.byref(n), w.data_ptr(), w.numel(), _stream()),
+           "bgk_fine_step")
+    return out, n.value
+
+
+_batched_ws: Dict[tuple, torch.Tensor] = {}
+
+
+def fine_step_batched(probs: Sequence, fs: Sequence[torch.Tensor], spans: Sequence[float],
+                      outs: Sequence[torch.Tensor] | None = None):
+    L = _gpu_lib()
+    n = len(probs)
+    arr = (_Problem * n)(*[problem_struct(p) for p in probs])
+    outs = [torch.empty_like(f) for f in fs] if outs is None else list(outs)
+    fin = (C.c_void_p * n)(*[_dev(f, "f_in") for f in fs])
+    fout = (C.c_void_p * n)(*[_dev(o, "f_out") for o in outs])
+    sp = (C.c_double * n)(*[float(s) for s in spans])
+    steps = (C.c_int32 * n)()
+    nb = int(L.bgk_workspace_bytes_batched(arr, n))
+    if nb == 0:
+        raise BgkError(E_INVALID, "bgk_workspace_bytes_batched", "invalid problems")
+    key = tuple(_key(p) for p in probs)
+    w = _batched_ws.get(key)
+    if w is None or w.numel() < nb:
+        w = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+        _batched_ws.clear()
+        _batched_ws[key] = w
+    _last_ws[:] = [w]
+    _check(L.bgk_fine_step_batched(arr, n, fin, fout, sp, steps, w.data_ptr(), w.numel(),
+                                   _stream()), "bgk_fine_step_batched")
+    return outs, list(steps)
+
+
+def fine_propagate_moments(p, V_in: torch.Tensor, t_span: float) -> torch.Tensor:
+    """Batched P F L over the leading dimension of V_in ([B][nx][5] conserved)."""
+    L = _gpu_lib()
+    V_in = V_in.contiguous()
+    B = V_in.shape[0] if V_in.dim() == 3 else 1
+    out = torch.empty_like(V_in)
+    w = workspace(p, OP_PROPAGATE, B)
+    _check(L.bgk_fine_propagate_moments(C.byref(problem_struct(p)), B, _dev(V_in, "V_in"),
+                                        _dev(out, "V_out"), t_span, w.data_ptr(),
+                                        w.numel(), _stream()), "bgk_fine_propagate_moments")
+    return out
+
+
+def euler_coarse_step(p, V: torch.Tensor, t_span: float):
+    L = _gpu_lib()
+    V = V.contiguous()
+    B = V.shape[0] if V.dim() == 3 else 1
+    out = torch.empty_like(V)
+    nsub = torch.zeros(B, dtype=torch.int32, device="cuda")
+    w = workspace(p, OP_COARSE, B)
+    _check(L.euler_coarse_step(C.byref(problem_struct(p)), B, _dev(V, "V_in"),
+                               _dev(out, "V_out"), t_span, nsub.data_ptr(), w.data_ptr(),
+                               w.numel(), _stream()), "euler_coarse_step")
+    return out, nsub
+
+
+def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float):
+    L = _gpu_lib()
+    W0 = _f64(W0)
+    V = torch.empty((n_slices + 1, p.nx, 5), dtype=torch.float64, device="cuda")
+    err = (C.c_double * max(k_max, 1))()
+    kd = C.c_int32()
+    w = workspace(p, OP_PARAREAL, n_slices)
+    _check(L.parareal_iterate(C.byref(problem_struct(p)), _dev(W0, "W0"), n_slices, T, k_max,
+                              tol, _dev(V, "V_out"), err, C.byref(kd), w.data_ptr(),
+                              w.numel(), _stream()), "parareal_iterate")
+    return V, [err[i] for i in range(kd.value)], kd.value
+
+
+def serial_fine(p, W0, n_slices: int, T: float) -> torch.Tensor:
+    L = _gpu_lib()
+    W0 = _f64(W0)
+    V = torch.empty((n_slices + 1, p.nx, 5), dtype=torch.float64, device="cuda")
+    w = workspace(p, OP_PARAREAL, n_slices)
+    _check(L.bgk_serial_fine(C.byref(problem_struct(p)), _dev(W0, "W0"), n_slices, T,
+                             _dev(V, "V_out"), w.data_ptr(), w.numel(), _stream()),
+           "bgk_serial_fine")
+    return V
+
+
+def fine_adjoint(p, f_ckpt: torch.Tensor, ckpt_every: int, n: int, dt: float,
+                 fbar_T: torch.Tensor, dlog_eps: torch.Tensor | None = None):
+    L = _gpu_lib()
+    fbar0 = torch.empty_like(fbar_T)
+    dle = torch.zeros(1, dtype=torch.float64, device="cuda") if dlog_eps is None else dlog_eps
+    w = workspace(p, OP_ADJOINT, ckpt_every)
+    _check(L.bgk_fine_adjoint(C.byref(problem_struct(p)), _dev(f_ckpt, "f_ckpt"), ckpt_every,
+                              n, dt, _dev(fbar_T, "fbar_T"), _dev(fbar0, "fbar_0"),
+                              _dev(dle, "dlog_eps"), w.data_ptr(), w.numel(), _stream()),
+           "bgk_fine_adjoint")
+    return fbar0, dle
+
+
+def lift_adjoint_rho(p, W, fbar: torch.Tensor) -> torch.Tensor:
+    L = _gpu_lib()
+    W = _f64(W)
+    rb = torch.empty(p.nx, dtype=torch.float64, device="cuda")
+    w = workspace(p, OP_LIFT)
+    _check(L.bgk_lift_adjoint_rho(C.byref(problem_struct(p)), _dev(W, "W"), _dev(fbar, "fbar"),
+                                  _dev(rb, "rhobar"), w.data_ptr(), w.numel(), _stream()),
+           "bgk_lift_adjoint_rho")
+    return rb
+
+
+def density_adjoint(p, rhobar: torch.Tensor) -> torch.Tensor:
+    L = _gpu_lib()
+    fbar = torch.empty((p.nx, p.nv[0] * p.nv[1] * p.nv[2]), dtype=torch.float64, device="cuda")
+    _check(L.bgk_density_adjoint(C.byref(problem_struct(p)), _dev(rhobar.contiguous(), "rhobar"),
+                                 _dev(fbar, "fbar"), _stream()), "bgk_density_adjoint")
+    return fbar
+
+
+def set_tiles(elems: int = 0, chunk: int = 0):
+    _check(load_library().bgk_set_tiles(elems, chunk), "bgk_set_tiles")
+
+
+def autotune(p, batch: int = 1) -> Tuple[int, int]:
+    L = _gpu_lib()
+    w = workspace(p, OP_PROPAGATE, batch)
+    e, c = C.c_int32(), C.c_int32()
+    _check(L.bgk_autotune(C.byref(problem_struct(p)), batch, w.data_ptr(), w.numel(),
+                          _stream(), C.byref(e), C.byref(c)), "bgk_autotune")
+    return e.value, c.value
+
+
+def prof_enable(on: bool = True):
+    _check(load_library().bgk_prof_enable(1 if on else 0), "bgk_prof_enable")
+
+
+def prof_read():
+    ms, n, cells = C.c_double(), C.c_int64(), C.c_double()
+    _check(load_library().bgk_prof_read(C.byref(ms), C.byref(n), C.byref(cells)),
+           "bgk_prof_read")
+    return ms.value, n.value, cells.value
+
+
+# ------------------------------------------------------------- autograd --
+class KineticDensity(torch.autograd.Function):
+    """rho(T) of the fine propagator started from the lifted Maxwellian
+    M[rho0, u0, theta0], differentiable in rho0 and log(eps).
+
+    forward: lift -> n IMEX steps (checkpoints every `ckpt_every` steps)
+    -> density; backward: density adjoint -> fine adjoint (recomputing each
+    checkpoint segment) -> lift adjoint.  All steps run in libbgk kernels."""
+
+    @staticmethod
+    def forward(ctx, rho0, log_eps, prob, u0, theta0, T, ckpt_every):
+        from dataclasses import replace
+        eps = math.exp(float(log_eps.detach().cpu()))
+        p = replace(prob, eps=eps)
+        nx = p.nx
+        W = torch.zeros((nx, 5), dtype=torch.float64, device="cuda")
+        W[:, 0] = rho0.detach()
+        W[:, 1:4] = _f64(u0).reshape(-1, 3) if not isinstance(u0, float) else u0
+        W[:, 4] = theta0
+        n, dt = n_steps(p, T)
+        f = lift(p, W)
+        n_ck = (n + ckpt_every - 1) // ckpt_every
+        ck = torch.empty((n_ck,) + tuple(f.shape), dtype=torch.float64, device="cuda")
+        for c in range(n_ck):
+            ck[c].copy_(f)
+            m = min(ckpt_every, n - c * ckpt_every)
+            f = fine_steps(p, f, dt, m)
+        _, Wt = moments(p, f)
+        ctx.save_for_backward(ck, W)
+        ctx.p, ctx.n, ctx.dt, ctx.ckpt_every = p, n, dt, ckpt_every
+        return Wt[:, 0].clone()
+
+    @staticmethod
+    def backward(ctx, grad_rho):
+        ck, W = ctx.saved_tensors
+        p = ctx.p
+        fbar = density_adjoint(p, grad_rho.contiguous().to(torch.float64))
+        fbar0, dle = fine_adjoint(p, ck, ctx.ckpt_every, ctx.n, ctx.dt, fbar)
+        rb = lift_adjoint_rho(p, W, fbar0)
+        return rb, dle.reshape(()), None, None, None, None, None
+
+
+def kinetic_density(rho0, log_eps, prob, u0=0.0, theta0=1.0, T=0.1, ckpt_every=16):
+    return KineticDensity.apply(rho0, log_eps, prob, u0, theta0, T, ckpt_every)

@@ -1,0 +1,991 @@
+// Host runtime and C ABI of libbgk (declared in include/bgk.h).
+//
+// The runtime validates arguments, carves the caller's workspace, builds the
+// per-instance descriptor tables the kernels read (written into the
+// workspace by a tiny kernel that takes them as kernel arguments, so no host
+// buffer has to outlive the call), and enqueues the kernel sequence of each
+// operation on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "bgk_internal.h"
+
+namespace bgk {
+
+// ---------------------------------------------------------------- errors --
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return BGK_E_HIP;
+}
+
+static int invalid(const char* why) {
+  set_error(why);
+  return BGK_E_INVALID;
+}
+
+// --------------------------------------------------------- host helpers --
+size_t align_up(size_t n, size_t a) { return (n + a - 1) / a * a; }
+
+double dx_of(const bgk_problem& p) { return (p.x_hi - p.x_lo) / p.nx; }
+double dv_of(const bgk_problem& p, int a) { return (p.v_hi[a] - p.v_lo[a]) / p.nv[a]; }
+
+int check_problem(const bgk_problem* p) {
+  if (p == nullptr) return invalid("problem is NULL");
+  if (p->nx < 2) return invalid("nx must be >= 2");
+  for (int a = 0; a < 3; ++a) {
+    if (p->nv[a] < 1 || p->nv[a] > kMaxNv) return invalid("nv out of range [1, 256]");
+    if (!(p->v_hi[a] > p->v_lo[a]) || !std::isfinite(p->v_hi[a] - p->v_lo[a]))
+      return invalid("empty velocity box");
+  }
+  if (!(p->x_hi > p->x_lo) || !std::isfinite(p->x_hi - p->x_lo))
+    return invalid("empty x domain");
+  if (p->bc != 0 && p->bc != 1) return invalid("bc must be 0 (Neumann) or 1 (periodic)");
+  if (!(p->eps > 0.0)) return invalid("eps must be > 0");
+  if (!(p->cfl > 0.0 && p->cfl <= 1.0)) return invalid("cfl must be in (0, 1]");
+  if (!(p->sound_gamma > 0.0) || !std::isfinite(p->sound_gamma))
+    return invalid("sound_gamma must be > 0");
+  const long long nv3 = (long long)p->nv[0] * p->nv[1] * p->nv[2];
+  if (nv3 * p->nx > (1LL << 40)) return invalid("grid too large");
+  return BGK_OK;
+}
+
+// Section 2.2 local step rule at velocity cell centres.
+int n_steps_for(const bgk_problem& p, double t_span, int32_t* n, double* dt) {
+  if (!(t_span > 0.0) || !std::isfinite(t_span)) return invalid("t_span must be > 0");
+  double vmax = 0.0;
+  const double dv = dv_of(p, 0);
+  for (int j = 0; j < p.nv[0]; ++j)
+    vmax = std::max(vmax, std::fabs(p.v_lo[0] + (j + 0.5) * dv));
+  const double dt_stab = p.cfl * dx_of(p) / vmax;
+  const double r = t_span / dt_stab;
+  if (!(r < 2.0e9)) return invalid("too many fine steps for t_span");
+  int32_t k = (int32_t)std::ceil(r - 1e-9);
+  if (k < 1) k = 1;
+  *n = k;
+  *dt = t_span / k;
+  return BGK_OK;
+}
+
+// ----------------------------------------------------------------- tiles --
+static std::mutex g_mu;
+static Tiles g_override = {0, 0};
+static std::map<std::tuple<int, int, int, int, int>, Tiles> g_tuned;
+
+static long long nv3_of(const bgk_problem& p) {
+  return (long long)p.nv[0] * p.nv[1] * p.nv[2];
+}
+
+static long long blocks_for_tiles(const bgk_problem& p, int batch, Tiles t) {
+  const long long ntiles = (nv3_of(p) + kWave * t.elems - 1) / (kWave * t.elems);
+  const long long ntg = (ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  return (long long)batch * ntg * ((p.nx + t.chunk - 1) / t.chunk);
+}
+
+Tiles choose_tiles(const bgk_problem& p, int batch) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Tiles t = {4, 16};
+  auto it = g_tuned.find({p.nx, p.nv[0], p.nv[1], p.nv[2], batch});
+  if (it != g_tuned.end()) t = it->second;
+  else {
+    // enough work items to fill 256 CUs several times over
+    while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 4096) t.chunk /= 2;
+    if (blocks_for_tiles(p, batch, t) < 1024) t.elems = 2;
+  }
+  if (g_override.elems) t.elems = g_override.elems;
+  if (g_override.chunk) t.chunk = g_override.chunk;
+  return t;
+}
+
+// ------------------------------------------------------------- workspace --
+// Every workspace starts with WsHeader, then a descriptor table, then the
+// regions of the operation.
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  }
+};
+
+constexpr int kMaxInst = 4096;
+
+struct FineRegions {  // fine solve of B members of one grid
+  size_t buf0, buf1, part, fac, vg, vout;
+};
+constexpr size_t kNone = ~(size_t)0;  // region not allocated
+
+static int part_tiles_of(const bgk_problem& p) {
+  return (int)((nv3_of(p) + kWave * kMinElems - 1) / (kWave * kMinElems));
+}
+
+static FineRegions carve_fine(Carve& c, const bgk_problem& p, int B, bool two_bufs) {
+  FineRegions r;
+  const size_t f = (size_t)B * p.nx * nv3_of(p) * sizeof(double);
+  r.buf0 = c.take(f);
+  r.buf1 = two_bufs ? c.take(f) : kNone;
+  r.part = c.take((size_t)B * p.nx * part_tiles_of(p) * 5 * sizeof(double));
+  r.fac = c.take((size_t)B * p.nx * (p.nv[0] + p.nv[1] + p.nv[2]) * sizeof(double));
+  r.vg = c.take((size_t)B * p.nx * 5 * sizeof(double));
+  r.vout = c.take((size_t)B * p.nx * 5 * sizeof(double));
+  return r;
+}
+
+struct Layout {
+  size_t header = 0, insts = 0;
+  FineRegions fine{};
+  size_t coarse = 0;                 // Euler scratch
+  size_t U0 = 0, U1 = 0, Gc = 0, VF = 0;
+  size_t states = 0, fbA = 0, fbB = 0, part6 = 0, coef = 0, dle = 0;
+  size_t total = 0;
+};
+
+static Layout layout_of(const bgk_problem& p, int op, int batch) {
+  Carve c;
+  Layout L;
+  L.header = c.take(sizeof(WsHeader));
+  L.insts = c.take(sizeof(Inst) * 4);
+  const size_t f1 = (size_t)p.nx * nv3_of(p) * sizeof(double);
+  const size_t sl = (size_t)p.nx * 5 * sizeof(double);
+  switch (op) {
+    case BGK_OP_FINE_STEP:
+      L.fine = carve_fine(c, p, 1, false);
+      break;
+    case BGK_OP_MOMENTS:
+    case BGK_OP_LIFT:
+      L.fine = carve_fine(c, p, 1, false);
+      break;
+    case BGK_OP_COARSE:
+      L.coarse = c.take((size_t)batch * 16 * p.nx * sizeof(double));
+      break;
+    case BGK_OP_PROPAGATE:
+      L.fine = carve_fine(c, p, batch, true);
+      break;
+    case BGK_OP_PARAREAL:
+      L.fine = carve_fine(c, p, batch, true);
+      L.coarse = c.take((size_t)21 * p.nx * sizeof(double));
+      L.U0 = c.take(sl * (batch + 1));
+      L.U1 = c.take(sl * (batch + 1));
+      L.Gc = c.take(sl * (batch + 1));
+      L.VF = c.take(sl * (batch + 1));
+      break;
+    case BGK_OP_ADJOINT: {
+      L.fine = carve_fine(c, p, 1, false);
+      L.states = c.take(f1 * batch);
+      L.fbA = c.take(f1);
+      L.fbB = c.take(f1);
+      const size_t nt = (nv3_of(p) + kWave * kAdjElems - 1) / (kWave * kAdjElems);
+      L.part6 = c.take((size_t)p.nx * nt * 6 * sizeof(double));
+      L.coef = c.take(sl);
+      L.dle = c.take((size_t)p.nx * sizeof(double));
+      break;
+    }
+    default:
+      break;
+  }
+  L.total = c.off;
+  return L;
+}
+
+template <class T>
+static T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+static int check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (ws == nullptr) {
+    set_error("workspace is NULL");
+    return BGK_E_WORKSPACE;
+  }
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) {
+    set_error("workspace must be 256-byte aligned");
+    return BGK_E_WORKSPACE;
+  }
+  if (ws_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return BGK_E_WORKSPACE;
+  }
+  return BGK_OK;
+}
+
+// -------------------------------------------------- descriptor uploads --
+constexpr int kPack = 12;  // descriptors per upload launch (kernel-argument bytes)
+struct InstPack {
+  Inst v[kPack];
+  int n;
+};
+
+__global__ void k_put_insts(Inst* dst, InstPack p) {
+  constexpr int W = sizeof(Inst) / sizeof(unsigned long long);
+  static_assert(sizeof(Inst) % sizeof(unsigned long long) == 0, "Inst padding");
+  const unsigned long long* s = reinterpret_cast<const unsigned long long*>(p.v);
+  unsigned long long* d = reinterpret_cast<unsigned long long*>(dst);
+  for (int k = threadIdx.x; k < p.n * W; k += blockDim.x) d[k] = s[k];
+}
+
+static int put_insts(Inst* d_dst, const Inst* h, int n, hipStream_t s) {
+  for (int b = 0; b < n; b += kPack) {
+    InstPack pk;
+    std::memset(&pk, 0, sizeof(pk));
+    pk.n = std::min(kPack, n - b);
+    for (int k = 0; k < pk.n; ++k) pk.v[k] = h[b + k];
+    hipLaunchKernelGGL(k_put_insts, dim3(1), dim3(256), 0, s, d_dst + b, pk);
+    BGK_HIP(hipGetLastError());
+  }
+  return BGK_OK;
+}
+
+__global__ void k_fill_int(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+__global__ void k_prim_to_cons(const double* __restrict__ W, double* V, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* w = W + 5 * (long long)i;
+  double* v = V + 5 * (long long)i;
+  const double rho = w[0];
+  const double usq = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+  v[0] = rho;
+  v[1] = rho * w[1];
+  v[2] = rho * w[2];
+  v[3] = rho * w[3];
+  v[4] = 0.5 * rho * usq + 1.5 * rho * w[4];
+}
+
+int launch_prim_to_cons(const double* W, double* V, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_prim_to_cons, dim3((n + 255) / 256), dim3(256), 0, s, W, V, n);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+// Descriptor of B members of one grid advanced with step dt.
+static Inst make_inst(const bgk_problem& p, int B, double dt, Tiles t) {
+  Inst I;
+  std::memset(&I, 0, sizeof(I));
+  I.nx = p.nx;
+  I.nvx = p.nv[0];
+  I.nvy = p.nv[1];
+  I.nvz = p.nv[2];
+  I.nv3 = (int)nv3_of(p);
+  I.nvs = p.nv[0] + p.nv[1] + p.nv[2];
+  I.bc = p.bc;
+  I.nbatch = B;
+  I.ntiles = (I.nv3 + kWave * t.elems - 1) / (kWave * t.elems);
+  I.ntg = (I.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  I.nchunks = (p.nx + t.chunk - 1) / t.chunk;
+  I.items = (long long)B * I.ntg * I.nchunks;
+  I.part_tiles = part_tiles_of(p);
+  for (int a = 0; a < 3; ++a) {
+    I.dv[a] = dv_of(p, a);
+    I.vlo[a] = p.v_lo[a];
+  }
+  I.dv3 = I.dv[0] * I.dv[1] * I.dv[2];
+  I.r = dt / dx_of(p);
+  const double lam = dt / p.eps;
+  if (std::isinf(lam)) {
+    I.a = 0.0;
+    I.al = 1.0;
+  } else {
+    I.a = 1.0 / (1.0 + lam);
+    I.al = lam / (1.0 + lam);
+  }
+  return I;
+}
+
+static void attach_fine(Inst& I, void* ws, const FineRegions& r, double* buf1) {
+  I.buf[0] = at<double>(ws, r.buf0);
+  I.buf[1] = buf1 ? buf1 : (r.buf1 == kNone ? nullptr : at<double>(ws, r.buf1));
+  I.part = at<double>(ws, r.part);
+  I.fac = at<double>(ws, r.fac);
+  I.vg = at<double>(ws, r.vg);
+  I.vout = at<double>(ws, r.vout);
+}
+
+static int lds_doubles(const Inst& I, Tiles t) { return (t.chunk + 2) * I.nvs; }
+
+// Runs `n` relax-then-transport steps on the (uploaded) descriptor d_I.
+// first_mode: kCopy or kLift.  Returns the buffer index holding g^n.
+static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
+                     bool project_last, Tiles t, int* d_status, hipStream_t s,
+                     int* last_sel) {
+  int w_prev = 1;  // step 1 writes buf[0]
+  for (int k = 1; k <= n; ++k) {
+    const int mode = (k == 1) ? first_mode : kRelax;
+    const int phase = w_prev;  // dst = buf[phase ^ 1], src = buf[phase]
+    prof_before(s);
+    int rc = launch_step(d_I, 1, h.items, mode, phase, t.elems, t.chunk,
+                         lds_doubles(h, t), d_status, s);
+    prof_after(s, (double)h.nbatch * h.nx * h.nv3);
+    if (rc) return rc;
+    const int red = (project_last && k == n) ? kRedProject : kRedRelaxFactors;
+    rc = launch_reduce(d_I, 1, (long long)h.nbatch * h.nx, red, 0, d_status, s);
+    if (rc) return rc;
+    w_prev = phase ^ 1;
+  }
+  *last_sel = w_prev;
+  return BGK_OK;
+}
+
+static long long relax_out_blocks(const Inst& h) {
+  const long long slabs = (h.nv3 + 4 * kBlock - 1) / (4 * kBlock);
+  return (long long)h.nbatch * h.nx * slabs;
+}
+
+// ------------------------------------------------------------- profiling --
+struct ProfRec {
+  hipEvent_t a, b;
+  double cells;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+static std::vector<hipEvent_t> g_prof_pool;
+static hipEvent_t g_prof_pending = nullptr;
+
+static hipEvent_t prof_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_before(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return;
+  g_prof_pending = prof_event();
+  if (g_prof_pending) (void)hipEventRecord(g_prof_pending, s);
+}
+
+void prof_after(hipStream_t s, double cells) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on || !g_prof_pending) return;
+  hipEvent_t e = prof_event();
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  g_prof.push_back({g_prof_pending, e, cells});
+  g_prof_pending = nullptr;
+}
+
+}  // namespace bgk
+
+using namespace bgk;
+
+// ======================================================================
+//                                C ABI
+// ======================================================================
+extern "C" {
+
+const char* bgk_last_error(void) { return g_last_error.c_str(); }
+
+const char* bgk_status_string(int st) {
+  switch (st) {
+    case BGK_OK: return "ok";
+    case BGK_E_INVALID: return "invalid argument";
+    case BGK_E_NONPHYSICAL: return "non-physical state (rho <= 0, theta <= 0 or NaN)";
+    case BGK_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case BGK_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+size_t bgk_workspace_bytes(const bgk_problem* prob, int32_t op, int32_t batch) {
+  if (check_problem(prob) || batch < 1 || op < 0 || op > BGK_OP_ADJOINT) return 0;
+  return layout_of(*prob, op, batch).total;
+}
+
+int bgk_n_steps(const bgk_problem* prob, double t_span, int32_t* n, double* dt) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  int32_t nn;
+  double d;
+  rc = n_steps_for(*prob, t_span, &nn, &d);
+  if (rc) return rc;
+  if (n) *n = nn;
+  if (dt) *dt = d;
+  return BGK_OK;
+}
+
+int bgk_status(void* ws, void* stream) {
+  if (ws == nullptr) return BGK_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  BGK_HIP(hipStreamSynchronize(s));
+  int st = 0;
+  BGK_HIP(hipMemcpy(&st, at<WsHeader>(ws, 0), sizeof(int), hipMemcpyDeviceToHost));
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, &at<WsHeader>(ws, 0)->status, 0);
+  BGK_HIP(hipGetLastError());
+  BGK_HIP(hipStreamSynchronize(s));
+  return st ? BGK_E_NONPHYSICAL : BGK_OK;
+}
+
+int bgk_lift(const bgk_problem* prob, const double* W, double* f, void* ws,
+             size_t ws_bytes, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!W || !f) return invalid("NULL array");
+  const Layout L = layout_of(*prob, BGK_OP_LIFT, 1);
+  if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const Tiles t = choose_tiles(*prob, 1);
+  Inst I = make_inst(*prob, 1, 1.0, t);
+  attach_fine(I, ws, L.fine, nullptr);
+  I.fout = f;
+  Inst* dI = at<Inst>(ws, L.insts);
+  int* st = &at<WsHeader>(ws, 0)->status;
+  if ((rc = put_insts(dI, &I, 1, s))) return rc;
+  if ((rc = launch_lift_factors(dI, 1, prob->nx, W, st, s))) return rc;
+  return launch_relax_out_blocks(dI, 1, relax_out_blocks(I), I.nvs, -1, s);
+}
+
+int bgk_moments(const bgk_problem* prob, const double* f, double* V, double* W,
+                void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!f) return invalid("NULL array");
+  const Layout L = layout_of(*prob, BGK_OP_MOMENTS, 1);
+  if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Tiles t = choose_tiles(*prob, 1);
+  Inst I = make_inst(*prob, 1, 1.0, t);
+  attach_fine(I, ws, L.fine, nullptr);
+  I.fin = f;
+  if (V) I.vg = V;
+  I.vout = W;  // primitive output (nullable)
+  Inst* dI = at<Inst>(ws, L.insts);
+  int* st = &at<WsHeader>(ws, 0)->status;
+  if ((rc = put_insts(dI, &I, 1, s))) return rc;
+  if ((rc = launch_partials(dI, 1, I.items, t.elems, t.chunk, s))) return rc;
+  return launch_reduce(dI, 1, prob->nx, kRedMomentsOnly, 0, st, s);
+}
+
+int bgk_fine_steps(const bgk_problem* prob, const double* f_in, double* f_out,
+                   double dt, int32_t n_steps, void* ws, size_t ws_bytes,
+                   void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!f_in || !f_out) return invalid("NULL array");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return invalid("dt must be > 0");
+  if (n_steps < 0) return invalid("n_steps must be >= 0");
+  const size_t fbytes = (size_t)prob->nx * nv3_of(*prob) * sizeof(double);
+  const char* a0 = (const char*)f_in;
+  const char* b0 = (const char*)f_out;
+  if (a0 < b0 + fbytes && b0 < a0 + fbytes) return invalid("f_in and f_out overlap");
+  const Layout L = layout_of(*prob, BGK_OP_FINE_STEP, 1);
+  if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (n_steps == 0) {
+    BGK_HIP(hipMemcpyAsync(f_out, f_in, fbytes, hipMemcpyDeviceToDevice, s));
+    return BGK_OK;
+  }
+  const Tiles t = choose_tiles(*prob, 1);
+  Inst I = make_inst(*prob, 1, dt, t);
+  attach_fine(I, ws, L.fine, f_out);  // ping-pong between ws and f_out
+  I.fin = f_in;
+  I.fout = f_out;
+  Inst* dI = at<Inst>(ws, L.insts);
+  int* st = &at<WsHeader>(ws, 0)->status;
+  if ((rc = put_insts(dI, &I, 1, s))) return rc;
+  int last = 0;
+  if ((rc = run_steps(dI, I, n_steps, kCopy, false, t, st, s, &last))) return rc;
+  return launch_relax_out_blocks(dI, 1, relax_out_blocks(I), I.nvs, last, s);
+}
+
+int bgk_fine_step(const bgk_problem* prob, const double* f_in, double* f_out,
+                  double t_span, int32_t* n_steps_out, void* ws, size_t ws_bytes,
+                  void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  int32_t n;
+  double dt;
+  if ((rc = n_steps_for(*prob, t_span, &n, &dt))) return rc;
+  if (n_steps_out) *n_steps_out = n;
+  return bgk_fine_steps(prob, f_in, f_out, dt, n, ws, ws_bytes, stream);
+}
+
+int bgk_fine_propagate_moments(const bgk_problem* prob, int32_t batch,
+                               const double* V_in, double* V_out, double t_span,
+                               void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (batch < 1) return invalid("batch must be >= 1");
+  if (!V_in || !V_out) return invalid("NULL array");
+  const size_t vb = (size_t)batch * prob->nx * 5 * sizeof(double);
+  const char* a0 = (const char*)V_in;
+  const char* b0 = (const char*)V_out;
+  if (a0 < b0 + vb && b0 < a0 + vb) return invalid("V_in and V_out overlap");
+  int32_t n;
+  double dt;
+  if ((rc = n_steps_for(*prob, t_span, &n, &dt))) return rc;
+  const Layout L = layout_of(*prob, BGK_OP_PROPAGATE, batch);
+  if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const Tiles t = choose_tiles(*prob, batch);
+  Inst I = make_inst(*prob, batch, dt, t);
+  attach_fine(I, ws, L.fine, nullptr);
+  I.vin = V_in;
+  I.vout = V_out;
+  Inst* dI = at<Inst>(ws, L.insts);
+  int* st = &at<WsHeader>(ws, 0)->status;
+  if ((rc = put_insts(dI, &I, 1, s))) return rc;
+  if ((rc = launch_lift_factors(dI, 1, (long long)batch * prob->nx, nullptr, st, s)))
+    return rc;
+  int last = 0;
+  return run_steps(dI, I, n, kLift, true, t, st, s, &last);
+}
+
+int euler_coarse_step(const bgk_problem* prob, int32_t batch, const double* V_in,
+                      double* V_out, double t_span, int32_t* n_sub_out, void* ws,
+                      size_t ws_bytes, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (batch < 1) return invalid("batch must be >= 1");
+  if (!V_in || !V_out) return invalid("NULL array");
+  if (!(t_span > 0.0) || !std::isfinite(t_span)) return invalid("t_span must be > 0");
+  const Layout L = layout_of(*prob, BGK_OP_COARSE, batch);
+  if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  return launch_euler(*prob, batch, V_in, V_out, t_span, n_sub_out,
+                      at<double>(ws, L.coarse), &at<WsHeader>(ws, 0)->status,
+                      (hipStream_t)stream);
+}
+
+int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices,
+                     double T, int32_t k_max, double tol, double* V_out,
+                     double* err_hist, int32_t* k_done, void* ws, size_t ws_bytes,
+                     void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!W0 || !V_out) return invalid("NULL array");
+  if (n_slices < 1 || k_max < 0) return invalid("n_slices >= 1 and k_max >= 0 required");
+  if (k_max > 0 && !err_hist) return invalid("err_hist is NULL");
+  if (!(T > 0.0) || !std::isfinite(T) || std::isnan(tol)) return invalid("bad T or tol");
+  const double span = T / n_slices;
+  int32_t n;
+  double dt;
+  if ((rc = n_steps_for(*prob, span, &n, &dt))) return rc;
+  const Layout L = layout_of(*prob, BGK_OP_PARAREAL, n_slices);
+  if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  WsHeader* hd = at<WsHeader>(ws, 0);
+  int* st = &hd->status;
+  const size_t sl = (size_t)prob->nx * 5;
+  double* U[2] = {at<double>(ws, L.U0), at<double>(ws, L.U1)};
+  double* Gc = at<double>(ws, L.Gc);
+  double* VF = at<double>(ws, L.VF);
+  double* scratch = at<double>(ws, L.coarse);
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, st, 0);
+  BGK_HIP(hipGetLastError());
+  if ((rc = launch_pararealsweep_init(*prob, n_slices, W0, U[0], Gc, span, scratch, st, s)))
+    return rc;
+  int cur = 0;
+  int32_t kd = 0;
+  Inst* dI = at<Inst>(ws, L.insts);
+  for (int k = 0; k < k_max; ++k) {
+    const int B = n_slices - k;
+    const Tiles t = choose_tiles(*prob, B);
+    Inst I = make_inst(*prob, B, dt, t);
+    attach_fine(I, ws, L.fine, nullptr);
+    I.vin = U[cur] + (size_t)k * sl;        // U^{n-1,k}, n = k+1..N
+    I.vout = VF + (size_t)(k + 1) * sl;     // P F L(U^{n-1,k})
+    if ((rc = put_insts(dI, &I, 1, s))) return rc;
+    if ((rc = launch_lift_factors(dI, 1, (long long)B * prob->nx, nullptr, st, s))) return rc;
+    int last = 0;
+    if ((rc = run_steps(dI, I, n, kLift, true, t, st, s, &last))) return rc;
+    if ((rc = launch_parareal_sweep(*prob, n_slices, k, U[cur], U[cur ^ 1], VF, Gc,
+                                    span, scratch, &hd->err, st, s)))
+      return rc;
+    struct {
+      int status;
+      int pad;
+      double err;
+    } h;
+    BGK_HIP(hipMemcpyAsync(&h, hd, sizeof(h), hipMemcpyDeviceToHost, s));
+    BGK_HIP(hipStreamSynchronize(s));
+    cur ^= 1;
+    err_hist[k] = h.err;
+    kd = k + 1;
+    if (h.status) {
+      if (k_done) *k_done = kd;
+      set_error("non-physical state during parareal iteration");
+      return BGK_E_NONPHYSICAL;
+    }
+    if (h.err < tol) break;
+  }
+  if (k_done) *k_done = kd;
+  BGK_HIP(hipMemcpyAsync(V_out, U[cur], sl * (n_slices + 1) * sizeof(double),
+                         hipMemcpyDeviceToDevice, s));
+  return BGK_OK;
+}
+
+int bgk_serial_fine(const bgk_problem* prob, const double* W0, int32_t n_slices,
+                    double T, double* V_out, void* ws, size_t ws_bytes,
+                    void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!W0 || !V_out) return invalid("NULL array");
+  if (n_slices < 1 || !(T > 0.0) || !std::isfinite(T)) return invalid("bad n_slices or T");
+  const double span = T / n_slices;
+  int32_t n;
+  double dt;
+  if ((rc = n_steps_for(*prob, span, &n, &dt))) return rc;
+  const Layout L = layout_of(*prob, BGK_OP_PARAREAL, n_slices);
+  if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int* st = &at<WsHeader>(ws, 0)->status;
+  const size_t sl = (size_t)prob->nx * 5;
+  if ((rc = launch_prim_to_cons(W0, V_out, prob->nx, s))) return rc;
+  const Tiles t = choose_tiles(*prob, 1);
+  Inst I = make_inst(*prob, 1, dt, t);
+  attach_fine(I, ws, L.fine, nullptr);
+  Inst* dI = at<Inst>(ws, L.insts);
+  for (int m = 1; m <= n_slices; ++m) {
+    I.vin = V_out + (size_t)(m - 1) * sl;
+    I.vout = V_out + (size_t)m * sl;
+    if ((rc = put_insts(dI, &I, 1, s))) return rc;
+    if ((rc = launch_lift_factors(dI, 1, prob->nx, nullptr, st, s))) return rc;
+    int last = 0;
+    if ((rc = run_steps(dI, I, n, kLift, true, t, st, s, &last))) return rc;
+  }
+  return BGK_OK;
+}
+
+int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
+                     int32_t ckpt_every, int32_t n_steps, double dt,
+                     const double* fbar_T, double* fbar_0, double* dlog_eps,
+                     void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!f_ckpt || !fbar_T || !fbar_0 || !dlog_eps) return invalid("NULL array");
+  if (ckpt_every < 1 || n_steps < 0) return invalid("ckpt_every >= 1, n_steps >= 0");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return invalid("dt must be > 0");
+  const size_t nf = (size_t)prob->nx * nv3_of(*prob);
+  const size_t fbytes = nf * sizeof(double);
+  {
+    const char* a0 = (const char*)fbar_T;
+    const char* b0 = (const char*)fbar_0;
+    if (a0 < b0 + fbytes && b0 < a0 + fbytes) return invalid("fbar_T and fbar_0 overlap");
+  }
+  const Layout L = layout_of(*prob, BGK_OP_ADJOINT, ckpt_every);
+  if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int* st = &at<WsHeader>(ws, 0)->status;
+  const Tiles t = choose_tiles(*prob, 1);
+  Inst base = make_inst(*prob, 1, dt, t);
+  attach_fine(base, ws, L.fine, nullptr);
+  double* states = at<double>(ws, L.states);
+  double* fb[2] = {at<double>(ws, L.fbA), at<double>(ws, L.fbB)};
+  double* part6 = at<double>(ws, L.part6);
+  double* coef = at<double>(ws, L.coef);
+  double* dle = at<double>(ws, L.dle);
+  Inst* dI = at<Inst>(ws, L.insts);
+  BGK_HIP(hipMemcpyAsync(fb[0], fbar_T, fbytes, hipMemcpyDeviceToDevice, s));
+  int cur = 0;
+  const int n_seg = (n_steps + ckpt_every - 1) / ckpt_every;
+  for (int c = n_seg - 1; c >= 0; --c) {
+    const int s0 = c * ckpt_every;
+    const int s1 = std::min(s0 + ckpt_every, (int)n_steps);
+    BGK_HIP(hipMemcpyAsync(states, f_ckpt + (size_t)c * nf, fbytes,
+                           hipMemcpyDeviceToDevice, s));
+    // forward states s0+1 .. s1-1 of the segment (transport, moments, relax)
+    for (int k = s0 + 1; k < s1; ++k) {
+      Inst I = base;
+      I.fin = states + (size_t)(k - 1 - s0) * nf;
+      I.fout = states + (size_t)(k - s0) * nf;
+      if ((rc = put_insts(dI, &I, 1, s))) return rc;
+      if ((rc = launch_step(dI, 1, I.items, kCopy, 1, t.elems, t.chunk,
+                            lds_doubles(I, t), st, s)))
+        return rc;
+      if ((rc = launch_reduce(dI, 1, prob->nx, kRedRelaxFactors, 0, st, s))) return rc;
+      if ((rc = launch_relax_out_blocks(dI, 1, relax_out_blocks(I), I.nvs, 0, s))) return rc;
+    }
+    for (int k = s1 - 1; k >= s0; --k) {
+      Inst I = base;
+      I.fin = states + (size_t)(k - s0) * nf;
+      if ((rc = put_insts(dI, &I, 1, s))) return rc;
+      // g = T f^k into buf[0], moments and the unscaled Maxwellian of U(g)
+      if ((rc = launch_step(dI, 1, I.items, kCopy, 1, t.elems, t.chunk,
+                            lds_doubles(I, t), st, s)))
+        return rc;
+      if ((rc = launch_reduce(dI, 1, prob->nx, kRedMaxwellFactors, 0, st, s))) return rc;
+      if ((rc = launch_adjoint_sums(dI, I, 0, fb[cur], part6, s))) return rc;
+      if ((rc = launch_adjoint_reduce(dI, I, part6, coef, dle, s))) return rc;
+      if ((rc = launch_sum_into(dle, prob->nx, dlog_eps, s))) return rc;
+      if ((rc = launch_adjoint_transpose(dI, I, t.chunk, fb[cur], coef, fb[cur ^ 1], s)))
+        return rc;
+      cur ^= 1;
+    }
+  }
+  BGK_HIP(hipMemcpyAsync(fbar_0, fb[cur], fbytes, hipMemcpyDeviceToDevice, s));
+  return BGK_OK;
+}
+
+int bgk_lift_adjoint_rho(const bgk_problem* prob, const double* W,
+                         const double* fbar, double* rhobar, void* ws,
+                         size_t ws_bytes, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!W || !fbar || !rhobar) return invalid("NULL array");
+  const Layout L = layout_of(*prob, BGK_OP_LIFT, 1);
+  if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const Tiles t = choose_tiles(*prob, 1);
+  Inst I = make_inst(*prob, 1, 1.0, t);
+  attach_fine(I, ws, L.fine, nullptr);
+  Inst* dI = at<Inst>(ws, L.insts);
+  int* st = &at<WsHeader>(ws, 0)->status;
+  if ((rc = put_insts(dI, &I, 1, s))) return rc;
+  if ((rc = launch_lift_factors(dI, 1, prob->nx, W, st, s))) return rc;
+  return launch_lift_adjoint_rho(dI, I, W, fbar, rhobar, s);
+}
+
+__global__ void k_density_adjoint(const double* __restrict__ rhobar, double* fbar,
+                                  long long nv3, long long n, double dv3) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) fbar[k] = rhobar[k / nv3] * dv3;
+}
+
+int bgk_density_adjoint(const bgk_problem* prob, const double* rhobar, double* fbar,
+                        void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!rhobar || !fbar) return invalid("NULL array");
+  const long long nv3 = nv3_of(*prob);
+  const long long n = nv3 * prob->nx;
+  const double dv3 = dv_of(*prob, 0) * dv_of(*prob, 1) * dv_of(*prob, 2);
+  hipLaunchKernelGGL(k_density_adjoint, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, rhobar, fbar, nv3, n, dv3);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+// -------------------------------------------------- uneven batches (C ABI) --
+struct BatchedLayout {
+  size_t header, insts;
+  std::vector<FineRegions> regions;
+  size_t total;
+};
+
+static BatchedLayout batched_layout(const bgk_problem* probs, int n) {
+  Carve c;
+  BatchedLayout L;
+  L.header = c.take(sizeof(WsHeader));
+  L.insts = c.take(sizeof(Inst) * (size_t)n);
+  for (int q = 0; q < n; ++q) L.regions.push_back(carve_fine(c, probs[q], 1, false));
+  L.total = c.off;
+  return L;
+}
+
+size_t bgk_workspace_bytes_batched(const bgk_problem* probs, int32_t n) {
+  if (!probs || n < 1 || n > kMaxInst) return 0;
+  for (int q = 0; q < n; ++q)
+    if (check_problem(&probs[q])) return 0;
+  return batched_layout(probs, n).total;
+}
+
+int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
+                          const double* const* f_in, double* const* f_out,
+                          const double* t_span, int32_t* n_steps_out, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (!probs || !f_in || !f_out || !t_span) return invalid("NULL argument");
+  if (n < 1 || n > kMaxInst) return invalid("n must be in [1, 4096]");
+  int rc;
+  std::vector<int32_t> steps(n);
+  std::vector<double> dts(n);
+  for (int q = 0; q < n; ++q) {
+    if ((rc = check_problem(&probs[q]))) return rc;
+    if (!f_in[q] || !f_out[q]) return invalid("NULL array");
+    if ((rc = n_steps_for(probs[q], t_span[q], &steps[q], &dts[q]))) return rc;
+    const size_t fb = (size_t)probs[q].nx * nv3_of(probs[q]) * sizeof(double);
+    const char* a0 = (const char*)f_in[q];
+    const char* b0 = (const char*)f_out[q];
+    if (a0 < b0 + fb && b0 < a0 + fb) return invalid("f_in and f_out overlap");
+  }
+  const BatchedLayout L = batched_layout(probs, n);
+  if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  if (n_steps_out)
+    for (int q = 0; q < n; ++q) n_steps_out[q] = steps[q];
+  hipStream_t s = (hipStream_t)stream;
+  // one tile shape for all instances; instances sorted by step count
+  // (descending) so that the active ones at any step form a prefix.
+  std::vector<int> order(n);
+  for (int q = 0; q < n; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return steps[x] > steps[y]; });
+  Tiles t = {4, 8};
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_override.elems) t.elems = g_override.elems;
+    if (g_override.chunk) t.chunk = g_override.chunk;
+  }
+  std::vector<Inst> h(n);
+  long long items = 0;
+  int nvs_max = 0;
+  std::vector<long long> items_prefix(n + 1, 0), cells_prefix(n + 1, 0);
+  for (int k = 0; k < n; ++k) {
+    const int q = order[k];
+    Inst I = make_inst(probs[q], 1, dts[q], t);
+    attach_fine(I, ws, L.regions[q], f_out[q]);
+    I.fin = f_in[q];
+    I.fout = f_out[q];
+    I.steps = steps[q];
+    I.item_begin = items;
+    items += I.items;
+    items_prefix[k + 1] = items;
+    cells_prefix[k + 1] = cells_prefix[k] + I.nx;
+    nvs_max = std::max(nvs_max, I.nvs);
+    h[k] = I;
+  }
+  Inst* dI = at<Inst>(ws, L.insts);
+  int* st = &at<WsHeader>(ws, 0)->status;
+  if ((rc = put_insts(dI, h.data(), n, s))) return rc;
+  const int smax = steps[order[0]];
+  int w_prev = 1;
+  for (int k = 1; k <= smax; ++k) {
+    int n_act = 0;
+    while (n_act < n && h[n_act].steps >= k) ++n_act;
+    const int mode = (k == 1) ? kCopy : kRelax;
+    const int phase = w_prev;
+    double cells = 0.0;
+    for (int q = 0; q < n_act; ++q) cells += (double)h[q].nx * h[q].nv3;
+    prof_before(s);
+    rc = launch_step(dI, n_act, items_prefix[n_act], mode, phase, t.elems, t.chunk,
+                     (t.chunk + 2) * nvs_max, st, s);
+    prof_after(s, cells);
+    if (rc) return rc;
+    if ((rc = launch_reduce(dI, n_act, cells_prefix[n_act], kRedRelaxFactors, 0, st, s)))
+      return rc;
+    w_prev = phase ^ 1;
+  }
+  // final relaxation, each instance from the buffer its last step wrote:
+  // step k writes buf[(k - 1) & 1]
+  for (int k = 0; k < n; ++k) {
+    const int sel = (h[k].steps - 1) & 1;
+    if ((rc = launch_relax_out_blocks(dI + k, 1, relax_out_blocks(h[k]), h[k].nvs, sel, s)))
+      return rc;
+  }
+  return BGK_OK;
+}
+
+// ------------------------------------------------------- tiles / autotune --
+int bgk_set_tiles(int32_t elems, int32_t chunk) {
+  if (!(elems == 0 || elems == 2 || elems == 4 || elems == 8))
+    return invalid("elems_per_lane must be 0, 2, 4 or 8");
+  if (chunk < 0 || chunk > kMaxChunk) return invalid("x_chunk must be in [0, 64]");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_override = {elems, chunk};
+  return BGK_OK;
+}
+
+int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_bytes,
+                 void* stream, int32_t* best_elems, int32_t* best_chunk) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (batch < 1) return invalid("batch must be >= 1");
+  const Layout L = layout_of(*prob, BGK_OP_PROPAGATE, batch);
+  if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  // moments of a smooth state to lift from
+  std::vector<double> hV((size_t)batch * prob->nx * 5);
+  for (int b = 0; b < batch; ++b)
+    for (int i = 0; i < prob->nx; ++i) {
+      double* v = &hV[((size_t)b * prob->nx + i) * 5];
+      v[0] = 1.0 + 0.1 * std::sin(6.283185307179586 * (i + 0.5) / prob->nx);
+      v[1] = v[2] = v[3] = 0.0;
+      v[4] = 1.5 * v[0];
+    }
+  double* Vin = at<double>(ws, L.fine.vg);   // borrow: lifted from before steps
+  double* Vout = at<double>(ws, L.fine.vout);
+  const int steps = 4;
+  const double dt = 0.5 * dx_of(*prob) / std::max(std::fabs(prob->v_lo[0]), std::fabs(prob->v_hi[0]));
+  hipEvent_t e0, e1;
+  BGK_HIP(hipEventCreate(&e0));
+  BGK_HIP(hipEventCreate(&e1));
+  Tiles best = {0, 0};
+  float best_ms = 1e30f;
+  const int Es[3] = {2, 4, 8};
+  const int Cs[6] = {1, 2, 4, 8, 16, 32};
+  for (int ei = 0; ei < 3; ++ei)
+    for (int ci = 0; ci < 6; ++ci) {
+      Tiles t = {Es[ei], Cs[ci]};
+      if (t.chunk > prob->nx) continue;
+      Inst I = make_inst(*prob, batch, dt, t);
+      attach_fine(I, ws, L.fine, nullptr);
+      I.vin = Vin;
+      I.vout = Vout;
+      Inst* dI = at<Inst>(ws, L.insts);
+      int* st = &at<WsHeader>(ws, 0)->status;
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        BGK_HIP(hipMemcpyAsync(Vin, hV.data(), hV.size() * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+        if ((rc = put_insts(dI, &I, 1, s))) break;
+        if ((rc = launch_lift_factors(dI, 1, (long long)batch * prob->nx, nullptr, st, s))) break;
+        BGK_HIP(hipEventRecord(e0, s));
+        int last = 0;
+        if ((rc = run_steps(dI, I, steps, kLift, false, t, st, s, &last))) break;
+        BGK_HIP(hipEventRecord(e1, s));
+        BGK_HIP(hipEventSynchronize(e1));
+        BGK_HIP(hipEventElapsedTime(&ms, e0, e1));
+      }
+      if (rc) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return rc;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tuned[{prob->nx, prob->nv[0], prob->nv[1], prob->nv[2], batch}] = best;
+  }
+  if (best_elems) *best_elems = best.elems;
+  if (best_chunk) *best_chunk = best.chunk;
+  return BGK_OK;
+}
+
+// -------------------------------------------------------------- profiling --
+int bgk_prof_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_prof) {
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof.clear();
+  g_prof_on = on != 0;
+  return BGK_OK;
+}
+
+int bgk_prof_read(double* total_ms, int64_t* launches, double* cells) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double ms = 0.0, c = 0.0;
+  for (auto& r : g_prof) {
+    BGK_HIP(hipEventSynchronize(r.b));
+    float x = 0.f;
+    BGK_HIP(hipEventElapsedTime(&x, r.a, r.b));
+    ms += x;
+    c += r.cells;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = (int64_t)g_prof.size();
+  if (cells) *cells = c;
+  return BGK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+// Internal declarations of libbgk (HIP, gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "bgk.h"
+
+namespace bgk {
+
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kWavesPerBlock = 4;    // fused step kernel: 4 independent waves
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kMinElems = 2;         // smallest velocity elements per lane
+constexpr int kMaxNv = 256;          // per velocity axis
+constexpr int kMaxChunk = 64;        // x cells per work item
+constexpr int kNumXcd = 8;           // MI355X: 8 accelerator complex dies
+
+// One problem (or a batch of same-grid members) as the kernels see it.  All
+// members b share the grid; member b's arrays start at b * (member stride).
+struct Inst {
+  int nx, nvx, nvy, nvz;
+  int nv3, nvs, bc, nbatch;    // nvs = nvx + nvy + nvz (factor row length)
+  int ntiles;                  // velocity tiles of kWave*E elements per x cell
+  int ntg;                     // tile groups (kWavesPerBlock tiles) per x cell
+  int nchunks;                 // x chunks of L cells
+  int steps;                   // steps this instance takes (uneven batches)
+  long long item_begin;        // first work item of this instance
+  long long items;             // nbatch * ntg * nchunks
+  int part_tiles;              // tile capacity of `part` per x cell
+  int pad_;
+  double vlo[3], dv[3];        // v_a(j) = vlo[a] + (j + 1/2) dv[a]
+  double dv3;                  // dv[0] dv[1] dv[2]
+  double r;                    // dt / dx
+  double a;                    // 1 / (1 + lambda)
+  double al;                   // lambda / (1 + lambda)
+  const double* fin;           // step-0 source in copy mode    [nbatch][nx][nv3]
+  double* buf[2];              // ping-pong g = f* buffers      [nbatch][nx][nv3]
+  double* fout;                // relaxed output                [nbatch][nx][nv3]
+  double* part;                // wave partial sums    [nbatch][nx][part_tiles][5]
+  double* fac;                 // Maxwellian factors            [nbatch][nx][nvs]
+  double* vg;                  // conserved moments of g        [nbatch][nx][5]
+  const double* vin;           // lift source moments (conserved)[nbatch][nx][5]
+  double* vout;                // projected relaxed moments     [nbatch][nx][5]
+};
+
+// Step-kernel source modes.
+enum StepMode : int {
+  kCopy = 0,   // f = fin (first step of a plain fine solve)
+  kRelax = 1,  // f = a g + F  (relax-then-transport: g from the last step)
+  kLift = 2,   // f = F        (Maxwellian lift fused into the first step)
+};
+
+// Reduce-kernel outputs.
+enum ReduceMode : int {
+  kRedRelaxFactors = 0,  // V(g) and relaxation factors al*M[U(g)]
+  kRedProject = 1,       // V(g) and vout = a V(g) + al V(M[U(g)])
+  kRedMomentsOnly = 2,   // V(g) into vg (and W into vout if set)
+  kRedMaxwellFactors = 3,  // V(g) and unscaled factors M[U(g)] (adjoint)
+};
+
+// ---------------------------------------------------------------- errors --
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define BGK_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return ::bgk::hip_fail(e_, #call); \
+  } while (0)
+
+// --------------------------------------------------------- host helpers --
+int check_problem(const bgk_problem* p);
+double dx_of(const bgk_problem& p);
+double dv_of(const bgk_problem& p, int a);
+int n_steps_for(const bgk_problem& p, double t_span, int32_t* n, double* dt);
+size_t align_up(size_t n, size_t a = 256);
+
+// Workspace header (first 256 bytes of every workspace).
+struct WsHeader {
+  int status;        // sticky non-physical flag
+  int pad0;
+  double err;        // parareal successive error
+  double scratch[30];
+};
+
+// ------------------------------------------------------------ launchers --
+struct Tiles {
+  int elems;   // velocity elements per lane
+  int chunk;   // x cells per work item
+};
+
+Tiles choose_tiles(const bgk_problem& p, int batch);
+
+// Fused relax-then-transport step over all instances in `d_insts`.
+int launch_step(const Inst* d_insts, int n_inst, long long total_items,
+                int mode, int phase, int elems, int chunk, int lds_doubles,
+                int* d_status, hipStream_t s);
+// Per-x-cell reduction of partial sums into moments and factors.
+int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
+                  int mode, int phase, int* d_status, hipStream_t s);
+// Lift factors from conserved (vin) or primitive moments.
+int launch_lift_factors(const Inst* d_insts, int n_inst, long long total_cells,
+                        const double* W, int* d_status, hipStream_t s);
+// Partial sums of an arbitrary f (source = fin), no transport.
+int launch_partials(const Inst* d_insts, int n_inst, long long total_items,
+                    int elems, int chunk, hipStream_t s);
+
+// Coarse Euler propagation, one workgroup per batch member.
+int launch_euler(const bgk_problem& p, int batch, const double* V_in,
+                 double* V_out, double t_span, int* n_sub, double* scratch,
+                 int* d_status, hipStream_t s);
+// Parareal initial coarse sweep and per-iteration correction sweep.
+int launch_pararealsweep_init(const bgk_problem& p, int n_slices,
+                              const double* W0, double* U, double* Gc,
+                              double t_span, double* scratch, int* d_status,
+                              hipStream_t s);
+int launch_parareal_sweep(const bgk_problem& p, int n_slices, int k,
+                          const double* U_old, double* U_new, const double* VF,
+                          double* Gc, double t_span, double* scratch,
+                          double* d_err, int* d_status, hipStream_t s);
+int launch_prim_to_cons(const double* W, double* V, int n, hipStream_t s);
+
+// f_out = a g + F from buf[src_sel], or f_out = F (pure lift) if src_sel < 0.
+int launch_relax_out_blocks(const Inst* d_insts, int n_inst, long long blocks,
+                            int nvs_max, int src_sel, hipStream_t s);
+
+// Adjoint kernels (single instance, nbatch = 1).  g is read from
+// buf[g_sel]; factors in fac are the unscaled Maxwellian of U(g).
+int launch_adjoint_sums(const Inst* d_inst, const Inst& h_inst, int g_sel,
+                        const double* fbar_next, double* part6, hipStream_t s);
+int launch_adjoint_reduce(const Inst* d_inst, const Inst& h_inst,
+                          const double* part6, double* coef,
+                          double* dle_cells, hipStream_t s);
+int launch_adjoint_transpose(const Inst* d_inst, const Inst& h_inst, int chunk,
+                             const double* fbar_next, const double* coef,
+                             double* fbar_prev, hipStream_t s);
+int launch_sum_into(const double* cells, int n, double* acc, hipStream_t s);
+int launch_lift_adjoint_rho(const Inst* d_inst, const Inst& h_inst,
+                            const double* W, const double* fbar, double* rhobar,
+                            hipStream_t s);
+
+constexpr int kAdjElems = 4;  // velocity elements per lane in adjoint kernels
+
+// Profiling of the fused step kernel.
+void prof_before(hipStream_t s);
+void prof_after(hipStream_t s, double cells);
+
+}  // namespace bgk

@@ -1,0 +1,576 @@
+// Fine kinetic propagator kernels for gfx950 (CDNA4), FP64.
+//
+// One IMEX step (Section 3.1) is upwind transport in x, moments of the
+// transported field, the Maxwellian of those moments and the implicit BGK
+// relaxation f = (f* + lambda M[P f*]) / (1 + lambda).  The relaxation only
+// needs each x cell's moments, so the kernels store g = f* (the transported,
+// not yet relaxed field) and relax it on the fly when it is read by the next
+// step ("relax-then-transport"): every step then reads g once and writes it
+// once (16 bytes per phase-space update), and the moments are carried between
+// steps as deterministic per-wave partial sums.
+//
+// Layout: g[member][x][v] with the flat velocity index fastest.  A wave owns a
+// tile of 64*E velocities (element e of lane l at tile*64E + e*64 + l, so every
+// load and store instruction of a wave covers 512 contiguous bytes) and
+// marches along a chunk of x cells, keeping rows i-1, i, i+1 in registers;
+// only the two halo rows of a chunk are read twice.  The Maxwellian is
+// separable, M = C Ex(v_x) Ey(v_y) Ez(v_z), so a step needs 3 Nv exponentials
+// per x cell (computed once per cell by the reduce kernel) and a workgroup
+// stages the factor rows of its chunk in LDS.
+#include "bgk_internal.h"
+
+#ifndef BGK_WAVE_REDUCE_DPP
+#define BGK_WAVE_REDUCE_DPP 1
+#endif
+
+namespace bgk {
+
+// ------------------------------------------------------------- helpers --
+
+// Bijective block -> work-item map that gives each XCD a contiguous range of
+// work items (blocks are dispatched round-robin over the 8 XCDs), so x-chunk
+// neighbours that share halo rows share an L2.
+__device__ __forceinline__ long long xcd_item(unsigned b, unsigned n) {
+  unsigned per = n / kNumXcd, rem = n % kNumXcd;
+  unsigned x = b % kNumXcd, k = b / kNumXcd;
+  return (x < rem) ? (long long)x * (per + 1) + k
+                   : (long long)rem * (per + 1) + (long long)(x - rem) * per + k;
+}
+
+__device__ __forceinline__ int ghost_row(int i, int nx, int bc) {
+  if (i < 0) return bc == 1 ? i + nx : 0;
+  if (i >= nx) return bc == 1 ? i - nx : nx - 1;
+  return i;
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_mov(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, true);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave; the total is valid in lane 63.  Fixed
+// combination order, so results are bitwise reproducible.
+__device__ __forceinline__ double wave_sum_to_last(double v) {
+#if BGK_WAVE_REDUCE_DPP
+  v += dpp_mov<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_mov<0x118, 0xf>(v);  // row_shr:8   -> lane 15 of each row
+  v += dpp_mov<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp_mov<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+  return v;
+#else
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+#endif
+}
+
+__device__ __forceinline__ double wave_sum_all(double v) {
+  return readlane_d(wave_sum_to_last(v), kWave - 1);
+}
+
+__device__ __forceinline__ int find_inst(const Inst* insts, int n_inst,
+                                         long long item) {
+  int q = 0;
+  while (q + 1 < n_inst && insts[q + 1].item_begin <= item) ++q;
+  return q;
+}
+
+__device__ __forceinline__ double vgrid(const Inst& I, int a, int j) {
+  return I.vlo[a] + (j + 0.5) * I.dv[a];
+}
+
+// Per-lane velocity elements of one tile.
+template <int E>
+struct Elems {
+  unsigned off[E];  // LDS factor offsets: ox | oy << 10 | oz << 20
+  double vx[E], vy[E], vz[E];
+  bool ok[E];
+};
+
+template <int E>
+__device__ __forceinline__ void setup_elems(const Inst& I, int tile, int lane,
+                                            Elems<E>& el) {
+  const int nyz = I.nvy * I.nvz;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    int j = tile * (kWave * E) + e * kWave + lane;
+    el.ok[e] = j < I.nv3;
+    int jj = el.ok[e] ? j : 0;
+    int jx = jj / nyz;
+    int rem = jj - jx * nyz;
+    int jy = rem / I.nvz;
+    int jz = rem - jy * I.nvz;
+    el.off[e] = (unsigned)jx | ((unsigned)(I.nvx + jy) << 10) |
+                ((unsigned)(I.nvx + I.nvy + jz) << 20);
+    el.vx[e] = vgrid(I, 0, jx);
+    el.vy[e] = vgrid(I, 1, jy);
+    el.vz[e] = vgrid(I, 2, jz);
+  }
+}
+
+__device__ __forceinline__ double fac3(const double* row, unsigned off) {
+  return row[off & 1023u] * row[(off >> 10) & 1023u] * row[off >> 20];
+}
+
+// ---------------------------------------------------- fused step kernel --
+// Work item = (instance, member b, tile group, x chunk); 4 waves per block
+// share the chunk (and its LDS factor rows) and take consecutive tiles.
+template <int E, int MODE>
+__global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
+                                                 int n_inst, int chunk,
+                                                 int phase) {
+  extern __shared__ double lds[];
+  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const int q = find_inst(insts, n_inst, item);
+  const Inst& I = insts[q];
+  const long long local = item - I.item_begin;
+  const int c = (int)(local % I.nchunks);
+  const long long t = local / I.nchunks;
+  const int tg = (int)(t % I.ntg);
+  const int b = (int)(t / I.ntg);
+  const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
+  const int i0 = c * chunk;
+  const int i1 = min(i0 + chunk, nx);
+
+  if (MODE != kCopy) {
+    // factor rows of cells i0-1 .. i1 (ghosts mapped by the BC)
+    const int rows = i1 - i0 + 2;
+    const double* fac = I.fac + (long long)b * nx * nvs;
+    for (int idx = threadIdx.x; idx < rows * nvs; idx += kBlock) {
+      int rr = idx / nvs;
+      int k = idx - rr * nvs;
+      lds[idx] = fac[(long long)ghost_row(i0 - 1 + rr, nx, I.bc) * nvs + k];
+    }
+    __syncthreads();
+  }
+
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int tile = tg * kWavesPerBlock + wave;
+  if (tile >= I.ntiles) return;
+
+  Elems<E> el;
+  setup_elems<E>(I, tile, lane, el);
+  const long long mbase = (long long)b * nx * nv3;
+  const double* src = (MODE == kCopy) ? I.fin : I.buf[phase];
+  double* dst = I.buf[phase ^ 1];
+  src += mbase + tile * (kWave * E) + lane;
+  dst += mbase + tile * (kWave * E) + lane;
+  const double a = I.a;
+  double nu[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) nu[e] = el.vx[e] * I.r;
+
+  // relaxed value of row r (global row index, ghost-mapped) from raw g
+  auto relax_row = [&](int r, const double* raw, double* out) {
+    const double* frow = lds + (r - (i0 - 1)) * nvs;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      double v;
+      if (MODE == kCopy) v = raw[e];
+      else if (MODE == kRelax) v = fma(a, raw[e], fac3(frow, el.off[e]));
+      else v = fac3(frow, el.off[e]);
+      out[e] = el.ok[e] ? v : 0.0;
+    }
+  };
+  auto load_row = [&](int r, double* raw) {
+    if (MODE == kLift) return;
+    const long long ro = (long long)ghost_row(r, nx, I.bc) * nv3;
+#pragma unroll
+    for (int e = 0; e < E; ++e) raw[e] = el.ok[e] ? src[ro + e * kWave] : 0.0;
+  };
+
+  double fm[E], f0[E], fp[E], rawp[E], rawn[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) rawn[e] = 0.0;
+  {
+    double raw[E];
+    load_row(i0 - 1, raw);
+    load_row(i0, rawp);
+    relax_row(i0 - 1, raw, fm);
+    load_row(i0 + 1, raw);
+    relax_row(i0, rawp, f0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) rawp[e] = raw[e];
+  }
+  double* part = I.part + (((long long)b * nx) * I.part_tiles + tile) * 5;
+  for (int i = i0; i < i1; ++i) {
+    if (i + 2 <= i1) load_row(i + 2, rawn);  // prefetch the next row
+    relax_row(i + 1, rawp, fp);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double nb = nu[e] > 0.0 ? fm[e] : fp[e];
+      const double gs = fma(fabs(nu[e]), nb - f0[e], f0[e]);
+      if (el.ok[e]) dst[(long long)i * nv3 + e * kWave] = gs;
+      const double vsq = el.vx[e] * el.vx[e] + el.vy[e] * el.vy[e] +
+                         el.vz[e] * el.vz[e];
+      s0 += gs;
+      s1 = fma(el.vx[e], gs, s1);
+      s2 = fma(el.vy[e], gs, s2);
+      s3 = fma(el.vz[e], gs, s3);
+      s4 = fma(vsq, gs, s4);
+    }
+    s0 = wave_sum_to_last(s0);
+    s1 = wave_sum_to_last(s1);
+    s2 = wave_sum_to_last(s2);
+    s3 = wave_sum_to_last(s3);
+    s4 = wave_sum_to_last(s4);
+    if (lane == kWave - 1) {
+      double* pp = part + (long long)i * I.part_tiles * 5;
+      pp[0] = s0;
+      pp[1] = s1;
+      pp[2] = s2;
+      pp[3] = s3;
+      pp[4] = s4;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      fm[e] = f0[e];
+      f0[e] = fp[e];
+      rawp[e] = rawn[e];
+    }
+  }
+}
+
+// -------------------------------------------- partial sums of a field --
+// Moments of an arbitrary f (source fin), same tiling, no transport.
+template <int E>
+__global__ __launch_bounds__(kBlock) void k_partials(
+    const Inst* __restrict__ insts, int n_inst, int chunk) {
+  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const int q = find_inst(insts, n_inst, item);
+  const Inst& I = insts[q];
+  const long long local = item - I.item_begin;
+  const int c = (int)(local % I.nchunks);
+  const long long t = local / I.nchunks;
+  const int tg = (int)(t % I.ntg);
+  const int b = (int)(t / I.ntg);
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int tile = tg * kWavesPerBlock + wave;
+  if (tile >= I.ntiles) return;
+  const int nx = I.nx, nv3 = I.nv3;
+  const int i0 = c * chunk, i1 = min(i0 + chunk, nx);
+  Elems<E> el;
+  setup_elems<E>(I, tile, lane, el);
+  const double* src = I.fin + (long long)b * nx * nv3 + tile * (kWave * E) + lane;
+  double* part = I.part + (((long long)b * nx) * I.part_tiles + tile) * 5;
+  for (int i = i0; i < i1; ++i) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double g = el.ok[e] ? src[(long long)i * nv3 + e * kWave] : 0.0;
+      const double vsq = el.vx[e] * el.vx[e] + el.vy[e] * el.vy[e] +
+                         el.vz[e] * el.vz[e];
+      s0 += g;
+      s1 = fma(el.vx[e], g, s1);
+      s2 = fma(el.vy[e], g, s2);
+      s3 = fma(el.vz[e], g, s3);
+      s4 = fma(vsq, g, s4);
+    }
+    s0 = wave_sum_to_last(s0);
+    s1 = wave_sum_to_last(s1);
+    s2 = wave_sum_to_last(s2);
+    s3 = wave_sum_to_last(s3);
+    s4 = wave_sum_to_last(s4);
+    if (lane == kWave - 1) {
+      double* pp = part + (long long)i * I.part_tiles * 5;
+      pp[0] = s0;
+      pp[1] = s1;
+      pp[2] = s2;
+      pp[3] = s3;
+      pp[4] = s4;
+    }
+  }
+}
+
+// ------------------------------------------------------- cell reduction --
+__device__ __forceinline__ int find_inst_cell(const Inst* insts, int n_inst,
+                                              long long cell,
+                                              long long* cell_local) {
+  long long begin = 0;
+  int q = 0;
+  for (;;) {
+    long long n = (long long)insts[q].nbatch * insts[q].nx;
+    if (cell < begin + n || q + 1 == n_inst) break;
+    begin += n;
+    ++q;
+  }
+  *cell_local = cell - begin;
+  return q;
+}
+
+__device__ __forceinline__ bool physical(double rho, double th) {
+  return rho > 0.0 && th > 0.0 && isfinite(rho) && isfinite(th);
+}
+
+// Writes factor row k in [0, nvs): Ex scaled by C, Ey, Ez.
+__device__ __forceinline__ void write_factors(const Inst& I, double* row,
+                                              int lane, double C,
+                                              const double u[3], double th) {
+  const double inv2t = 1.0 / (2.0 * th);
+  for (int k = lane; k < I.nvs; k += kWave) {
+    int ax = (k < I.nvx) ? 0 : (k < I.nvx + I.nvy ? 1 : 2);
+    int j = k - (ax == 0 ? 0 : (ax == 1 ? I.nvx : I.nvx + I.nvy));
+    double d = vgrid(I, ax, j) - u[ax];
+    double e = exp(-d * d * inv2t);
+    row[k] = ax == 0 ? C * e : e;
+  }
+}
+
+// One wave per (instance, member, x cell).
+__global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ insts,
+                                                   int n_inst,
+                                                   long long total_cells,
+                                                   int mode, int* status) {
+  const long long cell = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (cell >= total_cells) return;
+  const int lane = threadIdx.x % kWave;
+  long long cl;
+  const int q = find_inst_cell(insts, n_inst, cell, &cl);
+  const Inst& I = insts[q];
+  const double* pp = I.part + cl * I.part_tiles * 5;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t = lane; t < I.ntiles; t += kWave) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) s[c] += pp[t * 5 + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) s[c] = wave_sum_all(s[c]);
+  const double rho = s[0] * I.dv3;
+  const double m[3] = {s[1] * I.dv3, s[2] * I.dv3, s[3] * I.dv3};
+  const double E = 0.5 * s[4] * I.dv3;
+  const double u[3] = {m[0] / rho, m[1] / rho, m[2] / rho};
+  const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const double th = (2.0 * E / rho - usq) / 3.0;
+  if (lane == 0) {
+    double* vg = I.vg + cl * 5;
+    vg[0] = rho;
+    vg[1] = m[0];
+    vg[2] = m[1];
+    vg[3] = m[2];
+    vg[4] = E;
+    if (!physical(rho, th)) *status = 1;
+  }
+  if (mode == kRedMomentsOnly) {
+    if (I.vout != nullptr && lane == 0) {
+      double* w = I.vout + cl * 5;
+      w[0] = rho;
+      w[1] = u[0];
+      w[2] = u[1];
+      w[3] = u[2];
+      w[4] = th;
+    }
+    return;
+  }
+  const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
+  if (mode == kRedRelaxFactors || mode == kRedMaxwellFactors) {
+    write_factors(I, I.fac + cl * I.nvs, lane,
+                  mode == kRedRelaxFactors ? I.al * C0 : C0, u, th);
+    return;
+  }
+  // kRedProject: moments of the relaxed field a g + al M[U(g)], with the
+  // moments of the separable Maxwellian as products of 1D sums.
+  double t9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const double inv2t = 1.0 / (2.0 * th);
+  for (int k = lane; k < I.nvs; k += kWave) {
+    int ax = (k < I.nvx) ? 0 : (k < I.nvx + I.nvy ? 1 : 2);
+    int j = k - (ax == 0 ? 0 : (ax == 1 ? I.nvx : I.nvx + I.nvy));
+    double v = vgrid(I, ax, j);
+    double d = v - u[ax];
+    double e = exp(-d * d * inv2t);
+#pragma unroll
+    for (int a2 = 0; a2 < 3; ++a2) {
+      if (a2 == ax) {
+        t9[3 * a2] += e;
+        t9[3 * a2 + 1] += v * e;
+        t9[3 * a2 + 2] += v * v * e;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) t9[c] = wave_sum_all(t9[c]);
+  const double K = C0 * I.dv3;
+  const double X0 = t9[0], X1 = t9[1], X2 = t9[2];
+  const double Y0 = t9[3], Y1 = t9[4], Y2 = t9[5];
+  const double Z0 = t9[6], Z1 = t9[7], Z2 = t9[8];
+  const double vm[5] = {K * X0 * Y0 * Z0, K * X1 * Y0 * Z0, K * X0 * Y1 * Z0,
+                        K * X0 * Y0 * Z1,
+                        0.5 * K * (X2 * Y0 * Z0 + X0 * Y2 * Z0 + X0 * Y0 * Z2)};
+  const double vgv[5] = {rho, m[0], m[1], m[2], E};
+  if (lane == 0) {
+    double* vo = I.vout + cl * 5;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) vo[c] = I.a * vgv[c] + I.al * vm[c];
+  }
+}
+
+// Lift factors: C = rho (2 pi theta)^{-3/2} from primitive W (if given) or
+// from the conserved vin of each member.
+__global__ __launch_bounds__(kBlock) void k_lift_factors(
+    const Inst* __restrict__ insts, int n_inst, long long total_cells,
+    const double* __restrict__ W, int* status) {
+  const long long cell = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (cell >= total_cells) return;
+  const int lane = threadIdx.x % kWave;
+  long long cl;
+  const int q = find_inst_cell(insts, n_inst, cell, &cl);
+  const Inst& I = insts[q];
+  double rho, u[3], th;
+  if (W != nullptr) {
+    const double* w = W + cl * 5;
+    rho = w[0];
+    u[0] = w[1];
+    u[1] = w[2];
+    u[2] = w[3];
+    th = w[4];
+  } else {
+    const double* v = I.vin + cl * 5;
+    rho = v[0];
+    u[0] = v[1] / rho;
+    u[1] = v[2] / rho;
+    u[2] = v[3] / rho;
+    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    th = (2.0 * v[4] / rho - usq) / 3.0;
+  }
+  if (!physical(rho, th) || !isfinite(u[0]) || !isfinite(u[1]) || !isfinite(u[2])) {
+    if (lane == 0) *status = 1;
+  }
+  write_factors(I, I.fac + cl * I.nvs, lane, rho * pow(2.0 * M_PI * th, -1.5),
+                u, th);
+}
+
+// f_out = a g + F (relaxation of the last transported field), or f_out = F
+// when src_sel < 0 (pure lift).  One block per (cell, 1024-element slab).
+__global__ __launch_bounds__(kBlock) void k_relax_out(
+    const Inst* __restrict__ insts, int n_inst, long long total_cells,
+    int src_sel) {
+  extern __shared__ double lds[];
+  const long long blk = blockIdx.x;
+  // find the cell: each instance contributes nbatch*nx*slabs blocks
+  long long begin = 0;
+  int q = 0;
+  long long slabs = 0;
+  for (;;) {
+    slabs = (insts[q].nv3 + 4 * kBlock - 1) / (4 * kBlock);
+    long long n = (long long)insts[q].nbatch * insts[q].nx * slabs;
+    if (blk < begin + n || q + 1 == n_inst) break;
+    begin += n;
+    ++q;
+  }
+  const Inst& I = insts[q];
+  const long long local = blk - begin;
+  const long long cl = local / slabs;
+  const int slab = (int)(local % slabs);
+  const double* frow = I.fac + cl * I.nvs;
+  for (int k = threadIdx.x; k < I.nvs; k += kBlock) lds[k] = frow[k];
+  __syncthreads();
+  const int nyz = I.nvy * I.nvz;
+  const double* g = src_sel >= 0 ? I.buf[src_sel] + cl * I.nv3 : nullptr;
+  double* out = I.fout + cl * I.nv3;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    int j = slab * 4 * kBlock + e * kBlock + threadIdx.x;
+    if (j >= I.nv3) break;
+    int jx = j / nyz;
+    int rem = j - jx * nyz;
+    int jy = rem / I.nvz;
+    int jz = rem - jy * I.nvz;
+    double F = lds[jx] * lds[I.nvx + jy] * lds[I.nvx + I.nvy + jz];
+    out[j] = g ? fma(I.a, g[j], F) : F;
+  }
+  (void)total_cells;
+}
+
+// ------------------------------------------------------------- launchers --
+static int blocks_for(long long n) { return (int)n; }
+
+int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode,
+                int phase, int elems, int chunk, int lds_doubles, int* d_status,
+                hipStream_t s) {
+  (void)d_status;
+  if (total_items <= 0) return BGK_OK;
+  dim3 grid(blocks_for(total_items)), block(kBlock);
+  size_t lds = (mode == kCopy) ? 0 : (size_t)lds_doubles * sizeof(double);
+#define BGK_STEP_CASE(EE, MM)                                               \
+  if (elems == EE && mode == MM) {                                          \
+    hipLaunchKernelGGL((k_step<EE, MM>), grid, block, lds, s, d_insts,      \
+                       n_inst, chunk, phase);                               \
+    hipError_t e_ = hipGetLastError();                                      \
+    return e_ == hipSuccess ? BGK_OK : hip_fail(e_, "k_step");              \
+  }
+  BGK_STEP_CASE(2, kCopy)
+  BGK_STEP_CASE(2, kRelax)
+  BGK_STEP_CASE(2, kLift)
+  BGK_STEP_CASE(4, kCopy)
+  BGK_STEP_CASE(4, kRelax)
+  BGK_STEP_CASE(4, kLift)
+  BGK_STEP_CASE(8, kCopy)
+  BGK_STEP_CASE(8, kRelax)
+  BGK_STEP_CASE(8, kLift)
+#undef BGK_STEP_CASE
+  set_error("unsupported tile shape");
+  return BGK_E_INVALID;
+}
+
+int launch_partials(const Inst* d_insts, int n_inst, long long total_items,
+                    int elems, int chunk, hipStream_t s) {
+  if (total_items <= 0) return BGK_OK;
+  dim3 grid(blocks_for(total_items)), block(kBlock);
+  if (elems == 2)
+    hipLaunchKernelGGL(k_partials<2>, grid, block, 0, s, d_insts, n_inst, chunk);
+  else if (elems == 4)
+    hipLaunchKernelGGL(k_partials<4>, grid, block, 0, s, d_insts, n_inst, chunk);
+  else if (elems == 8)
+    hipLaunchKernelGGL(k_partials<8>, grid, block, 0, s, d_insts, n_inst, chunk);
+  else {
+    set_error("unsupported tile shape");
+    return BGK_E_INVALID;
+  }
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
+                  int mode, int phase, int* d_status, hipStream_t s) {
+  (void)phase;
+  if (total_cells <= 0) return BGK_OK;
+  dim3 grid((unsigned)((total_cells + kWavesPerBlock - 1) / kWavesPerBlock));
+  hipLaunchKernelGGL(k_reduce, grid, dim3(kBlock), 0, s, d_insts, n_inst,
+                     total_cells, mode, d_status);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+int launch_lift_factors(const Inst* d_insts, int n_inst, long long total_cells,
+                        const double* W, int* d_status, hipStream_t s) {
+  if (total_cells <= 0) return BGK_OK;
+  dim3 grid((unsigned)((total_cells + kWavesPerBlock - 1) / kWavesPerBlock));
+  hipLaunchKernelGGL(k_lift_factors, grid, dim3(kBlock), 0, s, d_insts, n_inst,
+                     total_cells, W, d_status);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+int launch_relax_out_blocks(const Inst* d_insts, int n_inst, long long blocks,
+                            int nvs_max, int src_sel, hipStream_t s) {
+  if (blocks <= 0) return BGK_OK;
+  hipLaunchKernelGGL(k_relax_out, dim3((unsigned)blocks), dim3(kBlock),
+                     (size_t)nvs_max * sizeof(double), s, d_insts, n_inst,
+                     (long long)0, src_sel);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+}  // namespace bgk
