@@ -198,22 +198,35 @@ const char* bgk_status_string(int status);
 const char* bgk_last_error(void);
 
 /* Tile shape of the fused step kernel: velocity elements per lane (2, 4 or 8)
- * and x cells per work item (1..64).  0 restores the built-in choice. */
-int bgk_set_tiles(int32_t elems_per_lane, int32_t x_chunk);
+ * and x cells per work item (1..64); 0 restores the built-in choice.  pair:
+ * 1 = lanes own pairs of adjacent v_z cells (used only when nv[2] is even and
+ * f is 16-byte aligned), 0 = one velocity per lane slot, -1 = built-in. */
+int bgk_set_tiles(int32_t elems_per_lane, int32_t x_chunk, int32_t pair);
 
 /* Times candidate tile shapes on `prob` with `batch` members (uses ws of
  * BGK_OP_PROPAGATE size; synchronises) and keeps the fastest for problems of
- * the same grid and batch.  [host] best_elems, best_chunk (nullable). */
+ * the same grid and batch.  [host] best_elems, best_chunk, best_pair
+ * (nullable). */
 int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws,
                  size_t ws_bytes, void* stream, int32_t* best_elems,
-                 int32_t* best_chunk);
+                 int32_t* best_chunk, int32_t* best_pair);
+
+/* Launch-bound sequences (each parareal iteration, the serial chain of
+ * bgk_serial_fine) are captured as HIP graphs on first use and replayed;
+ * 0 turns this off (every kernel launched on the stream directly), 1 on
+ * (default).  Kernel timing (bgk_prof_enable) always launches directly. */
+int bgk_set_graphs(int32_t on);
 
 /* Kernel timing of the fused step kernel: when on, every launch of it is
  * bracketed by HIP events on its stream.  bgk_prof_read synchronises and
- * returns the summed milliseconds, the launch count and the phase-space
- * cells updated (all since the last bgk_prof_enable(1)). */
+ * returns the summed milliseconds, the launch count, the phase-space cells
+ * updated and the algorithmic bytes moved (16 per cell for a step that reads
+ * and writes f, 8 for the first step of a slice, which computes the lifted
+ * Maxwellian instead of reading), all since the last bgk_prof_enable(1).
+ * [host] outputs, each nullable. */
 int bgk_prof_enable(int32_t on);
-int bgk_prof_read(double* total_ms, int64_t* launches, double* cells);
+int bgk_prof_read(double* total_ms, int64_t* launches, double* cells,
+                  double* bytes);
 
 #ifdef __cplusplus
 }

@@ -28,6 +28,7 @@ EXPORTS = [
     "bgk_serial_fine", "bgk_fine_adjoint", "bgk_lift_adjoint_rho",
     "bgk_density_adjoint", "bgk_status", "bgk_status_string", "bgk_last_error",
     "bgk_set_tiles", "bgk_autotune", "bgk_prof_enable", "bgk_prof_read",
+    "bgk_set_graphs",
 ]
 
 
@@ -80,10 +81,11 @@ def load_library(path: str = LIB_PATH):
         "bgk_status": (C.c_int, [V, V]),
         "bgk_status_string": (C.c_char_p, [C.c_int]),
         "bgk_last_error": (C.c_char_p, []),
-        "bgk_set_tiles": (C.c_int, [C.c_int32, C.c_int32]),
-        "bgk_autotune": (C.c_int, [P, C.c_int32, V, Z, V, I, I]),
+        "bgk_set_tiles": (C.c_int, [C.c_int32, C.c_int32, C.c_int32]),
+        "bgk_autotune": (C.c_int, [P, C.c_int32, V, Z, V, I, I, I]),
         "bgk_prof_enable": (C.c_int, [C.c_int32]),
-        "bgk_prof_read": (C.c_int, [D, C.POINTER(C.c_int64), D]),
+        "bgk_set_graphs": (C.c_int, [C.c_int32]),
+        "bgk_prof_read": (C.c_int, [D, C.POINTER(C.c_int64), D, D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -340,17 +342,22 @@ def density_adjoint(p, rhobar: torch.Tensor) -> torch.Tensor:
     return fbar
 
 
-def set_tiles(elems: int = 0, chunk: int = 0):
-    _check(load_library().bgk_set_tiles(elems, chunk), "bgk_set_tiles")
+def set_tiles(elems: int = 0, chunk: int = 0, pair: int = -1):
+    _check(load_library().bgk_set_tiles(elems, chunk, pair), "bgk_set_tiles")
 
 
-def autotune(p, batch: int = 1) -> Tuple[int, int]:
+def autotune(p, batch: int = 1) -> Tuple[int, int, int]:
     L = _gpu_lib()
     w = workspace(p, OP_PROPAGATE, batch)
-    e, c = C.c_int32(), C.c_int32()
+    e, c, pr = C.c_int32(), C.c_int32(), C.c_int32()
     _check(L.bgk_autotune(C.byref(problem_struct(p)), batch, w.data_ptr(), w.numel(),
-                          _stream(), C.byref(e), C.byref(c)), "bgk_autotune")
-    return e.value, c.value
+                          _stream(), C.byref(e), C.byref(c), C.byref(pr)), "bgk_autotune")
+    return e.value, c.value, pr.value
+
+
+def set_graphs(on: bool = True):
+    """Capture/replay launch-bound sequences as HIP graphs (default on)."""
+    _check(load_library().bgk_set_graphs(1 if on else 0), "bgk_set_graphs")
 
 
 def prof_enable(on: bool = True):
@@ -358,10 +365,12 @@ def prof_enable(on: bool = True):
 
 
 def prof_read():
-    ms, n, cells = C.c_double(), C.c_int64(), C.c_double()
-    _check(load_library().bgk_prof_read(C.byref(ms), C.byref(n), C.byref(cells)),
-           "bgk_prof_read")
-    return ms.value, n.value, cells.value
+    """(kernel milliseconds, launches, cells, algorithmic bytes) of the fused
+    step kernel since prof_enable(True)."""
+    ms, n, cells, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+    _check(load_library().bgk_prof_read(C.byref(ms), C.byref(n), C.byref(cells),
+                                        C.byref(by)), "bgk_prof_read")
+    return ms.value, n.value, cells.value, by.value
 
 
 # ------------------------------------------------------------- autograd --

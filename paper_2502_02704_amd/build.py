@@ -29,26 +29,29 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 4, out: str = LIB, defines=()) -> str:
+    """Compile all sources and link `out`.  `defines` (e.g. ["X=1"]) are
+    passed as -D options (used to build experimental variants)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objdir = os.path.join(HERE, "_build")
+    objdir = os.path.join(HERE, "_build" if not defines else "_build_" + str(abs(hash(tuple(defines)))))
     os.makedirs(objdir, exist_ok=True)
     objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [hipcc, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS
+        cmd = ([hipcc, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS +
+               ["-D" + d for d in defines])
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))
     bad = [p.wait() for p in procs]
     if any(bad):
         raise RuntimeError("hipcc failed")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs +
          ["-lamdhip64"], verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -77,7 +77,7 @@ int n_steps_for(const bgk_problem& p, double t_span, int32_t* n, double* dt) {
 
 // ----------------------------------------------------------------- tiles --
 static std::mutex g_mu;
-static Tiles g_override = {0, 0};
+static Tiles g_override = {0, 0, -1};
 static std::map<std::tuple<int, int, int, int, int>, Tiles> g_tuned;
 
 static long long nv3_of(const bgk_problem& p) {
@@ -92,16 +92,25 @@ static long long blocks_for_tiles(const bgk_problem& p, int batch, Tiles t) {
 
 Tiles choose_tiles(const bgk_problem& p, int batch) {
   std::lock_guard<std::mutex> lk(g_mu);
-  Tiles t = {4, 16};
+  Tiles t = {8, 4, p.nv[2] % 2 == 0 ? 1 : 0};
   auto it = g_tuned.find({p.nx, p.nv[0], p.nv[1], p.nv[2], batch});
   if (it != g_tuned.end()) t = it->second;
   else {
     // enough work items to fill 256 CUs several times over
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 4096) t.chunk /= 2;
+    if (blocks_for_tiles(p, batch, t) < 2048) t.elems = 4;
     if (blocks_for_tiles(p, batch, t) < 1024) t.elems = 2;
   }
   if (g_override.elems) t.elems = g_override.elems;
   if (g_override.chunk) t.chunk = g_override.chunk;
+  if (g_override.pair >= 0 && p.nv[2] % 2 == 0) t.pair = g_override.pair;
+  return t;
+}
+
+// The paired kernel needs 16-byte aligned rows of f.
+static Tiles aligned_tiles(Tiles t, std::initializer_list<const void*> ptrs) {
+  for (const void* q : ptrs)
+    if (q && reinterpret_cast<uintptr_t>(q) % 16 != 0) t.pair = 0;
   return t;
 }
 
@@ -124,8 +133,10 @@ struct FineRegions {  // fine solve of B members of one grid
 };
 constexpr size_t kNone = ~(size_t)0;  // region not allocated
 
+// Partial sums per x cell: at most one per wave tile of the generic kernel,
+// four (one per 16-lane row) per tile of the paired kernel.
 static int part_tiles_of(const bgk_problem& p) {
-  return (int)((nv3_of(p) + kWave * kMinElems - 1) / (kWave * kMinElems));
+  return 4 * (int)((nv3_of(p) + kWave * kMinElems - 1) / (kWave * kMinElems));
 }
 
 static FineRegions carve_fine(Carve& c, const bgk_problem& p, int B, bool two_bufs) {
@@ -282,6 +293,7 @@ static Inst make_inst(const bgk_problem& p, int B, double dt, Tiles t) {
   I.nbatch = B;
   I.ntiles = (I.nv3 + kWave * t.elems - 1) / (kWave * t.elems);
   I.ntg = (I.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  I.nparts = t.pair ? 4 * I.ntiles : I.ntiles;
   I.nchunks = (p.nx + t.chunk - 1) / t.chunk;
   I.items = (long long)B * I.ntg * I.nchunks;
   I.part_tiles = part_tiles_of(p);
@@ -323,9 +335,8 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
     const int mode = (k == 1) ? first_mode : kRelax;
     const int phase = w_prev;  // dst = buf[phase ^ 1], src = buf[phase]
     prof_before(s);
-    int rc = launch_step(d_I, 1, h.items, mode, phase, t.elems, t.chunk,
-                         lds_doubles(h, t), d_status, s);
-    prof_after(s, (double)h.nbatch * h.nx * h.nv3);
+    int rc = launch_step(d_I, 1, h.items, mode, phase, t, lds_doubles(h, t), d_status, s);
+    prof_after(s, (double)h.nbatch * h.nx * h.nv3, mode == kLift ? 8.0 : 16.0);
     if (rc) return rc;
     const int red = (project_last && k == n) ? kRedProject : kRedRelaxFactors;
     rc = launch_reduce(d_I, 1, (long long)h.nbatch * h.nx, red, 0, d_status, s);
@@ -344,7 +355,7 @@ static long long relax_out_blocks(const Inst& h) {
 // ------------------------------------------------------------- profiling --
 struct ProfRec {
   hipEvent_t a, b;
-  double cells;
+  double cells, bytes;
 };
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
@@ -370,14 +381,71 @@ void prof_before(hipStream_t s) {
   if (g_prof_pending) (void)hipEventRecord(g_prof_pending, s);
 }
 
-void prof_after(hipStream_t s, double cells) {
+void prof_after(hipStream_t s, double cells, double bytes_per_cell) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!g_prof_on || !g_prof_pending) return;
   hipEvent_t e = prof_event();
   if (!e) return;
   (void)hipEventRecord(e, s);
-  g_prof.push_back({g_prof_pending, e, cells});
+  g_prof.push_back({g_prof_pending, e, cells, cells * bytes_per_cell});
   g_prof_pending = nullptr;
+}
+
+// ----------------------------------------------------------- hipGraphs --
+// Launch-bound sequences (one parareal iteration, the serial chain of slice
+// solves) are captured once per (workspace, shape, iteration) on a private
+// capture stream and replayed on the caller's stream.  Everything a captured
+// sequence touches lives in the workspace, so the key names the workspace.
+static std::mutex g_graph_mu;
+static bool g_graphs_on = true;
+static std::map<std::string, hipGraphExec_t> g_graphs;
+static hipStream_t g_cap_stream = nullptr;
+constexpr size_t kMaxGraphs = 512;
+
+static std::string graph_key(const char* tag, const void* ws, size_t ws_bytes,
+                             const bgk_problem& p, std::initializer_list<double> xs) {
+  std::string k(tag);
+  auto add = [&](const void* q, size_t n) { k.append(static_cast<const char*>(q), n); };
+  add(&ws, sizeof(ws));
+  add(&ws_bytes, sizeof(ws_bytes));
+  add(&p, sizeof(p));
+  for (double x : xs) add(&x, sizeof(x));
+  return k;
+}
+
+template <class F>
+static int run_graph(const std::string& key, hipStream_t user, F&& enqueue) {
+  bool use;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    use = g_graphs_on && !g_prof_on;
+  }
+  if (!use) return enqueue(user);
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  auto it = g_graphs.find(key);
+  if (it == g_graphs.end()) {
+    if (g_graphs.size() >= kMaxGraphs) {
+      BGK_HIP(hipDeviceSynchronize());
+      for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+      g_graphs.clear();
+    }
+    if (!g_cap_stream) BGK_HIP(hipStreamCreateWithFlags(&g_cap_stream, hipStreamNonBlocking));
+    BGK_HIP(hipStreamBeginCapture(g_cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue(g_cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(g_cap_stream, &g);
+    if (rc || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc ? rc : hip_fail(e, "hipStreamEndCapture");
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    it = g_graphs.emplace(key, ex).first;
+  }
+  BGK_HIP(hipGraphLaunch(it->second, user));
+  return BGK_OK;
 }
 
 }  // namespace bgk
@@ -459,6 +527,7 @@ int bgk_moments(const bgk_problem* prob, const double* f, double* V, double* W,
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
   Tiles t = choose_tiles(*prob, 1);
+  t.pair = 0;  // the moment-partials kernel uses the generic lane mapping
   Inst I = make_inst(*prob, 1, 1.0, t);
   attach_fine(I, ws, L.fine, nullptr);
   I.fin = f;
@@ -490,7 +559,7 @@ int bgk_fine_steps(const bgk_problem* prob, const double* f_in, double* f_out,
     BGK_HIP(hipMemcpyAsync(f_out, f_in, fbytes, hipMemcpyDeviceToDevice, s));
     return BGK_OK;
   }
-  const Tiles t = choose_tiles(*prob, 1);
+  const Tiles t = aligned_tiles(choose_tiles(*prob, 1), {f_in, f_out});
   Inst I = make_inst(*prob, 1, dt, t);
   attach_fine(I, ws, L.fine, f_out);  // ping-pong between ws and f_out
   I.fin = f_in;
@@ -599,12 +668,21 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
     attach_fine(I, ws, L.fine, nullptr);
     I.vin = U[cur] + (size_t)k * sl;        // U^{n-1,k}, n = k+1..N
     I.vout = VF + (size_t)(k + 1) * sl;     // P F L(U^{n-1,k})
-    if ((rc = put_insts(dI, &I, 1, s))) return rc;
-    if ((rc = launch_lift_factors(dI, 1, (long long)B * prob->nx, nullptr, st, s))) return rc;
-    int last = 0;
-    if ((rc = run_steps(dI, I, n, kLift, true, t, st, s, &last))) return rc;
-    if ((rc = launch_parareal_sweep(*prob, n_slices, k, U[cur], U[cur ^ 1], VF, Gc,
-                                    span, scratch, &hd->err, st, s)))
+    // one iteration: batched lift + fine steps + projection of the active
+    // slices, then the sequential correction sweep (replayed as one graph)
+    auto iteration = [&](hipStream_t q) -> int {
+      int r;
+      if ((r = put_insts(dI, &I, 1, q))) return r;
+      if ((r = launch_lift_factors(dI, 1, (long long)B * prob->nx, nullptr, st, q))) return r;
+      int last = 0;
+      if ((r = run_steps(dI, I, n, kLift, true, t, st, q, &last))) return r;
+      return launch_parareal_sweep(*prob, n_slices, k, U[cur], U[cur ^ 1], VF, Gc, span,
+                                   scratch, &hd->err, st, q);
+    };
+    if ((rc = run_graph(graph_key("pit", ws, ws_bytes, *prob,
+                                  {(double)n_slices, span, (double)k, (double)t.elems,
+                                   (double)t.chunk, (double)t.pair}),
+                        s, iteration)))
       return rc;
     struct {
       int status;
@@ -645,19 +723,37 @@ int bgk_serial_fine(const bgk_problem* prob, const double* W0, int32_t n_slices,
   hipStream_t s = (hipStream_t)stream;
   int* st = &at<WsHeader>(ws, 0)->status;
   const size_t sl = (size_t)prob->nx * 5;
-  if ((rc = launch_prim_to_cons(W0, V_out, prob->nx, s))) return rc;
+  double* U = at<double>(ws, L.U0);  // chain computed in the workspace
+  if ((rc = launch_prim_to_cons(W0, U, prob->nx, s))) return rc;
   const Tiles t = choose_tiles(*prob, 1);
-  Inst I = make_inst(*prob, 1, dt, t);
-  attach_fine(I, ws, L.fine, nullptr);
   Inst* dI = at<Inst>(ws, L.insts);
-  for (int m = 1; m <= n_slices; ++m) {
-    I.vin = V_out + (size_t)(m - 1) * sl;
-    I.vout = V_out + (size_t)m * sl;
-    if ((rc = put_insts(dI, &I, 1, s))) return rc;
-    if ((rc = launch_lift_factors(dI, 1, prob->nx, nullptr, st, s))) return rc;
-    int last = 0;
-    if ((rc = run_steps(dI, I, n, kLift, true, t, st, s, &last))) return rc;
-  }
+  auto chain = [&](hipStream_t q) -> int {
+    int r;
+    Inst I = make_inst(*prob, 1, dt, t);
+    attach_fine(I, ws, L.fine, nullptr);
+    for (int m = 1; m <= n_slices; ++m) {
+      I.vin = U + (size_t)(m - 1) * sl;
+      I.vout = U + (size_t)m * sl;
+      if ((r = put_insts(dI, &I, 1, q))) return r;
+      if ((r = launch_lift_factors(dI, 1, prob->nx, nullptr, st, q))) return r;
+      int last = 0;
+      if ((r = run_steps(dI, I, n, kLift, true, t, st, q, &last))) return r;
+    }
+    return BGK_OK;
+  };
+  if ((rc = run_graph(graph_key("ser", ws, ws_bytes, *prob,
+                                {(double)n_slices, span, (double)t.elems, (double)t.chunk,
+                                 (double)t.pair}),
+                      s, chain)))
+    return rc;
+  BGK_HIP(hipMemcpyAsync(V_out, U, sl * (n_slices + 1) * sizeof(double),
+                         hipMemcpyDeviceToDevice, s));
+  return BGK_OK;
+}
+
+int bgk_set_graphs(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  g_graphs_on = on != 0;
   return BGK_OK;
 }
 
@@ -704,9 +800,7 @@ int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
       I.fin = states + (size_t)(k - 1 - s0) * nf;
       I.fout = states + (size_t)(k - s0) * nf;
       if ((rc = put_insts(dI, &I, 1, s))) return rc;
-      if ((rc = launch_step(dI, 1, I.items, kCopy, 1, t.elems, t.chunk,
-                            lds_doubles(I, t), st, s)))
-        return rc;
+      if ((rc = launch_step(dI, 1, I.items, kCopy, 1, t, lds_doubles(I, t), st, s))) return rc;
       if ((rc = launch_reduce(dI, 1, prob->nx, kRedRelaxFactors, 0, st, s))) return rc;
       if ((rc = launch_relax_out_blocks(dI, 1, relax_out_blocks(I), I.nvs, 0, s))) return rc;
     }
@@ -715,9 +809,7 @@ int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
       I.fin = states + (size_t)(k - s0) * nf;
       if ((rc = put_insts(dI, &I, 1, s))) return rc;
       // g = T f^k into buf[0], moments and the unscaled Maxwellian of U(g)
-      if ((rc = launch_step(dI, 1, I.items, kCopy, 1, t.elems, t.chunk,
-                            lds_doubles(I, t), st, s)))
-        return rc;
+      if ((rc = launch_step(dI, 1, I.items, kCopy, 1, t, lds_doubles(I, t), st, s))) return rc;
       if ((rc = launch_reduce(dI, 1, prob->nx, kRedMaxwellFactors, 0, st, s))) return rc;
       if ((rc = launch_adjoint_sums(dI, I, 0, fb[cur], part6, s))) return rc;
       if ((rc = launch_adjoint_reduce(dI, I, part6, coef, dle, s))) return rc;
@@ -823,11 +915,16 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   for (int q = 0; q < n; ++q) order[q] = q;
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return steps[x] > steps[y]; });
-  Tiles t = {4, 8};
+  Tiles t = {4, 8, 1};
+  for (int q = 0; q < n; ++q) {
+    if (probs[q].nv[2] % 2 != 0) t.pair = 0;
+    t = aligned_tiles(t, {f_in[q], f_out[q]});
+  }
   {
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_override.elems) t.elems = g_override.elems;
     if (g_override.chunk) t.chunk = g_override.chunk;
+    if (g_override.pair == 0) t.pair = 0;
   }
   std::vector<Inst> h(n);
   long long items = 0;
@@ -860,9 +957,9 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
     double cells = 0.0;
     for (int q = 0; q < n_act; ++q) cells += (double)h[q].nx * h[q].nv3;
     prof_before(s);
-    rc = launch_step(dI, n_act, items_prefix[n_act], mode, phase, t.elems, t.chunk,
+    rc = launch_step(dI, n_act, items_prefix[n_act], mode, phase, t,
                      (t.chunk + 2) * nvs_max, st, s);
-    prof_after(s, cells);
+    prof_after(s, cells, 16.0);
     if (rc) return rc;
     if ((rc = launch_reduce(dI, n_act, cells_prefix[n_act], kRedRelaxFactors, 0, st, s)))
       return rc;
@@ -879,17 +976,19 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
 }
 
 // ------------------------------------------------------- tiles / autotune --
-int bgk_set_tiles(int32_t elems, int32_t chunk) {
+int bgk_set_tiles(int32_t elems, int32_t chunk, int32_t pair) {
   if (!(elems == 0 || elems == 2 || elems == 4 || elems == 8))
     return invalid("elems_per_lane must be 0, 2, 4 or 8");
   if (chunk < 0 || chunk > kMaxChunk) return invalid("x_chunk must be in [0, 64]");
+  if (pair < -1 || pair > 1) return invalid("pair must be -1, 0 or 1");
   std::lock_guard<std::mutex> lk(g_mu);
-  g_override = {elems, chunk};
+  g_override = {elems, chunk, pair};
   return BGK_OK;
 }
 
 int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_bytes,
-                 void* stream, int32_t* best_elems, int32_t* best_chunk) {
+                 void* stream, int32_t* best_elems, int32_t* best_chunk,
+                 int32_t* best_pair) {
   int rc = check_problem(prob);
   if (rc) return rc;
   if (batch < 1) return invalid("batch must be >= 1");
@@ -912,14 +1011,15 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_byt
   hipEvent_t e0, e1;
   BGK_HIP(hipEventCreate(&e0));
   BGK_HIP(hipEventCreate(&e1));
-  Tiles best = {0, 0};
+  Tiles best = {0, 0, 0};
   float best_ms = 1e30f;
   const int Es[3] = {2, 4, 8};
   const int Cs[6] = {1, 2, 4, 8, 16, 32};
+  for (int pr = 0; pr < 2; ++pr)
   for (int ei = 0; ei < 3; ++ei)
     for (int ci = 0; ci < 6; ++ci) {
-      Tiles t = {Es[ei], Cs[ci]};
-      if (t.chunk > prob->nx) continue;
+      Tiles t = {Es[ei], Cs[ci], pr};
+      if (t.chunk > prob->nx || (pr && prob->nv[2] % 2 != 0)) continue;
       Inst I = make_inst(*prob, batch, dt, t);
       attach_fine(I, ws, L.fine, nullptr);
       I.vin = Vin;
@@ -957,6 +1057,7 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_byt
   }
   if (best_elems) *best_elems = best.elems;
   if (best_chunk) *best_chunk = best.chunk;
+  if (best_pair) *best_pair = best.pair;
   return BGK_OK;
 }
 
@@ -972,19 +1073,21 @@ int bgk_prof_enable(int32_t on) {
   return BGK_OK;
 }
 
-int bgk_prof_read(double* total_ms, int64_t* launches, double* cells) {
+int bgk_prof_read(double* total_ms, int64_t* launches, double* cells, double* bytes) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  double ms = 0.0, c = 0.0;
+  double ms = 0.0, c = 0.0, by = 0.0;
   for (auto& r : g_prof) {
     BGK_HIP(hipEventSynchronize(r.b));
     float x = 0.f;
     BGK_HIP(hipEventElapsedTime(&x, r.a, r.b));
     ms += x;
     c += r.cells;
+    by += r.bytes;
   }
   if (total_ms) *total_ms = ms;
   if (launches) *launches = (int64_t)g_prof.size();
   if (cells) *cells = c;
+  if (bytes) *bytes = by;
   return BGK_OK;
 }
 

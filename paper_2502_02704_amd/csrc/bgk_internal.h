@@ -15,6 +15,7 @@ constexpr int kWave = 64;            // CDNA wavefront
 constexpr int kWavesPerBlock = 4;    // fused step kernel: 4 independent waves
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kMinElems = 2;         // smallest velocity elements per lane
+constexpr int kPartElems = 32;       // fewest velocities behind one partial sum
 constexpr int kMaxNv = 256;          // per velocity axis
 constexpr int kMaxChunk = 64;        // x cells per work item
 constexpr int kNumXcd = 8;           // MI355X: 8 accelerator complex dies
@@ -30,8 +31,8 @@ struct Inst {
   int steps;                   // steps this instance takes (uneven batches)
   long long item_begin;        // first work item of this instance
   long long items;             // nbatch * ntg * nchunks
-  int part_tiles;              // tile capacity of `part` per x cell
-  int pad_;
+  int part_tiles;              // partial-sum capacity of `part` per x cell
+  int nparts;                  // partial sums per x cell the step writes
   double vlo[3], dv[3];        // v_a(j) = vlo[a] + (j + 1/2) dv[a]
   double dv3;                  // dv[0] dv[1] dv[2]
   double r;                    // dt / dx
@@ -91,14 +92,15 @@ struct WsHeader {
 struct Tiles {
   int elems;   // velocity elements per lane
   int chunk;   // x cells per work item
+  int pair;    // 1: lanes own pairs of adjacent velocities (needs even nv_z)
 };
 
 Tiles choose_tiles(const bgk_problem& p, int batch);
 
 // Fused relax-then-transport step over all instances in `d_insts`.
 int launch_step(const Inst* d_insts, int n_inst, long long total_items,
-                int mode, int phase, int elems, int chunk, int lds_doubles,
-                int* d_status, hipStream_t s);
+                int mode, int phase, Tiles t, int lds_doubles, int* d_status,
+                hipStream_t s);
 // Per-x-cell reduction of partial sums into moments and factors.
 int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
                   int mode, int phase, int* d_status, hipStream_t s);
@@ -147,6 +149,6 @@ constexpr int kAdjElems = 4;  // velocity elements per lane in adjoint kernels
 
 // Profiling of the fused step kernel.
 void prof_before(hipStream_t s);
-void prof_after(hipStream_t s, double cells);
+void prof_after(hipStream_t s, double cells, double bytes_per_cell);
 
 }  // namespace bgk

@@ -22,6 +22,10 @@
 #ifndef BGK_WAVE_REDUCE_DPP
 #define BGK_WAVE_REDUCE_DPP 1
 #endif
+// Non-temporal stores of g (streamed once, read back only by the next step).
+#ifndef BGK_NT_STORE
+#define BGK_NT_STORE 1
+#endif
 
 namespace bgk {
 
@@ -243,6 +247,207 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
   }
 }
 
+// ------------------------------------------- paired-velocity step kernel --
+// Same step, lanes own pairs of adjacent velocities (v_z and v_z + dv_z, same
+// v_x and v_y): 16-byte loads and stores, one transport select, one Ex*Ey
+// product and one ds_read2 per pair.  Pair p of lane l covers the flat
+// velocities tile*128P + p*128 + 2l + {0,1} (requires even nv_z, so a pair
+// never straddles a v_z row, and 16-byte aligned rows).  Moment partials are
+// reduced over the 16 lanes of each DPP row only and stored 4 per wave.
+
+// Row-level (16-lane) sums of five values, interleaved; valid in lane 15 of
+// each row.
+__device__ __forceinline__ void row_sum5(double (&s)[5]) {
+#pragma unroll
+  for (int c = 0; c < 5; ++c) s[c] += dpp_mov<0xb1, 0xf>(s[c]);  // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int c = 0; c < 5; ++c) s[c] += dpp_mov<0x4e, 0xf>(s[c]);  // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int c = 0; c < 5; ++c) s[c] += dpp_mov<0x114, 0xf>(s[c]); // row_shr:4
+#pragma unroll
+  for (int c = 0; c < 5; ++c) s[c] += dpp_mov<0x118, 0xf>(s[c]); // row_shr:8
+}
+
+// DIR = +1 marches the chunk's x cells upward, -1 downward.  Neighbouring
+// chunks march in opposite directions, so the two halo rows they share are
+// read by both blocks at nearly the same time (both at their start or both at
+// their end) and the second read hits L2.
+template <int P, int MODE, bool FULL, int DIR>
+__device__ __forceinline__ void step2_march(const Inst& I, const double* lds,
+                                            int b, int tile, int lane, int i0,
+                                            int i1, int phase) {
+  const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
+  const int nyz = I.nvy * I.nvz;
+  int jofs[P];
+  unsigned off[P];
+  double vx[P], vy[P], vz[P], q0[P], q1[P], nu[P];
+  bool ok[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int j = tile * (128 * P) + p * 128 + 2 * lane;
+    ok[p] = FULL || j < nv3;
+    const int jj = ok[p] ? j : 0;
+    jofs[p] = jj;
+    const int jx = jj / nyz;
+    const int rem = jj - jx * nyz;
+    const int jy = rem / I.nvz;
+    const int jz = rem - jy * I.nvz;
+    off[p] = (unsigned)jx | ((unsigned)(I.nvx + jy) << 10) |
+             ((unsigned)(I.nvx + I.nvy + jz) << 20);
+    vx[p] = vgrid(I, 0, jx);
+    vy[p] = vgrid(I, 1, jy);
+    vz[p] = vgrid(I, 2, jz);
+    const double vxy = vx[p] * vx[p] + vy[p] * vy[p];
+    q0[p] = vxy + vz[p] * vz[p];
+    const double vz1 = vgrid(I, 2, jz + 1);
+    q1[p] = vxy + vz1 * vz1;
+    nu[p] = vx[p] * I.r;
+  }
+  const double dvz = I.dv[2];
+  const long long mbase = (long long)b * nx * nv3;
+  const double* src = (MODE == kCopy) ? I.fin : I.buf[phase];
+  double* dst = I.buf[phase ^ 1];
+  src += mbase;
+  dst += mbase;
+  const double a = I.a;
+  const int len = i1 - i0;
+  // global row of march position k (k = -1 and k = len are the halo rows)
+  auto row_at = [&](int k) { return DIR > 0 ? i0 + k : i1 - 1 - k; };
+
+  auto load_row = [&](int r, double2 (&raw)[P]) {
+    if (MODE == kLift) return;
+    const double* row = src + (long long)ghost_row(r, nx, I.bc) * nv3;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+      raw[p] = ok[p] ? *reinterpret_cast<const double2*>(row + jofs[p])
+                     : make_double2(0.0, 0.0);
+  };
+  auto relax_row = [&](int r, const double2 (&raw)[P], double2 (&out)[P]) {
+    const double* fr = lds + (r - (i0 - 1)) * nvs;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      double2 v;
+      if (MODE == kCopy) {
+        v = raw[p];
+      } else {
+        const unsigned o = off[p];
+        const double fxy = fr[o & 1023u] * fr[(o >> 10) & 1023u];
+        const double* fz = fr + (o >> 20);
+        const double m0 = fxy * fz[0], m1 = fxy * fz[1];
+        if (MODE == kRelax) {
+          v.x = fma(a, raw[p].x, m0);
+          v.y = fma(a, raw[p].y, m1);
+        } else {
+          v.x = m0;
+          v.y = m1;
+        }
+      }
+      if (!FULL && !ok[p]) v = make_double2(0.0, 0.0);
+      out[p] = v;
+    }
+  };
+
+  // fb: relaxed row behind (k-1), f0: current (k), fa: ahead (k+1);
+  // r1: raw row k+1, r2: raw row k+2 (in flight)
+  double2 fb[P], f0[P], fa[P], r1[P], r2[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) r2[p] = make_double2(0.0, 0.0);
+  {
+    double2 t0[P];
+    load_row(row_at(-1), t0);
+    load_row(row_at(0), r1);
+    relax_row(row_at(-1), t0, fb);
+    load_row(row_at(1), t0);
+    relax_row(row_at(0), r1, f0);
+#pragma unroll
+    for (int p = 0; p < P; ++p) r1[p] = t0[p];
+  }
+  double* part = I.part + ((long long)b * nx) * I.part_tiles * 5 + (tile * 4 + lane / 16) * 5;
+  for (int k = 0; k < len; ++k) {
+    if (k + 2 <= len) load_row(row_at(k + 2), r2);  // prefetch
+    relax_row(row_at(k + 1), r1, fa);
+    const int r = row_at(k);
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double* drow = dst + (long long)r * nv3;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      // upwind neighbour: cell r-1 for v_x > 0, r+1 for v_x < 0
+      const bool take_behind = (nu[p] > 0.0) == (DIR > 0);
+      const double cn = fabs(nu[p]);
+      const double2 nb = take_behind ? fb[p] : fa[p];
+      double2 g;
+      g.x = fma(cn, nb.x - f0[p].x, f0[p].x);
+      g.y = fma(cn, nb.y - f0[p].y, f0[p].y);
+      if (FULL || ok[p]) {
+#if BGK_NT_STORE
+        __builtin_nontemporal_store(g.x, drow + jofs[p]);
+        __builtin_nontemporal_store(g.y, drow + jofs[p] + 1);
+#else
+        *reinterpret_cast<double2*>(drow + jofs[p]) = g;
+#endif
+      }
+      const double gs = g.x + g.y;
+      s[0] += gs;
+      s[1] = fma(vx[p], gs, s[1]);
+      s[2] = fma(vy[p], gs, s[2]);
+      s[3] = fma(vz[p], gs, fma(dvz, g.y, s[3]));
+      s[4] = fma(q0[p], g.x, fma(q1[p], g.y, s[4]));
+    }
+    row_sum5(s);
+    if ((lane & 15) == 15) {
+      double* pp = part + (long long)r * I.part_tiles * 5;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) pp[c] = s[c];
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      fb[p] = f0[p];
+      f0[p] = fa[p];
+      r1[p] = r2[p];
+    }
+  }
+}
+
+template <int P, int MODE>
+__global__ __launch_bounds__(kBlock) void k_step2(const Inst* __restrict__ insts,
+                                                  int n_inst, int chunk,
+                                                  int phase) {
+  extern __shared__ double lds[];
+  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const int q = find_inst(insts, n_inst, item);
+  const Inst& I = insts[q];
+  const long long local = item - I.item_begin;
+  const int c = (int)(local % I.nchunks);
+  const long long t = local / I.nchunks;
+  const int tg = (int)(t % I.ntg);
+  const int b = (int)(t / I.ntg);
+  const int nx = I.nx, nvs = I.nvs;
+  const int i0 = c * chunk;
+  const int i1 = min(i0 + chunk, nx);
+  if (MODE != kCopy) {
+    const int rows = i1 - i0 + 2;
+    const double* fac = I.fac + (long long)b * nx * nvs;
+    for (int idx = threadIdx.x; idx < rows * nvs; idx += kBlock) {
+      int rr = idx / nvs;
+      int k = idx - rr * nvs;
+      lds[idx] = fac[(long long)ghost_row(i0 - 1 + rr, nx, I.bc) * nvs + k];
+    }
+    __syncthreads();
+  }
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int tile = tg * kWavesPerBlock + wave;
+  if (tile >= I.ntiles) return;
+  const bool full = (tile + 1) * (128 * P) <= I.nv3;
+  if (c & 1) {
+    if (full) step2_march<P, MODE, true, -1>(I, lds, b, tile, lane, i0, i1, phase);
+    else step2_march<P, MODE, false, -1>(I, lds, b, tile, lane, i0, i1, phase);
+  } else {
+    if (full) step2_march<P, MODE, true, 1>(I, lds, b, tile, lane, i0, i1, phase);
+    else step2_march<P, MODE, false, 1>(I, lds, b, tile, lane, i0, i1, phase);
+  }
+}
+
 // -------------------------------------------- partial sums of a field --
 // Moments of an arbitrary f (source fin), same tiling, no transport.
 template <int E>
@@ -342,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
   const Inst& I = insts[q];
   const double* pp = I.part + cl * I.part_tiles * 5;
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int t = lane; t < I.ntiles; t += kWave) {
+  for (int t = lane; t < I.nparts; t += kWave) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) s[c] += pp[t * 5 + c];
   }
@@ -497,28 +702,40 @@ __global__ __launch_bounds__(kBlock) void k_relax_out(
 static int blocks_for(long long n) { return (int)n; }
 
 int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode,
-                int phase, int elems, int chunk, int lds_doubles, int* d_status,
-                hipStream_t s) {
+                int phase, Tiles t, int lds_doubles, int* d_status, hipStream_t s) {
   (void)d_status;
   if (total_items <= 0) return BGK_OK;
   dim3 grid(blocks_for(total_items)), block(kBlock);
   size_t lds = (mode == kCopy) ? 0 : (size_t)lds_doubles * sizeof(double);
-#define BGK_STEP_CASE(EE, MM)                                               \
-  if (elems == EE && mode == MM) {                                          \
-    hipLaunchKernelGGL((k_step<EE, MM>), grid, block, lds, s, d_insts,      \
-                       n_inst, chunk, phase);                               \
+  const int chunk = t.chunk;
+#define BGK_STEP_CASE(KER, EE, MM)                                          \
+  if (t.elems == EE && mode == MM) {                                        \
+    hipLaunchKernelGGL(KER, grid, block, lds, s, d_insts, n_inst, chunk,    \
+                       phase);                                              \
     hipError_t e_ = hipGetLastError();                                      \
     return e_ == hipSuccess ? BGK_OK : hip_fail(e_, "k_step");              \
   }
-  BGK_STEP_CASE(2, kCopy)
-  BGK_STEP_CASE(2, kRelax)
-  BGK_STEP_CASE(2, kLift)
-  BGK_STEP_CASE(4, kCopy)
-  BGK_STEP_CASE(4, kRelax)
-  BGK_STEP_CASE(4, kLift)
-  BGK_STEP_CASE(8, kCopy)
-  BGK_STEP_CASE(8, kRelax)
-  BGK_STEP_CASE(8, kLift)
+  if (t.pair) {
+    BGK_STEP_CASE((k_step2<1, kCopy>), 2, kCopy)
+    BGK_STEP_CASE((k_step2<1, kRelax>), 2, kRelax)
+    BGK_STEP_CASE((k_step2<1, kLift>), 2, kLift)
+    BGK_STEP_CASE((k_step2<2, kCopy>), 4, kCopy)
+    BGK_STEP_CASE((k_step2<2, kRelax>), 4, kRelax)
+    BGK_STEP_CASE((k_step2<2, kLift>), 4, kLift)
+    BGK_STEP_CASE((k_step2<4, kCopy>), 8, kCopy)
+    BGK_STEP_CASE((k_step2<4, kRelax>), 8, kRelax)
+    BGK_STEP_CASE((k_step2<4, kLift>), 8, kLift)
+  } else {
+    BGK_STEP_CASE((k_step<2, kCopy>), 2, kCopy)
+    BGK_STEP_CASE((k_step<2, kRelax>), 2, kRelax)
+    BGK_STEP_CASE((k_step<2, kLift>), 2, kLift)
+    BGK_STEP_CASE((k_step<4, kCopy>), 4, kCopy)
+    BGK_STEP_CASE((k_step<4, kRelax>), 4, kRelax)
+    BGK_STEP_CASE((k_step<4, kLift>), 4, kLift)
+    BGK_STEP_CASE((k_step<8, kCopy>), 8, kCopy)
+    BGK_STEP_CASE((k_step<8, kRelax>), 8, kRelax)
+    BGK_STEP_CASE((k_step<8, kLift>), 8, kLift)
+  }
 #undef BGK_STEP_CASE
   set_error("unsupported tile shape");
   return BGK_E_INVALID;

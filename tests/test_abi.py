@@ -49,8 +49,9 @@ def test_host_only_calls():
     assert e.value.code == bgk.E_INVALID
     lib = bgk.load_library()
     assert lib.bgk_status_string(bgk.E_NONPHYSICAL).decode().startswith("non-physical")
-    assert lib.bgk_set_tiles(3, 8) == bgk.E_INVALID
-    assert lib.bgk_set_tiles(0, 0) == bgk.OK
+    assert lib.bgk_set_tiles(3, 8, -1) == bgk.E_INVALID
+    assert lib.bgk_set_tiles(4, 8, 2) == bgk.E_INVALID
+    assert lib.bgk_set_tiles(0, 0, -1) == bgk.OK
 
 
 def test_problem_struct_layout_matches_oracle():

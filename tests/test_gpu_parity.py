@@ -31,15 +31,18 @@ GRIDS = {
                            bc=wl.BC_NEUMANN, eps=2e-2),
     "wide_periodic": wl.Problem(nx=40, nv=(12, 12, 12), v_lo=(-7,) * 3, v_hi=(7,) * 3,
                                 bc=wl.BC_PERIODIC, eps=1e-2),
+    "even_z_ragged": wl.Problem(nx=21, nv=(7, 3, 6), v_lo=(-6, -5, -6), v_hi=(6, 5, 6),
+                                bc=wl.BC_PERIODIC, eps=5e-2),
 }
-TILES = [(0, 0), (2, 1), (4, 3), (8, 16), (2, 64)]
+TILES = [(0, 0, -1), (2, 1, 0), (4, 3, 0), (8, 16, 0), (2, 64, 0), (2, 1, 1), (4, 3, 1),
+         (8, 16, 1), (4, 64, 1)]
 
 
 @pytest.fixture(autouse=True)
 def _reset_tiles():
-    bgk.set_tiles(0, 0)
+    bgk.set_tiles(0, 0, -1)
     yield
-    bgk.set_tiles(0, 0)
+    bgk.set_tiles(0, 0, -1)
 
 
 def states(p, seed, perturb=0.2):
@@ -364,3 +367,27 @@ def test_smooth_periodic_full_batch_sampled():
     for b in (0, 37):
         ref = oracle.fine_propagate_moments(p, V[b], span)
         assert rel_V(got[b], ref) < TOL
+
+
+# ----------------------------------------------------------- graph replays --
+def test_graph_replays_match_eager_launches():
+    """Parareal iterations and the serial chain replay as captured HIP graphs;
+    every replay (with eager work and syncs in between) equals the eager run."""
+    wk = wl.c1_sod_small()
+    p = wk.problem
+    W0 = cuda(wk.W0)
+    bgk.set_graphs(False)
+    try:
+        Ve, erre, _ = bgk.parareal_iterate(p, W0, wk.n_slices, wk.T, 3, 0.0)
+        Se = bgk.serial_fine(p, W0, wk.n_slices, wk.T)
+        Ve, Se = Ve.cpu().numpy(), Se.cpu().numpy()
+    finally:
+        bgk.set_graphs(True)
+    _, f = states(GRIDS["wide_periodic"], 50)
+    for rep in range(3):
+        V, err, kd = bgk.parareal_iterate(p, W0, wk.n_slices, wk.T, 3, 0.0)
+        assert np.array_equal(V.cpu().numpy(), Ve) and err == erre
+        bgk.fine_steps(GRIDS["wide_periodic"], cuda(f), 1e-3, 2)  # eager work between
+        torch.cuda.synchronize()
+        S = bgk.serial_fine(p, W0, wk.n_slices, wk.T)
+        assert np.array_equal(S.cpu().numpy(), Se)
