@@ -211,6 +211,15 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws,
                  size_t ws_bytes, void* stream, int32_t* best_elems,
                  int32_t* best_chunk, int32_t* best_pair);
 
+/* IMEX steps per pass over f: 2 (default) runs pairs of steps in one
+ * read-write pass (8 bytes per update instead of 16; the second step's
+ * moments follow by linearity of the transport from moment sums of the
+ * previous field weighted by max(nu,0) and max(-nu,0), nu = v_x dt/dx);
+ * 1 runs one step per pass.  Applies where the paired lane
+ * mapping is used (even nv[2], 16-byte aligned f); the uneven batch
+ * (bgk_fine_step_batched) always runs one step per pass. */
+int bgk_set_step_fusion(int32_t steps_per_pass);
+
 /* Launch-bound sequences (each parareal iteration, the serial chain of
  * bgk_serial_fine) are captured as HIP graphs on first use and replayed;
  * 0 turns this off (every kernel launched on the stream directly), 1 on

@@ -28,7 +28,7 @@ EXPORTS = [
     "bgk_serial_fine", "bgk_fine_adjoint", "bgk_lift_adjoint_rho",
     "bgk_density_adjoint", "bgk_status", "bgk_status_string", "bgk_last_error",
     "bgk_set_tiles", "bgk_autotune", "bgk_prof_enable", "bgk_prof_read",
-    "bgk_set_graphs",
+    "bgk_set_graphs", "bgk_set_step_fusion",
 ]
 
 
@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH):
         "bgk_autotune": (C.c_int, [P, C.c_int32, V, Z, V, I, I, I]),
         "bgk_prof_enable": (C.c_int, [C.c_int32]),
         "bgk_set_graphs": (C.c_int, [C.c_int32]),
+        "bgk_set_step_fusion": (C.c_int, [C.c_int32]),
         "bgk_prof_read": (C.c_int, [D, C.POINTER(C.c_int64), D, D]),
     }
     for name, (res, args) in sig.items():
@@ -358,6 +359,11 @@ def autotune(p, batch: int = 1) -> Tuple[int, int, int]:
 def set_graphs(on: bool = True):
     """Capture/replay launch-bound sequences as HIP graphs (default on)."""
     _check(load_library().bgk_set_graphs(1 if on else 0), "bgk_set_graphs")
+
+
+def set_step_fusion(steps_per_pass: int = 2):
+    """IMEX steps per read-write pass over f (2 = fused pairs, default)."""
+    _check(load_library().bgk_set_step_fusion(steps_per_pass), "bgk_set_step_fusion")
 
 
 def prof_enable(on: bool = True):

@@ -90,9 +90,14 @@ static long long blocks_for_tiles(const bgk_problem& p, int batch, Tiles t) {
   return (long long)batch * ntg * ((p.nx + t.chunk - 1) / t.chunk);
 }
 
+static bool g_fuse2 = true;  // two IMEX steps per pass where possible
+
 Tiles choose_tiles(const bgk_problem& p, int batch) {
   std::lock_guard<std::mutex> lk(g_mu);
-  Tiles t = {8, 4, p.nv[2] % 2 == 0 ? 1 : 0};
+  const int pair = p.nv[2] % 2 == 0 ? 1 : 0;
+  // measured best on the 512 x 32^3 x 64-slice batch: fused passes favour
+  // 4 velocities per lane over long chunks, single steps 8 over short ones
+  Tiles t = (pair && g_fuse2) ? Tiles{4, 16, 1} : Tiles{8, 4, pair};
   auto it = g_tuned.find({p.nx, p.nv[0], p.nv[1], p.nv[2], batch});
   if (it != g_tuned.end()) t = it->second;
   else {
@@ -129,7 +134,7 @@ struct Carve {
 constexpr int kMaxInst = 4096;
 
 struct FineRegions {  // fine solve of B members of one grid
-  size_t buf0, buf1, part, fac, vg, vout;
+  size_t buf0, buf1, part, fac, vg, vout, fac2, aux;
 };
 constexpr size_t kNone = ~(size_t)0;  // region not allocated
 
@@ -148,6 +153,8 @@ static FineRegions carve_fine(Carve& c, const bgk_problem& p, int B, bool two_bu
   r.fac = c.take((size_t)B * p.nx * (p.nv[0] + p.nv[1] + p.nv[2]) * sizeof(double));
   r.vg = c.take((size_t)B * p.nx * 5 * sizeof(double));
   r.vout = c.take((size_t)B * p.nx * 5 * sizeof(double));
+  r.fac2 = c.take((size_t)B * p.nx * (p.nv[0] + p.nv[1] + p.nv[2]) * sizeof(double));
+  r.aux = c.take((size_t)B * p.nx * kAux * sizeof(double));
   return r;
 }
 
@@ -279,8 +286,15 @@ int launch_prim_to_cons(const double* W, double* V, int n, hipStream_t s) {
   return BGK_OK;
 }
 
-// Descriptor of B members of one grid advanced with step dt.
-static Inst make_inst(const bgk_problem& p, int B, double dt, Tiles t) {
+// Two IMEX steps per pass over f (paired lane mapping only); switchable.
+static bool fused_for(const Tiles& t, int n_steps) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_fuse2 && t.pair && n_steps >= 2;
+}
+
+// Descriptor of B members of one grid advanced with step dt.  ns: sums per
+// moment partial (15 when the steps run fused two per pass).
+static Inst make_inst(const bgk_problem& p, int B, double dt, Tiles t, int ns = 5) {
   Inst I;
   std::memset(&I, 0, sizeof(I));
   I.nx = p.nx;
@@ -293,7 +307,8 @@ static Inst make_inst(const bgk_problem& p, int B, double dt, Tiles t) {
   I.nbatch = B;
   I.ntiles = (I.nv3 + kWave * t.elems - 1) / (kWave * t.elems);
   I.ntg = (I.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-  I.nparts = t.pair ? 4 * I.ntiles : I.ntiles;
+  I.nsum = ns;
+  I.nparts = t.pair ? (ns == 15 ? I.ntiles : 4 * I.ntiles) : I.ntiles;
   I.nchunks = (p.nx + t.chunk - 1) / t.chunk;
   I.items = (long long)B * I.ntg * I.nchunks;
   I.part_tiles = part_tiles_of(p);
@@ -321,30 +336,81 @@ static void attach_fine(Inst& I, void* ws, const FineRegions& r, double* buf1) {
   I.fac = at<double>(ws, r.fac);
   I.vg = at<double>(ws, r.vg);
   I.vout = at<double>(ws, r.vout);
+  I.fac2 = at<double>(ws, r.fac2);
+  I.aux = at<double>(ws, r.aux);
 }
 
 static int lds_doubles(const Inst& I, Tiles t) { return (t.chunk + 2) * I.nvs; }
+static int lds_doubles2(const Inst& I, Tiles t) { return (2 * t.chunk + 6) * I.nvs; }
 
 // Runs `n` relax-then-transport steps on the (uploaded) descriptor d_I.
-// first_mode: kCopy or kLift.  Returns the buffer index holding g^n.
+// first_mode: kCopy (read fin) or kLift (factors of the lifted Maxwellian
+// already in fac, and in aux when h.nsum == 15).  With h.nsum == 15 the steps
+// run two per pass where possible.  The last reduction writes the relaxation
+// factors of g^n, or with project_last the projected relaxed moments into
+// vout.  *last_sel receives the buffer index holding g^n.
 static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
                      bool project_last, Tiles t, int* d_status, hipStream_t s,
                      int* last_sel) {
-  int w_prev = 1;  // step 1 writes buf[0]
-  for (int k = 1; k <= n; ++k) {
-    const int mode = (k == 1) ? first_mode : kRelax;
-    const int phase = w_prev;  // dst = buf[phase ^ 1], src = buf[phase]
+  const long long cells = (long long)h.nbatch * h.nx;
+  const double upd = (double)cells * h.nv3;
+  int phase = 1;  // a pass reads buf[phase] and writes buf[phase ^ 1]
+  int rc;
+  auto single = [&](int mode) -> int {
     prof_before(s);
-    int rc = launch_step(d_I, 1, h.items, mode, phase, t, lds_doubles(h, t), d_status, s);
-    prof_after(s, (double)h.nbatch * h.nx * h.nv3, mode == kLift ? 8.0 : 16.0);
-    if (rc) return rc;
-    const int red = (project_last && k == n) ? kRedProject : kRedRelaxFactors;
-    rc = launch_reduce(d_I, 1, (long long)h.nbatch * h.nx, red, 0, d_status, s);
-    if (rc) return rc;
-    w_prev = phase ^ 1;
+    int r = launch_step(d_I, 1, h.items, mode, phase, t, lds_doubles(h, t), d_status, s,
+                        h.nsum);
+    prof_after(s, upd, mode == kLift ? 8.0 : 16.0);
+    phase ^= 1;
+    return r;
+  };
+  auto reduce = [&](int mode) { return launch_reduce(d_I, 1, cells, mode, 0, d_status, s); };
+  if (h.nsum != 15) {
+    for (int k = 1; k <= n; ++k) {
+      if ((rc = single(k == 1 ? first_mode : kRelax))) return rc;
+      if ((rc = reduce((project_last && k == n) ? kRedProject : kRedRelaxFactors))) return rc;
+    }
+    *last_sel = phase;
+    return BGK_OK;
   }
-  *last_sel = w_prev;
+  int done = 0;
+  auto pair_pass = [&](int mode) -> int {
+    prof_before(s);
+    int r = launch_step2x2(d_I, 1, h.items, mode, phase, t, lds_doubles2(h, t), s);
+    prof_after(s, 2.0 * upd, mode == kLift ? 4.0 : 8.0);
+    phase ^= 1;
+    done += 2;
+    return r;
+  };
+  if (first_mode == kLift && n >= 2) {
+    if ((rc = reduce(kRedW2))) return rc;
+    if ((rc = pair_pass(kLift))) return rc;
+  } else {
+    if ((rc = single(first_mode))) return rc;
+    done = 1;
+  }
+  while (n - done >= 2) {
+    if ((rc = reduce(kRedW1))) return rc;
+    if ((rc = reduce(kRedW2))) return rc;
+    if ((rc = pair_pass(kRelax))) return rc;
+  }
+  if (n - done == 1) {
+    if ((rc = reduce(kRedRelaxFactors))) return rc;
+    if ((rc = single(kRelax))) return rc;
+    done += 1;
+  }
+  if ((rc = reduce(project_last ? kRedProject : kRedRelaxFactors))) return rc;
+  *last_sel = phase;
   return BGK_OK;
+}
+
+// Lift (factors from the conserved vin of every member) then n steps.
+static int lift_and_run(const Inst* d_I, const Inst& h, int n, bool project_last, Tiles t,
+                        int* d_status, hipStream_t s, int* last_sel) {
+  int rc = launch_lift_factors(d_I, 1, (long long)h.nbatch * h.nx, nullptr, d_status, s,
+                               h.nsum == 15 ? 1 : 0);
+  if (rc) return rc;
+  return run_steps(d_I, h, n, kLift, project_last, t, d_status, s, last_sel);
 }
 
 static long long relax_out_blocks(const Inst& h) {
@@ -560,7 +626,7 @@ int bgk_fine_steps(const bgk_problem* prob, const double* f_in, double* f_out,
     return BGK_OK;
   }
   const Tiles t = aligned_tiles(choose_tiles(*prob, 1), {f_in, f_out});
-  Inst I = make_inst(*prob, 1, dt, t);
+  Inst I = make_inst(*prob, 1, dt, t, fused_for(t, n_steps) ? 15 : 5);
   attach_fine(I, ws, L.fine, f_out);  // ping-pong between ws and f_out
   I.fin = f_in;
   I.fout = f_out;
@@ -602,17 +668,15 @@ int bgk_fine_propagate_moments(const bgk_problem* prob, int32_t batch,
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
   const Tiles t = choose_tiles(*prob, batch);
-  Inst I = make_inst(*prob, batch, dt, t);
+  Inst I = make_inst(*prob, batch, dt, t, fused_for(t, n) ? 15 : 5);
   attach_fine(I, ws, L.fine, nullptr);
   I.vin = V_in;
   I.vout = V_out;
   Inst* dI = at<Inst>(ws, L.insts);
   int* st = &at<WsHeader>(ws, 0)->status;
   if ((rc = put_insts(dI, &I, 1, s))) return rc;
-  if ((rc = launch_lift_factors(dI, 1, (long long)batch * prob->nx, nullptr, st, s)))
-    return rc;
   int last = 0;
-  return run_steps(dI, I, n, kLift, true, t, st, s, &last);
+  return lift_and_run(dI, I, n, true, t, st, s, &last);
 }
 
 int euler_coarse_step(const bgk_problem* prob, int32_t batch, const double* V_in,
@@ -664,7 +728,7 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
   for (int k = 0; k < k_max; ++k) {
     const int B = n_slices - k;
     const Tiles t = choose_tiles(*prob, B);
-    Inst I = make_inst(*prob, B, dt, t);
+    Inst I = make_inst(*prob, B, dt, t, fused_for(t, n) ? 15 : 5);
     attach_fine(I, ws, L.fine, nullptr);
     I.vin = U[cur] + (size_t)k * sl;        // U^{n-1,k}, n = k+1..N
     I.vout = VF + (size_t)(k + 1) * sl;     // P F L(U^{n-1,k})
@@ -673,15 +737,14 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
     auto iteration = [&](hipStream_t q) -> int {
       int r;
       if ((r = put_insts(dI, &I, 1, q))) return r;
-      if ((r = launch_lift_factors(dI, 1, (long long)B * prob->nx, nullptr, st, q))) return r;
       int last = 0;
-      if ((r = run_steps(dI, I, n, kLift, true, t, st, q, &last))) return r;
+      if ((r = lift_and_run(dI, I, n, true, t, st, q, &last))) return r;
       return launch_parareal_sweep(*prob, n_slices, k, U[cur], U[cur ^ 1], VF, Gc, span,
                                    scratch, &hd->err, st, q);
     };
     if ((rc = run_graph(graph_key("pit", ws, ws_bytes, *prob,
                                   {(double)n_slices, span, (double)k, (double)t.elems,
-                                   (double)t.chunk, (double)t.pair}),
+                                   (double)t.chunk, (double)t.pair, (double)I.nsum}),
                         s, iteration)))
       return rc;
     struct {
@@ -727,27 +790,34 @@ int bgk_serial_fine(const bgk_problem* prob, const double* W0, int32_t n_slices,
   if ((rc = launch_prim_to_cons(W0, U, prob->nx, s))) return rc;
   const Tiles t = choose_tiles(*prob, 1);
   Inst* dI = at<Inst>(ws, L.insts);
+  const int ns = fused_for(t, n) ? 15 : 5;
   auto chain = [&](hipStream_t q) -> int {
     int r;
-    Inst I = make_inst(*prob, 1, dt, t);
+    Inst I = make_inst(*prob, 1, dt, t, ns);
     attach_fine(I, ws, L.fine, nullptr);
     for (int m = 1; m <= n_slices; ++m) {
       I.vin = U + (size_t)(m - 1) * sl;
       I.vout = U + (size_t)m * sl;
       if ((r = put_insts(dI, &I, 1, q))) return r;
-      if ((r = launch_lift_factors(dI, 1, prob->nx, nullptr, st, q))) return r;
       int last = 0;
-      if ((r = run_steps(dI, I, n, kLift, true, t, st, q, &last))) return r;
+      if ((r = lift_and_run(dI, I, n, true, t, st, q, &last))) return r;
     }
     return BGK_OK;
   };
   if ((rc = run_graph(graph_key("ser", ws, ws_bytes, *prob,
                                 {(double)n_slices, span, (double)t.elems, (double)t.chunk,
-                                 (double)t.pair}),
+                                 (double)t.pair, (double)ns}),
                       s, chain)))
     return rc;
   BGK_HIP(hipMemcpyAsync(V_out, U, sl * (n_slices + 1) * sizeof(double),
                          hipMemcpyDeviceToDevice, s));
+  return BGK_OK;
+}
+
+int bgk_set_step_fusion(int32_t steps_per_pass) {
+  if (steps_per_pass != 1 && steps_per_pass != 2) return invalid("steps_per_pass must be 1 or 2");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_fuse2 = steps_per_pass == 2;
   return BGK_OK;
 }
 
@@ -1020,7 +1090,7 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_byt
     for (int ci = 0; ci < 6; ++ci) {
       Tiles t = {Es[ei], Cs[ci], pr};
       if (t.chunk > prob->nx || (pr && prob->nv[2] % 2 != 0)) continue;
-      Inst I = make_inst(*prob, batch, dt, t);
+      Inst I = make_inst(*prob, batch, dt, t, fused_for(t, steps) ? 15 : 5);
       attach_fine(I, ws, L.fine, nullptr);
       I.vin = Vin;
       I.vout = Vout;
@@ -1031,10 +1101,9 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_byt
         BGK_HIP(hipMemcpyAsync(Vin, hV.data(), hV.size() * sizeof(double),
                                hipMemcpyHostToDevice, s));
         if ((rc = put_insts(dI, &I, 1, s))) break;
-        if ((rc = launch_lift_factors(dI, 1, (long long)batch * prob->nx, nullptr, st, s))) break;
         BGK_HIP(hipEventRecord(e0, s));
         int last = 0;
-        if ((rc = run_steps(dI, I, steps, kLift, false, t, st, s, &last))) break;
+        if ((rc = lift_and_run(dI, I, steps, false, t, st, s, &last))) break;
         BGK_HIP(hipEventRecord(e1, s));
         BGK_HIP(hipEventSynchronize(e1));
         BGK_HIP(hipEventElapsedTime(&ms, e0, e1));

@@ -33,6 +33,9 @@ struct Inst {
   long long items;             // nbatch * ntg * nchunks
   int part_tiles;              // partial-sum capacity of `part` per x cell
   int nparts;                  // partial sums per x cell the step writes
+  int nsum;                    // values per partial: 5 moments, or 15 with the
+                               // nu+ and nu- weighted moments (two-step passes)
+  int pad_;
   double vlo[3], dv[3];        // v_a(j) = vlo[a] + (j + 1/2) dv[a]
   double dv3;                  // dv[0] dv[1] dv[2]
   double r;                    // dt / dx
@@ -46,6 +49,8 @@ struct Inst {
   double* vg;                  // conserved moments of g        [nbatch][nx][5]
   const double* vin;           // lift source moments (conserved)[nbatch][nx][5]
   double* vout;                // projected relaxed moments     [nbatch][nx][5]
+  double* fac2;                // factors of the second step of a pass [..][nvs]
+  double* aux;                 // per-cell weighted sums (two-step)  [..][nx][30]
 };
 
 // Step-kernel source modes.
@@ -61,7 +66,15 @@ enum ReduceMode : int {
   kRedProject = 1,       // V(g) and vout = a V(g) + al V(M[U(g)])
   kRedMomentsOnly = 2,   // V(g) into vg (and W into vout if set)
   kRedMaxwellFactors = 3,  // V(g) and unscaled factors M[U(g)] (adjoint)
+  kRedW1 = 4,              // kRedRelaxFactors + the weighted sums in aux
+  kRedW2 = 5,              // moments of the next transported field from aux
+                           // of cells i-1, i, i+1 -> second-step factors fac2
 };
+
+// aux layout per x cell (conserved-moment units, 5 values each):
+//   S, S+, S-  moments of g weighted by 1, nu+ = max(nu,0), nu- = max(-nu,0)
+//   A, A+, A-  the same sums of the Maxwellian M[U(g)]
+constexpr int kAux = 30;
 
 // ---------------------------------------------------------------- errors --
 void set_error(const std::string& msg);
@@ -98,15 +111,20 @@ struct Tiles {
 Tiles choose_tiles(const bgk_problem& p, int batch);
 
 // Fused relax-then-transport step over all instances in `d_insts`.
+// ns: sums per partial, 5 (moments) or 15 (plus nu-weighted, paired only).
 int launch_step(const Inst* d_insts, int n_inst, long long total_items,
                 int mode, int phase, Tiles t, int lds_doubles, int* d_status,
-                hipStream_t s);
+                hipStream_t s, int ns = 5);
 // Per-x-cell reduction of partial sums into moments and factors.
 int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
                   int mode, int phase, int* d_status, hipStream_t s);
 // Lift factors from conserved (vin) or primitive moments.
 int launch_lift_factors(const Inst* d_insts, int n_inst, long long total_cells,
-                        const double* W, int* d_status, hipStream_t s);
+                        const double* W, int* d_status, hipStream_t s,
+                        int with_aux = 0);
+// Two IMEX steps per pass (paired lanes): mode kRelax or kLift for the first.
+int launch_step2x2(const Inst* d_insts, int n_inst, long long total_items,
+                   int mode, int phase, Tiles t, int lds_doubles, hipStream_t s);
 // Partial sums of an arbitrary f (source = fin), no transport.
 int launch_partials(const Inst* d_insts, int n_inst, long long total_items,
                     int elems, int chunk, hipStream_t s);

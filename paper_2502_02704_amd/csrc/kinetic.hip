@@ -252,8 +252,13 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
 // v_x and v_y): 16-byte loads and stores, one transport select, one Ex*Ey
 // product and one ds_read2 per pair.  Pair p of lane l covers the flat
 // velocities tile*128P + p*128 + 2l + {0,1} (requires even nv_z, so a pair
-// never straddles a v_z row, and 16-byte aligned rows).  Moment partials are
-// reduced over the 16 lanes of each DPP row only and stored 4 per wave.
+// never straddles a v_z row, and 16-byte aligned rows).
+//
+// Moment partials: with NS = 5 the five moment sums are reduced over the 16
+// lanes of each DPP row only and stored 4 per wave; with NS = 15 they are
+// joined by the same sums weighted by nu+ = max(nu,0) and nu- = max(-nu,0)
+// (needed to predict the next step's moments, see the two-step kernel) and
+// reduced over the whole wave, one partial per wave.
 
 // Row-level (16-lane) sums of five values, interleaved; valid in lane 15 of
 // each row.
@@ -268,81 +273,178 @@ __device__ __forceinline__ void row_sum5(double (&s)[5]) {
   for (int c = 0; c < 5; ++c) s[c] += dpp_mov<0x118, 0xf>(s[c]); // row_shr:8
 }
 
-// DIR = +1 marches the chunk's x cells upward, -1 downward.  Neighbouring
-// chunks march in opposite directions, so the two halo rows they share are
-// read by both blocks at nearly the same time (both at their start or both at
-// their end) and the second read hits L2.
-template <int P, int MODE, bool FULL, int DIR>
-__device__ __forceinline__ void step2_march(const Inst& I, const double* lds,
-                                            int b, int tile, int lane, int i0,
-                                            int i1, int phase) {
-  const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
-  const int nyz = I.nvy * I.nvz;
+// Whole-wave sums of N values, interleaved; valid in lane 63.
+template <int N>
+__device__ __forceinline__ void wave_sums_last(double (&s)[N]) {
+#pragma unroll
+  for (int c = 0; c < N; ++c) s[c] += dpp_mov<0xb1, 0xf>(s[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c) s[c] += dpp_mov<0x4e, 0xf>(s[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c) s[c] += dpp_mov<0x114, 0xf>(s[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c) s[c] += dpp_mov<0x118, 0xf>(s[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c) s[c] += dpp_mov<0x142, 0xa>(s[c]);
+#pragma unroll
+  for (int c = 0; c < N; ++c) s[c] += dpp_mov<0x143, 0xc>(s[c]);
+}
+
+// Per-pair velocity data of one lane.
+template <int P>
+struct PairEls {
   int jofs[P];
   unsigned off[P];
   double vx[P], vy[P], vz[P], q0[P], q1[P], nu[P];
   bool ok[P];
+};
+
+template <int P, bool FULL>
+__device__ __forceinline__ void setup_pairs(const Inst& I, int tile, int lane,
+                                            PairEls<P>& e) {
+  const int nyz = I.nvy * I.nvz;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const int j = tile * (128 * P) + p * 128 + 2 * lane;
-    ok[p] = FULL || j < nv3;
-    const int jj = ok[p] ? j : 0;
-    jofs[p] = jj;
+    e.ok[p] = FULL || j < I.nv3;
+    const int jj = e.ok[p] ? j : 0;
+    e.jofs[p] = jj;
     const int jx = jj / nyz;
     const int rem = jj - jx * nyz;
     const int jy = rem / I.nvz;
     const int jz = rem - jy * I.nvz;
-    off[p] = (unsigned)jx | ((unsigned)(I.nvx + jy) << 10) |
-             ((unsigned)(I.nvx + I.nvy + jz) << 20);
-    vx[p] = vgrid(I, 0, jx);
-    vy[p] = vgrid(I, 1, jy);
-    vz[p] = vgrid(I, 2, jz);
-    const double vxy = vx[p] * vx[p] + vy[p] * vy[p];
-    q0[p] = vxy + vz[p] * vz[p];
+    e.off[p] = (unsigned)jx | ((unsigned)(I.nvx + jy) << 10) |
+               ((unsigned)(I.nvx + I.nvy + jz) << 20);
+    e.vx[p] = vgrid(I, 0, jx);
+    e.vy[p] = vgrid(I, 1, jy);
+    e.vz[p] = vgrid(I, 2, jz);
+    const double vxy = e.vx[p] * e.vx[p] + e.vy[p] * e.vy[p];
+    e.q0[p] = vxy + e.vz[p] * e.vz[p];
     const double vz1 = vgrid(I, 2, jz + 1);
-    q1[p] = vxy + vz1 * vz1;
-    nu[p] = vx[p] * I.r;
+    e.q1[p] = vxy + vz1 * vz1;
+    e.nu[p] = e.vx[p] * I.r;
   }
+}
+
+// Moments of one transported pair into the NS running sums.
+template <int NS>
+__device__ __forceinline__ void accum_pair(double (&s)[NS], double2 g, double vx,
+                                           double vy, double vz, double dvz,
+                                           double q0, double q1, double nu) {
+  const double gs = g.x + g.y;
+  const double m[5] = {gs, vx * gs, vy * gs, fma(vz, gs, dvz * g.y),
+                       fma(q0, g.x, q1 * g.y)};
+#pragma unroll
+  for (int c = 0; c < 5; ++c) s[c] += m[c];
+  if (NS == 15) {
+    const double cp = nu > 0.0 ? nu : 0.0;
+    const double cm = nu < 0.0 ? -nu : 0.0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      s[5 + c] = fma(cp, m[c], s[5 + c]);
+      s[10 + c] = fma(cm, m[c], s[10 + c]);
+    }
+  }
+}
+
+// Reduce the running sums and store this wave's partial(s) for x cell r.
+template <int NS>
+__device__ __forceinline__ void store_partials(const Inst& I, double (&s)[NS],
+                                               int b, int r, int tile, int lane) {
+  double* cell = I.part + ((long long)b * I.nx + r) * I.part_tiles * 5;
+  if (NS == 5) {
+    row_sum5(*reinterpret_cast<double(*)[5]>(&s[0]));
+    if ((lane & 15) == 15) {
+      double* pp = cell + (tile * 4 + lane / 16) * 5;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) pp[c] = s[c];
+    }
+  } else {
+    wave_sums_last<NS>(s);
+    if (lane == kWave - 1) {
+      double* pp = cell + tile * NS;
+#pragma unroll
+      for (int c = 0; c < NS; ++c) pp[c] = s[c];
+    }
+  }
+}
+
+__device__ __forceinline__ void store_pair(double* drow, int jofs, double2 g) {
+#if BGK_NT_STORE
+  __builtin_nontemporal_store(g.x, drow + jofs);
+  __builtin_nontemporal_store(g.y, drow + jofs + 1);
+#else
+  *reinterpret_cast<double2*>(drow + jofs) = g;
+#endif
+}
+
+// One upwind transport of a pair: centre c, its neighbours behind (march
+// position k-1) and ahead (k+1).  The upwind cell is x-1 for v_x > 0.
+template <int DIR>
+__device__ __forceinline__ double2 transport_pair(double nu, double2 behind,
+                                                  double2 c, double2 ahead) {
+  const bool take_behind = (nu > 0.0) == (DIR > 0);
+  const double cn = fabs(nu);
+  const double2 nb = take_behind ? behind : ahead;
+  double2 g;
+  g.x = fma(cn, nb.x - c.x, c.x);
+  g.y = fma(cn, nb.y - c.y, c.y);
+  return g;
+}
+
+// Relaxed pair from raw g (or the Maxwellian alone in lift mode) with the
+// factor row `fr` (al*C*Ex | Ey | Ez, or C*Ex | Ey | Ez for the lift).
+template <int MODE>
+__device__ __forceinline__ double2 relax_pair(const double* fr, unsigned o,
+                                              double a, double2 raw) {
+  if (MODE == kCopy) return raw;
+  const double fxy = fr[o & 1023u] * fr[(o >> 10) & 1023u];
+  const double* fz = fr + (o >> 20);
+  const double m0 = fxy * fz[0], m1 = fxy * fz[1];
+  double2 v;
+  if (MODE == kRelax) {
+    v.x = fma(a, raw.x, m0);
+    v.y = fma(a, raw.y, m1);
+  } else {
+    v.x = m0;
+    v.y = m1;
+  }
+  return v;
+}
+
+// DIR = +1 marches the chunk's x cells upward, -1 downward.  Neighbouring
+// chunks march in opposite directions, so the two halo rows they share are
+// read by both blocks at nearly the same time (both at their start or both at
+// their end) and the second read hits L2.
+template <int P, int MODE, bool FULL, int DIR, int NS>
+__device__ __forceinline__ void step2_march(const Inst& I, const double* lds,
+                                            int b, int tile, int lane, int i0,
+                                            int i1, int phase) {
+  const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
+  PairEls<P> e;
+  setup_pairs<P, FULL>(I, tile, lane, e);
   const double dvz = I.dv[2];
   const long long mbase = (long long)b * nx * nv3;
-  const double* src = (MODE == kCopy) ? I.fin : I.buf[phase];
-  double* dst = I.buf[phase ^ 1];
-  src += mbase;
-  dst += mbase;
+  const double* src = ((MODE == kCopy) ? I.fin : I.buf[phase]) + mbase;
+  double* dst = I.buf[phase ^ 1] + mbase;
   const double a = I.a;
   const int len = i1 - i0;
   // global row of march position k (k = -1 and k = len are the halo rows)
   auto row_at = [&](int k) { return DIR > 0 ? i0 + k : i1 - 1 - k; };
-
   auto load_row = [&](int r, double2 (&raw)[P]) {
     if (MODE == kLift) return;
     const double* row = src + (long long)ghost_row(r, nx, I.bc) * nv3;
 #pragma unroll
     for (int p = 0; p < P; ++p)
-      raw[p] = ok[p] ? *reinterpret_cast<const double2*>(row + jofs[p])
-                     : make_double2(0.0, 0.0);
+      raw[p] = e.ok[p] ? *reinterpret_cast<const double2*>(row + e.jofs[p])
+                       : make_double2(0.0, 0.0);
   };
   auto relax_row = [&](int r, const double2 (&raw)[P], double2 (&out)[P]) {
     const double* fr = lds + (r - (i0 - 1)) * nvs;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      double2 v;
-      if (MODE == kCopy) {
-        v = raw[p];
-      } else {
-        const unsigned o = off[p];
-        const double fxy = fr[o & 1023u] * fr[(o >> 10) & 1023u];
-        const double* fz = fr + (o >> 20);
-        const double m0 = fxy * fz[0], m1 = fxy * fz[1];
-        if (MODE == kRelax) {
-          v.x = fma(a, raw[p].x, m0);
-          v.y = fma(a, raw[p].y, m1);
-        } else {
-          v.x = m0;
-          v.y = m1;
-        }
-      }
-      if (!FULL && !ok[p]) v = make_double2(0.0, 0.0);
+      double2 v = relax_pair<MODE>(fr, e.off[p], a, raw[p]);
+      if (!FULL && !e.ok[p]) v = make_double2(0.0, 0.0);
       out[p] = v;
     }
   };
@@ -362,43 +464,21 @@ __device__ __forceinline__ void step2_march(const Inst& I, const double* lds,
 #pragma unroll
     for (int p = 0; p < P; ++p) r1[p] = t0[p];
   }
-  double* part = I.part + ((long long)b * nx) * I.part_tiles * 5 + (tile * 4 + lane / 16) * 5;
   for (int k = 0; k < len; ++k) {
     if (k + 2 <= len) load_row(row_at(k + 2), r2);  // prefetch
     relax_row(row_at(k + 1), r1, fa);
     const int r = row_at(k);
-    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double s[NS];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) s[c] = 0.0;
     double* drow = dst + (long long)r * nv3;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      // upwind neighbour: cell r-1 for v_x > 0, r+1 for v_x < 0
-      const bool take_behind = (nu[p] > 0.0) == (DIR > 0);
-      const double cn = fabs(nu[p]);
-      const double2 nb = take_behind ? fb[p] : fa[p];
-      double2 g;
-      g.x = fma(cn, nb.x - f0[p].x, f0[p].x);
-      g.y = fma(cn, nb.y - f0[p].y, f0[p].y);
-      if (FULL || ok[p]) {
-#if BGK_NT_STORE
-        __builtin_nontemporal_store(g.x, drow + jofs[p]);
-        __builtin_nontemporal_store(g.y, drow + jofs[p] + 1);
-#else
-        *reinterpret_cast<double2*>(drow + jofs[p]) = g;
-#endif
-      }
-      const double gs = g.x + g.y;
-      s[0] += gs;
-      s[1] = fma(vx[p], gs, s[1]);
-      s[2] = fma(vy[p], gs, s[2]);
-      s[3] = fma(vz[p], gs, fma(dvz, g.y, s[3]));
-      s[4] = fma(q0[p], g.x, fma(q1[p], g.y, s[4]));
+      const double2 g = transport_pair<DIR>(e.nu[p], fb[p], f0[p], fa[p]);
+      if (FULL || e.ok[p]) store_pair(drow, e.jofs[p], g);
+      accum_pair<NS>(s, g, e.vx[p], e.vy[p], e.vz[p], dvz, e.q0[p], e.q1[p], e.nu[p]);
     }
-    row_sum5(s);
-    if ((lane & 15) == 15) {
-      double* pp = part + (long long)r * I.part_tiles * 5;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) pp[c] = s[c];
-    }
+    store_partials<NS>(I, s, b, r, tile, lane);
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       fb[p] = f0[p];
@@ -408,7 +488,18 @@ __device__ __forceinline__ void step2_march(const Inst& I, const double* lds,
   }
 }
 
-template <int P, int MODE>
+__device__ __forceinline__ void stage_rows(const Inst& I, const double* fac, int b,
+                                           int first_row, int rows, double* lds) {
+  const int nx = I.nx, nvs = I.nvs;
+  const double* f = fac + (long long)b * nx * nvs;
+  for (int idx = threadIdx.x; idx < rows * nvs; idx += kBlock) {
+    int rr = idx / nvs;
+    int k = idx - rr * nvs;
+    lds[idx] = f[(long long)ghost_row(first_row + rr, nx, I.bc) * nvs + k];
+  }
+}
+
+template <int P, int MODE, int NS>
 __global__ __launch_bounds__(kBlock) void k_step2(const Inst* __restrict__ insts,
                                                   int n_inst, int chunk,
                                                   int phase) {
@@ -421,17 +512,10 @@ __global__ __launch_bounds__(kBlock) void k_step2(const Inst* __restrict__ insts
   const long long t = local / I.nchunks;
   const int tg = (int)(t % I.ntg);
   const int b = (int)(t / I.ntg);
-  const int nx = I.nx, nvs = I.nvs;
   const int i0 = c * chunk;
-  const int i1 = min(i0 + chunk, nx);
+  const int i1 = min(i0 + chunk, I.nx);
   if (MODE != kCopy) {
-    const int rows = i1 - i0 + 2;
-    const double* fac = I.fac + (long long)b * nx * nvs;
-    for (int idx = threadIdx.x; idx < rows * nvs; idx += kBlock) {
-      int rr = idx / nvs;
-      int k = idx - rr * nvs;
-      lds[idx] = fac[(long long)ghost_row(i0 - 1 + rr, nx, I.bc) * nvs + k];
-    }
+    stage_rows(I, I.fac, b, i0 - 1, i1 - i0 + 2, lds);
     __syncthreads();
   }
   const int wave = threadIdx.x / kWave;
@@ -440,11 +524,158 @@ __global__ __launch_bounds__(kBlock) void k_step2(const Inst* __restrict__ insts
   if (tile >= I.ntiles) return;
   const bool full = (tile + 1) * (128 * P) <= I.nv3;
   if (c & 1) {
-    if (full) step2_march<P, MODE, true, -1>(I, lds, b, tile, lane, i0, i1, phase);
-    else step2_march<P, MODE, false, -1>(I, lds, b, tile, lane, i0, i1, phase);
+    if (full) step2_march<P, MODE, true, -1, NS>(I, lds, b, tile, lane, i0, i1, phase);
+    else step2_march<P, MODE, false, -1, NS>(I, lds, b, tile, lane, i0, i1, phase);
   } else {
-    if (full) step2_march<P, MODE, true, 1>(I, lds, b, tile, lane, i0, i1, phase);
-    else step2_march<P, MODE, false, 1>(I, lds, b, tile, lane, i0, i1, phase);
+    if (full) step2_march<P, MODE, true, 1, NS>(I, lds, b, tile, lane, i0, i1, phase);
+    else step2_march<P, MODE, false, 1, NS>(I, lds, b, tile, lane, i0, i1, phase);
+  }
+}
+
+// ------------------------------------------------ two steps in one pass --
+// Reads g^m once, writes g^{m+2} once: 8 bytes per phase-space update.
+//   f^m     = a g^m + al M[U(g^m)]            (lift: f^0 = M[U0])  -- factors fac
+//   g^{m+1} = T f^m                           (in registers)
+//   f^{m+1} = a g^{m+1} + al M[U(g^{m+1})]                          -- factors fac2
+//   g^{m+2} = T f^{m+1}                       (stored, with 15 weighted sums)
+// U(g^{m+1}) is known before the pass: transport is linear, so the moments of
+// T f^m at cell i follow from the nu-weighted moment sums of g^m and of
+// M[U(g^m)] at cells i-1, i, i+1 (the reduce kernel's kRedW2 mode).
+// The march keeps level-1 rows k..k+2 and level-2 rows k-1..k+1.  Level-2
+// values outside the domain are ghost copies of the boundary cell (Neumann)
+// or the wrapped cell (periodic), exactly as a single step would see them.
+template <int P, int MODE, bool FULL, int DIR>
+__device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
+                                              const double* lds2, int b, int tile,
+                                              int lane, int i0, int i1, int phase) {
+  const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
+  PairEls<P> e;
+  setup_pairs<P, FULL>(I, tile, lane, e);
+  const double dvz = I.dv[2];
+  const long long mbase = (long long)b * nx * nv3;
+  const double* src = I.buf[phase] + mbase;
+  double* dst = I.buf[phase ^ 1] + mbase;
+  const double a = I.a;
+  const bool neumann = I.bc == 0;
+  const int len = i1 - i0;
+  auto row_at = [&](int k) { return DIR > 0 ? i0 + k : i1 - 1 - k; };
+  auto outside = [&](int r) { return r < 0 || r >= nx; };
+  auto load_row = [&](int r, double2 (&raw)[P]) {
+    if (MODE == kLift) return;
+    const double* row = src + (long long)ghost_row(r, nx, I.bc) * nv3;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+      raw[p] = e.ok[p] ? *reinterpret_cast<const double2*>(row + e.jofs[p])
+                       : make_double2(0.0, 0.0);
+  };
+  // level 1: rows i0-2 .. i1+1 staged in lds1; level 2: rows i0-1 .. i1 in lds2
+  auto relax1 = [&](int r, const double2 (&raw)[P], double2 (&out)[P]) {
+    const double* fr = lds1 + (r - (i0 - 2)) * nvs;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      double2 v = relax_pair<MODE>(fr, e.off[p], a, raw[p]);
+      if (!FULL && !e.ok[p]) v = make_double2(0.0, 0.0);
+      out[p] = v;
+    }
+  };
+  auto level2 = [&](int r, const double2 (&b1)[P], const double2 (&c1)[P],
+                    const double2 (&a1)[P], double2 (&out)[P]) {
+    const double* fr = lds2 + (r - (i0 - 1)) * nvs;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const double2 g = transport_pair<DIR>(e.nu[p], b1[p], c1[p], a1[p]);
+      double2 v = relax_pair<kRelax>(fr, e.off[p], a, g);
+      if (!FULL && !e.ok[p]) v = make_double2(0.0, 0.0);
+      out[p] = v;
+    }
+  };
+
+  double2 f1b[P], f1c[P], f1a[P];  // level 1 at positions k, k+1, k+2
+  double2 f2b[P], f2c[P], f2a[P];  // level 2 at positions k-1, k, k+1
+  double2 rcur[P], rnext[P];       // raw rows k+2 (to relax), k+3 (in flight)
+#pragma unroll
+  for (int p = 0; p < P; ++p) rnext[p] = make_double2(0.0, 0.0);
+  {
+    double2 ra[P], rb[P], l0[P], l1[P];
+    load_row(row_at(-2), ra);
+    load_row(row_at(-1), rb);
+    relax1(row_at(-2), ra, l0);        // level 1 at -2
+    load_row(row_at(0), ra);
+    relax1(row_at(-1), rb, l1);        // level 1 at -1
+    load_row(row_at(1), rb);
+    relax1(row_at(0), ra, f1b);        // level 1 at 0
+    load_row(row_at(2), rcur);
+    relax1(row_at(1), rb, f1c);        // level 1 at 1
+    level2(row_at(-1), l0, l1, f1b, f2b);   // level 2 at -1
+    level2(row_at(0), l1, f1b, f1c, f2c);   // level 2 at 0
+    if (neumann && outside(row_at(-1))) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) f2b[p] = f2c[p];
+    }
+  }
+  for (int k = 0; k < len; ++k) {
+    if (k + 3 <= len + 1) load_row(row_at(k + 3), rnext);  // prefetch
+    relax1(row_at(k + 2), rcur, f1a);
+    level2(row_at(k + 1), f1b, f1c, f1a, f2a);
+    if (neumann && outside(row_at(k + 1))) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) f2a[p] = f2c[p];
+    }
+    const int r = row_at(k);
+    double s[15];
+#pragma unroll
+    for (int c = 0; c < 15; ++c) s[c] = 0.0;
+    double* drow = dst + (long long)r * nv3;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const double2 g = transport_pair<DIR>(e.nu[p], f2b[p], f2c[p], f2a[p]);
+      if (FULL || e.ok[p]) store_pair(drow, e.jofs[p], g);
+      accum_pair<15>(s, g, e.vx[p], e.vy[p], e.vz[p], dvz, e.q0[p], e.q1[p], e.nu[p]);
+    }
+    store_partials<15>(I, s, b, r, tile, lane);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      f1b[p] = f1c[p];
+      f1c[p] = f1a[p];
+      f2b[p] = f2c[p];
+      f2c[p] = f2a[p];
+      rcur[p] = rnext[p];
+    }
+  }
+}
+
+template <int P, int MODE>
+__global__ __launch_bounds__(kBlock) void k_step2x2(const Inst* __restrict__ insts,
+                                                    int n_inst, int chunk,
+                                                    int phase) {
+  extern __shared__ double lds[];
+  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const int q = find_inst(insts, n_inst, item);
+  const Inst& I = insts[q];
+  const long long local = item - I.item_begin;
+  const int c = (int)(local % I.nchunks);
+  const long long t = local / I.nchunks;
+  const int tg = (int)(t % I.ntg);
+  const int b = (int)(t / I.ntg);
+  const int i0 = c * chunk;
+  const int i1 = min(i0 + chunk, I.nx);
+  const int len = i1 - i0;
+  double* lds1 = lds;
+  double* lds2 = lds + (len + 4) * I.nvs;
+  stage_rows(I, I.fac, b, i0 - 2, len + 4, lds1);
+  stage_rows(I, I.fac2, b, i0 - 1, len + 2, lds2);
+  __syncthreads();
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int tile = tg * kWavesPerBlock + wave;
+  if (tile >= I.ntiles) return;
+  const bool full = (tile + 1) * (128 * P) <= I.nv3;
+  if (c & 1) {
+    if (full) step2x2_march<P, MODE, true, -1>(I, lds1, lds2, b, tile, lane, i0, i1, phase);
+    else step2x2_march<P, MODE, false, -1>(I, lds1, lds2, b, tile, lane, i0, i1, phase);
+  } else {
+    if (full) step2x2_march<P, MODE, true, 1>(I, lds1, lds2, b, tile, lane, i0, i1, phase);
+    else step2x2_march<P, MODE, false, 1>(I, lds1, lds2, b, tile, lane, i0, i1, phase);
   }
 }
 
@@ -534,6 +765,62 @@ __device__ __forceinline__ void write_factors(const Inst& I, double* row,
   }
 }
 
+// Separable moment sums of the Maxwellian with factors exp(-(v-u)^2/(2 theta))
+// per axis (C0 * dv3 applied by the caller): for weights w in {1, nu+, nu-} of
+// v_x (nu = v_x dt/dx), A^w = (rho, m_x, m_y, m_z, E) moments of w M.
+// Writes 15 values: A (5), A+ (5), A- (5), scaled by K = C0 dv3.  All lanes
+// return the same values.
+__device__ __forceinline__ void maxwell_weighted_sums(const Inst& I, int lane,
+                                                      const double u[3], double th,
+                                                      double K, double (&A)[15]) {
+  // x: X^w_k = sum w(vx) vx^k Ex, w in {1, nu+, nu-}, k = 0..2; y, z: k = 0..2
+  double t[15];
+#pragma unroll
+  for (int c = 0; c < 15; ++c) t[c] = 0.0;
+  const double inv2t = 1.0 / (2.0 * th);
+  for (int kk = lane; kk < I.nvs; kk += kWave) {
+    int ax = (kk < I.nvx) ? 0 : (kk < I.nvx + I.nvy ? 1 : 2);
+    int j = kk - (ax == 0 ? 0 : (ax == 1 ? I.nvx : I.nvx + I.nvy));
+    const double v = vgrid(I, ax, j);
+    const double d = v - u[ax];
+    const double ex = exp(-d * d * inv2t);
+    const double e1 = v * ex, e2 = v * v * ex;
+    if (ax == 0) {
+      const double nu = v * I.r;
+      const double wp = nu > 0.0 ? nu : 0.0, wm = nu < 0.0 ? -nu : 0.0;
+      t[0] += ex; t[1] += e1; t[2] += e2;
+      t[3] += wp * ex; t[4] += wp * e1; t[5] += wp * e2;
+      t[6] += wm * ex; t[7] += wm * e1; t[8] += wm * e2;
+    } else if (ax == 1) {
+      t[9] += ex; t[10] += e1; t[11] += e2;
+    } else {
+      t[12] += ex; t[13] += e1; t[14] += e2;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 15; ++c) t[c] = wave_sum_all(t[c]);
+  const double Y0 = t[9], Y1 = t[10], Y2 = t[11], Z0 = t[12], Z1 = t[13], Z2 = t[14];
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    const double X0 = t[3 * w], X1 = t[3 * w + 1], X2 = t[3 * w + 2];
+    A[5 * w + 0] = K * X0 * Y0 * Z0;
+    A[5 * w + 1] = K * X1 * Y0 * Z0;
+    A[5 * w + 2] = K * X0 * Y1 * Z0;
+    A[5 * w + 3] = K * X0 * Y0 * Z1;
+    A[5 * w + 4] = 0.5 * K * (X2 * Y0 * Z0 + X0 * Y2 * Z0 + X0 * Y0 * Z2);
+  }
+}
+
+__device__ __forceinline__ void cons_to_prim(const double* V, double& rho, double u[3],
+                                             double& th) {
+  rho = V[0];
+  u[0] = V[1] / rho;
+  u[1] = V[2] / rho;
+  u[2] = V[3] / rho;
+  const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  th = (2.0 * V[4] / rho - usq) / 3.0;
+}
+
 // One wave per (instance, member, x cell).
 __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ insts,
                                                    int n_inst,
@@ -545,17 +832,53 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
   long long cl;
   const int q = find_inst_cell(insts, n_inst, cell, &cl);
   const Inst& I = insts[q];
+  if (mode == kRedW2) {
+    // moments of the next transported field T(a g + al M[U(g)]) at this cell
+    const int nx = I.nx;
+    const long long b = cl / nx;
+    const int i = (int)(cl - b * nx);
+    const double* ac = I.aux + cl * kAux;
+    const double* am = I.aux + (b * nx + ghost_row(i - 1, nx, I.bc)) * kAux;
+    const double* ap = I.aux + (b * nx + ghost_row(i + 1, nx, I.bc)) * kAux;
+    double V[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const double tg = ac[c] - ac[5 + c] - ac[10 + c] + am[5 + c] + ap[10 + c];
+      const double tm = ac[15 + c] - ac[20 + c] - ac[25 + c] + am[20 + c] + ap[25 + c];
+      V[c] = I.a * tg + I.al * tm;
+    }
+    double rho, u[3], th;
+    cons_to_prim(V, rho, u, th);
+    if (lane == 0 && !physical(rho, th)) *status = 1;
+    write_factors(I, I.fac2 + cl * I.nvs, lane, I.al * rho * pow(2.0 * M_PI * th, -1.5),
+                  u, th);
+    return;
+  }
+  const int ns = I.nsum;
   const double* pp = I.part + cl * I.part_tiles * 5;
-  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double s[15];
+#pragma unroll
+  for (int c = 0; c < 15; ++c) s[c] = 0.0;
   for (int t = lane; t < I.nparts; t += kWave) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) s[c] += pp[t * 5 + c];
-  }
+    for (int c = 0; c < 5; ++c) s[c] += pp[t * ns + c];
+    if (mode == kRedW1) {
 #pragma unroll
-  for (int c = 0; c < 5; ++c) s[c] = wave_sum_all(s[c]);
-  const double rho = s[0] * I.dv3;
-  const double m[3] = {s[1] * I.dv3, s[2] * I.dv3, s[3] * I.dv3};
-  const double E = 0.5 * s[4] * I.dv3;
+      for (int c = 5; c < 15; ++c) s[c] += pp[t * ns + c];
+    }
+  }
+  const int nred = (mode == kRedW1) ? 15 : 5;
+  for (int c = 0; c < nred; ++c) s[c] = wave_sum_all(s[c]);
+  // conserved units: rho, m from sums times dv3; E = sum |v|^2 g dv3 / 2
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[5 * w + c] *= I.dv3;
+    s[5 * w + 4] *= 0.5 * I.dv3;
+  }
+  const double rho = s[0];
+  const double m[3] = {s[1], s[2], s[3]};
+  const double E = s[4];
   const double u[3] = {m[0] / rho, m[1] / rho, m[2] / rho};
   const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const double th = (2.0 * E / rho - usq) / 3.0;
@@ -580,52 +903,41 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
     return;
   }
   const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
-  if (mode == kRedRelaxFactors || mode == kRedMaxwellFactors) {
+  if (mode == kRedRelaxFactors || mode == kRedMaxwellFactors || mode == kRedW1) {
     write_factors(I, I.fac + cl * I.nvs, lane,
-                  mode == kRedRelaxFactors ? I.al * C0 : C0, u, th);
+                  mode == kRedMaxwellFactors ? C0 : I.al * C0, u, th);
+    if (mode == kRedW1) {
+      double A[15];
+      maxwell_weighted_sums(I, lane, u, th, C0 * I.dv3, A);
+      if (lane == 0) {
+        double* ax = I.aux + cl * kAux;
+#pragma unroll
+        for (int c = 0; c < 15; ++c) ax[c] = s[c];
+#pragma unroll
+        for (int c = 0; c < 15; ++c) ax[15 + c] = A[c];
+      }
+    }
     return;
   }
   // kRedProject: moments of the relaxed field a g + al M[U(g)], with the
   // moments of the separable Maxwellian as products of 1D sums.
-  double t9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  const double inv2t = 1.0 / (2.0 * th);
-  for (int k = lane; k < I.nvs; k += kWave) {
-    int ax = (k < I.nvx) ? 0 : (k < I.nvx + I.nvy ? 1 : 2);
-    int j = k - (ax == 0 ? 0 : (ax == 1 ? I.nvx : I.nvx + I.nvy));
-    double v = vgrid(I, ax, j);
-    double d = v - u[ax];
-    double e = exp(-d * d * inv2t);
-#pragma unroll
-    for (int a2 = 0; a2 < 3; ++a2) {
-      if (a2 == ax) {
-        t9[3 * a2] += e;
-        t9[3 * a2 + 1] += v * e;
-        t9[3 * a2 + 2] += v * v * e;
-      }
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < 9; ++c) t9[c] = wave_sum_all(t9[c]);
-  const double K = C0 * I.dv3;
-  const double X0 = t9[0], X1 = t9[1], X2 = t9[2];
-  const double Y0 = t9[3], Y1 = t9[4], Y2 = t9[5];
-  const double Z0 = t9[6], Z1 = t9[7], Z2 = t9[8];
-  const double vm[5] = {K * X0 * Y0 * Z0, K * X1 * Y0 * Z0, K * X0 * Y1 * Z0,
-                        K * X0 * Y0 * Z1,
-                        0.5 * K * (X2 * Y0 * Z0 + X0 * Y2 * Z0 + X0 * Y0 * Z2)};
+  double A[15];
+  maxwell_weighted_sums(I, lane, u, th, C0 * I.dv3, A);
   const double vgv[5] = {rho, m[0], m[1], m[2], E};
   if (lane == 0) {
     double* vo = I.vout + cl * 5;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) vo[c] = I.a * vgv[c] + I.al * vm[c];
+    for (int c = 0; c < 5; ++c) vo[c] = I.a * vgv[c] + I.al * A[c];
   }
 }
 
 // Lift factors: C = rho (2 pi theta)^{-3/2} from primitive W (if given) or
-// from the conserved vin of each member.
+// from the conserved vin of each member.  with_aux: also the weighted
+// Maxwellian sums into aux (both the "g" and the "M" slots: the lifted field
+// is its own Maxwellian), for a two-step first pass.
 __global__ __launch_bounds__(kBlock) void k_lift_factors(
     const Inst* __restrict__ insts, int n_inst, long long total_cells,
-    const double* __restrict__ W, int* status) {
+    const double* __restrict__ W, int* status, int with_aux) {
   const long long cell = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (cell >= total_cells) return;
   const int lane = threadIdx.x % kWave;
@@ -641,19 +953,25 @@ __global__ __launch_bounds__(kBlock) void k_lift_factors(
     u[2] = w[3];
     th = w[4];
   } else {
-    const double* v = I.vin + cl * 5;
-    rho = v[0];
-    u[0] = v[1] / rho;
-    u[1] = v[2] / rho;
-    u[2] = v[3] / rho;
-    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    th = (2.0 * v[4] / rho - usq) / 3.0;
+    cons_to_prim(I.vin + cl * 5, rho, u, th);
   }
   if (!physical(rho, th) || !isfinite(u[0]) || !isfinite(u[1]) || !isfinite(u[2])) {
     if (lane == 0) *status = 1;
   }
-  write_factors(I, I.fac + cl * I.nvs, lane, rho * pow(2.0 * M_PI * th, -1.5),
-                u, th);
+  const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
+  write_factors(I, I.fac + cl * I.nvs, lane, C0, u, th);
+  if (with_aux) {
+    double A[15];
+    maxwell_weighted_sums(I, lane, u, th, C0 * I.dv3, A);
+    if (lane == 0) {
+      double* ax = I.aux + cl * kAux;
+#pragma unroll
+      for (int c = 0; c < 15; ++c) {
+        ax[c] = A[c];
+        ax[15 + c] = A[c];
+      }
+    }
+  }
 }
 
 // f_out = a g + F (relaxation of the last transported field), or f_out = F
@@ -702,7 +1020,8 @@ __global__ __launch_bounds__(kBlock) void k_relax_out(
 static int blocks_for(long long n) { return (int)n; }
 
 int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode,
-                int phase, Tiles t, int lds_doubles, int* d_status, hipStream_t s) {
+                int phase, Tiles t, int lds_doubles, int* d_status, hipStream_t s,
+                int ns) {
   (void)d_status;
   if (total_items <= 0) return BGK_OK;
   dim3 grid(blocks_for(total_items)), block(kBlock);
@@ -715,16 +1034,26 @@ int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode
     hipError_t e_ = hipGetLastError();                                      \
     return e_ == hipSuccess ? BGK_OK : hip_fail(e_, "k_step");              \
   }
-  if (t.pair) {
-    BGK_STEP_CASE((k_step2<1, kCopy>), 2, kCopy)
-    BGK_STEP_CASE((k_step2<1, kRelax>), 2, kRelax)
-    BGK_STEP_CASE((k_step2<1, kLift>), 2, kLift)
-    BGK_STEP_CASE((k_step2<2, kCopy>), 4, kCopy)
-    BGK_STEP_CASE((k_step2<2, kRelax>), 4, kRelax)
-    BGK_STEP_CASE((k_step2<2, kLift>), 4, kLift)
-    BGK_STEP_CASE((k_step2<4, kCopy>), 8, kCopy)
-    BGK_STEP_CASE((k_step2<4, kRelax>), 8, kRelax)
-    BGK_STEP_CASE((k_step2<4, kLift>), 8, kLift)
+  if (t.pair && ns == 15) {
+    BGK_STEP_CASE((k_step2<1, kCopy, 15>), 2, kCopy)
+    BGK_STEP_CASE((k_step2<1, kRelax, 15>), 2, kRelax)
+    BGK_STEP_CASE((k_step2<1, kLift, 15>), 2, kLift)
+    BGK_STEP_CASE((k_step2<2, kCopy, 15>), 4, kCopy)
+    BGK_STEP_CASE((k_step2<2, kRelax, 15>), 4, kRelax)
+    BGK_STEP_CASE((k_step2<2, kLift, 15>), 4, kLift)
+    BGK_STEP_CASE((k_step2<4, kCopy, 15>), 8, kCopy)
+    BGK_STEP_CASE((k_step2<4, kRelax, 15>), 8, kRelax)
+    BGK_STEP_CASE((k_step2<4, kLift, 15>), 8, kLift)
+  } else if (t.pair) {
+    BGK_STEP_CASE((k_step2<1, kCopy, 5>), 2, kCopy)
+    BGK_STEP_CASE((k_step2<1, kRelax, 5>), 2, kRelax)
+    BGK_STEP_CASE((k_step2<1, kLift, 5>), 2, kLift)
+    BGK_STEP_CASE((k_step2<2, kCopy, 5>), 4, kCopy)
+    BGK_STEP_CASE((k_step2<2, kRelax, 5>), 4, kRelax)
+    BGK_STEP_CASE((k_step2<2, kLift, 5>), 4, kLift)
+    BGK_STEP_CASE((k_step2<4, kCopy, 5>), 8, kCopy)
+    BGK_STEP_CASE((k_step2<4, kRelax, 5>), 8, kRelax)
+    BGK_STEP_CASE((k_step2<4, kLift, 5>), 8, kLift)
   } else {
     BGK_STEP_CASE((k_step<2, kCopy>), 2, kCopy)
     BGK_STEP_CASE((k_step<2, kRelax>), 2, kRelax)
@@ -736,6 +1065,26 @@ int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode
     BGK_STEP_CASE((k_step<8, kRelax>), 8, kRelax)
     BGK_STEP_CASE((k_step<8, kLift>), 8, kLift)
   }
+  set_error("unsupported tile shape");
+  return BGK_E_INVALID;
+}
+
+int launch_step2x2(const Inst* d_insts, int n_inst, long long total_items, int mode,
+                   int phase, Tiles t, int lds_doubles, hipStream_t s) {
+  if (total_items <= 0) return BGK_OK;
+  if (!t.pair) {
+    set_error("two-step passes need the paired lane mapping");
+    return BGK_E_INVALID;
+  }
+  dim3 grid(blocks_for(total_items)), block(kBlock);
+  size_t lds = (size_t)lds_doubles * sizeof(double);
+  const int chunk = t.chunk;
+  BGK_STEP_CASE((k_step2x2<1, kRelax>), 2, kRelax)
+  BGK_STEP_CASE((k_step2x2<1, kLift>), 2, kLift)
+  BGK_STEP_CASE((k_step2x2<2, kRelax>), 4, kRelax)
+  BGK_STEP_CASE((k_step2x2<2, kLift>), 4, kLift)
+  BGK_STEP_CASE((k_step2x2<4, kRelax>), 8, kRelax)
+  BGK_STEP_CASE((k_step2x2<4, kLift>), 8, kLift)
 #undef BGK_STEP_CASE
   set_error("unsupported tile shape");
   return BGK_E_INVALID;
@@ -771,11 +1120,11 @@ int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
 }
 
 int launch_lift_factors(const Inst* d_insts, int n_inst, long long total_cells,
-                        const double* W, int* d_status, hipStream_t s) {
+                        const double* W, int* d_status, hipStream_t s, int with_aux) {
   if (total_cells <= 0) return BGK_OK;
   dim3 grid((unsigned)((total_cells + kWavesPerBlock - 1) / kWavesPerBlock));
   hipLaunchKernelGGL(k_lift_factors, grid, dim3(kBlock), 0, s, d_insts, n_inst,
-                     total_cells, W, d_status);
+                     total_cells, W, d_status, with_aux);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }

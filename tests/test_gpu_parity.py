@@ -41,8 +41,10 @@ TILES = [(0, 0, -1), (2, 1, 0), (4, 3, 0), (8, 16, 0), (2, 64, 0), (2, 1, 1), (4
 @pytest.fixture(autouse=True)
 def _reset_tiles():
     bgk.set_tiles(0, 0, -1)
+    bgk.set_step_fusion(2)
     yield
     bgk.set_tiles(0, 0, -1)
+    bgk.set_step_fusion(2)
 
 
 def states(p, seed, perturb=0.2):
@@ -92,6 +94,43 @@ def test_fine_steps(name, tiles):
     got = bgk.fine_steps(p, cuda(f), dt, n).cpu().numpy()
     bgk.check_status()
     assert rel_f(got, oracle.fine_steps(p, f, dt, n)) < TOL
+
+
+FUSION_GRIDS = ["sod_nx64_nv16", "asym_box", "wide_periodic", "even_z_ragged"]
+
+
+@pytest.mark.parametrize("tiles", [(0, 0, -1), (2, 1, 1), (4, 3, 1), (8, 64, 1)])
+@pytest.mark.parametrize("n", [2, 3, 4, 7])
+@pytest.mark.parametrize("name", FUSION_GRIDS)
+def test_two_steps_per_pass(name, n, tiles):
+    """Steps fused two per pass (next moments by linearity of the transport)
+    agree with the oracle and with one step per pass."""
+    p = GRIDS[name]
+    bgk.set_tiles(*tiles)
+    _, f = states(p, 60 + n)
+    dt = 0.4 * (1.0 / p.nx) / max(abs(p.v_lo[0]), abs(p.v_hi[0]))
+    fused = bgk.fine_steps(p, cuda(f), dt, n).cpu().numpy()
+    bgk.check_status()
+    bgk.set_step_fusion(1)
+    single = bgk.fine_steps(p, cuda(f), dt, n).cpu().numpy()
+    ref = oracle.fine_steps(p, f, dt, n)
+    assert rel_f(fused, ref) < TOL
+    assert rel_f(single, ref) < TOL
+    assert rel_f(fused, single) < 1e-13
+
+
+@pytest.mark.parametrize("n_span", [0.0021, 0.004, 0.0065])
+@pytest.mark.parametrize("name", ["sod_nx64_nv16", "wide_periodic", "even_z_ragged"])
+def test_two_steps_per_pass_from_lift(name, n_span):
+    p = GRIDS[name]
+    W, _ = states(p, 70)
+    V = np.column_stack([W[:, 0], W[:, 0:1] * W[:, 1:4],
+                         0.5 * W[:, 0] * (W[:, 1:4] ** 2).sum(1) + 1.5 * W[:, 0] * W[:, 4]])
+    Vin = np.stack([V, V[::-1].copy()])
+    got = bgk.fine_propagate_moments(p, cuda(Vin), n_span).cpu().numpy()
+    bgk.check_status()
+    for b in range(2):
+        assert rel_V(got[b], oracle.fine_propagate_moments(p, Vin[b], n_span)) < TOL
 
 
 def test_fine_step_sod_slice():
@@ -335,16 +374,17 @@ def test_invalid_arguments_rejected():
 
 # ------------------------------------------------------ full-size workloads --
 def test_sod_large_full_size_two_steps():
-    """Nx=2048, 48^3 on [-10,10]^3 (the large Sod workload): two steps from the
-    lifted Sod data, whole field against the oracle."""
+    """Nx=2048, 48^3 on [-10,10]^3 (the large Sod workload): three steps from
+    the lifted Sod data (one single step, one fused pair), whole field against
+    the oracle."""
     wk = wl.c3_sod_large()
     p = wk.problem
     n, dt = oracle.n_steps(p, wk.T / wk.n_slices)
     assert n == 188
     f0 = oracle.lift(p, wk.W0)
-    got = bgk.fine_steps(p, cuda(f0), dt, 2).cpu().numpy()
+    got = bgk.fine_steps(p, cuda(f0), dt, 3).cpu().numpy()
     bgk.check_status()
-    ref = oracle.fine_steps(p, f0, dt, 2)
+    ref = oracle.fine_steps(p, f0, dt, 3)
     assert rel_f(got, ref) < TOL
 
 
