@@ -95,9 +95,10 @@ static bool g_fuse2 = true;  // two IMEX steps per pass where possible
 Tiles choose_tiles(const bgk_problem& p, int batch) {
   std::lock_guard<std::mutex> lk(g_mu);
   const int pair = p.nv[2] % 2 == 0 ? 1 : 0;
-  // measured best on the 512 x 32^3 x 64-slice batch: fused passes favour
-  // 4 velocities per lane over long chunks, single steps 8 over short ones
-  Tiles t = (pair && g_fuse2) ? Tiles{4, 16, 1} : Tiles{8, 4, pair};
+  // measured best on the 512 x 32^3 x 64-slice batch with 8-wave blocks:
+  // fused passes 8 velocities per lane over 16-cell chunks, single steps 8
+  // over short chunks
+  Tiles t = (pair && g_fuse2) ? Tiles{8, 16, 1} : Tiles{8, 4, pair};
   auto it = g_tuned.find({p.nx, p.nv[0], p.nv[1], p.nv[2], batch});
   if (it != g_tuned.end()) t = it->second;
   else {
@@ -138,17 +139,18 @@ struct FineRegions {  // fine solve of B members of one grid
 };
 constexpr size_t kNone = ~(size_t)0;  // region not allocated
 
-// Partial sums per x cell: at most one per wave tile of the generic kernel,
-// four (one per 16-lane row) per tile of the paired kernel.
+// Capacity per x cell, in 5-double units: one record (5 or 15 doubles) per
+// wave tile of at least 64 * kMinElems velocities.
 static int part_tiles_of(const bgk_problem& p) {
-  return 4 * (int)((nv3_of(p) + kWave * kMinElems - 1) / (kWave * kMinElems));
+  return 3 * (int)((nv3_of(p) + kWave * kMinElems - 1) / (kWave * kMinElems));
 }
 
-static FineRegions carve_fine(Carve& c, const bgk_problem& p, int B, bool two_bufs) {
+// nbufs: phase-space buffers of B members to carve (0, 1 or 2).
+static FineRegions carve_fine(Carve& c, const bgk_problem& p, int B, int nbufs) {
   FineRegions r;
   const size_t f = (size_t)B * p.nx * nv3_of(p) * sizeof(double);
-  r.buf0 = c.take(f);
-  r.buf1 = two_bufs ? c.take(f) : kNone;
+  r.buf0 = nbufs >= 1 ? c.take(f) : kNone;
+  r.buf1 = nbufs >= 2 ? c.take(f) : kNone;
   r.part = c.take((size_t)B * p.nx * part_tiles_of(p) * 5 * sizeof(double));
   r.fac = c.take((size_t)B * p.nx * (p.nv[0] + p.nv[1] + p.nv[2]) * sizeof(double));
   r.vg = c.take((size_t)B * p.nx * 5 * sizeof(double));
@@ -162,7 +164,7 @@ struct Layout {
   size_t header = 0, insts = 0;
   FineRegions fine{};
   size_t coarse = 0;                 // Euler scratch
-  size_t U0 = 0, U1 = 0, Gc = 0, VF = 0;
+  size_t U0 = 0, U1 = 0, Gc = 0, VF = 0, errs = 0;
   size_t states = 0, fbA = 0, fbB = 0, part6 = 0, coef = 0, dle = 0;
   size_t total = 0;
 };
@@ -176,28 +178,29 @@ static Layout layout_of(const bgk_problem& p, int op, int batch) {
   const size_t sl = (size_t)p.nx * 5 * sizeof(double);
   switch (op) {
     case BGK_OP_FINE_STEP:
-      L.fine = carve_fine(c, p, 1, false);
+      L.fine = carve_fine(c, p, 1, 1);
       break;
     case BGK_OP_MOMENTS:
     case BGK_OP_LIFT:
-      L.fine = carve_fine(c, p, 1, false);
+      L.fine = carve_fine(c, p, 1, 0);
       break;
     case BGK_OP_COARSE:
       L.coarse = c.take((size_t)batch * 16 * p.nx * sizeof(double));
       break;
     case BGK_OP_PROPAGATE:
-      L.fine = carve_fine(c, p, batch, true);
+      L.fine = carve_fine(c, p, batch, 2);
       break;
     case BGK_OP_PARAREAL:
-      L.fine = carve_fine(c, p, batch, true);
+      L.fine = carve_fine(c, p, batch, 2);
       L.coarse = c.take((size_t)21 * p.nx * sizeof(double));
+      L.errs = c.take((size_t)(batch + 1) * sizeof(double));
       L.U0 = c.take(sl * (batch + 1));
       L.U1 = c.take(sl * (batch + 1));
       L.Gc = c.take(sl * (batch + 1));
       L.VF = c.take(sl * (batch + 1));
       break;
     case BGK_OP_ADJOINT: {
-      L.fine = carve_fine(c, p, 1, false);
+      L.fine = carve_fine(c, p, 1, 1);
       L.states = c.take(f1 * batch);
       L.fbA = c.take(f1);
       L.fbB = c.take(f1);
@@ -308,7 +311,7 @@ static Inst make_inst(const bgk_problem& p, int B, double dt, Tiles t, int ns = 
   I.ntiles = (I.nv3 + kWave * t.elems - 1) / (kWave * t.elems);
   I.ntg = (I.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   I.nsum = ns;
-  I.nparts = t.pair ? (ns == 15 ? I.ntiles : 4 * I.ntiles) : I.ntiles;
+  I.nparts = I.ntiles;  // one partial record per wave tile
   I.nchunks = (p.nx + t.chunk - 1) / t.chunk;
   I.items = (long long)B * I.ntg * I.nchunks;
   I.part_tiles = part_tiles_of(p);
@@ -330,7 +333,7 @@ static Inst make_inst(const bgk_problem& p, int B, double dt, Tiles t, int ns = 
 }
 
 static void attach_fine(Inst& I, void* ws, const FineRegions& r, double* buf1) {
-  I.buf[0] = at<double>(ws, r.buf0);
+  I.buf[0] = r.buf0 == kNone ? nullptr : at<double>(ws, r.buf0);
   I.buf[1] = buf1 ? buf1 : (r.buf1 == kNone ? nullptr : at<double>(ws, r.buf1));
   I.part = at<double>(ws, r.part);
   I.fac = at<double>(ws, r.fac);
@@ -718,6 +721,7 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
   double* Gc = at<double>(ws, L.Gc);
   double* VF = at<double>(ws, L.VF);
   double* scratch = at<double>(ws, L.coarse);
+  double* errs = at<double>(ws, L.errs);  // per-iteration errors (fixed K)
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, st, 0);
   BGK_HIP(hipGetLastError());
   if ((rc = launch_pararealsweep_init(*prob, n_slices, W0, U[0], Gc, span, scratch, st, s)))
@@ -740,13 +744,16 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
       int last = 0;
       if ((r = lift_and_run(dI, I, n, true, t, st, q, &last))) return r;
       return launch_parareal_sweep(*prob, n_slices, k, U[cur], U[cur ^ 1], VF, Gc, span,
-                                   scratch, &hd->err, st, q);
+                                   scratch, tol > 0.0 ? &hd->err : errs + k, st, q);
     };
     if ((rc = run_graph(graph_key("pit", ws, ws_bytes, *prob,
                                   {(double)n_slices, span, (double)k, (double)t.elems,
                                    (double)t.chunk, (double)t.pair, (double)I.nsum}),
                         s, iteration)))
       return rc;
+    cur ^= 1;
+    kd = k + 1;
+    if (!(tol > 0.0)) continue;  // fixed K: nothing to decide on the host yet
     struct {
       int status;
       int pad;
@@ -754,15 +761,25 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
     } h;
     BGK_HIP(hipMemcpyAsync(&h, hd, sizeof(h), hipMemcpyDeviceToHost, s));
     BGK_HIP(hipStreamSynchronize(s));
-    cur ^= 1;
     err_hist[k] = h.err;
-    kd = k + 1;
     if (h.status) {
       if (k_done) *k_done = kd;
       set_error("non-physical state during parareal iteration");
       return BGK_E_NONPHYSICAL;
     }
     if (h.err < tol) break;
+  }
+  if (!(tol > 0.0) && kd > 0) {
+    // one readback for all iterations
+    int st_h = 0;
+    BGK_HIP(hipMemcpyAsync(err_hist, errs, sizeof(double) * kd, hipMemcpyDeviceToHost, s));
+    BGK_HIP(hipMemcpyAsync(&st_h, st, sizeof(int), hipMemcpyDeviceToHost, s));
+    BGK_HIP(hipStreamSynchronize(s));
+    if (st_h) {
+      if (k_done) *k_done = kd;
+      set_error("non-physical state during parareal iteration");
+      return BGK_E_NONPHYSICAL;
+    }
   }
   if (k_done) *k_done = kd;
   BGK_HIP(hipMemcpyAsync(V_out, U[cur], sl * (n_slices + 1) * sizeof(double),
@@ -944,7 +961,7 @@ static BatchedLayout batched_layout(const bgk_problem* probs, int n) {
   BatchedLayout L;
   L.header = c.take(sizeof(WsHeader));
   L.insts = c.take(sizeof(Inst) * (size_t)n);
-  for (int q = 0; q < n; ++q) L.regions.push_back(carve_fine(c, probs[q], 1, false));
+  for (int q = 0; q < n; ++q) L.regions.push_back(carve_fine(c, probs[q], 1, 1));
   L.total = c.off;
   return L;
 }

@@ -4,8 +4,9 @@
 // G is the Euler system in conserved variables V = (rho, rho u, E) with
 // Rusanov fluxes and adaptive CFL substeps.  It is cheap (5 Nx numbers) and
 // inherently sequential in time, so one workgroup owns one propagation: it
-// keeps the state in a global scratch slab (L2-resident) and synchronises
-// with workgroup barriers, and the whole sequential correction sweep of an
+// keeps the state in LDS (or an L2-resident global slab when it does not fit)
+// and synchronises with workgroup barriers, and the whole sequential
+// correction sweep of an
 // iteration (N slices, each a G propagation plus the jump update) runs inside
 // one single-workgroup kernel with no host round trip.
 #include "bgk_internal.h"
@@ -39,8 +40,9 @@ __device__ double block_max(double v, double* red) {
   return m;
 }
 
-// Propagates one state over `span`; scratch holds 16*nx doubles.
-// Returns the substep count (identical in all threads).
+// Propagates one state over `span`; scratch holds 16*nx doubles (in LDS
+// when it fits, else an L2-resident global slab).  Returns the substep count
+// (identical in all threads).
 __device__ int euler_propagate(const CoarseGeo& G, const double* Vin,
                                double* Vout, double span, double* scratch,
                                double* red, int* status) {
@@ -74,7 +76,7 @@ __device__ int euler_propagate(const CoarseGeo& G, const double* Vin,
       lmax = fmax(lmax, spd[i]);
     }
     if (bad) *status = 1;
-    const double smax = block_max(bad ? NAN : lmax, red);  // includes a barrier
+    const double smax = block_max(bad ? INFINITY : lmax, red);  // includes a barrier
     if (!(smax > 0.0) || !isfinite(smax) || nsub >= kMaxSubsteps) {
       *status = 1;
       break;  // uniform: every thread sees the same smax and nsub
@@ -106,22 +108,29 @@ __device__ int euler_propagate(const CoarseGeo& G, const double* Vin,
   return nsub;
 }
 
+// Scratch of one workgroup: its dynamic LDS when use_lds, else the slab.
+__device__ __forceinline__ double* coarse_scratch(bool use_lds, double* slab) {
+  extern __shared__ double lds_scratch[];
+  return use_lds ? lds_scratch : slab;
+}
+
 __global__ __launch_bounds__(kCoarseBlock) void k_euler(
     CoarseGeo G, const double* __restrict__ Vin, double* Vout, double span,
-    int* nsub_out, double* scratch, int* status) {
+    int* nsub_out, double* scratch, int* status, int use_lds) {
   __shared__ double red[kCoarseBlock / 64];
   const long long m = blockIdx.x;
   const long long sl = 5LL * G.nx;
-  int n = euler_propagate(G, Vin + m * sl, Vout + m * sl, span,
-                          scratch + m * 16LL * G.nx, red, status);
+  double* sc = coarse_scratch(use_lds, scratch + m * 16LL * G.nx);
+  int n = euler_propagate(G, Vin + m * sl, Vout + m * sl, span, sc, red, status);
   if (nsub_out != nullptr && threadIdx.x == 0) nsub_out[m] = n;
 }
 
 // U[0] = V(W0), U[n] = G(U[n-1]) for n = 1..N; Gc[n] = U[n].
 __global__ __launch_bounds__(kCoarseBlock) void k_parareal_init(
     CoarseGeo G, int n_slices, const double* __restrict__ W0, double* U,
-    double* Gc, double span, double* scratch, int* status) {
+    double* Gc, double span, double* scratch_slab, int* status, int use_lds) {
   __shared__ double red[kCoarseBlock / 64];
+  double* scratch = coarse_scratch(use_lds, scratch_slab);
   const int nx = G.nx;
   const long long sl = 5LL * nx;
   for (int i = threadIdx.x; i < nx; i += blockDim.x) {
@@ -149,8 +158,9 @@ __global__ __launch_bounds__(kCoarseBlock) void k_parareal_init(
 __global__ __launch_bounds__(kCoarseBlock) void k_parareal_sweep(
     CoarseGeo G, int n_slices, int k, const double* __restrict__ U_old,
     double* U_new, const double* __restrict__ VF, double* Gc, double span,
-    double* scratch, double* err, int* status) {
+    double* scratch_slab, double* err, int* status, int use_lds) {
   __shared__ double red[kCoarseBlock / 64];
+  double* scratch = coarse_scratch(use_lds, scratch_slab);
   const long long sl = 5LL * G.nx;
   for (long long q = threadIdx.x; q < (k + 1) * sl; q += blockDim.x) U_new[q] = U_old[q];
   __syncthreads();
@@ -181,13 +191,25 @@ CoarseGeo geo_of(const bgk_problem& p) {
   return G;
 }
 
+// Threads per coarse workgroup: one per cell up to 256 (whole waves).
+int coarse_threads(int nx) {
+  return nx <= 64 ? 64 : (nx <= 128 ? 128 : kCoarseBlock);
+}
+
+// Dynamic LDS bytes for `doubles` of scratch, or 0 if it must stay in HBM.
+size_t coarse_lds(size_t doubles) {
+  const size_t bytes = doubles * sizeof(double);
+  return bytes <= 60 * 1024 ? bytes : 0;
+}
+
 }  // namespace
 
 int launch_euler(const bgk_problem& p, int batch, const double* V_in,
                  double* V_out, double t_span, int* n_sub, double* scratch,
                  int* d_status, hipStream_t s) {
-  hipLaunchKernelGGL(k_euler, dim3(batch), dim3(kCoarseBlock), 0, s, geo_of(p),
-                     V_in, V_out, t_span, n_sub, scratch, d_status);
+  const size_t lds = coarse_lds(16 * (size_t)p.nx);
+  hipLaunchKernelGGL(k_euler, dim3(batch), dim3(coarse_threads(p.nx)), lds, s, geo_of(p),
+                     V_in, V_out, t_span, n_sub, scratch, d_status, lds ? 1 : 0);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }
@@ -196,8 +218,10 @@ int launch_pararealsweep_init(const bgk_problem& p, int n_slices,
                               const double* W0, double* U, double* Gc,
                               double t_span, double* scratch, int* d_status,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_parareal_init, dim3(1), dim3(kCoarseBlock), 0, s,
-                     geo_of(p), n_slices, W0, U, Gc, t_span, scratch, d_status);
+  const size_t lds = coarse_lds(16 * (size_t)p.nx);
+  hipLaunchKernelGGL(k_parareal_init, dim3(1), dim3(coarse_threads(p.nx)), lds, s,
+                     geo_of(p), n_slices, W0, U, Gc, t_span, scratch, d_status,
+                     lds ? 1 : 0);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }
@@ -206,9 +230,10 @@ int launch_parareal_sweep(const bgk_problem& p, int n_slices, int k,
                           const double* U_old, double* U_new, const double* VF,
                           double* Gc, double t_span, double* scratch,
                           double* d_err, int* d_status, hipStream_t s) {
-  hipLaunchKernelGGL(k_parareal_sweep, dim3(1), dim3(kCoarseBlock), 0, s,
+  const size_t lds = coarse_lds(21 * (size_t)p.nx);
+  hipLaunchKernelGGL(k_parareal_sweep, dim3(1), dim3(coarse_threads(p.nx)), lds, s,
                      geo_of(p), n_slices, k, U_old, U_new, VF, Gc, t_span,
-                     scratch, d_err, d_status);
+                     scratch, d_err, d_status, lds ? 1 : 0);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }

@@ -254,49 +254,102 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
 // velocities tile*128P + p*128 + 2l + {0,1} (requires even nv_z, so a pair
 // never straddles a v_z row, and 16-byte aligned rows).
 //
-// Moment partials: with NS = 5 the five moment sums are reduced over the 16
-// lanes of each DPP row only and stored 4 per wave; with NS = 15 they are
-// joined by the same sums weighted by nu+ = max(nu,0) and nu- = max(-nu,0)
-// (needed to predict the next step's moments, see the two-step kernel) and
-// reduced over the whole wave, one partial per wave.
+// Moment partials, one record per wave and x cell: the five moment sums
+// (NS = 5), joined with NS = 15 by the same sums weighted by nu+ = max(nu,0)
+// and nu- = max(-nu,0) (needed to predict the next step's moments, see the
+// two-step kernel), reduced over the wave by reduce-scatter.
 
-// Row-level (16-lane) sums of five values, interleaved; valid in lane 15 of
-// each row.
-__device__ __forceinline__ void row_sum5(double (&s)[5]) {
-#pragma unroll
-  for (int c = 0; c < 5; ++c) s[c] += dpp_mov<0xb1, 0xf>(s[c]);  // quad_perm [1,0,3,2]
-#pragma unroll
-  for (int c = 0; c < 5; ++c) s[c] += dpp_mov<0x4e, 0xf>(s[c]);  // quad_perm [2,3,0,1]
-#pragma unroll
-  for (int c = 0; c < 5; ++c) s[c] += dpp_mov<0x114, 0xf>(s[c]); // row_shr:4
-#pragma unroll
-  for (int c = 0; c < 5; ++c) s[c] += dpp_mov<0x118, 0xf>(s[c]); // row_shr:8
+// Lane exchange with partner lane ^ (1 << STAGE): DPP quad permutations for
+// bits 0-1, ds_swizzle (bit mode, within 32 lanes) for bits 2-4, bpermute for
+// bit 5.
+template <int PATTERN>
+__device__ __forceinline__ double swizzle_d(double v) {
+  int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), PATTERN);
+  int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), PATTERN);
+  return __hiloint2double(hi, lo);
 }
 
-// Whole-wave sums of N values, interleaved; valid in lane 63.
-template <int N>
-__device__ __forceinline__ void wave_sums_last(double (&s)[N]) {
-#pragma unroll
-  for (int c = 0; c < N; ++c) s[c] += dpp_mov<0xb1, 0xf>(s[c]);
-#pragma unroll
-  for (int c = 0; c < N; ++c) s[c] += dpp_mov<0x4e, 0xf>(s[c]);
-#pragma unroll
-  for (int c = 0; c < N; ++c) s[c] += dpp_mov<0x114, 0xf>(s[c]);
-#pragma unroll
-  for (int c = 0; c < N; ++c) s[c] += dpp_mov<0x118, 0xf>(s[c]);
-#pragma unroll
-  for (int c = 0; c < N; ++c) s[c] += dpp_mov<0x142, 0xa>(s[c]);
-#pragma unroll
-  for (int c = 0; c < N; ++c) s[c] += dpp_mov<0x143, 0xc>(s[c]);
+template <int STAGE>
+__device__ __forceinline__ double xor_lane(double v) {
+  if (STAGE == 0) return dpp_mov<0xb1, 0xf>(v);        // quad_perm [1,0,3,2]
+  if (STAGE == 1) return dpp_mov<0x4e, 0xf>(v);        // quad_perm [2,3,0,1]
+  if (STAGE == 2) return swizzle_d<0x1F | (4 << 10)>(v);
+  if (STAGE == 3) return swizzle_d<0x1F | (8 << 10)>(v);
+  if (STAGE == 4) return swizzle_d<0x1F | (16 << 10)>(v);
+  return __shfl_xor(v, 32, kWave);
 }
+
+// One reduce-scatter stage: the lanes split by bit STAGE; each keeps one half
+// of its H*2 running sums (the half its partner does not keep), adds the
+// partner's copy of that half, and drops the other.
+template <int STAGE, int H, int N>
+__device__ __forceinline__ void scatter_stage(double (&s)[N], int lane) {
+  const bool upper = (lane >> STAGE) & 1;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const double send = upper ? s[i] : s[i + H];
+    const double keep = upper ? s[i + H] : s[i];
+    s[i] = keep + xor_lane<STAGE>(send);
+  }
+}
+
+// Sums of 16 values over the 64 lanes of a wave by reduce-scatter: 17 lane
+// exchanges instead of 16 x 6.  Returns this lane's total of value
+// index 8 b0 + 4 b1 + 2 b2 + b3 (b = bits of the lane id); lanes 0..15 hold
+// all 16 totals.  Fixed combination order: bitwise reproducible.
+__device__ __forceinline__ double wave_reduce_scatter16(double (&s)[16], int lane) {
+  scatter_stage<0, 8>(s, lane);
+  scatter_stage<1, 4>(s, lane);
+  scatter_stage<2, 2>(s, lane);
+  scatter_stage<3, 1>(s, lane);
+  s[0] += xor_lane<4>(s[0]);
+  s[0] += xor_lane<5>(s[0]);
+  return s[0];
+}
+
+__device__ __forceinline__ int scatter16_index(int lane) {
+  return 8 * (lane & 1) + 4 * ((lane >> 1) & 1) + 2 * ((lane >> 2) & 1) + ((lane >> 3) & 1);
+}
+
+// Raw rows in flight ahead of the one relaxed, in the two-step march.
+#ifndef BGK_PF2X2
+#define BGK_PF2X2 1
+#endif
+// Minimum waves per SIMD requested for the two-step kernel (0 = compiler's
+// choice).
+#ifndef BGK_WAVES2X2
+#define BGK_WAVES2X2 0
+#endif
+
+// Recompute |v|^2 and nu per use instead of holding them in registers.
+#ifndef BGK_RECOMPUTE_Q
+#define BGK_RECOMPUTE_Q 0
+#endif
 
 // Per-pair velocity data of one lane.
 template <int P>
 struct PairEls {
   int jofs[P];
   unsigned off[P];
-  double vx[P], vy[P], vz[P], q0[P], q1[P], nu[P];
+  double vx[P], vy[P], vz[P];
+#if !BGK_RECOMPUTE_Q
+  double q0_[P], q1_[P], nu_[P];
+#endif
+  double r, dvz;
   bool ok[P];
+#if BGK_RECOMPUTE_Q
+  __device__ __forceinline__ double q0(int p) const {
+    return fma(vx[p], vx[p], fma(vy[p], vy[p], vz[p] * vz[p]));
+  }
+  __device__ __forceinline__ double q1(int p) const {
+    return fma(dvz, fma(2.0, vz[p], dvz), q0(p));
+  }
+  __device__ __forceinline__ double nu(int p) const { return vx[p] * r; }
+#else
+  __device__ __forceinline__ double q0(int p) const { return q0_[p]; }
+  __device__ __forceinline__ double q1(int p) const { return q1_[p]; }
+  __device__ __forceinline__ double nu(int p) const { return nu_[p]; }
+#endif
 };
 
 template <int P, bool FULL>
@@ -318,56 +371,119 @@ __device__ __forceinline__ void setup_pairs(const Inst& I, int tile, int lane,
     e.vx[p] = vgrid(I, 0, jx);
     e.vy[p] = vgrid(I, 1, jy);
     e.vz[p] = vgrid(I, 2, jz);
+#if !BGK_RECOMPUTE_Q
     const double vxy = e.vx[p] * e.vx[p] + e.vy[p] * e.vy[p];
-    e.q0[p] = vxy + e.vz[p] * e.vz[p];
+    e.q0_[p] = vxy + e.vz[p] * e.vz[p];
     const double vz1 = vgrid(I, 2, jz + 1);
-    e.q1[p] = vxy + vz1 * vz1;
-    e.nu[p] = e.vx[p] * I.r;
+    e.q1_[p] = vxy + vz1 * vz1;
+    e.nu_[p] = e.vx[p] * I.r;
+#endif
   }
+  e.r = I.r;
+  e.dvz = I.dv[2];
 }
 
-// Moments of one transported pair into the NS running sums.
-template <int NS>
-__device__ __forceinline__ void accum_pair(double (&s)[NS], double2 g, double vx,
-                                           double vy, double vz, double dvz,
-                                           double q0, double q1, double nu) {
-  const double gs = g.x + g.y;
-  const double m[5] = {gs, vx * gs, vy * gs, fma(vz, gs, dvz * g.y),
-                       fma(q0, g.x, q1 * g.y)};
-#pragma unroll
-  for (int c = 0; c < 5; ++c) s[c] += m[c];
-  if (NS == 15) {
-    const double cp = nu > 0.0 ? nu : 0.0;
-    const double cm = nu < 0.0 ? -nu : 0.0;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      s[5 + c] = fma(cp, m[c], s[5 + c]);
-      s[10 + c] = fma(cm, m[c], s[10 + c]);
-    }
-  }
+// Readlane of a double from a uniform lane.
+__device__ __forceinline__ double bcast_lane(double v, int lane) {
+  return readlane_d(v, lane);
 }
 
-// Reduce the running sums and store this wave's partial(s) for x cell r.
-template <int NS>
-__device__ __forceinline__ void store_partials(const Inst& I, double (&s)[NS],
-                                               int b, int r, int tile, int lane) {
-  double* cell = I.part + ((long long)b * I.nx + r) * I.part_tiles * 5;
-  if (NS == 5) {
-    row_sum5(*reinterpret_cast<double(*)[5]>(&s[0]));
-    if ((lane & 15) == 15) {
-      double* pp = cell + (tile * 4 + lane / 16) * 5;
+// Sums of NSLOT (4, 8 or 16) values over the 64 lanes by reduce-scatter;
+// returns this lane's total, of value index slot_of_lane<NSLOT>(lane).
+template <int NSLOT>
+__device__ __forceinline__ double wave_reduce_scatter(double (&s)[NSLOT], int lane) {
+  if (NSLOT >= 16) scatter_stage<0, 8>(s, lane);
+  if (NSLOT >= 8) scatter_stage<(NSLOT >= 16 ? 1 : 0), 4>(s, lane);
+  scatter_stage<(NSLOT >= 16 ? 2 : (NSLOT >= 8 ? 1 : 0)), 2>(s, lane);
+  scatter_stage<(NSLOT >= 16 ? 3 : (NSLOT >= 8 ? 2 : 1)), 1>(s, lane);
+  // remaining lane bits: plain sums of the one value each lane holds
+  if (NSLOT <= 8) s[0] += xor_lane<(NSLOT >= 8 ? 3 : 2)>(s[0]);
+  if (NSLOT <= 4) s[0] += xor_lane<3>(s[0]);
+  s[0] += xor_lane<4>(s[0]);
+  s[0] += xor_lane<5>(s[0]);
+  return s[0];
+}
+
+template <int NSLOT>
+__device__ __forceinline__ int slot_of_lane(int lane) {
+  if (NSLOT == 16) return scatter16_index(lane);
+  if (NSLOT == 8) return 4 * (lane & 1) + 2 * ((lane >> 1) & 1) + ((lane >> 2) & 1);
+  return 2 * (lane & 1) + ((lane >> 1) & 1);
+}
+
+// Lane holding slot k after a 4-slot reduce-scatter.
+__device__ __forceinline__ constexpr int lane_of_slot4(int k) {
+  return (k >> 1) | ((k & 1) << 1);
+}
+
+// Running moment sums of one wave over its tile, for one x cell, and their
+// reduction into the partial-sum record of the wave: NS values, the five
+// moment sums (1, v_x, v_y, v_z, |v|^2) and, with NS = 15, the same sums
+// weighted by nu+ = max(nu,0) and nu- = max(-nu,0), nu = v_x dt/dx.
+// UNI: the tile lies in one v_x plane, so v_x and nu are the same for all
+// its velocities: the v_x and nu-weighted sums are multiples of the plain
+// sum and only four sums need a cross-lane reduction.
+template <int NS, bool UNI>
+struct Acc {
+  static constexpr int N = UNI ? 4 : NS;
+  double s[N];
+  __device__ __forceinline__ void zero() {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) pp[c] = s[c];
+    for (int c = 0; c < N; ++c) s[c] = 0.0;
+  }
+  __device__ __forceinline__ void add(double2 g, double vx, double vy, double vz,
+                                      double dvz, double q0, double q1, double nu) {
+    const double gs = g.x + g.y;
+    if (UNI) {
+      s[0] += gs;
+      s[1] = fma(vy, gs, s[1]);
+      s[2] = fma(vz, gs, fma(dvz, g.y, s[2]));
+      s[3] = fma(q0, g.x, fma(q1, g.y, s[3]));
+      return;
     }
-  } else {
-    wave_sums_last<NS>(s);
-    if (lane == kWave - 1) {
-      double* pp = cell + tile * NS;
+    const double m[5] = {gs, vx * gs, vy * gs, fma(vz, gs, dvz * g.y),
+                         fma(q0, g.x, q1 * g.y)};
 #pragma unroll
-      for (int c = 0; c < NS; ++c) pp[c] = s[c];
+    for (int c = 0; c < 5; ++c) s[c] += m[c];
+    if (NS == 15) {
+      const double cp = nu > 0.0 ? nu : 0.0;
+      const double cm = nu < 0.0 ? -nu : 0.0;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        s[5 + c] = fma(cp, m[c], s[5 + c]);
+        s[10 + c] = fma(cm, m[c], s[10 + c]);
+      }
     }
   }
-}
+  // vxu, nuu: the tile's v_x and nu (used when UNI)
+  __device__ __forceinline__ void store(const Inst& I, int b, int r, int tile, int lane,
+                                        double vxu, double nuu) {
+    double* rec = I.part + ((long long)b * I.nx + r) * I.part_tiles * 5 + tile * NS;
+    if (UNI) {
+      double t4[4] = {s[0], s[1], s[2], s[3]};
+      const double tot = wave_reduce_scatter<4>(t4, lane);
+      const double T0 = bcast_lane(tot, lane_of_slot4(0));
+      const double T1 = bcast_lane(tot, lane_of_slot4(1));
+      const double T2 = bcast_lane(tot, lane_of_slot4(2));
+      const double T3 = bcast_lane(tot, lane_of_slot4(3));
+      if (lane < NS) {
+        const int c = lane % 5, w = lane / 5;
+        const double S = c == 0 ? T0 : (c == 1 ? vxu * T0 : (c == 2 ? T1 : (c == 3 ? T2 : T3)));
+        const double wt = w == 0 ? 1.0 : (w == 1 ? (nuu > 0.0 ? nuu : 0.0)
+                                                  : (nuu < 0.0 ? -nuu : 0.0));
+        rec[lane] = wt * S;
+      }
+      return;
+    }
+    constexpr int NSLOT = NS <= 8 ? 8 : 16;
+    double t[NSLOT];
+#pragma unroll
+    for (int c = 0; c < NSLOT; ++c) t[c] = c < NS ? s[c] : 0.0;
+    const double tot = wave_reduce_scatter<NSLOT>(t, lane);
+    const int idx = slot_of_lane<NSLOT>(lane);
+    if (lane < NSLOT && idx < NS) rec[idx] = tot;
+  }
+};
 
 __device__ __forceinline__ void store_pair(double* drow, int jofs, double2 g) {
 #if BGK_NT_STORE
@@ -380,10 +496,11 @@ __device__ __forceinline__ void store_pair(double* drow, int jofs, double2 g) {
 
 // One upwind transport of a pair: centre c, its neighbours behind (march
 // position k-1) and ahead (k+1).  The upwind cell is x-1 for v_x > 0.
-template <int DIR>
+// SGN != 0: the sign of nu is known (uniform over the wave), no select.
+template <int DIR, int SGN>
 __device__ __forceinline__ double2 transport_pair(double nu, double2 behind,
                                                   double2 c, double2 ahead) {
-  const bool take_behind = (nu > 0.0) == (DIR > 0);
+  const bool take_behind = SGN != 0 ? ((SGN > 0) == (DIR > 0)) : ((nu > 0.0) == (DIR > 0));
   const double cn = fabs(nu);
   const double2 nb = take_behind ? behind : ahead;
   double2 g;
@@ -412,14 +529,34 @@ __device__ __forceinline__ double2 relax_pair(const double* fr, unsigned o,
   return v;
 }
 
+// Tile classes of the paired kernels: a full tile inside one v_x plane with
+// nu > 0 or nu < 0 (uniform fast path), a full mixed tile, a ragged tile.
+enum TileCase : int { kTilePos = 0, kTileNeg = 1, kTileMixed = 2, kTileRagged = 3 };
+
+__device__ __forceinline__ int tile_case(const Inst& I, int tile, int P, double* vxu,
+                                         double* nuu) {
+  const int t0 = tile * 128 * P;
+  const int t1 = t0 + 128 * P;  // exclusive
+  const int nyz = I.nvy * I.nvz;
+  const int jx = t0 / nyz;
+  *vxu = vgrid(I, 0, jx);
+  *nuu = *vxu * I.r;
+  if (t1 > I.nv3) return kTileRagged;
+  if ((t1 - 1) / nyz != jx) return kTileMixed;
+  return *nuu > 0.0 ? kTilePos : kTileNeg;
+}
+
 // DIR = +1 marches the chunk's x cells upward, -1 downward.  Neighbouring
 // chunks march in opposite directions, so the two halo rows they share are
 // read by both blocks at nearly the same time (both at their start or both at
 // their end) and the second read hits L2.
-template <int P, int MODE, bool FULL, int DIR, int NS>
+template <int P, int MODE, int CASE, int DIR, int NS>
 __device__ __forceinline__ void step2_march(const Inst& I, const double* lds,
                                             int b, int tile, int lane, int i0,
-                                            int i1, int phase) {
+                                            int i1, int phase, double vxu, double nuu) {
+  constexpr bool FULL = CASE != kTileRagged;
+  constexpr bool UNI = CASE == kTilePos || CASE == kTileNeg;
+  constexpr int SGN = CASE == kTilePos ? 1 : (CASE == kTileNeg ? -1 : 0);
   const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
   PairEls<P> e;
   setup_pairs<P, FULL>(I, tile, lane, e);
@@ -468,17 +605,17 @@ __device__ __forceinline__ void step2_march(const Inst& I, const double* lds,
     if (k + 2 <= len) load_row(row_at(k + 2), r2);  // prefetch
     relax_row(row_at(k + 1), r1, fa);
     const int r = row_at(k);
-    double s[NS];
-#pragma unroll
-    for (int c = 0; c < NS; ++c) s[c] = 0.0;
+    Acc<NS, UNI> acc;
+    acc.zero();
     double* drow = dst + (long long)r * nv3;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const double2 g = transport_pair<DIR>(e.nu[p], fb[p], f0[p], fa[p]);
+      const double nu = UNI ? nuu : e.nu(p);
+      const double2 g = transport_pair<DIR, SGN>(nu, fb[p], f0[p], fa[p]);
       if (FULL || e.ok[p]) store_pair(drow, e.jofs[p], g);
-      accum_pair<NS>(s, g, e.vx[p], e.vy[p], e.vz[p], dvz, e.q0[p], e.q1[p], e.nu[p]);
+      acc.add(g, e.vx[p], e.vy[p], e.vz[p], dvz, e.q0(p), e.q1(p), nu);
     }
-    store_partials<NS>(I, s, b, r, tile, lane);
+    acc.store(I, b, r, tile, lane, vxu, nuu);
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       fb[p] = f0[p];
@@ -498,6 +635,33 @@ __device__ __forceinline__ void stage_rows(const Inst& I, const double* fac, int
     lds[idx] = f[(long long)ghost_row(first_row + rr, nx, I.bc) * nvs + k];
   }
 }
+
+// Dispatch of a march over the tile class and march direction.
+#define BGK_MARCH_DISPATCH(CALL, ...)                                            \
+  do {                                                                           \
+    const int tc_ = tile_case(I, tile, P, &vxu, &nuu);                           \
+    if (c & 1) {                                                                 \
+      if (tc_ == kTilePos) CALL::template run<kTilePos, -1>(__VA_ARGS__);        \
+      else if (tc_ == kTileNeg) CALL::template run<kTileNeg, -1>(__VA_ARGS__);   \
+      else if (tc_ == kTileMixed) CALL::template run<kTileMixed, -1>(__VA_ARGS__); \
+      else CALL::template run<kTileRagged, -1>(__VA_ARGS__);                     \
+    } else {                                                                     \
+      if (tc_ == kTilePos) CALL::template run<kTilePos, 1>(__VA_ARGS__);         \
+      else if (tc_ == kTileNeg) CALL::template run<kTileNeg, 1>(__VA_ARGS__);    \
+      else if (tc_ == kTileMixed) CALL::template run<kTileMixed, 1>(__VA_ARGS__); \
+      else CALL::template run<kTileRagged, 1>(__VA_ARGS__);                      \
+    }                                                                            \
+  } while (0)
+
+template <int P, int MODE, int NS>
+struct Step2Call {
+  template <int CASE, int DIR>
+  static __device__ __forceinline__ void run(const Inst& I, const double* lds, int b,
+                                             int tile, int lane, int i0, int i1,
+                                             int phase, double vxu, double nuu) {
+    step2_march<P, MODE, CASE, DIR, NS>(I, lds, b, tile, lane, i0, i1, phase, vxu, nuu);
+  }
+};
 
 template <int P, int MODE, int NS>
 __global__ __launch_bounds__(kBlock) void k_step2(const Inst* __restrict__ insts,
@@ -522,14 +686,9 @@ __global__ __launch_bounds__(kBlock) void k_step2(const Inst* __restrict__ insts
   const int lane = threadIdx.x % kWave;
   const int tile = tg * kWavesPerBlock + wave;
   if (tile >= I.ntiles) return;
-  const bool full = (tile + 1) * (128 * P) <= I.nv3;
-  if (c & 1) {
-    if (full) step2_march<P, MODE, true, -1, NS>(I, lds, b, tile, lane, i0, i1, phase);
-    else step2_march<P, MODE, false, -1, NS>(I, lds, b, tile, lane, i0, i1, phase);
-  } else {
-    if (full) step2_march<P, MODE, true, 1, NS>(I, lds, b, tile, lane, i0, i1, phase);
-    else step2_march<P, MODE, false, 1, NS>(I, lds, b, tile, lane, i0, i1, phase);
-  }
+  double vxu, nuu;
+  using Call = Step2Call<P, MODE, NS>;
+  BGK_MARCH_DISPATCH(Call, I, lds, b, tile, lane, i0, i1, phase, vxu, nuu);
 }
 
 // ------------------------------------------------ two steps in one pass --
@@ -544,10 +703,14 @@ __global__ __launch_bounds__(kBlock) void k_step2(const Inst* __restrict__ insts
 // The march keeps level-1 rows k..k+2 and level-2 rows k-1..k+1.  Level-2
 // values outside the domain are ghost copies of the boundary cell (Neumann)
 // or the wrapped cell (periodic), exactly as a single step would see them.
-template <int P, int MODE, bool FULL, int DIR>
+template <int P, int MODE, int CASE, int DIR>
 __device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
                                               const double* lds2, int b, int tile,
-                                              int lane, int i0, int i1, int phase) {
+                                              int lane, int i0, int i1, int phase,
+                                              double vxu, double nuu) {
+  constexpr bool FULL = CASE != kTileRagged;
+  constexpr bool UNI = CASE == kTilePos || CASE == kTileNeg;
+  constexpr int SGN = CASE == kTilePos ? 1 : (CASE == kTileNeg ? -1 : 0);
   const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
   PairEls<P> e;
   setup_pairs<P, FULL>(I, tile, lane, e);
@@ -583,7 +746,8 @@ __device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
     const double* fr = lds2 + (r - (i0 - 1)) * nvs;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const double2 g = transport_pair<DIR>(e.nu[p], b1[p], c1[p], a1[p]);
+      const double nu = UNI ? nuu : e.nu(p);
+      const double2 g = transport_pair<DIR, SGN>(nu, b1[p], c1[p], a1[p]);
       double2 v = relax_pair<kRelax>(fr, e.off[p], a, g);
       if (!FULL && !e.ok[p]) v = make_double2(0.0, 0.0);
       out[p] = v;
@@ -592,9 +756,7 @@ __device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
 
   double2 f1b[P], f1c[P], f1a[P];  // level 1 at positions k, k+1, k+2
   double2 f2b[P], f2c[P], f2a[P];  // level 2 at positions k-1, k, k+1
-  double2 rcur[P], rnext[P];       // raw rows k+2 (to relax), k+3 (in flight)
-#pragma unroll
-  for (int p = 0; p < P; ++p) rnext[p] = make_double2(0.0, 0.0);
+  double2 rcur[P];                 // raw row k+2; refilled with k+3 once used
   {
     double2 ra[P], rb[P], l0[P], l1[P];
     load_row(row_at(-2), ra);
@@ -614,35 +776,46 @@ __device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
     }
   }
   for (int k = 0; k < len; ++k) {
-    if (k + 3 <= len + 1) load_row(row_at(k + 3), rnext);  // prefetch
     relax1(row_at(k + 2), rcur, f1a);
+    if (k + 3 <= len + 1) load_row(row_at(k + 3), rcur);  // in flight during the rest
     level2(row_at(k + 1), f1b, f1c, f1a, f2a);
     if (neumann && outside(row_at(k + 1))) {
 #pragma unroll
       for (int p = 0; p < P; ++p) f2a[p] = f2c[p];
     }
     const int r = row_at(k);
-    double s[15];
-#pragma unroll
-    for (int c = 0; c < 15; ++c) s[c] = 0.0;
+    Acc<15, UNI> acc;
+    acc.zero();
     double* drow = dst + (long long)r * nv3;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const double2 g = transport_pair<DIR>(e.nu[p], f2b[p], f2c[p], f2a[p]);
+      const double nu = UNI ? nuu : e.nu(p);
+      const double2 g = transport_pair<DIR, SGN>(nu, f2b[p], f2c[p], f2a[p]);
       if (FULL || e.ok[p]) store_pair(drow, e.jofs[p], g);
-      accum_pair<15>(s, g, e.vx[p], e.vy[p], e.vz[p], dvz, e.q0[p], e.q1[p], e.nu[p]);
+      acc.add(g, e.vx[p], e.vy[p], e.vz[p], dvz, e.q0(p), e.q1(p), nu);
     }
-    store_partials<15>(I, s, b, r, tile, lane);
+    acc.store(I, b, r, tile, lane, vxu, nuu);
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       f1b[p] = f1c[p];
       f1c[p] = f1a[p];
       f2b[p] = f2c[p];
       f2c[p] = f2a[p];
-      rcur[p] = rnext[p];
     }
   }
 }
+
+template <int P, int MODE>
+struct Step2x2Call {
+  template <int CASE, int DIR>
+  static __device__ __forceinline__ void run(const Inst& I, const double* lds1,
+                                             const double* lds2, int b, int tile,
+                                             int lane, int i0, int i1, int phase,
+                                             double vxu, double nuu) {
+    step2x2_march<P, MODE, CASE, DIR>(I, lds1, lds2, b, tile, lane, i0, i1, phase, vxu,
+                                      nuu);
+  }
+};
 
 template <int P, int MODE>
 __global__ __launch_bounds__(kBlock) void k_step2x2(const Inst* __restrict__ insts,
@@ -669,14 +842,9 @@ __global__ __launch_bounds__(kBlock) void k_step2x2(const Inst* __restrict__ ins
   const int lane = threadIdx.x % kWave;
   const int tile = tg * kWavesPerBlock + wave;
   if (tile >= I.ntiles) return;
-  const bool full = (tile + 1) * (128 * P) <= I.nv3;
-  if (c & 1) {
-    if (full) step2x2_march<P, MODE, true, -1>(I, lds1, lds2, b, tile, lane, i0, i1, phase);
-    else step2x2_march<P, MODE, false, -1>(I, lds1, lds2, b, tile, lane, i0, i1, phase);
-  } else {
-    if (full) step2x2_march<P, MODE, true, 1>(I, lds1, lds2, b, tile, lane, i0, i1, phase);
-    else step2x2_march<P, MODE, false, 1>(I, lds1, lds2, b, tile, lane, i0, i1, phase);
-  }
+  double vxu, nuu;
+  using Call = Step2x2Call<P, MODE>;
+  BGK_MARCH_DISPATCH(Call, I, lds1, lds2, b, tile, lane, i0, i1, phase, vxu, nuu);
 }
 
 // -------------------------------------------- partial sums of a field --
