@@ -192,10 +192,10 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic_from_profile(per_launch_alg),
-                "kernel": "k_step (fused relax-then-transport)",
+                "kernel": "k_step2x2 (two relax-then-transport steps per pass over f)",
                 "launches": k_launches, "avg_launch_us": round(k_ms * 1e3 / max(k_launches, 1), 2),
                 "alg_bytes_per_launch": per_launch_alg,
-                "alg_bytes_per_update": 16}
+                "alg_bytes_per_update": round(k_bytes / (updates_per_step * args.steps), 3)}
     line = {"metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,

@@ -100,8 +100,14 @@ Tiles choose_tiles(const bgk_problem& p, int batch) {
   // over short chunks
   Tiles t = (pair && g_fuse2) ? Tiles{8, 16, 1} : Tiles{8, 4, pair};
   auto it = g_tuned.find({p.nx, p.nv[0], p.nv[1], p.nv[2], batch});
+  const long long cells = (long long)batch * p.nx * nv3_of(p);
   if (it != g_tuned.end()) t = it->second;
-  else {
+  else if (pair && g_fuse2 && cells < (1LL << 24)) {
+    // latency-bound sizes (f fits the last-level cache): short velocity
+    // tiles, x chunks as long as the grid keeps about two blocks per CU
+    t = Tiles{2, 16, 1};
+    while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 512) t.chunk /= 2;
+  } else {
     // enough work items to fill 256 CUs several times over
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 4096) t.chunk /= 2;
     if (blocks_for_tiles(p, batch, t) < 2048) t.elems = 4;
@@ -192,7 +198,7 @@ static Layout layout_of(const bgk_problem& p, int op, int batch) {
       break;
     case BGK_OP_PARAREAL:
       L.fine = carve_fine(c, p, batch, 2);
-      L.coarse = c.take((size_t)21 * p.nx * sizeof(double));
+      L.coarse = c.take((size_t)16 * p.nx * sizeof(double));
       L.errs = c.take((size_t)(batch + 1) * sizeof(double));
       L.U0 = c.take(sl * (batch + 1));
       L.U1 = c.take(sl * (batch + 1));

@@ -29,8 +29,28 @@ __device__ __forceinline__ int gh(int i, int nx, int bc) {
   return i;
 }
 
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_get(double v) {
+  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, true);
+  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Maximum over the block of non-negative values (lanes that read outside a
+// DPP row see 0, which is neutral here).  One wave: DPP steps that leave
+// the maximum in lane 63, no LDS and no barrier.  Several waves: one more
+// exchange through LDS between two barriers.
 __device__ double block_max(double v, double* red) {
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  v = fmax(v, dpp_get<0xb1, 0xf>(v));   // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_get<0x4e, 0xf>(v));   // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_get<0x114, 0xf>(v));  // row_shr:4
+  v = fmax(v, dpp_get<0x118, 0xf>(v));  // row_shr:8 -> lane 15 of each row
+  v = fmax(v, dpp_get<0x142, 0xa>(v));  // row_bcast:15 into rows 1, 3
+  v = fmax(v, dpp_get<0x143, 0xc>(v));  // row_bcast:31 into rows 2, 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  v = __hiloint2double(hi, lo);
+  if (blockDim.x == 64) return v;
   const int w = threadIdx.x / 64;
   __syncthreads();
   if (threadIdx.x % 64 == 0) red[w] = v;
@@ -40,19 +60,14 @@ __device__ double block_max(double v, double* red) {
   return m;
 }
 
-// Propagates one state over `span`; scratch holds 16*nx doubles (in LDS
-// when it fits, else an L2-resident global slab).  Returns the substep count
-// (identical in all threads).
-__device__ int euler_propagate(const CoarseGeo& G, const double* Vin,
-                               double* Vout, double span, double* scratch,
-                               double* red, int* status) {
+// Advances the state held in `cur` (5*nx doubles) over `span`, ping-ponging
+// with `nxt`; h (5*nx) and spd (nx) are flux scratch.  Returns the buffer
+// that holds the final state (cur or nxt; identical in all threads) and the
+// substep count.  Ends with a barrier after the last write of the state.
+__device__ double* euler_advance(const CoarseGeo& G, double* cur, double* nxt, double* h,
+                                 double* spd, double span, double* red, int* status,
+                                 int* nsub_out) {
   const int nx = G.nx;
-  double* cur = scratch;
-  double* nxt = scratch + 5 * nx;
-  double* h = scratch + 10 * nx;
-  double* spd = scratch + 15 * nx;
-  for (int k = threadIdx.x; k < 5 * nx; k += blockDim.x) cur[k] = Vin[k];
-  __syncthreads();
   double t = 0.0;
   int nsub = 0;
   while (span - t > 1e-14 * span) {
@@ -76,7 +91,10 @@ __device__ int euler_propagate(const CoarseGeo& G, const double* Vin,
       lmax = fmax(lmax, spd[i]);
     }
     if (bad) *status = 1;
-    const double smax = block_max(bad ? INFINITY : lmax, red);  // includes a barrier
+    // block_max has barriers for several waves; one wave takes a barrier of
+    // its own (cheap) so that the spd/h writes are ordered before the reads
+    const double smax = block_max(bad ? INFINITY : lmax, red);
+    if (blockDim.x == 64) __syncthreads();
     if (!(smax > 0.0) || !isfinite(smax) || nsub >= kMaxSubsteps) {
       *status = 1;
       break;  // uniform: every thread sees the same smax and nsub
@@ -103,7 +121,23 @@ __device__ int euler_propagate(const CoarseGeo& G, const double* Vin,
     t += dt;
     ++nsub;
   }
-  for (int k = threadIdx.x; k < 5 * nx; k += blockDim.x) Vout[k] = cur[k];
+  if (nsub_out) *nsub_out = nsub;
+  return cur;
+}
+
+// Propagates one state over `span`; scratch holds 16*nx doubles (in LDS
+// when it fits, else an L2-resident global slab).  Returns the substep count
+// (identical in all threads).
+__device__ int euler_propagate(const CoarseGeo& G, const double* Vin,
+                               double* Vout, double span, double* scratch,
+                               double* red, int* status) {
+  const int nx = G.nx;
+  for (int k = threadIdx.x; k < 5 * nx; k += blockDim.x) scratch[k] = Vin[k];
+  __syncthreads();
+  int nsub = 0;
+  const double* fin = euler_advance(G, scratch, scratch + 5 * nx, scratch + 10 * nx,
+                                    scratch + 15 * nx, span, red, status, &nsub);
+  for (int k = threadIdx.x; k < 5 * nx; k += blockDim.x) Vout[k] = fin[k];
   __syncthreads();
   return nsub;
 }
@@ -125,7 +159,8 @@ __global__ __launch_bounds__(kCoarseBlock) void k_euler(
   if (nsub_out != nullptr && threadIdx.x == 0) nsub_out[m] = n;
 }
 
-// U[0] = V(W0), U[n] = G(U[n-1]) for n = 1..N; Gc[n] = U[n].
+// U[0] = V(W0), U[n] = G(U[n-1]) for n = 1..N; Gc[n] = U[n].  The state
+// stays in the workgroup's scratch from one slice to the next.
 __global__ __launch_bounds__(kCoarseBlock) void k_parareal_init(
     CoarseGeo G, int n_slices, const double* __restrict__ W0, double* U,
     double* Gc, double span, double* scratch_slab, int* status, int use_lds) {
@@ -133,49 +168,89 @@ __global__ __launch_bounds__(kCoarseBlock) void k_parareal_init(
   double* scratch = coarse_scratch(use_lds, scratch_slab);
   const int nx = G.nx;
   const long long sl = 5LL * nx;
+  double* cur = scratch;
+  double* oth = scratch + 5 * nx;
   for (int i = threadIdx.x; i < nx; i += blockDim.x) {
     const double* w = W0 + 5 * i;
     const double rho = w[0];
     const double usq = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
-    double* v = U + 5 * i;
-    v[0] = rho;
-    v[1] = rho * w[1];
-    v[2] = rho * w[2];
-    v[3] = rho * w[3];
-    v[4] = 0.5 * rho * usq + 1.5 * rho * w[4];
+    double v[5] = {rho, rho * w[1], rho * w[2], rho * w[3], 0.5 * rho * usq + 1.5 * rho * w[4]};
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      U[5 * i + c] = v[c];
+      cur[5 * i + c] = v[c];
+    }
   }
   __syncthreads();
   for (int n = 1; n <= n_slices; ++n) {
-    euler_propagate(G, U + (n - 1) * sl, U + n * sl, span, scratch, red, status);
-    for (int k = threadIdx.x; k < sl; k += blockDim.x) Gc[n * sl + k] = U[n * sl + k];
-    __syncthreads();
+    double* fin = euler_advance(G, cur, oth, scratch + 10 * nx, scratch + 15 * nx, span, red,
+                                status, nullptr);
+    for (long long q = threadIdx.x; q < sl; q += blockDim.x) {
+      U[n * sl + q] = fin[q];
+      Gc[n * sl + q] = fin[q];
+    }
+    oth = (fin == cur) ? oth : cur;
+    cur = fin;
   }
 }
 
 // One correction sweep of iteration k: U_new[n] = U_old[n] for n <= k, then
 // for n = k+1..N in order: g = G(U_new[n-1]); U_new[n] = g + (VF[n] - Gc[n]);
 // Gc[n] = g.  *err = max over n, cells, components of |U_new - U_old|.
+// The state stays in the workgroup's scratch from one slice to the next.
+// R > 0: each thread owns R entries q = tid + r * blockDim of a slice and
+// loads VF, Gc and U_old of slice n before propagating into it, so those
+// reads overlap the propagation (requires R * blockDim >= 5 * nx).
+template <int R>
 __global__ __launch_bounds__(kCoarseBlock) void k_parareal_sweep(
     CoarseGeo G, int n_slices, int k, const double* __restrict__ U_old,
     double* U_new, const double* __restrict__ VF, double* Gc, double span,
     double* scratch_slab, double* err, int* status, int use_lds) {
   __shared__ double red[kCoarseBlock / 64];
   double* scratch = coarse_scratch(use_lds, scratch_slab);
-  const long long sl = 5LL * G.nx;
+  const int nx = G.nx;
+  const long long sl = 5LL * nx;
+  double* cur = scratch;
+  double* oth = scratch + 5 * nx;
   for (long long q = threadIdx.x; q < (k + 1) * sl; q += blockDim.x) U_new[q] = U_old[q];
+  for (long long q = threadIdx.x; q < sl; q += blockDim.x) cur[q] = U_old[k * sl + q];
   __syncthreads();
-  double* g = scratch + 16LL * G.nx;  // after the propagation scratch
   double lerr = 0.0;
   for (int n = k + 1; n <= n_slices; ++n) {
-    euler_propagate(G, U_new + (n - 1) * sl, g, span, scratch, red, status);
-    for (long long q = threadIdx.x; q < sl; q += blockDim.x) {
-      const double jump = VF[n * sl + q] - Gc[n * sl + q];
-      const double un = g[q] + jump;
-      U_new[n * sl + q] = un;
-      Gc[n * sl + q] = g[q];
-      lerr = fmax(lerr, fabs(un - U_old[n * sl + q]));
+    const long long base = n * sl;
+    double vf[R > 0 ? R : 1], gc[R > 0 ? R : 1], uo[R > 0 ? R : 1];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const long long q = threadIdx.x + (long long)r * blockDim.x;
+      if (q < sl) {
+        vf[r] = VF[base + q];
+        gc[r] = Gc[base + q];
+        uo[r] = U_old[base + q];
+      }
+    }
+    double* fin = euler_advance(G, cur, oth, scratch + 10 * nx, scratch + 15 * nx, span, red,
+                                status, nullptr);
+    auto update = [&](long long q, double v, double c, double o) {
+      const double g = fin[q];
+      const double un = g + (v - c);
+      U_new[base + q] = un;
+      Gc[base + q] = g;
+      lerr = fmax(lerr, fabs(un - o));
+      fin[q] = un;  // the next slice starts from U_new[n]
+    };
+    if (R > 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const long long q = threadIdx.x + (long long)r * blockDim.x;
+        if (q < sl) update(q, vf[r], gc[r], uo[r]);
+      }
+    } else {
+      for (long long q = threadIdx.x; q < sl; q += blockDim.x)
+        update(q, VF[base + q], Gc[base + q], U_old[base + q]);
     }
     __syncthreads();
+    oth = (fin == cur) ? oth : cur;
+    cur = fin;
   }
   const double e = block_max(lerr, red);
   if (threadIdx.x == 0) *err = e;
@@ -230,10 +305,22 @@ int launch_parareal_sweep(const bgk_problem& p, int n_slices, int k,
                           const double* U_old, double* U_new, const double* VF,
                           double* Gc, double t_span, double* scratch,
                           double* d_err, int* d_status, hipStream_t s) {
-  const size_t lds = coarse_lds(21 * (size_t)p.nx);
-  hipLaunchKernelGGL(k_parareal_sweep, dim3(1), dim3(coarse_threads(p.nx)), lds, s,
-                     geo_of(p), n_slices, k, U_old, U_new, VF, Gc, t_span,
-                     scratch, d_err, d_status, lds ? 1 : 0);
+  const size_t lds = coarse_lds(16 * (size_t)p.nx);
+  const int threads = coarse_threads(p.nx);
+  const long long per = (5LL * p.nx + threads - 1) / threads;  // entries per thread
+  if (per <= 5) {
+    hipLaunchKernelGGL(k_parareal_sweep<5>, dim3(1), dim3(threads), lds, s, geo_of(p),
+                       n_slices, k, U_old, U_new, VF, Gc, t_span, scratch, d_err, d_status,
+                       lds ? 1 : 0);
+  } else if (per <= 10) {
+    hipLaunchKernelGGL(k_parareal_sweep<10>, dim3(1), dim3(threads), lds, s, geo_of(p),
+                       n_slices, k, U_old, U_new, VF, Gc, t_span, scratch, d_err, d_status,
+                       lds ? 1 : 0);
+  } else {
+    hipLaunchKernelGGL(k_parareal_sweep<0>, dim3(1), dim3(threads), lds, s, geo_of(p),
+                       n_slices, k, U_old, U_new, VF, Gc, t_span, scratch, d_err, d_status,
+                       lds ? 1 : 0);
+  }
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }

@@ -989,11 +989,13 @@ __device__ __forceinline__ void cons_to_prim(const double* V, double& rho, doubl
   th = (2.0 * V[4] / rho - usq) / 3.0;
 }
 
-// One wave per (instance, member, x cell).
+// One wave per (instance, member, x cell).  The mode is a template argument
+// so that the independent wave reductions are unrolled and interleaved.
+template <int mode>
 __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ insts,
                                                    int n_inst,
                                                    long long total_cells,
-                                                   int mode, int* status) {
+                                                   int* status) {
   const long long cell = (long long)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (cell >= total_cells) return;
   const int lane = threadIdx.x % kWave;
@@ -1035,7 +1037,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
       for (int c = 5; c < 15; ++c) s[c] += pp[t * ns + c];
     }
   }
-  const int nred = (mode == kRedW1) ? 15 : 5;
+  constexpr int nred = (mode == kRedW1) ? 15 : 5;
+#pragma unroll
   for (int c = 0; c < nred; ++c) s[c] = wave_sum_all(s[c]);
   // conserved units: rho, m from sums times dv3; E = sum |v|^2 g dv3 / 2
 #pragma unroll
@@ -1281,8 +1284,23 @@ int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
   (void)phase;
   if (total_cells <= 0) return BGK_OK;
   dim3 grid((unsigned)((total_cells + kWavesPerBlock - 1) / kWavesPerBlock));
-  hipLaunchKernelGGL(k_reduce, grid, dim3(kBlock), 0, s, d_insts, n_inst,
-                     total_cells, mode, d_status);
+  switch (mode) {
+#define BGK_REDUCE_CASE(M)                                                       \
+  case M:                                                                       \
+    hipLaunchKernelGGL(k_reduce<M>, grid, dim3(kBlock), 0, s, d_insts, n_inst, \
+                       total_cells, d_status);                                  \
+    break;
+    BGK_REDUCE_CASE(kRedRelaxFactors)
+    BGK_REDUCE_CASE(kRedProject)
+    BGK_REDUCE_CASE(kRedMomentsOnly)
+    BGK_REDUCE_CASE(kRedMaxwellFactors)
+    BGK_REDUCE_CASE(kRedW1)
+    BGK_REDUCE_CASE(kRedW2)
+#undef BGK_REDUCE_CASE
+    default:
+      set_error("unknown reduction mode");
+      return BGK_E_INVALID;
+  }
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }
