@@ -96,9 +96,9 @@ Tiles choose_tiles(const bgk_problem& p, int batch) {
   std::lock_guard<std::mutex> lk(g_mu);
   const int pair = p.nv[2] % 2 == 0 ? 1 : 0;
   // measured best on the 512 x 32^3 x 64-slice batch with 8-wave blocks:
-  // fused passes 8 velocities per lane over 16-cell chunks, single steps 8
+  // fused passes 8 velocities per lane over 8-cell chunks, single steps 8
   // over short chunks
-  Tiles t = (pair && g_fuse2) ? Tiles{8, 16, 1} : Tiles{8, 4, pair};
+  Tiles t = (pair && g_fuse2) ? Tiles{8, 8, 1} : Tiles{8, 4, pair};
   auto it = g_tuned.find({p.nx, p.nv[0], p.nv[1], p.nv[2], batch});
   const long long cells = (long long)batch * p.nx * nv3_of(p);
   if (it != g_tuned.end()) t = it->second;

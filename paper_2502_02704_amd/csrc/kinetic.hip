@@ -89,6 +89,28 @@ __device__ __forceinline__ int find_inst(const Inst* insts, int n_inst,
   return q;
 }
 
+// Work item -> (member b, tile group tg, x chunk c).  BGK_TG_FASTEST: tile
+// groups fastest, so the blocks that run together on one XCD cover whole
+// rows of a few x chunks (a compact address window; shared halo rows stay
+// in that XCD's L2); else x chunks fastest.
+#ifndef BGK_TG_FASTEST
+#define BGK_TG_FASTEST 1
+#endif
+__device__ __forceinline__ void decode_item(const Inst& I, long long local, int& b, int& tg,
+                                            int& c) {
+#if BGK_TG_FASTEST
+  tg = (int)(local % I.ntg);
+  const long long t = local / I.ntg;
+  c = (int)(t % I.nchunks);
+  b = (int)(t / I.nchunks);
+#else
+  c = (int)(local % I.nchunks);
+  const long long t = local / I.nchunks;
+  tg = (int)(t % I.ntg);
+  b = (int)(t / I.ntg);
+#endif
+}
+
 __device__ __forceinline__ double vgrid(const Inst& I, int a, int j) {
   return I.vlo[a] + (j + 0.5) * I.dv[a];
 }
@@ -138,10 +160,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
   const int q = find_inst(insts, n_inst, item);
   const Inst& I = insts[q];
   const long long local = item - I.item_begin;
-  const int c = (int)(local % I.nchunks);
-  const long long t = local / I.nchunks;
-  const int tg = (int)(t % I.ntg);
-  const int b = (int)(t / I.ntg);
+  int b, tg, c;
+  decode_item(I, local, b, tg, c);
   const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
   const int i0 = c * chunk;
   const int i1 = min(i0 + chunk, nx);
@@ -672,10 +692,8 @@ __global__ __launch_bounds__(kBlock) void k_step2(const Inst* __restrict__ insts
   const int q = find_inst(insts, n_inst, item);
   const Inst& I = insts[q];
   const long long local = item - I.item_begin;
-  const int c = (int)(local % I.nchunks);
-  const long long t = local / I.nchunks;
-  const int tg = (int)(t % I.ntg);
-  const int b = (int)(t / I.ntg);
+  int b, tg, c;
+  decode_item(I, local, b, tg, c);
   const int i0 = c * chunk;
   const int i1 = min(i0 + chunk, I.nx);
   if (MODE != kCopy) {
@@ -826,10 +844,8 @@ __global__ __launch_bounds__(kBlock) void k_step2x2(const Inst* __restrict__ ins
   const int q = find_inst(insts, n_inst, item);
   const Inst& I = insts[q];
   const long long local = item - I.item_begin;
-  const int c = (int)(local % I.nchunks);
-  const long long t = local / I.nchunks;
-  const int tg = (int)(t % I.ntg);
-  const int b = (int)(t / I.ntg);
+  int b, tg, c;
+  decode_item(I, local, b, tg, c);
   const int i0 = c * chunk;
   const int i1 = min(i0 + chunk, I.nx);
   const int len = i1 - i0;
@@ -856,10 +872,8 @@ __global__ __launch_bounds__(kBlock) void k_partials(
   const int q = find_inst(insts, n_inst, item);
   const Inst& I = insts[q];
   const long long local = item - I.item_begin;
-  const int c = (int)(local % I.nchunks);
-  const long long t = local / I.nchunks;
-  const int tg = (int)(t % I.ntg);
-  const int b = (int)(t / I.ntg);
+  int b, tg, c;
+  decode_item(I, local, b, tg, c);
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   const int tile = tg * kWavesPerBlock + wave;
