@@ -226,15 +226,28 @@ int bgk_set_step_fusion(int32_t steps_per_pass);
  * (default).  Kernel timing (bgk_prof_enable) always launches directly. */
 int bgk_set_graphs(int32_t on);
 
-/* Kernel timing of the fused step kernel: when on, every launch of it is
- * bracketed by HIP events on its stream.  bgk_prof_read synchronises and
- * returns the summed milliseconds, the launch count, the phase-space cells
- * updated and the algorithmic bytes moved (16 per cell for a step that reads
- * and writes f, 8 for the first step of a slice, which computes the lifted
- * Maxwellian instead of reading), all since the last bgk_prof_enable(1).
- * [host] outputs, each nullable. */
+/* Kernel timing of the step kernels: when on, every launch of one is
+ * bracketed by HIP events on its stream and tagged with its kind:
+ *   BGK_PROF_TWO_STEP       two IMEX steps per pass, reading and writing f
+ *                           (16 algorithmic bytes per cell per pass)
+ *   BGK_PROF_TWO_STEP_LIFT  two steps from the lifted Maxwellian (writes f
+ *                           only: 8 bytes per cell per pass)
+ *   BGK_PROF_ONE_STEP       one step per pass (16 bytes per cell; 8 for the
+ *                           first step of a slice, which computes the lifted
+ *                           Maxwellian instead of reading it)
+ * bgk_prof_read synchronises and returns, over the launches of `kind`
+ * (BGK_PROF_ALL: every kind) since the last bgk_prof_enable(1), the summed
+ * milliseconds, the launch count, the phase-space updates (cells times steps)
+ * and the algorithmic bytes moved.  [host] outputs, each nullable.
+ * BGK_E_INVALID for an unknown kind. */
+enum {
+  BGK_PROF_ALL = 0,
+  BGK_PROF_TWO_STEP = 1,
+  BGK_PROF_TWO_STEP_LIFT = 2,
+  BGK_PROF_ONE_STEP = 3
+};
 int bgk_prof_enable(int32_t on);
-int bgk_prof_read(double* total_ms, int64_t* launches, double* cells,
+int bgk_prof_read(int32_t kind, double* total_ms, int64_t* launches, double* updates,
                   double* bytes);
 
 #ifdef __cplusplus

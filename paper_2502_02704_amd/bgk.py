@@ -86,7 +86,7 @@ def load_library(path: str = LIB_PATH):
         "bgk_prof_enable": (C.c_int, [C.c_int32]),
         "bgk_set_graphs": (C.c_int, [C.c_int32]),
         "bgk_set_step_fusion": (C.c_int, [C.c_int32]),
-        "bgk_prof_read": (C.c_int, [D, C.POINTER(C.c_int64), D, D]),
+        "bgk_prof_read": (C.c_int, [C.c_int32, D, C.POINTER(C.c_int64), D, D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -370,11 +370,14 @@ def prof_enable(on: bool = True):
     _check(load_library().bgk_prof_enable(1 if on else 0), "bgk_prof_enable")
 
 
-def prof_read():
-    """(kernel milliseconds, launches, cells, algorithmic bytes) of the fused
-    step kernel since prof_enable(True)."""
+PROF_ALL, PROF_TWO_STEP, PROF_TWO_STEP_LIFT, PROF_ONE_STEP = 0, 1, 2, 3
+
+
+def prof_read(kind: int = PROF_ALL):
+    """(kernel milliseconds, launches, phase-space updates, algorithmic bytes)
+    of the step-kernel launches of `kind` since prof_enable(True)."""
     ms, n, cells, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
-    _check(load_library().bgk_prof_read(C.byref(ms), C.byref(n), C.byref(cells),
+    _check(load_library().bgk_prof_read(kind, C.byref(ms), C.byref(n), C.byref(cells),
                                         C.byref(by)), "bgk_prof_read")
     return ms.value, n.value, cells.value, by.value
 

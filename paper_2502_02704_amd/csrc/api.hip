@@ -369,7 +369,7 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
     prof_before(s);
     int r = launch_step(d_I, 1, h.items, mode, phase, t, lds_doubles(h, t), d_status, s,
                         h.nsum);
-    prof_after(s, upd, mode == kLift ? 8.0 : 16.0);
+    prof_after(s, upd, mode == kLift ? 8.0 : 16.0, BGK_PROF_ONE_STEP);
     phase ^= 1;
     return r;
   };
@@ -385,8 +385,10 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
   int done = 0;
   auto pair_pass = [&](int mode) -> int {
     prof_before(s);
-    int r = launch_step2x2(d_I, 1, h.items, mode, phase, t, lds_doubles2(h, t), s);
-    prof_after(s, 2.0 * upd, mode == kLift ? 4.0 : 8.0);
+    const bool uni = (h.nvy * h.nvz) % (kWave * t.elems) == 0;
+    int r = launch_step2x2(d_I, 1, h.items, mode, phase, t, lds_doubles2(h, t), uni, s);
+    prof_after(s, 2.0 * upd, mode == kLift ? 4.0 : 8.0,
+               mode == kLift ? BGK_PROF_TWO_STEP_LIFT : BGK_PROF_TWO_STEP);
     phase ^= 1;
     done += 2;
     return r;
@@ -431,6 +433,7 @@ static long long relax_out_blocks(const Inst& h) {
 struct ProfRec {
   hipEvent_t a, b;
   double cells, bytes;
+  int kind;
 };
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
@@ -456,13 +459,13 @@ void prof_before(hipStream_t s) {
   if (g_prof_pending) (void)hipEventRecord(g_prof_pending, s);
 }
 
-void prof_after(hipStream_t s, double cells, double bytes_per_cell) {
+void prof_after(hipStream_t s, double cells, double bytes_per_cell, int kind) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (!g_prof_on || !g_prof_pending) return;
   hipEvent_t e = prof_event();
   if (!e) return;
   (void)hipEventRecord(e, s);
-  g_prof.push_back({g_prof_pending, e, cells, cells * bytes_per_cell});
+  g_prof.push_back({g_prof_pending, e, cells, cells * bytes_per_cell, kind});
   g_prof_pending = nullptr;
 }
 
@@ -1052,7 +1055,7 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
     prof_before(s);
     rc = launch_step(dI, n_act, items_prefix[n_act], mode, phase, t,
                      (t.chunk + 2) * nvs_max, st, s);
-    prof_after(s, cells, 16.0);
+    prof_after(s, cells, 16.0, BGK_PROF_ONE_STEP);
     if (rc) return rc;
     if ((rc = launch_reduce(dI, n_act, cells_prefix[n_act], kRedRelaxFactors, 0, st, s)))
       return rc;
@@ -1165,19 +1168,24 @@ int bgk_prof_enable(int32_t on) {
   return BGK_OK;
 }
 
-int bgk_prof_read(double* total_ms, int64_t* launches, double* cells, double* bytes) {
+int bgk_prof_read(int32_t kind, double* total_ms, int64_t* launches, double* cells,
+                  double* bytes) {
+  if (kind < BGK_PROF_ALL || kind > BGK_PROF_ONE_STEP) return invalid("unknown timing kind");
   std::lock_guard<std::mutex> lk(g_prof_mu);
   double ms = 0.0, c = 0.0, by = 0.0;
+  int64_t n = 0;
   for (auto& r : g_prof) {
+    if (kind != BGK_PROF_ALL && r.kind != kind) continue;
     BGK_HIP(hipEventSynchronize(r.b));
     float x = 0.f;
     BGK_HIP(hipEventElapsedTime(&x, r.a, r.b));
     ms += x;
     c += r.cells;
     by += r.bytes;
+    ++n;
   }
   if (total_ms) *total_ms = ms;
-  if (launches) *launches = (int64_t)g_prof.size();
+  if (launches) *launches = n;
   if (cells) *cells = c;
   if (bytes) *bytes = by;
   return BGK_OK;

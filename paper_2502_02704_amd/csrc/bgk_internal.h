@@ -126,8 +126,10 @@ int launch_lift_factors(const Inst* d_insts, int n_inst, long long total_cells,
                         const double* W, int* d_status, hipStream_t s,
                         int with_aux = 0);
 // Two IMEX steps per pass (paired lanes): mode kRelax or kLift for the first.
+// uni_only: every tile lies in one v_x plane (nvy*nvz a multiple of 64*elems).
 int launch_step2x2(const Inst* d_insts, int n_inst, long long total_items,
-                   int mode, int phase, Tiles t, int lds_doubles, hipStream_t s);
+                   int mode, int phase, Tiles t, int lds_doubles, bool uni_only,
+                   hipStream_t s);
 // Partial sums of an arbitrary f (source = fin), no transport.
 int launch_partials(const Inst* d_insts, int n_inst, long long total_items,
                     int elems, int chunk, hipStream_t s);
@@ -168,8 +170,8 @@ int launch_lift_adjoint_rho(const Inst* d_inst, const Inst& h_inst,
 
 constexpr int kAdjElems = 4;  // velocity elements per lane in adjoint kernels
 
-// Profiling of the fused step kernel.
+// Timing of the step kernels; kind is one of the BGK_PROF_* tags.
 void prof_before(hipStream_t s);
-void prof_after(hipStream_t s, double cells, double bytes_per_cell);
+void prof_after(hipStream_t s, double cells, double bytes_per_cell, int kind);
 
 }  // namespace bgk

@@ -673,6 +673,21 @@ __device__ __forceinline__ void stage_rows(const Inst& I, const double* fac, int
     }                                                                            \
   } while (0)
 
+// Variant for grids whose v_x planes are whole multiples of a tile (then
+// every tile is uniform in sign): only the two uniform cases are compiled
+// into the kernel, whose register budget is then not set by the mixed case.
+#define BGK_MARCH_DISPATCH_UNI(CALL, ...)                                        \
+  do {                                                                           \
+    const int tc_ = tile_case(I, tile, P, &vxu, &nuu);                           \
+    if (c & 1) {                                                                 \
+      if (tc_ == kTileNeg) CALL::template run<kTileNeg, -1>(__VA_ARGS__);        \
+      else CALL::template run<kTilePos, -1>(__VA_ARGS__);                        \
+    } else {                                                                     \
+      if (tc_ == kTileNeg) CALL::template run<kTileNeg, 1>(__VA_ARGS__);         \
+      else CALL::template run<kTilePos, 1>(__VA_ARGS__);                         \
+    }                                                                            \
+  } while (0)
+
 template <int P, int MODE, int NS>
 struct Step2Call {
   template <int CASE, int DIR>
@@ -835,7 +850,7 @@ struct Step2x2Call {
   }
 };
 
-template <int P, int MODE>
+template <int P, int MODE, bool UNI_ONLY>
 __global__ __launch_bounds__(kBlock) void k_step2x2(const Inst* __restrict__ insts,
                                                     int n_inst, int chunk,
                                                     int phase) {
@@ -860,7 +875,10 @@ __global__ __launch_bounds__(kBlock) void k_step2x2(const Inst* __restrict__ ins
   if (tile >= I.ntiles) return;
   double vxu, nuu;
   using Call = Step2x2Call<P, MODE>;
-  BGK_MARCH_DISPATCH(Call, I, lds1, lds2, b, tile, lane, i0, i1, phase, vxu, nuu);
+  if (UNI_ONLY)
+    BGK_MARCH_DISPATCH_UNI(Call, I, lds1, lds2, b, tile, lane, i0, i1, phase, vxu, nuu);
+  else
+    BGK_MARCH_DISPATCH(Call, I, lds1, lds2, b, tile, lane, i0, i1, phase, vxu, nuu);
 }
 
 // -------------------------------------------- partial sums of a field --
@@ -1255,7 +1273,7 @@ int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode
 }
 
 int launch_step2x2(const Inst* d_insts, int n_inst, long long total_items, int mode,
-                   int phase, Tiles t, int lds_doubles, hipStream_t s) {
+                   int phase, Tiles t, int lds_doubles, bool uni_only, hipStream_t s) {
   if (total_items <= 0) return BGK_OK;
   if (!t.pair) {
     set_error("two-step passes need the paired lane mapping");
@@ -1264,12 +1282,20 @@ int launch_step2x2(const Inst* d_insts, int n_inst, long long total_items, int m
   dim3 grid(blocks_for(total_items)), block(kBlock);
   size_t lds = (size_t)lds_doubles * sizeof(double);
   const int chunk = t.chunk;
-  BGK_STEP_CASE((k_step2x2<1, kRelax>), 2, kRelax)
-  BGK_STEP_CASE((k_step2x2<1, kLift>), 2, kLift)
-  BGK_STEP_CASE((k_step2x2<2, kRelax>), 4, kRelax)
-  BGK_STEP_CASE((k_step2x2<2, kLift>), 4, kLift)
-  BGK_STEP_CASE((k_step2x2<4, kRelax>), 8, kRelax)
-  BGK_STEP_CASE((k_step2x2<4, kLift>), 8, kLift)
+  if (uni_only) {
+    BGK_STEP_CASE((k_step2x2<1, kRelax, true>), 2, kRelax)
+    BGK_STEP_CASE((k_step2x2<1, kLift, true>), 2, kLift)
+    BGK_STEP_CASE((k_step2x2<2, kRelax, true>), 4, kRelax)
+    BGK_STEP_CASE((k_step2x2<2, kLift, true>), 4, kLift)
+    BGK_STEP_CASE((k_step2x2<4, kRelax, true>), 8, kRelax)
+    BGK_STEP_CASE((k_step2x2<4, kLift, true>), 8, kLift)
+  }
+  BGK_STEP_CASE((k_step2x2<1, kRelax, false>), 2, kRelax)
+  BGK_STEP_CASE((k_step2x2<1, kLift, false>), 2, kLift)
+  BGK_STEP_CASE((k_step2x2<2, kRelax, false>), 4, kRelax)
+  BGK_STEP_CASE((k_step2x2<2, kLift, false>), 4, kLift)
+  BGK_STEP_CASE((k_step2x2<4, kRelax, false>), 8, kRelax)
+  BGK_STEP_CASE((k_step2x2<4, kLift, false>), 8, kLift)
 #undef BGK_STEP_CASE
   set_error("unsupported tile shape");
   return BGK_E_INVALID;
