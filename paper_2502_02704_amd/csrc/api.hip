@@ -757,7 +757,8 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
     };
     if ((rc = run_graph(graph_key("pit", ws, ws_bytes, *prob,
                                   {(double)n_slices, span, (double)k, (double)t.elems,
-                                   (double)t.chunk, (double)t.pair, (double)I.nsum}),
+                                   (double)t.chunk, (double)t.pair, (double)I.nsum,
+                                   tol > 0.0 ? 1.0 : 0.0}),
                         s, iteration)))
       return rc;
     cur ^= 1;

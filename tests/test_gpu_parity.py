@@ -431,6 +431,18 @@ def test_graph_replays_match_eager_launches():
         torch.cuda.synchronize()
         S = bgk.serial_fine(p, W0, wk.n_slices, wk.T)
         assert np.array_equal(S.cpu().numpy(), Se)
+    # a tolerance run reads the error the captured sweep leaves for the host;
+    # it must not replay the fixed-K graphs captured above on this workspace
+    bgk.set_graphs(False)
+    try:
+        Vt, errt, kdt = bgk.parareal_iterate(p, W0, wk.n_slices, wk.T, 8, 1e-3)
+        Vt = Vt.cpu().numpy()
+    finally:
+        bgk.set_graphs(True)
+    assert 1 < kdt < 8
+    for rep in range(2):
+        V, err, kd = bgk.parareal_iterate(p, W0, wk.n_slices, wk.T, 8, 1e-3)
+        assert kd == kdt and err == errt and np.array_equal(V.cpu().numpy(), Vt)
 
 
 def test_adjoint_workload_full_size_gradients():
