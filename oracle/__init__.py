@@ -66,6 +66,15 @@ def lib():
             "bgk_oracle_fine_adjoint": [P, D, C.c_int32, C.c_int32, C.c_double, D,
                                         D, D],
             "bgk_oracle_lift_adjoint_rho": [P, D, D, D],
+            "bgk_oracle_n_steps_force": [P, D, C.c_double, I, D],
+            "bgk_oracle_transport_force": [P, D, D, C.c_double, D],
+            "bgk_oracle_fine_steps_force": [P, D, D, D, C.c_double, C.c_int32],
+            "bgk_oracle_fine_step_force": [P, D, D, D, C.c_double, I],
+            "bgk_oracle_fine_propagate_moments_force": [P, D, D, D, C.c_double],
+            "bgk_oracle_euler_coarse_step_force": [P, D, D, D, C.c_double, I],
+            "bgk_oracle_parareal_iterate_force": [P, D, D, C.c_int32, C.c_double,
+                                                  C.c_int32, C.c_double, D, D, I],
+            "bgk_oracle_serial_fine_force": [P, D, D, C.c_int32, C.c_double, D],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -116,11 +125,23 @@ def get_threads() -> int:
     return int(lib().bgk_oracle_get_threads())
 
 
-def n_steps(p, t_span: float):
+def _force(p, E):
+    """Exterior force at the x-cell centres as a contiguous [nx] array."""
+    E = _arr(E)
+    if E.shape != (p.nx,):
+        raise ValueError(f"E must have shape ({p.nx},)")
+    return E
+
+
+def n_steps(p, t_span: float, E=None):
     n = C.c_int32()
     dt = C.c_double()
-    _chk(lib().bgk_oracle_n_steps(C.byref(_prob(p)), t_span, C.byref(n),
-                                  C.byref(dt)), "n_steps")
+    if E is None:
+        rc = lib().bgk_oracle_n_steps(C.byref(_prob(p)), t_span, C.byref(n), C.byref(dt))
+    else:
+        rc = lib().bgk_oracle_n_steps_force(C.byref(_prob(p)), _d(_force(p, E)), t_span,
+                                            C.byref(n), C.byref(dt))
+    _chk(rc, "n_steps")
     return n.value, dt.value
 
 
@@ -140,11 +161,15 @@ def moments(p, f):
     return V, W
 
 
-def transport(p, f, dt: float) -> np.ndarray:
+def transport(p, f, dt: float, E=None) -> np.ndarray:
     f = _arr(f)
     out = np.empty_like(f)
-    _chk(lib().bgk_oracle_transport(C.byref(_prob(p)), _d(f), dt, _d(out)),
-         "transport")
+    if E is None:
+        rc = lib().bgk_oracle_transport(C.byref(_prob(p)), _d(f), dt, _d(out))
+    else:
+        E = _force(p, E)
+        rc = lib().bgk_oracle_transport_force(C.byref(_prob(p)), _d(E), _d(f), dt, _d(out))
+    _chk(rc, "transport")
     return out
 
 
@@ -156,56 +181,90 @@ def relax(p, f_star, dt: float) -> np.ndarray:
     return out
 
 
-def fine_steps(p, f, dt: float, n: int) -> np.ndarray:
+def fine_steps(p, f, dt: float, n: int, E=None) -> np.ndarray:
     f = _arr(f)
     out = np.empty_like(f)
-    _chk(lib().bgk_oracle_fine_steps(C.byref(_prob(p)), _d(f), _d(out), dt, n),
-         "fine_steps")
+    if E is None:
+        rc = lib().bgk_oracle_fine_steps(C.byref(_prob(p)), _d(f), _d(out), dt, n)
+    else:
+        E = _force(p, E)
+        rc = lib().bgk_oracle_fine_steps_force(C.byref(_prob(p)), _d(E), _d(f), _d(out),
+                                               dt, n)
+    _chk(rc, "fine_steps")
     return out
 
 
-def fine_step(p, f, t_span: float):
+def fine_step(p, f, t_span: float, E=None):
     f = _arr(f)
     out = np.empty_like(f)
     n = C.c_int32()
-    _chk(lib().bgk_oracle_fine_step(C.byref(_prob(p)), _d(f), _d(out), t_span,
-                                    C.byref(n)), "fine_step")
+    if E is None:
+        rc = lib().bgk_oracle_fine_step(C.byref(_prob(p)), _d(f), _d(out), t_span,
+                                        C.byref(n))
+    else:
+        E = _force(p, E)
+        rc = lib().bgk_oracle_fine_step_force(C.byref(_prob(p)), _d(E), _d(f), _d(out),
+                                              t_span, C.byref(n))
+    _chk(rc, "fine_step")
     return out, n.value
 
 
-def fine_propagate_moments(p, V, t_span: float) -> np.ndarray:
+def fine_propagate_moments(p, V, t_span: float, E=None) -> np.ndarray:
     V = _arr(V)
     out = np.empty_like(V)
-    _chk(lib().bgk_oracle_fine_propagate_moments(C.byref(_prob(p)), _d(V),
-                                                 _d(out), t_span), "PFL")
+    if E is None:
+        rc = lib().bgk_oracle_fine_propagate_moments(C.byref(_prob(p)), _d(V), _d(out),
+                                                     t_span)
+    else:
+        E = _force(p, E)
+        rc = lib().bgk_oracle_fine_propagate_moments_force(C.byref(_prob(p)), _d(E), _d(V),
+                                                           _d(out), t_span)
+    _chk(rc, "PFL")
     return out
 
 
-def euler_coarse_step(p, V, t_span: float):
+def euler_coarse_step(p, V, t_span: float, E=None):
     V = _arr(V)
     out = np.empty_like(V)
     n = C.c_int32()
-    _chk(lib().bgk_oracle_euler_coarse_step(C.byref(_prob(p)), _d(V), _d(out),
-                                            t_span, C.byref(n)), "euler")
+    if E is None:
+        rc = lib().bgk_oracle_euler_coarse_step(C.byref(_prob(p)), _d(V), _d(out), t_span,
+                                                C.byref(n))
+    else:
+        E = _force(p, E)
+        rc = lib().bgk_oracle_euler_coarse_step_force(C.byref(_prob(p)), _d(E), _d(V),
+                                                      _d(out), t_span, C.byref(n))
+    _chk(rc, "euler")
     return out, n.value
 
 
-def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float):
+def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=None):
     W0 = _arr(W0)
     V = np.empty((n_slices + 1, p.nx, 5))
     err = np.zeros(max(k_max, 1))
     kd = C.c_int32()
-    _chk(lib().bgk_oracle_parareal_iterate(C.byref(_prob(p)), _d(W0), n_slices,
-                                           T, k_max, tol, _d(V), _d(err),
-                                           C.byref(kd)), "parareal")
+    if E is None:
+        rc = lib().bgk_oracle_parareal_iterate(C.byref(_prob(p)), _d(W0), n_slices, T,
+                                               k_max, tol, _d(V), _d(err), C.byref(kd))
+    else:
+        E = _force(p, E)
+        rc = lib().bgk_oracle_parareal_iterate_force(C.byref(_prob(p)), _d(E), _d(W0),
+                                                     n_slices, T, k_max, tol, _d(V),
+                                                     _d(err), C.byref(kd))
+    _chk(rc, "parareal")
     return V, err[:kd.value].copy(), kd.value
 
 
-def serial_fine(p, W0, n_slices: int, T: float) -> np.ndarray:
+def serial_fine(p, W0, n_slices: int, T: float, E=None) -> np.ndarray:
     W0 = _arr(W0)
     V = np.empty((n_slices + 1, p.nx, 5))
-    _chk(lib().bgk_oracle_serial_fine(C.byref(_prob(p)), _d(W0), n_slices, T,
-                                      _d(V)), "serial_fine")
+    if E is None:
+        rc = lib().bgk_oracle_serial_fine(C.byref(_prob(p)), _d(W0), n_slices, T, _d(V))
+    else:
+        E = _force(p, E)
+        rc = lib().bgk_oracle_serial_fine_force(C.byref(_prob(p)), _d(E), _d(W0), n_slices,
+                                                T, _d(V))
+    _chk(rc, "serial_fine")
     return V
 
 

@@ -87,24 +87,46 @@ static int ghost(const bgk_oracle_problem* p, int i) {
 }
 
 /* ---------------------------------------------------------- time steps -- */
-/* Section 2.2: the fine propagator runs at the stability-limited step,
- * dt_stab = cfl * dx / max_j |v_x,j|, and the span is cut into the smallest
- * number of uniform steps not exceeding it. */
-int bgk_oracle_n_steps(const bgk_oracle_problem* p, double t_span,
-                       int32_t* n_steps, double* dt) {
-  if (check_problem(p) || !(t_span > 0.0)) return ORACLE_E_INVALID;
+/* Section 2.2: the fine propagator runs at the stability-limited step and
+ * the span is cut into the smallest number of uniform steps not exceeding
+ * it.  Without force dt_stab = cfl * dx / max_j |v_x,j|; with an exterior
+ * force both explicit fluxes share the step,
+ * dt_stab = cfl / (max_j |v_x,j| / dx + E_max / dv_x). */
+static double emax_of(const bgk_oracle_problem* p, const double* E) {
+  double m = 0.0;
+  if (E)
+    for (int i = 0; i < p->nx; ++i)
+      if (fabs(E[i]) > m) m = fabs(E[i]);
+  return m;
+}
+
+static int n_steps_impl(const bgk_oracle_problem* p, double emax, double t_span,
+                        int32_t* n_steps, double* dt) {
+  if (check_problem(p) || !(t_span > 0.0) || !(emax >= 0.0)) return ORACLE_E_INVALID;
   double vmax = 0.0;
   for (int j = 0; j < p->nv[0]; ++j) {
     double a = fabs(vc(p, 0, j));
     if (a > vmax) vmax = a;
   }
-  double dt_stab = p->cfl * dx_of(p) / vmax;
+  double dt_stab = emax > 0.0 ? p->cfl / (vmax / dx_of(p) + emax / dv_of(p, 0))
+                              : p->cfl * dx_of(p) / vmax;
   double r = t_span / dt_stab;
   int32_t n = (int32_t)ceil(r - 1e-9);
   if (n < 1) n = 1;
   if (n_steps) *n_steps = n;
   if (dt) *dt = t_span / n;
   return ORACLE_OK;
+}
+
+int bgk_oracle_n_steps(const bgk_oracle_problem* p, double t_span,
+                       int32_t* n_steps, double* dt) {
+  return n_steps_impl(p, 0.0, t_span, n_steps, dt);
+}
+
+int bgk_oracle_n_steps_force(const bgk_oracle_problem* p, const double* E,
+                             double t_span, int32_t* n_steps, double* dt) {
+  if (!E) return ORACLE_E_INVALID;
+  return n_steps_impl(p, emax_of(p, E), t_span, n_steps, dt);
 }
 
 /* ------------------------------------------------------------ Maxwellian -- */
@@ -211,12 +233,22 @@ int bgk_oracle_moments(const bgk_oracle_problem* p, const double* f,
 /* ------------------------------------------------------------ transport -- */
 /* Section 3.1: explicit upwind finite volumes in x,
  *   f*_ij = f_ij - dt/dx (F_{i+1/2,j} - F_{i-1/2,j}),
- *   F_{i+1/2,j} = max(v_x,0) f_ij + min(v_x,0) f_{i+1,j}. */
-int bgk_oracle_transport(const bgk_oracle_problem* p, const double* f,
-                         double dt, double* f_star) {
+ *   F_{i+1/2,j} = max(v_x,0) f_ij + min(v_x,0) f_{i+1,j},
+ * and, with an exterior force E_i along x, Rusanov fluxes in v_x,
+ *   f*_ij -= dt/dv_x (G_{i,j+1/2} - G_{i,j-1/2}),
+ *   G_{i,j+1/2} = E_i/2 (f_ij + f_{i,j+1}) - E_max/2 (f_{i,j+1} - f_ij),
+ * j+1 the next v_x point at the same (v_y, v_z), E_max = max_i |E_i|.  The
+ * printed dissipation term differences a value with itself; it is read as
+ * the Rusanov one above.  No flux crosses the ends of the truncated v_x
+ * range, so the scheme conserves mass. */
+static int transport_impl(const bgk_oracle_problem* p, const double* E,
+                          const double* f, double dt, double* f_star) {
   if (check_problem(p) || !f || !f_star || f == f_star) return ORACLE_E_INVALID;
   const long nv3 = nv3_of(p);
+  const int nyz = p->nv[1] * p->nv[2];
   const double r = dt / dx_of(p);
+  const double rv = dt / dv_of(p, 0);
+  const double emax = emax_of(p, E);
 #pragma omp parallel for num_threads(NT)
   for (int i = 0; i < p->nx; ++i) {
     const double* fm = f + (long)ghost(p, i - 1) * nv3;
@@ -227,14 +259,38 @@ int bgk_oracle_transport(const bgk_oracle_problem* p, const double* f,
       double vx = vc(p, 0, jx);
       double vp = vx > 0.0 ? vx : 0.0;
       double vm = vx < 0.0 ? vx : 0.0;
-      for (int jyz = 0; jyz < p->nv[1] * p->nv[2]; ++jyz, ++j) {
+      for (int jyz = 0; jyz < nyz; ++jyz, ++j) {
         double F_right = vp * f0[j] + vm * fp[j];
         double F_left = vp * fm[j] + vm * f0[j];
-        f_star[(long)i * nv3 + j] = f0[j] - r * (F_right - F_left);
+        double out = f0[j] - r * (F_right - F_left);
+        if (E) {
+          double G_up = 0.0, G_down = 0.0;
+          if (jx + 1 < p->nv[0]) {
+            double a = f0[j], b = f0[j + nyz];
+            G_up = 0.5 * E[i] * (a + b) - 0.5 * emax * (b - a);
+          }
+          if (jx > 0) {
+            double a = f0[j - nyz], b = f0[j];
+            G_down = 0.5 * E[i] * (a + b) - 0.5 * emax * (b - a);
+          }
+          out -= rv * (G_up - G_down);
+        }
+        f_star[(long)i * nv3 + j] = out;
       }
     }
   }
   return ORACLE_OK;
+}
+
+int bgk_oracle_transport(const bgk_oracle_problem* p, const double* f,
+                         double dt, double* f_star) {
+  return transport_impl(p, NULL, f, dt, f_star);
+}
+
+int bgk_oracle_transport_force(const bgk_oracle_problem* p, const double* E,
+                               const double* f, double dt, double* f_star) {
+  if (!E) return ORACLE_E_INVALID;
+  return transport_impl(p, E, f, dt, f_star);
 }
 
 /* ---------------------------------------------------------- relaxation -- */
@@ -269,8 +325,9 @@ int bgk_oracle_relax(const bgk_oracle_problem* p, const double* f_star,
 }
 
 /* ---------------------------------------------------- fine propagator -- */
-int bgk_oracle_fine_steps(const bgk_oracle_problem* p, const double* f_in,
-                          double* f_out, double dt, int32_t n_steps) {
+static int fine_steps_impl(const bgk_oracle_problem* p, const double* E,
+                           const double* f_in, double* f_out, double dt,
+                           int32_t n_steps) {
   if (check_problem(p) || !f_in || !f_out || n_steps < 0 || !(dt > 0.0))
     return ORACLE_E_INVALID;
   const size_t n = (size_t)p->nx * nv3_of(p);
@@ -284,7 +341,7 @@ int bgk_oracle_fine_steps(const bgk_oracle_problem* p, const double* f_in,
   memcpy(cur, f_in, n * sizeof(double));
   int rc = ORACLE_OK;
   for (int32_t s = 0; s < n_steps && rc == ORACLE_OK; ++s) {
-    rc = bgk_oracle_transport(p, cur, dt, star);
+    rc = transport_impl(p, E, cur, dt, star);
     if (rc == ORACLE_OK) rc = bgk_oracle_relax(p, star, dt, cur);
   }
   if (rc == ORACLE_OK) memcpy(f_out, cur, n * sizeof(double));
@@ -293,14 +350,39 @@ int bgk_oracle_fine_steps(const bgk_oracle_problem* p, const double* f_in,
   return rc;
 }
 
-int bgk_oracle_fine_step(const bgk_oracle_problem* p, const double* f_in,
-                         double* f_out, double t_span, int32_t* n_steps_out) {
+int bgk_oracle_fine_steps(const bgk_oracle_problem* p, const double* f_in,
+                          double* f_out, double dt, int32_t n_steps) {
+  return fine_steps_impl(p, NULL, f_in, f_out, dt, n_steps);
+}
+
+int bgk_oracle_fine_steps_force(const bgk_oracle_problem* p, const double* E,
+                                const double* f_in, double* f_out, double dt,
+                                int32_t n_steps) {
+  if (!E) return ORACLE_E_INVALID;
+  return fine_steps_impl(p, E, f_in, f_out, dt, n_steps);
+}
+
+static int fine_step_impl(const bgk_oracle_problem* p, const double* E,
+                          const double* f_in, double* f_out, double t_span,
+                          int32_t* n_steps_out) {
   int32_t n;
   double dt;
-  int rc = bgk_oracle_n_steps(p, t_span, &n, &dt);
+  int rc = n_steps_impl(p, emax_of(p, E), t_span, &n, &dt);
   if (rc) return rc;
   if (n_steps_out) *n_steps_out = n;
-  return bgk_oracle_fine_steps(p, f_in, f_out, dt, n);
+  return fine_steps_impl(p, E, f_in, f_out, dt, n);
+}
+
+int bgk_oracle_fine_step(const bgk_oracle_problem* p, const double* f_in,
+                         double* f_out, double t_span, int32_t* n_steps_out) {
+  return fine_step_impl(p, NULL, f_in, f_out, t_span, n_steps_out);
+}
+
+int bgk_oracle_fine_step_force(const bgk_oracle_problem* p, const double* E,
+                               const double* f_in, double* f_out, double t_span,
+                               int32_t* n_steps_out) {
+  if (!E) return ORACLE_E_INVALID;
+  return fine_step_impl(p, E, f_in, f_out, t_span, n_steps_out);
 }
 
 static void conserved_to_primitive(const double* V5, double* W5) {
@@ -315,9 +397,8 @@ static void conserved_to_primitive(const double* V5, double* W5) {
 }
 
 /* Steps 5-7 of Algorithm 2: lifting, kinetic propagation, projection. */
-int bgk_oracle_fine_propagate_moments(const bgk_oracle_problem* p,
-                                      const double* V_in, double* V_out,
-                                      double t_span) {
+static int propagate_impl(const bgk_oracle_problem* p, const double* E,
+                          const double* V_in, double* V_out, double t_span) {
   if (check_problem(p) || !V_in || !V_out) return ORACLE_E_INVALID;
   const size_t n = (size_t)p->nx * nv3_of(p);
   double* W = (double*)malloc(5 * (size_t)p->nx * sizeof(double));
@@ -329,11 +410,24 @@ int bgk_oracle_fine_propagate_moments(const bgk_oracle_problem* p,
   }
   for (int i = 0; i < p->nx; ++i) conserved_to_primitive(V_in + 5 * i, W + 5 * i);
   int rc = bgk_oracle_lift(p, W, f);
-  if (rc == ORACLE_OK) rc = bgk_oracle_fine_step(p, f, f, t_span, NULL);
+  if (rc == ORACLE_OK) rc = fine_step_impl(p, E, f, f, t_span, NULL);
   if (rc == ORACLE_OK) rc = bgk_oracle_moments(p, f, V_out, NULL);
   free(W);
   free(f);
   return rc;
+}
+
+int bgk_oracle_fine_propagate_moments(const bgk_oracle_problem* p,
+                                      const double* V_in, double* V_out,
+                                      double t_span) {
+  return propagate_impl(p, NULL, V_in, V_out, t_span);
+}
+
+int bgk_oracle_fine_propagate_moments_force(const bgk_oracle_problem* p,
+                                            const double* E, const double* V_in,
+                                            double* V_out, double t_span) {
+  if (!E) return ORACLE_E_INVALID;
+  return propagate_impl(p, E, V_in, V_out, t_span);
 }
 
 /* ------------------------------------------------------------ coarse G -- */
@@ -367,9 +461,12 @@ static void euler_flux(const double* V5, double ux, double uy, double uz,
   h[4] = ux * (V5[4] + pr);
 }
 
-int bgk_oracle_euler_coarse_step(const bgk_oracle_problem* p,
-                                 const double* V_in, double* V_out,
-                                 double t_span, int32_t* n_sub_out) {
+/* With an exterior force E_i the Euler system carries the source
+ * S = (0, rho E, 0, 0, rho u_x E) (Section 3.2 allows a source term), added
+ * explicitly in each substep from the substep's initial state. */
+static int euler_impl(const bgk_oracle_problem* p, const double* E,
+                      const double* V_in, double* V_out, double t_span,
+                      int32_t* n_sub_out) {
   if (check_problem(p) || !V_in || !V_out || !(t_span > 0.0))
     return ORACLE_E_INVALID;
   const int nx = p->nx;
@@ -412,6 +509,11 @@ int bgk_oracle_euler_coarse_step(const bgk_oracle_problem* p,
     for (int i = 0; i < nx; ++i)
       for (int c = 0; c < 5; ++c)
         Vn[5 * i + c] = V[5 * i + c] - dt / dx * (H[5 * (i + 1) + c] - H[5 * i + c]);
+    if (E)
+      for (int i = 0; i < nx; ++i) {
+        Vn[5 * i + 1] += dt * V[5 * i + 0] * E[i];
+        Vn[5 * i + 4] += dt * V[5 * i + 1] * E[i];
+      }
     memcpy(V, Vn, 5 * (size_t)nx * sizeof(double));
     t += dt;
     ++nsub;
@@ -427,6 +529,20 @@ int bgk_oracle_euler_coarse_step(const bgk_oracle_problem* p,
   if (n_sub_out) *n_sub_out = nsub;
   free(V); free(Vn); free(H); free(spd); free(hh);
   return rc;
+}
+
+int bgk_oracle_euler_coarse_step(const bgk_oracle_problem* p,
+                                 const double* V_in, double* V_out,
+                                 double t_span, int32_t* n_sub_out) {
+  return euler_impl(p, NULL, V_in, V_out, t_span, n_sub_out);
+}
+
+int bgk_oracle_euler_coarse_step_force(const bgk_oracle_problem* p,
+                                       const double* E, const double* V_in,
+                                       double* V_out, double t_span,
+                                       int32_t* n_sub_out) {
+  if (!E) return ORACLE_E_INVALID;
+  return euler_impl(p, E, V_in, V_out, t_span, n_sub_out);
 }
 
 /* ------------------------------------------------------------ parareal -- */
@@ -448,10 +564,10 @@ static void primitive_to_conserved(const double* W5, double* V5) {
  *     U^{n,k+1} = G(U^{n-1,k+1}) + Delta^n             for n = k+1..N (in order)
  *     err_k = max_{n,i,c} |U^{n,k+1} - U^{n,k}|;  stop at K or err < tol.
  * The jump loop is the parallel one (Section 2.2 and Section 4). */
-int bgk_oracle_parareal_iterate(const bgk_oracle_problem* p, const double* W0,
-                                int32_t n_slices, double T, int32_t k_max,
-                                double tol, double* V_out, double* err_hist,
-                                int32_t* k_done) {
+static int parareal_impl(const bgk_oracle_problem* p, const double* E,
+                         const double* W0, int32_t n_slices, double T,
+                         int32_t k_max, double tol, double* V_out,
+                         double* err_hist, int32_t* k_done) {
   if (check_problem(p) || !W0 || !V_out || n_slices < 1 || k_max < 0 ||
       !(T > 0.0))
     return ORACLE_E_INVALID;
@@ -468,7 +584,7 @@ int bgk_oracle_parareal_iterate(const bgk_oracle_problem* p, const double* W0,
   for (int i = 0; i < nx; ++i) primitive_to_conserved(W0 + 5 * i, U + 5 * i);
   int rc = ORACLE_OK;
   for (int n = 1; n <= n_slices && rc == ORACLE_OK; ++n)
-    rc = bgk_oracle_euler_coarse_step(p, U + sl * (n - 1), U + sl * n, dT, NULL);
+    rc = euler_impl(p, E, U + sl * (n - 1), U + sl * n, dT, NULL);
   int32_t kd = 0;
   for (int k = 0; k < k_max && rc == ORACLE_OK; ++k) {
     /* jumps, independent over n */
@@ -476,8 +592,8 @@ int bgk_oracle_parareal_iterate(const bgk_oracle_problem* p, const double* W0,
     for (int n = k + 1; n <= n_slices; ++n) {
       double* Fv = (double*)malloc(sl * sizeof(double));
       double* Gv = (double*)malloc(sl * sizeof(double));
-      int r1 = bgk_oracle_fine_propagate_moments(p, U + sl * (n - 1), Fv, dT);
-      int r2 = r1 ? r1 : bgk_oracle_euler_coarse_step(p, U + sl * (n - 1), Gv, dT, NULL);
+      int r1 = propagate_impl(p, E, U + sl * (n - 1), Fv, dT);
+      int r2 = r1 ? r1 : euler_impl(p, E, U + sl * (n - 1), Gv, dT, NULL);
       if (r1 || r2) bad = r1 ? r1 : r2;
       else
         for (size_t q = 0; q < sl; ++q) D[sl * n + q] = Fv[q] - Gv[q];
@@ -492,7 +608,7 @@ int bgk_oracle_parareal_iterate(const bgk_oracle_problem* p, const double* W0,
     /* frozen prefix, then the sequential correction */
     memcpy(Un, U, sl * (k + 1) * sizeof(double));
     for (int n = k + 1; n <= n_slices && rc == ORACLE_OK; ++n) {
-      rc = bgk_oracle_euler_coarse_step(p, Un + sl * (n - 1), Un + sl * n, dT, NULL);
+      rc = euler_impl(p, E, Un + sl * (n - 1), Un + sl * n, dT, NULL);
       if (rc == ORACLE_OK)
         for (size_t q = 0; q < sl; ++q) Un[sl * n + q] += D[sl * n + q];
     }
@@ -513,19 +629,45 @@ int bgk_oracle_parareal_iterate(const bgk_oracle_problem* p, const double* W0,
   return rc;
 }
 
+int bgk_oracle_parareal_iterate(const bgk_oracle_problem* p, const double* W0,
+                                int32_t n_slices, double T, int32_t k_max,
+                                double tol, double* V_out, double* err_hist,
+                                int32_t* k_done) {
+  return parareal_impl(p, NULL, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
+}
+
+int bgk_oracle_parareal_iterate_force(const bgk_oracle_problem* p, const double* E,
+                                      const double* W0, int32_t n_slices, double T,
+                                      int32_t k_max, double tol, double* V_out,
+                                      double* err_hist, int32_t* k_done) {
+  if (!E) return ORACLE_E_INVALID;
+  return parareal_impl(p, E, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
+}
+
 /* The fine reference that parareal converges to: U^n = P F L(U^{n-1}). */
-int bgk_oracle_serial_fine(const bgk_oracle_problem* p, const double* W0,
-                           int32_t n_slices, double T, double* V_out) {
+static int serial_impl(const bgk_oracle_problem* p, const double* E,
+                       const double* W0, int32_t n_slices, double T, double* V_out) {
   if (check_problem(p) || !W0 || !V_out || n_slices < 1 || !(T > 0.0))
     return ORACLE_E_INVALID;
   const size_t sl = 5 * (size_t)p->nx;
   for (int i = 0; i < p->nx; ++i) primitive_to_conserved(W0 + 5 * i, V_out + 5 * i);
   for (int n = 1; n <= n_slices; ++n) {
-    int rc = bgk_oracle_fine_propagate_moments(p, V_out + sl * (n - 1),
-                                               V_out + sl * n, T / n_slices);
+    int rc = propagate_impl(p, E, V_out + sl * (n - 1), V_out + sl * n, T / n_slices);
     if (rc) return rc;
   }
   return ORACLE_OK;
+}
+
+int bgk_oracle_serial_fine(const bgk_oracle_problem* p, const double* W0,
+                           int32_t n_slices, double T, double* V_out) {
+  return serial_impl(p, NULL, W0, n_slices, T, V_out);
+}
+
+int bgk_oracle_serial_fine_force(const bgk_oracle_problem* p, const double* E,
+                                 const double* W0, int32_t n_slices, double T,
+                                 double* V_out) {
+  if (!E) return ORACLE_E_INVALID;
+  return serial_impl(p, E, W0, n_slices, T, V_out);
 }
 
 /* --------------------------------------------------------------- adjoint -- */

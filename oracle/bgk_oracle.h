@@ -114,6 +114,37 @@ int bgk_oracle_fine_adjoint(const bgk_oracle_problem* p, const double* f_ckpt,
 int bgk_oracle_lift_adjoint_rho(const bgk_oracle_problem* p, const double* W,
                                 const double* fbar, double* rhobar);
 
+/* Exterior force E_i along x at the cell centres (host [nx]; Section 3.1 with
+ * E != 0): Rusanov fluxes in v_x with E_max = max_i |E_i|, zero flux through
+ * the ends of the v_x range; the shared explicit step satisfies
+ * dt (max|v_x|/dx + E_max/dv_x) <= cfl.  The coarse propagator adds the
+ * source (0, rho E, 0, 0, rho u_x E).  Same contracts as the names without
+ * _force. */
+int bgk_oracle_n_steps_force(const bgk_oracle_problem* p, const double* E,
+                             double t_span, int32_t* n_steps, double* dt);
+int bgk_oracle_transport_force(const bgk_oracle_problem* p, const double* E,
+                               const double* f, double dt, double* f_star);
+int bgk_oracle_fine_steps_force(const bgk_oracle_problem* p, const double* E,
+                                const double* f_in, double* f_out, double dt,
+                                int32_t n_steps);
+int bgk_oracle_fine_step_force(const bgk_oracle_problem* p, const double* E,
+                               const double* f_in, double* f_out, double t_span,
+                               int32_t* n_steps_out);
+int bgk_oracle_fine_propagate_moments_force(const bgk_oracle_problem* p,
+                                            const double* E, const double* V_in,
+                                            double* V_out, double t_span);
+int bgk_oracle_euler_coarse_step_force(const bgk_oracle_problem* p,
+                                       const double* E, const double* V_in,
+                                       double* V_out, double t_span,
+                                       int32_t* n_sub_out);
+int bgk_oracle_parareal_iterate_force(const bgk_oracle_problem* p, const double* E,
+                                      const double* W0, int32_t n_slices, double T,
+                                      int32_t k_max, double tol, double* V_out,
+                                      double* err_hist, int32_t* k_done);
+int bgk_oracle_serial_fine_force(const bgk_oracle_problem* p, const double* E,
+                                 const double* W0, int32_t n_slices, double T,
+                                 double* V_out);
+
 void bgk_oracle_set_threads(int n);
 int bgk_oracle_get_threads(void);
 

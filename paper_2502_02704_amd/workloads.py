@@ -173,6 +173,54 @@ def c5_uneven(n_instances: int = 32, nx_range=(128, 1024),
     return out
 
 
+def exterior_force(x) -> np.ndarray:
+    """The exterior force of the paper's third test, E(x) = -5 x^4 (x-2)^4 (x-1)
+    on [0, 2]: it pushes mass towards x = 1."""
+    x = np.asarray(x, dtype=np.float64)
+    return -5.0 * x ** 4 * (x - 2.0) ** 4 * (x - 1.0)
+
+
+@dataclass
+class ForceWorkload:
+    name: str
+    problem: Problem
+    E: np.ndarray        # force at the x-cell centres
+    W_beams: tuple       # primitive states of the two beams
+    T: float
+    n_slices: int
+
+    def f0(self, lift) -> np.ndarray:
+        """Initial phase-space field: the sum of the two beams' Maxwellians,
+        each lifted with the given lifting routine."""
+        p = self.problem
+        return sum(lift(p, np.tile(np.asarray(w, dtype=np.float64), (p.nx, 1)))
+                   for w in self.W_beams)
+
+    def U0(self) -> np.ndarray:
+        """Primitive moments of f0: the beams have equal densities and
+        opposite x velocities, so rho = 2, u = 0, theta = 1 + 1/3 (continuous
+        moments)."""
+        p = self.problem
+        W = np.zeros((p.nx, 5))
+        W[:, 0] = 2.0
+        W[:, 4] = 4.0 / 3.0
+        return W
+
+
+def c6_two_beam_force(nx: int = 100, nv=(256, 16, 16), eps: float = 1e-5,
+                      n_slices: int = 20, T: float = 0.5) -> ForceWorkload:
+    """Two opposite beams M(1, +e_x, 1) + M(1, -e_x, 1) under the exterior
+    force E(x) = -5 x^4 (x-2)^4 (x-1), x in [0, 2] periodic, velocity box
+    [-8, 8]^3 refined in v_x, eps = 1e-5, T = 0.5."""
+    lo, hi = (-8.0,) * 3, (8.0,) * 3
+    p = Problem(nx=nx, nv=tuple(nv), x_lo=0.0, x_hi=2.0, v_lo=lo, v_hi=hi,
+                bc=BC_PERIODIC, eps=eps)
+    E = exterior_force(p.x_centres())
+    beams = ((1.0, 1.0, 0.0, 0.0, 1.0), (1.0, -1.0, 0.0, 0.0, 1.0))
+    return ForceWorkload(f"two_beam_force_nx{nx}_nv{nv[0]}x{nv[1]}x{nv[2]}", p, E, beams,
+                         T, n_slices)
+
+
 def random_f(prob: Problem, seed: int, lo: float = 0.5, hi: float = 1.5) -> np.ndarray:
     """A strictly positive random phase-space field, for unit tests only."""
     rng = np.random.default_rng(seed)

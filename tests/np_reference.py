@@ -59,6 +59,29 @@ def transport(p, f, dt):
     return f - dt / dx * (flux_r - flux_l)
 
 
+def transport_force(p, f, dt, E):
+    """x transport followed by the v_x Rusanov flux difference of an
+    exterior force E (one value per x cell), no flux through the ends of the
+    v_x range: planes of constant v_x are slices of a [nx, nvx, nvy*nvz] view."""
+    g = transport(p, f, dt)
+    nvx = p.nv[0]
+    F = f.reshape(p.nx, nvx, -1)
+    dvx = (p.v_hi[0] - p.v_lo[0]) / nvx
+    a = np.max(np.abs(E))
+    Ec = np.asarray(E)[:, None, None]
+    faces = np.zeros((p.nx, nvx + 1, F.shape[2]))
+    faces[:, 1:-1] = 0.5 * Ec * (F[:, :-1] + F[:, 1:]) - 0.5 * a * (F[:, 1:] - F[:, :-1])
+    return g - dt / dvx * (faces[:, 1:] - faces[:, :-1]).reshape(p.nx, -1)
+
+
+def step_force(p, f, dt, E):
+    g = transport_force(p, f, dt, E)
+    rho, u, th = prim(p, g)
+    M = maxwell(p, rho, u, th)
+    lam = dt / p.eps
+    return (g + lam * M) / (1 + lam)
+
+
 def step(p, f, dt):
     g = transport(p, f, dt)
     rho, u, th = prim(p, g)
@@ -67,7 +90,7 @@ def step(p, f, dt):
     return (g + lam * M) / (1 + lam)
 
 
-def euler_substep(p, V, dt):
+def euler_substep(p, V, dt, E=None):
     rho = V[:, 0]
     u = V[:, 1:4] / rho[:, None]
     th = (2 * V[:, 4] / rho - (u ** 2).sum(1)) / 3
@@ -84,4 +107,8 @@ def euler_substep(p, V, dt):
     S = np.maximum(s[idxL], s[idxR])[:, None]
     H = 0.5 * (h[idxL] + h[idxR]) - 0.5 * S * (V[idxR] - V[idxL])
     dx = (p.x_hi - p.x_lo) / p.nx
-    return V - dt / dx * (H[1:] - H[:-1]), s.max()
+    out = V - dt / dx * (H[1:] - H[:-1])
+    if E is not None:
+        out[:, 1] += dt * V[:, 0] * E
+        out[:, 4] += dt * V[:, 1] * E
+    return out, s.max()

@@ -576,6 +576,160 @@ class TestBruteForce:
         assert relmax(Wo[:, 4], th) < 1e-14
 
 
+class TestExteriorForce:
+    """Section 3.1 with E != 0: Rusanov fluxes in v_x, no flux through the
+    ends of the truncated v_x range; the coarse Euler system takes the source
+    (0, rho E, 0, 0, rho u_x E)."""
+
+    @staticmethod
+    def _grid(bc=wl.BC_PERIODIC, nv=(9, 3, 2), nx=7, eps=INF):
+        return wl.Problem(nx=nx, nv=nv, v_lo=(-4, -2, -3), v_hi=(5, 2, 3), bc=bc, eps=eps)
+
+    def test_zero_force_is_plain_transport(self):
+        p = self._grid(bc=wl.BC_NEUMANN)
+        f = wl.random_f(p, 3)
+        a = oracle.transport(p, f, 2e-3, E=np.zeros(p.nx))
+        assert np.array_equal(a, oracle.transport(p, f, 2e-3))
+
+    def test_mass_conserved_per_velocity_column(self):
+        # periodic in x and no flux through the v_x ends: sum over x and v_x
+        # of each (v_y, v_z) column is invariant
+        p = self._grid()
+        f = wl.random_f(p, 4)
+        E = np.random.default_rng(5).uniform(-2, 2, p.nx)
+        out = oracle.transport(p, f, 3e-3, E=E)
+        a = f.reshape(p.nx, p.nv[0], -1).sum((0, 1))
+        b = out.reshape(p.nx, p.nv[0], -1).sum((0, 1))
+        assert np.max(np.abs(a - b)) < 1e-15 * np.max(a) * p.nx * p.nv[0]
+
+    @pytest.mark.parametrize("sign", [1.0, -1.0])
+    def test_courant_one_is_exact_velocity_shift(self, sign):
+        # f uniform in x (no x transport), E the same in every cell, so
+        # E_max = |E| and Rusanov is upwind in v_x; at dt |E| / dv_x = 1 every
+        # v_x plane moves one cell in the direction of E, the plane at the
+        # inflow end empties and the plane at the outflow end keeps its mass
+        p = self._grid()
+        rng = np.random.default_rng(6)
+        f = np.tile(rng.uniform(0.5, 1.5, p.nv3), (p.nx, 1))
+        Ev = 1.7 * sign
+        dv = (p.v_hi[0] - p.v_lo[0]) / p.nv[0]
+        out = oracle.transport(p, f, dv / abs(Ev), E=np.full(p.nx, Ev))
+        F = f.reshape(p.nx, p.nv[0], -1)
+        O = out.reshape(p.nx, p.nv[0], -1)
+        if sign > 0:
+            assert np.max(np.abs(O[:, 1:-1] - F[:, :-2])) < 1e-15
+            assert np.max(np.abs(O[:, 0])) < 1e-15
+            assert np.max(np.abs(O[:, -1] - F[:, -1] - F[:, -2])) < 1e-15
+        else:
+            assert np.max(np.abs(O[:, 1:-1] - F[:, 2:])) < 1e-15
+            assert np.max(np.abs(O[:, -1])) < 1e-15
+            assert np.max(np.abs(O[:, 0] - F[:, 0] - F[:, 1])) < 1e-15
+
+    def test_momentum_balance_closed_form(self):
+        # f uniform in x: summing v_x times the flux difference by parts, the
+        # v_x momentum of each (cell, v_y, v_z) column changes by
+        # dt [E (S - (f_0 + f_last)/2) - E_max (f_last - f_0)/2], S the column sum
+        p = self._grid(nv=(11, 2, 3))
+        rng = np.random.default_rng(7)
+        f = np.tile(rng.uniform(0.5, 1.5, p.nv3), (p.nx, 1))
+        E = rng.uniform(-1.5, 1.5, p.nx)
+        dt = 2e-3
+        out = oracle.transport(p, f, dt, E=E)
+        vx = npr.axes(p)[0]
+        F = f.reshape(p.nx, p.nv[0], -1)
+        dmom = ((out.reshape(F.shape) - F) * vx[None, :, None]).sum(1)
+        S = F.sum(1)
+        a = np.max(np.abs(E))
+        want = dt * (E[:, None] * (S - 0.5 * (F[:, 0] + F[:, -1])) -
+                     0.5 * a * (F[:, -1] - F[:, 0]))
+        assert np.max(np.abs(dmom - want)) < 1e-13 * np.max(np.abs(want))
+
+    def test_force_accelerates_resolved_maxwellian(self):
+        # Newton: a resolved Maxwellian far from the ends of the box gains
+        # momentum rho E per unit time (the v_x tails are below 1e-20)
+        p = wl.Problem(nx=4, nv=(96, 2, 2), v_lo=(-12, -3, -3), v_hi=(12, 3, 3),
+                       bc=wl.BC_PERIODIC, eps=INF)
+        W = np.tile([1.3, 0.4, 0.0, 0.0, 0.9], (p.nx, 1))
+        f = oracle.lift(p, W)
+        E = np.array([0.8, -0.5, 0.3, 1.1])
+        dt = 1e-3
+        out = oracle.transport(p, f, dt, E=E)
+        V0, _ = oracle.moments(p, f)
+        V1, _ = oracle.moments(p, out)
+        assert np.max(np.abs(V1[:, 0] - V0[:, 0])) < 1e-13
+        assert np.max(np.abs((V1[:, 1] - V0[:, 1]) / dt - V0[:, 0] * E)) < 1e-10
+
+    def test_step_rule_with_force(self):
+        p = self._grid(nx=10)
+        E = np.linspace(-2.5, 1.0, p.nx)
+        vmax = max(abs(v) for v in npr.axes(p)[0])
+        dx = (p.x_hi - p.x_lo) / p.nx
+        dv = (p.v_hi[0] - p.v_lo[0]) / p.nv[0]
+        stab = p.cfl / (vmax / dx + 2.5 / dv)
+        for span in (0.37 * stab, 3 * stab, 7.5 * stab):
+            n, dt = oracle.n_steps(p, span, E=E)
+            assert n == math.ceil(span / stab - 1e-9) and dt <= stab * (1 + 1e-12)
+            assert abs(n * dt - span) < 1e-15
+
+    @pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_PERIODIC])
+    def test_matches_numpy_steps(self, bc):
+        p = self._grid(bc=bc, eps=4e-3)
+        f = wl.random_f(p, 9)
+        E = np.random.default_rng(10).uniform(-1, 1, p.nx)
+        g = f
+        for _ in range(3):
+            g = npr.step_force(p, g, 1e-3, E)
+        assert relmax(oracle.fine_steps(p, f, 1e-3, 3, E=E), g) < 1e-14
+
+    def test_coarse_source_matches_numpy_substeps(self):
+        p = wl.small_problem(nx=12, bc=wl.BC_PERIODIC)
+        x = p.x_centres()
+        V = np.column_stack([1 + 0.2 * np.sin(2 * np.pi * x), 0.1 * np.cos(2 * np.pi * x),
+                             0 * x, 0 * x, 1.5 + 0.1 * np.sin(2 * np.pi * x)])
+        E = 0.7 * np.cos(2 * np.pi * x)
+        span = 0.03
+        out, n = oracle.euler_coarse_step(p, V, span, E=E)
+        t, Vn, cnt = 0.0, V.copy(), 0
+        while span - t > 1e-14 * span:
+            _, smax = npr.euler_substep(p, Vn, 0.0)
+            dt = min(p.cfl / p.nx / smax, span - t)
+            Vn, _ = npr.euler_substep(p, Vn, dt, E)
+            t += dt
+            cnt += 1
+        assert cnt == n
+        assert np.max(np.abs(out - Vn)) < 1e-14
+
+    def test_coarse_source_momentum_and_power(self):
+        # a uniform state: fluxes cancel, so one substep adds exactly
+        # dt rho E to the momentum and dt m_x E to the energy
+        p = wl.small_problem(nx=6, bc=wl.BC_PERIODIC)
+        V = np.tile([1.2, 0.3, 0.0, 0.0, 1.9], (p.nx, 1))
+        E = np.linspace(-1, 1, p.nx)
+        out, n = oracle.euler_coarse_step(p, V, 1e-4, E=E)
+        assert n == 1
+        assert np.max(np.abs(out[:, 1] - (0.3 + 1e-4 * 1.2 * E))) < 1e-15
+        assert np.max(np.abs(out[:, 4] - (1.9 + 1e-4 * 0.3 * E))) < 1e-15
+        assert np.array_equal(out[:, 0], V[:, 0])
+
+    def test_parareal_k_equals_n_with_force(self):
+        wk = wl.c6_two_beam_force(nx=12, nv=(24, 12, 12), eps=1e-3, n_slices=4, T=0.05)
+        p = wk.problem
+        W0 = wk.U0()
+        ref = oracle.serial_fine(p, W0, 4, wk.T, E=wk.E)
+        V, err, kd = oracle.parareal_iterate(p, W0, 4, wk.T, 4, 0.0, E=wk.E)
+        assert kd == 4
+        assert np.max(np.abs(V - ref)) < 1e-13
+        assert all(err[i + 1] < err[i] for i in range(len(err) - 2))
+
+    def test_force_of_the_exterior_force_test(self):
+        # E(x) = -5 x^4 (x-2)^4 (x-1): zero at 0, 1, 2, odd about x = 1
+        x = np.array([0.0, 1.0, 2.0, 0.3, 1.7, 0.5])
+        E = wl.exterior_force(x)
+        assert E[0] == 0 and E[1] == 0 and E[2] == 0
+        assert abs(E[3] + E[4]) < 1e-15 and E[3] > 0
+        assert abs(E[5] - 5 * 0.5 ** 4 * 1.5 ** 4 * 0.5) < 1e-15
+
+
 class TestErrors:
     def test_invalid_arguments(self):
         from dataclasses import replace
