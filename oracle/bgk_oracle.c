@@ -174,20 +174,41 @@ int bgk_oracle_lift(const bgk_oracle_problem* p, const double* W, double* f) {
  * quadrature, literal two-pass form:
  *   rho = sum f dv,  rho u = sum v f dv,  3 rho theta = sum |v-u|^2 f dv.
  * Conserved energy from the Section 1 relation E = (rho|u|^2 + 3 rho theta)/2. */
+/* Compensated (Neumaier) running sum: the moments below are sums over up to
+ * 10^5 velocities, where a plain running sum loses up to ~1e-13 relative;
+ * the compensation keeps each sum within a few ulps of the exact one, in the
+ * same left-to-right order. */
+typedef struct {
+  double s, c;
+} csum;
+
+static void csum_add(csum* a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x))
+    a->c += (a->s - t) + x;
+  else
+    a->c += (x - t) + a->s;
+  a->s = t;
+}
+
+static double csum_value(const csum* a) { return a->s + a->c; }
+
 static int moments_cell(const bgk_oracle_problem* p, const double* fi,
                         double* V5, double* W5) {
   const double dv3 = dv3_of(p);
-  double rho = 0.0, mom[3] = {0.0, 0.0, 0.0};
+  csum rho_s = {0.0, 0.0}, mom_s[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
   long j = 0;
   for (int jx = 0; jx < p->nv[0]; ++jx)
     for (int jy = 0; jy < p->nv[1]; ++jy)
       for (int jz = 0; jz < p->nv[2]; ++jz, ++j) {
         double v[3] = {vc(p, 0, jx), vc(p, 1, jy), vc(p, 2, jz)};
-        rho += fi[j] * dv3;
-        for (int a = 0; a < 3; ++a) mom[a] += v[a] * fi[j] * dv3;
+        csum_add(&rho_s, fi[j] * dv3);
+        for (int a = 0; a < 3; ++a) csum_add(&mom_s[a], v[a] * fi[j] * dv3);
       }
-  double u[3] = {mom[0] / rho, mom[1] / rho, mom[2] / rho};
-  double s2 = 0.0;
+  double rho = csum_value(&rho_s);
+  double u[3] = {csum_value(&mom_s[0]) / rho, csum_value(&mom_s[1]) / rho,
+                 csum_value(&mom_s[2]) / rho};
+  csum s2_s = {0.0, 0.0};
   j = 0;
   for (int jx = 0; jx < p->nv[0]; ++jx)
     for (int jy = 0; jy < p->nv[1]; ++jy)
@@ -195,8 +216,9 @@ static int moments_cell(const bgk_oracle_problem* p, const double* fi,
         double v[3] = {vc(p, 0, jx), vc(p, 1, jy), vc(p, 2, jz)};
         double d2 = 0.0;
         for (int a = 0; a < 3; ++a) d2 += (v[a] - u[a]) * (v[a] - u[a]);
-        s2 += d2 * fi[j] * dv3;
+        csum_add(&s2_s, d2 * fi[j] * dv3);
       }
+  double s2 = csum_value(&s2_s);
   double theta = s2 / (3.0 * rho);
   if (W5) {
     W5[0] = rho;
