@@ -163,6 +163,50 @@ int bgk_serial_fine(const bgk_problem* prob, const double* W0, int32_t n_slices,
                     double T, double* V_out, void* ws, size_t ws_bytes,
                     void* stream);
 
+/* ------------------------------------------------------ exterior force --
+ * Section 3.1 with E != 0: the step also transports in v_x under an exterior
+ * force E_i per x cell,
+ *   f* -= dt/dv_x (G_{i,j+1/2} - G_{i,j-1/2}),
+ *   G_{i,j+1/2} = E_i/2 (f_ij + f_i,j+1) - e_max/2 (f_i,j+1 - f_ij),
+ * j+1 the next v_x point at the same (v_y, v_z), no flux through the ends of
+ * the v_x range (mass is conserved); the printed dissipation term is read as
+ * this Rusanov one.  The explicit step satisfies
+ * dt (max|v_x|/dx + e_max/dv_x) <= cfl.  The coarse propagator adds the
+ * source (0, rho E, 0, 0, rho u_x E) to the Euler system (Section 3.2).
+ * [device] E [nx] at the x-cell centres, read during the call (and by the
+ * replays of captured sequences: keep it alive and unchanged while a
+ * workspace is reused with it).  e_max: host scalar, the Rusanov coefficient,
+ * which must be >= max_i |E_i| (checked on the device: a violation or a
+ * non-finite E_i makes bgk_status return BGK_E_INVALID).  Steps run one per
+ * pass on the generic lane mapping.  Arguments, workspaces (same BGK_OP_*
+ * sizes) and errors otherwise as the functions without _force. */
+int bgk_n_steps_force(const bgk_problem* prob, double e_max, double t_span,
+                      int32_t* n_steps, double* dt);
+int bgk_fine_steps_force(const bgk_problem* prob, const double* E, double e_max,
+                         const double* f_in, double* f_out, double dt,
+                         int32_t n_steps, void* ws, size_t ws_bytes, void* stream);
+int bgk_fine_step_force(const bgk_problem* prob, const double* E, double e_max,
+                        const double* f_in, double* f_out, double t_span,
+                        int32_t* n_steps_out, void* ws, size_t ws_bytes,
+                        void* stream);
+int bgk_fine_propagate_moments_force(const bgk_problem* prob, const double* E,
+                                     double e_max, int32_t batch,
+                                     const double* V_in, double* V_out,
+                                     double t_span, void* ws, size_t ws_bytes,
+                                     void* stream);
+int euler_coarse_step_force(const bgk_problem* prob, const double* E,
+                            int32_t batch, const double* V_in, double* V_out,
+                            double t_span, int32_t* n_sub_out, void* ws,
+                            size_t ws_bytes, void* stream);
+int parareal_iterate_force(const bgk_problem* prob, const double* E, double e_max,
+                           const double* W0, int32_t n_slices, double T,
+                           int32_t k_max, double tol, double* V_out,
+                           double* err_hist, int32_t* k_done, void* ws,
+                           size_t ws_bytes, void* stream);
+int bgk_serial_fine_force(const bgk_problem* prob, const double* E, double e_max,
+                          const double* W0, int32_t n_slices, double T,
+                          double* V_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Adjoint of n_steps IMEX steps of size dt (the transpose of the step's
  * Jacobian: transposed upwind stencil, adjoint of moments -> Maxwellian ->
  * relaxation).  [device] f_ckpt [ceil(n_steps/ckpt_every)][nx][nv3] forward
@@ -188,8 +232,9 @@ int bgk_lift_adjoint_rho(const bgk_problem* prob, const double* W,
 int bgk_density_adjoint(const bgk_problem* prob, const double* rhobar,
                         double* fbar, void* stream);
 
-/* Synchronises `stream`, returns and clears the sticky device status in ws
- * (BGK_OK or BGK_E_NONPHYSICAL). */
+/* Synchronises `stream`, returns and clears the sticky device status in ws:
+ * BGK_OK, BGK_E_NONPHYSICAL, or BGK_E_INVALID for an exterior force that
+ * exceeds e_max or is not finite. */
 int bgk_status(void* ws, void* stream);
 
 const char* bgk_status_string(int status);

@@ -13,6 +13,7 @@ import math
 import os
 from typing import Dict, List, Sequence, Tuple
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,7 +29,9 @@ EXPORTS = [
     "bgk_serial_fine", "bgk_fine_adjoint", "bgk_lift_adjoint_rho",
     "bgk_density_adjoint", "bgk_status", "bgk_status_string", "bgk_last_error",
     "bgk_set_tiles", "bgk_autotune", "bgk_prof_enable", "bgk_prof_read",
-    "bgk_set_graphs", "bgk_set_step_fusion",
+    "bgk_set_graphs", "bgk_set_step_fusion", "bgk_n_steps_force", "bgk_fine_steps_force",
+    "bgk_fine_step_force", "bgk_fine_propagate_moments_force", "euler_coarse_step_force",
+    "parareal_iterate_force", "bgk_serial_fine_force",
 ]
 
 
@@ -87,6 +90,18 @@ def load_library(path: str = LIB_PATH):
         "bgk_set_graphs": (C.c_int, [C.c_int32]),
         "bgk_set_step_fusion": (C.c_int, [C.c_int32]),
         "bgk_prof_read": (C.c_int, [C.c_int32, D, C.POINTER(C.c_int64), D, D]),
+        "bgk_n_steps_force": (C.c_int, [P, C.c_double, C.c_double, I, D]),
+        "bgk_fine_steps_force": (C.c_int, [P, V, C.c_double, V, V, C.c_double, C.c_int32,
+                                           V, Z, V]),
+        "bgk_fine_step_force": (C.c_int, [P, V, C.c_double, V, V, C.c_double, I, V, Z, V]),
+        "bgk_fine_propagate_moments_force": (C.c_int, [P, V, C.c_double, C.c_int32, V, V,
+                                                       C.c_double, V, Z, V]),
+        "euler_coarse_step_force": (C.c_int, [P, V, C.c_int32, V, V, C.c_double, V, V, Z,
+                                              V]),
+        "parareal_iterate_force": (C.c_int, [P, V, C.c_double, V, C.c_int32, C.c_double,
+                                             C.c_int32, C.c_double, V, D, I, V, Z, V]),
+        "bgk_serial_fine_force": (C.c_int, [P, V, C.c_double, V, C.c_int32, C.c_double, V,
+                                            V, Z, V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -186,10 +201,32 @@ def check_status(ws: torch.Tensor | None = None):
 
 
 # ------------------------------------------------------------ operations --
-def n_steps(p, t_span: float) -> Tuple[int, float]:
+# Functions taking E=None also run the exterior-force variant of the method
+# when E (force at the x centres, [nx], numpy or tensor) is given; its Rusanov
+# coefficient e_max is max |E_i| of those values.
+def _emax(E) -> float:
+    if isinstance(E, torch.Tensor):
+        return float(E.detach().abs().max().item())
+    return float(np.max(np.abs(np.asarray(E, dtype=np.float64))))
+
+
+def _force(p, E):
+    """(device [nx] float64 tensor, e_max) of an exterior force."""
+    Ed = _f64(E)
+    if Ed.shape != (p.nx,):
+        raise ValueError(f"E must have shape ({p.nx},)")
+    return Ed, _emax(E)
+
+
+def n_steps(p, t_span: float, E=None) -> Tuple[int, float]:
     n, dt = C.c_int32(), C.c_double()
-    _check(load_library().bgk_n_steps(C.byref(problem_struct(p)), t_span, C.byref(n),
-                                      C.byref(dt)), "bgk_n_steps")
+    L = load_library()
+    if E is None:
+        rc = L.bgk_n_steps(C.byref(problem_struct(p)), t_span, C.byref(n), C.byref(dt))
+    else:
+        rc = L.bgk_n_steps_force(C.byref(problem_struct(p)), _emax(E), t_span, C.byref(n),
+                                 C.byref(dt))
+    _check(rc, "bgk_n_steps")
     return n.value, dt.value
 
 
@@ -213,23 +250,39 @@ def moments(p, f: torch.Tensor):
     return V, W
 
 
-def fine_steps(p, f: torch.Tensor, dt: float, n: int, out: torch.Tensor | None = None):
+def fine_steps(p, f: torch.Tensor, dt: float, n: int, out: torch.Tensor | None = None,
+               E=None):
     L = _gpu_lib()
     out = torch.empty_like(f) if out is None else out
     w = workspace(p, OP_FINE_STEP)
-    _check(L.bgk_fine_steps(C.byref(problem_struct(p)), _dev(f, "f_in"), _dev(out, "f_out"),
-                            dt, n, w.data_ptr(), w.numel(), _stream()), "bgk_fine_steps")
+    ps = C.byref(problem_struct(p))
+    if E is None:
+        rc = L.bgk_fine_steps(ps, _dev(f, "f_in"), _dev(out, "f_out"), dt, n, w.data_ptr(),
+                              w.numel(), _stream())
+    else:
+        Ed, emax = _force(p, E)
+        rc = L.bgk_fine_steps_force(ps, _dev(Ed, "E"), emax, _dev(f, "f_in"),
+                                    _dev(out, "f_out"), dt, n, w.data_ptr(), w.numel(),
+                                    _stream())
+    _check(rc, "bgk_fine_steps")
     return out
 
 
-def fine_step(p, f: torch.Tensor, t_span: float, out: torch.Tensor | None = None):
+def fine_step(p, f: torch.Tensor, t_span: float, out: torch.Tensor | None = None, E=None):
     L = _gpu_lib()
     out = torch.empty_like(f) if out is None else out
     n = C.c_int32()
     w = workspace(p, OP_FINE_STEP)
-    _check(L.bgk_fine_step(C.byref(problem_struct(p)), _dev(f, "f_in"), _dev(out, "f_out"),
-                           t_span, C.byref(n), w.data_ptr(), w.numel(), _stream()),
-           "bgk_fine_step")
+    ps = C.byref(problem_struct(p))
+    if E is None:
+        rc = L.bgk_fine_step(ps, _dev(f, "f_in"), _dev(out, "f_out"), t_span, C.byref(n),
+                             w.data_ptr(), w.numel(), _stream())
+    else:
+        Ed, emax = _force(p, E)
+        rc = L.bgk_fine_step_force(ps, _dev(Ed, "E"), emax, _dev(f, "f_in"),
+                                   _dev(out, "f_out"), t_span, C.byref(n), w.data_ptr(),
+                                   w.numel(), _stream())
+    _check(rc, "bgk_fine_step")
     return out, n.value
 
 
@@ -261,53 +314,81 @@ def fine_step_batched(probs: Sequence, fs: Sequence[torch.Tensor], spans: Sequen
     return outs, list(steps)
 
 
-def fine_propagate_moments(p, V_in: torch.Tensor, t_span: float) -> torch.Tensor:
+def fine_propagate_moments(p, V_in: torch.Tensor, t_span: float, E=None) -> torch.Tensor:
     """Batched P F L over the leading dimension of V_in ([B][nx][5] conserved)."""
     L = _gpu_lib()
     V_in = V_in.contiguous()
     B = V_in.shape[0] if V_in.dim() == 3 else 1
     out = torch.empty_like(V_in)
     w = workspace(p, OP_PROPAGATE, B)
-    _check(L.bgk_fine_propagate_moments(C.byref(problem_struct(p)), B, _dev(V_in, "V_in"),
-                                        _dev(out, "V_out"), t_span, w.data_ptr(),
-                                        w.numel(), _stream()), "bgk_fine_propagate_moments")
+    ps = C.byref(problem_struct(p))
+    if E is None:
+        rc = L.bgk_fine_propagate_moments(ps, B, _dev(V_in, "V_in"), _dev(out, "V_out"),
+                                          t_span, w.data_ptr(), w.numel(), _stream())
+    else:
+        Ed, emax = _force(p, E)
+        rc = L.bgk_fine_propagate_moments_force(ps, _dev(Ed, "E"), emax, B,
+                                                _dev(V_in, "V_in"), _dev(out, "V_out"),
+                                                t_span, w.data_ptr(), w.numel(), _stream())
+    _check(rc, "bgk_fine_propagate_moments")
     return out
 
 
-def euler_coarse_step(p, V: torch.Tensor, t_span: float):
+def euler_coarse_step(p, V: torch.Tensor, t_span: float, E=None):
     L = _gpu_lib()
     V = V.contiguous()
     B = V.shape[0] if V.dim() == 3 else 1
     out = torch.empty_like(V)
     nsub = torch.zeros(B, dtype=torch.int32, device="cuda")
     w = workspace(p, OP_COARSE, B)
-    _check(L.euler_coarse_step(C.byref(problem_struct(p)), B, _dev(V, "V_in"),
-                               _dev(out, "V_out"), t_span, nsub.data_ptr(), w.data_ptr(),
-                               w.numel(), _stream()), "euler_coarse_step")
+    ps = C.byref(problem_struct(p))
+    if E is None:
+        rc = L.euler_coarse_step(ps, B, _dev(V, "V_in"), _dev(out, "V_out"), t_span,
+                                 nsub.data_ptr(), w.data_ptr(), w.numel(), _stream())
+    else:
+        Ed, _ = _force(p, E)
+        rc = L.euler_coarse_step_force(ps, _dev(Ed, "E"), B, _dev(V, "V_in"),
+                                       _dev(out, "V_out"), t_span, nsub.data_ptr(),
+                                       w.data_ptr(), w.numel(), _stream())
+    _check(rc, "euler_coarse_step")
     return out, nsub
 
 
-def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float):
+def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=None):
     L = _gpu_lib()
     W0 = _f64(W0)
     V = torch.empty((n_slices + 1, p.nx, 5), dtype=torch.float64, device="cuda")
     err = (C.c_double * max(k_max, 1))()
     kd = C.c_int32()
     w = workspace(p, OP_PARAREAL, n_slices)
-    _check(L.parareal_iterate(C.byref(problem_struct(p)), _dev(W0, "W0"), n_slices, T, k_max,
-                              tol, _dev(V, "V_out"), err, C.byref(kd), w.data_ptr(),
-                              w.numel(), _stream()), "parareal_iterate")
+    ps = C.byref(problem_struct(p))
+    if E is None:
+        rc = L.parareal_iterate(ps, _dev(W0, "W0"), n_slices, T, k_max, tol,
+                                _dev(V, "V_out"), err, C.byref(kd), w.data_ptr(), w.numel(),
+                                _stream())
+    else:
+        Ed, emax = _force(p, E)
+        rc = L.parareal_iterate_force(ps, _dev(Ed, "E"), emax, _dev(W0, "W0"), n_slices, T,
+                                      k_max, tol, _dev(V, "V_out"), err, C.byref(kd),
+                                      w.data_ptr(), w.numel(), _stream())
+    _check(rc, "parareal_iterate")
     return V, [err[i] for i in range(kd.value)], kd.value
 
 
-def serial_fine(p, W0, n_slices: int, T: float) -> torch.Tensor:
+def serial_fine(p, W0, n_slices: int, T: float, E=None) -> torch.Tensor:
     L = _gpu_lib()
     W0 = _f64(W0)
     V = torch.empty((n_slices + 1, p.nx, 5), dtype=torch.float64, device="cuda")
     w = workspace(p, OP_PARAREAL, n_slices)
-    _check(L.bgk_serial_fine(C.byref(problem_struct(p)), _dev(W0, "W0"), n_slices, T,
-                             _dev(V, "V_out"), w.data_ptr(), w.numel(), _stream()),
-           "bgk_serial_fine")
+    ps = C.byref(problem_struct(p))
+    if E is None:
+        rc = L.bgk_serial_fine(ps, _dev(W0, "W0"), n_slices, T, _dev(V, "V_out"),
+                               w.data_ptr(), w.numel(), _stream())
+    else:
+        Ed, emax = _force(p, E)
+        rc = L.bgk_serial_fine_force(ps, _dev(Ed, "E"), emax, _dev(W0, "W0"), n_slices, T,
+                                     _dev(V, "V_out"), w.data_ptr(), w.numel(), _stream())
+    _check(rc, "bgk_serial_fine")
     return V
 
 

@@ -58,14 +58,18 @@ int check_problem(const bgk_problem* p) {
   return BGK_OK;
 }
 
-// Section 2.2 local step rule at velocity cell centres.
-int n_steps_for(const bgk_problem& p, double t_span, int32_t* n, double* dt) {
+// Section 2.2 local step rule at velocity cell centres; with an exterior
+// force (emax > 0) the x and v_x fluxes share the explicit step:
+// dt (max|v_x| / dx + emax / dv_x) <= cfl.
+int n_steps_for(const bgk_problem& p, double t_span, int32_t* n, double* dt, double emax) {
   if (!(t_span > 0.0) || !std::isfinite(t_span)) return invalid("t_span must be > 0");
+  if (!(emax >= 0.0) || !std::isfinite(emax)) return invalid("e_max must be finite and >= 0");
   double vmax = 0.0;
   const double dv = dv_of(p, 0);
   for (int j = 0; j < p.nv[0]; ++j)
     vmax = std::max(vmax, std::fabs(p.v_lo[0] + (j + 0.5) * dv));
-  const double dt_stab = p.cfl * dx_of(p) / vmax;
+  const double dt_stab = emax > 0.0 ? p.cfl / (vmax / dx_of(p) + emax / dv)
+                                    : p.cfl * dx_of(p) / vmax;
   const double r = t_span / dt_stab;
   if (!(r < 2.0e9)) return invalid("too many fine steps for t_span");
   int32_t k = (int32_t)std::ceil(r - 1e-9);
@@ -92,9 +96,9 @@ static long long blocks_for_tiles(const bgk_problem& p, int batch, Tiles t) {
 
 static bool g_fuse2 = true;  // two IMEX steps per pass where possible
 
-Tiles choose_tiles(const bgk_problem& p, int batch) {
+Tiles choose_tiles(const bgk_problem& p, int batch, bool generic) {
   std::lock_guard<std::mutex> lk(g_mu);
-  const int pair = p.nv[2] % 2 == 0 ? 1 : 0;
+  const int pair = (p.nv[2] % 2 == 0 && !generic) ? 1 : 0;
   // measured best on the 512 x 32^3 x 64-slice batch with 8-wave blocks:
   // fused passes 8 velocities per lane over 8-cell chunks, single steps 8
   // over short chunks
@@ -115,7 +119,7 @@ Tiles choose_tiles(const bgk_problem& p, int batch) {
   }
   if (g_override.elems) t.elems = g_override.elems;
   if (g_override.chunk) t.chunk = g_override.chunk;
-  if (g_override.pair >= 0 && p.nv[2] % 2 == 0) t.pair = g_override.pair;
+  if (g_override.pair >= 0 && p.nv[2] % 2 == 0 && !generic) t.pair = g_override.pair;
   return t;
 }
 
@@ -368,7 +372,7 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
   auto single = [&](int mode) -> int {
     prof_before(s);
     int r = launch_step(d_I, 1, h.items, mode, phase, t, lds_doubles(h, t), d_status, s,
-                        h.nsum);
+                        h.nsum, h.efield != nullptr);
     prof_after(s, upd, mode == kLift ? 8.0 : 16.0, BGK_PROF_ONE_STEP);
     phase ^= 1;
     return r;
@@ -526,6 +530,56 @@ static int run_graph(const std::string& key, hipStream_t user, F&& enqueue) {
   return BGK_OK;
 }
 
+// ------------------------------------------------------ exterior force --
+// E: device [nx] force at the x centres (null: none); emax: the Rusanov
+// coefficient of the v_x flux, which must bound max |E_i|.
+struct Force {
+  const double* E = nullptr;
+  double emax = 0.0;
+  bool on() const { return E != nullptr; }
+};
+
+constexpr int kStatusBadForce = 2;  // sticky status: |E_i| > emax or not finite
+
+__global__ void k_check_force(const double* __restrict__ E, int n, double emax, int* status) {
+  for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x)
+    if (!(fabs(E[i]) <= emax)) *status = kStatusBadForce;
+}
+
+static int check_force(const bgk_problem& p, const Force& F, int* d_status, hipStream_t s) {
+  if (!F.on()) return BGK_OK;
+  if (!(F.emax >= 0.0) || !std::isfinite(F.emax)) return invalid("e_max must be finite and >= 0");
+  hipLaunchKernelGGL(k_check_force, dim3((p.nx + 255) / 256), dim3(256), 0, s, F.E, p.nx,
+                     F.emax, d_status);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+// Force fields of a descriptor (the v_x flux needs dt / dv_x).
+static void attach_force(Inst& I, const bgk_problem& p, const Force& F, double dt) {
+  I.efield = F.E;
+  I.emax = F.emax;
+  I.rv = dt / dv_of(p, 0);
+}
+
+// Tiles and sums per partial for a fine solve of `n` steps: the force step
+// runs one step per pass on the generic lane mapping.
+static Tiles fine_tiles(const bgk_problem& p, int batch, const Force& F) {
+  return choose_tiles(p, batch, F.on());
+}
+static int fine_nsum(const Tiles& t, int n, const Force& F) {
+  return (!F.on() && fused_for(t, n)) ? 15 : 5;
+}
+
+static int status_code(int st) {
+  if (st == 0) return BGK_OK;
+  if (st == kStatusBadForce) {
+    set_error("exterior force exceeds e_max or is not finite");
+    return BGK_E_INVALID;
+  }
+  return BGK_E_NONPHYSICAL;
+}
+
 }  // namespace bgk
 
 using namespace bgk;
@@ -574,7 +628,7 @@ int bgk_status(void* ws, void* stream) {
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, &at<WsHeader>(ws, 0)->status, 0);
   BGK_HIP(hipGetLastError());
   BGK_HIP(hipStreamSynchronize(s));
-  return st ? BGK_E_NONPHYSICAL : BGK_OK;
+  return status_code(st);
 }
 
 int bgk_lift(const bgk_problem* prob, const double* W, double* f, void* ws,
@@ -618,9 +672,9 @@ int bgk_moments(const bgk_problem* prob, const double* f, double* V, double* W,
   return launch_reduce(dI, 1, prob->nx, kRedMomentsOnly, 0, st, s);
 }
 
-int bgk_fine_steps(const bgk_problem* prob, const double* f_in, double* f_out,
-                   double dt, int32_t n_steps, void* ws, size_t ws_bytes,
-                   void* stream) {
+static int fine_steps_impl(const bgk_problem* prob, const Force& F, const double* f_in,
+                           double* f_out, double dt, int32_t n_steps, void* ws,
+                           size_t ws_bytes, void* stream) {
   int rc = check_problem(prob);
   if (rc) return rc;
   if (!f_in || !f_out) return invalid("NULL array");
@@ -637,34 +691,65 @@ int bgk_fine_steps(const bgk_problem* prob, const double* f_in, double* f_out,
     BGK_HIP(hipMemcpyAsync(f_out, f_in, fbytes, hipMemcpyDeviceToDevice, s));
     return BGK_OK;
   }
-  const Tiles t = aligned_tiles(choose_tiles(*prob, 1), {f_in, f_out});
-  Inst I = make_inst(*prob, 1, dt, t, fused_for(t, n_steps) ? 15 : 5);
+  const Tiles t = aligned_tiles(fine_tiles(*prob, 1, F), {f_in, f_out});
+  Inst I = make_inst(*prob, 1, dt, t, fine_nsum(t, n_steps, F));
   attach_fine(I, ws, L.fine, f_out);  // ping-pong between ws and f_out
+  attach_force(I, *prob, F, dt);
   I.fin = f_in;
   I.fout = f_out;
   Inst* dI = at<Inst>(ws, L.insts);
   int* st = &at<WsHeader>(ws, 0)->status;
+  if ((rc = check_force(*prob, F, st, s))) return rc;
   if ((rc = put_insts(dI, &I, 1, s))) return rc;
   int last = 0;
   if ((rc = run_steps(dI, I, n_steps, kCopy, false, t, st, s, &last))) return rc;
   return launch_relax_out_blocks(dI, 1, relax_out_blocks(I), I.nvs, last, s);
 }
 
-int bgk_fine_step(const bgk_problem* prob, const double* f_in, double* f_out,
-                  double t_span, int32_t* n_steps_out, void* ws, size_t ws_bytes,
-                  void* stream) {
+int bgk_fine_steps(const bgk_problem* prob, const double* f_in, double* f_out,
+                   double dt, int32_t n_steps, void* ws, size_t ws_bytes,
+                   void* stream) {
+  return fine_steps_impl(prob, Force{}, f_in, f_out, dt, n_steps, ws, ws_bytes, stream);
+}
+
+int bgk_fine_steps_force(const bgk_problem* prob, const double* E, double e_max,
+                         const double* f_in, double* f_out, double dt, int32_t n_steps,
+                         void* ws, size_t ws_bytes, void* stream) {
+  if (!E) return invalid("E is NULL");
+  return fine_steps_impl(prob, Force{E, e_max}, f_in, f_out, dt, n_steps, ws, ws_bytes,
+                         stream);
+}
+
+static int fine_step_impl(const bgk_problem* prob, const Force& F, const double* f_in,
+                          double* f_out, double t_span, int32_t* n_steps_out, void* ws,
+                          size_t ws_bytes, void* stream) {
   int rc = check_problem(prob);
   if (rc) return rc;
   int32_t n;
   double dt;
-  if ((rc = n_steps_for(*prob, t_span, &n, &dt))) return rc;
+  if ((rc = n_steps_for(*prob, t_span, &n, &dt, F.emax))) return rc;
   if (n_steps_out) *n_steps_out = n;
-  return bgk_fine_steps(prob, f_in, f_out, dt, n, ws, ws_bytes, stream);
+  return fine_steps_impl(prob, F, f_in, f_out, dt, n, ws, ws_bytes, stream);
 }
 
-int bgk_fine_propagate_moments(const bgk_problem* prob, int32_t batch,
-                               const double* V_in, double* V_out, double t_span,
-                               void* ws, size_t ws_bytes, void* stream) {
+int bgk_fine_step(const bgk_problem* prob, const double* f_in, double* f_out,
+                  double t_span, int32_t* n_steps_out, void* ws, size_t ws_bytes,
+                  void* stream) {
+  return fine_step_impl(prob, Force{}, f_in, f_out, t_span, n_steps_out, ws, ws_bytes,
+                        stream);
+}
+
+int bgk_fine_step_force(const bgk_problem* prob, const double* E, double e_max,
+                        const double* f_in, double* f_out, double t_span,
+                        int32_t* n_steps_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!E) return invalid("E is NULL");
+  return fine_step_impl(prob, Force{E, e_max}, f_in, f_out, t_span, n_steps_out, ws,
+                        ws_bytes, stream);
+}
+
+static int propagate_impl(const bgk_problem* prob, const Force& F, int32_t batch,
+                          const double* V_in, double* V_out, double t_span, void* ws,
+                          size_t ws_bytes, void* stream) {
   int rc = check_problem(prob);
   if (rc) return rc;
   if (batch < 1) return invalid("batch must be >= 1");
@@ -675,25 +760,42 @@ int bgk_fine_propagate_moments(const bgk_problem* prob, int32_t batch,
   if (a0 < b0 + vb && b0 < a0 + vb) return invalid("V_in and V_out overlap");
   int32_t n;
   double dt;
-  if ((rc = n_steps_for(*prob, t_span, &n, &dt))) return rc;
+  if ((rc = n_steps_for(*prob, t_span, &n, &dt, F.emax))) return rc;
   const Layout L = layout_of(*prob, BGK_OP_PROPAGATE, batch);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  const Tiles t = choose_tiles(*prob, batch);
-  Inst I = make_inst(*prob, batch, dt, t, fused_for(t, n) ? 15 : 5);
+  const Tiles t = fine_tiles(*prob, batch, F);
+  Inst I = make_inst(*prob, batch, dt, t, fine_nsum(t, n, F));
   attach_fine(I, ws, L.fine, nullptr);
+  attach_force(I, *prob, F, dt);
   I.vin = V_in;
   I.vout = V_out;
   Inst* dI = at<Inst>(ws, L.insts);
   int* st = &at<WsHeader>(ws, 0)->status;
+  if ((rc = check_force(*prob, F, st, s))) return rc;
   if ((rc = put_insts(dI, &I, 1, s))) return rc;
   int last = 0;
   return lift_and_run(dI, I, n, true, t, st, s, &last);
 }
 
-int euler_coarse_step(const bgk_problem* prob, int32_t batch, const double* V_in,
-                      double* V_out, double t_span, int32_t* n_sub_out, void* ws,
-                      size_t ws_bytes, void* stream) {
+int bgk_fine_propagate_moments(const bgk_problem* prob, int32_t batch,
+                               const double* V_in, double* V_out, double t_span,
+                               void* ws, size_t ws_bytes, void* stream) {
+  return propagate_impl(prob, Force{}, batch, V_in, V_out, t_span, ws, ws_bytes, stream);
+}
+
+int bgk_fine_propagate_moments_force(const bgk_problem* prob, const double* E,
+                                     double e_max, int32_t batch, const double* V_in,
+                                     double* V_out, double t_span, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  if (!E) return invalid("E is NULL");
+  return propagate_impl(prob, Force{E, e_max}, batch, V_in, V_out, t_span, ws, ws_bytes,
+                        stream);
+}
+
+static int euler_impl(const bgk_problem* prob, const double* E, int32_t batch,
+                      const double* V_in, double* V_out, double t_span, int32_t* n_sub_out,
+                      void* ws, size_t ws_bytes, void* stream) {
   int rc = check_problem(prob);
   if (rc) return rc;
   if (batch < 1) return invalid("batch must be >= 1");
@@ -703,13 +805,27 @@ int euler_coarse_step(const bgk_problem* prob, int32_t batch, const double* V_in
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
   return launch_euler(*prob, batch, V_in, V_out, t_span, n_sub_out,
                       at<double>(ws, L.coarse), &at<WsHeader>(ws, 0)->status,
-                      (hipStream_t)stream);
+                      (hipStream_t)stream, E);
 }
 
-int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices,
-                     double T, int32_t k_max, double tol, double* V_out,
-                     double* err_hist, int32_t* k_done, void* ws, size_t ws_bytes,
-                     void* stream) {
+int euler_coarse_step(const bgk_problem* prob, int32_t batch, const double* V_in,
+                      double* V_out, double t_span, int32_t* n_sub_out, void* ws,
+                      size_t ws_bytes, void* stream) {
+  return euler_impl(prob, nullptr, batch, V_in, V_out, t_span, n_sub_out, ws, ws_bytes,
+                    stream);
+}
+
+int euler_coarse_step_force(const bgk_problem* prob, const double* E, int32_t batch,
+                            const double* V_in, double* V_out, double t_span,
+                            int32_t* n_sub_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!E) return invalid("E is NULL");
+  return euler_impl(prob, E, batch, V_in, V_out, t_span, n_sub_out, ws, ws_bytes, stream);
+}
+
+static int parareal_impl(const bgk_problem* prob, const Force& F, const double* W0,
+                         int32_t n_slices, double T, int32_t k_max, double tol,
+                         double* V_out, double* err_hist, int32_t* k_done, void* ws,
+                         size_t ws_bytes, void* stream) {
   int rc = check_problem(prob);
   if (rc) return rc;
   if (!W0 || !V_out) return invalid("NULL array");
@@ -719,7 +835,7 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
   const double span = T / n_slices;
   int32_t n;
   double dt;
-  if ((rc = n_steps_for(*prob, span, &n, &dt))) return rc;
+  if ((rc = n_steps_for(*prob, span, &n, &dt, F.emax))) return rc;
   const Layout L = layout_of(*prob, BGK_OP_PARAREAL, n_slices);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
@@ -733,16 +849,19 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
   double* errs = at<double>(ws, L.errs);  // per-iteration errors (fixed K)
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, st, 0);
   BGK_HIP(hipGetLastError());
-  if ((rc = launch_pararealsweep_init(*prob, n_slices, W0, U[0], Gc, span, scratch, st, s)))
+  if ((rc = check_force(*prob, F, st, s))) return rc;
+  if ((rc = launch_pararealsweep_init(*prob, n_slices, W0, U[0], Gc, span, scratch, st, s,
+                                      F.E)))
     return rc;
   int cur = 0;
   int32_t kd = 0;
   Inst* dI = at<Inst>(ws, L.insts);
   for (int k = 0; k < k_max; ++k) {
     const int B = n_slices - k;
-    const Tiles t = choose_tiles(*prob, B);
-    Inst I = make_inst(*prob, B, dt, t, fused_for(t, n) ? 15 : 5);
+    const Tiles t = fine_tiles(*prob, B, F);
+    Inst I = make_inst(*prob, B, dt, t, fine_nsum(t, n, F));
     attach_fine(I, ws, L.fine, nullptr);
+    attach_force(I, *prob, F, dt);
     I.vin = U[cur] + (size_t)k * sl;        // U^{n-1,k}, n = k+1..N
     I.vout = VF + (size_t)(k + 1) * sl;     // P F L(U^{n-1,k})
     // one iteration: batched lift + fine steps + projection of the active
@@ -753,12 +872,12 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
       int last = 0;
       if ((r = lift_and_run(dI, I, n, true, t, st, q, &last))) return r;
       return launch_parareal_sweep(*prob, n_slices, k, U[cur], U[cur ^ 1], VF, Gc, span,
-                                   scratch, tol > 0.0 ? &hd->err : errs + k, st, q);
+                                   scratch, tol > 0.0 ? &hd->err : errs + k, st, q, F.E);
     };
     if ((rc = run_graph(graph_key("pit", ws, ws_bytes, *prob,
                                   {(double)n_slices, span, (double)k, (double)t.elems,
                                    (double)t.chunk, (double)t.pair, (double)I.nsum,
-                                   tol > 0.0 ? 1.0 : 0.0}),
+                                   tol > 0.0 ? 1.0 : 0.0, (double)(uintptr_t)F.E, F.emax}),
                         s, iteration)))
       return rc;
     cur ^= 1;
@@ -775,7 +894,7 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
     if (h.status) {
       if (k_done) *k_done = kd;
       set_error("non-physical state during parareal iteration");
-      return BGK_E_NONPHYSICAL;
+      return status_code(h.status);
     }
     if (h.err < tol) break;
   }
@@ -788,7 +907,7 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
     if (st_h) {
       if (k_done) *k_done = kd;
       set_error("non-physical state during parareal iteration");
-      return BGK_E_NONPHYSICAL;
+      return status_code(st_h);
     }
   }
   if (k_done) *k_done = kd;
@@ -797,9 +916,26 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
   return BGK_OK;
 }
 
-int bgk_serial_fine(const bgk_problem* prob, const double* W0, int32_t n_slices,
-                    double T, double* V_out, void* ws, size_t ws_bytes,
-                    void* stream) {
+int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices,
+                     double T, int32_t k_max, double tol, double* V_out,
+                     double* err_hist, int32_t* k_done, void* ws, size_t ws_bytes,
+                     void* stream) {
+  return parareal_impl(prob, Force{}, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done,
+                       ws, ws_bytes, stream);
+}
+
+int parareal_iterate_force(const bgk_problem* prob, const double* E, double e_max,
+                           const double* W0, int32_t n_slices, double T, int32_t k_max,
+                           double tol, double* V_out, double* err_hist, int32_t* k_done,
+                           void* ws, size_t ws_bytes, void* stream) {
+  if (!E) return invalid("E is NULL");
+  return parareal_impl(prob, Force{E, e_max}, W0, n_slices, T, k_max, tol, V_out, err_hist,
+                       k_done, ws, ws_bytes, stream);
+}
+
+static int serial_impl(const bgk_problem* prob, const Force& F, const double* W0,
+                       int32_t n_slices, double T, double* V_out, void* ws,
+                       size_t ws_bytes, void* stream) {
   int rc = check_problem(prob);
   if (rc) return rc;
   if (!W0 || !V_out) return invalid("NULL array");
@@ -807,21 +943,23 @@ int bgk_serial_fine(const bgk_problem* prob, const double* W0, int32_t n_slices,
   const double span = T / n_slices;
   int32_t n;
   double dt;
-  if ((rc = n_steps_for(*prob, span, &n, &dt))) return rc;
+  if ((rc = n_steps_for(*prob, span, &n, &dt, F.emax))) return rc;
   const Layout L = layout_of(*prob, BGK_OP_PARAREAL, n_slices);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
   int* st = &at<WsHeader>(ws, 0)->status;
   const size_t sl = (size_t)prob->nx * 5;
   double* U = at<double>(ws, L.U0);  // chain computed in the workspace
+  if ((rc = check_force(*prob, F, st, s))) return rc;
   if ((rc = launch_prim_to_cons(W0, U, prob->nx, s))) return rc;
-  const Tiles t = choose_tiles(*prob, 1);
+  const Tiles t = fine_tiles(*prob, 1, F);
   Inst* dI = at<Inst>(ws, L.insts);
-  const int ns = fused_for(t, n) ? 15 : 5;
+  const int ns = fine_nsum(t, n, F);
   auto chain = [&](hipStream_t q) -> int {
     int r;
     Inst I = make_inst(*prob, 1, dt, t, ns);
     attach_fine(I, ws, L.fine, nullptr);
+    attach_force(I, *prob, F, dt);
     for (int m = 1; m <= n_slices; ++m) {
       I.vin = U + (size_t)(m - 1) * sl;
       I.vout = U + (size_t)m * sl;
@@ -833,11 +971,36 @@ int bgk_serial_fine(const bgk_problem* prob, const double* W0, int32_t n_slices,
   };
   if ((rc = run_graph(graph_key("ser", ws, ws_bytes, *prob,
                                 {(double)n_slices, span, (double)t.elems, (double)t.chunk,
-                                 (double)t.pair, (double)ns}),
+                                 (double)t.pair, (double)ns, (double)(uintptr_t)F.E, F.emax}),
                       s, chain)))
     return rc;
   BGK_HIP(hipMemcpyAsync(V_out, U, sl * (n_slices + 1) * sizeof(double),
                          hipMemcpyDeviceToDevice, s));
+  return BGK_OK;
+}
+
+int bgk_serial_fine(const bgk_problem* prob, const double* W0, int32_t n_slices,
+                    double T, double* V_out, void* ws, size_t ws_bytes,
+                    void* stream) {
+  return serial_impl(prob, Force{}, W0, n_slices, T, V_out, ws, ws_bytes, stream);
+}
+
+int bgk_serial_fine_force(const bgk_problem* prob, const double* E, double e_max,
+                          const double* W0, int32_t n_slices, double T, double* V_out,
+                          void* ws, size_t ws_bytes, void* stream) {
+  if (!E) return invalid("E is NULL");
+  return serial_impl(prob, Force{E, e_max}, W0, n_slices, T, V_out, ws, ws_bytes, stream);
+}
+
+int bgk_n_steps_force(const bgk_problem* prob, double e_max, double t_span, int32_t* n,
+                      double* dt) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  int32_t nn;
+  double d;
+  if ((rc = n_steps_for(*prob, t_span, &nn, &d, e_max))) return rc;
+  if (n) *n = nn;
+  if (dt) *dt = d;
   return BGK_OK;
 }
 

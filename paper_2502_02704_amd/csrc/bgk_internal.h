@@ -54,6 +54,9 @@ struct Inst {
   double* vout;                // projected relaxed moments     [nbatch][nx][5]
   double* fac2;                // factors of the second step of a pass [..][nvs]
   double* aux;                 // per-cell weighted sums (two-step)  [..][nx][30]
+  const double* efield;        // exterior force E_i at x centres [nx]; null = none
+  double emax;                 // Rusanov coefficient of the v_x flux (>= max |E_i|)
+  double rv;                   // dt / dv_x
 };
 
 // Step-kernel source modes.
@@ -93,7 +96,8 @@ int hip_fail(hipError_t e, const char* what);
 int check_problem(const bgk_problem* p);
 double dx_of(const bgk_problem& p);
 double dv_of(const bgk_problem& p, int a);
-int n_steps_for(const bgk_problem& p, double t_span, int32_t* n, double* dt);
+int n_steps_for(const bgk_problem& p, double t_span, int32_t* n, double* dt,
+                double emax = 0.0);
 size_t align_up(size_t n, size_t a = 256);
 
 // Workspace header (first 256 bytes of every workspace).
@@ -111,13 +115,15 @@ struct Tiles {
   int pair;    // 1: lanes own pairs of adjacent velocities (needs even nv_z)
 };
 
-Tiles choose_tiles(const bgk_problem& p, int batch);
+// generic: tiles for the generic lane mapping (no velocity pairs).
+Tiles choose_tiles(const bgk_problem& p, int batch, bool generic = false);
 
 // Fused relax-then-transport step over all instances in `d_insts`.
 // ns: sums per partial, 5 (moments) or 15 (plus nu-weighted, paired only).
+// force: one step with the exterior-force v_x transport (generic lanes only).
 int launch_step(const Inst* d_insts, int n_inst, long long total_items,
                 int mode, int phase, Tiles t, int lds_doubles, int* d_status,
-                hipStream_t s, int ns = 5);
+                hipStream_t s, int ns = 5, bool force = false);
 // Per-x-cell reduction of partial sums into moments and factors.
 int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
                   int mode, int phase, int* d_status, hipStream_t s);
@@ -134,19 +140,21 @@ int launch_step2x2(const Inst* d_insts, int n_inst, long long total_items,
 int launch_partials(const Inst* d_insts, int n_inst, long long total_items,
                     int elems, int chunk, hipStream_t s);
 
-// Coarse Euler propagation, one workgroup per batch member.
+// Coarse Euler propagation, one workgroup per batch member.  E: exterior
+// force at the x centres (device, nullable), added as a source term.
 int launch_euler(const bgk_problem& p, int batch, const double* V_in,
                  double* V_out, double t_span, int* n_sub, double* scratch,
-                 int* d_status, hipStream_t s);
+                 int* d_status, hipStream_t s, const double* E = nullptr);
 // Parareal initial coarse sweep and per-iteration correction sweep.
 int launch_pararealsweep_init(const bgk_problem& p, int n_slices,
                               const double* W0, double* U, double* Gc,
                               double t_span, double* scratch, int* d_status,
-                              hipStream_t s);
+                              hipStream_t s, const double* E = nullptr);
 int launch_parareal_sweep(const bgk_problem& p, int n_slices, int k,
                           const double* U_old, double* U_new, const double* VF,
                           double* Gc, double t_span, double* scratch,
-                          double* d_err, int* d_status, hipStream_t s);
+                          double* d_err, int* d_status, hipStream_t s,
+                          const double* E = nullptr);
 int launch_prim_to_cons(const double* W, double* V, int n, hipStream_t s);
 
 // f_out = a g + F from buf[src_sel], or f_out = F (pure lift) if src_sel < 0.

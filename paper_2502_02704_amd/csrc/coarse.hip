@@ -21,6 +21,7 @@ constexpr int kMaxSubsteps = 1 << 20;  // hard cap: every loop ends
 struct CoarseGeo {
   int nx, bc;
   double dx, cfl, gamma;
+  const double* E;  // exterior force at the x centres (null: none)
 };
 
 __device__ __forceinline__ int gh(int i, int nx, int bc) {
@@ -61,7 +62,9 @@ __device__ double block_max(double v, double* red) {
 }
 
 // Advances the state held in `cur` (5*nx doubles) over `span`, ping-ponging
-// with `nxt`; h (5*nx) and spd (nx) are flux scratch.  Returns the buffer
+// with `nxt`; h (5*nx) and spd (nx) are flux scratch.  With an exterior force
+// each substep also adds the source (0, rho E, 0, 0, rho u_x E) of its
+// initial state.  Returns the buffer
 // that holds the final state (cur or nxt; identical in all threads) and the
 // substep count.  Ends with a barrier after the last write of the state.
 __device__ double* euler_advance(const CoarseGeo& G, double* cur, double* nxt, double* h,
@@ -112,6 +115,11 @@ __device__ double* euler_advance(const CoarseGeo& G, double* cur, double* nxt, d
         const double Hl = 0.5 * (h[5 * L + c] + h[5 * i + c]) -
                           0.5 * SL * (cur[5 * i + c] - cur[5 * L + c]);
         nxt[5 * i + c] = cur[5 * i + c] - r * (Hr - Hl);
+      }
+      if (G.E != nullptr) {
+        const double Ei = G.E[i];
+        nxt[5 * i + 1] += dt * cur[5 * i + 0] * Ei;
+        nxt[5 * i + 4] += dt * cur[5 * i + 1] * Ei;
       }
     }
     __syncthreads();
@@ -256,13 +264,14 @@ __global__ __launch_bounds__(kCoarseBlock) void k_parareal_sweep(
   if (threadIdx.x == 0) *err = e;
 }
 
-CoarseGeo geo_of(const bgk_problem& p) {
+CoarseGeo geo_of(const bgk_problem& p, const double* E) {
   CoarseGeo G;
   G.nx = p.nx;
   G.bc = p.bc;
   G.dx = dx_of(p);
   G.cfl = p.cfl;
   G.gamma = p.sound_gamma;
+  G.E = E;
   return G;
 }
 
@@ -281,9 +290,9 @@ size_t coarse_lds(size_t doubles) {
 
 int launch_euler(const bgk_problem& p, int batch, const double* V_in,
                  double* V_out, double t_span, int* n_sub, double* scratch,
-                 int* d_status, hipStream_t s) {
+                 int* d_status, hipStream_t s, const double* E) {
   const size_t lds = coarse_lds(16 * (size_t)p.nx);
-  hipLaunchKernelGGL(k_euler, dim3(batch), dim3(coarse_threads(p.nx)), lds, s, geo_of(p),
+  hipLaunchKernelGGL(k_euler, dim3(batch), dim3(coarse_threads(p.nx)), lds, s, geo_of(p, E),
                      V_in, V_out, t_span, n_sub, scratch, d_status, lds ? 1 : 0);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
@@ -292,10 +301,10 @@ int launch_euler(const bgk_problem& p, int batch, const double* V_in,
 int launch_pararealsweep_init(const bgk_problem& p, int n_slices,
                               const double* W0, double* U, double* Gc,
                               double t_span, double* scratch, int* d_status,
-                              hipStream_t s) {
+                              hipStream_t s, const double* E) {
   const size_t lds = coarse_lds(16 * (size_t)p.nx);
   hipLaunchKernelGGL(k_parareal_init, dim3(1), dim3(coarse_threads(p.nx)), lds, s,
-                     geo_of(p), n_slices, W0, U, Gc, t_span, scratch, d_status,
+                     geo_of(p, E), n_slices, W0, U, Gc, t_span, scratch, d_status,
                      lds ? 1 : 0);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
@@ -304,20 +313,20 @@ int launch_pararealsweep_init(const bgk_problem& p, int n_slices,
 int launch_parareal_sweep(const bgk_problem& p, int n_slices, int k,
                           const double* U_old, double* U_new, const double* VF,
                           double* Gc, double t_span, double* scratch,
-                          double* d_err, int* d_status, hipStream_t s) {
+                          double* d_err, int* d_status, hipStream_t s, const double* E) {
   const size_t lds = coarse_lds(16 * (size_t)p.nx);
   const int threads = coarse_threads(p.nx);
   const long long per = (5LL * p.nx + threads - 1) / threads;  // entries per thread
   if (per <= 5) {
-    hipLaunchKernelGGL(k_parareal_sweep<5>, dim3(1), dim3(threads), lds, s, geo_of(p),
+    hipLaunchKernelGGL(k_parareal_sweep<5>, dim3(1), dim3(threads), lds, s, geo_of(p, E),
                        n_slices, k, U_old, U_new, VF, Gc, t_span, scratch, d_err, d_status,
                        lds ? 1 : 0);
   } else if (per <= 10) {
-    hipLaunchKernelGGL(k_parareal_sweep<10>, dim3(1), dim3(threads), lds, s, geo_of(p),
+    hipLaunchKernelGGL(k_parareal_sweep<10>, dim3(1), dim3(threads), lds, s, geo_of(p, E),
                        n_slices, k, U_old, U_new, VF, Gc, t_span, scratch, d_err, d_status,
                        lds ? 1 : 0);
   } else {
-    hipLaunchKernelGGL(k_parareal_sweep<0>, dim3(1), dim3(threads), lds, s, geo_of(p),
+    hipLaunchKernelGGL(k_parareal_sweep<0>, dim3(1), dim3(threads), lds, s, geo_of(p, E),
                        n_slices, k, U_old, U_new, VF, Gc, t_span, scratch, d_err, d_status,
                        lds ? 1 : 0);
   }

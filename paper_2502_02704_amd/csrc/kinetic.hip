@@ -149,9 +149,15 @@ __device__ __forceinline__ double fac3(const double* row, unsigned off) {
 }
 
 // ---------------------------------------------------- fused step kernel --
-// Work item = (instance, member b, tile group, x chunk); 4 waves per block
+// Work item = (instance, member b, tile group, x chunk); the waves of a block
 // share the chunk (and its LDS factor rows) and take consecutive tiles.
-template <int E, int MODE>
+// FORCE: the step also transports in v_x under the exterior force E_i of the
+// x cell (Rusanov flux, coefficient emax, no flux through the ends of the v_x
+// range).  A lane's v_x neighbours lie nvy*nvz elements away in the same x
+// row; they are read directly (other waves of the block or nearby blocks
+// read them as their own centre values, so they mostly hit L2) and relaxed
+// with the factor of the neighbouring v_x point.
+template <int E, int MODE, bool FORCE = false>
 __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
                                                  int n_inst, int chunk,
                                                  int phase) {
@@ -227,15 +233,42 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
 #pragma unroll
     for (int e = 0; e < E; ++e) rawp[e] = raw[e];
   }
+  // relaxed value at the v_x neighbour (dir = -1 or +1) of element e in row i
+  const int nyz = I.nvy * I.nvz;
+  auto vneighbour = [&](int i, int e, int dir) -> double {
+    const double* frow = lds + (i - (i0 - 1)) * nvs;
+    const unsigned off = el.off[e] + (unsigned)dir;  // Ex index is the low field
+    double raw = 0.0;
+    if (MODE != kLift) raw = src[(long long)i * nv3 + e * kWave + dir * nyz];
+    if (MODE == kCopy) return raw;
+    if (MODE == kRelax) return fma(a, raw, fac3(frow, off));
+    return fac3(frow, off);
+  };
   double* part = I.part + (((long long)b * nx) * I.part_tiles + tile) * 5;
   for (int i = i0; i < i1; ++i) {
     if (i + 2 <= i1) load_row(i + 2, rawn);  // prefetch the next row
     relax_row(i + 1, rawp, fp);
+    double Ei = 0.0;
+    if (FORCE) Ei = I.efield[i];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const double nb = nu[e] > 0.0 ? fm[e] : fp[e];
-      const double gs = fma(fabs(nu[e]), nb - f0[e], f0[e]);
+      double gs = fma(fabs(nu[e]), nb - f0[e], f0[e]);
+      if (FORCE && el.ok[e]) {
+        const int jx = (int)(el.off[e] & 1023u);
+        const double c = f0[e];
+        double g_up = 0.0, g_down = 0.0;
+        if (jx + 1 < I.nvx) {
+          const double u = vneighbour(i, e, 1);
+          g_up = 0.5 * Ei * (c + u) - 0.5 * I.emax * (u - c);
+        }
+        if (jx > 0) {
+          const double d = vneighbour(i, e, -1);
+          g_down = 0.5 * Ei * (d + c) - 0.5 * I.emax * (c - d);
+        }
+        gs -= I.rv * (g_up - g_down);
+      }
       if (el.ok[e]) dst[(long long)i * nv3 + e * kWave] = gs;
       const double vsq = el.vx[e] * el.vx[e] + el.vy[e] * el.vy[e] +
                          el.vz[e] * el.vz[e];
@@ -1224,7 +1257,7 @@ static int blocks_for(long long n) { return (int)n; }
 
 int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode,
                 int phase, Tiles t, int lds_doubles, int* d_status, hipStream_t s,
-                int ns) {
+                int ns, bool force) {
   (void)d_status;
   if (total_items <= 0) return BGK_OK;
   dim3 grid(blocks_for(total_items)), block(kBlock);
@@ -1237,7 +1270,21 @@ int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode
     hipError_t e_ = hipGetLastError();                                      \
     return e_ == hipSuccess ? BGK_OK : hip_fail(e_, "k_step");              \
   }
-  if (t.pair && ns == 15) {
+  if (force) {
+    if (t.pair) {
+      set_error("the force step uses the generic lane mapping");
+      return BGK_E_INVALID;
+    }
+    BGK_STEP_CASE((k_step<2, kCopy, true>), 2, kCopy)
+    BGK_STEP_CASE((k_step<2, kRelax, true>), 2, kRelax)
+    BGK_STEP_CASE((k_step<2, kLift, true>), 2, kLift)
+    BGK_STEP_CASE((k_step<4, kCopy, true>), 4, kCopy)
+    BGK_STEP_CASE((k_step<4, kRelax, true>), 4, kRelax)
+    BGK_STEP_CASE((k_step<4, kLift, true>), 4, kLift)
+    BGK_STEP_CASE((k_step<8, kCopy, true>), 8, kCopy)
+    BGK_STEP_CASE((k_step<8, kRelax, true>), 8, kRelax)
+    BGK_STEP_CASE((k_step<8, kLift, true>), 8, kLift)
+  } else if (t.pair && ns == 15) {
     BGK_STEP_CASE((k_step2<1, kCopy, 15>), 2, kCopy)
     BGK_STEP_CASE((k_step2<1, kRelax, 15>), 2, kRelax)
     BGK_STEP_CASE((k_step2<1, kLift, 15>), 2, kLift)
