@@ -115,20 +115,21 @@ def parareal_speedup(torch, bgk, wl, reps=5):
             ts.append(time.perf_counter() - t0)
         return out, float(np.median(ts))
 
-    cases = [wl.c1_sod_small(),
-             wl.c2_smooth_periodic(eps=1e-4, nx=64, nv=16, n_slices=16)]
+    cases = [(wk.name, wk.problem, wk.W0, wk.n_slices, wk.T, None)
+             for wk in (wl.c1_sod_small(),
+                        wl.c2_smooth_periodic(eps=1e-4, nx=64, nv=16, n_slices=16))]
+    fk = wl.c6_two_beam_force()
+    cases.append((fk.name, fk.problem, fk.U0(), fk.n_slices, fk.T, fk.E))
     out = []
-    for wk in cases:
-        p = wk.problem
-        W0 = torch.from_numpy(wk.W0).cuda()
-        N, T = wk.n_slices, wk.T
-        ref, t_serial = timed(lambda: bgk.serial_fine(p, W0, N, T))
+    for name, p, W0np, N, T, E in cases:
+        W0 = torch.from_numpy(W0np).cuda()
+        ref, t_serial = timed(lambda: bgk.serial_fine(p, W0, N, T, E=E))
         ref = ref.cpu().numpy()
-        res = {"workload": wk.name, "slices": N, "serial_fine_ms": round(t_serial * 1e3, 4),
+        res = {"workload": name, "slices": N, "serial_fine_ms": round(t_serial * 1e3, 4),
                "K": []}
         chosen = None
         for K in range(1, N + 1):
-            (V, err, kd), t_par = timed(lambda: bgk.parareal_iterate(p, W0, N, T, K, 0.0))
+            (V, err, kd), t_par = timed(lambda: bgk.parareal_iterate(p, W0, N, T, K, 0.0, E=E))
             e = float(np.max(np.abs(V.cpu().numpy() - ref)))
             res["K"].append({"K": K, "ms": round(t_par * 1e3, 4), "err_vs_fine": e,
                              "speedup": round(t_serial / t_par, 3)})
@@ -139,6 +140,39 @@ def parareal_speedup(torch, bgk, wl, reps=5):
         res["speedup_at_1e-6"] = chosen["speedup"] if chosen else None
         out.append(res)
     return out
+
+
+def force_throughput(torch, bgk, wl, reps=5):
+    """The exterior-force path on the two-beam test grid (Nx=100,
+    256x16x16 velocities, eps=1e-5): all 20 slices of the first parareal
+    iteration batched, lift + 21 steps (one per pass, with the v_x Rusanov
+    transport) + projection.  Updates/s of the whole call and HBM rate of the
+    one-step kernel (16 algorithmic bytes per update)."""
+    import numpy as np
+    wk = wl.c6_two_beam_force()
+    p, N = wk.problem, wk.n_slices
+    W = wk.U0()
+    V1 = np.column_stack([W[:, 0], W[:, 0:1] * W[:, 1:4],
+                          0.5 * W[:, 0] * (W[:, 1:4] ** 2).sum(1) + 1.5 * W[:, 0] * W[:, 4]])
+    V = torch.from_numpy(np.stack([V1] * N)).cuda()
+    span = wk.T / N
+    n, _ = bgk.n_steps(p, span, E=wk.E)
+    E = torch.from_numpy(wk.E).cuda()
+    bgk.fine_propagate_moments(p, V, span, E=E)
+    torch.cuda.synchronize()
+    bgk.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bgk.fine_propagate_moments(p, V, span, E=E)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    ms, launches, upd, by = bgk.prof_read(bgk.PROF_ONE_STEP)
+    bgk.prof_enable(False)
+    bgk.check_status()
+    return {"workload": wk.name + f"_slices{N}", "steps": n,
+            "updates_per_s": N * p.cells * n / el, "ms_per_call": round(el * 1e3, 3),
+            "step_kernel_GBs": round(by / (ms * 1e-3) / 1e9, 1),
+            "step_kernel_avg_us": round(ms * 1e3 / max(launches, 1), 2)}
 
 
 def main():
@@ -223,6 +257,7 @@ def main():
             "roofline": roofline}
     if not args.no_parareal:
         line["parareal"] = parareal_speedup(torch, bgk, wl)
+        line["exterior_force"] = force_throughput(torch, bgk, wl)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wk, V_np, span)
     print(json.dumps(line), flush=True)

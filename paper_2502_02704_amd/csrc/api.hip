@@ -105,7 +105,12 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic) {
   Tiles t = (pair && g_fuse2) ? Tiles{8, 8, 1} : Tiles{8, 4, pair};
   auto it = g_tuned.find({p.nx, p.nv[0], p.nv[1], p.nv[2], batch});
   const long long cells = (long long)batch * p.nx * nv3_of(p);
-  if (it != g_tuned.end()) t = it->second;
+  if (generic) {
+    // the exterior-force step (measured on the 100 x 256x16x16 two-beam grid):
+    // 2 velocities per lane keep its extra neighbour registers unspilled
+    t = Tiles{2, 8, 0};
+    while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 512) t.chunk /= 2;
+  } else if (it != g_tuned.end()) t = it->second;
   else if (pair && g_fuse2 && cells < (1LL << 24)) {
     // latency-bound sizes (f fits the last-level cache): short velocity
     // tiles, x chunks as long as the grid keeps about two blocks per CU

@@ -233,20 +233,33 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
 #pragma unroll
     for (int e = 0; e < E; ++e) rawp[e] = raw[e];
   }
-  // relaxed value at the v_x neighbour (dir = -1 or +1) of element e in row i
+  // FORCE: raw values at the v_x neighbours (dn: -nyz, up: +nyz) of each
+  // element, loaded one row ahead of their use; relaxed with the factor of
+  // the neighbouring v_x point (the Ex index is the low field of off)
   const int nyz = I.nvy * I.nvz;
-  auto vneighbour = [&](int i, int e, int dir) -> double {
-    const double* frow = lds + (i - (i0 - 1)) * nvs;
-    const unsigned off = el.off[e] + (unsigned)dir;  // Ex index is the low field
-    double raw = 0.0;
-    if (MODE != kLift) raw = src[(long long)i * nv3 + e * kWave + dir * nyz];
+  double dn_cur[FORCE ? E : 1], up_cur[FORCE ? E : 1];
+  double dn_nxt[FORCE ? E : 1], up_nxt[FORCE ? E : 1];
+  auto load_vnb = [&](int r, double* dn, double* up) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int jx = (int)(el.off[e] & 1023u);
+      const long long o = (long long)r * nv3 + e * kWave;
+      dn[e] = (MODE != kLift && el.ok[e] && jx > 0) ? src[o - nyz] : 0.0;
+      up[e] = (MODE != kLift && el.ok[e] && jx + 1 < I.nvx) ? src[o + nyz] : 0.0;
+    }
+  };
+  auto relax_vnb = [&](int r, int e, int dir, double raw) -> double {
+    const double* frow = lds + (r - (i0 - 1)) * nvs;
+    const unsigned off = el.off[e] + (unsigned)dir;
     if (MODE == kCopy) return raw;
     if (MODE == kRelax) return fma(a, raw, fac3(frow, off));
     return fac3(frow, off);
   };
+  if (FORCE) load_vnb(i0, dn_cur, up_cur);
   double* part = I.part + (((long long)b * nx) * I.part_tiles + tile) * 5;
   for (int i = i0; i < i1; ++i) {
     if (i + 2 <= i1) load_row(i + 2, rawn);  // prefetch the next row
+    if (FORCE && i + 1 < i1) load_vnb(i + 1, dn_nxt, up_nxt);
     relax_row(i + 1, rawp, fp);
     double Ei = 0.0;
     if (FORCE) Ei = I.efield[i];
@@ -260,11 +273,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
         const double c = f0[e];
         double g_up = 0.0, g_down = 0.0;
         if (jx + 1 < I.nvx) {
-          const double u = vneighbour(i, e, 1);
+          const double u = relax_vnb(i, e, 1, up_cur[e]);
           g_up = 0.5 * Ei * (c + u) - 0.5 * I.emax * (u - c);
         }
         if (jx > 0) {
-          const double d = vneighbour(i, e, -1);
+          const double d = relax_vnb(i, e, -1, dn_cur[e]);
           g_down = 0.5 * Ei * (d + c) - 0.5 * I.emax * (c - d);
         }
         gs -= I.rv * (g_up - g_down);
@@ -296,6 +309,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
       fm[e] = f0[e];
       f0[e] = fp[e];
       rawp[e] = rawn[e];
+      if (FORCE) {
+        dn_cur[e] = dn_nxt[e];
+        up_cur[e] = up_nxt[e];
+      }
     }
   }
 }
