@@ -75,6 +75,9 @@ def lib():
             "bgk_oracle_parareal_iterate_force": [P, D, D, C.c_int32, C.c_double,
                                                   C.c_int32, C.c_double, D, D, I],
             "bgk_oracle_serial_fine_force": [P, D, D, C.c_int32, C.c_double, D],
+            "bgk_oracle_cns_coarse_step": [P, D, D, D, C.c_double, I],
+            "bgk_oracle_parareal_iterate_cns": [P, D, D, C.c_int32, C.c_double, C.c_int32,
+                                                C.c_double, D, D, I],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -236,6 +239,32 @@ def euler_coarse_step(p, V, t_span: float, E=None):
                                                       _d(out), t_span, C.byref(n))
     _chk(rc, "euler")
     return out, n.value
+
+
+def cns_coarse_step(p, V, t_span: float, E=None):
+    """Navier-Stokes coarse propagator (BGK coefficients); E optional."""
+    V = _arr(V)
+    out = np.empty_like(V)
+    n = C.c_int32()
+    Ea = _force(p, E) if E is not None else None
+    Ep = _d(Ea) if Ea is not None else None
+    _chk(lib().bgk_oracle_cns_coarse_step(C.byref(_prob(p)), Ep, _d(V), _d(out), t_span,
+                                          C.byref(n)), "cns")
+    return out, n.value
+
+
+def parareal_iterate_cns(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=None):
+    """Algorithm 2 with the Navier-Stokes coarse propagator."""
+    W0 = _arr(W0)
+    V = np.empty((n_slices + 1, p.nx, 5))
+    err = np.zeros(max(k_max, 1))
+    kd = C.c_int32()
+    Ea = _force(p, E) if E is not None else None
+    Ep = _d(Ea) if Ea is not None else None
+    _chk(lib().bgk_oracle_parareal_iterate_cns(C.byref(_prob(p)), Ep, _d(W0), n_slices, T,
+                                               k_max, tol, _d(V), _d(err), C.byref(kd)),
+         "parareal_cns")
+    return V, err[:kd.value].copy(), kd.value
 
 
 def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=None):

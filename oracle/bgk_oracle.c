@@ -485,12 +485,28 @@ static void euler_flux(const double* V5, double ux, double uy, double uz,
 
 /* With an exterior force E_i the Euler system carries the source
  * S = (0, rho E, 0, 0, rho u_x E) (Section 3.2 allows a source term), added
- * explicitly in each substep from the substep's initial state. */
-static int euler_impl(const bgk_oracle_problem* p, const double* E,
-                      const double* V_in, double* V_out, double t_span,
-                      int32_t* n_sub_out) {
+ * explicitly in each substep from the substep's initial state.
+ *
+ * viscous = 1: the compressible Navier-Stokes system of Section 1 (the
+ * first-order Chapman-Enskog correction of Euler's equations), with the BGK
+ * transport coefficients of tau = 1: viscosity mu = rho theta and heat
+ * conductivity kappa = (5/2) rho theta (Prandtl number 1).  In 1D-3V the
+ * strain terms are sigma_xx = (4/3) du_x/dx, sigma_xy = du_y/dx,
+ * sigma_xz = du_z/dx.  Face viscous flux (central differences, face values
+ * the mean of the two cells):
+ *   D = eps/dx (0, 4/3 mu (ux_R-ux_L), mu (uy_R-uy_L), mu (uz_R-uz_L),
+ *               mu (4/3 ux (ux_R-ux_L) + uy (uy_R-uy_L) + uz (uz_R-uz_L))
+ *               + kappa (theta_R-theta_L)),
+ * added as V += dt/dx (D_{i+1/2} - D_{i-1/2}); the substep also obeys the
+ * explicit diffusion limit dt <= cfl dx^2 / (2 eps (5/3) max theta), 5/3
+ * theta being the larger of the two diffusivities 4/3 mu/rho and
+ * kappa/(rho c_v). */
+static int coarse_impl(const bgk_oracle_problem* p, const double* E, int viscous,
+                       const double* V_in, double* V_out, double t_span,
+                       int32_t* n_sub_out) {
   if (check_problem(p) || !V_in || !V_out || !(t_span > 0.0))
     return ORACLE_E_INVALID;
+  if (viscous && !isfinite(p->eps)) return ORACLE_E_INVALID;
   const int nx = p->nx;
   const double dx = dx_of(p);
   double* V = (double*)malloc(5 * (size_t)nx * sizeof(double));
@@ -498,8 +514,9 @@ static int euler_impl(const bgk_oracle_problem* p, const double* E,
   double* H = (double*)malloc(5 * (size_t)(nx + 1) * sizeof(double));
   double* spd = (double*)malloc((size_t)nx * sizeof(double));
   double* hh = (double*)malloc(5 * (size_t)nx * sizeof(double));
-  if (!V || !Vn || !H || !spd || !hh) {
-    free(V); free(Vn); free(H); free(spd); free(hh);
+  double* pr = (double*)malloc(4 * (size_t)nx * sizeof(double)); /* ux uy uz theta */
+  if (!V || !Vn || !H || !spd || !hh || !pr) {
+    free(V); free(Vn); free(H); free(spd); free(hh); free(pr);
     return ORACLE_E_INVALID;
   }
   memcpy(V, V_in, 5 * (size_t)nx * sizeof(double));
@@ -508,7 +525,7 @@ static int euler_impl(const bgk_oracle_problem* p, const double* E,
   int rc = ORACLE_OK;
   while (t_span - t > 1e-14 * t_span) {
     /* cell-wise primitive variables, wave speed and physical flux */
-    double smax = 0.0;
+    double smax = 0.0, thmax = 0.0;
     for (int i = 0; i < nx && rc == ORACLE_OK; ++i) {
       double ux, uy, uz, th, c;
       rc = euler_prim(V + 5 * i, p->sound_gamma, &ux, &uy, &uz, &th, &c);
@@ -516,9 +533,18 @@ static int euler_impl(const bgk_oracle_problem* p, const double* E,
       spd[i] = fabs(ux) + c;
       euler_flux(V + 5 * i, ux, uy, uz, th, hh + 5 * i);
       if (spd[i] > smax) smax = spd[i];
+      if (th > thmax) thmax = th;
+      pr[4 * i + 0] = ux;
+      pr[4 * i + 1] = uy;
+      pr[4 * i + 2] = uz;
+      pr[4 * i + 3] = th;
     }
     if (rc) break;
     double dt = p->cfl * dx / smax;
+    if (viscous) {
+      double dt_visc = p->cfl * dx * dx / (2.0 * p->eps * (5.0 / 3.0) * thmax);
+      if (dt_visc < dt) dt = dt_visc;
+    }
     if (dt > t_span - t) dt = t_span - t;
     /* interface fluxes H_{f-1/2} for f = 0..nx, ghosts from the BC */
     for (int fc = 0; fc <= nx; ++fc) {
@@ -531,6 +557,28 @@ static int euler_impl(const bgk_oracle_problem* p, const double* E,
     for (int i = 0; i < nx; ++i)
       for (int c = 0; c < 5; ++c)
         Vn[5 * i + c] = V[5 * i + c] - dt / dx * (H[5 * (i + 1) + c] - H[5 * i + c]);
+    if (viscous) {
+      /* face viscous fluxes D_{f-1/2}, f = 0..nx, into H (reused) */
+      for (int fc = 0; fc <= nx; ++fc) {
+        int L = ghost(p, fc - 1), R = ghost(p, fc);
+        const double* a = pr + 4 * L;
+        const double* b = pr + 4 * R;
+        double mu = 0.5 * (V[5 * L] * a[3] + V[5 * R] * b[3]);
+        double kappa = 2.5 * mu;
+        double dux = b[0] - a[0], duy = b[1] - a[1], duz = b[2] - a[2];
+        double uxf = 0.5 * (a[0] + b[0]), uyf = 0.5 * (a[1] + b[1]), uzf = 0.5 * (a[2] + b[2]);
+        double k = p->eps / dx;
+        H[5 * fc + 0] = 0.0;
+        H[5 * fc + 1] = k * (4.0 / 3.0) * mu * dux;
+        H[5 * fc + 2] = k * mu * duy;
+        H[5 * fc + 3] = k * mu * duz;
+        H[5 * fc + 4] = k * (mu * ((4.0 / 3.0) * uxf * dux + uyf * duy + uzf * duz) +
+                             kappa * (b[3] - a[3]));
+      }
+      for (int i = 0; i < nx; ++i)
+        for (int c = 1; c < 5; ++c)
+          Vn[5 * i + c] += dt / dx * (H[5 * (i + 1) + c] - H[5 * i + c]);
+    }
     if (E)
       for (int i = 0; i < nx; ++i) {
         Vn[5 * i + 1] += dt * V[5 * i + 0] * E[i];
@@ -549,14 +597,26 @@ static int euler_impl(const bgk_oracle_problem* p, const double* E,
   }
   if (rc == ORACLE_OK) memcpy(V_out, V, 5 * (size_t)nx * sizeof(double));
   if (n_sub_out) *n_sub_out = nsub;
-  free(V); free(Vn); free(H); free(spd); free(hh);
+  free(V); free(Vn); free(H); free(spd); free(hh); free(pr);
   return rc;
+}
+
+static int euler_impl(const bgk_oracle_problem* p, const double* E,
+                      const double* V_in, double* V_out, double t_span,
+                      int32_t* n_sub_out) {
+  return coarse_impl(p, E, 0, V_in, V_out, t_span, n_sub_out);
 }
 
 int bgk_oracle_euler_coarse_step(const bgk_oracle_problem* p,
                                  const double* V_in, double* V_out,
                                  double t_span, int32_t* n_sub_out) {
   return euler_impl(p, NULL, V_in, V_out, t_span, n_sub_out);
+}
+
+int bgk_oracle_cns_coarse_step(const bgk_oracle_problem* p, const double* E,
+                               const double* V_in, double* V_out, double t_span,
+                               int32_t* n_sub_out) {
+  return coarse_impl(p, E, 1, V_in, V_out, t_span, n_sub_out);
 }
 
 int bgk_oracle_euler_coarse_step_force(const bgk_oracle_problem* p,
@@ -586,7 +646,7 @@ static void primitive_to_conserved(const double* W5, double* V5) {
  *     U^{n,k+1} = G(U^{n-1,k+1}) + Delta^n             for n = k+1..N (in order)
  *     err_k = max_{n,i,c} |U^{n,k+1} - U^{n,k}|;  stop at K or err < tol.
  * The jump loop is the parallel one (Section 2.2 and Section 4). */
-static int parareal_impl(const bgk_oracle_problem* p, const double* E,
+static int parareal_impl(const bgk_oracle_problem* p, const double* E, int viscous,
                          const double* W0, int32_t n_slices, double T,
                          int32_t k_max, double tol, double* V_out,
                          double* err_hist, int32_t* k_done) {
@@ -606,7 +666,7 @@ static int parareal_impl(const bgk_oracle_problem* p, const double* E,
   for (int i = 0; i < nx; ++i) primitive_to_conserved(W0 + 5 * i, U + 5 * i);
   int rc = ORACLE_OK;
   for (int n = 1; n <= n_slices && rc == ORACLE_OK; ++n)
-    rc = euler_impl(p, E, U + sl * (n - 1), U + sl * n, dT, NULL);
+    rc = coarse_impl(p, E, viscous, U + sl * (n - 1), U + sl * n, dT, NULL);
   int32_t kd = 0;
   for (int k = 0; k < k_max && rc == ORACLE_OK; ++k) {
     /* jumps, independent over n */
@@ -615,7 +675,7 @@ static int parareal_impl(const bgk_oracle_problem* p, const double* E,
       double* Fv = (double*)malloc(sl * sizeof(double));
       double* Gv = (double*)malloc(sl * sizeof(double));
       int r1 = propagate_impl(p, E, U + sl * (n - 1), Fv, dT);
-      int r2 = r1 ? r1 : euler_impl(p, E, U + sl * (n - 1), Gv, dT, NULL);
+      int r2 = r1 ? r1 : coarse_impl(p, E, viscous, U + sl * (n - 1), Gv, dT, NULL);
       if (r1 || r2) bad = r1 ? r1 : r2;
       else
         for (size_t q = 0; q < sl; ++q) D[sl * n + q] = Fv[q] - Gv[q];
@@ -630,7 +690,7 @@ static int parareal_impl(const bgk_oracle_problem* p, const double* E,
     /* frozen prefix, then the sequential correction */
     memcpy(Un, U, sl * (k + 1) * sizeof(double));
     for (int n = k + 1; n <= n_slices && rc == ORACLE_OK; ++n) {
-      rc = euler_impl(p, E, Un + sl * (n - 1), Un + sl * n, dT, NULL);
+      rc = coarse_impl(p, E, viscous, Un + sl * (n - 1), Un + sl * n, dT, NULL);
       if (rc == ORACLE_OK)
         for (size_t q = 0; q < sl; ++q) Un[sl * n + q] += D[sl * n + q];
     }
@@ -655,7 +715,7 @@ int bgk_oracle_parareal_iterate(const bgk_oracle_problem* p, const double* W0,
                                 int32_t n_slices, double T, int32_t k_max,
                                 double tol, double* V_out, double* err_hist,
                                 int32_t* k_done) {
-  return parareal_impl(p, NULL, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
+  return parareal_impl(p, NULL, 0, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
 }
 
 int bgk_oracle_parareal_iterate_force(const bgk_oracle_problem* p, const double* E,
@@ -663,7 +723,14 @@ int bgk_oracle_parareal_iterate_force(const bgk_oracle_problem* p, const double*
                                       int32_t k_max, double tol, double* V_out,
                                       double* err_hist, int32_t* k_done) {
   if (!E) return ORACLE_E_INVALID;
-  return parareal_impl(p, E, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
+  return parareal_impl(p, E, 0, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
+}
+
+int bgk_oracle_parareal_iterate_cns(const bgk_oracle_problem* p, const double* E,
+                                    const double* W0, int32_t n_slices, double T,
+                                    int32_t k_max, double tol, double* V_out,
+                                    double* err_hist, int32_t* k_done) {
+  return parareal_impl(p, E, 1, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
 }
 
 /* The fine reference that parareal converges to: U^n = P F L(U^{n-1}). */

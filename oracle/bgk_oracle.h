@@ -145,6 +145,21 @@ int bgk_oracle_serial_fine_force(const bgk_oracle_problem* p, const double* E,
                                  const double* W0, int32_t n_slices, double T,
                                  double* V_out);
 
+/* Coarse propagator G as the compressible Navier-Stokes system (Section 1,
+ * the Chapman-Enskog correction of Euler's equations) with the BGK transport
+ * coefficients mu = rho theta, kappa = (5/2) rho theta: Rusanov convective
+ * fluxes plus central viscous and heat fluxes, explicit, with the convective
+ * and diffusive step limits.  E (host [nx]) may be NULL (no force).  Needs a
+ * finite eps.  The parareal variant uses it as G; its fixed point is the
+ * same serial fine chain. */
+int bgk_oracle_cns_coarse_step(const bgk_oracle_problem* p, const double* E,
+                               const double* V_in, double* V_out, double t_span,
+                               int32_t* n_sub_out);
+int bgk_oracle_parareal_iterate_cns(const bgk_oracle_problem* p, const double* E,
+                                    const double* W0, int32_t n_slices, double T,
+                                    int32_t k_max, double tol, double* V_out,
+                                    double* err_hist, int32_t* k_done);
+
 void bgk_oracle_set_threads(int n);
 int bgk_oracle_get_threads(void);
 

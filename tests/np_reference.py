@@ -112,3 +112,33 @@ def euler_substep(p, V, dt, E=None):
         out[:, 1] += dt * V[:, 0] * E
         out[:, 4] += dt * V[:, 1] * E
     return out, s.max()
+
+
+def cns_substep(p, V, dt, E=None):
+    """Euler substep plus the Navier-Stokes viscous and heat fluxes with BGK
+    coefficients (mu = rho theta, kappa = 5/2 rho theta), central face
+    differences, arrays of faces built with np.roll / edge padding.
+    Returns (V_new, smax, theta_max)."""
+    out, smax = euler_substep(p, V, dt, E)
+    rho = V[:, 0]
+    u = V[:, 1:4] / rho[:, None]
+    th = (2 * V[:, 4] / rho - (u ** 2).sum(1)) / 3
+    if p.bc == 1:
+        L = np.arange(-1, p.nx) % p.nx
+        R = np.arange(0, p.nx + 1) % p.nx
+    else:
+        L = np.clip(np.arange(-1, p.nx), 0, p.nx - 1)
+        R = np.clip(np.arange(0, p.nx + 1), 0, p.nx - 1)
+    dx = (p.x_hi - p.x_lo) / p.nx
+    mu = 0.5 * (rho[L] * th[L] + rho[R] * th[R])
+    du = u[R] - u[L]
+    uf = 0.5 * (u[L] + u[R])
+    D = np.zeros((p.nx + 1, 5))
+    D[:, 1] = (4.0 / 3.0) * mu * du[:, 0]
+    D[:, 2] = mu * du[:, 1]
+    D[:, 3] = mu * du[:, 2]
+    D[:, 4] = mu * ((4.0 / 3.0) * uf[:, 0] * du[:, 0] + uf[:, 1] * du[:, 1] +
+                    uf[:, 2] * du[:, 2]) + 2.5 * mu * (th[R] - th[L])
+    D *= p.eps / dx
+    out = out + dt / dx * (D[1:] - D[:-1])
+    return out, smax, th.max()

@@ -733,6 +733,85 @@ class TestExteriorForce:
         assert abs(E[5] - 5 * 0.5 ** 4 * 1.5 ** 4 * 0.5) < 1e-15
 
 
+class TestNavierStokesCoarse:
+    """The compressible Navier-Stokes coarse propagator (Section 1 system,
+    BGK coefficients mu = rho theta, kappa = 5/2 rho theta)."""
+
+    @pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_PERIODIC])
+    def test_constant_state_exact(self, bc):
+        p = wl.small_problem(nx=10, bc=bc, eps=0.3)
+        V = np.tile([1.3, 0.2, -0.1, 0.05, 2.2], (p.nx, 1))
+        out, _ = oracle.cns_coarse_step(p, V, 0.02)
+        assert np.array_equal(out, V)
+
+    def test_periodic_totals_conserved(self):
+        p = wl.small_problem(nx=24, bc=wl.BC_PERIODIC, eps=0.2)
+        x = p.x_centres()
+        V = np.column_stack([1 + 0.3 * np.sin(2 * np.pi * x), 0.2 * np.cos(2 * np.pi * x),
+                             0.1 * np.sin(4 * np.pi * x), 0 * x,
+                             2 + 0.2 * np.cos(2 * np.pi * x)])
+        out, n = oracle.cns_coarse_step(p, V, 0.05)
+        assert n > 1
+        assert np.max(np.abs(out.sum(0) - V.sum(0))) < 1e-13 * p.nx
+
+    def test_vanishing_eps_is_euler(self):
+        p = wl.small_problem(nx=16, bc=wl.BC_NEUMANN, eps=1e-300)
+        W0 = wl.riemann_W0(p, wl.SOD_LEFT, wl.SOD_RIGHT)
+        V = np.column_stack([W0[:, 0], 0 * W0[:, 0], 0 * W0[:, 0], 0 * W0[:, 0],
+                             1.5 * W0[:, 0] * W0[:, 4]])
+        a, na = oracle.cns_coarse_step(p, V, 0.03)
+        b, nb = oracle.euler_coarse_step(p, V, 0.03)
+        assert na == nb and np.array_equal(a, b)
+
+    def test_shear_wave_decays_at_the_viscous_rate(self):
+        # u_y = A sin(2 pi x) on a uniform gas (rho = theta = 1): linearised,
+        # the viscous term damps it at eps * (mu/rho) * lambda_h with mu/rho =
+        # theta = 1 and lambda_h = (2 - 2 cos(k dx)) / dx^2 the eigenvalue of
+        # the central second difference; the Rusanov part damps it equally in
+        # the Euler run, which is subtracted
+        p = wl.small_problem(nx=128, bc=wl.BC_PERIODIC, eps=0.5)
+        x = p.x_centres()
+        A = 1e-4
+        s = np.sin(2 * np.pi * x)
+        V = np.column_stack([1 + 0 * x, 0 * x, A * s, 0 * x, 1.5 + 0.5 * (A * s) ** 2])
+        t = 0.01
+        a = oracle.cns_coarse_step(p, V, t)[0][:, 2] @ s / (s @ s)
+        b = oracle.euler_coarse_step(p, V, t)[0][:, 2] @ s / (s @ s)
+        dx = 1.0 / p.nx
+        lam = (2 - 2 * np.cos(2 * np.pi * dx)) / dx ** 2
+        rate = (np.log(b) - np.log(a)) / t
+        assert abs(rate / (p.eps * lam) - 1) < 2e-3
+
+    def test_matches_numpy_substeps(self):
+        p = wl.small_problem(nx=14, bc=wl.BC_NEUMANN, eps=0.05)
+        x = p.x_centres()
+        V = np.column_stack([1 + 0.2 * np.sin(3 * x), 0.1 * np.cos(5 * x), 0.05 * x,
+                             -0.02 * x, 1.6 + 0.2 * np.cos(4 * x)])
+        E = 0.4 * np.sin(2 * np.pi * x)
+        span = 0.02
+        out, n = oracle.cns_coarse_step(p, V, span, E=E)
+        t, Vn, cnt = 0.0, V.copy(), 0
+        dx = 1 / p.nx
+        while span - t > 1e-14 * span:
+            _, smax, thmax = npr.cns_substep(p, Vn, 0.0)
+            dt = min(p.cfl * dx / smax, p.cfl * dx * dx / (2 * p.eps * (5 / 3) * thmax), span - t)
+            Vn, _, _ = npr.cns_substep(p, Vn, dt, E)
+            t += dt
+            cnt += 1
+        assert cnt == n
+        assert np.max(np.abs(out - Vn)) < 1e-14
+
+    def test_parareal_with_navier_stokes_coarse(self):
+        # K = N reproduces the serial fine chain whatever the coarse model;
+        # the successive errors decrease
+        wk = wl.c2_smooth_periodic(eps=1e-2, nx=12, nv=8, n_slices=4)
+        p = wk.problem
+        ref = oracle.serial_fine(p, wk.W0, 4, wk.T)
+        V, err, kd = oracle.parareal_iterate_cns(p, wk.W0, 4, wk.T, 4, 0.0)
+        assert kd == 4 and np.max(np.abs(V - ref)) < 1e-13
+        assert all(err[i + 1] < err[i] for i in range(len(err) - 2))
+
+
 class TestErrors:
     def test_invalid_arguments(self):
         from dataclasses import replace
