@@ -207,6 +207,31 @@ int bgk_serial_fine_force(const bgk_problem* prob, const double* E, double e_max
                           const double* W0, int32_t n_slices, double T,
                           double* V_out, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------- Navier-Stokes coarse model --
+ * The compressible Navier-Stokes system of Section 1 (the first-order
+ * Chapman-Enskog correction of Euler's equations) with the BGK transport
+ * coefficients of the relaxation rate 1/eps: viscosity eps*mu, mu = rho
+ * theta, heat conductivity eps*kappa, kappa = (5/2) rho theta (Prandtl number
+ * 1); in 1D-3V sigma_xx = (4/3) du_x/dx, sigma_xy = du_y/dx, sigma_xz =
+ * du_z/dx.  Rusanov convective fluxes plus central viscous and heat face
+ * fluxes (face coefficients the mean of the two cells), explicit, with
+ * dt = min(cfl dx / max(|u_x| + c), cfl dx^2 / (2 eps (5/3) max theta)).  A
+ * finer coarse propagator for parareal (Section 3.2): same fixed point (the
+ * serial fine chain), fewer iterations where viscosity matters.  E may be
+ * NULL (no force; e_max ignored) or an exterior force as in the _force calls.
+ * BGK_E_INVALID for an infinite eps.  Workspaces: BGK_OP_COARSE and
+ * BGK_OP_PARAREAL sizes; arguments otherwise as euler_coarse_step and
+ * parareal_iterate. */
+int euler_coarse_step_cns(const bgk_problem* prob, const double* E, int32_t batch,
+                          const double* V_in, double* V_out, double t_span,
+                          int32_t* n_sub_out, void* ws, size_t ws_bytes,
+                          void* stream);
+int parareal_iterate_cns(const bgk_problem* prob, const double* E, double e_max,
+                         const double* W0, int32_t n_slices, double T,
+                         int32_t k_max, double tol, double* V_out,
+                         double* err_hist, int32_t* k_done, void* ws,
+                         size_t ws_bytes, void* stream);
+
 /* Adjoint of n_steps IMEX steps of size dt (the transpose of the step's
  * Jacobian: transposed upwind stencil, adjoint of moments -> Maxwellian ->
  * relaxation).  [device] f_ckpt [ceil(n_steps/ckpt_every)][nx][nv3] forward

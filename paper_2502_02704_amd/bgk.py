@@ -31,7 +31,8 @@ EXPORTS = [
     "bgk_set_tiles", "bgk_autotune", "bgk_prof_enable", "bgk_prof_read",
     "bgk_set_graphs", "bgk_set_step_fusion", "bgk_n_steps_force", "bgk_fine_steps_force",
     "bgk_fine_step_force", "bgk_fine_propagate_moments_force", "euler_coarse_step_force",
-    "parareal_iterate_force", "bgk_serial_fine_force",
+    "parareal_iterate_force", "bgk_serial_fine_force", "euler_coarse_step_cns",
+    "parareal_iterate_cns",
 ]
 
 
@@ -102,6 +103,9 @@ def load_library(path: str = LIB_PATH):
                                              C.c_int32, C.c_double, V, D, I, V, Z, V]),
         "bgk_serial_fine_force": (C.c_int, [P, V, C.c_double, V, C.c_int32, C.c_double, V,
                                             V, Z, V]),
+        "euler_coarse_step_cns": (C.c_int, [P, V, C.c_int32, V, V, C.c_double, V, V, Z, V]),
+        "parareal_iterate_cns": (C.c_int, [P, V, C.c_double, V, C.c_int32, C.c_double,
+                                           C.c_int32, C.c_double, V, D, I, V, Z, V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -334,7 +338,9 @@ def fine_propagate_moments(p, V_in: torch.Tensor, t_span: float, E=None) -> torc
     return out
 
 
-def euler_coarse_step(p, V: torch.Tensor, t_span: float, E=None):
+def euler_coarse_step(p, V: torch.Tensor, t_span: float, E=None, coarse: str = "euler"):
+    """Coarse propagator over t_span for each member of V ([B][nx][5]);
+    coarse = "euler" (Section 3.2) or "cns" (Navier-Stokes, BGK coefficients)."""
     L = _gpu_lib()
     V = V.contiguous()
     B = V.shape[0] if V.dim() == 3 else 1
@@ -342,7 +348,14 @@ def euler_coarse_step(p, V: torch.Tensor, t_span: float, E=None):
     nsub = torch.zeros(B, dtype=torch.int32, device="cuda")
     w = workspace(p, OP_COARSE, B)
     ps = C.byref(problem_struct(p))
-    if E is None:
+    if coarse not in ("euler", "cns"):
+        raise ValueError("coarse must be 'euler' or 'cns'")
+    if coarse == "cns":
+        Ed = _force(p, E)[0] if E is not None else None
+        rc = L.euler_coarse_step_cns(ps, _dev(Ed, "E") if Ed is not None else None, B,
+                                     _dev(V, "V_in"), _dev(out, "V_out"), t_span,
+                                     nsub.data_ptr(), w.data_ptr(), w.numel(), _stream())
+    elif E is None:
         rc = L.euler_coarse_step(ps, B, _dev(V, "V_in"), _dev(out, "V_out"), t_span,
                                  nsub.data_ptr(), w.data_ptr(), w.numel(), _stream())
     else:
@@ -354,7 +367,9 @@ def euler_coarse_step(p, V: torch.Tensor, t_span: float, E=None):
     return out, nsub
 
 
-def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=None):
+def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=None,
+                     coarse: str = "euler"):
+    """Algorithm 2; coarse = "euler" or "cns" (Navier-Stokes coarse propagator)."""
     L = _gpu_lib()
     W0 = _f64(W0)
     V = torch.empty((n_slices + 1, p.nx, 5), dtype=torch.float64, device="cuda")
@@ -362,7 +377,14 @@ def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=N
     kd = C.c_int32()
     w = workspace(p, OP_PARAREAL, n_slices)
     ps = C.byref(problem_struct(p))
-    if E is None:
+    if coarse not in ("euler", "cns"):
+        raise ValueError("coarse must be 'euler' or 'cns'")
+    if coarse == "cns":
+        Ed, emax = _force(p, E) if E is not None else (None, 0.0)
+        rc = L.parareal_iterate_cns(ps, _dev(Ed, "E") if Ed is not None else None, emax,
+                                    _dev(W0, "W0"), n_slices, T, k_max, tol, _dev(V, "V_out"),
+                                    err, C.byref(kd), w.data_ptr(), w.numel(), _stream())
+    elif E is None:
         rc = L.parareal_iterate(ps, _dev(W0, "W0"), n_slices, T, k_max, tol,
                                 _dev(V, "V_out"), err, C.byref(kd), w.data_ptr(), w.numel(),
                                 _stream())

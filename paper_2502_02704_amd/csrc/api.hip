@@ -200,14 +200,14 @@ static Layout layout_of(const bgk_problem& p, int op, int batch) {
       L.fine = carve_fine(c, p, 1, 0);
       break;
     case BGK_OP_COARSE:
-      L.coarse = c.take((size_t)batch * 16 * p.nx * sizeof(double));
+      L.coarse = c.take((size_t)batch * kCoarseScratch * p.nx * sizeof(double));
       break;
     case BGK_OP_PROPAGATE:
       L.fine = carve_fine(c, p, batch, 2);
       break;
     case BGK_OP_PARAREAL:
       L.fine = carve_fine(c, p, batch, 2);
-      L.coarse = c.take((size_t)16 * p.nx * sizeof(double));
+      L.coarse = c.take((size_t)kCoarseScratch * p.nx * sizeof(double));
       L.errs = c.take((size_t)(batch + 1) * sizeof(double));
       L.U0 = c.take(sl * (batch + 1));
       L.U1 = c.take(sl * (batch + 1));
@@ -798,10 +798,12 @@ int bgk_fine_propagate_moments_force(const bgk_problem* prob, const double* E,
                         stream);
 }
 
-static int euler_impl(const bgk_problem* prob, const double* E, int32_t batch,
+static int euler_impl(const bgk_problem* prob, const double* E, bool viscous, int32_t batch,
                       const double* V_in, double* V_out, double t_span, int32_t* n_sub_out,
                       void* ws, size_t ws_bytes, void* stream) {
   int rc = check_problem(prob);
+  if (rc) return rc;
+  if (viscous && !std::isfinite(prob->eps)) return invalid("the Navier-Stokes model needs a finite eps");
   if (rc) return rc;
   if (batch < 1) return invalid("batch must be >= 1");
   if (!V_in || !V_out) return invalid("NULL array");
@@ -810,24 +812,33 @@ static int euler_impl(const bgk_problem* prob, const double* E, int32_t batch,
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
   return launch_euler(*prob, batch, V_in, V_out, t_span, n_sub_out,
                       at<double>(ws, L.coarse), &at<WsHeader>(ws, 0)->status,
-                      (hipStream_t)stream, E);
+                      (hipStream_t)stream, E, viscous);
 }
 
 int euler_coarse_step(const bgk_problem* prob, int32_t batch, const double* V_in,
                       double* V_out, double t_span, int32_t* n_sub_out, void* ws,
                       size_t ws_bytes, void* stream) {
-  return euler_impl(prob, nullptr, batch, V_in, V_out, t_span, n_sub_out, ws, ws_bytes,
-                    stream);
+  return euler_impl(prob, nullptr, false, batch, V_in, V_out, t_span, n_sub_out, ws,
+                    ws_bytes, stream);
 }
 
 int euler_coarse_step_force(const bgk_problem* prob, const double* E, int32_t batch,
                             const double* V_in, double* V_out, double t_span,
                             int32_t* n_sub_out, void* ws, size_t ws_bytes, void* stream) {
   if (!E) return invalid("E is NULL");
-  return euler_impl(prob, E, batch, V_in, V_out, t_span, n_sub_out, ws, ws_bytes, stream);
+  return euler_impl(prob, E, false, batch, V_in, V_out, t_span, n_sub_out, ws, ws_bytes,
+                    stream);
 }
 
-static int parareal_impl(const bgk_problem* prob, const Force& F, const double* W0,
+int euler_coarse_step_cns(const bgk_problem* prob, const double* E, int32_t batch,
+                          const double* V_in, double* V_out, double t_span,
+                          int32_t* n_sub_out, void* ws, size_t ws_bytes, void* stream) {
+  return euler_impl(prob, E, true, batch, V_in, V_out, t_span, n_sub_out, ws, ws_bytes,
+                    stream);
+}
+
+static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
+                         const double* W0,
                          int32_t n_slices, double T, int32_t k_max, double tol,
                          double* V_out, double* err_hist, int32_t* k_done, void* ws,
                          size_t ws_bytes, void* stream) {
@@ -837,6 +848,7 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, const double* 
   if (n_slices < 1 || k_max < 0) return invalid("n_slices >= 1 and k_max >= 0 required");
   if (k_max > 0 && !err_hist) return invalid("err_hist is NULL");
   if (!(T > 0.0) || !std::isfinite(T) || std::isnan(tol)) return invalid("bad T or tol");
+  if (viscous && !std::isfinite(prob->eps)) return invalid("the Navier-Stokes model needs a finite eps");
   const double span = T / n_slices;
   int32_t n;
   double dt;
@@ -856,7 +868,7 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, const double* 
   BGK_HIP(hipGetLastError());
   if ((rc = check_force(*prob, F, st, s))) return rc;
   if ((rc = launch_pararealsweep_init(*prob, n_slices, W0, U[0], Gc, span, scratch, st, s,
-                                      F.E)))
+                                      F.E, viscous)))
     return rc;
   int cur = 0;
   int32_t kd = 0;
@@ -877,12 +889,14 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, const double* 
       int last = 0;
       if ((r = lift_and_run(dI, I, n, true, t, st, q, &last))) return r;
       return launch_parareal_sweep(*prob, n_slices, k, U[cur], U[cur ^ 1], VF, Gc, span,
-                                   scratch, tol > 0.0 ? &hd->err : errs + k, st, q, F.E);
+                                   scratch, tol > 0.0 ? &hd->err : errs + k, st, q, F.E,
+                                   viscous);
     };
     if ((rc = run_graph(graph_key("pit", ws, ws_bytes, *prob,
                                   {(double)n_slices, span, (double)k, (double)t.elems,
                                    (double)t.chunk, (double)t.pair, (double)I.nsum,
-                                   tol > 0.0 ? 1.0 : 0.0, (double)(uintptr_t)F.E, F.emax}),
+                                   tol > 0.0 ? 1.0 : 0.0, (double)(uintptr_t)F.E, F.emax,
+                                   viscous ? 1.0 : 0.0}),
                         s, iteration)))
       return rc;
     cur ^= 1;
@@ -925,8 +939,8 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
                      double T, int32_t k_max, double tol, double* V_out,
                      double* err_hist, int32_t* k_done, void* ws, size_t ws_bytes,
                      void* stream) {
-  return parareal_impl(prob, Force{}, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done,
-                       ws, ws_bytes, stream);
+  return parareal_impl(prob, Force{}, false, W0, n_slices, T, k_max, tol, V_out, err_hist,
+                       k_done, ws, ws_bytes, stream);
 }
 
 int parareal_iterate_force(const bgk_problem* prob, const double* E, double e_max,
@@ -934,8 +948,17 @@ int parareal_iterate_force(const bgk_problem* prob, const double* E, double e_ma
                            double tol, double* V_out, double* err_hist, int32_t* k_done,
                            void* ws, size_t ws_bytes, void* stream) {
   if (!E) return invalid("E is NULL");
-  return parareal_impl(prob, Force{E, e_max}, W0, n_slices, T, k_max, tol, V_out, err_hist,
-                       k_done, ws, ws_bytes, stream);
+  return parareal_impl(prob, Force{E, e_max}, false, W0, n_slices, T, k_max, tol, V_out,
+                       err_hist, k_done, ws, ws_bytes, stream);
+}
+
+int parareal_iterate_cns(const bgk_problem* prob, const double* E, double e_max,
+                         const double* W0, int32_t n_slices, double T, int32_t k_max,
+                         double tol, double* V_out, double* err_hist, int32_t* k_done,
+                         void* ws, size_t ws_bytes, void* stream) {
+  const Force F = E ? Force{E, e_max} : Force{};
+  return parareal_impl(prob, F, true, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done,
+                       ws, ws_bytes, stream);
 }
 
 static int serial_impl(const bgk_problem* prob, const Force& F, const double* W0,

@@ -140,21 +140,28 @@ int launch_step2x2(const Inst* d_insts, int n_inst, long long total_items,
 int launch_partials(const Inst* d_insts, int n_inst, long long total_items,
                     int elems, int chunk, hipStream_t s);
 
-// Coarse Euler propagation, one workgroup per batch member.  E: exterior
-// force at the x centres (device, nullable), added as a source term.
+// Scratch doubles per x cell of one coarse propagation: state and next state
+// (5 + 5), physical flux (5), wave speed (1), primitive u and theta (4).
+constexpr int kCoarseScratch = 20;
+
+// Coarse propagation, one workgroup per batch member.  E: exterior force at
+// the x centres (device, nullable), added as a source term; viscous: the
+// Navier-Stokes system of the BGK model instead of Euler's.
 int launch_euler(const bgk_problem& p, int batch, const double* V_in,
                  double* V_out, double t_span, int* n_sub, double* scratch,
-                 int* d_status, hipStream_t s, const double* E = nullptr);
+                 int* d_status, hipStream_t s, const double* E = nullptr,
+                 bool viscous = false);
 // Parareal initial coarse sweep and per-iteration correction sweep.
 int launch_pararealsweep_init(const bgk_problem& p, int n_slices,
                               const double* W0, double* U, double* Gc,
                               double t_span, double* scratch, int* d_status,
-                              hipStream_t s, const double* E = nullptr);
+                              hipStream_t s, const double* E = nullptr,
+                              bool viscous = false);
 int launch_parareal_sweep(const bgk_problem& p, int n_slices, int k,
                           const double* U_old, double* U_new, const double* VF,
                           double* Gc, double t_span, double* scratch,
                           double* d_err, int* d_status, hipStream_t s,
-                          const double* E = nullptr);
+                          const double* E = nullptr, bool viscous = false);
 int launch_prim_to_cons(const double* W, double* V, int n, hipStream_t s);
 
 // f_out = a g + F from buf[src_sel], or f_out = F (pure lift) if src_sel < 0.

@@ -22,7 +22,9 @@ struct CoarseGeo {
   int nx, bc;
   double dx, cfl, gamma;
   const double* E;  // exterior force at the x centres (null: none)
+  double eps;       // > 0: Navier-Stokes viscous and heat fluxes with this eps
 };
+
 
 __device__ __forceinline__ int gh(int i, int nx, int bc) {
   if (i < 0) return bc == 1 ? i + nx : 0;
@@ -61,20 +63,42 @@ __device__ double block_max(double v, double* red) {
   return m;
 }
 
+// Navier-Stokes face flux between cells a (left) and b (right).
+__device__ __forceinline__ void visc_flux(const CoarseGeo& G, const double* V,
+                                          const double* prim, int a, int b, double* D) {
+  const double* pa = prim + 4 * a;
+  const double* pb = prim + 4 * b;
+  const double mu = 0.5 * (V[5 * a] * pa[3] + V[5 * b] * pb[3]);
+  const double kappa = 2.5 * mu;
+  const double dux = pb[0] - pa[0], duy = pb[1] - pa[1], duz = pb[2] - pa[2];
+  const double uxf = 0.5 * (pa[0] + pb[0]), uyf = 0.5 * (pa[1] + pb[1]),
+               uzf = 0.5 * (pa[2] + pb[2]);
+  const double k = G.eps / G.dx;
+  D[0] = 0.0;
+  D[1] = k * (4.0 / 3.0) * mu * dux;
+  D[2] = k * mu * duy;
+  D[3] = k * mu * duz;
+  D[4] = k * (mu * ((4.0 / 3.0) * uxf * dux + uyf * duy + uzf * duz) + kappa * (pb[3] - pa[3]));
+}
+
 // Advances the state held in `cur` (5*nx doubles) over `span`, ping-ponging
-// with `nxt`; h (5*nx) and spd (nx) are flux scratch.  With an exterior force
-// each substep also adds the source (0, rho E, 0, 0, rho u_x E) of its
-// initial state.  Returns the buffer
-// that holds the final state (cur or nxt; identical in all threads) and the
-// substep count.  Ends with a barrier after the last write of the state.
+// with `nxt`; h (5*nx), spd (nx) and prim (4*nx) are flux scratch.  With an
+// exterior force each substep also adds the source (0, rho E, 0, 0,
+// rho u_x E) of its initial state.  With G.eps > 0 it is the Navier-Stokes
+// system of the BGK model (mu = rho theta, kappa = 5/2 rho theta): central
+// viscous and heat face fluxes, and the diffusive step limit
+// dt <= cfl dx^2 / (2 eps (5/3) max theta).  Returns the buffer that holds
+// the final state (cur or nxt; identical in all threads) and the substep
+// count.  Ends with a barrier after the last write of the state.
 __device__ double* euler_advance(const CoarseGeo& G, double* cur, double* nxt, double* h,
-                                 double* spd, double span, double* red, int* status,
-                                 int* nsub_out) {
+                                 double* spd, double* prim, double span, double* red,
+                                 int* status, int* nsub_out) {
   const int nx = G.nx;
+  const bool viscous = G.eps > 0.0;
   double t = 0.0;
   int nsub = 0;
   while (span - t > 1e-14 * span) {
-    double lmax = 0.0;
+    double lmax = 0.0, thmax = 0.0;
     int bad = 0;
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
       const double* V = cur + 5 * i;
@@ -92,6 +116,13 @@ __device__ double* euler_advance(const CoarseGeo& G, double* cur, double* nxt, d
       h[5 * i + 3] = rho * ux * uz;
       h[5 * i + 4] = ux * (V[4] + pr);
       lmax = fmax(lmax, spd[i]);
+      if (viscous) {
+        prim[4 * i + 0] = ux;
+        prim[4 * i + 1] = uy;
+        prim[4 * i + 2] = uz;
+        prim[4 * i + 3] = th;
+        thmax = fmax(thmax, th);
+      }
     }
     if (bad) *status = 1;
     // block_max has barriers for several waves; one wave takes a barrier of
@@ -103,6 +134,11 @@ __device__ double* euler_advance(const CoarseGeo& G, double* cur, double* nxt, d
       break;  // uniform: every thread sees the same smax and nsub
     }
     double dt = G.cfl * G.dx / smax;
+    if (viscous) {
+      const double tm = block_max(bad ? INFINITY : thmax, red);
+      const double dt_visc = G.cfl * G.dx * G.dx / (2.0 * G.eps * (5.0 / 3.0) * tm);
+      if (dt_visc < dt) dt = dt_visc;
+    }
     if (dt > span - t) dt = span - t;
     const double r = dt / G.dx;
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
@@ -115,6 +151,13 @@ __device__ double* euler_advance(const CoarseGeo& G, double* cur, double* nxt, d
         const double Hl = 0.5 * (h[5 * L + c] + h[5 * i + c]) -
                           0.5 * SL * (cur[5 * i + c] - cur[5 * L + c]);
         nxt[5 * i + c] = cur[5 * i + c] - r * (Hr - Hl);
+      }
+      if (viscous) {
+        double Dl[5], Dr[5];
+        visc_flux(G, cur, prim, L, i, Dl);
+        visc_flux(G, cur, prim, i, R, Dr);
+#pragma unroll
+        for (int c = 1; c < 5; ++c) nxt[5 * i + c] += r * (Dr[c] - Dl[c]);
       }
       if (G.E != nullptr) {
         const double Ei = G.E[i];
@@ -144,7 +187,8 @@ __device__ int euler_propagate(const CoarseGeo& G, const double* Vin,
   __syncthreads();
   int nsub = 0;
   const double* fin = euler_advance(G, scratch, scratch + 5 * nx, scratch + 10 * nx,
-                                    scratch + 15 * nx, span, red, status, &nsub);
+                                    scratch + 15 * nx, scratch + 16 * nx, span, red, status,
+                                    &nsub);
   for (int k = threadIdx.x; k < 5 * nx; k += blockDim.x) Vout[k] = fin[k];
   __syncthreads();
   return nsub;
@@ -162,7 +206,7 @@ __global__ __launch_bounds__(kCoarseBlock) void k_euler(
   __shared__ double red[kCoarseBlock / 64];
   const long long m = blockIdx.x;
   const long long sl = 5LL * G.nx;
-  double* sc = coarse_scratch(use_lds, scratch + m * 16LL * G.nx);
+  double* sc = coarse_scratch(use_lds, scratch + m * (long long)kCoarseScratch * G.nx);
   int n = euler_propagate(G, Vin + m * sl, Vout + m * sl, span, sc, red, status);
   if (nsub_out != nullptr && threadIdx.x == 0) nsub_out[m] = n;
 }
@@ -191,7 +235,8 @@ __global__ __launch_bounds__(kCoarseBlock) void k_parareal_init(
   }
   __syncthreads();
   for (int n = 1; n <= n_slices; ++n) {
-    double* fin = euler_advance(G, cur, oth, scratch + 10 * nx, scratch + 15 * nx, span, red,
+    double* fin = euler_advance(G, cur, oth, scratch + 10 * nx, scratch + 15 * nx,
+                                scratch + 16 * nx, span, red,
                                 status, nullptr);
     for (long long q = threadIdx.x; q < sl; q += blockDim.x) {
       U[n * sl + q] = fin[q];
@@ -236,7 +281,8 @@ __global__ __launch_bounds__(kCoarseBlock) void k_parareal_sweep(
         uo[r] = U_old[base + q];
       }
     }
-    double* fin = euler_advance(G, cur, oth, scratch + 10 * nx, scratch + 15 * nx, span, red,
+    double* fin = euler_advance(G, cur, oth, scratch + 10 * nx, scratch + 15 * nx,
+                                scratch + 16 * nx, span, red,
                                 status, nullptr);
     auto update = [&](long long q, double v, double c, double o) {
       const double g = fin[q];
@@ -264,7 +310,7 @@ __global__ __launch_bounds__(kCoarseBlock) void k_parareal_sweep(
   if (threadIdx.x == 0) *err = e;
 }
 
-CoarseGeo geo_of(const bgk_problem& p, const double* E) {
+CoarseGeo geo_of(const bgk_problem& p, const double* E, bool viscous) {
   CoarseGeo G;
   G.nx = p.nx;
   G.bc = p.bc;
@@ -272,6 +318,7 @@ CoarseGeo geo_of(const bgk_problem& p, const double* E) {
   G.cfl = p.cfl;
   G.gamma = p.sound_gamma;
   G.E = E;
+  G.eps = viscous ? p.eps : 0.0;
   return G;
 }
 
@@ -290,9 +337,9 @@ size_t coarse_lds(size_t doubles) {
 
 int launch_euler(const bgk_problem& p, int batch, const double* V_in,
                  double* V_out, double t_span, int* n_sub, double* scratch,
-                 int* d_status, hipStream_t s, const double* E) {
-  const size_t lds = coarse_lds(16 * (size_t)p.nx);
-  hipLaunchKernelGGL(k_euler, dim3(batch), dim3(coarse_threads(p.nx)), lds, s, geo_of(p, E),
+                 int* d_status, hipStream_t s, const double* E, bool viscous) {
+  const size_t lds = coarse_lds(kCoarseScratch * (size_t)p.nx);
+  hipLaunchKernelGGL(k_euler, dim3(batch), dim3(coarse_threads(p.nx)), lds, s, geo_of(p, E, viscous),
                      V_in, V_out, t_span, n_sub, scratch, d_status, lds ? 1 : 0);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
@@ -301,10 +348,10 @@ int launch_euler(const bgk_problem& p, int batch, const double* V_in,
 int launch_pararealsweep_init(const bgk_problem& p, int n_slices,
                               const double* W0, double* U, double* Gc,
                               double t_span, double* scratch, int* d_status,
-                              hipStream_t s, const double* E) {
-  const size_t lds = coarse_lds(16 * (size_t)p.nx);
+                              hipStream_t s, const double* E, bool viscous) {
+  const size_t lds = coarse_lds(kCoarseScratch * (size_t)p.nx);
   hipLaunchKernelGGL(k_parareal_init, dim3(1), dim3(coarse_threads(p.nx)), lds, s,
-                     geo_of(p, E), n_slices, W0, U, Gc, t_span, scratch, d_status,
+                     geo_of(p, E, viscous), n_slices, W0, U, Gc, t_span, scratch, d_status,
                      lds ? 1 : 0);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
@@ -313,20 +360,21 @@ int launch_pararealsweep_init(const bgk_problem& p, int n_slices,
 int launch_parareal_sweep(const bgk_problem& p, int n_slices, int k,
                           const double* U_old, double* U_new, const double* VF,
                           double* Gc, double t_span, double* scratch,
-                          double* d_err, int* d_status, hipStream_t s, const double* E) {
-  const size_t lds = coarse_lds(16 * (size_t)p.nx);
+                          double* d_err, int* d_status, hipStream_t s, const double* E,
+                          bool viscous) {
+  const size_t lds = coarse_lds(kCoarseScratch * (size_t)p.nx);
   const int threads = coarse_threads(p.nx);
   const long long per = (5LL * p.nx + threads - 1) / threads;  // entries per thread
   if (per <= 5) {
-    hipLaunchKernelGGL(k_parareal_sweep<5>, dim3(1), dim3(threads), lds, s, geo_of(p, E),
+    hipLaunchKernelGGL(k_parareal_sweep<5>, dim3(1), dim3(threads), lds, s, geo_of(p, E, viscous),
                        n_slices, k, U_old, U_new, VF, Gc, t_span, scratch, d_err, d_status,
                        lds ? 1 : 0);
   } else if (per <= 10) {
-    hipLaunchKernelGGL(k_parareal_sweep<10>, dim3(1), dim3(threads), lds, s, geo_of(p, E),
+    hipLaunchKernelGGL(k_parareal_sweep<10>, dim3(1), dim3(threads), lds, s, geo_of(p, E, viscous),
                        n_slices, k, U_old, U_new, VF, Gc, t_span, scratch, d_err, d_status,
                        lds ? 1 : 0);
   } else {
-    hipLaunchKernelGGL(k_parareal_sweep<0>, dim3(1), dim3(threads), lds, s, geo_of(p, E),
+    hipLaunchKernelGGL(k_parareal_sweep<0>, dim3(1), dim3(threads), lds, s, geo_of(p, E, viscous),
                        n_slices, k, U_old, U_new, VF, Gc, t_span, scratch, d_err, d_status,
                        lds ? 1 : 0);
   }
