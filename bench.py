@@ -115,21 +115,27 @@ def parareal_speedup(torch, bgk, wl, reps=5):
             ts.append(time.perf_counter() - t0)
         return out, float(np.median(ts))
 
-    cases = [(wk.name, wk.problem, wk.W0, wk.n_slices, wk.T, None)
-             for wk in (wl.c1_sod_small(),
-                        wl.c2_smooth_periodic(eps=1e-4, nx=64, nv=16, n_slices=16))]
+    sod = wl.c1_sod_small()
+    s4 = wl.c2_smooth_periodic(eps=1e-4, nx=64, nv=16, n_slices=16)
+    s2 = wl.c2_smooth_periodic(eps=1e-2, nx=64, nv=16, n_slices=16)
     fk = wl.c6_two_beam_force()
-    cases.append((fk.name, fk.problem, fk.U0(), fk.n_slices, fk.T, fk.E))
+    cases = [(sod.name, sod.problem, sod.W0, sod.n_slices, sod.T, None, "euler"),
+             (s4.name, s4.problem, s4.W0, s4.n_slices, s4.T, None, "euler"),
+             (s4.name, s4.problem, s4.W0, s4.n_slices, s4.T, None, "cns"),
+             (s2.name, s2.problem, s2.W0, s2.n_slices, s2.T, None, "euler"),
+             (s2.name, s2.problem, s2.W0, s2.n_slices, s2.T, None, "cns"),
+             (fk.name, fk.problem, fk.U0(), fk.n_slices, fk.T, fk.E, "euler")]
     out = []
-    for name, p, W0np, N, T, E in cases:
+    for name, p, W0np, N, T, E, coarse in cases:
         W0 = torch.from_numpy(W0np).cuda()
         ref, t_serial = timed(lambda: bgk.serial_fine(p, W0, N, T, E=E))
         ref = ref.cpu().numpy()
-        res = {"workload": name, "slices": N, "serial_fine_ms": round(t_serial * 1e3, 4),
-               "K": []}
+        res = {"workload": name, "coarse": coarse, "slices": N,
+               "serial_fine_ms": round(t_serial * 1e3, 4), "K": []}
         chosen = None
         for K in range(1, N + 1):
-            (V, err, kd), t_par = timed(lambda: bgk.parareal_iterate(p, W0, N, T, K, 0.0, E=E))
+            (V, err, kd), t_par = timed(lambda: bgk.parareal_iterate(p, W0, N, T, K, 0.0, E=E,
+                                                                     coarse=coarse))
             e = float(np.max(np.abs(V.cpu().numpy() - ref)))
             res["K"].append({"K": K, "ms": round(t_par * 1e3, 4), "err_vs_fine": e,
                              "speedup": round(t_serial / t_par, 3)})
