@@ -76,6 +76,11 @@ def lib():
                                                   C.c_int32, C.c_double, D, D, I],
             "bgk_oracle_serial_fine_force": [P, D, D, C.c_int32, C.c_double, D],
             "bgk_oracle_cns_coarse_step": [P, D, D, D, C.c_double, I],
+            "bgk_oracle_lift_ce": [P, D, D],
+            "bgk_oracle_fine_propagate_moments_opts": [P, D, C.c_int32, D, D, C.c_double],
+            "bgk_oracle_parareal_iterate_opts": [P, D, C.c_int32, C.c_int32, D, C.c_int32,
+                                                 C.c_double, C.c_int32, C.c_double, D, D, I],
+            "bgk_oracle_serial_fine_opts": [P, D, C.c_int32, D, C.c_int32, C.c_double, D],
             "bgk_oracle_parareal_iterate_cns": [P, D, D, C.c_int32, C.c_double, C.c_int32,
                                                 C.c_double, D, D, I],
         }
@@ -239,6 +244,50 @@ def euler_coarse_step(p, V, t_span: float, E=None):
                                                       _d(out), t_span, C.byref(n))
     _chk(rc, "euler")
     return out, n.value
+
+
+def lift_ce(p, W) -> np.ndarray:
+    """Lifting of order one (first Chapman-Enskog correction)."""
+    W = _arr(W)
+    f = np.empty((p.nx, p.nv[0] * p.nv[1] * p.nv[2]))
+    _chk(lib().bgk_oracle_lift_ce(C.byref(_prob(p)), _d(W), _d(f)), "lift_ce")
+    return f
+
+
+COARSE = {"euler": 0, "cns": 1}
+
+
+def fine_propagate_moments_opts(p, V, t_span: float, E=None, lift_order: int = 0):
+    V = _arr(V)
+    out = np.empty_like(V)
+    Ea = _force(p, E) if E is not None else None
+    _chk(lib().bgk_oracle_fine_propagate_moments_opts(
+        C.byref(_prob(p)), _d(Ea) if Ea is not None else None, lift_order, _d(V), _d(out),
+        t_span), "PFL_opts")
+    return out
+
+
+def parareal_iterate_opts(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=None,
+                          coarse: str = "euler", lift_order: int = 0):
+    W0 = _arr(W0)
+    V = np.empty((n_slices + 1, p.nx, 5))
+    err = np.zeros(max(k_max, 1))
+    kd = C.c_int32()
+    Ea = _force(p, E) if E is not None else None
+    _chk(lib().bgk_oracle_parareal_iterate_opts(
+        C.byref(_prob(p)), _d(Ea) if Ea is not None else None, COARSE[coarse], lift_order,
+        _d(W0), n_slices, T, k_max, tol, _d(V), _d(err), C.byref(kd)), "parareal_opts")
+    return V, err[:kd.value].copy(), kd.value
+
+
+def serial_fine_opts(p, W0, n_slices: int, T: float, E=None, lift_order: int = 0):
+    W0 = _arr(W0)
+    V = np.empty((n_slices + 1, p.nx, 5))
+    Ea = _force(p, E) if E is not None else None
+    _chk(lib().bgk_oracle_serial_fine_opts(
+        C.byref(_prob(p)), _d(Ea) if Ea is not None else None, lift_order, _d(W0), n_slices,
+        T, _d(V)), "serial_opts")
+    return V
 
 
 def cns_coarse_step(p, V, t_span: float, E=None):

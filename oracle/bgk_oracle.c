@@ -169,6 +169,50 @@ int bgk_oracle_lift(const bgk_oracle_problem* p, const double* W, double* f) {
   return bad ? ORACLE_E_NONPHYSICAL : ORACLE_OK;
 }
 
+/* Lifting of order one (Definition 3 with L = 1) for the BGK operator with
+ * tau = 1: the first Chapman-Enskog correction (the perturbation whose stress
+ * and heat flux are the Navier-Stokes ones, mu = rho theta, kappa = 5/2 rho
+ * theta),
+ *   f = M[rho,u,theta] (1 - eps P),  c = v - u,
+ *   P = (u_x'/theta)(c_x^2 - |c|^2/3) + (u_y'/theta) c_x c_y
+ *       + (u_z'/theta) c_x c_z + (theta'/theta) c_x (|c|^2/(2 theta) - 5/2),
+ * ' the x-derivative by central differences of the primitive moments, with
+ * the boundary condition's ghost cells.  Needs a finite eps. */
+int bgk_oracle_lift_ce(const bgk_oracle_problem* p, const double* W, double* f) {
+  if (check_problem(p) || !W || !f || !isfinite(p->eps)) return ORACLE_E_INVALID;
+  const long nv3 = nv3_of(p);
+  const double dx = dx_of(p);
+  int bad = 0;
+  for (int i = 0; i < p->nx; ++i) {
+    const double* w = W + 5 * (long)i;
+    if (!physical(w[0], w[4]) || !isfinite(w[1]) || !isfinite(w[2]) || !isfinite(w[3]))
+      bad = 1;
+  }
+  if (bad) return ORACLE_E_NONPHYSICAL;
+#pragma omp parallel for num_threads(NT)
+  for (int i = 0; i < p->nx; ++i) {
+    const double* w = W + 5 * (long)i;
+    const double* wl = W + 5 * (long)ghost(p, i - 1);
+    const double* wr = W + 5 * (long)ghost(p, i + 1);
+    double u[3] = {w[1], w[2], w[3]};
+    const double th = w[4];
+    double d[4];  /* u_x', u_y', u_z', theta' */
+    for (int c = 0; c < 4; ++c) d[c] = (wr[1 + c] - wl[1 + c]) / (2.0 * dx);
+    long j = 0;
+    for (int jx = 0; jx < p->nv[0]; ++jx)
+      for (int jy = 0; jy < p->nv[1]; ++jy)
+        for (int jz = 0; jz < p->nv[2]; ++jz, ++j) {
+          double v[3] = {vc(p, 0, jx), vc(p, 1, jy), vc(p, 2, jz)};
+          double c[3] = {v[0] - u[0], v[1] - u[1], v[2] - u[2]};
+          double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+          double P = d[0] / th * (c[0] * c[0] - c2 / 3.0) + d[1] / th * c[0] * c[1] +
+                     d[2] / th * c[0] * c[2] + d[3] / th * c[0] * (c2 / (2.0 * th) - 2.5);
+          f[(long)i * nv3 + j] = maxwellian(w[0], u, th, v) * (1.0 - p->eps * P);
+        }
+  }
+  return ORACLE_OK;
+}
+
 /* ------------------------------------------------------------- moments -- */
 /* Discrete projection operator (Section 3.3, Definition 1), first-order
  * quadrature, literal two-pass form:
@@ -419,7 +463,7 @@ static void conserved_to_primitive(const double* V5, double* W5) {
 }
 
 /* Steps 5-7 of Algorithm 2: lifting, kinetic propagation, projection. */
-static int propagate_impl(const bgk_oracle_problem* p, const double* E,
+static int propagate_impl(const bgk_oracle_problem* p, const double* E, int lift_order,
                           const double* V_in, double* V_out, double t_span) {
   if (check_problem(p) || !V_in || !V_out) return ORACLE_E_INVALID;
   const size_t n = (size_t)p->nx * nv3_of(p);
@@ -431,7 +475,7 @@ static int propagate_impl(const bgk_oracle_problem* p, const double* E,
     return ORACLE_E_INVALID;
   }
   for (int i = 0; i < p->nx; ++i) conserved_to_primitive(V_in + 5 * i, W + 5 * i);
-  int rc = bgk_oracle_lift(p, W, f);
+  int rc = lift_order == 1 ? bgk_oracle_lift_ce(p, W, f) : bgk_oracle_lift(p, W, f);
   if (rc == ORACLE_OK) rc = fine_step_impl(p, E, f, f, t_span, NULL);
   if (rc == ORACLE_OK) rc = bgk_oracle_moments(p, f, V_out, NULL);
   free(W);
@@ -442,14 +486,14 @@ static int propagate_impl(const bgk_oracle_problem* p, const double* E,
 int bgk_oracle_fine_propagate_moments(const bgk_oracle_problem* p,
                                       const double* V_in, double* V_out,
                                       double t_span) {
-  return propagate_impl(p, NULL, V_in, V_out, t_span);
+  return propagate_impl(p, NULL, 0, V_in, V_out, t_span);
 }
 
 int bgk_oracle_fine_propagate_moments_force(const bgk_oracle_problem* p,
                                             const double* E, const double* V_in,
                                             double* V_out, double t_span) {
   if (!E) return ORACLE_E_INVALID;
-  return propagate_impl(p, E, V_in, V_out, t_span);
+  return propagate_impl(p, E, 0, V_in, V_out, t_span);
 }
 
 /* ------------------------------------------------------------ coarse G -- */
@@ -647,7 +691,7 @@ static void primitive_to_conserved(const double* W5, double* V5) {
  *     err_k = max_{n,i,c} |U^{n,k+1} - U^{n,k}|;  stop at K or err < tol.
  * The jump loop is the parallel one (Section 2.2 and Section 4). */
 static int parareal_impl(const bgk_oracle_problem* p, const double* E, int viscous,
-                         const double* W0, int32_t n_slices, double T,
+                         int lift_order, const double* W0, int32_t n_slices, double T,
                          int32_t k_max, double tol, double* V_out,
                          double* err_hist, int32_t* k_done) {
   if (check_problem(p) || !W0 || !V_out || n_slices < 1 || k_max < 0 ||
@@ -674,7 +718,7 @@ static int parareal_impl(const bgk_oracle_problem* p, const double* E, int visco
     for (int n = k + 1; n <= n_slices; ++n) {
       double* Fv = (double*)malloc(sl * sizeof(double));
       double* Gv = (double*)malloc(sl * sizeof(double));
-      int r1 = propagate_impl(p, E, U + sl * (n - 1), Fv, dT);
+      int r1 = propagate_impl(p, E, lift_order, U + sl * (n - 1), Fv, dT);
       int r2 = r1 ? r1 : coarse_impl(p, E, viscous, U + sl * (n - 1), Gv, dT, NULL);
       if (r1 || r2) bad = r1 ? r1 : r2;
       else
@@ -715,7 +759,7 @@ int bgk_oracle_parareal_iterate(const bgk_oracle_problem* p, const double* W0,
                                 int32_t n_slices, double T, int32_t k_max,
                                 double tol, double* V_out, double* err_hist,
                                 int32_t* k_done) {
-  return parareal_impl(p, NULL, 0, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
+  return parareal_impl(p, NULL, 0, 0, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
 }
 
 int bgk_oracle_parareal_iterate_force(const bgk_oracle_problem* p, const double* E,
@@ -723,25 +767,26 @@ int bgk_oracle_parareal_iterate_force(const bgk_oracle_problem* p, const double*
                                       int32_t k_max, double tol, double* V_out,
                                       double* err_hist, int32_t* k_done) {
   if (!E) return ORACLE_E_INVALID;
-  return parareal_impl(p, E, 0, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
+  return parareal_impl(p, E, 0, 0, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
 }
 
 int bgk_oracle_parareal_iterate_cns(const bgk_oracle_problem* p, const double* E,
                                     const double* W0, int32_t n_slices, double T,
                                     int32_t k_max, double tol, double* V_out,
                                     double* err_hist, int32_t* k_done) {
-  return parareal_impl(p, E, 1, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
+  return parareal_impl(p, E, 1, 0, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
 }
 
 /* The fine reference that parareal converges to: U^n = P F L(U^{n-1}). */
-static int serial_impl(const bgk_oracle_problem* p, const double* E,
+static int serial_impl(const bgk_oracle_problem* p, const double* E, int lift_order,
                        const double* W0, int32_t n_slices, double T, double* V_out) {
   if (check_problem(p) || !W0 || !V_out || n_slices < 1 || !(T > 0.0))
     return ORACLE_E_INVALID;
   const size_t sl = 5 * (size_t)p->nx;
   for (int i = 0; i < p->nx; ++i) primitive_to_conserved(W0 + 5 * i, V_out + 5 * i);
   for (int n = 1; n <= n_slices; ++n) {
-    int rc = propagate_impl(p, E, V_out + sl * (n - 1), V_out + sl * n, T / n_slices);
+    int rc = propagate_impl(p, E, lift_order, V_out + sl * (n - 1), V_out + sl * n,
+                            T / n_slices);
     if (rc) return rc;
   }
   return ORACLE_OK;
@@ -749,14 +794,14 @@ static int serial_impl(const bgk_oracle_problem* p, const double* E,
 
 int bgk_oracle_serial_fine(const bgk_oracle_problem* p, const double* W0,
                            int32_t n_slices, double T, double* V_out) {
-  return serial_impl(p, NULL, W0, n_slices, T, V_out);
+  return serial_impl(p, NULL, 0, W0, n_slices, T, V_out);
 }
 
 int bgk_oracle_serial_fine_force(const bgk_oracle_problem* p, const double* E,
                                  const double* W0, int32_t n_slices, double T,
                                  double* V_out) {
   if (!E) return ORACLE_E_INVALID;
-  return serial_impl(p, E, W0, n_slices, T, V_out);
+  return serial_impl(p, E, 0, W0, n_slices, T, V_out);
 }
 
 /* --------------------------------------------------------------- adjoint -- */
@@ -926,4 +971,31 @@ int bgk_oracle_lift_adjoint_rho(const bgk_oracle_problem* p, const double* W,
     rhobar[i] = s;
   }
   return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------- options -- */
+int bgk_oracle_fine_propagate_moments_opts(const bgk_oracle_problem* p,
+                                           const double* E, int32_t lift_order,
+                                           const double* V_in, double* V_out,
+                                           double t_span) {
+  if (lift_order != 0 && lift_order != 1) return ORACLE_E_INVALID;
+  return propagate_impl(p, E, lift_order, V_in, V_out, t_span);
+}
+
+int bgk_oracle_parareal_iterate_opts(const bgk_oracle_problem* p, const double* E,
+                                     int32_t coarse, int32_t lift_order,
+                                     const double* W0, int32_t n_slices, double T,
+                                     int32_t k_max, double tol, double* V_out,
+                                     double* err_hist, int32_t* k_done) {
+  if ((coarse != 0 && coarse != 1) || (lift_order != 0 && lift_order != 1))
+    return ORACLE_E_INVALID;
+  return parareal_impl(p, E, coarse, lift_order, W0, n_slices, T, k_max, tol, V_out,
+                       err_hist, k_done);
+}
+
+int bgk_oracle_serial_fine_opts(const bgk_oracle_problem* p, const double* E,
+                                int32_t lift_order, const double* W0,
+                                int32_t n_slices, double T, double* V_out) {
+  if (lift_order != 0 && lift_order != 1) return ORACLE_E_INVALID;
+  return serial_impl(p, E, lift_order, W0, n_slices, T, V_out);
 }

@@ -160,6 +160,30 @@ int bgk_oracle_parareal_iterate_cns(const bgk_oracle_problem* p, const double* E
                                     int32_t k_max, double tol, double* V_out,
                                     double* err_hist, int32_t* k_done);
 
+/* Lifting of order one (Definition 3, L = 1): Maxwellian times
+ * (1 - eps P), P the first Chapman-Enskog correction of the BGK operator
+ * (its stress and heat flux are the Navier-Stokes ones with mu = rho theta,
+ * kappa = 5/2 rho theta), x-derivatives of the primitive moments W by central
+ * differences with the boundary condition's ghost cells.  Finite eps only. */
+int bgk_oracle_lift_ce(const bgk_oracle_problem* p, const double* W, double* f);
+
+/* General forms: E (host [nx]) may be NULL; coarse 0 = Euler, 1 =
+ * Navier-Stokes; lift_order 0 = Maxwellian (Definition 2), 1 = the lifting
+ * above.  The serial fine chain with the same lift_order is parareal's fixed
+ * point. */
+int bgk_oracle_fine_propagate_moments_opts(const bgk_oracle_problem* p,
+                                           const double* E, int32_t lift_order,
+                                           const double* V_in, double* V_out,
+                                           double t_span);
+int bgk_oracle_parareal_iterate_opts(const bgk_oracle_problem* p, const double* E,
+                                     int32_t coarse, int32_t lift_order,
+                                     const double* W0, int32_t n_slices, double T,
+                                     int32_t k_max, double tol, double* V_out,
+                                     double* err_hist, int32_t* k_done);
+int bgk_oracle_serial_fine_opts(const bgk_oracle_problem* p, const double* E,
+                                int32_t lift_order, const double* W0,
+                                int32_t n_slices, double T, double* V_out);
+
 void bgk_oracle_set_threads(int n);
 int bgk_oracle_get_threads(void);
 

@@ -142,3 +142,23 @@ def cns_substep(p, V, dt, E=None):
     D *= p.eps / dx
     out = out + dt / dx * (D[1:] - D[:-1])
     return out, smax, th.max()
+
+
+def lift_ce(p, W):
+    """First-order Chapman-Enskog lifting: the Maxwellian of W times
+    1 - eps P(c), the x-derivatives of u and theta by central differences
+    (np.roll for periodic, edge padding for Neumann)."""
+    if p.bc == 1:
+        Wl, Wr = np.roll(W, 1, axis=0), np.roll(W, -1, axis=0)
+    else:
+        Wp = np.pad(W, ((1, 1), (0, 0)), mode="edge")
+        Wl, Wr = Wp[:-2], Wp[2:]
+    dx = (p.x_hi - p.x_lo) / p.nx
+    g = (Wr - Wl) / (2 * dx)
+    VX, VY, VZ = vgrid(p)
+    th = W[:, 4:5]
+    cx, cy, cz = VX[None] - W[:, 1:2], VY[None] - W[:, 2:3], VZ[None] - W[:, 3:4]
+    c2 = cx ** 2 + cy ** 2 + cz ** 2
+    P = (g[:, 1:2] * (cx ** 2 - c2 / 3) + g[:, 2:3] * cx * cy + g[:, 3:4] * cx * cz +
+         g[:, 4:5] * cx * (c2 / (2 * th) - 2.5)) / th
+    return maxwell(p, W[:, 0], W[:, 1:4], W[:, 4]) * (1 - p.eps * P)

@@ -812,6 +812,78 @@ class TestNavierStokesCoarse:
         assert all(err[i + 1] < err[i] for i in range(len(err) - 2))
 
 
+class TestChapmanEnskogLift:
+    """Lifting of order one (Definition 3): the Maxwellian times 1 - eps P with
+    P the first Chapman-Enskog correction of the BGK operator."""
+
+    @staticmethod
+    def _smooth(p, seed=11):
+        rng = np.random.default_rng(seed)
+        x = p.x_centres()
+        a = rng.uniform(-1, 1, 5)
+        return np.column_stack([1 + 0.2 * np.sin(2 * np.pi * x + a[0]),
+                                0.3 * np.sin(2 * np.pi * x + a[1]),
+                                0.2 * np.cos(2 * np.pi * x + a[2]),
+                                0.1 * np.sin(4 * np.pi * x + a[3]),
+                                1 + 0.2 * np.cos(2 * np.pi * x + a[4])])
+
+    def test_uniform_state_is_the_maxwellian(self):
+        p = wl.small_problem(nx=6, bc=wl.BC_NEUMANN, eps=0.3)
+        W = np.tile([1.2, 0.3, -0.2, 0.1, 0.9], (p.nx, 1))
+        assert np.array_equal(oracle.lift_ce(p, W), oracle.lift(p, W))
+
+    def test_moments_are_those_of_the_maxwellian(self):
+        # the correction has no mass, momentum or energy (resolved grid)
+        p = wl.Problem(nx=16, nv=(40, 40, 40), v_lo=(-10,) * 3, v_hi=(10,) * 3,
+                       bc=wl.BC_PERIODIC, eps=0.05)
+        W = self._smooth(p)
+        V1, _ = oracle.moments(p, oracle.lift_ce(p, W))
+        V0, _ = oracle.moments(p, oracle.lift(p, W))
+        assert np.max(np.abs(V1 - V0)) < 1e-12
+
+    def test_stress_and_heat_flux_are_navier_stokes(self):
+        # Chapman-Enskog: P_xx - p = -eps (4/3) mu u_x', P_xy = -eps mu u_y',
+        # P_xz = -eps mu u_z', q_x = -eps kappa theta', mu = rho theta,
+        # kappa = 5/2 rho theta (the BGK transport coefficients)
+        p = wl.Problem(nx=16, nv=(40, 40, 40), v_lo=(-10,) * 3, v_hi=(10,) * 3,
+                       bc=wl.BC_PERIODIC, eps=0.05)
+        W = self._smooth(p)
+        f1 = oracle.lift_ce(p, W)
+        f0 = oracle.lift(p, W)
+        VX, VY, VZ = npr.vgrid(p)
+        w = npr.dv3(p)
+        dx = 1.0 / p.nx
+        g = (np.roll(W, -1, 0) - np.roll(W, 1, 0)) / (2 * dx)
+        cx, cy, cz = VX[None] - W[:, 1:2], VY[None] - W[:, 2:3], VZ[None] - W[:, 3:4]
+        mu = W[:, 0] * W[:, 4]
+        eps = p.eps
+        Pxx = ((f1 - f0) * cx ** 2).sum(1) * w
+        Pxy = (f1 * cx * cy).sum(1) * w
+        Pxz = (f1 * cx * cz).sum(1) * w
+        qx = 0.5 * (f1 * cx * (cx ** 2 + cy ** 2 + cz ** 2)).sum(1) * w
+        scale = eps * np.max(mu * np.abs(g[:, 1:5]).max(1))
+        assert np.max(np.abs(Pxx + eps * 4 / 3 * mu * g[:, 1])) < 1e-10 * scale
+        assert np.max(np.abs(Pxy + eps * mu * g[:, 2])) < 1e-10 * scale
+        assert np.max(np.abs(Pxz + eps * mu * g[:, 3])) < 1e-10 * scale
+        assert np.max(np.abs(qx + eps * 2.5 * mu * g[:, 4])) < 1e-10 * scale
+
+    @pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_PERIODIC])
+    def test_matches_numpy(self, bc):
+        p = wl.Problem(nx=7, nv=(6, 5, 4), v_lo=(-5, -4, -4), v_hi=(5, 4, 4.5), bc=bc,
+                       eps=0.1)
+        W = self._smooth(p, 12)
+        assert relmax(oracle.lift_ce(p, W), npr.lift_ce(p, W)) < 1e-14
+
+    def test_parareal_k_equals_n_with_order_one_lift(self):
+        wk = wl.c2_smooth_periodic(eps=1e-2, nx=12, nv=8, n_slices=4)
+        p = wk.problem
+        ref = oracle.serial_fine_opts(p, wk.W0, 4, wk.T, lift_order=1)
+        V, err, kd = oracle.parareal_iterate_opts(p, wk.W0, 4, wk.T, 4, 0.0, coarse="cns",
+                                                  lift_order=1)
+        assert kd == 4 and np.max(np.abs(V - ref)) < 1e-13
+        assert np.max(np.abs(ref - oracle.serial_fine(p, wk.W0, 4, wk.T))) > 1e-8
+
+
 class TestErrors:
     def test_invalid_arguments(self):
         from dataclasses import replace
