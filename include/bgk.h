@@ -232,6 +232,50 @@ int parareal_iterate_cns(const bgk_problem* prob, const double* E, double e_max,
                          double* err_hist, int32_t* k_done, void* ws,
                          size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------ general options --
+ * Lifting of order one (Definition 3 with L = 1) for the BGK operator with
+ * relaxation rate 1/eps:
+ *   f = M[rho,u,theta] (1 - eps P),  c = v - u,
+ *   P = (u_x'/theta)(c_x^2 - |c|^2/3) + (u_y'/theta) c_x c_y
+ *       + (u_z'/theta) c_x c_z + (theta'/theta) c_x (|c|^2/(2 theta) - 5/2),
+ * the first Chapman-Enskog correction (its stress and heat flux are the
+ * Navier-Stokes ones with mu = rho theta, kappa = 5/2 rho theta); x-derivatives
+ * of the primitive moments by central differences with the boundary
+ * condition's ghost cells.  bgk_lift_ce: [device] W [nx][5] primitive, f
+ * [nx][nv3] output; BGK_OP_LIFT workspace; BGK_E_INVALID for an infinite eps.
+ *
+ * bgk_options selects, for the propagate / parareal / serial-fine calls, an
+ * exterior force (E device [nx] or NULL, e_max as in the _force calls), the
+ * coarse model (BGK_COARSE_EULER: Section 3.2; BGK_COARSE_NAVIER_STOKES: the
+ * Navier-Stokes model above) and the lifting order (0: Definition 2's
+ * Maxwellian; 1: the order-one lifting, which the fine propagator then starts
+ * from; the serial fine chain with the same order is parareal's fixed point).
+ * A NULL options pointer means no force, Euler, order 0.  Workspaces and the
+ * other arguments as bgk_fine_propagate_moments, parareal_iterate and
+ * bgk_serial_fine. */
+enum { BGK_COARSE_EULER = 0, BGK_COARSE_NAVIER_STOKES = 1 };
+typedef struct {
+  const double* E;    /* exterior force at the x centres, or NULL */
+  double e_max;       /* Rusanov coefficient >= max |E_i| (ignored without E) */
+  int32_t coarse;     /* BGK_COARSE_EULER or BGK_COARSE_NAVIER_STOKES */
+  int32_t lift_order; /* 0 or 1 */
+} bgk_options;
+
+int bgk_lift_ce(const bgk_problem* prob, const double* W, double* f, void* ws,
+                size_t ws_bytes, void* stream);
+int bgk_fine_propagate_moments_opts(const bgk_problem* prob, const bgk_options* opts,
+                                    int32_t batch, const double* V_in,
+                                    double* V_out, double t_span, void* ws,
+                                    size_t ws_bytes, void* stream);
+int parareal_iterate_opts(const bgk_problem* prob, const bgk_options* opts,
+                          const double* W0, int32_t n_slices, double T,
+                          int32_t k_max, double tol, double* V_out,
+                          double* err_hist, int32_t* k_done, void* ws,
+                          size_t ws_bytes, void* stream);
+int bgk_serial_fine_opts(const bgk_problem* prob, const bgk_options* opts,
+                         const double* W0, int32_t n_slices, double T,
+                         double* V_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Adjoint of n_steps IMEX steps of size dt (the transpose of the step's
  * Jacobian: transposed upwind stencil, adjoint of moments -> Maxwellian ->
  * relaxation).  [device] f_ckpt [ceil(n_steps/ckpt_every)][nx][nv3] forward

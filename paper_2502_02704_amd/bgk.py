@@ -32,8 +32,17 @@ EXPORTS = [
     "bgk_set_graphs", "bgk_set_step_fusion", "bgk_n_steps_force", "bgk_fine_steps_force",
     "bgk_fine_step_force", "bgk_fine_propagate_moments_force", "euler_coarse_step_force",
     "parareal_iterate_force", "bgk_serial_fine_force", "euler_coarse_step_cns",
-    "parareal_iterate_cns",
+    "parareal_iterate_cns", "bgk_lift_ce", "bgk_fine_propagate_moments_opts",
+    "parareal_iterate_opts", "bgk_serial_fine_opts",
 ]
+
+
+class _Options(C.Structure):
+    _fields_ = [("E", C.c_void_p), ("e_max", C.c_double), ("coarse", C.c_int32),
+                ("lift_order", C.c_int32)]
+
+
+COARSE = {"euler": 0, "cns": 1}
 
 
 class BgkError(RuntimeError):
@@ -106,6 +115,14 @@ def load_library(path: str = LIB_PATH):
         "euler_coarse_step_cns": (C.c_int, [P, V, C.c_int32, V, V, C.c_double, V, V, Z, V]),
         "parareal_iterate_cns": (C.c_int, [P, V, C.c_double, V, C.c_int32, C.c_double,
                                            C.c_int32, C.c_double, V, D, I, V, Z, V]),
+        "bgk_lift_ce": (C.c_int, [P, V, V, V, Z, V]),
+        "bgk_fine_propagate_moments_opts": (C.c_int, [P, C.POINTER(_Options), C.c_int32, V,
+                                                      V, C.c_double, V, Z, V]),
+        "parareal_iterate_opts": (C.c_int, [P, C.POINTER(_Options), V, C.c_int32,
+                                            C.c_double, C.c_int32, C.c_double, V, D, I, V,
+                                            Z, V]),
+        "bgk_serial_fine_opts": (C.c_int, [P, C.POINTER(_Options), V, C.c_int32, C.c_double,
+                                           V, V, Z, V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -244,6 +261,31 @@ def lift(p, W) -> torch.Tensor:
     return f
 
 
+def lift_ce(p, W) -> torch.Tensor:
+    """Lifting of order one (first Chapman-Enskog correction) of primitive W."""
+    L = _gpu_lib()
+    W = _f64(W)
+    f = torch.empty((p.nx, p.nv[0] * p.nv[1] * p.nv[2]), dtype=torch.float64, device="cuda")
+    w = workspace(p, OP_LIFT)
+    _check(L.bgk_lift_ce(C.byref(problem_struct(p)), _dev(W, "W"), _dev(f, "f"),
+                         w.data_ptr(), w.numel(), _stream()), "bgk_lift_ce")
+    return f
+
+
+def _options(p, E, coarse: str, lift_order: int):
+    """(ctypes options, device force tensor kept alive by the caller)."""
+    if coarse not in COARSE:
+        raise ValueError("coarse must be 'euler' or 'cns'")
+    o = _Options()
+    Ed = None
+    if E is not None:
+        Ed, o.e_max = _force(p, E)
+        o.E = Ed.data_ptr()
+    o.coarse = COARSE[coarse]
+    o.lift_order = int(lift_order)
+    return o, Ed
+
+
 def moments(p, f: torch.Tensor):
     L = _gpu_lib()
     V = torch.empty((p.nx, 5), dtype=torch.float64, device="cuda")
@@ -318,15 +360,22 @@ def fine_step_batched(probs: Sequence, fs: Sequence[torch.Tensor], spans: Sequen
     return outs, list(steps)
 
 
-def fine_propagate_moments(p, V_in: torch.Tensor, t_span: float, E=None) -> torch.Tensor:
-    """Batched P F L over the leading dimension of V_in ([B][nx][5] conserved)."""
+def fine_propagate_moments(p, V_in: torch.Tensor, t_span: float, E=None,
+                           lift_order: int = 0) -> torch.Tensor:
+    """Batched P F L over the leading dimension of V_in ([B][nx][5] conserved);
+    lift_order 1 lifts with the first Chapman-Enskog correction."""
     L = _gpu_lib()
     V_in = V_in.contiguous()
     B = V_in.shape[0] if V_in.dim() == 3 else 1
     out = torch.empty_like(V_in)
     w = workspace(p, OP_PROPAGATE, B)
     ps = C.byref(problem_struct(p))
-    if E is None:
+    if lift_order != 0:
+        o, Ed = _options(p, E, "euler", lift_order)
+        rc = L.bgk_fine_propagate_moments_opts(ps, C.byref(o), B, _dev(V_in, "V_in"),
+                                               _dev(out, "V_out"), t_span, w.data_ptr(),
+                                               w.numel(), _stream())
+    elif E is None:
         rc = L.bgk_fine_propagate_moments(ps, B, _dev(V_in, "V_in"), _dev(out, "V_out"),
                                           t_span, w.data_ptr(), w.numel(), _stream())
     else:
@@ -368,8 +417,9 @@ def euler_coarse_step(p, V: torch.Tensor, t_span: float, E=None, coarse: str = "
 
 
 def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=None,
-                     coarse: str = "euler"):
-    """Algorithm 2; coarse = "euler" or "cns" (Navier-Stokes coarse propagator)."""
+                     coarse: str = "euler", lift_order: int = 0):
+    """Algorithm 2; coarse = "euler" or "cns" (Navier-Stokes coarse propagator);
+    lift_order 1 = the order-one (Chapman-Enskog) lifting."""
     L = _gpu_lib()
     W0 = _f64(W0)
     V = torch.empty((n_slices + 1, p.nx, 5), dtype=torch.float64, device="cuda")
@@ -379,7 +429,12 @@ def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=N
     ps = C.byref(problem_struct(p))
     if coarse not in ("euler", "cns"):
         raise ValueError("coarse must be 'euler' or 'cns'")
-    if coarse == "cns":
+    if lift_order != 0:
+        o, Ed = _options(p, E, coarse, lift_order)
+        rc = L.parareal_iterate_opts(ps, C.byref(o), _dev(W0, "W0"), n_slices, T, k_max, tol,
+                                     _dev(V, "V_out"), err, C.byref(kd), w.data_ptr(),
+                                     w.numel(), _stream())
+    elif coarse == "cns":
         Ed, emax = _force(p, E) if E is not None else (None, 0.0)
         rc = L.parareal_iterate_cns(ps, _dev(Ed, "E") if Ed is not None else None, emax,
                                     _dev(W0, "W0"), n_slices, T, k_max, tol, _dev(V, "V_out"),
@@ -397,13 +452,18 @@ def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=N
     return V, [err[i] for i in range(kd.value)], kd.value
 
 
-def serial_fine(p, W0, n_slices: int, T: float, E=None) -> torch.Tensor:
+def serial_fine(p, W0, n_slices: int, T: float, E=None, lift_order: int = 0) -> torch.Tensor:
+    """The chained serial fine reference U^n = P F L(U^{n-1})."""
     L = _gpu_lib()
     W0 = _f64(W0)
     V = torch.empty((n_slices + 1, p.nx, 5), dtype=torch.float64, device="cuda")
     w = workspace(p, OP_PARAREAL, n_slices)
     ps = C.byref(problem_struct(p))
-    if E is None:
+    if lift_order != 0:
+        o, Ed = _options(p, E, "euler", lift_order)
+        rc = L.bgk_serial_fine_opts(ps, C.byref(o), _dev(W0, "W0"), n_slices, T,
+                                    _dev(V, "V_out"), w.data_ptr(), w.numel(), _stream())
+    elif E is None:
         rc = L.bgk_serial_fine(ps, _dev(W0, "W0"), n_slices, T, _dev(V, "V_out"),
                                w.data_ptr(), w.numel(), _stream())
     else:

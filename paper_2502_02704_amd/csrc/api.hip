@@ -433,6 +433,30 @@ static int lift_and_run(const Inst* d_I, const Inst& h, int n, bool project_last
   return run_steps(d_I, h, n, kLift, project_last, t, d_status, s, last_sel);
 }
 
+// Lifting of order lift_order (0: Maxwellian, fused into the first pass;
+// 1: first Chapman-Enskog correction, written into buf[1], which the first
+// step then reads in copy mode; prepare_lift must have set h.fin before the
+// descriptor was uploaded) followed by n steps and the projection.
+static void prepare_lift(Inst& h, int lift_order) {
+  if (lift_order == 1) h.fin = h.buf[1];
+}
+
+static int run_lifted(const Inst* d_I, const Inst& h, int n, int lift_order,
+                      const bgk_problem& p, Tiles t, int* d_status, hipStream_t s,
+                      int* last_sel) {
+  if (lift_order == 0) return lift_and_run(d_I, h, n, true, t, d_status, s, last_sel);
+  int rc = launch_lift_ce(d_I, h, dx_of(p), p.eps, d_status, s);
+  if (rc) return rc;
+  return run_steps(d_I, h, n, kCopy, true, t, d_status, s, last_sel);
+}
+
+static int check_lift_order(const bgk_problem& p, int lift_order) {
+  if (lift_order != 0 && lift_order != 1) return invalid("lift_order must be 0 or 1");
+  if (lift_order == 1 && !std::isfinite(p.eps))
+    return invalid("the order-one lifting needs a finite eps");
+  return BGK_OK;
+}
+
 static long long relax_out_blocks(const Inst& h) {
   const long long slabs = (h.nv3 + 4 * kBlock - 1) / (4 * kBlock);
   return (long long)h.nbatch * h.nx * slabs;
@@ -752,10 +776,12 @@ int bgk_fine_step_force(const bgk_problem* prob, const double* E, double e_max,
                         ws_bytes, stream);
 }
 
-static int propagate_impl(const bgk_problem* prob, const Force& F, int32_t batch,
-                          const double* V_in, double* V_out, double t_span, void* ws,
-                          size_t ws_bytes, void* stream) {
+static int propagate_impl(const bgk_problem* prob, const Force& F, int lift_order,
+                          int32_t batch, const double* V_in, double* V_out, double t_span,
+                          void* ws, size_t ws_bytes, void* stream) {
   int rc = check_problem(prob);
+  if (rc) return rc;
+  if ((rc = check_lift_order(*prob, lift_order))) return rc;
   if (rc) return rc;
   if (batch < 1) return invalid("batch must be >= 1");
   if (!V_in || !V_out) return invalid("NULL array");
@@ -773,6 +799,7 @@ static int propagate_impl(const bgk_problem* prob, const Force& F, int32_t batch
   Inst I = make_inst(*prob, batch, dt, t, fine_nsum(t, n, F));
   attach_fine(I, ws, L.fine, nullptr);
   attach_force(I, *prob, F, dt);
+  prepare_lift(I, lift_order);
   I.vin = V_in;
   I.vout = V_out;
   Inst* dI = at<Inst>(ws, L.insts);
@@ -780,13 +807,13 @@ static int propagate_impl(const bgk_problem* prob, const Force& F, int32_t batch
   if ((rc = check_force(*prob, F, st, s))) return rc;
   if ((rc = put_insts(dI, &I, 1, s))) return rc;
   int last = 0;
-  return lift_and_run(dI, I, n, true, t, st, s, &last);
+  return run_lifted(dI, I, n, lift_order, *prob, t, st, s, &last);
 }
 
 int bgk_fine_propagate_moments(const bgk_problem* prob, int32_t batch,
                                const double* V_in, double* V_out, double t_span,
                                void* ws, size_t ws_bytes, void* stream) {
-  return propagate_impl(prob, Force{}, batch, V_in, V_out, t_span, ws, ws_bytes, stream);
+  return propagate_impl(prob, Force{}, 0, batch, V_in, V_out, t_span, ws, ws_bytes, stream);
 }
 
 int bgk_fine_propagate_moments_force(const bgk_problem* prob, const double* E,
@@ -794,7 +821,7 @@ int bgk_fine_propagate_moments_force(const bgk_problem* prob, const double* E,
                                      double* V_out, double t_span, void* ws,
                                      size_t ws_bytes, void* stream) {
   if (!E) return invalid("E is NULL");
-  return propagate_impl(prob, Force{E, e_max}, batch, V_in, V_out, t_span, ws, ws_bytes,
+  return propagate_impl(prob, Force{E, e_max}, 0, batch, V_in, V_out, t_span, ws, ws_bytes,
                         stream);
 }
 
@@ -838,7 +865,7 @@ int euler_coarse_step_cns(const bgk_problem* prob, const double* E, int32_t batc
 }
 
 static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
-                         const double* W0,
+                         int lift_order, const double* W0,
                          int32_t n_slices, double T, int32_t k_max, double tol,
                          double* V_out, double* err_hist, int32_t* k_done, void* ws,
                          size_t ws_bytes, void* stream) {
@@ -849,6 +876,7 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
   if (k_max > 0 && !err_hist) return invalid("err_hist is NULL");
   if (!(T > 0.0) || !std::isfinite(T) || std::isnan(tol)) return invalid("bad T or tol");
   if (viscous && !std::isfinite(prob->eps)) return invalid("the Navier-Stokes model needs a finite eps");
+  if ((rc = check_lift_order(*prob, lift_order))) return rc;
   const double span = T / n_slices;
   int32_t n;
   double dt;
@@ -879,6 +907,7 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
     Inst I = make_inst(*prob, B, dt, t, fine_nsum(t, n, F));
     attach_fine(I, ws, L.fine, nullptr);
     attach_force(I, *prob, F, dt);
+    prepare_lift(I, lift_order);
     I.vin = U[cur] + (size_t)k * sl;        // U^{n-1,k}, n = k+1..N
     I.vout = VF + (size_t)(k + 1) * sl;     // P F L(U^{n-1,k})
     // one iteration: batched lift + fine steps + projection of the active
@@ -887,7 +916,7 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
       int r;
       if ((r = put_insts(dI, &I, 1, q))) return r;
       int last = 0;
-      if ((r = lift_and_run(dI, I, n, true, t, st, q, &last))) return r;
+      if ((r = run_lifted(dI, I, n, lift_order, *prob, t, st, q, &last))) return r;
       return launch_parareal_sweep(*prob, n_slices, k, U[cur], U[cur ^ 1], VF, Gc, span,
                                    scratch, tol > 0.0 ? &hd->err : errs + k, st, q, F.E,
                                    viscous);
@@ -896,7 +925,7 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
                                   {(double)n_slices, span, (double)k, (double)t.elems,
                                    (double)t.chunk, (double)t.pair, (double)I.nsum,
                                    tol > 0.0 ? 1.0 : 0.0, (double)(uintptr_t)F.E, F.emax,
-                                   viscous ? 1.0 : 0.0}),
+                                   viscous ? 1.0 : 0.0, (double)lift_order}),
                         s, iteration)))
       return rc;
     cur ^= 1;
@@ -939,7 +968,7 @@ int parareal_iterate(const bgk_problem* prob, const double* W0, int32_t n_slices
                      double T, int32_t k_max, double tol, double* V_out,
                      double* err_hist, int32_t* k_done, void* ws, size_t ws_bytes,
                      void* stream) {
-  return parareal_impl(prob, Force{}, false, W0, n_slices, T, k_max, tol, V_out, err_hist,
+  return parareal_impl(prob, Force{}, false, 0, W0, n_slices, T, k_max, tol, V_out, err_hist,
                        k_done, ws, ws_bytes, stream);
 }
 
@@ -948,7 +977,7 @@ int parareal_iterate_force(const bgk_problem* prob, const double* E, double e_ma
                            double tol, double* V_out, double* err_hist, int32_t* k_done,
                            void* ws, size_t ws_bytes, void* stream) {
   if (!E) return invalid("E is NULL");
-  return parareal_impl(prob, Force{E, e_max}, false, W0, n_slices, T, k_max, tol, V_out,
+  return parareal_impl(prob, Force{E, e_max}, false, 0, W0, n_slices, T, k_max, tol, V_out,
                        err_hist, k_done, ws, ws_bytes, stream);
 }
 
@@ -957,14 +986,16 @@ int parareal_iterate_cns(const bgk_problem* prob, const double* E, double e_max,
                          double tol, double* V_out, double* err_hist, int32_t* k_done,
                          void* ws, size_t ws_bytes, void* stream) {
   const Force F = E ? Force{E, e_max} : Force{};
-  return parareal_impl(prob, F, true, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done,
+  return parareal_impl(prob, F, true, 0, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done,
                        ws, ws_bytes, stream);
 }
 
-static int serial_impl(const bgk_problem* prob, const Force& F, const double* W0,
-                       int32_t n_slices, double T, double* V_out, void* ws,
-                       size_t ws_bytes, void* stream) {
+static int serial_impl(const bgk_problem* prob, const Force& F, int lift_order,
+                       const double* W0, int32_t n_slices, double T, double* V_out,
+                       void* ws, size_t ws_bytes, void* stream) {
   int rc = check_problem(prob);
+  if (rc) return rc;
+  if ((rc = check_lift_order(*prob, lift_order))) return rc;
   if (rc) return rc;
   if (!W0 || !V_out) return invalid("NULL array");
   if (n_slices < 1 || !(T > 0.0) || !std::isfinite(T)) return invalid("bad n_slices or T");
@@ -988,18 +1019,20 @@ static int serial_impl(const bgk_problem* prob, const Force& F, const double* W0
     Inst I = make_inst(*prob, 1, dt, t, ns);
     attach_fine(I, ws, L.fine, nullptr);
     attach_force(I, *prob, F, dt);
+    prepare_lift(I, lift_order);
     for (int m = 1; m <= n_slices; ++m) {
       I.vin = U + (size_t)(m - 1) * sl;
       I.vout = U + (size_t)m * sl;
       if ((r = put_insts(dI, &I, 1, q))) return r;
       int last = 0;
-      if ((r = lift_and_run(dI, I, n, true, t, st, q, &last))) return r;
+      if ((r = run_lifted(dI, I, n, lift_order, *prob, t, st, q, &last))) return r;
     }
     return BGK_OK;
   };
   if ((rc = run_graph(graph_key("ser", ws, ws_bytes, *prob,
                                 {(double)n_slices, span, (double)t.elems, (double)t.chunk,
-                                 (double)t.pair, (double)ns, (double)(uintptr_t)F.E, F.emax}),
+                                 (double)t.pair, (double)ns, (double)(uintptr_t)F.E, F.emax,
+                                 (double)lift_order}),
                       s, chain)))
     return rc;
   BGK_HIP(hipMemcpyAsync(V_out, U, sl * (n_slices + 1) * sizeof(double),
@@ -1010,14 +1043,75 @@ static int serial_impl(const bgk_problem* prob, const Force& F, const double* W0
 int bgk_serial_fine(const bgk_problem* prob, const double* W0, int32_t n_slices,
                     double T, double* V_out, void* ws, size_t ws_bytes,
                     void* stream) {
-  return serial_impl(prob, Force{}, W0, n_slices, T, V_out, ws, ws_bytes, stream);
+  return serial_impl(prob, Force{}, 0, W0, n_slices, T, V_out, ws, ws_bytes, stream);
 }
 
 int bgk_serial_fine_force(const bgk_problem* prob, const double* E, double e_max,
                           const double* W0, int32_t n_slices, double T, double* V_out,
                           void* ws, size_t ws_bytes, void* stream) {
   if (!E) return invalid("E is NULL");
-  return serial_impl(prob, Force{E, e_max}, W0, n_slices, T, V_out, ws, ws_bytes, stream);
+  return serial_impl(prob, Force{E, e_max}, 0, W0, n_slices, T, V_out, ws, ws_bytes, stream);
+}
+
+static Force force_of(const bgk_options* o) {
+  return (o && o->E) ? Force{o->E, o->e_max} : Force{};
+}
+
+static int check_options(const bgk_options* o) {
+  if (o && o->coarse != BGK_COARSE_EULER && o->coarse != BGK_COARSE_NAVIER_STOKES)
+    return invalid("coarse must be BGK_COARSE_EULER or BGK_COARSE_NAVIER_STOKES");
+  return BGK_OK;
+}
+
+int bgk_fine_propagate_moments_opts(const bgk_problem* prob, const bgk_options* opts,
+                                    int32_t batch, const double* V_in, double* V_out,
+                                    double t_span, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_options(opts);
+  if (rc) return rc;
+  return propagate_impl(prob, force_of(opts), opts ? opts->lift_order : 0, batch, V_in,
+                        V_out, t_span, ws, ws_bytes, stream);
+}
+
+int parareal_iterate_opts(const bgk_problem* prob, const bgk_options* opts,
+                          const double* W0, int32_t n_slices, double T, int32_t k_max,
+                          double tol, double* V_out, double* err_hist, int32_t* k_done,
+                          void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_options(opts);
+  if (rc) return rc;
+  return parareal_impl(prob, force_of(opts),
+                       opts && opts->coarse == BGK_COARSE_NAVIER_STOKES,
+                       opts ? opts->lift_order : 0, W0, n_slices, T, k_max, tol, V_out,
+                       err_hist, k_done, ws, ws_bytes, stream);
+}
+
+int bgk_serial_fine_opts(const bgk_problem* prob, const bgk_options* opts, const double* W0,
+                         int32_t n_slices, double T, double* V_out, void* ws,
+                         size_t ws_bytes, void* stream) {
+  int rc = check_options(opts);
+  if (rc) return rc;
+  return serial_impl(prob, force_of(opts), opts ? opts->lift_order : 0, W0, n_slices, T,
+                     V_out, ws, ws_bytes, stream);
+}
+
+int bgk_lift_ce(const bgk_problem* prob, const double* W, double* f, void* ws,
+                size_t ws_bytes, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if ((rc = check_lift_order(*prob, 1))) return rc;
+  if (!W || !f) return invalid("NULL array");
+  const Layout L = layout_of(*prob, BGK_OP_LIFT, 1);
+  if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const Tiles t = choose_tiles(*prob, 1);
+  Inst I = make_inst(*prob, 1, 1.0, t);
+  attach_fine(I, ws, L.fine, f);  // the lift writes buf[1] = f
+  double* V = at<double>(ws, L.fine.vg);  // conserved moments of W
+  if ((rc = launch_prim_to_cons(W, V, prob->nx, s))) return rc;
+  I.vin = V;
+  Inst* dI = at<Inst>(ws, L.insts);
+  int* st = &at<WsHeader>(ws, 0)->status;
+  if ((rc = put_insts(dI, &I, 1, s))) return rc;
+  return launch_lift_ce(dI, I, dx_of(*prob), prob->eps, st, s);
 }
 
 int bgk_n_steps_force(const bgk_problem* prob, double e_max, double t_span, int32_t* n,

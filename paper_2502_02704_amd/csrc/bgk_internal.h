@@ -144,6 +144,11 @@ int launch_partials(const Inst* d_insts, int n_inst, long long total_items,
 // (5 + 5), physical flux (5), wave speed (1), primitive u and theta (4).
 constexpr int kCoarseScratch = 20;
 
+// Lifting of order one (first Chapman-Enskog correction) of the conserved
+// moments h.vin of every member into h.buf[1] (device copy d_inst of h).
+int launch_lift_ce(const Inst* d_inst, const Inst& h, double dx, double eps, int* d_status,
+                   hipStream_t s);
+
 // Coarse propagation, one workgroup per batch member.  E: exterior force at
 // the x centres (device, nullable), added as a source term; viscous: the
 // Navier-Stokes system of the BGK model instead of Euler's.

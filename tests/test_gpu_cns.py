@@ -92,3 +92,66 @@ def test_cns_needs_finite_eps():
     with pytest.raises(bgk.BgkError) as e:
         bgk.euler_coarse_step(p, cuda(V), 0.01, coarse="cns")
     assert e.value.code == bgk.E_INVALID
+
+
+# ------------------------------------------- order-one (Chapman-Enskog) lift --
+from tests.test_gpu_parity import GRIDS, states  # noqa: E402
+from tests.gpu_util import rel_f  # noqa: E402
+
+
+@pytest.mark.parametrize("name", list(GRIDS))
+def test_lift_ce_matches_oracle(name):
+    p = GRIDS[name]
+    W, _ = states(p, 91)
+    got = bgk.lift_ce(p, cuda(W)).cpu().numpy()
+    bgk.check_status()
+    assert rel_f(got, oracle.lift_ce(p, W)) < TOL
+
+
+@pytest.mark.parametrize("name", ["sod_nx64_nv16", "wide_periodic", "even_z_ragged",
+                                  "ragged_neumann"])
+def test_propagate_with_order_one_lift(name):
+    p = GRIDS[name]
+    Vin = np.stack([smooth_states(p, 92, 1)[0], smooth_states(p, 93, 1)[0]])
+    got = bgk.fine_propagate_moments(p, cuda(Vin), 0.0043, lift_order=1).cpu().numpy()
+    bgk.check_status()
+    for b in range(2):
+        ref = oracle.fine_propagate_moments_opts(p, Vin[b], 0.0043, lift_order=1)
+        assert rel_V(got[b], ref) < TOL
+
+
+def test_parareal_order_one_lift_cns_matches_oracle():
+    wk = small_smooth()
+    p = wk.problem
+    V, err, kd = bgk.parareal_iterate(p, cuda(wk.W0), wk.n_slices, wk.T, 3, 0.0,
+                                      coarse="cns", lift_order=1)
+    Vr, errr, kdr = oracle.parareal_iterate_opts(p, wk.W0, wk.n_slices, wk.T, 3, 0.0,
+                                                 coarse="cns", lift_order=1)
+    assert kd == kdr == 3
+    assert rel_V(V.cpu().numpy(), Vr) < TOL
+    assert np.allclose(err, errr, rtol=1e-6, atol=1e-13)
+
+
+def test_parareal_order_one_lift_k_equals_n_is_serial_fine():
+    wk = small_smooth()
+    p, N = wk.problem, wk.n_slices
+    V, _, kd = bgk.parareal_iterate(p, cuda(wk.W0), N, wk.T, N, 0.0, coarse="cns",
+                                    lift_order=1)
+    S = bgk.serial_fine(p, cuda(wk.W0), N, wk.T, lift_order=1).cpu().numpy()
+    assert kd == N
+    assert rel_V(V.cpu().numpy(), S) < 1e-13
+    assert rel_V(S, oracle.serial_fine_opts(p, wk.W0, N, wk.T, lift_order=1)) < TOL
+
+
+def test_order_one_lift_with_force():
+    wk = wl.c6_two_beam_force(nx=24, nv=(32, 12, 12), eps=1e-3, n_slices=4, T=0.04)
+    p = wk.problem
+    W0 = wk.U0()
+    x = p.x_centres()
+    W0[:, 1] = 0.2 * np.sin(np.pi * x)  # a velocity gradient for the correction
+    V, _, kd = bgk.parareal_iterate(p, cuda(W0), 4, wk.T, 2, 0.0, E=wk.E, coarse="cns",
+                                    lift_order=1)
+    Vr, _, kdr = oracle.parareal_iterate_opts(p, W0, 4, wk.T, 2, 0.0, E=wk.E, coarse="cns",
+                                              lift_order=1)
+    assert kd == kdr == 2
+    assert rel_V(V.cpu().numpy(), Vr) < TOL
