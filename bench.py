@@ -125,17 +125,22 @@ def parareal_speedup(torch, bgk, wl, reps=5):
              (s2.name, s2.problem, s2.W0, s2.n_slices, s2.T, None, "euler"),
              (s2.name, s2.problem, s2.W0, s2.n_slices, s2.T, None, "cns"),
              (fk.name, fk.problem, fk.U0(), fk.n_slices, fk.T, fk.E, "euler")]
+    cases = [c + (0,) for c in cases]
+    # the multiscale variant: Navier-Stokes coarse model with the order-one
+    # (Chapman-Enskog) lifting, against the serial chain with the same lifting
+    cases.append((s2.name, s2.problem, s2.W0, s2.n_slices, s2.T, None, "cns", 1))
     out = []
-    for name, p, W0np, N, T, E, coarse in cases:
+    for name, p, W0np, N, T, E, coarse, lo in cases:
         W0 = torch.from_numpy(W0np).cuda()
-        ref, t_serial = timed(lambda: bgk.serial_fine(p, W0, N, T, E=E))
+        ref, t_serial = timed(lambda: bgk.serial_fine(p, W0, N, T, E=E, lift_order=lo))
         ref = ref.cpu().numpy()
-        res = {"workload": name, "coarse": coarse, "slices": N,
+        res = {"workload": name, "coarse": coarse, "lift_order": lo, "slices": N,
                "serial_fine_ms": round(t_serial * 1e3, 4), "K": []}
         chosen = None
         for K in range(1, N + 1):
             (V, err, kd), t_par = timed(lambda: bgk.parareal_iterate(p, W0, N, T, K, 0.0, E=E,
-                                                                     coarse=coarse))
+                                                                     coarse=coarse,
+                                                                     lift_order=lo))
             e = float(np.max(np.abs(V.cpu().numpy() - ref)))
             res["K"].append({"K": K, "ms": round(t_par * 1e3, 4), "err_vs_fine": e,
                              "speedup": round(t_serial / t_par, 3)})
