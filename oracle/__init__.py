@@ -77,10 +77,15 @@ def lib():
             "bgk_oracle_serial_fine_force": [P, D, D, C.c_int32, C.c_double, D],
             "bgk_oracle_cns_coarse_step": [P, D, D, D, C.c_double, I],
             "bgk_oracle_lift_ce": [P, D, D],
-            "bgk_oracle_fine_propagate_moments_opts": [P, D, C.c_int32, D, D, C.c_double],
-            "bgk_oracle_parareal_iterate_opts": [P, D, C.c_int32, C.c_int32, D, C.c_int32,
-                                                 C.c_double, C.c_int32, C.c_double, D, D, I],
-            "bgk_oracle_serial_fine_opts": [P, D, C.c_int32, D, C.c_int32, C.c_double, D],
+            "bgk_oracle_transport_opts": [P, D, C.c_int32, D, C.c_double, D],
+            "bgk_oracle_fine_steps_opts": [P, D, C.c_int32, D, D, C.c_double, C.c_int32],
+            "bgk_oracle_fine_propagate_moments_opts": [P, D, C.c_int32, C.c_int32, D, D,
+                                                       C.c_double],
+            "bgk_oracle_parareal_iterate_opts": [P, D, C.c_int32, C.c_int32, C.c_int32, D,
+                                                 C.c_int32, C.c_double, C.c_int32,
+                                                 C.c_double, D, D, I],
+            "bgk_oracle_serial_fine_opts": [P, D, C.c_int32, C.c_int32, D, C.c_int32,
+                                            C.c_double, D],
             "bgk_oracle_parareal_iterate_cns": [P, D, D, C.c_int32, C.c_double, C.c_int32,
                                                 C.c_double, D, D, I],
         }
@@ -257,18 +262,39 @@ def lift_ce(p, W) -> np.ndarray:
 COARSE = {"euler": 0, "cns": 1}
 
 
-def fine_propagate_moments_opts(p, V, t_span: float, E=None, lift_order: int = 0):
+def transport_opts(p, f, dt: float, E=None, fine_order: int = 1) -> np.ndarray:
+    """One explicit transport; fine_order 2 adds the van Leer limited
+    Lax-Wendroff correction in x."""
+    f = _arr(f)
+    out = np.empty_like(f)
+    Ea = _force(p, E) if E is not None else None
+    _chk(lib().bgk_oracle_transport_opts(C.byref(_prob(p)), _d(Ea) if Ea is not None else None,
+                                         fine_order, _d(f), dt, _d(out)), "transport_opts")
+    return out
+
+
+def fine_steps_opts(p, f, dt: float, n: int, E=None, fine_order: int = 1) -> np.ndarray:
+    f = _arr(f)
+    out = np.empty_like(f)
+    Ea = _force(p, E) if E is not None else None
+    _chk(lib().bgk_oracle_fine_steps_opts(C.byref(_prob(p)), _d(Ea) if Ea is not None else None,
+                                          fine_order, _d(f), _d(out), dt, n), "steps_opts")
+    return out
+
+
+def fine_propagate_moments_opts(p, V, t_span: float, E=None, lift_order: int = 0,
+                                fine_order: int = 1):
     V = _arr(V)
     out = np.empty_like(V)
     Ea = _force(p, E) if E is not None else None
     _chk(lib().bgk_oracle_fine_propagate_moments_opts(
-        C.byref(_prob(p)), _d(Ea) if Ea is not None else None, lift_order, _d(V), _d(out),
-        t_span), "PFL_opts")
+        C.byref(_prob(p)), _d(Ea) if Ea is not None else None, lift_order, fine_order, _d(V),
+        _d(out), t_span), "PFL_opts")
     return out
 
 
 def parareal_iterate_opts(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=None,
-                          coarse: str = "euler", lift_order: int = 0):
+                          coarse: str = "euler", lift_order: int = 0, fine_order: int = 1):
     W0 = _arr(W0)
     V = np.empty((n_slices + 1, p.nx, 5))
     err = np.zeros(max(k_max, 1))
@@ -276,17 +302,19 @@ def parareal_iterate_opts(p, W0, n_slices: int, T: float, k_max: int, tol: float
     Ea = _force(p, E) if E is not None else None
     _chk(lib().bgk_oracle_parareal_iterate_opts(
         C.byref(_prob(p)), _d(Ea) if Ea is not None else None, COARSE[coarse], lift_order,
-        _d(W0), n_slices, T, k_max, tol, _d(V), _d(err), C.byref(kd)), "parareal_opts")
+        fine_order, _d(W0), n_slices, T, k_max, tol, _d(V), _d(err), C.byref(kd)),
+        "parareal_opts")
     return V, err[:kd.value].copy(), kd.value
 
 
-def serial_fine_opts(p, W0, n_slices: int, T: float, E=None, lift_order: int = 0):
+def serial_fine_opts(p, W0, n_slices: int, T: float, E=None, lift_order: int = 0,
+                     fine_order: int = 1):
     W0 = _arr(W0)
     V = np.empty((n_slices + 1, p.nx, 5))
     Ea = _force(p, E) if E is not None else None
     _chk(lib().bgk_oracle_serial_fine_opts(
-        C.byref(_prob(p)), _d(Ea) if Ea is not None else None, lift_order, _d(W0), n_slices,
-        T, _d(V)), "serial_opts")
+        C.byref(_prob(p)), _d(Ea) if Ea is not None else None, lift_order, fine_order, _d(W0),
+        n_slices, T, _d(V)), "serial_opts")
     return V
 
 

@@ -307,7 +307,26 @@ int bgk_oracle_moments(const bgk_oracle_problem* p, const double* f,
  * printed dissipation term differences a value with itself; it is read as
  * the Rusanov one above.  No flux crosses the ends of the truncated v_x
  * range, so the scheme conserves mass. */
-static int transport_impl(const bgk_oracle_problem* p, const double* E,
+/* Second order in x (order = 2): the upwind flux gains the Lax-Wendroff
+ * correction limited by van Leer's limiter (the flux limiters the paper names
+ * as the natural improvement, Section 3.1), written with the limited
+ * difference L(a, b) = 2ab/(a+b) when ab > 0, else 0:
+ *   v_x > 0: F_{i+1/2} = v_x [f_i + (1-nu)/2 L(f_i - f_{i-1}, f_{i+1} - f_i)]
+ *   v_x < 0: F_{i+1/2} = v_x [f_{i+1} - (1-|nu|)/2 L(f_{i+2} - f_{i+1}, f_{i+1} - f_i)]
+ * nu = v_x dt/dx; ghost cells two deep from the boundary condition.  It is
+ * TVD for |nu| <= 1 and second order where the data are smooth. */
+static double vl_limited(double a, double b) {
+  return a * b > 0.0 ? 2.0 * a * b / (a + b) : 0.0;
+}
+
+static double flux2(double vx, double nu, double fm, double f0, double fp, double fp2) {
+  /* flux through the face between f0 (cell i) and fp (cell i+1) */
+  if (vx > 0.0) return vx * (f0 + 0.5 * (1.0 - nu) * vl_limited(f0 - fm, fp - f0));
+  if (vx < 0.0) return vx * (fp - 0.5 * (1.0 + nu) * vl_limited(fp2 - fp, fp - f0));
+  return 0.0;
+}
+
+static int transport_impl(const bgk_oracle_problem* p, const double* E, int order,
                           const double* f, double dt, double* f_star) {
   if (check_problem(p) || !f || !f_star || f == f_star) return ORACLE_E_INVALID;
   const long nv3 = nv3_of(p);
@@ -317,17 +336,26 @@ static int transport_impl(const bgk_oracle_problem* p, const double* E,
   const double emax = emax_of(p, E);
 #pragma omp parallel for num_threads(NT)
   for (int i = 0; i < p->nx; ++i) {
+    const double* fm2 = f + (long)ghost(p, i - 2) * nv3;
     const double* fm = f + (long)ghost(p, i - 1) * nv3;
     const double* f0 = f + (long)i * nv3;
     const double* fp = f + (long)ghost(p, i + 1) * nv3;
+    const double* fp2 = f + (long)ghost(p, i + 2) * nv3;
     long j = 0;
     for (int jx = 0; jx < p->nv[0]; ++jx) {
       double vx = vc(p, 0, jx);
       double vp = vx > 0.0 ? vx : 0.0;
       double vm = vx < 0.0 ? vx : 0.0;
+      double nu = vx * r;
       for (int jyz = 0; jyz < nyz; ++jyz, ++j) {
-        double F_right = vp * f0[j] + vm * fp[j];
-        double F_left = vp * fm[j] + vm * f0[j];
+        double F_right, F_left;
+        if (order == 2) {
+          F_right = flux2(vx, nu, fm[j], f0[j], fp[j], fp2[j]);
+          F_left = flux2(vx, nu, fm2[j], fm[j], f0[j], fp[j]);
+        } else {
+          F_right = vp * f0[j] + vm * fp[j];
+          F_left = vp * fm[j] + vm * f0[j];
+        }
         double out = f0[j] - r * (F_right - F_left);
         if (E) {
           double G_up = 0.0, G_down = 0.0;
@@ -350,13 +378,13 @@ static int transport_impl(const bgk_oracle_problem* p, const double* E,
 
 int bgk_oracle_transport(const bgk_oracle_problem* p, const double* f,
                          double dt, double* f_star) {
-  return transport_impl(p, NULL, f, dt, f_star);
+  return transport_impl(p, NULL, 1, f, dt, f_star);
 }
 
 int bgk_oracle_transport_force(const bgk_oracle_problem* p, const double* E,
                                const double* f, double dt, double* f_star) {
   if (!E) return ORACLE_E_INVALID;
-  return transport_impl(p, E, f, dt, f_star);
+  return transport_impl(p, E, 1, f, dt, f_star);
 }
 
 /* ---------------------------------------------------------- relaxation -- */
@@ -391,7 +419,7 @@ int bgk_oracle_relax(const bgk_oracle_problem* p, const double* f_star,
 }
 
 /* ---------------------------------------------------- fine propagator -- */
-static int fine_steps_impl(const bgk_oracle_problem* p, const double* E,
+static int fine_steps_impl(const bgk_oracle_problem* p, const double* E, int order,
                            const double* f_in, double* f_out, double dt,
                            int32_t n_steps) {
   if (check_problem(p) || !f_in || !f_out || n_steps < 0 || !(dt > 0.0))
@@ -407,7 +435,7 @@ static int fine_steps_impl(const bgk_oracle_problem* p, const double* E,
   memcpy(cur, f_in, n * sizeof(double));
   int rc = ORACLE_OK;
   for (int32_t s = 0; s < n_steps && rc == ORACLE_OK; ++s) {
-    rc = transport_impl(p, E, cur, dt, star);
+    rc = transport_impl(p, E, order, cur, dt, star);
     if (rc == ORACLE_OK) rc = bgk_oracle_relax(p, star, dt, cur);
   }
   if (rc == ORACLE_OK) memcpy(f_out, cur, n * sizeof(double));
@@ -418,17 +446,17 @@ static int fine_steps_impl(const bgk_oracle_problem* p, const double* E,
 
 int bgk_oracle_fine_steps(const bgk_oracle_problem* p, const double* f_in,
                           double* f_out, double dt, int32_t n_steps) {
-  return fine_steps_impl(p, NULL, f_in, f_out, dt, n_steps);
+  return fine_steps_impl(p, NULL, 1, f_in, f_out, dt, n_steps);
 }
 
 int bgk_oracle_fine_steps_force(const bgk_oracle_problem* p, const double* E,
                                 const double* f_in, double* f_out, double dt,
                                 int32_t n_steps) {
   if (!E) return ORACLE_E_INVALID;
-  return fine_steps_impl(p, E, f_in, f_out, dt, n_steps);
+  return fine_steps_impl(p, E, 1, f_in, f_out, dt, n_steps);
 }
 
-static int fine_step_impl(const bgk_oracle_problem* p, const double* E,
+static int fine_step_impl(const bgk_oracle_problem* p, const double* E, int order,
                           const double* f_in, double* f_out, double t_span,
                           int32_t* n_steps_out) {
   int32_t n;
@@ -436,19 +464,19 @@ static int fine_step_impl(const bgk_oracle_problem* p, const double* E,
   int rc = n_steps_impl(p, emax_of(p, E), t_span, &n, &dt);
   if (rc) return rc;
   if (n_steps_out) *n_steps_out = n;
-  return fine_steps_impl(p, E, f_in, f_out, dt, n);
+  return fine_steps_impl(p, E, order, f_in, f_out, dt, n);
 }
 
 int bgk_oracle_fine_step(const bgk_oracle_problem* p, const double* f_in,
                          double* f_out, double t_span, int32_t* n_steps_out) {
-  return fine_step_impl(p, NULL, f_in, f_out, t_span, n_steps_out);
+  return fine_step_impl(p, NULL, 1, f_in, f_out, t_span, n_steps_out);
 }
 
 int bgk_oracle_fine_step_force(const bgk_oracle_problem* p, const double* E,
                                const double* f_in, double* f_out, double t_span,
                                int32_t* n_steps_out) {
   if (!E) return ORACLE_E_INVALID;
-  return fine_step_impl(p, E, f_in, f_out, t_span, n_steps_out);
+  return fine_step_impl(p, E, 1, f_in, f_out, t_span, n_steps_out);
 }
 
 static void conserved_to_primitive(const double* V5, double* W5) {
@@ -463,7 +491,8 @@ static void conserved_to_primitive(const double* V5, double* W5) {
 }
 
 /* Steps 5-7 of Algorithm 2: lifting, kinetic propagation, projection. */
-static int propagate_impl(const bgk_oracle_problem* p, const double* E, int lift_order,
+static int propagate_impl(const bgk_oracle_problem* p, const double* E, int order,
+                          int lift_order,
                           const double* V_in, double* V_out, double t_span) {
   if (check_problem(p) || !V_in || !V_out) return ORACLE_E_INVALID;
   const size_t n = (size_t)p->nx * nv3_of(p);
@@ -476,7 +505,7 @@ static int propagate_impl(const bgk_oracle_problem* p, const double* E, int lift
   }
   for (int i = 0; i < p->nx; ++i) conserved_to_primitive(V_in + 5 * i, W + 5 * i);
   int rc = lift_order == 1 ? bgk_oracle_lift_ce(p, W, f) : bgk_oracle_lift(p, W, f);
-  if (rc == ORACLE_OK) rc = fine_step_impl(p, E, f, f, t_span, NULL);
+  if (rc == ORACLE_OK) rc = fine_step_impl(p, E, order, f, f, t_span, NULL);
   if (rc == ORACLE_OK) rc = bgk_oracle_moments(p, f, V_out, NULL);
   free(W);
   free(f);
@@ -486,14 +515,14 @@ static int propagate_impl(const bgk_oracle_problem* p, const double* E, int lift
 int bgk_oracle_fine_propagate_moments(const bgk_oracle_problem* p,
                                       const double* V_in, double* V_out,
                                       double t_span) {
-  return propagate_impl(p, NULL, 0, V_in, V_out, t_span);
+  return propagate_impl(p, NULL, 1, 0, V_in, V_out, t_span);
 }
 
 int bgk_oracle_fine_propagate_moments_force(const bgk_oracle_problem* p,
                                             const double* E, const double* V_in,
                                             double* V_out, double t_span) {
   if (!E) return ORACLE_E_INVALID;
-  return propagate_impl(p, E, 0, V_in, V_out, t_span);
+  return propagate_impl(p, E, 1, 0, V_in, V_out, t_span);
 }
 
 /* ------------------------------------------------------------ coarse G -- */
@@ -691,7 +720,7 @@ static void primitive_to_conserved(const double* W5, double* V5) {
  *     err_k = max_{n,i,c} |U^{n,k+1} - U^{n,k}|;  stop at K or err < tol.
  * The jump loop is the parallel one (Section 2.2 and Section 4). */
 static int parareal_impl(const bgk_oracle_problem* p, const double* E, int viscous,
-                         int lift_order, const double* W0, int32_t n_slices, double T,
+                         int lift_order, int order, const double* W0, int32_t n_slices, double T,
                          int32_t k_max, double tol, double* V_out,
                          double* err_hist, int32_t* k_done) {
   if (check_problem(p) || !W0 || !V_out || n_slices < 1 || k_max < 0 ||
@@ -718,7 +747,7 @@ static int parareal_impl(const bgk_oracle_problem* p, const double* E, int visco
     for (int n = k + 1; n <= n_slices; ++n) {
       double* Fv = (double*)malloc(sl * sizeof(double));
       double* Gv = (double*)malloc(sl * sizeof(double));
-      int r1 = propagate_impl(p, E, lift_order, U + sl * (n - 1), Fv, dT);
+      int r1 = propagate_impl(p, E, order, lift_order, U + sl * (n - 1), Fv, dT);
       int r2 = r1 ? r1 : coarse_impl(p, E, viscous, U + sl * (n - 1), Gv, dT, NULL);
       if (r1 || r2) bad = r1 ? r1 : r2;
       else
@@ -759,7 +788,7 @@ int bgk_oracle_parareal_iterate(const bgk_oracle_problem* p, const double* W0,
                                 int32_t n_slices, double T, int32_t k_max,
                                 double tol, double* V_out, double* err_hist,
                                 int32_t* k_done) {
-  return parareal_impl(p, NULL, 0, 0, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
+  return parareal_impl(p, NULL, 0, 0, 1, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
 }
 
 int bgk_oracle_parareal_iterate_force(const bgk_oracle_problem* p, const double* E,
@@ -767,25 +796,25 @@ int bgk_oracle_parareal_iterate_force(const bgk_oracle_problem* p, const double*
                                       int32_t k_max, double tol, double* V_out,
                                       double* err_hist, int32_t* k_done) {
   if (!E) return ORACLE_E_INVALID;
-  return parareal_impl(p, E, 0, 0, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
+  return parareal_impl(p, E, 0, 0, 1, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
 }
 
 int bgk_oracle_parareal_iterate_cns(const bgk_oracle_problem* p, const double* E,
                                     const double* W0, int32_t n_slices, double T,
                                     int32_t k_max, double tol, double* V_out,
                                     double* err_hist, int32_t* k_done) {
-  return parareal_impl(p, E, 1, 0, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
+  return parareal_impl(p, E, 1, 0, 1, W0, n_slices, T, k_max, tol, V_out, err_hist, k_done);
 }
 
 /* The fine reference that parareal converges to: U^n = P F L(U^{n-1}). */
-static int serial_impl(const bgk_oracle_problem* p, const double* E, int lift_order,
+static int serial_impl(const bgk_oracle_problem* p, const double* E, int lift_order, int order,
                        const double* W0, int32_t n_slices, double T, double* V_out) {
   if (check_problem(p) || !W0 || !V_out || n_slices < 1 || !(T > 0.0))
     return ORACLE_E_INVALID;
   const size_t sl = 5 * (size_t)p->nx;
   for (int i = 0; i < p->nx; ++i) primitive_to_conserved(W0 + 5 * i, V_out + 5 * i);
   for (int n = 1; n <= n_slices; ++n) {
-    int rc = propagate_impl(p, E, lift_order, V_out + sl * (n - 1), V_out + sl * n,
+    int rc = propagate_impl(p, E, order, lift_order, V_out + sl * (n - 1), V_out + sl * n,
                             T / n_slices);
     if (rc) return rc;
   }
@@ -794,14 +823,14 @@ static int serial_impl(const bgk_oracle_problem* p, const double* E, int lift_or
 
 int bgk_oracle_serial_fine(const bgk_oracle_problem* p, const double* W0,
                            int32_t n_slices, double T, double* V_out) {
-  return serial_impl(p, NULL, 0, W0, n_slices, T, V_out);
+  return serial_impl(p, NULL, 0, 1, W0, n_slices, T, V_out);
 }
 
 int bgk_oracle_serial_fine_force(const bgk_oracle_problem* p, const double* E,
                                  const double* W0, int32_t n_slices, double T,
                                  double* V_out) {
   if (!E) return ORACLE_E_INVALID;
-  return serial_impl(p, E, 0, W0, n_slices, T, V_out);
+  return serial_impl(p, E, 0, 1, W0, n_slices, T, V_out);
 }
 
 /* --------------------------------------------------------------- adjoint -- */
@@ -974,28 +1003,50 @@ int bgk_oracle_lift_adjoint_rho(const bgk_oracle_problem* p, const double* W,
 }
 
 /* ------------------------------------------------------------- options -- */
+static int check_opts(int32_t lift_order, int32_t fine_order) {
+  return ((lift_order != 0 && lift_order != 1) || (fine_order != 1 && fine_order != 2))
+             ? ORACLE_E_INVALID
+             : ORACLE_OK;
+}
+
+int bgk_oracle_transport_opts(const bgk_oracle_problem* p, const double* E,
+                              int32_t fine_order, const double* f, double dt,
+                              double* f_star) {
+  if (check_opts(0, fine_order)) return ORACLE_E_INVALID;
+  return transport_impl(p, E, fine_order, f, dt, f_star);
+}
+
+int bgk_oracle_fine_steps_opts(const bgk_oracle_problem* p, const double* E,
+                               int32_t fine_order, const double* f_in, double* f_out,
+                               double dt, int32_t n_steps) {
+  if (check_opts(0, fine_order)) return ORACLE_E_INVALID;
+  return fine_steps_impl(p, E, fine_order, f_in, f_out, dt, n_steps);
+}
+
 int bgk_oracle_fine_propagate_moments_opts(const bgk_oracle_problem* p,
                                            const double* E, int32_t lift_order,
-                                           const double* V_in, double* V_out,
-                                           double t_span) {
-  if (lift_order != 0 && lift_order != 1) return ORACLE_E_INVALID;
-  return propagate_impl(p, E, lift_order, V_in, V_out, t_span);
+                                           int32_t fine_order, const double* V_in,
+                                           double* V_out, double t_span) {
+  if (check_opts(lift_order, fine_order)) return ORACLE_E_INVALID;
+  return propagate_impl(p, E, fine_order, lift_order, V_in, V_out, t_span);
 }
 
 int bgk_oracle_parareal_iterate_opts(const bgk_oracle_problem* p, const double* E,
                                      int32_t coarse, int32_t lift_order,
-                                     const double* W0, int32_t n_slices, double T,
-                                     int32_t k_max, double tol, double* V_out,
-                                     double* err_hist, int32_t* k_done) {
-  if ((coarse != 0 && coarse != 1) || (lift_order != 0 && lift_order != 1))
+                                     int32_t fine_order, const double* W0,
+                                     int32_t n_slices, double T, int32_t k_max,
+                                     double tol, double* V_out, double* err_hist,
+                                     int32_t* k_done) {
+  if ((coarse != 0 && coarse != 1) || check_opts(lift_order, fine_order))
     return ORACLE_E_INVALID;
-  return parareal_impl(p, E, coarse, lift_order, W0, n_slices, T, k_max, tol, V_out,
-                       err_hist, k_done);
+  return parareal_impl(p, E, coarse, lift_order, fine_order, W0, n_slices, T, k_max, tol,
+                       V_out, err_hist, k_done);
 }
 
 int bgk_oracle_serial_fine_opts(const bgk_oracle_problem* p, const double* E,
-                                int32_t lift_order, const double* W0,
-                                int32_t n_slices, double T, double* V_out) {
-  if (lift_order != 0 && lift_order != 1) return ORACLE_E_INVALID;
-  return serial_impl(p, E, lift_order, W0, n_slices, T, V_out);
+                                int32_t lift_order, int32_t fine_order,
+                                const double* W0, int32_t n_slices, double T,
+                                double* V_out) {
+  if (check_opts(lift_order, fine_order)) return ORACLE_E_INVALID;
+  return serial_impl(p, E, lift_order, fine_order, W0, n_slices, T, V_out);
 }

@@ -169,20 +169,30 @@ int bgk_oracle_lift_ce(const bgk_oracle_problem* p, const double* W, double* f);
 
 /* General forms: E (host [nx]) may be NULL; coarse 0 = Euler, 1 =
  * Navier-Stokes; lift_order 0 = Maxwellian (Definition 2), 1 = the lifting
- * above.  The serial fine chain with the same lift_order is parareal's fixed
+ * above; fine_order 1 = the upwind transport of Section 3.1, 2 = with the
+ * van Leer limited Lax-Wendroff correction (second order where smooth, TVD).
+ * The serial fine chain with the same lifting and order is parareal's fixed
  * point. */
+int bgk_oracle_transport_opts(const bgk_oracle_problem* p, const double* E,
+                              int32_t fine_order, const double* f, double dt,
+                              double* f_star);
+int bgk_oracle_fine_steps_opts(const bgk_oracle_problem* p, const double* E,
+                               int32_t fine_order, const double* f_in, double* f_out,
+                               double dt, int32_t n_steps);
 int bgk_oracle_fine_propagate_moments_opts(const bgk_oracle_problem* p,
                                            const double* E, int32_t lift_order,
-                                           const double* V_in, double* V_out,
-                                           double t_span);
+                                           int32_t fine_order, const double* V_in,
+                                           double* V_out, double t_span);
 int bgk_oracle_parareal_iterate_opts(const bgk_oracle_problem* p, const double* E,
                                      int32_t coarse, int32_t lift_order,
-                                     const double* W0, int32_t n_slices, double T,
-                                     int32_t k_max, double tol, double* V_out,
-                                     double* err_hist, int32_t* k_done);
+                                     int32_t fine_order, const double* W0,
+                                     int32_t n_slices, double T, int32_t k_max,
+                                     double tol, double* V_out, double* err_hist,
+                                     int32_t* k_done);
 int bgk_oracle_serial_fine_opts(const bgk_oracle_problem* p, const double* E,
-                                int32_t lift_order, const double* W0,
-                                int32_t n_slices, double T, double* V_out);
+                                int32_t lift_order, int32_t fine_order,
+                                const double* W0, int32_t n_slices, double T,
+                                double* V_out);
 
 void bgk_oracle_set_threads(int n);
 int bgk_oracle_get_threads(void);

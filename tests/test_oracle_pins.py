@@ -884,6 +884,74 @@ class TestChapmanEnskogLift:
         assert np.max(np.abs(ref - oracle.serial_fine(p, wk.W0, 4, wk.T))) > 1e-8
 
 
+class TestSecondOrderTransport:
+    """x transport with the van Leer limited Lax-Wendroff correction (the flux
+    limiters Section 3.1 names as the natural improvement)."""
+
+    @pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_PERIODIC])
+    def test_courant_one_is_the_same_exact_shift(self, bc):
+        # at |nu| = 1 the correction carries the factor 1 - |nu| = 0
+        p = wl.Problem(nx=9, nv=(2, 1, 1), v_lo=(-2, -1, -1), v_hi=(2, 1, 1), bc=bc, eps=INF)
+        f = wl.random_f(p, 13)
+        dt = 1.0 / p.nx
+        a = oracle.transport_opts(p, f, dt, fine_order=2)
+        assert np.array_equal(a, oracle.transport(p, f, dt))
+
+    def test_second_order_convergence(self):
+        # a smooth periodic profile advected by v_x = +-1: the L1 error after a
+        # fixed time falls ~4x per halving of dx (2x for the upwind scheme)
+        errs = {1: [], 2: []}
+        for nx in (64, 128, 256):
+            p = wl.Problem(nx=nx, nv=(2, 1, 1), v_lo=(-2, -1, -1), v_hi=(2, 1, 1),
+                           bc=wl.BC_PERIODIC, eps=INF)
+            x = p.x_centres()
+            f = np.column_stack([2 + np.sin(2 * np.pi * x)] * 2)
+            dt = 0.5 / nx
+            n = nx // 2  # t = 0.25
+            exact = np.column_stack([2 + np.sin(2 * np.pi * (x + 0.25)),
+                                     2 + np.sin(2 * np.pi * (x - 0.25))])
+            for order in (1, 2):
+                g = oracle.fine_steps_opts(p, f, dt, n, fine_order=order)
+                errs[order].append(np.mean(np.abs(g - exact)))
+        r2 = [errs[2][i] / errs[2][i + 1] for i in range(2)]
+        r1 = [errs[1][i] / errs[1][i + 1] for i in range(2)]
+        assert min(r2) > 3.0 and max(r1) < 2.2
+        assert errs[2][-1] < 0.05 * errs[1][-1]
+
+    def test_total_variation_and_extrema(self):
+        p = wl.Problem(nx=40, nv=(6, 1, 1), v_lo=(-3, -1, -1), v_hi=(3, 1, 1),
+                       bc=wl.BC_PERIODIC, eps=INF)
+        x = p.x_centres()
+        col = np.where((x > 0.3) & (x < 0.6), 2.0, 0.5) + 0.3 * (x > 0.8)
+        f = np.column_stack([col] * p.nv3)
+        tv = lambda g: np.abs(np.diff(np.vstack([g, g[:1]]), axis=0)).sum(0)  # noqa: E731
+        dt = 0.9 / p.nx / 2.5
+        g = f
+        for _ in range(20):
+            h = oracle.transport_opts(p, g, dt, fine_order=2)
+            assert np.all(tv(h) <= tv(g) + 1e-13)
+            g = h
+        assert g.min() >= f.min() - 1e-14 and g.max() <= f.max() + 1e-14
+        assert abs(g.sum() - f.sum()) < 1e-12 * f.sum()
+
+    @pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_PERIODIC])
+    def test_matches_numpy(self, bc):
+        p = wl.Problem(nx=11, nv=(5, 3, 2), v_lo=(-3, -2, -2), v_hi=(4, 2, 2), bc=bc, eps=INF)
+        rng = np.random.default_rng(14)
+        f = rng.uniform(0.5, 1.5, (p.nx, p.nv3))
+        f[3:5] = 1.0  # flat stretches: zero differences in the limiter
+        dt = 0.6 / p.nx / 4
+        assert relmax(oracle.transport_opts(p, f, dt, fine_order=2), npr.transport2(p, f, dt)) < 1e-14
+
+    def test_parareal_k_equals_n_with_second_order_fine(self):
+        wk = wl.c2_smooth_periodic(eps=1e-2, nx=12, nv=8, n_slices=4)
+        p = wk.problem
+        ref = oracle.serial_fine_opts(p, wk.W0, 4, wk.T, fine_order=2)
+        V, err, kd = oracle.parareal_iterate_opts(p, wk.W0, 4, wk.T, 4, 0.0, fine_order=2)
+        assert kd == 4 and np.max(np.abs(V - ref)) < 1e-13
+        assert np.max(np.abs(ref - oracle.serial_fine(p, wk.W0, 4, wk.T))) > 1e-8
+
+
 class TestErrors:
     def test_invalid_arguments(self):
         from dataclasses import replace
