@@ -250,19 +250,33 @@ int parareal_iterate_cns(const bgk_problem* prob, const double* E, double e_max,
  * Navier-Stokes model above) and the lifting order (0: Definition 2's
  * Maxwellian; 1: the order-one lifting, which the fine propagator then starts
  * from; the serial fine chain with the same order is parareal's fixed point).
- * A NULL options pointer means no force, Euler, order 0.  Workspaces and the
- * other arguments as bgk_fine_propagate_moments, parareal_iterate and
- * bgk_serial_fine. */
+ * fine_order 2 gives the fine propagator second order in x: the upwind flux
+ * with the Lax-Wendroff correction limited by van Leer's limiter (the flux
+ * limiters Section 3.1 names as the natural improvement),
+ *   v_x > 0: F_{i+1/2} = v_x [f_i + (1-nu)/2 L(f_i - f_{i-1}, f_{i+1} - f_i)],
+ *   v_x < 0: F_{i+1/2} = v_x [f_{i+1} - (1-|nu|)/2 L(f_{i+2} - f_{i+1}, f_{i+1} - f_i)],
+ * L(a, b) = 2ab/(a+b) if ab > 0 else 0, nu = v_x dt/dx, ghost cells two deep;
+ * TVD for |nu| <= 1; it runs one step per pass on the generic lane mapping
+ * (2 or 4 velocities per lane).  bgk_fine_steps_opts is bgk_fine_steps with
+ * these options (the coarse and lift fields are ignored there).
+ * A NULL options pointer means no force, Euler, order 0 lift, order 1
+ * transport.  Workspaces and the other arguments as bgk_fine_steps,
+ * bgk_fine_propagate_moments, parareal_iterate and bgk_serial_fine. */
 enum { BGK_COARSE_EULER = 0, BGK_COARSE_NAVIER_STOKES = 1 };
 typedef struct {
   const double* E;    /* exterior force at the x centres, or NULL */
   double e_max;       /* Rusanov coefficient >= max |E_i| (ignored without E) */
   int32_t coarse;     /* BGK_COARSE_EULER or BGK_COARSE_NAVIER_STOKES */
   int32_t lift_order; /* 0 or 1 */
+  int32_t fine_order; /* x transport: 1 (or 0) upwind; 2 van Leer limited */
+  int32_t reserved;   /* 0 */
 } bgk_options;
 
 int bgk_lift_ce(const bgk_problem* prob, const double* W, double* f, void* ws,
                 size_t ws_bytes, void* stream);
+int bgk_fine_steps_opts(const bgk_problem* prob, const bgk_options* opts,
+                        const double* f_in, double* f_out, double dt,
+                        int32_t n_steps, void* ws, size_t ws_bytes, void* stream);
 int bgk_fine_propagate_moments_opts(const bgk_problem* prob, const bgk_options* opts,
                                     int32_t batch, const double* V_in,
                                     double* V_out, double t_span, void* ws,

@@ -33,13 +33,13 @@ EXPORTS = [
     "bgk_fine_step_force", "bgk_fine_propagate_moments_force", "euler_coarse_step_force",
     "parareal_iterate_force", "bgk_serial_fine_force", "euler_coarse_step_cns",
     "parareal_iterate_cns", "bgk_lift_ce", "bgk_fine_propagate_moments_opts",
-    "parareal_iterate_opts", "bgk_serial_fine_opts",
+    "parareal_iterate_opts", "bgk_serial_fine_opts", "bgk_fine_steps_opts",
 ]
 
 
 class _Options(C.Structure):
     _fields_ = [("E", C.c_void_p), ("e_max", C.c_double), ("coarse", C.c_int32),
-                ("lift_order", C.c_int32)]
+                ("lift_order", C.c_int32), ("fine_order", C.c_int32), ("reserved", C.c_int32)]
 
 
 COARSE = {"euler": 0, "cns": 1}
@@ -116,6 +116,8 @@ def load_library(path: str = LIB_PATH):
         "parareal_iterate_cns": (C.c_int, [P, V, C.c_double, V, C.c_int32, C.c_double,
                                            C.c_int32, C.c_double, V, D, I, V, Z, V]),
         "bgk_lift_ce": (C.c_int, [P, V, V, V, Z, V]),
+        "bgk_fine_steps_opts": (C.c_int, [P, C.POINTER(_Options), V, V, C.c_double, C.c_int32,
+                                          V, Z, V]),
         "bgk_fine_propagate_moments_opts": (C.c_int, [P, C.POINTER(_Options), C.c_int32, V,
                                                       V, C.c_double, V, Z, V]),
         "parareal_iterate_opts": (C.c_int, [P, C.POINTER(_Options), V, C.c_int32,
@@ -272,7 +274,7 @@ def lift_ce(p, W) -> torch.Tensor:
     return f
 
 
-def _options(p, E, coarse: str, lift_order: int):
+def _options(p, E, coarse: str, lift_order: int, fine_order: int = 1):
     """(ctypes options, device force tensor kept alive by the caller)."""
     if coarse not in COARSE:
         raise ValueError("coarse must be 'euler' or 'cns'")
@@ -283,6 +285,7 @@ def _options(p, E, coarse: str, lift_order: int):
         o.E = Ed.data_ptr()
     o.coarse = COARSE[coarse]
     o.lift_order = int(lift_order)
+    o.fine_order = int(fine_order)
     return o, Ed
 
 
@@ -297,12 +300,17 @@ def moments(p, f: torch.Tensor):
 
 
 def fine_steps(p, f: torch.Tensor, dt: float, n: int, out: torch.Tensor | None = None,
-               E=None):
+               E=None, fine_order: int = 1):
+    """n IMEX steps of size dt; fine_order 2 = van Leer limited x transport."""
     L = _gpu_lib()
     out = torch.empty_like(f) if out is None else out
     w = workspace(p, OP_FINE_STEP)
     ps = C.byref(problem_struct(p))
-    if E is None:
+    if fine_order != 1:
+        o, Ed = _options(p, E, "euler", 0, fine_order)
+        rc = L.bgk_fine_steps_opts(ps, C.byref(o), _dev(f, "f_in"), _dev(out, "f_out"), dt, n,
+                                   w.data_ptr(), w.numel(), _stream())
+    elif E is None:
         rc = L.bgk_fine_steps(ps, _dev(f, "f_in"), _dev(out, "f_out"), dt, n, w.data_ptr(),
                               w.numel(), _stream())
     else:
@@ -361,7 +369,7 @@ def fine_step_batched(probs: Sequence, fs: Sequence[torch.Tensor], spans: Sequen
 
 
 def fine_propagate_moments(p, V_in: torch.Tensor, t_span: float, E=None,
-                           lift_order: int = 0) -> torch.Tensor:
+                           lift_order: int = 0, fine_order: int = 1) -> torch.Tensor:
     """Batched P F L over the leading dimension of V_in ([B][nx][5] conserved);
     lift_order 1 lifts with the first Chapman-Enskog correction."""
     L = _gpu_lib()
@@ -370,8 +378,8 @@ def fine_propagate_moments(p, V_in: torch.Tensor, t_span: float, E=None,
     out = torch.empty_like(V_in)
     w = workspace(p, OP_PROPAGATE, B)
     ps = C.byref(problem_struct(p))
-    if lift_order != 0:
-        o, Ed = _options(p, E, "euler", lift_order)
+    if lift_order != 0 or fine_order != 1:
+        o, Ed = _options(p, E, "euler", lift_order, fine_order)
         rc = L.bgk_fine_propagate_moments_opts(ps, C.byref(o), B, _dev(V_in, "V_in"),
                                                _dev(out, "V_out"), t_span, w.data_ptr(),
                                                w.numel(), _stream())
@@ -417,7 +425,7 @@ def euler_coarse_step(p, V: torch.Tensor, t_span: float, E=None, coarse: str = "
 
 
 def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=None,
-                     coarse: str = "euler", lift_order: int = 0):
+                     coarse: str = "euler", lift_order: int = 0, fine_order: int = 1):
     """Algorithm 2; coarse = "euler" or "cns" (Navier-Stokes coarse propagator);
     lift_order 1 = the order-one (Chapman-Enskog) lifting."""
     L = _gpu_lib()
@@ -429,8 +437,8 @@ def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=N
     ps = C.byref(problem_struct(p))
     if coarse not in ("euler", "cns"):
         raise ValueError("coarse must be 'euler' or 'cns'")
-    if lift_order != 0:
-        o, Ed = _options(p, E, coarse, lift_order)
+    if lift_order != 0 or fine_order != 1:
+        o, Ed = _options(p, E, coarse, lift_order, fine_order)
         rc = L.parareal_iterate_opts(ps, C.byref(o), _dev(W0, "W0"), n_slices, T, k_max, tol,
                                      _dev(V, "V_out"), err, C.byref(kd), w.data_ptr(),
                                      w.numel(), _stream())
@@ -452,15 +460,16 @@ def parareal_iterate(p, W0, n_slices: int, T: float, k_max: int, tol: float, E=N
     return V, [err[i] for i in range(kd.value)], kd.value
 
 
-def serial_fine(p, W0, n_slices: int, T: float, E=None, lift_order: int = 0) -> torch.Tensor:
+def serial_fine(p, W0, n_slices: int, T: float, E=None, lift_order: int = 0,
+                fine_order: int = 1) -> torch.Tensor:
     """The chained serial fine reference U^n = P F L(U^{n-1})."""
     L = _gpu_lib()
     W0 = _f64(W0)
     V = torch.empty((n_slices + 1, p.nx, 5), dtype=torch.float64, device="cuda")
     w = workspace(p, OP_PARAREAL, n_slices)
     ps = C.byref(problem_struct(p))
-    if lift_order != 0:
-        o, Ed = _options(p, E, "euler", lift_order)
+    if lift_order != 0 or fine_order != 1:
+        o, Ed = _options(p, E, "euler", lift_order, fine_order)
         rc = L.bgk_serial_fine_opts(ps, C.byref(o), _dev(W0, "W0"), n_slices, T,
                                     _dev(V, "V_out"), w.data_ptr(), w.numel(), _stream())
     elif E is None:

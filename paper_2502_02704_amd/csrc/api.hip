@@ -326,6 +326,7 @@ static Inst make_inst(const bgk_problem& p, int B, double dt, Tiles t, int ns = 
   I.ntiles = (I.nv3 + kWave * t.elems - 1) / (kWave * t.elems);
   I.ntg = (I.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   I.nsum = ns;
+  I.order = 1;
   I.nparts = I.ntiles;  // one partial record per wave tile
   I.nchunks = (p.nx + t.chunk - 1) / t.chunk;
   I.items = (long long)B * I.ntg * I.nchunks;
@@ -358,7 +359,9 @@ static void attach_fine(Inst& I, void* ws, const FineRegions& r, double* buf1) {
   I.aux = at<double>(ws, r.aux);
 }
 
-static int lds_doubles(const Inst& I, Tiles t) { return (t.chunk + 2) * I.nvs; }
+static int lds_doubles(const Inst& I, Tiles t) {
+  return (t.chunk + (I.order == 2 ? 4 : 2)) * I.nvs;
+}
 static int lds_doubles2(const Inst& I, Tiles t) { return (2 * t.chunk + 6) * I.nvs; }
 
 // Runs `n` relax-then-transport steps on the (uploaded) descriptor d_I.
@@ -377,7 +380,7 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
   auto single = [&](int mode) -> int {
     prof_before(s);
     int r = launch_step(d_I, 1, h.items, mode, phase, t, lds_doubles(h, t), d_status, s,
-                        h.nsum, h.efield != nullptr);
+                        h.nsum, h.efield != nullptr, h.order == 2 ? 2 : 1);
     prof_after(s, upd, mode == kLift ? 8.0 : 16.0, BGK_PROF_ONE_STEP);
     phase ^= 1;
     return r;
@@ -559,12 +562,14 @@ static int run_graph(const std::string& key, hipStream_t user, F&& enqueue) {
   return BGK_OK;
 }
 
-// ------------------------------------------------------ exterior force --
-// E: device [nx] force at the x centres (null: none); emax: the Rusanov
-// coefficient of the v_x flux, which must bound max |E_i|.
+// ------------------------------------------------------ fine-step method --
+// E: device [nx] exterior force at the x centres (null: none); emax: the
+// Rusanov coefficient of the v_x flux, which must bound max |E_i|; order: x
+// transport, 1 upwind (Section 3.1), 2 with the van Leer limited correction.
 struct Force {
   const double* E = nullptr;
   double emax = 0.0;
+  int order = 1;
   bool on() const { return E != nullptr; }
 };
 
@@ -584,20 +589,21 @@ static int check_force(const bgk_problem& p, const Force& F, int* d_status, hipS
   return BGK_OK;
 }
 
-// Force fields of a descriptor (the v_x flux needs dt / dv_x).
+// Method fields of a descriptor (the v_x flux needs dt / dv_x).
 static void attach_force(Inst& I, const bgk_problem& p, const Force& F, double dt) {
   I.efield = F.E;
   I.emax = F.emax;
   I.rv = dt / dv_of(p, 0);
+  I.order = F.order;
 }
 
 // Tiles and sums per partial for a fine solve of `n` steps: the force step
-// runs one step per pass on the generic lane mapping.
+// and the second-order step run one step per pass on the generic lane mapping.
 static Tiles fine_tiles(const bgk_problem& p, int batch, const Force& F) {
-  return choose_tiles(p, batch, F.on());
+  return choose_tiles(p, batch, F.on() || F.order == 2);
 }
 static int fine_nsum(const Tiles& t, int n, const Force& F) {
-  return (!F.on() && fused_for(t, n)) ? 15 : 5;
+  return (!F.on() && F.order != 2 && fused_for(t, n)) ? 15 : 5;
 }
 
 static int status_code(int st) {
@@ -1054,13 +1060,25 @@ int bgk_serial_fine_force(const bgk_problem* prob, const double* E, double e_max
 }
 
 static Force force_of(const bgk_options* o) {
-  return (o && o->E) ? Force{o->E, o->e_max} : Force{};
+  Force F = (o && o->E) ? Force{o->E, o->e_max} : Force{};
+  F.order = (o && o->fine_order == 2) ? 2 : 1;
+  return F;
 }
 
 static int check_options(const bgk_options* o) {
   if (o && o->coarse != BGK_COARSE_EULER && o->coarse != BGK_COARSE_NAVIER_STOKES)
     return invalid("coarse must be BGK_COARSE_EULER or BGK_COARSE_NAVIER_STOKES");
+  if (o && o->fine_order != 0 && o->fine_order != 1 && o->fine_order != 2)
+    return invalid("fine_order must be 1 or 2 (0 means 1)");
   return BGK_OK;
+}
+
+int bgk_fine_steps_opts(const bgk_problem* prob, const bgk_options* opts, const double* f_in,
+                        double* f_out, double dt, int32_t n_steps, void* ws, size_t ws_bytes,
+                        void* stream) {
+  int rc = check_options(opts);
+  if (rc) return rc;
+  return fine_steps_impl(prob, force_of(opts), f_in, f_out, dt, n_steps, ws, ws_bytes, stream);
 }
 
 int bgk_fine_propagate_moments_opts(const bgk_problem* prob, const bgk_options* opts,

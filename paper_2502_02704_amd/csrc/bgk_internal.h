@@ -57,6 +57,8 @@ struct Inst {
   const double* efield;        // exterior force E_i at x centres [nx]; null = none
   double emax;                 // Rusanov coefficient of the v_x flux (>= max |E_i|)
   double rv;                   // dt / dv_x
+  int order;                   // x transport: 1 upwind, 2 van Leer limited
+  int pad2_;
 };
 
 // Step-kernel source modes.
@@ -121,9 +123,11 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic = false);
 // Fused relax-then-transport step over all instances in `d_insts`.
 // ns: sums per partial, 5 (moments) or 15 (plus nu-weighted, paired only).
 // force: one step with the exterior-force v_x transport (generic lanes only).
+// order 2: x transport with the van Leer limited Lax-Wendroff correction
+// (generic lanes, 2 or 4 elements per lane, LDS rows for (chunk + 4) cells).
 int launch_step(const Inst* d_insts, int n_inst, long long total_items,
                 int mode, int phase, Tiles t, int lds_doubles, int* d_status,
-                hipStream_t s, int ns = 5, bool force = false);
+                hipStream_t s, int ns = 5, bool force = false, int order = 1);
 // Per-x-cell reduction of partial sums into moments and factors.
 int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
                   int mode, int phase, int* d_status, hipStream_t s);

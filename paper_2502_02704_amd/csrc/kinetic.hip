@@ -157,10 +157,26 @@ __device__ __forceinline__ double fac3(const double* row, unsigned off) {
 // row; they are read directly (other waves of the block or nearby blocks
 // read them as their own centre values, so they mostly hit L2) and relaxed
 // with the factor of the neighbouring v_x point.
-template <int E, int MODE, bool FORCE = false>
+// LIMITED: second order in x, the upwind flux with the Lax-Wendroff
+// correction limited by van Leer's limiter (five-point stencil, so the march
+// keeps rows i-2 .. i+2 and the ghost cells are two deep).
+__device__ __forceinline__ double vl_limited(double a, double b) {
+  return a * b > 0.0 ? 2.0 * a * b / (a + b) : 0.0;
+}
+
+// Limited flux through the face between f0 (cell i) and fp (cell i+1).
+__device__ __forceinline__ double flux2(double vx, double nu, double fm, double f0,
+                                        double fp, double fp2) {
+  if (vx > 0.0) return vx * (f0 + 0.5 * (1.0 - nu) * vl_limited(f0 - fm, fp - f0));
+  if (vx < 0.0) return vx * (fp - 0.5 * (1.0 + nu) * vl_limited(fp2 - fp, fp - f0));
+  return 0.0;
+}
+
+template <int E, int MODE, bool FORCE = false, bool LIMITED = false>
 __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
                                                  int n_inst, int chunk,
                                                  int phase) {
+  constexpr int H = LIMITED ? 2 : 1;  // stencil half-width in x
   extern __shared__ double lds[];
   const long long item = xcd_item(blockIdx.x, gridDim.x);
   const int q = find_inst(insts, n_inst, item);
@@ -171,15 +187,16 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
   const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
   const int i0 = c * chunk;
   const int i1 = min(i0 + chunk, nx);
+  const int rbase = i0 - H;  // first staged factor row
 
   if (MODE != kCopy) {
-    // factor rows of cells i0-1 .. i1 (ghosts mapped by the BC)
-    const int rows = i1 - i0 + 2;
+    // factor rows of cells i0-H .. i1+H-1 (ghosts mapped by the BC)
+    const int rows = i1 - i0 + 2 * H;
     const double* fac = I.fac + (long long)b * nx * nvs;
     for (int idx = threadIdx.x; idx < rows * nvs; idx += kBlock) {
       int rr = idx / nvs;
       int k = idx - rr * nvs;
-      lds[idx] = fac[(long long)ghost_row(i0 - 1 + rr, nx, I.bc) * nvs + k];
+      lds[idx] = fac[(long long)ghost_row(rbase + rr, nx, I.bc) * nvs + k];
     }
     __syncthreads();
   }
@@ -203,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
 
   // relaxed value of row r (global row index, ghost-mapped) from raw g
   auto relax_row = [&](int r, const double* raw, double* out) {
-    const double* frow = lds + (r - (i0 - 1)) * nvs;
+    const double* frow = lds + (r - rbase) * nvs;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       double v;
@@ -220,19 +237,17 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
     for (int e = 0; e < E; ++e) raw[e] = el.ok[e] ? src[ro + e * kWave] : 0.0;
   };
 
-  double fm[E], f0[E], fp[E], rawp[E], rawn[E];
+  // relaxed rows i-H .. i+H of the march; raw row i+H (rawp) and i+H+1 (rawn)
+  double w[2 * H + 1][E], rawp[E], rawn[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) rawn[e] = 0.0;
-  {
-    double raw[E];
-    load_row(i0 - 1, raw);
-    load_row(i0, rawp);
-    relax_row(i0 - 1, raw, fm);
-    load_row(i0 + 1, raw);
-    relax_row(i0, rawp, f0);
 #pragma unroll
-    for (int e = 0; e < E; ++e) rawp[e] = raw[e];
+  for (int k = 0; k < 2 * H; ++k) {
+    double raw[E];
+    load_row(i0 - H + k, raw);
+    relax_row(i0 - H + k, raw, w[k]);
   }
+  load_row(i0 + H, rawp);
   // FORCE: raw values at the v_x neighbours (dn: -nyz, up: +nyz) of each
   // element, loaded one row ahead of their use; relaxed with the factor of
   // the neighbouring v_x point (the Ex index is the low field of off)
@@ -249,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
     }
   };
   auto relax_vnb = [&](int r, int e, int dir, double raw) -> double {
-    const double* frow = lds + (r - (i0 - 1)) * nvs;
+    const double* frow = lds + (r - rbase) * nvs;
     const unsigned off = el.off[e] + (unsigned)dir;
     if (MODE == kCopy) return raw;
     if (MODE == kRelax) return fma(a, raw, fac3(frow, off));
@@ -258,19 +273,28 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
   if (FORCE) load_vnb(i0, dn_cur, up_cur);
   double* part = I.part + (((long long)b * nx) * I.part_tiles + tile) * 5;
   for (int i = i0; i < i1; ++i) {
-    if (i + 2 <= i1) load_row(i + 2, rawn);  // prefetch the next row
+    if (i + 2 <= i1) load_row(i + H + 1, rawn);  // prefetch the next row
     if (FORCE && i + 1 < i1) load_vnb(i + 1, dn_nxt, up_nxt);
-    relax_row(i + 1, rawp, fp);
+    relax_row(i + H, rawp, w[2 * H]);
     double Ei = 0.0;
     if (FORCE) Ei = I.efield[i];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const double nb = nu[e] > 0.0 ? fm[e] : fp[e];
-      double gs = fma(fabs(nu[e]), nb - f0[e], f0[e]);
+      double gs;
+      if (LIMITED) {
+        const double fr = flux2(el.vx[e], nu[e], w[H - 1][e], w[H][e], w[H + 1][e],
+                                w[H + 2 < 2 * H + 1 ? H + 2 : 2 * H][e]);
+        const double fl = flux2(el.vx[e], nu[e], w[H - 2 >= 0 ? H - 2 : 0][e], w[H - 1][e],
+                                w[H][e], w[H + 1][e]);
+        gs = w[H][e] - I.r * (fr - fl);
+      } else {
+        const double nb = nu[e] > 0.0 ? w[H - 1][e] : w[H + 1][e];
+        gs = fma(fabs(nu[e]), nb - w[H][e], w[H][e]);
+      }
       if (FORCE && el.ok[e]) {
         const int jx = (int)(el.off[e] & 1023u);
-        const double c = f0[e];
+        const double c = w[H][e];
         double g_up = 0.0, g_down = 0.0;
         if (jx + 1 < I.nvx) {
           const double u = relax_vnb(i, e, 1, up_cur[e]);
@@ -306,8 +330,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      fm[e] = f0[e];
-      f0[e] = fp[e];
+#pragma unroll
+      for (int k = 0; k < 2 * H; ++k) w[k][e] = w[k + 1][e];
       rawp[e] = rawn[e];
       if (FORCE) {
         dn_cur[e] = dn_nxt[e];
@@ -1274,7 +1298,7 @@ static int blocks_for(long long n) { return (int)n; }
 
 int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode,
                 int phase, Tiles t, int lds_doubles, int* d_status, hipStream_t s,
-                int ns, bool force) {
+                int ns, bool force, int order) {
   (void)d_status;
   if (total_items <= 0) return BGK_OK;
   dim3 grid(blocks_for(total_items)), block(kBlock);
@@ -1287,7 +1311,27 @@ int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode
     hipError_t e_ = hipGetLastError();                                      \
     return e_ == hipSuccess ? BGK_OK : hip_fail(e_, "k_step");              \
   }
-  if (force) {
+  if (order == 2) {
+    if (t.pair || ns != 5) {
+      set_error("the second-order step uses the generic lane mapping, one step per pass");
+      return BGK_E_INVALID;
+    }
+    if (force) {
+      BGK_STEP_CASE((k_step<2, kCopy, true, true>), 2, kCopy)
+      BGK_STEP_CASE((k_step<2, kRelax, true, true>), 2, kRelax)
+      BGK_STEP_CASE((k_step<2, kLift, true, true>), 2, kLift)
+      BGK_STEP_CASE((k_step<4, kCopy, true, true>), 4, kCopy)
+      BGK_STEP_CASE((k_step<4, kRelax, true, true>), 4, kRelax)
+      BGK_STEP_CASE((k_step<4, kLift, true, true>), 4, kLift)
+    } else {
+      BGK_STEP_CASE((k_step<2, kCopy, false, true>), 2, kCopy)
+      BGK_STEP_CASE((k_step<2, kRelax, false, true>), 2, kRelax)
+      BGK_STEP_CASE((k_step<2, kLift, false, true>), 2, kLift)
+      BGK_STEP_CASE((k_step<4, kCopy, false, true>), 4, kCopy)
+      BGK_STEP_CASE((k_step<4, kRelax, false, true>), 4, kRelax)
+      BGK_STEP_CASE((k_step<4, kLift, false, true>), 4, kLift)
+    }
+  } else if (force) {
     if (t.pair) {
       set_error("the force step uses the generic lane mapping");
       return BGK_E_INVALID;
