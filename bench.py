@@ -186,6 +186,28 @@ def force_throughput(torch, bgk, wl, reps=5):
             "step_kernel_avg_us": round(ms * 1e3 / max(launches, 1), 2)}
 
 
+def second_order_throughput(torch, bgk, V, p, span, reps=2):
+    """The second-order (van Leer limited) fine transport on the benchmark
+    batch: one step per pass (16 algorithmic bytes per update)."""
+    n, _ = bgk.n_steps(p, span)
+    bgk.fine_propagate_moments(p, V, span, fine_order=2)
+    torch.cuda.synchronize()
+    bgk.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bgk.fine_propagate_moments(p, V, span, fine_order=2)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    ms, launches, upd, by = bgk.prof_read(bgk.PROF_ONE_STEP)
+    bgk.prof_enable(False)
+    bgk.check_status()
+    B = V.shape[0]
+    return {"workload": f"smooth_periodic_nx{p.nx}_nv{p.nv[0]}_slices{B}", "steps": n,
+            "updates_per_s": B * p.cells * n / el, "ms_per_call": round(el * 1e3, 3),
+            "step_kernel_GBs": round(by / (ms * 1e-3) / 1e9, 1),
+            "step_kernel_avg_us": round(ms * 1e3 / max(launches, 1), 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +291,7 @@ def main():
     if not args.no_parareal:
         line["parareal"] = parareal_speedup(torch, bgk, wl)
         line["exterior_force"] = force_throughput(torch, bgk, wl)
+        line["second_order_fine"] = second_order_throughput(torch, bgk, V, p, span)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wk, V_np, span)
     print(json.dumps(line), flush=True)
