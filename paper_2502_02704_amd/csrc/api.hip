@@ -405,7 +405,9 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
     done += 2;
     return r;
   };
-  if (first_mode == kLift && n >= 2) {
+  // An odd step count takes its single step first, from the lift: that pass
+  // only writes f (8 bytes per update instead of the 16 of a later single).
+  if (first_mode == kLift && n >= 2 && n % 2 == 0) {
     if ((rc = reduce(kRedW2))) return rc;
     if ((rc = pair_pass(kLift))) return rc;
   } else {
