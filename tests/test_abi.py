@@ -58,3 +58,49 @@ def test_problem_struct_layout_matches_oracle():
     import oracle
     assert ctypes.sizeof(bgk._Problem) == ctypes.sizeof(oracle._Problem)
     assert [f[0] for f in bgk._Problem._fields_] == [f[0] for f in oracle._Problem._fields_]
+
+
+def test_host_side_validation_of_the_widened_entry_points():
+    """Option and argument checks of the exterior-force, Navier-Stokes,
+    order-one lifting and second-order calls fail before any device work."""
+    from dataclasses import replace
+    import oracle
+    lib = bgk.load_library()
+    fk = wl.c6_two_beam_force()
+    p = fk.problem
+    ps = ctypes.byref(bgk.problem_struct(p))
+    span = fk.T / fk.n_slices
+    # step rule with a force: library and oracle agree (host arithmetic only)
+    assert bgk.n_steps(p, span, E=fk.E) == oracle.n_steps(p, span, E=fk.E)
+    n, dt = ctypes.c_int32(), ctypes.c_double()
+    assert lib.bgk_n_steps_force(ps, -1.0, span, ctypes.byref(n), ctypes.byref(dt)) == bgk.E_INVALID
+    # a force call without its force array
+    assert lib.bgk_fine_steps_force(ps, None, 1.0, None, None, 1e-3, 1, None, 0,
+                                    None) == bgk.E_INVALID
+    # the Navier-Stokes model and the order-one lifting need a finite eps
+    pinf = ctypes.byref(bgk.problem_struct(replace(p, eps=float("inf"))))
+    assert lib.euler_coarse_step_cns(pinf, None, 1, None, None, 0.1, None, None, 0,
+                                     None) == bgk.E_INVALID
+    assert lib.bgk_lift_ce(pinf, None, None, None, 0, None) == bgk.E_INVALID
+    # option fields out of range
+    o = bgk._Options()
+    o.coarse = 7
+    err = (ctypes.c_double * 1)()
+    kd = ctypes.c_int32()
+    assert lib.parareal_iterate_opts(ps, ctypes.byref(o), None, 4, 0.1, 1, 0.0, None, err,
+                                     ctypes.byref(kd), None, 0, None) == bgk.E_INVALID
+    o.coarse = 0
+    o.fine_order = 3
+    assert lib.bgk_fine_steps_opts(ps, ctypes.byref(o), None, None, 1e-3, 1, None, 0,
+                                   None) == bgk.E_INVALID
+    o.fine_order = 1
+    o.lift_order = 2
+    assert lib.bgk_serial_fine_opts(ps, ctypes.byref(o), None, 4, 0.1, None, None, 0,
+                                    None) == bgk.E_INVALID
+
+
+def test_options_struct_layout():
+    # pointer, double, four int32: 32 bytes, as include/bgk.h lays it out
+    assert ctypes.sizeof(bgk._Options) == 32
+    assert [f[0] for f in bgk._Options._fields_] == ["E", "e_max", "coarse", "lift_order",
+                                                      "fine_order", "reserved"]
