@@ -10,7 +10,8 @@ CPU oracle timed on a bounded sample, and the parareal vs serial-fine speedup
 on two small workloads where one slice's step is latency bound.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--eps E]
-       [--no-cpu-baseline] [--no-parareal] [--copy-calibration]
+       [--no-cpu-baseline] [--no-parareal] [--extras parareal,force,order2]
+       [--copy-calibration]
 """
 import argparse
 import hashlib
@@ -157,8 +158,9 @@ def force_throughput(torch, bgk, wl, reps=5):
     """The exterior-force path on the two-beam test grid (Nx=100,
     256x16x16 velocities, eps=1e-5): all 20 slices of the first parareal
     iteration batched, lift + 21 steps (one per pass, with the v_x Rusanov
-    transport) + projection.  Updates/s of the whole call and HBM rate of the
-    one-step kernel (16 algorithmic bytes per update)."""
+    transport, lanes on v_x columns) + projection.  Updates/s of the whole
+    call and HBM rate of the one-step kernel (16 algorithmic bytes per
+    update, 8 for the lifted first step)."""
     import numpy as np
     wk = wl.c6_two_beam_force()
     p, N = wk.problem, wk.n_slices
@@ -215,7 +217,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-parareal", action="store_true")
+    ap.add_argument("--no-parareal", action="store_true",
+                    help="skip every section after the main line (same as --extras '')")
+    ap.add_argument("--extras", default="parareal,force,order2",
+                    help="comma list of the extra sections: parareal, force, order2")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -288,9 +293,12 @@ def main():
                        "fine_steps_per_slice": n_fine, "eps": p.eps, "bc": "periodic",
                        "updates_per_step": updates_per_step},
             "roofline": roofline}
-    if not args.no_parareal:
+    extras = set() if args.no_parareal else {x for x in args.extras.split(",") if x}
+    if "parareal" in extras:
         line["parareal"] = parareal_speedup(torch, bgk, wl)
+    if "force" in extras:
         line["exterior_force"] = force_throughput(torch, bgk, wl)
+    if "order2" in extras:
         line["second_order_fine"] = second_order_throughput(torch, bgk, V, p, span)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wk, V_np, span)

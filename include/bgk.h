@@ -328,7 +328,13 @@ const char* bgk_last_error(void);
 /* Tile shape of the fused step kernel: velocity elements per lane (2, 4 or 8)
  * and x cells per work item (1..64); 0 restores the built-in choice.  pair:
  * 1 = lanes own pairs of adjacent v_z cells (used only when nv[2] is even and
- * f is 16-byte aligned), 0 = one velocity per lane slot, -1 = built-in. */
+ * f is 16-byte aligned), 0 = one velocity per lane slot, -1 = built-in,
+ * 2 = the exterior-force step on v_x columns (a lane owns one (v_y, v_z)
+ * point and elems consecutive v_x points) even where nv[1] nv[2] < 64, 3 =
+ * the same with two adjacent (v_y, v_z) points per lane (even nv[1] nv[2],
+ * 16-byte aligned f, elems 2 or 4); the built-in choice takes columns, paired
+ * where it can, when nv[1] nv[2] >= 64, and 0 keeps that step on the flat
+ * mapping. */
 int bgk_set_tiles(int32_t elems_per_lane, int32_t x_chunk, int32_t pair);
 
 /* Times candidate tile shapes on `prob` with `batch` members (uses ws of

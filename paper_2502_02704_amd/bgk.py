@@ -516,6 +516,9 @@ def density_adjoint(p, rhobar: torch.Tensor) -> torch.Tensor:
 
 
 def set_tiles(elems: int = 0, chunk: int = 0, pair: int = -1):
+    """Tile shape of the step kernels (0 / -1: built-in).  pair: 1 paired
+    v_z lanes, 0 one velocity per lane slot; the exterior-force step on v_x
+    columns with 2 one, 3 two (v_y, v_z) points per lane."""
     _check(load_library().bgk_set_tiles(elems, chunk, pair), "bgk_set_tiles")
 
 

@@ -88,15 +88,33 @@ static long long nv3_of(const bgk_problem& p) {
   return (long long)p.nv[0] * p.nv[1] * p.nv[2];
 }
 
+// Wave tiles per x cell: runs of 64 * elems flat velocities, or with the
+// v_x-column mapping blocks of 64 (v_y, v_z) points by elems v_x points.
+static long long ntiles_of(const bgk_problem& p, Tiles t) {
+  if (t.vcol) {
+    const long long nyz = (long long)p.nv[1] * p.nv[2];
+    const long long span = (long long)kWave * (t.pair ? 2 : 1);
+    return ((nyz + span - 1) / span) * ((p.nv[0] + t.elems - 1) / t.elems);
+  }
+  return (nv3_of(p) + kWave * t.elems - 1) / (kWave * t.elems);
+}
+
+static int part_tiles_of(const bgk_problem& p);
+
 static long long blocks_for_tiles(const bgk_problem& p, int batch, Tiles t) {
-  const long long ntiles = (nv3_of(p) + kWave * t.elems - 1) / (kWave * t.elems);
+  const long long ntiles = ntiles_of(p, t);
   const long long ntg = (ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   return (long long)batch * ntg * ((p.nx + t.chunk - 1) / t.chunk);
 }
 
 static bool g_fuse2 = true;  // two IMEX steps per pass where possible
 
-Tiles choose_tiles(const bgk_problem& p, int batch, bool generic) {
+// The v_x-column mapping fits a grid whose tiles fit the partial-sum capacity.
+static bool vcol_fits(const bgk_problem& p, Tiles t) {
+  return ntiles_of(p, t) <= part_tiles_of(p);
+}
+
+Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force) {
   std::lock_guard<std::mutex> lk(g_mu);
   const int pair = (p.nv[2] % 2 == 0 && !generic) ? 1 : 0;
   // measured best on the 512 x 32^3 x 64-slice batch with 8-wave blocks:
@@ -105,9 +123,26 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic) {
   Tiles t = (pair && g_fuse2) ? Tiles{8, 8, 1} : Tiles{8, 4, pair};
   auto it = g_tuned.find({p.nx, p.nv[0], p.nv[1], p.nv[2], batch});
   const long long cells = (long long)batch * p.nx * nv3_of(p);
+  // The exterior-force step runs on v_x columns (the v_x neighbours of a
+  // lane's elements in its own registers) when a v_x plane fills a wave, or
+  // when asked to (pair = 2: one (v_y, v_z) point per lane, 3: two), else on
+  // the flat mapping below.  Built-in: two points per lane (16-byte
+  // accesses) when nvy nvz is even.
+  const long long nyz = (long long)p.nv[1] * p.nv[2];
+  const int ov = g_override.pair;
+  if (force && (ov >= 2 || (ov != 0 && nyz >= kWave))) {
+    // measured on the 100 x 256x16x16 two-beam grid: 4 v_x points by 2
+    // (v_y, v_z) points per lane over 8-cell chunks, for 1 and 20 slices
+    Tiles c = {4, 8, (nyz % 2 == 0 && ov != 2) ? 1 : 0, 1};
+    while (c.chunk > 1 && blocks_for_tiles(p, batch, c) < 128) c.chunk /= 2;
+    if (g_override.elems) c.elems = g_override.elems;
+    if (g_override.chunk) c.chunk = g_override.chunk;
+    if (c.elems == 8) c.pair = 0;  // paired columns take 2 or 4 v_x points
+    if (vcol_fits(p, c)) return c;
+  }
   if (generic) {
-    // the exterior-force step (measured on the 100 x 256x16x16 two-beam grid):
-    // 2 velocities per lane keep its extra neighbour registers unspilled
+    // the exterior-force step on the flat mapping, and the second-order
+    // step: 2 velocities per lane keep the extra registers unspilled
     t = Tiles{2, 8, 0};
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 512) t.chunk /= 2;
   } else if (it != g_tuned.end()) t = it->second;
@@ -124,14 +159,19 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic) {
   }
   if (g_override.elems) t.elems = g_override.elems;
   if (g_override.chunk) t.chunk = g_override.chunk;
-  if (g_override.pair >= 0 && p.nv[2] % 2 == 0 && !generic) t.pair = g_override.pair;
+  if ((g_override.pair == 0 || g_override.pair == 1) && p.nv[2] % 2 == 0 && !generic)
+    t.pair = g_override.pair;
   return t;
 }
 
 // The paired kernel needs 16-byte aligned rows of f.
-static Tiles aligned_tiles(Tiles t, std::initializer_list<const void*> ptrs) {
+// Columns without pairs have more tiles: back to the flat mapping where they
+// exceed the partial-sum capacity.
+static Tiles aligned_tiles(Tiles t, const bgk_problem& p,
+                           std::initializer_list<const void*> ptrs) {
   for (const void* q : ptrs)
     if (q && reinterpret_cast<uintptr_t>(q) % 16 != 0) t.pair = 0;
+  if (t.vcol && !vcol_fits(p, t)) t = Tiles{2, t.chunk, 0, 0};
   return t;
 }
 
@@ -323,7 +363,7 @@ static Inst make_inst(const bgk_problem& p, int B, double dt, Tiles t, int ns = 
   I.nvs = p.nv[0] + p.nv[1] + p.nv[2];
   I.bc = p.bc;
   I.nbatch = B;
-  I.ntiles = (I.nv3 + kWave * t.elems - 1) / (kWave * t.elems);
+  I.ntiles = (int)ntiles_of(p, t);
   I.ntg = (I.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   I.nsum = ns;
   I.order = 1;
@@ -602,7 +642,7 @@ static void attach_force(Inst& I, const bgk_problem& p, const Force& F, double d
 // Tiles and sums per partial for a fine solve of `n` steps: the force step
 // and the second-order step run one step per pass on the generic lane mapping.
 static Tiles fine_tiles(const bgk_problem& p, int batch, const Force& F) {
-  return choose_tiles(p, batch, F.on() || F.order == 2);
+  return choose_tiles(p, batch, F.on() || F.order == 2, F.on());
 }
 static int fine_nsum(const Tiles& t, int n, const Force& F) {
   return (!F.on() && F.order != 2 && fused_for(t, n)) ? 15 : 5;
@@ -728,7 +768,7 @@ static int fine_steps_impl(const bgk_problem* prob, const Force& F, const double
     BGK_HIP(hipMemcpyAsync(f_out, f_in, fbytes, hipMemcpyDeviceToDevice, s));
     return BGK_OK;
   }
-  const Tiles t = aligned_tiles(fine_tiles(*prob, 1, F), {f_in, f_out});
+  const Tiles t = aligned_tiles(fine_tiles(*prob, 1, F), *prob, {f_in, f_out});
   Inst I = make_inst(*prob, 1, dt, t, fine_nsum(t, n_steps, F));
   attach_fine(I, ws, L.fine, f_out);  // ping-pong between ws and f_out
   attach_force(I, *prob, F, dt);
@@ -931,7 +971,8 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
     };
     if ((rc = run_graph(graph_key("pit", ws, ws_bytes, *prob,
                                   {(double)n_slices, span, (double)k, (double)t.elems,
-                                   (double)t.chunk, (double)t.pair, (double)I.nsum,
+                                   (double)t.chunk, (double)(t.pair + 2 * t.vcol),
+                                   (double)I.nsum,
                                    tol > 0.0 ? 1.0 : 0.0, (double)(uintptr_t)F.E, F.emax,
                                    viscous ? 1.0 : 0.0, (double)lift_order}),
                         s, iteration)))
@@ -1039,7 +1080,8 @@ static int serial_impl(const bgk_problem* prob, const Force& F, int lift_order,
   };
   if ((rc = run_graph(graph_key("ser", ws, ws_bytes, *prob,
                                 {(double)n_slices, span, (double)t.elems, (double)t.chunk,
-                                 (double)t.pair, (double)ns, (double)(uintptr_t)F.E, F.emax,
+                                 (double)(t.pair + 2 * t.vcol), (double)ns,
+                                 (double)(uintptr_t)F.E, F.emax,
                                  (double)lift_order}),
                       s, chain)))
     return rc;
@@ -1320,7 +1362,7 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   Tiles t = {4, 8, 1};
   for (int q = 0; q < n; ++q) {
     if (probs[q].nv[2] % 2 != 0) t.pair = 0;
-    t = aligned_tiles(t, {f_in[q], f_out[q]});
+    t = aligned_tiles(t, probs[q], {f_in[q], f_out[q]});
   }
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -1382,7 +1424,7 @@ int bgk_set_tiles(int32_t elems, int32_t chunk, int32_t pair) {
   if (!(elems == 0 || elems == 2 || elems == 4 || elems == 8))
     return invalid("elems_per_lane must be 0, 2, 4 or 8");
   if (chunk < 0 || chunk > kMaxChunk) return invalid("x_chunk must be in [0, 64]");
-  if (pair < -1 || pair > 1) return invalid("pair must be -1, 0 or 1");
+  if (pair < -1 || pair > 3) return invalid("pair must be -1, 0, 1, 2 or 3");
   std::lock_guard<std::mutex> lk(g_mu);
   g_override = {elems, chunk, pair};
   return BGK_OK;

@@ -115,14 +115,19 @@ struct Tiles {
   int elems;   // velocity elements per lane
   int chunk;   // x cells per work item
   int pair;    // 1: lanes own pairs of adjacent velocities (needs even nv_z)
+  int vcol;    // 1: lanes own (v_y, v_z) points, elements run along v_x
+               //    (exterior-force step only; elems = v_x points per lane)
 };
 
-// generic: tiles for the generic lane mapping (no velocity pairs).
-Tiles choose_tiles(const bgk_problem& p, int batch, bool generic = false);
+// generic: tiles for the generic lane mapping (no velocity pairs); force:
+// the exterior-force step, on v_x columns where the grid allows.
+Tiles choose_tiles(const bgk_problem& p, int batch, bool generic = false,
+                   bool force = false);
 
 // Fused relax-then-transport step over all instances in `d_insts`.
 // ns: sums per partial, 5 (moments) or 15 (plus nu-weighted, paired only).
-// force: one step with the exterior-force v_x transport (generic lanes only).
+// force: one step with the exterior-force v_x transport (generic lanes, or
+// the v_x-column mapping t.vcol).
 // order 2: x transport with the van Leer limited Lax-Wendroff correction
 // (generic lanes, 2 or 4 elements per lane, LDS rows for (chunk + 4) cells).
 int launch_step(const Inst* d_insts, int n_inst, long long total_items,

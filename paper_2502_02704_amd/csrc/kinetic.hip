@@ -579,6 +579,254 @@ struct Acc {
   }
 };
 
+// ----------------------------------------- v_x-column exterior-force step --
+// The exterior-force step with lanes owning (v_y, v_z) points and the E
+// elements of a lane running along v_x.  The v_x neighbours of every element
+// but the first and the last are then in registers, and the two v_x planes
+// just outside the tile (its halo planes) are one coalesced load each; the
+// factor of element e is (Mx[x0 + e] My[v_y]) Mz[v_z], the same product as
+// in the other step kernels, with My and Mz read once per x row.  A lane owns
+// PY adjacent (v_y, v_z) points (PY = 2: 16-byte loads and stores; needs an
+// even nvy nvz and 16-byte aligned f).  Tile t of an x cell covers the
+// (v_y, v_z) points 64 PY (t mod nyzb) + PY lane + {0 .. PY-1} and the v_x
+// points x0 + e, x0 = E (t div nyzb), with nyzb = ceil(nvy nvz / (64 PY)).
+// The v_x flux through the face between two neighbouring v_x points is
+// computed once and used by both (Rusanov flux, no flux through the ends of
+// the v_x range).
+template <int PY>
+struct Col {
+  double v[PY];
+};
+
+template <int PY>
+__device__ __forceinline__ Col<PY> ld_col(const double* p) {
+  Col<PY> c;
+  if constexpr (PY == 2) {
+    const double2 t = *reinterpret_cast<const double2*>(p);
+    c.v[0] = t.x;
+    c.v[1] = t.y;
+  } else {
+    c.v[0] = *p;
+  }
+  return c;
+}
+
+template <int PY>
+__device__ __forceinline__ void st_col(double* p, const Col<PY>& c) {
+  if constexpr (PY == 2) {
+    *reinterpret_cast<double2*>(p) = make_double2(c.v[0], c.v[1]);
+  } else {
+    *p = c.v[0];
+  }
+}
+
+template <int E, int MODE, bool LIMITED, int PY>
+__global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ insts,
+                                                      int n_inst, int chunk, int phase) {
+  constexpr int H = LIMITED ? 2 : 1;
+  extern __shared__ double lds[];
+  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const int q = find_inst(insts, n_inst, item);
+  const Inst& I = insts[q];
+  const long long local = item - I.item_begin;
+  int b, tg, c;
+  decode_item(I, local, b, tg, c);
+  const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
+  const int i0 = c * chunk;
+  const int i1 = min(i0 + chunk, nx);
+  const int rbase = i0 - H;
+
+  if (MODE != kCopy) {
+    const int rows = i1 - i0 + 2 * H;
+    const double* fac = I.fac + (long long)b * nx * nvs;
+    for (int idx = threadIdx.x; idx < rows * nvs; idx += kBlock) {
+      int rr = idx / nvs;
+      int k = idx - rr * nvs;
+      lds[idx] = fac[(long long)ghost_row(rbase + rr, nx, I.bc) * nvs + k];
+    }
+    __syncthreads();
+  }
+
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int tile = __builtin_amdgcn_readfirstlane(tg * kWavesPerBlock + wave);
+  if (tile >= I.ntiles) return;
+
+  const int nvx = I.nvx;
+  const int nyz = I.nvy * I.nvz;
+  const int nyzb = (nyz + kWave * PY - 1) / (kWave * PY);
+  const int yz = (tile % nyzb) * (kWave * PY) + PY * lane;
+  const int x0 = (tile / nyzb) * E;       // first v_x point of the tile
+  const int nel = min(E, nvx - x0);       // v_x points in the tile (wave-uniform)
+  const bool ok = yz < nyz;               // PY = 2: nyz even, so yz + 1 < nyz too
+  const bool has_dn = x0 > 0;             // v_x plane x0 - 1 exists
+  const bool has_up = x0 + E < nvx;       // v_x plane x0 + E exists (nel == E)
+  int oy[PY], oz[PY];                     // factor-row offsets
+  double vy[PY], vz[PY], vyz2[PY];
+#pragma unroll
+  for (int p = 0; p < PY; ++p) {
+    const int jj = ok ? yz + p : 0;
+    const int jy = jj / I.nvz;
+    const int jz = jj - jy * I.nvz;
+    oy[p] = nvx + jy;
+    oz[p] = nvx + I.nvy + jz;
+    vy[p] = vgrid(I, 1, jy);
+    vz[p] = vgrid(I, 2, jz);
+    vyz2[p] = vy[p] * vy[p] + vz[p] * vz[p];
+  }
+  double vx[E], nu[E];
+  int ox[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    ox[e] = min(x0 + e, nvx - 1);
+    vx[e] = vgrid(I, 0, ox[e]);
+    nu[e] = vx[e] * I.r;
+  }
+  const long long mbase = (long long)b * nx * nv3 + (long long)x0 * nyz + yz;
+  const double* src = ((MODE == kCopy) ? I.fin : I.buf[phase]) + mbase;
+  double* dst = I.buf[phase ^ 1] + mbase;
+  const double a = I.a;
+
+  auto relax1 = [&](double raw, double fe) -> double {
+    if (MODE == kCopy) return raw;
+    if (MODE == kRelax) return fma(a, raw, fe);
+    return fe;
+  };
+  // (values of dead elements, e >= nel or a lane past nvy nvz, are finite
+  // and never used: their results are zeroed and their faces carry no flux)
+  auto relax_row = [&](int r, const Col<PY>* raw, Col<PY>* out) {
+    const double* frow = lds + (r - rbase) * nvs;
+    double my[PY], mz[PY];
+#pragma unroll
+    for (int p = 0; p < PY; ++p) {
+      my[p] = (MODE == kCopy) ? 0.0 : frow[oy[p]];
+      mz[p] = (MODE == kCopy) ? 0.0 : frow[oz[p]];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double mx = (MODE == kCopy) ? 0.0 : frow[ox[e]];
+#pragma unroll
+      for (int p = 0; p < PY; ++p) out[e].v[p] = relax1(raw[e].v[p], mx * my[p] * mz[p]);
+    }
+  };
+  auto load_row = [&](int r, Col<PY>* raw) {
+    if (MODE == kLift) return;
+    const long long ro = (long long)ghost_row(r, nx, I.bc) * nv3;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (ok && e < nel) raw[e] = ld_col<PY>(src + ro + (long long)e * nyz);
+      else
+#pragma unroll
+        for (int p = 0; p < PY; ++p) raw[e].v[p] = 0.0;
+    }
+  };
+  // raw values of the halo planes of centre row r (loaded one row ahead)
+  auto load_halo = [&](int r, Col<PY>& dn, Col<PY>& up) {
+    const long long ro = (long long)r * nv3;
+#pragma unroll
+    for (int p = 0; p < PY; ++p) dn.v[p] = up.v[p] = 0.0;
+    if (MODE == kLift || !ok) return;
+    if (has_dn) dn = ld_col<PY>(src + ro - nyz);
+    if (has_up) up = ld_col<PY>(src + ro + (long long)E * nyz);
+  };
+
+  Col<PY> w[2 * H + 1][E], rawp[E], rawn[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+#pragma unroll
+    for (int p = 0; p < PY; ++p) rawp[e].v[p] = rawn[e].v[p] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2 * H; ++k) {
+    Col<PY> raw[E];
+    load_row(i0 - H + k, raw);
+    relax_row(i0 - H + k, raw, w[k]);
+  }
+  load_row(i0 + H, rawp);
+  Col<PY> dn_cur, up_cur, dn_nxt, up_nxt;
+  load_halo(i0, dn_cur, up_cur);
+#pragma unroll
+  for (int p = 0; p < PY; ++p) dn_nxt.v[p] = up_nxt.v[p] = 0.0;
+  const double hm = 0.5 * I.emax;
+  double* part = I.part + ((long long)b * nx * I.part_tiles + tile) * 5;
+  for (int i = i0; i < i1; ++i) {
+    if (i + 2 <= i1) load_row(i + H + 1, rawn);  // prefetch the next row
+    if (i + 1 < i1) load_halo(i + 1, dn_nxt, up_nxt);
+    relax_row(i + H, rawp, w[2 * H]);
+    const double he = 0.5 * I.efield[i];
+    const double* frow = lds + (i - rbase) * nvs;
+    // v_x face fluxes: face k lies below element k (k = 0 .. E); the halo
+    // values are relaxed with the factors of row i
+    double G[E + 1][PY];
+#pragma unroll
+    for (int p = 0; p < PY; ++p) {
+      const double myz = (MODE == kCopy) ? 0.0 : frow[oy[p]];
+      const double mzz = (MODE == kCopy) ? 0.0 : frow[oz[p]];
+      double hd = 0.0, hu = 0.0;
+      if (has_dn) hd = relax1(dn_cur.v[p], (MODE == kCopy) ? 0.0 : frow[x0 - 1] * myz * mzz);
+      if (has_up) hu = relax1(up_cur.v[p], (MODE == kCopy) ? 0.0 : frow[x0 + E] * myz * mzz);
+      G[0][p] = has_dn ? he * (hd + w[H][0].v[p]) - hm * (w[H][0].v[p] - hd) : 0.0;
+#pragma unroll
+      for (int k = 1; k < E; ++k)
+        G[k][p] = (k < nel) ? he * (w[H][k - 1].v[p] + w[H][k].v[p]) -
+                                  hm * (w[H][k].v[p] - w[H][k - 1].v[p])
+                            : 0.0;
+      G[E][p] = has_up ? he * (w[H][E - 1].v[p] + hu) - hm * (hu - w[H][E - 1].v[p]) : 0.0;
+    }
+    double u0[PY], t1 = 0.0, t4 = 0.0;
+#pragma unroll
+    for (int p = 0; p < PY; ++p) u0[p] = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const bool live = ok && e < nel;
+      Col<PY> out;
+#pragma unroll
+      for (int p = 0; p < PY; ++p) {
+        double gs;
+        if (LIMITED) {
+          const int hp2 = H + 2 < 2 * H + 1 ? H + 2 : 2 * H;
+          const int hm2 = H - 2 >= 0 ? H - 2 : 0;
+          const double fr = flux2(vx[e], nu[e], w[H - 1][e].v[p], w[H][e].v[p],
+                                  w[H + 1][e].v[p], w[hp2][e].v[p]);
+          const double fl = flux2(vx[e], nu[e], w[hm2][e].v[p], w[H - 1][e].v[p],
+                                  w[H][e].v[p], w[H + 1][e].v[p]);
+          gs = w[H][e].v[p] - I.r * (fr - fl);
+        } else {
+          const double nb = nu[e] > 0.0 ? w[H - 1][e].v[p] : w[H + 1][e].v[p];
+          gs = fma(fabs(nu[e]), nb - w[H][e].v[p], w[H][e].v[p]);
+        }
+        gs -= I.rv * (G[e + 1][p] - G[e][p]);
+        gs = live ? gs : 0.0;
+        out.v[p] = gs;
+        u0[p] += gs;
+        t1 = fma(vx[e], gs, t1);
+        t4 = fma(vx[e] * vx[e], gs, t4);
+      }
+      if (live) st_col<PY>(dst + (long long)i * nv3 + (long long)e * nyz, out);
+    }
+    double t0 = 0.0, t2 = 0.0, t3 = 0.0;
+#pragma unroll
+    for (int p = 0; p < PY; ++p) {
+      t0 += u0[p];
+      t2 = fma(vy[p], u0[p], t2);
+      t3 = fma(vz[p], u0[p], t3);
+      t4 = fma(vyz2[p], u0[p], t4);
+    }
+    // the wave's five sums by reduce-scatter: lanes 0..7 hold the totals
+    double t8[8] = {t0, t1, t2, t3, t4, 0.0, 0.0, 0.0};
+    const double tot = wave_reduce_scatter<8>(t8, lane);
+    const int slot = slot_of_lane<8>(lane);
+    if (lane < 8 && slot < 5) part[(long long)i * I.part_tiles * 5 + slot] = tot;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+#pragma unroll
+      for (int k = 0; k < 2 * H; ++k) w[k][e] = w[k + 1][e];
+      rawp[e] = rawn[e];
+    }
+    dn_cur = dn_nxt;
+    up_cur = up_nxt;
+  }
+}
+
 __device__ __forceinline__ void store_pair(double* drow, int jofs, double2 g) {
 #if BGK_NT_STORE
   __builtin_nontemporal_store(g.x, drow + jofs);
@@ -1311,7 +1559,34 @@ int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode
     hipError_t e_ = hipGetLastError();                                      \
     return e_ == hipSuccess ? BGK_OK : hip_fail(e_, "k_step");              \
   }
-  if (order == 2) {
+  if (t.vcol) {
+    if (!force || ns != 5) {
+      set_error("the v_x-column lane mapping serves the exterior-force step only");
+      return BGK_E_INVALID;
+    }
+#define BGK_VCOL_CASES(EE, LIM, PYY)                                \
+  BGK_STEP_CASE((k_step_vcol<EE, kCopy, LIM, PYY>), EE, kCopy)      \
+  BGK_STEP_CASE((k_step_vcol<EE, kRelax, LIM, PYY>), EE, kRelax)    \
+  BGK_STEP_CASE((k_step_vcol<EE, kLift, LIM, PYY>), EE, kLift)
+    if (t.pair) {
+      if (order == 2) {
+        BGK_VCOL_CASES(2, true, 2)
+        BGK_VCOL_CASES(4, true, 2)
+      } else {
+        BGK_VCOL_CASES(2, false, 2)
+        BGK_VCOL_CASES(4, false, 2)
+      }
+    } else if (order == 2) {
+      BGK_VCOL_CASES(2, true, 1)
+      BGK_VCOL_CASES(4, true, 1)
+      BGK_VCOL_CASES(8, true, 1)
+    } else {
+      BGK_VCOL_CASES(2, false, 1)
+      BGK_VCOL_CASES(4, false, 1)
+      BGK_VCOL_CASES(8, false, 1)
+    }
+#undef BGK_VCOL_CASES
+  } else if (order == 2) {
     if (t.pair || ns != 5) {
       set_error("the second-order step uses the generic lane mapping, one step per pass");
       return BGK_E_INVALID;

@@ -50,7 +50,9 @@ def test_host_only_calls():
     lib = bgk.load_library()
     assert lib.bgk_status_string(bgk.E_NONPHYSICAL).decode().startswith("non-physical")
     assert lib.bgk_set_tiles(3, 8, -1) == bgk.E_INVALID
-    assert lib.bgk_set_tiles(4, 8, 2) == bgk.E_INVALID
+    assert lib.bgk_set_tiles(4, 8, 4) == bgk.E_INVALID
+    assert lib.bgk_set_tiles(4, 8, 3) == bgk.OK
+    assert lib.bgk_set_tiles(4, 8, 2) == bgk.OK
     assert lib.bgk_set_tiles(0, 0, -1) == bgk.OK
 
 

@@ -14,7 +14,12 @@ from tests.test_gpu_parity import GRIDS, cuda, states
 
 pytestmark = pytest.mark.gpu
 
-FORCE_TILES = [(0, 0, -1), (2, 1, 0), (4, 3, 0), (8, 16, 0), (2, 64, 0)]
+# (elems, x chunk, lane mapping): 0 = flat velocity runs, 2 = v_x columns,
+# 3 = v_x columns with two (v_y, v_z) points per lane, -1 = built-in (columns
+# where a v_x plane fills a wave)
+FORCE_TILES = [(0, 0, -1), (2, 1, 0), (4, 3, 0), (8, 16, 0), (2, 64, 0),
+               (0, 0, 2), (2, 1, 2), (4, 3, 2), (8, 16, 2), (8, 64, 2),
+               (0, 0, 3), (2, 1, 3), (4, 5, 3), (2, 64, 3)]
 
 
 @pytest.fixture(autouse=True)
@@ -154,4 +159,36 @@ def test_two_beam_exterior_force_full_grid():
     assert rel_f(got.cpu().numpy(), ref) < TOL
     V, _ = bgk.moments(p, got)
     Vr, _ = oracle.moments(p, ref)
+    assert rel_V(V.cpu().numpy(), Vr) < TOL
+
+
+@pytest.mark.parametrize("tiles", [(4, 8, 2), (8, 2, 2), (2, 5, 2), (4, 8, 3), (2, 3, 3)])
+def test_two_beam_columns_match_flat_mapping(tiles):
+    """On the two-beam grid (256 x 16 x 16 velocities) the v_x-column force
+    step and the flat-mapping one agree to rounding, over a lifted start and
+    relaxed steps, and both agree with the oracle."""
+    wk = wl.c6_two_beam_force(nx=24)
+    p = wk.problem
+    f0 = wk.f0(oracle.lift)
+    n, dt = oracle.n_steps(p, 0.01, E=wk.E)
+    n = min(n, 4)
+    bgk.set_tiles(2, 8, 0)
+    flat = bgk.fine_steps(p, cuda(f0), dt, n, E=wk.E).cpu().numpy()
+    bgk.set_tiles(*tiles)
+    col = bgk.fine_steps(p, cuda(f0), dt, n, E=wk.E).cpu().numpy()
+    bgk.check_status()
+    assert rel_f(col, flat) < 1e-14
+    assert rel_f(col, oracle.fine_steps(p, f0, dt, n, E=wk.E)) < TOL
+
+
+@pytest.mark.parametrize("mapping", [0, 2, 3])
+def test_parareal_force_lane_mappings(mapping):
+    """The parareal iterate with the force is the same on either lane
+    mapping of the force step (batched slices, graph-captured iterations)."""
+    wk = small_two_beam()
+    p, W0 = wk.problem, wk.U0()
+    bgk.set_tiles(0, 0, mapping)
+    V, _, kd = bgk.parareal_iterate(p, cuda(W0), wk.n_slices, wk.T, 2, 0.0, E=wk.E)
+    Vr, _, _ = oracle.parareal_iterate(p, W0, wk.n_slices, wk.T, 2, 0.0, E=wk.E)
+    assert kd == 2
     assert rel_V(V.cpu().numpy(), Vr) < TOL

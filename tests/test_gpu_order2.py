@@ -13,6 +13,9 @@ from tests.test_gpu_parity import GRIDS, cuda, states
 pytestmark = pytest.mark.gpu
 
 ORDER2_TILES = [(0, 0, -1), (2, 1, 0), (4, 3, 0), (2, 16, 0), (4, 64, 0)]
+# with the exterior force: the v_x-column mapping too (pair = 2)
+ORDER2_FORCE_TILES = ORDER2_TILES + [(0, 0, 2), (2, 1, 2), (4, 5, 2), (8, 16, 2),
+                                     (0, 0, 3), (2, 3, 3), (4, 16, 3)]
 
 
 @pytest.fixture(autouse=True)
@@ -35,9 +38,11 @@ def test_fine_steps_second_order(name, tiles):
     assert rel_f(got, oracle.fine_steps_opts(p, f, dt, n, fine_order=2)) < TOL
 
 
+@pytest.mark.parametrize("tiles", ORDER2_FORCE_TILES)
 @pytest.mark.parametrize("name", ["ragged_neumann", "wide_periodic", "even_z_ragged"])
-def test_second_order_with_force(name):
+def test_second_order_with_force(name, tiles):
     p = GRIDS[name]
+    bgk.set_tiles(*tiles)
     _, f = states(p, 101)
     E = np.random.default_rng(102).uniform(-2, 2, p.nx)
     n, dt = oracle.n_steps(p, 0.004, E=E)
