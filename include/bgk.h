@@ -257,7 +257,8 @@ int parareal_iterate_cns(const bgk_problem* prob, const double* E, double e_max,
  *   v_x < 0: F_{i+1/2} = v_x [f_{i+1} - (1-|nu|)/2 L(f_{i+2} - f_{i+1}, f_{i+1} - f_i)],
  * L(a, b) = 2ab/(a+b) if ab > 0 else 0, nu = v_x dt/dx, ghost cells two deep;
  * TVD for |nu| <= 1; it runs one step per pass on the generic lane mapping
- * (2 or 4 velocities per lane).  bgk_fine_steps_opts is bgk_fine_steps with
+ * (2 or 4 velocities per lane: a tile override of 8 runs as 4), or with the
+ * exterior force on v_x columns.  bgk_fine_steps_opts is bgk_fine_steps with
  * these options (the coarse and lift fields are ignored there).
  * A NULL options pointer means no force, Euler, order 0 lift, order 1
  * transport.  Workspaces and the other arguments as bgk_fine_steps,

@@ -114,7 +114,7 @@ static bool vcol_fits(const bgk_problem& p, Tiles t) {
   return ntiles_of(p, t) <= part_tiles_of(p);
 }
 
-Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force) {
+Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bool limited) {
   std::lock_guard<std::mutex> lk(g_mu);
   const int pair = (p.nv[2] % 2 == 0 && !generic) ? 1 : 0;
   // measured best on the 512 x 32^3 x 64-slice batch with 8-wave blocks:
@@ -132,9 +132,11 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force) {
   const int ov = g_override.pair;
   if (force && (ov >= 2 || (ov != 0 && nyz >= kWave))) {
     // measured on the 100 x 256x16x16 two-beam grid: 4 v_x points by 2
-    // (v_y, v_z) points per lane over 8-cell chunks, for 1 and 20 slices
-    Tiles c = {4, 8, (nyz % 2 == 0 && ov != 2) ? 1 : 0, 1};
-    while (c.chunk > 1 && blocks_for_tiles(p, batch, c) < 128) c.chunk /= 2;
+    // (v_y, v_z) points per lane over 8-cell chunks for 1 and 20 slices;
+    // 16-cell chunks with the second-order x flux where the grid keeps
+    // enough blocks
+    Tiles c = {4, limited ? 16 : 8, (nyz % 2 == 0 && ov != 2) ? 1 : 0, 1};
+    while (c.chunk > 1 && blocks_for_tiles(p, batch, c) < (limited ? 192 : 128)) c.chunk /= 2;
     if (g_override.elems) c.elems = g_override.elems;
     if (g_override.chunk) c.chunk = g_override.chunk;
     if (c.elems == 8) c.pair = 0;  // paired columns take 2 or 4 v_x points
@@ -142,8 +144,10 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force) {
   }
   if (generic) {
     // the exterior-force step on the flat mapping, and the second-order
-    // step: 2 velocities per lane keep the extra registers unspilled
-    t = Tiles{2, 8, 0};
+    // step: 2 velocities per lane keep the extra registers unspilled; the
+    // second-order march amortises its 5-row window over 16-cell chunks
+    // (measured on the 512 x 32^3 x 64-slice batch)
+    t = Tiles{2, limited ? 16 : 8, 0};
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 512) t.chunk /= 2;
   } else if (it != g_tuned.end()) t = it->second;
   else if (pair && g_fuse2 && cells < (1LL << 24)) {
@@ -161,6 +165,7 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force) {
   if (g_override.chunk) t.chunk = g_override.chunk;
   if ((g_override.pair == 0 || g_override.pair == 1) && p.nv[2] % 2 == 0 && !generic)
     t.pair = g_override.pair;
+  if (limited && t.elems > 4) t.elems = 4;  // second-order flat kernels take 2 or 4
   return t;
 }
 
@@ -642,7 +647,7 @@ static void attach_force(Inst& I, const bgk_problem& p, const Force& F, double d
 // Tiles and sums per partial for a fine solve of `n` steps: the force step
 // and the second-order step run one step per pass on the generic lane mapping.
 static Tiles fine_tiles(const bgk_problem& p, int batch, const Force& F) {
-  return choose_tiles(p, batch, F.on() || F.order == 2, F.on());
+  return choose_tiles(p, batch, F.on() || F.order == 2, F.on(), F.order == 2);
 }
 static int fine_nsum(const Tiles& t, int n, const Force& F) {
   return (!F.on() && F.order != 2 && fused_for(t, n)) ? 15 : 5;

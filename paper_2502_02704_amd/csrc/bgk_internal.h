@@ -120,9 +120,10 @@ struct Tiles {
 };
 
 // generic: tiles for the generic lane mapping (no velocity pairs); force:
-// the exterior-force step, on v_x columns where the grid allows.
+// the exterior-force step, on v_x columns where the grid allows; limited:
+// the second-order x transport.
 Tiles choose_tiles(const bgk_problem& p, int batch, bool generic = false,
-                   bool force = false);
+                   bool force = false, bool limited = false);
 
 // Fused relax-then-transport step over all instances in `d_insts`.
 // ns: sums per partial, 5 (moments) or 15 (plus nu-weighted, paired only).

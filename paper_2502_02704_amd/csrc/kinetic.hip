@@ -78,6 +78,13 @@ __device__ __forceinline__ double wave_sum_to_last(double v) {
 #endif
 }
 
+// A wave-uniform double moved to scalar registers.
+__device__ __forceinline__ double uniform_d(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_sum_all(double v) {
   return readlane_d(wave_sum_to_last(v), kWave - 1);
 }
@@ -148,211 +155,7 @@ __device__ __forceinline__ double fac3(const double* row, unsigned off) {
   return row[off & 1023u] * row[(off >> 10) & 1023u] * row[off >> 20];
 }
 
-// ---------------------------------------------------- fused step kernel --
-// Work item = (instance, member b, tile group, x chunk); the waves of a block
-// share the chunk (and its LDS factor rows) and take consecutive tiles.
-// FORCE: the step also transports in v_x under the exterior force E_i of the
-// x cell (Rusanov flux, coefficient emax, no flux through the ends of the v_x
-// range).  A lane's v_x neighbours lie nvy*nvz elements away in the same x
-// row; they are read directly (other waves of the block or nearby blocks
-// read them as their own centre values, so they mostly hit L2) and relaxed
-// with the factor of the neighbouring v_x point.
-// LIMITED: second order in x, the upwind flux with the Lax-Wendroff
-// correction limited by van Leer's limiter (five-point stencil, so the march
-// keeps rows i-2 .. i+2 and the ghost cells are two deep).
-__device__ __forceinline__ double vl_limited(double a, double b) {
-  return a * b > 0.0 ? 2.0 * a * b / (a + b) : 0.0;
-}
-
-// Limited flux through the face between f0 (cell i) and fp (cell i+1).
-__device__ __forceinline__ double flux2(double vx, double nu, double fm, double f0,
-                                        double fp, double fp2) {
-  if (vx > 0.0) return vx * (f0 + 0.5 * (1.0 - nu) * vl_limited(f0 - fm, fp - f0));
-  if (vx < 0.0) return vx * (fp - 0.5 * (1.0 + nu) * vl_limited(fp2 - fp, fp - f0));
-  return 0.0;
-}
-
-template <int E, int MODE, bool FORCE = false, bool LIMITED = false>
-__global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
-                                                 int n_inst, int chunk,
-                                                 int phase) {
-  constexpr int H = LIMITED ? 2 : 1;  // stencil half-width in x
-  extern __shared__ double lds[];
-  const long long item = xcd_item(blockIdx.x, gridDim.x);
-  const int q = find_inst(insts, n_inst, item);
-  const Inst& I = insts[q];
-  const long long local = item - I.item_begin;
-  int b, tg, c;
-  decode_item(I, local, b, tg, c);
-  const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
-  const int i0 = c * chunk;
-  const int i1 = min(i0 + chunk, nx);
-  const int rbase = i0 - H;  // first staged factor row
-
-  if (MODE != kCopy) {
-    // factor rows of cells i0-H .. i1+H-1 (ghosts mapped by the BC)
-    const int rows = i1 - i0 + 2 * H;
-    const double* fac = I.fac + (long long)b * nx * nvs;
-    for (int idx = threadIdx.x; idx < rows * nvs; idx += kBlock) {
-      int rr = idx / nvs;
-      int k = idx - rr * nvs;
-      lds[idx] = fac[(long long)ghost_row(rbase + rr, nx, I.bc) * nvs + k];
-    }
-    __syncthreads();
-  }
-
-  const int wave = threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  const int tile = tg * kWavesPerBlock + wave;
-  if (tile >= I.ntiles) return;
-
-  Elems<E> el;
-  setup_elems<E>(I, tile, lane, el);
-  const long long mbase = (long long)b * nx * nv3;
-  const double* src = (MODE == kCopy) ? I.fin : I.buf[phase];
-  double* dst = I.buf[phase ^ 1];
-  src += mbase + tile * (kWave * E) + lane;
-  dst += mbase + tile * (kWave * E) + lane;
-  const double a = I.a;
-  double nu[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) nu[e] = el.vx[e] * I.r;
-
-  // relaxed value of row r (global row index, ghost-mapped) from raw g
-  auto relax_row = [&](int r, const double* raw, double* out) {
-    const double* frow = lds + (r - rbase) * nvs;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      double v;
-      if (MODE == kCopy) v = raw[e];
-      else if (MODE == kRelax) v = fma(a, raw[e], fac3(frow, el.off[e]));
-      else v = fac3(frow, el.off[e]);
-      out[e] = el.ok[e] ? v : 0.0;
-    }
-  };
-  auto load_row = [&](int r, double* raw) {
-    if (MODE == kLift) return;
-    const long long ro = (long long)ghost_row(r, nx, I.bc) * nv3;
-#pragma unroll
-    for (int e = 0; e < E; ++e) raw[e] = el.ok[e] ? src[ro + e * kWave] : 0.0;
-  };
-
-  // relaxed rows i-H .. i+H of the march; raw row i+H (rawp) and i+H+1 (rawn)
-  double w[2 * H + 1][E], rawp[E], rawn[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) rawn[e] = 0.0;
-#pragma unroll
-  for (int k = 0; k < 2 * H; ++k) {
-    double raw[E];
-    load_row(i0 - H + k, raw);
-    relax_row(i0 - H + k, raw, w[k]);
-  }
-  load_row(i0 + H, rawp);
-  // FORCE: raw values at the v_x neighbours (dn: -nyz, up: +nyz) of each
-  // element, loaded one row ahead of their use; relaxed with the factor of
-  // the neighbouring v_x point (the Ex index is the low field of off)
-  const int nyz = I.nvy * I.nvz;
-  double dn_cur[FORCE ? E : 1], up_cur[FORCE ? E : 1];
-  double dn_nxt[FORCE ? E : 1], up_nxt[FORCE ? E : 1];
-  auto load_vnb = [&](int r, double* dn, double* up) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int jx = (int)(el.off[e] & 1023u);
-      const long long o = (long long)r * nv3 + e * kWave;
-      dn[e] = (MODE != kLift && el.ok[e] && jx > 0) ? src[o - nyz] : 0.0;
-      up[e] = (MODE != kLift && el.ok[e] && jx + 1 < I.nvx) ? src[o + nyz] : 0.0;
-    }
-  };
-  auto relax_vnb = [&](int r, int e, int dir, double raw) -> double {
-    const double* frow = lds + (r - rbase) * nvs;
-    const unsigned off = el.off[e] + (unsigned)dir;
-    if (MODE == kCopy) return raw;
-    if (MODE == kRelax) return fma(a, raw, fac3(frow, off));
-    return fac3(frow, off);
-  };
-  if (FORCE) load_vnb(i0, dn_cur, up_cur);
-  double* part = I.part + (((long long)b * nx) * I.part_tiles + tile) * 5;
-  for (int i = i0; i < i1; ++i) {
-    if (i + 2 <= i1) load_row(i + H + 1, rawn);  // prefetch the next row
-    if (FORCE && i + 1 < i1) load_vnb(i + 1, dn_nxt, up_nxt);
-    relax_row(i + H, rawp, w[2 * H]);
-    double Ei = 0.0;
-    if (FORCE) Ei = I.efield[i];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      double gs;
-      if (LIMITED) {
-        const double fr = flux2(el.vx[e], nu[e], w[H - 1][e], w[H][e], w[H + 1][e],
-                                w[H + 2 < 2 * H + 1 ? H + 2 : 2 * H][e]);
-        const double fl = flux2(el.vx[e], nu[e], w[H - 2 >= 0 ? H - 2 : 0][e], w[H - 1][e],
-                                w[H][e], w[H + 1][e]);
-        gs = w[H][e] - I.r * (fr - fl);
-      } else {
-        const double nb = nu[e] > 0.0 ? w[H - 1][e] : w[H + 1][e];
-        gs = fma(fabs(nu[e]), nb - w[H][e], w[H][e]);
-      }
-      if (FORCE && el.ok[e]) {
-        const int jx = (int)(el.off[e] & 1023u);
-        const double c = w[H][e];
-        double g_up = 0.0, g_down = 0.0;
-        if (jx + 1 < I.nvx) {
-          const double u = relax_vnb(i, e, 1, up_cur[e]);
-          g_up = 0.5 * Ei * (c + u) - 0.5 * I.emax * (u - c);
-        }
-        if (jx > 0) {
-          const double d = relax_vnb(i, e, -1, dn_cur[e]);
-          g_down = 0.5 * Ei * (d + c) - 0.5 * I.emax * (c - d);
-        }
-        gs -= I.rv * (g_up - g_down);
-      }
-      if (el.ok[e]) dst[(long long)i * nv3 + e * kWave] = gs;
-      const double vsq = el.vx[e] * el.vx[e] + el.vy[e] * el.vy[e] +
-                         el.vz[e] * el.vz[e];
-      s0 += gs;
-      s1 = fma(el.vx[e], gs, s1);
-      s2 = fma(el.vy[e], gs, s2);
-      s3 = fma(el.vz[e], gs, s3);
-      s4 = fma(vsq, gs, s4);
-    }
-    s0 = wave_sum_to_last(s0);
-    s1 = wave_sum_to_last(s1);
-    s2 = wave_sum_to_last(s2);
-    s3 = wave_sum_to_last(s3);
-    s4 = wave_sum_to_last(s4);
-    if (lane == kWave - 1) {
-      double* pp = part + (long long)i * I.part_tiles * 5;
-      pp[0] = s0;
-      pp[1] = s1;
-      pp[2] = s2;
-      pp[3] = s3;
-      pp[4] = s4;
-    }
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-#pragma unroll
-      for (int k = 0; k < 2 * H; ++k) w[k][e] = w[k + 1][e];
-      rawp[e] = rawn[e];
-      if (FORCE) {
-        dn_cur[e] = dn_nxt[e];
-        up_cur[e] = up_nxt[e];
-      }
-    }
-  }
-}
-
-// ------------------------------------------- paired-velocity step kernel --
-// Same step, lanes own pairs of adjacent velocities (v_z and v_z + dv_z, same
-// v_x and v_y): 16-byte loads and stores, one transport select, one Ex*Ey
-// product and one ds_read2 per pair.  Pair p of lane l covers the flat
-// velocities tile*128P + p*128 + 2l + {0,1} (requires even nv_z, so a pair
-// never straddles a v_z row, and 16-byte aligned rows).
-//
-// Moment partials, one record per wave and x cell: the five moment sums
-// (NS = 5), joined with NS = 15 by the same sums weighted by nu+ = max(nu,0)
-// and nu- = max(-nu,0) (needed to predict the next step's moments, see the
-// two-step kernel), reduced over the wave by reduce-scatter.
-
+// ------------------------------------------------ lane reductions --
 // Lane exchange with partner lane ^ (1 << STAGE): DPP quad permutations for
 // bits 0-1, ds_swizzle (bit mode, within 32 lanes) for bits 2-4, bpermute for
 // bit 5.
@@ -509,6 +312,216 @@ __device__ __forceinline__ int slot_of_lane(int lane) {
 __device__ __forceinline__ constexpr int lane_of_slot4(int k) {
   return (k >> 1) | ((k & 1) << 1);
 }
+
+// ---------------------------------------------------- fused step kernel --
+// Work item = (instance, member b, tile group, x chunk); the waves of a block
+// share the chunk (and its LDS factor rows) and take consecutive tiles.
+// FORCE: the step also transports in v_x under the exterior force E_i of the
+// x cell (Rusanov flux, coefficient emax, no flux through the ends of the v_x
+// range).  A lane's v_x neighbours lie nvy*nvz elements away in the same x
+// row; they are read directly (other waves of the block or nearby blocks
+// read them as their own centre values, so they mostly hit L2) and relaxed
+// with the factor of the neighbouring v_x point.
+// LIMITED: second order in x, the upwind flux with the Lax-Wendroff
+// correction limited by van Leer's limiter (five-point stencil, so the march
+// keeps rows i-2 .. i+2 and the ghost cells are two deep).
+__device__ __forceinline__ double vl_limited(double a, double b) {
+  return a * b > 0.0 ? 2.0 * a * b / (a + b) : 0.0;
+}
+
+// Limited flux through the face between f0 (cell i) and fp (cell i+1): the
+// upwind value plus the limited correction taken on the upwind side, one
+// limiter per face (pos: v_x > 0; anu = |nu|).  For v_x < 0 the factor
+// -(1 - |nu|)/2 equals -(1 + nu)/2 exactly.
+__device__ __forceinline__ double flux2(double vx, double anu, double fm, double f0,
+                                        double fp, double fp2) {
+  const bool pos = vx > 0.0;
+  const double up = pos ? f0 : fp;
+  const double d1 = pos ? f0 - fm : fp2 - fp;
+  const double h = 0.5 * (1.0 - anu);
+  const double c = pos ? h : -h;
+  return vx * (up + c * vl_limited(d1, fp - f0));
+}
+
+template <int E, int MODE, bool FORCE = false, bool LIMITED = false>
+__global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
+                                                 int n_inst, int chunk,
+                                                 int phase) {
+  constexpr int H = LIMITED ? 2 : 1;  // stencil half-width in x
+  extern __shared__ double lds[];
+  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const int q = find_inst(insts, n_inst, item);
+  const Inst& I = insts[q];
+  const long long local = item - I.item_begin;
+  int b, tg, c;
+  decode_item(I, local, b, tg, c);
+  const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
+  const int i0 = c * chunk;
+  const int i1 = min(i0 + chunk, nx);
+  const int rbase = i0 - H;  // first staged factor row
+
+  if (MODE != kCopy) {
+    // factor rows of cells i0-H .. i1+H-1 (ghosts mapped by the BC)
+    const int rows = i1 - i0 + 2 * H;
+    const double* fac = I.fac + (long long)b * nx * nvs;
+    for (int idx = threadIdx.x; idx < rows * nvs; idx += kBlock) {
+      int rr = idx / nvs;
+      int k = idx - rr * nvs;
+      lds[idx] = fac[(long long)ghost_row(rbase + rr, nx, I.bc) * nvs + k];
+    }
+    __syncthreads();
+  }
+
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int tile = tg * kWavesPerBlock + wave;
+  if (tile >= I.ntiles) return;
+
+  Elems<E> el;
+  setup_elems<E>(I, tile, lane, el);
+  const long long mbase = (long long)b * nx * nv3;
+  const double* src = (MODE == kCopy) ? I.fin : I.buf[phase];
+  double* dst = I.buf[phase ^ 1];
+  src += mbase + tile * (kWave * E) + lane;
+  dst += mbase + tile * (kWave * E) + lane;
+  const double a = I.a;
+  double nu[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) nu[e] = el.vx[e] * I.r;
+
+  // relaxed value of row r (global row index, ghost-mapped) from raw g
+  auto relax_row = [&](int r, const double* raw, double* out) {
+    const double* frow = lds + (r - rbase) * nvs;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      double v;
+      if (MODE == kCopy) v = raw[e];
+      else if (MODE == kRelax) v = fma(a, raw[e], fac3(frow, el.off[e]));
+      else v = fac3(frow, el.off[e]);
+      out[e] = el.ok[e] ? v : 0.0;
+    }
+  };
+  auto load_row = [&](int r, double* raw) {
+    if (MODE == kLift) return;
+    const long long ro = (long long)ghost_row(r, nx, I.bc) * nv3;
+#pragma unroll
+    for (int e = 0; e < E; ++e) raw[e] = el.ok[e] ? src[ro + e * kWave] : 0.0;
+  };
+
+  // relaxed rows i-H .. i+H of the march; raw row i+H (rawp) and i+H+1 (rawn)
+  double w[2 * H + 1][E], rawp[E], rawn[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) rawn[e] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2 * H; ++k) {
+    double raw[E];
+    load_row(i0 - H + k, raw);
+    relax_row(i0 - H + k, raw, w[k]);
+  }
+  load_row(i0 + H, rawp);
+  // FORCE: raw values at the v_x neighbours (dn: -nyz, up: +nyz) of each
+  // element, loaded one row ahead of their use; relaxed with the factor of
+  // the neighbouring v_x point (the Ex index is the low field of off)
+  const int nyz = I.nvy * I.nvz;
+  double dn_cur[FORCE ? E : 1], up_cur[FORCE ? E : 1];
+  double dn_nxt[FORCE ? E : 1], up_nxt[FORCE ? E : 1];
+  auto load_vnb = [&](int r, double* dn, double* up) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int jx = (int)(el.off[e] & 1023u);
+      const long long o = (long long)r * nv3 + e * kWave;
+      dn[e] = (MODE != kLift && el.ok[e] && jx > 0) ? src[o - nyz] : 0.0;
+      up[e] = (MODE != kLift && el.ok[e] && jx + 1 < I.nvx) ? src[o + nyz] : 0.0;
+    }
+  };
+  auto relax_vnb = [&](int r, int e, int dir, double raw) -> double {
+    const double* frow = lds + (r - rbase) * nvs;
+    const unsigned off = el.off[e] + (unsigned)dir;
+    if (MODE == kCopy) return raw;
+    if (MODE == kRelax) return fma(a, raw, fac3(frow, off));
+    return fac3(frow, off);
+  };
+  if (FORCE) load_vnb(i0, dn_cur, up_cur);
+  // LIMITED: flux through the left face of the current row, carried over
+  // from the right face of the previous one (computed once per face)
+  double fcar[LIMITED ? E : 1];
+  if (LIMITED) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      fcar[e] = flux2(el.vx[e], fabs(nu[e]), w[0][e], w[1][e], w[2][e], w[3 < 2 * H ? 3 : 0][e]);
+  }
+  double* part = I.part + (((long long)b * nx) * I.part_tiles + tile) * 5;
+  for (int i = i0; i < i1; ++i) {
+    if (i + 2 <= i1) load_row(i + H + 1, rawn);  // prefetch the next row
+    if (FORCE && i + 1 < i1) load_vnb(i + 1, dn_nxt, up_nxt);
+    relax_row(i + H, rawp, w[2 * H]);
+    double Ei = 0.0;
+    if (FORCE) Ei = I.efield[i];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      double gs;
+      if (LIMITED) {
+        const double fr = flux2(el.vx[e], fabs(nu[e]), w[H - 1][e], w[H][e], w[H + 1][e],
+                                w[H + 2 < 2 * H + 1 ? H + 2 : 2 * H][e]);
+        gs = w[H][e] - I.r * (fr - fcar[e]);
+        fcar[e] = fr;
+      } else {
+        const double nb = nu[e] > 0.0 ? w[H - 1][e] : w[H + 1][e];
+        gs = fma(fabs(nu[e]), nb - w[H][e], w[H][e]);
+      }
+      if (FORCE && el.ok[e]) {
+        const int jx = (int)(el.off[e] & 1023u);
+        const double c = w[H][e];
+        double g_up = 0.0, g_down = 0.0;
+        if (jx + 1 < I.nvx) {
+          const double u = relax_vnb(i, e, 1, up_cur[e]);
+          g_up = 0.5 * Ei * (c + u) - 0.5 * I.emax * (u - c);
+        }
+        if (jx > 0) {
+          const double d = relax_vnb(i, e, -1, dn_cur[e]);
+          g_down = 0.5 * Ei * (d + c) - 0.5 * I.emax * (c - d);
+        }
+        gs -= I.rv * (g_up - g_down);
+      }
+      if (el.ok[e]) dst[(long long)i * nv3 + e * kWave] = gs;
+      const double vsq = el.vx[e] * el.vx[e] + el.vy[e] * el.vy[e] +
+                         el.vz[e] * el.vz[e];
+      s0 += gs;
+      s1 = fma(el.vx[e], gs, s1);
+      s2 = fma(el.vy[e], gs, s2);
+      s3 = fma(el.vz[e], gs, s3);
+      s4 = fma(vsq, gs, s4);
+    }
+    // the wave's five sums by reduce-scatter: lanes 0..7 hold the totals
+    double t8[8] = {s0, s1, s2, s3, s4, 0.0, 0.0, 0.0};
+    const double tot = wave_reduce_scatter<8>(t8, lane);
+    const int slot = slot_of_lane<8>(lane);
+    if (lane < 8 && slot < 5) part[(long long)i * I.part_tiles * 5 + slot] = tot;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+#pragma unroll
+      for (int k = 0; k < 2 * H; ++k) w[k][e] = w[k + 1][e];
+      rawp[e] = rawn[e];
+      if (FORCE) {
+        dn_cur[e] = dn_nxt[e];
+        up_cur[e] = up_nxt[e];
+      }
+    }
+  }
+}
+
+// ------------------------------------------- paired-velocity step kernel --
+// Same step, lanes own pairs of adjacent velocities (v_z and v_z + dv_z, same
+// v_x and v_y): 16-byte loads and stores, one transport select, one Ex*Ey
+// product and one ds_read2 per pair.  Pair p of lane l covers the flat
+// velocities tile*128P + p*128 + 2l + {0,1} (requires even nv_z, so a pair
+// never straddles a v_z row, and 16-byte aligned rows).
+//
+// Moment partials, one record per wave and x cell: the five moment sums
+// (NS = 5), joined with NS = 15 by the same sums weighted by nu+ = max(nu,0)
+// and nu- = max(-nu,0) (needed to predict the next step's moments, see the
+// two-step kernel), reduced over the wave by reduce-scatter.
 
 // Running moment sums of one wave over its tile, for one x cell, and their
 // reduction into the partial-sum record of the wave: NS values, the five
@@ -674,13 +687,14 @@ __global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ i
     vz[p] = vgrid(I, 2, jz);
     vyz2[p] = vy[p] * vy[p] + vz[p] * vz[p];
   }
+  // v_x, nu of the tile's v_x points: wave-uniform, kept in scalar registers
   double vx[E], nu[E];
   int ox[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     ox[e] = min(x0 + e, nvx - 1);
-    vx[e] = vgrid(I, 0, ox[e]);
-    nu[e] = vx[e] * I.r;
+    vx[e] = uniform_d(vgrid(I, 0, ox[e]));
+    nu[e] = uniform_d(vx[e] * I.r);
   }
   const long long mbase = (long long)b * nx * nv3 + (long long)x0 * nyz + yz;
   const double* src = ((MODE == kCopy) ? I.fin : I.buf[phase]) + mbase;
@@ -730,11 +744,13 @@ __global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ i
     if (has_up) up = ld_col<PY>(src + ro + (long long)E * nyz);
   };
 
-  Col<PY> w[2 * H + 1][E], rawp[E], rawn[E];
+  // one raw row in flight: row i+H is relaxed at the top of step i, then the
+  // same registers take the load of row i+H+1 (likewise the halo planes)
+  Col<PY> w[2 * H + 1][E], rawp[E];
 #pragma unroll
   for (int e = 0; e < E; ++e)
 #pragma unroll
-    for (int p = 0; p < PY; ++p) rawp[e].v[p] = rawn[e].v[p] = 0.0;
+    for (int p = 0; p < PY; ++p) rawp[e].v[p] = 0.0;
 #pragma unroll
   for (int k = 0; k < 2 * H; ++k) {
     Col<PY> raw[E];
@@ -742,36 +758,44 @@ __global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ i
     relax_row(i0 - H + k, raw, w[k]);
   }
   load_row(i0 + H, rawp);
-  Col<PY> dn_cur, up_cur, dn_nxt, up_nxt;
-  load_halo(i0, dn_cur, up_cur);
-#pragma unroll
-  for (int p = 0; p < PY; ++p) dn_nxt.v[p] = up_nxt.v[p] = 0.0;
+  Col<PY> dn_raw, up_raw;
+  load_halo(i0, dn_raw, up_raw);
   const double hm = 0.5 * I.emax;
+  // LIMITED: x flux through the left face of the current row, carried over
+  // from the right face of the previous one (computed once per face)
+  double fcar[LIMITED ? E : 1][PY];
+  if (LIMITED) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+#pragma unroll
+      for (int p = 0; p < PY; ++p)
+        fcar[e][p] = flux2(vx[e], fabs(nu[e]), w[0][e].v[p], w[1][e].v[p], w[2][e].v[p],
+                           w[3 < 2 * H ? 3 : 0][e].v[p]);
+  }
   double* part = I.part + ((long long)b * nx * I.part_tiles + tile) * 5;
   for (int i = i0; i < i1; ++i) {
-    if (i + 2 <= i1) load_row(i + H + 1, rawn);  // prefetch the next row
-    if (i + 1 < i1) load_halo(i + 1, dn_nxt, up_nxt);
     relax_row(i + H, rawp, w[2 * H]);
-    const double he = 0.5 * I.efield[i];
+    if (i + 2 <= i1) load_row(i + H + 1, rawp);  // prefetch the next row
     const double* frow = lds + (i - rbase) * nvs;
-    // v_x face fluxes: face k lies below element k (k = 0 .. E); the halo
-    // values are relaxed with the factors of row i
-    double G[E + 1][PY];
+    // relaxed halo values of row i (factors of row i), then the next halo loads
+    double hd_[PY], hu_[PY];
 #pragma unroll
     for (int p = 0; p < PY; ++p) {
       const double myz = (MODE == kCopy) ? 0.0 : frow[oy[p]];
       const double mzz = (MODE == kCopy) ? 0.0 : frow[oz[p]];
-      double hd = 0.0, hu = 0.0;
-      if (has_dn) hd = relax1(dn_cur.v[p], (MODE == kCopy) ? 0.0 : frow[x0 - 1] * myz * mzz);
-      if (has_up) hu = relax1(up_cur.v[p], (MODE == kCopy) ? 0.0 : frow[x0 + E] * myz * mzz);
-      G[0][p] = has_dn ? he * (hd + w[H][0].v[p]) - hm * (w[H][0].v[p] - hd) : 0.0;
-#pragma unroll
-      for (int k = 1; k < E; ++k)
-        G[k][p] = (k < nel) ? he * (w[H][k - 1].v[p] + w[H][k].v[p]) -
-                                  hm * (w[H][k].v[p] - w[H][k - 1].v[p])
-                            : 0.0;
-      G[E][p] = has_up ? he * (w[H][E - 1].v[p] + hu) - hm * (hu - w[H][E - 1].v[p]) : 0.0;
+      hd_[p] = has_dn ? relax1(dn_raw.v[p], (MODE == kCopy) ? 0.0 : frow[x0 - 1] * myz * mzz)
+                     : 0.0;
+      hu_[p] = has_up ? relax1(up_raw.v[p], (MODE == kCopy) ? 0.0 : frow[x0 + E] * myz * mzz)
+                     : 0.0;
     }
+    if (i + 1 < i1) load_halo(i + 1, dn_raw, up_raw);
+    const double he = 0.5 * I.efield[i];
+    // v_x face fluxes (face k lies below element k), carried along the
+    // column: each face's flux is computed once
+    auto face = [&](double lo, double hi) { return he * (lo + hi) - hm * (hi - lo); };
+    double glo[PY];
+#pragma unroll
+    for (int p = 0; p < PY; ++p) glo[p] = has_dn ? face(hd_[p], w[H][0].v[p]) : 0.0;
     double u0[PY], t1 = 0.0, t4 = 0.0;
 #pragma unroll
     for (int p = 0; p < PY; ++p) u0[p] = 0.0;
@@ -784,17 +808,19 @@ __global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ i
         double gs;
         if (LIMITED) {
           const int hp2 = H + 2 < 2 * H + 1 ? H + 2 : 2 * H;
-          const int hm2 = H - 2 >= 0 ? H - 2 : 0;
-          const double fr = flux2(vx[e], nu[e], w[H - 1][e].v[p], w[H][e].v[p],
+          const double fr = flux2(vx[e], fabs(nu[e]), w[H - 1][e].v[p], w[H][e].v[p],
                                   w[H + 1][e].v[p], w[hp2][e].v[p]);
-          const double fl = flux2(vx[e], nu[e], w[hm2][e].v[p], w[H - 1][e].v[p],
-                                  w[H][e].v[p], w[H + 1][e].v[p]);
-          gs = w[H][e].v[p] - I.r * (fr - fl);
+          gs = w[H][e].v[p] - I.r * (fr - fcar[e][p]);
+          fcar[e][p] = fr;
         } else {
           const double nb = nu[e] > 0.0 ? w[H - 1][e].v[p] : w[H + 1][e].v[p];
           gs = fma(fabs(nu[e]), nb - w[H][e].v[p], w[H][e].v[p]);
         }
-        gs -= I.rv * (G[e + 1][p] - G[e][p]);
+        double ghi;
+        if (e + 1 < E) ghi = (e + 1 < nel) ? face(w[H][e].v[p], w[H][e + 1].v[p]) : 0.0;
+        else ghi = has_up ? face(w[H][E - 1].v[p], hu_[p]) : 0.0;
+        gs -= I.rv * (ghi - glo[p]);
+        glo[p] = ghi;
         gs = live ? gs : 0.0;
         out.v[p] = gs;
         u0[p] += gs;
@@ -817,13 +843,9 @@ __global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ i
     const int slot = slot_of_lane<8>(lane);
     if (lane < 8 && slot < 5) part[(long long)i * I.part_tiles * 5 + slot] = tot;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
+    for (int e = 0; e < E; ++e)
 #pragma unroll
       for (int k = 0; k < 2 * H; ++k) w[k][e] = w[k + 1][e];
-      rawp[e] = rawn[e];
-    }
-    dn_cur = dn_nxt;
-    up_cur = up_nxt;
   }
 }
 
