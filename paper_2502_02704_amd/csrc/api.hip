@@ -371,6 +371,10 @@ static Inst make_inst(const bgk_problem& p, int B, double dt, Tiles t, int ns = 
   I.ntiles = (int)ntiles_of(p, t);
   I.ntg = (I.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   I.nsum = ns;
+  // fused passes on grids whose tiles each lie in one v_x plane write
+  // compact 4-value partial records
+  if (ns == 15 && t.pair && ((long long)p.nv[1] * p.nv[2]) % (kWave * t.elems) == 0)
+    I.crec = kWave * t.elems;
   I.order = 1;
   I.nparts = I.ntiles;  // one partial record per wave tile
   I.nchunks = (p.nx + t.chunk - 1) / t.chunk;

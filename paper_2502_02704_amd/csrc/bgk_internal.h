@@ -38,7 +38,9 @@ struct Inst {
   int nparts;                  // partial sums per x cell the step writes
   int nsum;                    // values per partial: 5 moments, or 15 with the
                                // nu+ and nu- weighted moments (two-step passes)
-  int pad_;
+  int crec;                    // nonzero: compact records, 4 values per tile of
+                               // crec velocities inside one v_x plane (the nu
+                               // weights follow from the tile's v_x)
   double vlo[3], dv[3];        // v_a(j) = vlo[a] + (j + 1/2) dv[a]
   double dv3;                  // dv[0] dv[1] dv[2]
   double r;                    // dt / dx

@@ -569,6 +569,13 @@ struct Acc {
     if (UNI) {
       double t4[4] = {s[0], s[1], s[2], s[3]};
       const double tot = wave_reduce_scatter<4>(t4, lane);
+      if (I.crec) {
+        // compact record: the four totals; the reduction rebuilds the v_x and
+        // nu-weighted sums from the tile's v_x
+        double* crec = I.part + ((long long)b * I.nx + r) * I.part_tiles * 5 + tile * 4;
+        if (lane < 4) crec[slot_of_lane<4>(lane)] = tot;
+        return;
+      }
       const double T0 = bcast_lane(tot, lane_of_slot4(0));
       const double T1 = bcast_lane(tot, lane_of_slot4(1));
       const double T2 = bcast_lane(tot, lane_of_slot4(2));
@@ -1405,12 +1412,34 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
   double s[15];
 #pragma unroll
   for (int c = 0; c < 15; ++c) s[c] = 0.0;
-  for (int t = lane; t < I.nparts; t += kWave) {
+  if (I.crec) {
+    // compact records (tiles inside one v_x plane): (sum g, sum v_y g,
+    // sum v_z g, sum |v|^2 g); v_x and nu are the tile's
+    const int nyz = I.nvy * I.nvz;
+    for (int t = lane; t < I.nparts; t += kWave) {
+      const double vx = vgrid(I, 0, (int)(((long long)t * I.crec) / nyz));
+      const double* q = pp + t * 4;
+      const double m[5] = {q[0], vx * q[0], q[1], q[2], q[3]};
 #pragma unroll
-    for (int c = 0; c < 5; ++c) s[c] += pp[t * ns + c];
-    if (mode == kRedW1) {
+      for (int c = 0; c < 5; ++c) s[c] += m[c];
+      if (mode == kRedW1) {
+        const double nu = vx * I.r;
+        const double wp = nu > 0.0 ? nu : 0.0, wm = nu < 0.0 ? -nu : 0.0;
 #pragma unroll
-      for (int c = 5; c < 15; ++c) s[c] += pp[t * ns + c];
+        for (int c = 0; c < 5; ++c) {
+          s[5 + c] += wp * m[c];
+          s[10 + c] += wm * m[c];
+        }
+      }
+    }
+  } else {
+    for (int t = lane; t < I.nparts; t += kWave) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) s[c] += pp[t * ns + c];
+      if (mode == kRedW1) {
+#pragma unroll
+        for (int c = 5; c < 15; ++c) s[c] += pp[t * ns + c];
+      }
     }
   }
   constexpr int nred = (mode == kRedW1) ? 15 : 5;
