@@ -3,11 +3,12 @@
 A step = one pass of the whole hot path over one batch: every one of the 64
 parareal slices of the smooth periodic workload (Nx=512, 32^3 velocities on
 [-8,8]^3, eps=1e-2) is lifted from its moments, advanced by one slice (25 IMEX
-steps, two per pass over f where possible) and projected back to moments, all
-slices batched in one launch per pass.  Prints one JSON line: phase-space
-updates/s, the roofline of the dominant kernel (the two-step relax pass), the
-CPU oracle timed on a bounded sample, and the parareal vs serial-fine speedup
-on two small workloads where one slice's step is latency bound.
+steps, three per pass over f where possible) and projected back to moments,
+all slices batched in one launch per pass.  Prints one JSON line: phase-space
+updates/s, the roofline of the dominant kernel (the three-step relax pass; the
+two-step pass is timed beside it), the CPU oracle timed on a bounded sample,
+and the parareal vs serial-fine speedup on small workloads where one slice's
+step is latency bound.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--eps E]
        [--no-cpu-baseline] [--no-parareal] [--extras parareal,force,order2]
@@ -26,7 +27,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "BGK phase-space updates/s (Nx*Nv^3*steps) + parareal vs serial-fine speedup"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step2x2_smooth_periodic_traffic.md")
+TRAFFIC_SUMMARY = {
+    "three": os.path.join(ROOT, "profiles", "k_step3x_smooth_periodic_traffic.md"),
+    "two": os.path.join(ROOT, "profiles", "k_step2x2_smooth_periodic_traffic.md"),
+}
 KERNEL_SRC = os.path.join(ROOT, "paper_2502_02704_amd", "csrc", "kinetic.hip")
 
 
@@ -49,12 +53,14 @@ def slice_moments(wk, B):
     return V
 
 
-def traffic_from_profile(launch_bytes_alg):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+def traffic_from_profile(which):
+    """HBM bytes per launch of the three- or two-step pass from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source;
+    else None."""
+    path = TRAFFIC_SUMMARY[which]
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_SUMMARY).read()
+    txt = open(path).read()
     m = re.search(r"^traffic_json:\s*(\{.*\})\s*$", txt, flags=re.M)
     if not m:
         return None
@@ -256,11 +262,42 @@ def main():
         out = bgk.fine_propagate_moments(p, V, span)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    k_ms, k_launches, k_upd, k_bytes = bgk.prof_read(bgk.PROF_TWO_STEP)
+    which = "three"
+    k_ms, k_launches, k_upd, k_bytes = bgk.prof_read(bgk.PROF_THREE_STEP)
+    if k_launches == 0:
+        which = "two"
+        k_ms, k_launches, k_upd, k_bytes = bgk.prof_read(bgk.PROF_TWO_STEP)
     a_ms, a_launches, a_upd, a_bytes = bgk.prof_read(bgk.PROF_ALL)
     bgk.prof_enable(False)
     bgk.check_status()
     assert torch.isfinite(out).all().item()
+
+    # the same batch with two steps per pass, for comparison
+    two = None
+    if which == "three":
+        bgk.set_step_fusion(2)
+        try:
+            bgk.fine_propagate_moments(p, V, span)
+            torch.cuda.synchronize()
+            bgk.prof_enable(True)
+            reps2 = max(1, min(args.steps, 3))
+            t2 = time.perf_counter()
+            for _ in range(reps2):
+                bgk.fine_propagate_moments(p, V, span)
+            torch.cuda.synchronize()
+            el2 = (time.perf_counter() - t2) / reps2
+            m2, l2, u2, b2 = bgk.prof_read(bgk.PROF_TWO_STEP)
+            bgk.prof_enable(False)
+            bgk.check_status()
+        finally:
+            bgk.set_step_fusion(3)
+        ach2 = b2 / (m2 * 1e-3) / 1e9
+        two = {"kernel": "k_step2x2 relax passes (two IMEX steps per pass over f)",
+               "updates_per_s": updates_per_step / el2, "ms_per_step": round(el2 * 1e3, 3),
+               "achieved": round(ach2, 1), "frac": round(ach2 / HBM_PEAK_GBS, 4),
+               "avg_launch_us": round(m2 * 1e3 / max(l2, 1), 2), "launches": l2,
+               "alg_bytes_per_update": round(b2 / max(u2, 1.0), 3),
+               "traffic": traffic_from_profile("two")}
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -275,8 +312,10 @@ def main():
     per_launch_alg = k_bytes / max(k_launches, 1)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_from_profile(per_launch_alg),
-                "kernel": "k_step2x2 relax passes (two IMEX steps per pass over f)",
+                "traffic": traffic_from_profile(which),
+                "kernel": ("k_step3x relax passes (three IMEX steps per pass over f)"
+                           if which == "three" else
+                           "k_step2x2 relax passes (two IMEX steps per pass over f)"),
                 "launches": k_launches, "avg_launch_us": round(k_ms * 1e3 / max(k_launches, 1), 2),
                 "alg_bytes_per_launch": per_launch_alg,
                 "alg_bytes_per_update": round(k_bytes / max(k_upd, 1.0), 3),
@@ -284,6 +323,8 @@ def main():
                     "launches": a_launches, "avg_launch_us": round(a_ms * 1e3 / max(a_launches, 1), 2),
                     "achieved": round(a_bytes / (a_ms * 1e-3) / 1e9, 1),
                     "alg_bytes_per_update": round(a_bytes / max(a_upd, 1.0), 3)}}
+    if two is not None:
+        roofline["two_step_pass"] = two
     line = {"metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,

@@ -346,13 +346,16 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws,
                  size_t ws_bytes, void* stream, int32_t* best_elems,
                  int32_t* best_chunk, int32_t* best_pair);
 
-/* IMEX steps per pass over f: 2 (default) runs pairs of steps in one
+/* IMEX steps per pass over f: 2 runs pairs of steps in one
  * read-write pass (8 bytes per update instead of 16; the second step's
  * moments follow by linearity of the transport from moment sums of the
  * previous field weighted by max(nu,0) and max(-nu,0), nu = v_x dt/dx);
- * 1 runs one step per pass.  Applies where the paired lane
- * mapping is used (even nv[2], 16-byte aligned f); the uneven batch
- * (bgk_fine_step_batched) always runs one step per pass. */
+ * 3 (default) runs triples (16/3 bytes per update; the third step's moments need the
+ * sums weighted by max(nu,0)^2 and max(-nu,0)^2 too) where every velocity tile
+ * lies in one v_x plane (nv[1] nv[2] a multiple of 64 times the velocities
+ * per lane) and nx >= 3, else pairs; 1 runs one step per pass.  Applies where
+ * the paired lane mapping is used (even nv[2], 16-byte aligned f); the
+ * uneven batch (bgk_fine_step_batched) always runs one step per pass. */
 int bgk_set_step_fusion(int32_t steps_per_pass);
 
 /* Launch-bound sequences (each parareal iteration, the serial chain of
@@ -370,6 +373,9 @@ int bgk_set_graphs(int32_t on);
  *   BGK_PROF_ONE_STEP       one step per pass (16 bytes per cell; 8 for the
  *                           first step of a slice, which computes the lifted
  *                           Maxwellian instead of reading it)
+ *   BGK_PROF_THREE_STEP     three IMEX steps per pass, reading and writing f
+ *                           (16 algorithmic bytes per cell per pass)
+ *   BGK_PROF_THREE_STEP_LIFT three steps from the lifted Maxwellian (8)
  * bgk_prof_read synchronises and returns, over the launches of `kind`
  * (BGK_PROF_ALL: every kind) since the last bgk_prof_enable(1), the summed
  * milliseconds, the launch count, the phase-space updates (cells times steps)
@@ -379,7 +385,9 @@ enum {
   BGK_PROF_ALL = 0,
   BGK_PROF_TWO_STEP = 1,
   BGK_PROF_TWO_STEP_LIFT = 2,
-  BGK_PROF_ONE_STEP = 3
+  BGK_PROF_ONE_STEP = 3,
+  BGK_PROF_THREE_STEP = 4,
+  BGK_PROF_THREE_STEP_LIFT = 5
 };
 int bgk_prof_enable(int32_t on);
 int bgk_prof_read(int32_t kind, double* total_ms, int64_t* launches, double* updates,

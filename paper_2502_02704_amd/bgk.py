@@ -536,8 +536,10 @@ def set_graphs(on: bool = True):
     _check(load_library().bgk_set_graphs(1 if on else 0), "bgk_set_graphs")
 
 
-def set_step_fusion(steps_per_pass: int = 2):
-    """IMEX steps per read-write pass over f (2 = fused pairs, default)."""
+def set_step_fusion(steps_per_pass: int = 3):
+    """IMEX steps per read-write pass over f: 1, 2 (fused pairs) or 3 (fused
+    triples where every velocity tile lies in one v_x plane, else pairs;
+    the default)."""
     _check(load_library().bgk_set_step_fusion(steps_per_pass), "bgk_set_step_fusion")
 
 
@@ -546,6 +548,7 @@ def prof_enable(on: bool = True):
 
 
 PROF_ALL, PROF_TWO_STEP, PROF_TWO_STEP_LIFT, PROF_ONE_STEP = 0, 1, 2, 3
+PROF_THREE_STEP, PROF_THREE_STEP_LIFT = 4, 5
 
 
 def prof_read(kind: int = PROF_ALL):

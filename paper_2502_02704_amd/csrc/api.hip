@@ -107,7 +107,7 @@ static long long blocks_for_tiles(const bgk_problem& p, int batch, Tiles t) {
   return (long long)batch * ntg * ((p.nx + t.chunk - 1) / t.chunk);
 }
 
-static bool g_fuse2 = true;  // two IMEX steps per pass where possible
+static int g_fuse = 3;  // IMEX steps per pass (1, 2 or 3) where possible
 
 // The v_x-column mapping fits a grid whose tiles fit the partial-sum capacity.
 static bool vcol_fits(const bgk_problem& p, Tiles t) {
@@ -120,7 +120,7 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
   // measured best on the 512 x 32^3 x 64-slice batch with 8-wave blocks:
   // fused passes 8 velocities per lane over 8-cell chunks, single steps 8
   // over short chunks
-  Tiles t = (pair && g_fuse2) ? Tiles{8, 8, 1} : Tiles{8, 4, pair};
+  Tiles t = (pair && g_fuse >= 2) ? Tiles{8, 8, 1} : Tiles{8, 4, pair};
   auto it = g_tuned.find({p.nx, p.nv[0], p.nv[1], p.nv[2], batch});
   const long long cells = (long long)batch * p.nx * nv3_of(p);
   // The exterior-force step runs on v_x columns (the v_x neighbours of a
@@ -150,13 +150,19 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
     t = Tiles{2, limited ? 16 : 8, 0};
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 512) t.chunk /= 2;
   } else if (it != g_tuned.end()) t = it->second;
-  else if (pair && g_fuse2 && cells < (1LL << 24)) {
+  else if (pair && g_fuse >= 2 && cells < (1LL << 24)) {
     // latency-bound sizes (f fits the last-level cache): short velocity
     // tiles, x chunks as long as the grid keeps about two blocks per CU
     t = Tiles{2, 16, 1};
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 512) t.chunk /= 2;
   } else {
-    // enough work items to fill 256 CUs several times over
+    // enough work items to fill 256 CUs several times over.  Three-step
+    // passes (grids whose v_x planes are whole tiles of 4 velocities per
+    // lane) hold three levels of rows: 4 velocities per lane, and 16-cell
+    // chunks to amortise the deeper halo (measured on the 512 x 32^3 x
+    // 64-slice batch)
+    if (pair && g_fuse == 3 && p.nx >= 3 && ((long long)p.nv[1] * p.nv[2]) % (kWave * 4) == 0)
+      t = Tiles{4, 16, 1};
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 4096) t.chunk /= 2;
     if (blocks_for_tiles(p, batch, t) < 2048) t.elems = 4;
     if (blocks_for_tiles(p, batch, t) < 1024) t.elems = 2;
@@ -195,7 +201,7 @@ struct Carve {
 constexpr int kMaxInst = 4096;
 
 struct FineRegions {  // fine solve of B members of one grid
-  size_t buf0, buf1, part, fac, vg, vout, fac2, aux;
+  size_t buf0, buf1, part, fac, vg, vout, fac2, aux, fac3, aux2;
 };
 constexpr size_t kNone = ~(size_t)0;  // region not allocated
 
@@ -217,6 +223,8 @@ static FineRegions carve_fine(Carve& c, const bgk_problem& p, int B, int nbufs) 
   r.vout = c.take((size_t)B * p.nx * 5 * sizeof(double));
   r.fac2 = c.take((size_t)B * p.nx * (p.nv[0] + p.nv[1] + p.nv[2]) * sizeof(double));
   r.aux = c.take((size_t)B * p.nx * kAux * sizeof(double));
+  r.fac3 = c.take((size_t)B * p.nx * (p.nv[0] + p.nv[1] + p.nv[2]) * sizeof(double));
+  r.aux2 = c.take((size_t)B * p.nx * kAux2 * sizeof(double));
   return r;
 }
 
@@ -352,7 +360,7 @@ int launch_prim_to_cons(const double* W, double* V, int n, hipStream_t s) {
 // Two IMEX steps per pass over f (paired lane mapping only); switchable.
 static bool fused_for(const Tiles& t, int n_steps) {
   std::lock_guard<std::mutex> lk(g_mu);
-  return g_fuse2 && t.pair && n_steps >= 2;
+  return g_fuse >= 2 && t.pair && n_steps >= 2;
 }
 
 // Descriptor of B members of one grid advanced with step dt.  ns: sums per
@@ -406,12 +414,34 @@ static void attach_fine(Inst& I, void* ws, const FineRegions& r, double* buf1) {
   I.vout = at<double>(ws, r.vout);
   I.fac2 = at<double>(ws, r.fac2);
   I.aux = at<double>(ws, r.aux);
+  I.fac3 = at<double>(ws, r.fac3);
+  I.aux2 = at<double>(ws, r.aux2);
 }
 
 static int lds_doubles(const Inst& I, Tiles t) {
   return (t.chunk + (I.order == 2 ? 4 : 2)) * I.nvs;
 }
 static int lds_doubles2(const Inst& I, Tiles t) { return (2 * t.chunk + 6) * I.nvs; }
+static int lds_doubles3(const Inst& I, Tiles t) { return (3 * t.chunk + 12) * I.nvs; }
+
+static int fuse_mode() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_fuse;
+}
+
+// Three IMEX steps per pass: on when asked for, on grids with compact records
+// (every tile in one v_x plane), nx >= 3 (ghost rows three deep), 2 or 4
+// velocities per lane (three levels of rows in registers) and factor rows of
+// the three levels within 64 KiB of LDS.
+static bool triple_for(const Inst& h, Tiles t) {
+  int fuse;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    fuse = g_fuse;
+  }
+  return fuse == 3 && h.crec != 0 && h.nsum == 15 && h.nx >= 3 && t.pair && t.elems <= 4 &&
+         (size_t)lds_doubles3(h, t) * sizeof(double) <= 65536;
+}
 
 // Runs `n` relax-then-transport steps on the (uploaded) descriptor d_I.
 // first_mode: kCopy (read fin) or kLift (factors of the lifted Maxwellian
@@ -454,6 +484,49 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
     done += 2;
     return r;
   };
+  if (triple_for(h, t)) {
+    auto triple_pass = [&](int mode) -> int {
+      prof_before(s);
+      int r = launch_step3x(d_I, 1, h.items, mode, phase, t, lds_doubles3(h, t), s);
+      prof_after(s, 3.0 * upd, mode == kLift ? 8.0 / 3.0 : 16.0 / 3.0,
+                 mode == kLift ? BGK_PROF_THREE_STEP_LIFT : BGK_PROF_THREE_STEP);
+      phase ^= 1;
+      done += 3;
+      return r;
+    };
+    // the first pass starts from the lift (write-only) or the copy: n mod 3
+    // decides whether it takes three, two or one step
+    if (first_mode == kLift && n >= 3 && n % 3 == 0) {
+      if ((rc = reduce(kRedW2x3))) return rc;
+      if ((rc = reduce(kRedW3x3))) return rc;
+      if ((rc = triple_pass(kLift))) return rc;
+    } else if (first_mode == kLift && n >= 2 && n % 3 == 2) {
+      if ((rc = reduce(kRedW2))) return rc;
+      if ((rc = pair_pass(kLift))) return rc;
+    } else {
+      if ((rc = single(first_mode))) return rc;
+      done = 1;
+    }
+    if ((n - done) % 3 == 2) {
+      if ((rc = reduce(kRedW1))) return rc;
+      if ((rc = reduce(kRedW2))) return rc;
+      if ((rc = pair_pass(kRelax))) return rc;
+    }
+    while (n - done >= 3) {
+      if ((rc = reduce(kRedW1x3))) return rc;
+      if ((rc = reduce(kRedW2x3))) return rc;
+      if ((rc = reduce(kRedW3x3))) return rc;
+      if ((rc = triple_pass(kRelax))) return rc;
+    }
+    if (n - done == 1) {
+      if ((rc = reduce(kRedRelaxFactors))) return rc;
+      if ((rc = single(kRelax))) return rc;
+      done += 1;
+    }
+    if ((rc = reduce(project_last ? kRedProject : kRedRelaxFactors))) return rc;
+    *last_sel = phase;
+    return BGK_OK;
+  }
   // An odd step count takes its single step first, from the lift: that pass
   // only writes f (8 bytes per update instead of the 16 of a later single).
   if (first_mode == kLift && n >= 2 && n % 2 == 0) {
@@ -481,8 +554,9 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
 // Lift (factors from the conserved vin of every member) then n steps.
 static int lift_and_run(const Inst* d_I, const Inst& h, int n, bool project_last, Tiles t,
                         int* d_status, hipStream_t s, int* last_sel) {
+  // a three-step first pass needs the nu+^2, nu-^2 weighted sums of the lift
   int rc = launch_lift_factors(d_I, 1, (long long)h.nbatch * h.nx, nullptr, d_status, s,
-                               h.nsum == 15 ? 1 : 0);
+                               h.nsum == 15 ? (triple_for(h, t) ? 2 : 1) : 0);
   if (rc) return rc;
   return run_steps(d_I, h, n, kLift, project_last, t, d_status, s, last_sel);
 }
@@ -981,7 +1055,7 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
     if ((rc = run_graph(graph_key("pit", ws, ws_bytes, *prob,
                                   {(double)n_slices, span, (double)k, (double)t.elems,
                                    (double)t.chunk, (double)(t.pair + 2 * t.vcol),
-                                   (double)I.nsum,
+                                   (double)I.nsum, (double)fuse_mode(),
                                    tol > 0.0 ? 1.0 : 0.0, (double)(uintptr_t)F.E, F.emax,
                                    viscous ? 1.0 : 0.0, (double)lift_order}),
                         s, iteration)))
@@ -1090,6 +1164,7 @@ static int serial_impl(const bgk_problem* prob, const Force& F, int lift_order,
   if ((rc = run_graph(graph_key("ser", ws, ws_bytes, *prob,
                                 {(double)n_slices, span, (double)t.elems, (double)t.chunk,
                                  (double)(t.pair + 2 * t.vcol), (double)ns,
+                                 (double)fuse_mode(),
                                  (double)(uintptr_t)F.E, F.emax,
                                  (double)lift_order}),
                       s, chain)))
@@ -1198,9 +1273,9 @@ int bgk_n_steps_force(const bgk_problem* prob, double e_max, double t_span, int3
 }
 
 int bgk_set_step_fusion(int32_t steps_per_pass) {
-  if (steps_per_pass != 1 && steps_per_pass != 2) return invalid("steps_per_pass must be 1 or 2");
+  if (steps_per_pass < 1 || steps_per_pass > 3) return invalid("steps_per_pass must be 1, 2 or 3");
   std::lock_guard<std::mutex> lk(g_mu);
-  g_fuse2 = steps_per_pass == 2;
+  g_fuse = steps_per_pass;
   return BGK_OK;
 }
 
@@ -1527,7 +1602,7 @@ int bgk_prof_enable(int32_t on) {
 
 int bgk_prof_read(int32_t kind, double* total_ms, int64_t* launches, double* cells,
                   double* bytes) {
-  if (kind < BGK_PROF_ALL || kind > BGK_PROF_ONE_STEP) return invalid("unknown timing kind");
+  if (kind < BGK_PROF_ALL || kind > BGK_PROF_THREE_STEP_LIFT) return invalid("unknown timing kind");
   std::lock_guard<std::mutex> lk(g_prof_mu);
   double ms = 0.0, c = 0.0, by = 0.0;
   int64_t n = 0;

@@ -55,7 +55,9 @@ struct Inst {
   const double* vin;           // lift source moments (conserved)[nbatch][nx][5]
   double* vout;                // projected relaxed moments     [nbatch][nx][5]
   double* fac2;                // factors of the second step of a pass [..][nvs]
-  double* aux;                 // per-cell weighted sums (two-step)  [..][nx][30]
+  double* aux;                 // per-cell weighted sums (fused passes) [..][nx][kAux]
+  double* fac3;                // factors of the third step of a pass  [..][nvs]
+  double* aux2;                // sums of the second step (three-step) [..][nx][kAux2]
   const double* efield;        // exterior force E_i at x centres [nx]; null = none
   double emax;                 // Rusanov coefficient of the v_x flux (>= max |E_i|)
   double rv;                   // dt / dv_x
@@ -79,12 +81,21 @@ enum ReduceMode : int {
   kRedW1 = 4,              // kRedRelaxFactors + the weighted sums in aux
   kRedW2 = 5,              // moments of the next transported field from aux
                            // of cells i-1, i, i+1 -> second-step factors fac2
+  kRedW1x3 = 6,            // kRedW1 with the nu+^2, nu-^2 weighted sums too
+  kRedW2x3 = 7,            // kRedW2 -> fac2, and the weighted sums of the
+                           // second-step fields into aux2
+  kRedW3x3 = 8,            // kRedW2 on aux2 -> third-step factors fac3
 };
 
 // aux layout per x cell (conserved-moment units, 5 values each):
-//   S, S+, S-  moments of g weighted by 1, nu+ = max(nu,0), nu- = max(-nu,0)
-//   A, A+, A-  the same sums of the Maxwellian M[U(g)]
-constexpr int kAux = 30;
+//   S, S+, S-    moments of g weighted by 1, nu+ = max(nu,0), nu- = max(-nu,0)
+//   A, A+, A-    the same sums of the Maxwellian M[U(g)]
+//   S++, S--     moments of g weighted by nu+^2, nu-^2   (three-step passes)
+//   A++, A--     the same sums of M[U(g)]                (three-step passes)
+// aux2 (three-step passes) holds the first 30 values of that layout for the
+// pass's second-step field g^{m+1} and its Maxwellian.
+constexpr int kAux = 50;
+constexpr int kAux2 = 30;
 
 // ---------------------------------------------------------------- errors --
 void set_error(const std::string& msg);
@@ -148,6 +159,10 @@ int launch_lift_factors(const Inst* d_insts, int n_inst, long long total_cells,
 int launch_step2x2(const Inst* d_insts, int n_inst, long long total_items,
                    int mode, int phase, Tiles t, int lds_doubles, bool uni_only,
                    hipStream_t s);
+// Three IMEX steps per pass (paired lanes, every tile in one v_x plane,
+// compact records, nx >= 3): mode kRelax or kLift for the first.
+int launch_step3x(const Inst* d_insts, int n_inst, long long total_items, int mode,
+                  int phase, Tiles t, int lds_doubles, hipStream_t s);
 // Partial sums of an arbitrary f (source = fin), no transport.
 int launch_partials(const Inst* d_insts, int n_inst, long long total_items,
                     int elems, int chunk, hipStream_t s);

@@ -208,6 +208,29 @@ __device__ __forceinline__ int scatter16_index(int lane) {
   return 8 * (lane & 1) + 4 * ((lane >> 1) & 1) + 2 * ((lane >> 2) & 1) + ((lane >> 3) & 1);
 }
 
+// Lane holding total c after wave_reduce_scatter16 (the 4-bit reversal).
+__device__ __forceinline__ constexpr int lane_of_slot16(int c) {
+  return ((c & 1) << 3) | ((c & 2) << 1) | ((c & 4) >> 1) | ((c & 8) >> 3);
+}
+
+// Sums of N values over the 64 lanes, every total returned to every lane:
+// reduce-scatter in groups of 16 (17 lane exchanges per group instead of 96),
+// then each total read from the lane that holds it.  Fixed order: bitwise
+// reproducible.
+template <int N>
+__device__ __forceinline__ void wave_sum_all_n(double (&v)[N], int lane) {
+#pragma unroll
+  for (int g = 0; g < N; g += 16) {
+    double t[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) t[c] = g + c < N ? v[g + c] : 0.0;
+    const double tot = wave_reduce_scatter16(t, lane);
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (g + c < N) v[g + c] = readlane_d(tot, lane_of_slot16(c));
+  }
+}
+
 // Raw rows in flight ahead of the one relaxed, in the two-step march.
 #ifndef BGK_PF2X2
 #define BGK_PF2X2 1
@@ -1232,6 +1255,191 @@ __global__ __launch_bounds__(kBlock) void k_step2x2(const Inst* __restrict__ ins
     BGK_MARCH_DISPATCH(Call, I, lds1, lds2, b, tile, lane, i0, i1, phase, vxu, nuu);
 }
 
+// ---------------------------------------------- three steps in one pass --
+// Reads g^m once, writes g^{m+3} once: 16/3 bytes per phase-space update.
+//   f^m     = a g^m + al M[U(g^m)]           (lift: f^0 = M[U0])  -- factors fac
+//   g^{m+1} = T f^m,  f^{m+1} = a g^{m+1} + al M[U(g^{m+1})]         -- fac2
+//   g^{m+2} = T f^{m+1},  f^{m+2} = a g^{m+2} + al M[U(g^{m+2})]     -- fac3
+//   g^{m+3} = T f^{m+2}                      (stored, with compact records)
+// U(g^{m+1}) and U(g^{m+2}) are known before the pass.  Upwind transport is
+// T h_i = (1 - nu+ - nu-) h_i + nu+ h_{i-1} + nu- h_{i+1} per velocity, so the
+// moments of T h and their nu+ and nu- weighted sums (nu+ nu- = 0) follow
+// from the sums of h weighted by 1, nu+, nu-, nu+^2, nu-^2 at cells i-1, i,
+// i+1; for h = a g + al M those come from the records of g and from 1-D sums
+// of the separable M (reductions kRedW1x3, kRedW2x3, kRedW3x3).  Tiles lie in
+// one v_x plane (uniform nu).  The march keeps level-1 rows k+1 .. k+3,
+// level-2 rows k .. k+2 and level-3 rows k-1 .. k+1 around output row k;
+// level-2 and level-3 values outside the domain are, for Neumann ends, copies
+// of the boundary row of the same level (the single step's ghost cells).
+// Raw rows in flight in the three-step march.
+#ifndef BGK_PF3X
+#define BGK_PF3X 2
+#endif
+
+template <int P, int MODE, int CASE, int DIR>
+__device__ __forceinline__ void step3x_march(const Inst& I, const double* lds1,
+                                             const double* lds2, const double* lds3,
+                                             int b, int tile, int lane, int i0, int i1,
+                                             int phase, double vxu, double nuu) {
+  constexpr int SGN = CASE == kTilePos ? 1 : -1;
+  const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
+  PairEls<P> e;
+  setup_pairs<P, true>(I, tile, lane, e);
+  const double dvz = I.dv[2];
+  const long long mbase = (long long)b * nx * nv3;
+  const double* src = I.buf[phase] + mbase;
+  double* dst = I.buf[phase ^ 1] + mbase;
+  const double a = I.a;
+  const bool neumann = I.bc == 0;
+  const int len = i1 - i0;
+  auto row_at = [&](int k) { return DIR > 0 ? i0 + k : i1 - 1 - k; };
+  auto outside = [&](int k) {
+    const int r = row_at(k);
+    return r < 0 || r >= nx;
+  };
+  auto load_row = [&](int k, double2 (&raw)[P]) {
+    if (MODE == kLift) return;
+    const double* row = src + (long long)ghost_row(row_at(k), nx, I.bc) * nv3;
+#pragma unroll
+    for (int p = 0; p < P; ++p) raw[p] = *reinterpret_cast<const double2*>(row + e.jofs[p]);
+  };
+  // level 1 at position k: rows i0-3 .. i1+2 staged in lds1
+  auto level1 = [&](int k, const double2 (&raw)[P], double2 (&out)[P]) {
+    const double* fr = lds1 + (row_at(k) - (i0 - 3)) * nvs;
+#pragma unroll
+    for (int p = 0; p < P; ++p) out[p] = relax_pair<MODE>(fr, e.off[p], a, raw[p]);
+  };
+  // level L+1 at position k from level L at k-1, k, k+1 (lds: the factor
+  // rows of level L+1, first row `first`)
+  auto next = [&](const double* lds, int first, int k, const double2 (&bh)[P],
+                  const double2 (&c)[P], const double2 (&ah)[P], double2 (&out)[P]) {
+    const double* fr = lds + (row_at(k) - first) * nvs;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const double2 g = transport_pair<DIR, SGN>(nuu, bh[p], c[p], ah[p]);
+      out[p] = relax_pair<kRelax>(fr, e.off[p], a, g);
+    }
+  };
+  auto copy = [&](double2 (&d)[P], const double2 (&s)[P]) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) d[p] = s[p];
+  };
+
+  double2 l1b[P], l1c[P];  // level 1 at positions k+1, k+2
+  double2 l2b[P], l2c[P];  // level 2 at k, k+1
+  double2 l3b[P], l3c[P];  // level 3 at k-1, k
+  // raw rows in flight: rows k+3 .. k+2+R in R buffers used in turn (the loop
+  // is unrolled by R, so no buffer is copied while its load is outstanding)
+  constexpr int R = BGK_PF3X;
+  double2 raw[R][P];
+  {
+    double2 x0[P], x1[P], x2[P], r0[P], r1[P], y0[P], y1[P];
+    load_row(-3, r0);
+    load_row(-2, r1);
+    level1(-3, r0, x0);
+    load_row(-1, r0);
+    level1(-2, r1, x1);
+    load_row(0, r1);
+    level1(-1, r0, x2);
+    next(lds2, i0 - 2, -2, x0, x1, x2, y0);  // level 2 at -2
+    load_row(1, r0);
+    level1(0, r1, x0);
+    next(lds2, i0 - 2, -1, x1, x2, x0, y1);  // level 2 at -1
+    load_row(2, r1);
+    level1(1, r0, x1);
+    next(lds2, i0 - 2, 0, x2, x0, x1, l2b);  // level 2 at 0
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (3 + j <= len + 2) load_row(3 + j, raw[j]);
+    level1(2, r1, x2);
+    next(lds2, i0 - 2, 1, x0, x1, x2, l2c);  // level 2 at 1
+    if (neumann) {
+      // position 0 is inside; outside positions copy their inner neighbour
+      if (outside(1)) copy(l2c, l2b);
+      if (outside(-1)) copy(y1, l2b);
+      if (outside(-2)) copy(y0, y1);
+    }
+    next(lds3, i0 - 1, -1, y0, y1, l2b, l3b);  // level 3 at -1
+    next(lds3, i0 - 1, 0, y1, l2b, l2c, l3c);  // level 3 at 0
+    if (neumann && outside(-1)) copy(l3b, l3c);
+    copy(l1b, x1);
+    copy(l1c, x2);
+  }
+  // output row k; rw holds row k+3 and takes the load of row k+3+R
+  auto step = [&](int k, double2 (&rw)[P]) {
+    double2 l1a[P], l2a[P], l3a[P];
+    level1(k + 3, rw, l1a);
+    if (k + 3 + R <= len + 2) load_row(k + 3 + R, rw);  // in flight meanwhile
+    next(lds2, i0 - 2, k + 2, l1b, l1c, l1a, l2a);
+    if (neumann && outside(k + 2)) copy(l2a, l2c);
+    next(lds3, i0 - 1, k + 1, l2b, l2c, l2a, l3a);
+    if (neumann && outside(k + 1)) copy(l3a, l3c);
+    const int r = row_at(k);
+    Acc<15, true> acc;
+    acc.zero();
+    double* drow = dst + (long long)r * nv3;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const double2 g = transport_pair<DIR, SGN>(nuu, l3b[p], l3c[p], l3a[p]);
+      store_pair(drow, e.jofs[p], g);
+      acc.add(g, e.vx[p], e.vy[p], e.vz[p], dvz, e.q0(p), e.q1(p), nuu);
+    }
+    acc.store(I, b, r, tile, lane, vxu, nuu);
+    copy(l1b, l1c);
+    copy(l1c, l1a);
+    copy(l2b, l2c);
+    copy(l2c, l2a);
+    copy(l3b, l3c);
+    copy(l3c, l3a);
+  };
+  for (int k = 0; k < len; k += R) {
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (k + j < len) step(k + j, raw[j]);
+  }
+}
+
+template <int P, int MODE>
+struct Step3xCall {
+  template <int CASE, int DIR>
+  static __device__ __forceinline__ void run(const Inst& I, const double* lds1,
+                                             const double* lds2, const double* lds3, int b,
+                                             int tile, int lane, int i0, int i1, int phase,
+                                             double vxu, double nuu) {
+    step3x_march<P, MODE, CASE, DIR>(I, lds1, lds2, lds3, b, tile, lane, i0, i1, phase,
+                                     vxu, nuu);
+  }
+};
+
+template <int P, int MODE>
+__global__ __launch_bounds__(kBlock) void k_step3x(const Inst* __restrict__ insts,
+                                                   int n_inst, int chunk, int phase) {
+  extern __shared__ double lds[];
+  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const int q = find_inst(insts, n_inst, item);
+  const Inst& I = insts[q];
+  const long long local = item - I.item_begin;
+  int b, tg, c;
+  decode_item(I, local, b, tg, c);
+  const int i0 = c * chunk;
+  const int i1 = min(i0 + chunk, I.nx);
+  const int len = i1 - i0;
+  double* lds1 = lds;
+  double* lds2 = lds1 + (len + 6) * I.nvs;
+  double* lds3 = lds2 + (len + 4) * I.nvs;
+  stage_rows(I, I.fac, b, i0 - 3, len + 6, lds1);
+  stage_rows(I, I.fac2, b, i0 - 2, len + 4, lds2);
+  stage_rows(I, I.fac3, b, i0 - 1, len + 2, lds3);
+  __syncthreads();
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int tile = tg * kWavesPerBlock + wave;
+  if (tile >= I.ntiles) return;
+  double vxu, nuu;
+  using Call = Step3xCall<P, MODE>;
+  BGK_MARCH_DISPATCH_UNI(Call, I, lds1, lds2, lds3, b, tile, lane, i0, i1, phase, vxu, nuu);
+}
+
 // -------------------------------------------- partial sums of a field --
 // Moments of an arbitrary f (source fin), same tiling, no transport.
 template <int E>
@@ -1317,17 +1525,23 @@ __device__ __forceinline__ void write_factors(const Inst& I, double* row,
 }
 
 // Separable moment sums of the Maxwellian with factors exp(-(v-u)^2/(2 theta))
-// per axis (C0 * dv3 applied by the caller): for weights w in {1, nu+, nu-} of
-// v_x (nu = v_x dt/dx), A^w = (rho, m_x, m_y, m_z, E) moments of w M.
-// Writes 15 values: A (5), A+ (5), A- (5), scaled by K = C0 dv3.  All lanes
-// return the same values.
+// per axis (C0 * dv3 applied by the caller): for weights w of v_x in {1, nu+,
+// nu-} (NW = 3) and also nu+^2, nu-^2 (NW = 5), nu = v_x dt/dx, A^w = (rho,
+// m_x, m_y, m_z, E) moments of w M, scaled by K = C0 dv3: 5 NW values in that
+// weight order.  All lanes return the same values.
+// row (nullable): also writes the factor row of the same exponentials (Ex
+// scaled by Cx, Ey, Ez), as write_factors does.
+template <int NW>
 __device__ __forceinline__ void maxwell_weighted_sums(const Inst& I, int lane,
                                                       const double u[3], double th,
-                                                      double K, double (&A)[15]) {
-  // x: X^w_k = sum w(vx) vx^k Ex, w in {1, nu+, nu-}, k = 0..2; y, z: k = 0..2
-  double t[15];
+                                                      double K, double (&A)[5 * NW],
+                                                      double* row = nullptr,
+                                                      double Cx = 0.0) {
+  // x: X^w_k = sum w(vx) vx^k Ex, k = 0..2 (3 NW values); y, z: k = 0..2
+  constexpr int NT = 3 * NW + 6;
+  double t[NT];
 #pragma unroll
-  for (int c = 0; c < 15; ++c) t[c] = 0.0;
+  for (int c = 0; c < NT; ++c) t[c] = 0.0;
   const double inv2t = 1.0 / (2.0 * th);
   for (int kk = lane; kk < I.nvs; kk += kWave) {
     int ax = (kk < I.nvx) ? 0 : (kk < I.nvx + I.nvy ? 1 : 2);
@@ -1335,6 +1549,7 @@ __device__ __forceinline__ void maxwell_weighted_sums(const Inst& I, int lane,
     const double v = vgrid(I, ax, j);
     const double d = v - u[ax];
     const double ex = exp(-d * d * inv2t);
+    if (row != nullptr) row[kk] = ax == 0 ? Cx * ex : ex;
     const double e1 = v * ex, e2 = v * v * ex;
     if (ax == 0) {
       const double nu = v * I.r;
@@ -1342,17 +1557,22 @@ __device__ __forceinline__ void maxwell_weighted_sums(const Inst& I, int lane,
       t[0] += ex; t[1] += e1; t[2] += e2;
       t[3] += wp * ex; t[4] += wp * e1; t[5] += wp * e2;
       t[6] += wm * ex; t[7] += wm * e1; t[8] += wm * e2;
+      if (NW == 5) {
+        const double wpp = wp * wp, wmm = wm * wm;
+        t[9] += wpp * ex; t[10] += wpp * e1; t[11] += wpp * e2;
+        t[12] += wmm * ex; t[13] += wmm * e1; t[14] += wmm * e2;
+      }
     } else if (ax == 1) {
-      t[9] += ex; t[10] += e1; t[11] += e2;
+      t[3 * NW] += ex; t[3 * NW + 1] += e1; t[3 * NW + 2] += e2;
     } else {
-      t[12] += ex; t[13] += e1; t[14] += e2;
+      t[3 * NW + 3] += ex; t[3 * NW + 4] += e1; t[3 * NW + 5] += e2;
     }
   }
+  wave_sum_all_n<NT>(t, lane);
+  const double Y0 = t[3 * NW], Y1 = t[3 * NW + 1], Y2 = t[3 * NW + 2];
+  const double Z0 = t[3 * NW + 3], Z1 = t[3 * NW + 4], Z2 = t[3 * NW + 5];
 #pragma unroll
-  for (int c = 0; c < 15; ++c) t[c] = wave_sum_all(t[c]);
-  const double Y0 = t[9], Y1 = t[10], Y2 = t[11], Z0 = t[12], Z1 = t[13], Z2 = t[14];
-#pragma unroll
-  for (int w = 0; w < 3; ++w) {
+  for (int w = 0; w < NW; ++w) {
     const double X0 = t[3 * w], X1 = t[3 * w + 1], X2 = t[3 * w + 2];
     A[5 * w + 0] = K * X0 * Y0 * Z0;
     A[5 * w + 1] = K * X1 * Y0 * Z0;
@@ -1385,33 +1605,67 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
   long long cl;
   const int q = find_inst_cell(insts, n_inst, cell, &cl);
   const Inst& I = insts[q];
-  if (mode == kRedW2) {
+  if (mode == kRedW2 || mode == kRedW2x3 || mode == kRedW3x3) {
     // moments of the next transported field T(a g + al M[U(g)]) at this cell
+    // from the weighted sums of g and M at cells i-1, i, i+1 (upwind
+    // transport: T h_i = (1 - nu+ - nu-) h_i + nu+ h_{i-1} + nu- h_{i+1})
     const int nx = I.nx;
     const long long b = cl / nx;
     const int i = (int)(cl - b * nx);
-    const double* ac = I.aux + cl * kAux;
-    const double* am = I.aux + (b * nx + ghost_row(i - 1, nx, I.bc)) * kAux;
-    const double* ap = I.aux + (b * nx + ghost_row(i + 1, nx, I.bc)) * kAux;
+    const double* base = mode == kRedW3x3 ? I.aux2 : I.aux;
+    const int stride = mode == kRedW3x3 ? kAux2 : kAux;
+    const double* ac = base + cl * stride;
+    const double* am = base + (b * nx + ghost_row(i - 1, nx, I.bc)) * stride;
+    const double* ap = base + (b * nx + ghost_row(i + 1, nx, I.bc)) * stride;
+    // lane 5 w + c forms component c of the plain (w = 0) moments of T h and,
+    // for kRedW2x3, of its nu+ (w = 1) and nu- (w = 2) weighted sums (nu+ nu-
+    // = 0: the sums of h weighted by nu+ and nu+^2 at i and i-1, by nu- and
+    // nu-^2 at i and i+1)
+    double val = 0.0;
+    if (lane < (mode == kRedW2x3 ? 15 : 5)) {
+      const int w = lane / 5, c = lane - 5 * (lane / 5);
+      double tg, tm;
+      if (w == 0) {
+        tg = ac[c] - ac[5 + c] - ac[10 + c] + am[5 + c] + ap[10 + c];
+        tm = ac[15 + c] - ac[20 + c] - ac[25 + c] + am[20 + c] + ap[25 + c];
+      } else if (w == 1) {
+        tg = ac[5 + c] - ac[30 + c] + am[30 + c];
+        tm = ac[20 + c] - ac[40 + c] + am[40 + c];
+      } else {
+        tg = ac[10 + c] - ac[35 + c] + ap[35 + c];
+        tm = ac[25 + c] - ac[45 + c] + ap[45 + c];
+      }
+      val = I.a * tg + I.al * tm;
+    }
     double V[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      const double tg = ac[c] - ac[5 + c] - ac[10 + c] + am[5 + c] + ap[10 + c];
-      const double tm = ac[15 + c] - ac[20 + c] - ac[25 + c] + am[20 + c] + ap[25 + c];
-      V[c] = I.a * tg + I.al * tm;
-    }
+    for (int c = 0; c < 5; ++c) V[c] = readlane_d(val, c);
     double rho, u[3], th;
     cons_to_prim(V, rho, u, th);
     if (lane == 0 && !physical(rho, th)) *status = 1;
-    write_factors(I, I.fac2 + cl * I.nvs, lane, I.al * rho * pow(2.0 * M_PI * th, -1.5),
-                  u, th);
+    const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
+    double* fout = (mode == kRedW3x3 ? I.fac3 : I.fac2) + cl * I.nvs;
+    if (mode != kRedW2x3) write_factors(I, fout, lane, I.al * C0, u, th);
+    if (mode == kRedW2x3) {
+      double A[15];
+      maxwell_weighted_sums<3>(I, lane, u, th, C0 * I.dv3, A, fout, I.al * C0);
+      double* ax = I.aux2 + cl * kAux2;
+      if (lane < 15) ax[lane] = val;
+      if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 15; ++c) ax[15 + c] = A[c];
+      }
+    }
     return;
   }
   const int ns = I.nsum;
   const double* pp = I.part + cl * I.part_tiles * 5;
-  double s[15];
+  // weight classes of the sums: 1 (and nu+, nu- for W1; and nu+^2, nu-^2
+  // for W1x3, which needs compact records)
+  constexpr int NW = mode == kRedW1x3 ? 5 : (mode == kRedW1 ? 3 : 1);
+  double s[25];
 #pragma unroll
-  for (int c = 0; c < 15; ++c) s[c] = 0.0;
+  for (int c = 0; c < 25; ++c) s[c] = 0.0;
   if (I.crec) {
     // compact records (tiles inside one v_x plane): (sum g, sum v_y g,
     // sum v_z g, sum |v|^2 g); v_x and nu are the tile's
@@ -1422,13 +1676,21 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
       const double m[5] = {q[0], vx * q[0], q[1], q[2], q[3]};
 #pragma unroll
       for (int c = 0; c < 5; ++c) s[c] += m[c];
-      if (mode == kRedW1) {
+      if (NW >= 3) {
         const double nu = vx * I.r;
         const double wp = nu > 0.0 ? nu : 0.0, wm = nu < 0.0 ? -nu : 0.0;
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
           s[5 + c] += wp * m[c];
           s[10 + c] += wm * m[c];
+        }
+        if (NW == 5) {
+          const double wpp = wp * wp, wmm = wm * wm;
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            s[15 + c] += wpp * m[c];
+            s[20 + c] += wmm * m[c];
+          }
         }
       }
     }
@@ -1442,12 +1704,17 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
       }
     }
   }
-  constexpr int nred = (mode == kRedW1) ? 15 : 5;
+  {
+    double t[5 * NW];
 #pragma unroll
-  for (int c = 0; c < nred; ++c) s[c] = wave_sum_all(s[c]);
+    for (int c = 0; c < 5 * NW; ++c) t[c] = s[c];
+    wave_sum_all_n<5 * NW>(t, lane);
+#pragma unroll
+    for (int c = 0; c < 5 * NW; ++c) s[c] = t[c];
+  }
   // conserved units: rho, m from sums times dv3; E = sum |v|^2 g dv3 / 2
 #pragma unroll
-  for (int w = 0; w < 3; ++w) {
+  for (int w = 0; w < NW; ++w) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) s[5 * w + c] *= I.dv3;
     s[5 * w + 4] *= 0.5 * I.dv3;
@@ -1479,12 +1746,32 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
     return;
   }
   const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
-  if (mode == kRedRelaxFactors || mode == kRedMaxwellFactors || mode == kRedW1) {
-    write_factors(I, I.fac + cl * I.nvs, lane,
-                  mode == kRedMaxwellFactors ? C0 : I.al * C0, u, th);
+  if (mode == kRedRelaxFactors || mode == kRedMaxwellFactors || mode == kRedW1 ||
+      mode == kRedW1x3) {
+    // (W1, W1x3: the factor row is written with the weighted sums' exponentials)
+    if (mode == kRedRelaxFactors || mode == kRedMaxwellFactors)
+      write_factors(I, I.fac + cl * I.nvs, lane,
+                    mode == kRedMaxwellFactors ? C0 : I.al * C0, u, th);
+    if (mode == kRedW1x3) {
+      double A[25];
+      maxwell_weighted_sums<5>(I, lane, u, th, C0 * I.dv3, A, I.fac + cl * I.nvs, I.al * C0);
+      if (lane == 0) {
+        double* ax = I.aux + cl * kAux;
+#pragma unroll
+        for (int c = 0; c < 15; ++c) {
+          ax[c] = s[c];
+          ax[15 + c] = A[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 10; ++c) {
+          ax[30 + c] = s[15 + c];
+          ax[40 + c] = A[15 + c];
+        }
+      }
+    }
     if (mode == kRedW1) {
       double A[15];
-      maxwell_weighted_sums(I, lane, u, th, C0 * I.dv3, A);
+      maxwell_weighted_sums<3>(I, lane, u, th, C0 * I.dv3, A, I.fac + cl * I.nvs, I.al * C0);
       if (lane == 0) {
         double* ax = I.aux + cl * kAux;
 #pragma unroll
@@ -1498,7 +1785,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
   // kRedProject: moments of the relaxed field a g + al M[U(g)], with the
   // moments of the separable Maxwellian as products of 1D sums.
   double A[15];
-  maxwell_weighted_sums(I, lane, u, th, C0 * I.dv3, A);
+  maxwell_weighted_sums<3>(I, lane, u, th, C0 * I.dv3, A);
   const double vgv[5] = {rho, m[0], m[1], m[2], E};
   if (lane == 0) {
     double* vo = I.vout + cl * 5;
@@ -1510,7 +1797,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
 // Lift factors: C = rho (2 pi theta)^{-3/2} from primitive W (if given) or
 // from the conserved vin of each member.  with_aux: also the weighted
 // Maxwellian sums into aux (both the "g" and the "M" slots: the lifted field
-// is its own Maxwellian), for a two-step first pass.
+// is its own Maxwellian), for a two-step (1) or three-step (2) first pass.
 __global__ __launch_bounds__(kBlock) void k_lift_factors(
     const Inst* __restrict__ insts, int n_inst, long long total_cells,
     const double* __restrict__ W, int* status, int with_aux) {
@@ -1535,16 +1822,34 @@ __global__ __launch_bounds__(kBlock) void k_lift_factors(
     if (lane == 0) *status = 1;
   }
   const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
-  write_factors(I, I.fac + cl * I.nvs, lane, C0, u, th);
-  if (with_aux) {
+  double* row = I.fac + cl * I.nvs;
+  if (!with_aux) write_factors(I, row, lane, C0, u, th);
+  if (with_aux == 1) {
     double A[15];
-    maxwell_weighted_sums(I, lane, u, th, C0 * I.dv3, A);
+    maxwell_weighted_sums<3>(I, lane, u, th, C0 * I.dv3, A, row, C0);
     if (lane == 0) {
       double* ax = I.aux + cl * kAux;
 #pragma unroll
       for (int c = 0; c < 15; ++c) {
         ax[c] = A[c];
         ax[15 + c] = A[c];
+      }
+    }
+  } else if (with_aux == 2) {
+    // with the nu+^2, nu-^2 weighted sums, for a three-step first pass
+    double A[25];
+    maxwell_weighted_sums<5>(I, lane, u, th, C0 * I.dv3, A, row, C0);
+    if (lane == 0) {
+      double* ax = I.aux + cl * kAux;
+#pragma unroll
+      for (int c = 0; c < 15; ++c) {
+        ax[c] = A[c];
+        ax[15 + c] = A[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 10; ++c) {
+        ax[30 + c] = A[15 + c];
+        ax[40 + c] = A[15 + c];
       }
     }
   }
@@ -1735,6 +2040,31 @@ int launch_step2x2(const Inst* d_insts, int n_inst, long long total_items, int m
   return BGK_E_INVALID;
 }
 
+int launch_step3x(const Inst* d_insts, int n_inst, long long total_items, int mode,
+                  int phase, Tiles t, int lds_doubles, hipStream_t s) {
+  if (total_items <= 0) return BGK_OK;
+  if (!t.pair) {
+    set_error("three-step passes need the paired lane mapping");
+    return BGK_E_INVALID;
+  }
+  dim3 grid(blocks_for(total_items)), block(kBlock);
+  const size_t lds = (size_t)lds_doubles * sizeof(double);
+#define BGK_STEP3_CASE(PP, MM)                                                    \
+  if (t.elems == 2 * PP && mode == MM) {                                          \
+    hipLaunchKernelGGL((k_step3x<PP, MM>), grid, block, lds, s, d_insts, n_inst,  \
+                       t.chunk, phase);                                           \
+    hipError_t e_ = hipGetLastError();                                            \
+    return e_ == hipSuccess ? BGK_OK : hip_fail(e_, "k_step3x");                  \
+  }
+  BGK_STEP3_CASE(1, kRelax)
+  BGK_STEP3_CASE(1, kLift)
+  BGK_STEP3_CASE(2, kRelax)
+  BGK_STEP3_CASE(2, kLift)
+#undef BGK_STEP3_CASE
+  set_error("unsupported tile shape for a three-step pass");
+  return BGK_E_INVALID;
+}
+
 int launch_partials(const Inst* d_insts, int n_inst, long long total_items,
                     int elems, int chunk, hipStream_t s) {
   if (total_items <= 0) return BGK_OK;
@@ -1770,6 +2100,9 @@ int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
     BGK_REDUCE_CASE(kRedMaxwellFactors)
     BGK_REDUCE_CASE(kRedW1)
     BGK_REDUCE_CASE(kRedW2)
+    BGK_REDUCE_CASE(kRedW1x3)
+    BGK_REDUCE_CASE(kRedW2x3)
+    BGK_REDUCE_CASE(kRedW3x3)
 #undef BGK_REDUCE_CASE
     default:
       set_error("unknown reduction mode");

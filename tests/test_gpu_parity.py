@@ -41,10 +41,10 @@ TILES = [(0, 0, -1), (2, 1, 0), (4, 3, 0), (8, 16, 0), (2, 64, 0), (2, 1, 1), (4
 @pytest.fixture(autouse=True)
 def _reset_tiles():
     bgk.set_tiles(0, 0, -1)
-    bgk.set_step_fusion(2)
+    bgk.set_step_fusion(3)
     yield
     bgk.set_tiles(0, 0, -1)
-    bgk.set_step_fusion(2)
+    bgk.set_step_fusion(3)
 
 
 def states(p, seed, perturb=0.2):
@@ -107,6 +107,7 @@ def test_two_steps_per_pass(name, n, tiles):
     agree with the oracle and with one step per pass."""
     p = GRIDS[name]
     bgk.set_tiles(*tiles)
+    bgk.set_step_fusion(2)
     _, f = states(p, 60 + n)
     dt = 0.4 * (1.0 / p.nx) / max(abs(p.v_lo[0]), abs(p.v_hi[0]))
     fused = bgk.fine_steps(p, cuda(f), dt, n).cpu().numpy()
@@ -123,6 +124,7 @@ def test_two_steps_per_pass(name, n, tiles):
 @pytest.mark.parametrize("name", ["sod_nx64_nv16", "wide_periodic", "even_z_ragged"])
 def test_two_steps_per_pass_from_lift(name, n_span):
     p = GRIDS[name]
+    bgk.set_step_fusion(2)
     W, _ = states(p, 70)
     V = np.column_stack([W[:, 0], W[:, 0:1] * W[:, 1:4],
                          0.5 * W[:, 0] * (W[:, 1:4] ** 2).sum(1) + 1.5 * W[:, 0] * W[:, 4]])

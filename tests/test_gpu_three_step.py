@@ -1,0 +1,189 @@
+"""Three IMEX steps per read-write pass over f (Section 3.1's scheme, fused):
+parity with the CPU oracle and with one step per pass, element by element on
+the same seeded inputs at the 1e-12 normwise bar.  The fused pass needs the
+moments of the second and third fields before it runs; they follow from sums
+of the previous field weighted by 1, nu+, nu-, nu+^2 and nu-^2 (linearity of
+the upwind transport), so these tests exercise every weight class, both
+boundary conditions, ragged x chunks, chunks shorter than the three-deep
+stencil and every step count modulo 3."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2502_02704_amd import bgk
+from paper_2502_02704_amd import workloads as wl
+from tests.gpu_util import TOL, rel_f, rel_V
+from tests.test_gpu_parity import GRIDS, cuda, states
+
+pytestmark = pytest.mark.gpu
+
+# grids whose v_x planes are whole tiles of 128 (P = 1) or 256 (P = 2) velocities
+UNI_GRIDS = {
+    "uni_neumann": wl.Problem(nx=13, nv=(12, 8, 16), v_lo=(-6, -5, -7), v_hi=(6.5, 5, 7),
+                              bc=wl.BC_NEUMANN, eps=3e-3),
+    "uni_periodic": wl.Problem(nx=11, nv=(5, 16, 16), v_lo=(-6,) * 3, v_hi=(6,) * 3,
+                               bc=wl.BC_PERIODIC, eps=0.5),
+    "uni_nx3_neumann": wl.Problem(nx=3, nv=(4, 8, 16), v_lo=(-5,) * 3, v_hi=(5,) * 3,
+                                  bc=wl.BC_NEUMANN, eps=1e-2),
+    "uni_nx3_periodic": wl.Problem(nx=3, nv=(4, 8, 16), v_lo=(-5,) * 3, v_hi=(5,) * 3,
+                                   bc=wl.BC_PERIODIC, eps=2e-2),
+    "sod_nx64_nv16": wl.c1_sod_small().problem,
+}
+
+
+@pytest.fixture(autouse=True)
+def _reset():
+    bgk.set_tiles(0, 0, -1)
+    bgk.set_step_fusion(3)
+    yield
+    bgk.set_tiles(0, 0, -1)
+    bgk.set_step_fusion(3)
+
+
+def dt_of(p):
+    return 0.45 * ((p.x_hi - p.x_lo) / p.nx) / max(abs(p.v_lo[0]), abs(p.v_hi[0]))
+
+
+def conserved(W):
+    return np.column_stack([W[:, 0], W[:, 0:1] * W[:, 1:4],
+                            0.5 * W[:, 0] * (W[:, 1:4] ** 2).sum(1) + 1.5 * W[:, 0] * W[:, 4]])
+
+
+def tiles_for(p):
+    nyz = p.nv[1] * p.nv[2]
+    out = [(2, 1, 1), (2, 2, 1), (2, 5, 1), (2, 64, 1)]
+    if nyz % 256 == 0:
+        out += [(4, 3, 1), (4, 8, 1)]
+    return out
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6, 7, 9])
+@pytest.mark.parametrize("name", list(UNI_GRIDS))
+def test_three_steps_per_pass(name, n):
+    """Copy-mode start (a single step first), then triples and a remainder
+    pair or single: equal to the oracle and to one step per pass."""
+    p = UNI_GRIDS[name]
+    _, f = states(p, 300 + n)
+    dt = dt_of(p)
+    ref = oracle.fine_steps(p, f, dt, n)
+    bgk.set_step_fusion(1)
+    single = bgk.fine_steps(p, cuda(f), dt, n).cpu().numpy()
+    assert rel_f(single, ref) < TOL
+    bgk.set_step_fusion(3)
+    for tiles in tiles_for(p):
+        bgk.set_tiles(*tiles)
+        fused = bgk.fine_steps(p, cuda(f), dt, n).cpu().numpy()
+        bgk.check_status()
+        assert rel_f(fused, ref) < TOL, tiles
+        assert rel_f(fused, single) < 1e-13, tiles
+
+
+@pytest.mark.parametrize("span_steps", [3, 4, 5, 6, 8, 12])
+@pytest.mark.parametrize("name", ["uni_neumann", "uni_periodic", "uni_nx3_neumann",
+                                  "sod_nx64_nv16"])
+def test_three_steps_from_lift(name, span_steps):
+    """Lift-mode start: the first pass takes three, two or one steps from the
+    lifted Maxwellian (n mod 3), then triples; batched members, projected
+    moments against the oracle."""
+    p = UNI_GRIDS[name]
+    dv = (p.v_hi[0] - p.v_lo[0]) / p.nv[0]
+    vmax = max(abs(p.v_lo[0] + 0.5 * dv), abs(p.v_hi[0] - 0.5 * dv))
+    span = (span_steps - 0.5) * p.cfl * ((p.x_hi - p.x_lo) / p.nx) / vmax
+    n, _ = oracle.n_steps(p, span)
+    assert n == span_steps
+    Vs = [conserved(states(p, 320 + b)[0]) for b in range(2)]
+    Vin = np.stack(Vs)
+    for tiles in [(0, 0, -1), (2, 3, 1), (2, 16, 1)]:
+        bgk.set_tiles(*tiles)
+        got = bgk.fine_propagate_moments(p, cuda(Vin), span).cpu().numpy()
+        bgk.check_status()
+        for b in range(2):
+            assert rel_V(got[b], oracle.fine_propagate_moments(p, Vin[b], span)) < TOL, tiles
+
+
+def test_non_uniform_tiles_fall_back_to_pairs():
+    """Grids whose tiles straddle v_x planes run fused pairs under the
+    three-step setting: same results as with pairs."""
+    for name in ["wide_periodic", "asym_box", "even_z_ragged"]:
+        p = GRIDS[name]
+        _, f = states(p, 340)
+        dt = dt_of(p)
+        got3 = bgk.fine_steps(p, cuda(f), dt, 7).cpu().numpy()
+        bgk.set_step_fusion(2)
+        got2 = bgk.fine_steps(p, cuda(f), dt, 7).cpu().numpy()
+        bgk.set_step_fusion(3)
+        bgk.check_status()
+        assert np.array_equal(got3, got2), name
+        assert rel_f(got3, oracle.fine_steps(p, f, dt, 7)) < TOL
+
+
+def test_nx_two_falls_back_to_pairs():
+    p = wl.Problem(nx=2, nv=(4, 8, 16), v_lo=(-5,) * 3, v_hi=(5,) * 3, bc=wl.BC_PERIODIC,
+                   eps=1e-2)
+    _, f = states(p, 341)
+    dt = dt_of(p)
+    got = bgk.fine_steps(p, cuda(f), dt, 6).cpu().numpy()
+    bgk.check_status()
+    assert rel_f(got, oracle.fine_steps(p, f, dt, 6)) < TOL
+
+
+def test_three_step_kernel_runs_and_is_timed():
+    """On a grid with whole-plane tiles the propagation runs three-step
+    passes (timing kind BGK_PROF_THREE_STEP, 16/3 algorithmic bytes per
+    update)."""
+    p = UNI_GRIDS["sod_nx64_nv16"]
+    V = np.stack([conserved(states(p, 342)[0])])
+    n, _ = oracle.n_steps(p, 0.01)
+    bgk.prof_enable(True)
+    try:
+        bgk.fine_propagate_moments(p, cuda(V), 0.01)
+        ms, launches, upd, by = bgk.prof_read(bgk.PROF_THREE_STEP)
+        ms_l, launches_l, _, _ = bgk.prof_read(bgk.PROF_THREE_STEP_LIFT)
+    finally:
+        bgk.prof_enable(False)
+    assert launches + launches_l == n // 3
+    assert launches >= 1 and abs(by / upd - 16.0 / 3.0) < 1e-9
+
+
+def test_parareal_and_serial_with_three_step_passes():
+    """Parareal and the serial chain (graph-captured) under three-step
+    passes: equal to the oracle; switching the setting between calls does
+    not replay graphs captured under the other one."""
+    wk = wl.c1_sod_small()
+    p, W0 = wk.problem, cuda(wk.W0)
+    Vr, _, _ = oracle.parareal_iterate(p, wk.W0, wk.n_slices, wk.T, 3, 0.0)
+    Sr = oracle.serial_fine(p, wk.W0, wk.n_slices, wk.T)
+    outs = {}
+    for fuse in (3, 2, 3, 1, 3):
+        bgk.set_step_fusion(fuse)
+        V, _, kd = bgk.parareal_iterate(p, W0, wk.n_slices, wk.T, 3, 0.0)
+        S = bgk.serial_fine(p, W0, wk.n_slices, wk.T)
+        bgk.check_status()
+        V, S = V.cpu().numpy(), S.cpu().numpy()
+        assert kd == 3
+        assert rel_V(V, Vr) < TOL and rel_V(S, Sr) < TOL, fuse
+        if fuse in outs:
+            assert np.array_equal(V, outs[fuse][0]) and np.array_equal(S, outs[fuse][1])
+        outs[fuse] = (V, S)
+    assert rel_V(outs[3][0], outs[1][0]) < 1e-13
+
+
+def test_smooth_periodic_full_batch_three_steps_sampled():
+    """The benchmark batch (64 slices of 512 x 32^3, 25 steps: one single
+    step from the lift, then eight triples) under three-step passes; two
+    sampled members against the oracle."""
+    wk = wl.c2_smooth_periodic(eps=1e-2)
+    p = wk.problem
+    B = wk.n_slices
+    x = p.x_centres()
+    V = np.empty((B, p.nx, 5))
+    for b in range(B):
+        rho = 1 + 0.2 * np.sin(2 * np.pi * (x + b / B))
+        u = 0.1 * np.sin(2 * np.pi * (x + b / B))
+        V[b] = np.column_stack([rho, rho * u, 0 * x, 0 * x, 0.5 * rho * u * u + 1.5 * rho])
+    span = wk.T / wk.n_slices
+    got = bgk.fine_propagate_moments(p, cuda(V), span).cpu().numpy()
+    bgk.check_status()
+    for b in (0, 41):
+        assert rel_V(got[b], oracle.fine_propagate_moments(p, V[b], span)) < TOL
