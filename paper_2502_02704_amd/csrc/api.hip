@@ -161,8 +161,13 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
     // lane) hold three levels of rows: 4 velocities per lane, and 16-cell
     // chunks to amortise the deeper halo (measured on the 512 x 32^3 x
     // 64-slice batch)
-    if (pair && g_fuse == 3 && p.nx >= 3 && ((long long)p.nv[1] * p.nv[2]) % (kWave * 4) == 0)
-      t = Tiles{4, 16, 1};
+    if (pair && g_fuse == 3 && p.nx >= 3 && ((long long)p.nv[1] * p.nv[2]) % (kWave * 4) == 0) {
+      // the longest chunk up to 16 whose three levels of factor rows fit 64 KiB of LDS
+      const long long nvs = (long long)p.nv[0] + p.nv[1] + p.nv[2];
+      int ch = 16;
+      while (ch > 1 && (3LL * ch + 12) * nvs * (long long)sizeof(double) > 65536) --ch;
+      t = Tiles{4, ch, 1};
+    }
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 4096) t.chunk /= 2;
     if (blocks_for_tiles(p, batch, t) < 2048) t.elems = 4;
     if (blocks_for_tiles(p, batch, t) < 1024) t.elems = 2;

@@ -187,3 +187,23 @@ def test_smooth_periodic_full_batch_three_steps_sampled():
     bgk.check_status()
     for b in (0, 41):
         assert rel_V(got[b], oracle.fine_propagate_moments(p, V[b], span)) < TOL
+
+
+def test_sod_large_full_size_three_step_pass():
+    """Nx=2048, 48^3 on [-10,10]^3 (the large Sod workload, 144 factor values
+    per x row, so 14-cell chunks keep three levels of factor rows in 64 KiB of
+    LDS): four steps from the lifted Sod data (one single step, one three-step
+    pass), whole field against the oracle."""
+    wk = wl.c3_sod_large()
+    p = wk.problem
+    n, dt = oracle.n_steps(p, wk.T / wk.n_slices)
+    f0 = oracle.lift(p, wk.W0)
+    bgk.prof_enable(True)
+    try:
+        got = bgk.fine_steps(p, cuda(f0), dt, 4).cpu().numpy()
+        _, launches, _, _ = bgk.prof_read(bgk.PROF_THREE_STEP)
+    finally:
+        bgk.prof_enable(False)
+    bgk.check_status()
+    assert launches == 1
+    assert rel_f(got, oracle.fine_steps(p, f0, dt, 4)) < TOL
