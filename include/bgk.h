@@ -364,6 +364,13 @@ int bgk_set_step_fusion(int32_t steps_per_pass);
  * (default).  Kernel timing (bgk_prof_enable) always launches directly. */
 int bgk_set_graphs(int32_t on);
 
+/* Destroys every cached graph, after synchronising the device (none cached:
+ * returns at once, no device call).  The cache is per process, keyed by the
+ * workspace, the problem and the launch parameters, so later calls capture
+ * again; call it before freeing workspaces to give the graphs' resources
+ * back.  [host] */
+int bgk_release_graphs(void);
+
 /* Kernel timing of the step kernels: when on, every launch of one is
  * bracketed by HIP events on its stream and tagged with its kind:
  *   BGK_PROF_TWO_STEP       two IMEX steps per pass, reading and writing f

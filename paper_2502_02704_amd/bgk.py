@@ -29,7 +29,7 @@ EXPORTS = [
     "bgk_serial_fine", "bgk_fine_adjoint", "bgk_lift_adjoint_rho",
     "bgk_density_adjoint", "bgk_status", "bgk_status_string", "bgk_last_error",
     "bgk_set_tiles", "bgk_autotune", "bgk_prof_enable", "bgk_prof_read",
-    "bgk_set_graphs", "bgk_set_step_fusion", "bgk_n_steps_force", "bgk_fine_steps_force",
+    "bgk_set_graphs", "bgk_release_graphs", "bgk_set_step_fusion", "bgk_n_steps_force", "bgk_fine_steps_force",
     "bgk_fine_step_force", "bgk_fine_propagate_moments_force", "euler_coarse_step_force",
     "parareal_iterate_force", "bgk_serial_fine_force", "euler_coarse_step_cns",
     "parareal_iterate_cns", "bgk_lift_ce", "bgk_fine_propagate_moments_opts",
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH):
         "bgk_prof_enable": (C.c_int, [C.c_int32]),
         "bgk_set_graphs": (C.c_int, [C.c_int32]),
         "bgk_set_step_fusion": (C.c_int, [C.c_int32]),
+        "bgk_release_graphs": (C.c_int, []),
         "bgk_prof_read": (C.c_int, [C.c_int32, D, C.POINTER(C.c_int64), D, D]),
         "bgk_n_steps_force": (C.c_int, [P, C.c_double, C.c_double, I, D]),
         "bgk_fine_steps_force": (C.c_int, [P, V, C.c_double, V, V, C.c_double, C.c_int32,
@@ -529,6 +530,11 @@ def autotune(p, batch: int = 1) -> Tuple[int, int, int]:
     _check(L.bgk_autotune(C.byref(problem_struct(p)), batch, w.data_ptr(), w.numel(),
                           _stream(), C.byref(e), C.byref(c), C.byref(pr)), "bgk_autotune")
     return e.value, c.value, pr.value
+
+
+def release_graphs():
+    """Destroy every cached HIP graph (synchronises the device)."""
+    _check(load_library().bgk_release_graphs(), "bgk_release_graphs")
 
 
 def set_graphs(on: bool = True):

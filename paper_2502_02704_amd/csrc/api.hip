@@ -1290,6 +1290,15 @@ int bgk_set_graphs(int32_t on) {
   return BGK_OK;
 }
 
+int bgk_release_graphs(void) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  if (g_graphs.empty()) return BGK_OK;
+  BGK_HIP(hipDeviceSynchronize());
+  for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+  g_graphs.clear();
+  return BGK_OK;
+}
+
 int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
                      int32_t ckpt_every, int32_t n_steps, double dt,
                      const double* fbar_T, double* fbar_0, double* dlog_eps,

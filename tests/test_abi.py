@@ -54,6 +54,8 @@ def test_host_only_calls():
     assert lib.bgk_set_tiles(4, 8, 3) == bgk.OK
     assert lib.bgk_set_tiles(4, 8, 2) == bgk.OK
     assert lib.bgk_set_tiles(0, 0, -1) == bgk.OK
+    # nothing cached in a process that made no GPU call: no device call
+    assert lib.bgk_release_graphs() == bgk.OK
     # steps per pass: 1, 2 or 3 (the default)
     for bad in (0, 4, -1):
         assert lib.bgk_set_step_fusion(bad) == bgk.E_INVALID

@@ -445,6 +445,10 @@ def test_graph_replays_match_eager_launches():
     for rep in range(2):
         V, err, kd = bgk.parareal_iterate(p, W0, wk.n_slices, wk.T, 8, 1e-3)
         assert kd == kdt and err == errt and np.array_equal(V.cpu().numpy(), Vt)
+    # released graphs are captured again on the next call
+    bgk.release_graphs()
+    V, err, kd = bgk.parareal_iterate(p, W0, wk.n_slices, wk.T, 3, 0.0)
+    assert np.array_equal(V.cpu().numpy(), Ve) and err == erre
 
 
 def test_adjoint_workload_full_size_gradients():
