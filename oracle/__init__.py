@@ -259,7 +259,9 @@ def lift_ce(p, W) -> np.ndarray:
     return f
 
 
-COARSE = {"euler": 0, "cns": 1}
+# coarse models of the parareal iteration; "fine" (the fine propagator as G)
+# exists to pin the correction: with G = F one iteration gives the serial chain
+COARSE = {"euler": 0, "cns": 1, "fine": 2}
 
 
 def transport_opts(p, f, dt: float, E=None, fine_order: int = 1) -> np.ndarray:

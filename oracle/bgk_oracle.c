@@ -719,6 +719,15 @@ static void primitive_to_conserved(const double* W5, double* V5) {
  *     U^{n,k+1} = G(U^{n-1,k+1}) + Delta^n             for n = k+1..N (in order)
  *     err_k = max_{n,i,c} |U^{n,k+1} - U^{n,k}|;  stop at K or err < tol.
  * The jump loop is the parallel one (Section 2.2 and Section 4). */
+/* The coarse model G of the parareal iteration: 0 the Euler system, 1 the
+ * Navier-Stokes system, 2 the fine propagator itself (a check of the
+ * correction: with G = F the first iteration reproduces the serial chain). */
+static int coarse_of(const bgk_oracle_problem* p, const double* E, int coarse, int order,
+                     int lift_order, const double* in, double* out, double dT) {
+  if (coarse == 2) return propagate_impl(p, E, order, lift_order, in, out, dT);
+  return coarse_impl(p, E, coarse, in, out, dT, NULL);
+}
+
 static int parareal_impl(const bgk_oracle_problem* p, const double* E, int viscous,
                          int lift_order, int order, const double* W0, int32_t n_slices, double T,
                          int32_t k_max, double tol, double* V_out,
@@ -739,7 +748,7 @@ static int parareal_impl(const bgk_oracle_problem* p, const double* E, int visco
   for (int i = 0; i < nx; ++i) primitive_to_conserved(W0 + 5 * i, U + 5 * i);
   int rc = ORACLE_OK;
   for (int n = 1; n <= n_slices && rc == ORACLE_OK; ++n)
-    rc = coarse_impl(p, E, viscous, U + sl * (n - 1), U + sl * n, dT, NULL);
+    rc = coarse_of(p, E, viscous, order, lift_order, U + sl * (n - 1), U + sl * n, dT);
   int32_t kd = 0;
   for (int k = 0; k < k_max && rc == ORACLE_OK; ++k) {
     /* jumps, independent over n */
@@ -748,7 +757,7 @@ static int parareal_impl(const bgk_oracle_problem* p, const double* E, int visco
       double* Fv = (double*)malloc(sl * sizeof(double));
       double* Gv = (double*)malloc(sl * sizeof(double));
       int r1 = propagate_impl(p, E, order, lift_order, U + sl * (n - 1), Fv, dT);
-      int r2 = r1 ? r1 : coarse_impl(p, E, viscous, U + sl * (n - 1), Gv, dT, NULL);
+      int r2 = r1 ? r1 : coarse_of(p, E, viscous, order, lift_order, U + sl * (n - 1), Gv, dT);
       if (r1 || r2) bad = r1 ? r1 : r2;
       else
         for (size_t q = 0; q < sl; ++q) D[sl * n + q] = Fv[q] - Gv[q];
@@ -763,7 +772,7 @@ static int parareal_impl(const bgk_oracle_problem* p, const double* E, int visco
     /* frozen prefix, then the sequential correction */
     memcpy(Un, U, sl * (k + 1) * sizeof(double));
     for (int n = k + 1; n <= n_slices && rc == ORACLE_OK; ++n) {
-      rc = coarse_impl(p, E, viscous, Un + sl * (n - 1), Un + sl * n, dT, NULL);
+      rc = coarse_of(p, E, viscous, order, lift_order, Un + sl * (n - 1), Un + sl * n, dT);
       if (rc == ORACLE_OK)
         for (size_t q = 0; q < sl; ++q) Un[sl * n + q] += D[sl * n + q];
     }
@@ -1037,7 +1046,7 @@ int bgk_oracle_parareal_iterate_opts(const bgk_oracle_problem* p, const double* 
                                      int32_t n_slices, double T, int32_t k_max,
                                      double tol, double* V_out, double* err_hist,
                                      int32_t* k_done) {
-  if ((coarse != 0 && coarse != 1) || check_opts(lift_order, fine_order))
+  if (coarse < 0 || coarse > 2 || check_opts(lift_order, fine_order))
     return ORACLE_E_INVALID;
   return parareal_impl(p, E, coarse, lift_order, fine_order, W0, n_slices, T, k_max, tol,
                        V_out, err_hist, k_done);

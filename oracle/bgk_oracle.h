@@ -168,7 +168,9 @@ int bgk_oracle_parareal_iterate_cns(const bgk_oracle_problem* p, const double* E
 int bgk_oracle_lift_ce(const bgk_oracle_problem* p, const double* W, double* f);
 
 /* General forms: E (host [nx]) may be NULL; coarse 0 = Euler, 1 =
- * Navier-Stokes; lift_order 0 = Maxwellian (Definition 2), 1 = the lifting
+ * Navier-Stokes, 2 = the fine propagator itself as G (a check of the
+ * correction: with G = F one iteration reproduces the serial fine chain);
+ * lift_order 0 = Maxwellian (Definition 2), 1 = the lifting
  * above; fine_order 1 = the upwind transport of Section 3.1, 2 = with the
  * van Leer limited Lax-Wendroff correction (second order where smooth, TVD).
  * The serial fine chain with the same lifting and order is parareal's fixed

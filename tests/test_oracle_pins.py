@@ -437,6 +437,23 @@ class TestParareal:
         V, err, kd = oracle.parareal_iterate(p, W0, 6, 0.06, 6, 1e30)
         assert kd == 1
 
+    def test_exact_coarse_converges_in_one_iteration(self):
+        """With the fine propagator itself as G, the initial coarse sweep is
+        the serial chained fine solve, and the correction G(U^{n-1,k+1}) +
+        F(U^{n-1,k}) - G(U^{n-1,k}) reduces to F(U^{n-1,k+1}): every iteration
+        leaves it unchanged up to the rounding of a + b - b (a dropped or
+        doubled term, or a wrong sign, in the correction fails this)."""
+        p, W0 = self._case()
+        N, T = 4, 0.04
+        S = oracle.serial_fine(p, W0, N, T)
+        V1, err1, k1 = oracle.parareal_iterate_opts(p, W0, N, T, 1, 0.0, coarse="fine")
+        V2, err2, k2 = oracle.parareal_iterate_opts(p, W0, N, T, 2, 0.0, coarse="fine")
+        assert k1 == 1 and k2 == 2
+        scale = np.abs(S).max()
+        assert np.abs(V1 - S).max() < 1e-13 * scale
+        assert np.abs(V2 - S).max() < 1e-13 * scale
+        assert max(err1[0], err2[0], err2[1]) < 1e-13 * scale
+
     def test_coarse_initial_guess(self):
         p, W0 = self._case()
         V, err, kd = oracle.parareal_iterate(p, W0, 3, 0.03, 0, 0.0)
