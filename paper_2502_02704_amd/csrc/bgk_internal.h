@@ -37,7 +37,7 @@ struct Inst {
   int part_tiles;              // partial-sum capacity of `part` per x cell
   int nparts;                  // partial sums per x cell the step writes
   int nsum;                    // values per partial: 5 moments, or 15 with the
-                               // nu+ and nu- weighted moments (two-step passes)
+                               // nu+ and nu- weighted moments (fused passes)
   int crec;                    // nonzero: compact records, 4 values per tile of
                                // crec velocities inside one v_x plane (the nu
                                // weights follow from the tile's v_x)

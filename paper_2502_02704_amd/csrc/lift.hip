@@ -9,8 +9,8 @@
 // heat flux are the Navier-Stokes ones with mu = rho theta and kappa =
 // 5/2 rho theta.  One block per (member, x cell, slab of 4 * kBlock
 // velocities): the block forms the cell's separable Maxwellian factors in LDS
-// (3 Nv exponentials) and writes its slab of f, which the one- or two-step
-// passes then read as their copy-mode source.
+// (3 Nv exponentials) and writes its slab of f, which the first step then
+// reads as its copy-mode source.
 #include "bgk_internal.h"
 
 namespace bgk {
