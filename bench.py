@@ -323,6 +323,12 @@ def main():
                     "launches": a_launches, "avg_launch_us": round(a_ms * 1e3 / max(a_launches, 1), 2),
                     "achieved": round(a_bytes / (a_ms * 1e-3) / 1e9, 1),
                     "alg_bytes_per_update": round(a_bytes / max(a_upd, 1.0), 3)}}
+    if which == "three":
+        # the pass's own updates/s against the HBM ceiling of a two-steps-per-pass
+        # design (8 B per update): what moving a third fewer bytes buys
+        pass_ups = k_upd / (k_ms * 1e-3)
+        roofline["pass_updates_per_s"] = pass_ups
+        roofline["frac_of_8B_per_update_ceiling"] = round(pass_ups / (HBM_PEAK_GBS * 1e9 / 8.0), 4)
     if two is not None:
         roofline["two_step_pass"] = two
     line = {"metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
