@@ -1548,7 +1548,8 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_byt
     }
   double* Vin = at<double>(ws, L.fine.vg);   // borrow: lifted from before steps
   double* Vout = at<double>(ws, L.fine.vout);
-  const int steps = 4;
+  // six steps: whole passes both with two and with three steps per pass
+  const int steps = 6;
   const double dt = 0.5 * dx_of(*prob) / std::max(std::fabs(prob->v_lo[0]), std::fabs(prob->v_hi[0]));
   hipEvent_t e0, e1;
   BGK_HIP(hipEventCreate(&e0));

@@ -207,3 +207,20 @@ def test_sod_large_full_size_three_step_pass():
     bgk.check_status()
     assert launches == 1
     assert rel_f(got, oracle.fine_steps(p, f0, dt, 4)) < TOL
+
+
+def test_autotune_picks_a_valid_shape_and_keeps_parity():
+    """bgk_autotune times the candidate tile shapes (two and three steps per
+    pass among them) on a grid used by no other test, keeps the fastest for
+    that grid and batch, and later calls with it still match the oracle."""
+    p = wl.Problem(nx=24, nv=(8, 8, 16), v_lo=(-6,) * 3, v_hi=(6,) * 3, bc=wl.BC_PERIODIC,
+                   eps=2e-2)
+    B = 3
+    e, c, pr = bgk.autotune(p, B)
+    assert e in (2, 4, 8) and 1 <= c <= 32 and pr in (0, 1)
+    Vin = np.stack([conserved(states(p, 360 + b)[0]) for b in range(B)])
+    span = 0.004
+    got = bgk.fine_propagate_moments(p, cuda(Vin), span).cpu().numpy()
+    bgk.check_status()
+    for b in range(B):
+        assert rel_V(got[b], oracle.fine_propagate_moments(p, Vin[b], span)) < TOL
