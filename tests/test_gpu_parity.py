@@ -521,3 +521,30 @@ def test_uneven_batch_full_set_sampled():
         ref, nr = oracle.fine_step(w.problem, oracle.lift(w.problem, w.W0), spans[q])
         assert steps[q] == nr
         assert rel_f(outs[q].cpu().numpy(), ref) < TOL
+
+
+def test_uneven_batch_graph_replays_match_eager():
+    """The uneven batch is captured as one HIP graph per (workspace, problems,
+    buffers, spans); replays, with eager work between them, equal the eager
+    launch sequence bit for bit."""
+    insts = [w for q, w in enumerate(wl.c5_uneven()) if q in (1, 2, 4, 5, 6)]
+    probs = [w.problem for w in insts]
+    spans = [0.002, 0.001, 0.0015, 0.002, 0.001]
+    fs = [bgk.lift(w.problem, cuda(w.W0)) for w in insts]
+    bgk.check_status()
+    bgk.set_graphs(False)
+    try:
+        eager, steps_e = bgk.fine_step_batched(probs, fs, spans)
+        eager = [o.cpu().numpy() for o in eager]
+    finally:
+        bgk.set_graphs(True)
+    outs = [torch.empty_like(f) for f in fs]
+    _, f = states(GRIDS["wide_periodic"], 51)
+    for rep in range(3):
+        _, steps = bgk.fine_step_batched(probs, fs, spans, outs)
+        assert steps == steps_e
+        for o, e in zip(outs, eager):
+            assert np.array_equal(o.cpu().numpy(), e)
+        bgk.fine_steps(GRIDS["wide_periodic"], cuda(f), 1e-3, 2)  # eager work between
+        torch.cuda.synchronize()
+    bgk.check_status()
