@@ -11,7 +11,7 @@ and the parareal vs serial-fine speedup on small workloads where one slice's
 step is latency bound.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--eps E]
-       [--no-cpu-baseline] [--no-parareal] [--extras parareal,force,order2,uneven]
+       [--no-cpu-baseline] [--no-parareal] [--extras parareal,force,order2,uneven,adjoint]
        [--copy-calibration]
 """
 import argparse
@@ -225,6 +225,45 @@ def uneven_throughput(torch, bgk, wl, span=0.01, reps=3):
             "step_kernel_avg_us": round(ms * 1e3 / max(launches, 1), 2)}
 
 
+def adjoint_timing(torch, bgk, wl, reps=3):
+    """Gradients of the final-time density misfit with respect to the initial
+    density and log eps through the fine solve (Nx=256, 24^3 velocities,
+    393 steps, checkpoints every 16 steps): forward and backward wall-clock,
+    median of `reps` after a warm-up."""
+    import numpy as np
+    wk, rho0, eps_t, _ = wl.c4_adjoint()
+    p = wk.problem
+    n, _ = bgk.n_steps(p, wk.T)
+    r0 = torch.tensor(rho0, dtype=torch.float64, device="cuda", requires_grad=True)
+    le = torch.tensor(np.log(p.eps), dtype=torch.float64, device="cuda", requires_grad=True)
+    with torch.no_grad():
+        target = bgk.kinetic_density(r0.detach(), torch.tensor(np.log(eps_t), dtype=torch.float64,
+                                                               device="cuda"), p, T=wk.T)
+
+    def once():
+        r0.grad, le.grad = None, None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rho = bgk.kinetic_density(r0, le, p, T=wk.T, ckpt_every=16)
+        loss = 0.5 * (1.0 / p.nx) * torch.sum((rho - target) ** 2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        return t1 - t0, time.perf_counter() - t1
+
+    once()
+    ts = [once() for _ in range(reps)]
+    bgk.check_status()
+    fw = float(np.median([t[0] for t in ts]))
+    bw = float(np.median([t[1] for t in ts]))
+    n_ck = (n + 15) // 16
+    return {"workload": f"adjoint_nx{p.nx}_nv{p.nv[0]}", "steps": n, "checkpoint_every": 16,
+            "checkpoint_bytes": n_ck * p.cells * 8, "forward_ms": round(fw * 1e3, 2),
+            "backward_ms": round(bw * 1e3, 2), "backward_over_forward": round(bw / fw, 2),
+            "forward_updates_per_s": p.cells * n / fw}
+
+
 def second_order_throughput(torch, bgk, V, p, span, reps=2):
     """The second-order (van Leer limited) fine transport on the benchmark
     batch: one step per pass (16 algorithmic bytes per update)."""
@@ -256,8 +295,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parareal", action="store_true",
                     help="skip every section after the main line (same as --extras '')")
-    ap.add_argument("--extras", default="parareal,force,order2,uneven",
-                    help="comma list of the extra sections: parareal, force, order2, uneven")
+    ap.add_argument("--extras", default="parareal,force,order2,uneven,adjoint",
+                    help="comma list of the extra sections: parareal, force, order2, uneven, "
+                         "adjoint")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -380,6 +420,8 @@ def main():
         line["second_order_fine"] = second_order_throughput(torch, bgk, V, p, span)
     if "uneven" in extras:
         line["uneven_batch"] = uneven_throughput(torch, bgk, wl)
+    if "adjoint" in extras:
+        line["adjoint"] = adjoint_timing(torch, bgk, wl)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wk, V_np, span)
     print(json.dumps(line), flush=True)

@@ -1339,41 +1339,52 @@ int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
   double* coef = at<double>(ws, L.coef);
   double* dle = at<double>(ws, L.dle);
   Inst* dI = at<Inst>(ws, L.insts);
-  BGK_HIP(hipMemcpyAsync(fb[0], fbar_T, fbytes, hipMemcpyDeviceToDevice, s));
-  int cur = 0;
   const int n_seg = (n_steps + ckpt_every - 1) / ckpt_every;
-  for (int c = n_seg - 1; c >= 0; --c) {
-    const int s0 = c * ckpt_every;
-    const int s1 = std::min(s0 + ckpt_every, (int)n_steps);
-    BGK_HIP(hipMemcpyAsync(states, f_ckpt + (size_t)c * nf, fbytes,
-                           hipMemcpyDeviceToDevice, s));
-    // forward states s0+1 .. s1-1 of the segment (transport, moments, relax)
-    for (int k = s0 + 1; k < s1; ++k) {
-      Inst I = base;
-      I.fin = states + (size_t)(k - 1 - s0) * nf;
-      I.fout = states + (size_t)(k - s0) * nf;
-      if ((rc = put_insts(dI, &I, 1, s))) return rc;
-      if ((rc = launch_step(dI, 1, I.items, kCopy, 1, t, lds_doubles(I, t), st, s))) return rc;
-      if ((rc = launch_reduce(dI, 1, prob->nx, kRedRelaxFactors, 0, st, s))) return rc;
-      if ((rc = launch_relax_out_blocks(dI, 1, relax_out_blocks(I), I.nvs, 0, s))) return rc;
+  auto sequence = [&](hipStream_t q) -> int {
+    int r;
+    BGK_HIP(hipMemcpyAsync(fb[0], fbar_T, fbytes, hipMemcpyDeviceToDevice, q));
+    int cur = 0;
+    for (int c = n_seg - 1; c >= 0; --c) {
+      const int s0 = c * ckpt_every;
+      const int s1 = std::min(s0 + ckpt_every, (int)n_steps);
+      BGK_HIP(hipMemcpyAsync(states, f_ckpt + (size_t)c * nf, fbytes,
+                             hipMemcpyDeviceToDevice, q));
+      // forward states s0+1 .. s1-1 of the segment (transport, moments, relax)
+      for (int k = s0 + 1; k < s1; ++k) {
+        Inst I = base;
+        I.fin = states + (size_t)(k - 1 - s0) * nf;
+        I.fout = states + (size_t)(k - s0) * nf;
+        if ((r = put_insts(dI, &I, 1, q))) return r;
+        if ((r = launch_step(dI, 1, I.items, kCopy, 1, t, lds_doubles(I, t), st, q))) return r;
+        if ((r = launch_reduce(dI, 1, prob->nx, kRedRelaxFactors, 0, st, q))) return r;
+        if ((r = launch_relax_out_blocks(dI, 1, relax_out_blocks(I), I.nvs, 0, q))) return r;
+      }
+      for (int k = s1 - 1; k >= s0; --k) {
+        Inst I = base;
+        I.fin = states + (size_t)(k - s0) * nf;
+        if ((r = put_insts(dI, &I, 1, q))) return r;
+        // g = T f^k into buf[0], moments and the unscaled Maxwellian of U(g)
+        if ((r = launch_step(dI, 1, I.items, kCopy, 1, t, lds_doubles(I, t), st, q))) return r;
+        if ((r = launch_reduce(dI, 1, prob->nx, kRedMaxwellFactors, 0, st, q))) return r;
+        if ((r = launch_adjoint_sums(dI, I, 0, fb[cur], part6, q))) return r;
+        if ((r = launch_adjoint_reduce(dI, I, part6, coef, dle, q))) return r;
+        if ((r = launch_sum_into(dle, prob->nx, dlog_eps, q))) return r;
+        if ((r = launch_adjoint_transpose(dI, I, t.chunk, fb[cur], coef, fb[cur ^ 1], q)))
+          return r;
+        cur ^= 1;
+      }
     }
-    for (int k = s1 - 1; k >= s0; --k) {
-      Inst I = base;
-      I.fin = states + (size_t)(k - s0) * nf;
-      if ((rc = put_insts(dI, &I, 1, s))) return rc;
-      // g = T f^k into buf[0], moments and the unscaled Maxwellian of U(g)
-      if ((rc = launch_step(dI, 1, I.items, kCopy, 1, t, lds_doubles(I, t), st, s))) return rc;
-      if ((rc = launch_reduce(dI, 1, prob->nx, kRedMaxwellFactors, 0, st, s))) return rc;
-      if ((rc = launch_adjoint_sums(dI, I, 0, fb[cur], part6, s))) return rc;
-      if ((rc = launch_adjoint_reduce(dI, I, part6, coef, dle, s))) return rc;
-      if ((rc = launch_sum_into(dle, prob->nx, dlog_eps, s))) return rc;
-      if ((rc = launch_adjoint_transpose(dI, I, t.chunk, fb[cur], coef, fb[cur ^ 1], s)))
-        return rc;
-      cur ^= 1;
-    }
-  }
-  BGK_HIP(hipMemcpyAsync(fbar_0, fb[cur], fbytes, hipMemcpyDeviceToDevice, s));
-  return BGK_OK;
+    BGK_HIP(hipMemcpyAsync(fbar_0, fb[cur], fbytes, hipMemcpyDeviceToDevice, q));
+    return BGK_OK;
+  };
+  // the whole sequence (about 11 launches per step) is captured once per
+  // (workspace, problem, buffers, steps) and replayed
+  return run_graph(graph_key("adj", ws, ws_bytes, *prob,
+                             {(double)(uintptr_t)f_ckpt, (double)ckpt_every, (double)n_steps,
+                              dt, (double)(uintptr_t)fbar_T, (double)(uintptr_t)fbar_0,
+                              (double)(uintptr_t)dlog_eps, (double)t.elems, (double)t.chunk,
+                              (double)(t.pair + 2 * t.vcol)}),
+                   s, sequence);
 }
 
 int bgk_lift_adjoint_rho(const bgk_problem* prob, const double* W,

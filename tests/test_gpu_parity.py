@@ -548,3 +548,31 @@ def test_uneven_batch_graph_replays_match_eager():
         bgk.fine_steps(GRIDS["wide_periodic"], cuda(f), 1e-3, 2)  # eager work between
         torch.cuda.synchronize()
     bgk.check_status()
+
+
+def test_adjoint_graph_replays_match_eager():
+    """The adjoint sequence is captured as one HIP graph per (workspace,
+    problem, buffers, steps); replays into the same buffers, with eager work
+    between them, equal the eager launches bit for bit, and the log-eps
+    gradient accumulates into the caller's scalar as in the eager run."""
+    p, f0 = _adj_case(wl.BC_PERIODIC)
+    dt, n, every = 2e-3, 7, 3
+    ck, _ = oracle.checkpoints(p, f0, dt, n, every)
+    w = np.random.default_rng(34).standard_normal(f0.shape)
+    ckd, wd = cuda(ck), cuda(w)
+    bgk.set_graphs(False)
+    try:
+        fb_e, dle_e = bgk.fine_adjoint(p, ckd, every, n, dt, wd)
+        fb_e, dle_e = fb_e.cpu().numpy(), float(dle_e.cpu())
+    finally:
+        bgk.set_graphs(True)
+    dle = torch.zeros(1, dtype=torch.float64, device="cuda")
+    _, f = states(GRIDS["wide_periodic"], 52)
+    for rep in range(3):
+        dle.zero_()
+        fb, _ = bgk.fine_adjoint(p, ckd, every, n, dt, wd, dle)
+        assert np.array_equal(fb.cpu().numpy(), fb_e)
+        assert float(dle.cpu()) == dle_e
+        bgk.fine_steps(GRIDS["wide_periodic"], cuda(f), 1e-3, 2)  # eager work between
+        torch.cuda.synchronize()
+    bgk.check_status()
