@@ -97,6 +97,36 @@ enum ReduceMode : int {
 constexpr int kAux = 50;
 constexpr int kAux2 = 30;
 
+// ------------------------------------------------ global-memory pointers --
+// The arrays an Inst points to live in device global memory, but a pointer
+// loaded from a struct is generic to the compiler, and an access through it
+// is a FLAT instruction.  FLAT accesses count against the LDS counter as well
+// as the vector-memory one, so every wait for an LDS read would also wait for
+// the HBM loads and stores still in flight.  Device code converts such a
+// pointer once with gmem() and addresses through gptr<> from then on, which
+// gives global_load / global_store.
+#define BGK_GLOBAL __attribute__((address_space(1)))
+template <class T>
+using gptr = BGK_GLOBAL T*;
+template <class T>
+__device__ __forceinline__ gptr<T> gmem(T* p) {
+  return (gptr<T>)p;
+}
+// 16-byte load and store of two doubles (p 16-byte aligned), through the
+// compiler's native vector type: double2's members cannot bind to an object
+// in the global address space.
+typedef double bgk_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld2(gptr<const double> p) {
+  const bgk_d2 t = *reinterpret_cast<gptr<const bgk_d2>>(p);
+  return make_double2(t.x, t.y);
+}
+__device__ __forceinline__ void st2(gptr<double> p, double x, double y) {
+  bgk_d2 t;
+  t.x = x;
+  t.y = y;
+  *reinterpret_cast<gptr<bgk_d2>>(p) = t;
+}
+
 // ---------------------------------------------------------------- errors --
 void set_error(const std::string& msg);
 int hip_fail(hipError_t e, const char* what);

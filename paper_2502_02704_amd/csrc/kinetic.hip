@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
   if (MODE != kCopy) {
     // factor rows of cells i0-H .. i1+H-1 (ghosts mapped by the BC)
     const int rows = i1 - i0 + 2 * H;
-    const double* fac = I.fac + (long long)b * nx * nvs;
+    gptr<const double> fac = gmem(I.fac) + (long long)b * nx * nvs;
     for (int idx = threadIdx.x; idx < rows * nvs; idx += kBlock) {
       int rr = idx / nvs;
       int k = idx - rr * nvs;
@@ -403,8 +403,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
   Elems<E> el;
   setup_elems<E>(I, tile, lane, el);
   const long long mbase = (long long)b * nx * nv3;
-  const double* src = (MODE == kCopy) ? I.fin : I.buf[phase];
-  double* dst = I.buf[phase ^ 1];
+  gptr<const double> src = gmem((MODE == kCopy) ? I.fin : I.buf[phase]);
+  gptr<double> dst = gmem(I.buf[phase ^ 1]);
   src += mbase + tile * (kWave * E) + lane;
   dst += mbase + tile * (kWave * E) + lane;
   const double a = I.a;
@@ -473,13 +473,13 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
     for (int e = 0; e < E; ++e)
       fcar[e] = flux2(el.vx[e], fabs(nu[e]), w[0][e], w[1][e], w[2][e], w[3 < 2 * H ? 3 : 0][e]);
   }
-  double* part = I.part + (((long long)b * nx) * I.part_tiles + tile) * 5;
+  gptr<double> part = gmem(I.part) + (((long long)b * nx) * I.part_tiles + tile) * 5;
   for (int i = i0; i < i1; ++i) {
     if (i + 2 <= i1) load_row(i + H + 1, rawn);  // prefetch the next row
     if (FORCE && i + 1 < i1) load_vnb(i + 1, dn_nxt, up_nxt);
     relax_row(i + H, rawp, w[2 * H]);
     double Ei = 0.0;
-    if (FORCE) Ei = I.efield[i];
+    if (FORCE) Ei = gmem(I.efield)[i];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -588,14 +588,14 @@ struct Acc {
   // vxu, nuu: the tile's v_x and nu (used when UNI)
   __device__ __forceinline__ void store(const Inst& I, int b, int r, int tile, int lane,
                                         double vxu, double nuu) {
-    double* rec = I.part + ((long long)b * I.nx + r) * I.part_tiles * 5 + tile * NS;
+    gptr<double> rec = gmem(I.part) + ((long long)b * I.nx + r) * I.part_tiles * 5 + tile * NS;
     if (UNI) {
       double t4[4] = {s[0], s[1], s[2], s[3]};
       const double tot = wave_reduce_scatter<4>(t4, lane);
       if (I.crec) {
         // compact record: the four totals; the reduction rebuilds the v_x and
         // nu-weighted sums from the tile's v_x
-        double* crec = I.part + ((long long)b * I.nx + r) * I.part_tiles * 5 + tile * 4;
+        gptr<double> crec = gmem(I.part) + ((long long)b * I.nx + r) * I.part_tiles * 5 + tile * 4;
         if (lane < 4) crec[slot_of_lane<4>(lane)] = tot;
         return;
       }
@@ -642,10 +642,10 @@ struct Col {
 };
 
 template <int PY>
-__device__ __forceinline__ Col<PY> ld_col(const double* p) {
+__device__ __forceinline__ Col<PY> ld_col(gptr<const double> p) {
   Col<PY> c;
   if constexpr (PY == 2) {
-    const double2 t = *reinterpret_cast<const double2*>(p);
+    const double2 t = ld2(p);
     c.v[0] = t.x;
     c.v[1] = t.y;
   } else {
@@ -655,9 +655,9 @@ __device__ __forceinline__ Col<PY> ld_col(const double* p) {
 }
 
 template <int PY>
-__device__ __forceinline__ void st_col(double* p, const Col<PY>& c) {
+__device__ __forceinline__ void st_col(gptr<double> p, const Col<PY>& c) {
   if constexpr (PY == 2) {
-    *reinterpret_cast<double2*>(p) = make_double2(c.v[0], c.v[1]);
+    st2(p, c.v[0], c.v[1]);
   } else {
     *p = c.v[0];
   }
@@ -681,7 +681,7 @@ __global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ i
 
   if (MODE != kCopy) {
     const int rows = i1 - i0 + 2 * H;
-    const double* fac = I.fac + (long long)b * nx * nvs;
+    gptr<const double> fac = gmem(I.fac) + (long long)b * nx * nvs;
     for (int idx = threadIdx.x; idx < rows * nvs; idx += kBlock) {
       int rr = idx / nvs;
       int k = idx - rr * nvs;
@@ -727,8 +727,8 @@ __global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ i
     nu[e] = uniform_d(vx[e] * I.r);
   }
   const long long mbase = (long long)b * nx * nv3 + (long long)x0 * nyz + yz;
-  const double* src = ((MODE == kCopy) ? I.fin : I.buf[phase]) + mbase;
-  double* dst = I.buf[phase ^ 1] + mbase;
+  gptr<const double> src = gmem((MODE == kCopy) ? I.fin : I.buf[phase]) + mbase;
+  gptr<double> dst = gmem(I.buf[phase ^ 1]) + mbase;
   const double a = I.a;
 
   auto relax1 = [&](double raw, double fe) -> double {
@@ -802,7 +802,7 @@ __global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ i
         fcar[e][p] = flux2(vx[e], fabs(nu[e]), w[0][e].v[p], w[1][e].v[p], w[2][e].v[p],
                            w[3 < 2 * H ? 3 : 0][e].v[p]);
   }
-  double* part = I.part + ((long long)b * nx * I.part_tiles + tile) * 5;
+  gptr<double> part = gmem(I.part) + ((long long)b * nx * I.part_tiles + tile) * 5;
   for (int i = i0; i < i1; ++i) {
     relax_row(i + H, rawp, w[2 * H]);
     if (i + 2 <= i1) load_row(i + H + 1, rawp);  // prefetch the next row
@@ -819,7 +819,7 @@ __global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ i
                      : 0.0;
     }
     if (i + 1 < i1) load_halo(i + 1, dn_raw, up_raw);
-    const double he = 0.5 * I.efield[i];
+    const double he = 0.5 * gmem(I.efield)[i];
     // v_x face fluxes (face k lies below element k), carried along the
     // column: each face's flux is computed once
     auto face = [&](double lo, double hi) { return he * (lo + hi) - hm * (hi - lo); };
@@ -879,12 +879,12 @@ __global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ i
   }
 }
 
-__device__ __forceinline__ void store_pair(double* drow, int jofs, double2 g) {
+__device__ __forceinline__ void store_pair(gptr<double> drow, int jofs, double2 g) {
 #if BGK_NT_STORE
   __builtin_nontemporal_store(g.x, drow + jofs);
   __builtin_nontemporal_store(g.y, drow + jofs + 1);
 #else
-  *reinterpret_cast<double2*>(drow + jofs) = g;
+  st2(drow + jofs, g.x, g.y);
 #endif
 }
 
@@ -956,18 +956,18 @@ __device__ __forceinline__ void step2_march(const Inst& I, const double* lds,
   setup_pairs<P, FULL>(I, tile, lane, e);
   const double dvz = I.dv[2];
   const long long mbase = (long long)b * nx * nv3;
-  const double* src = ((MODE == kCopy) ? I.fin : I.buf[phase]) + mbase;
-  double* dst = I.buf[phase ^ 1] + mbase;
+  gptr<const double> src = gmem((MODE == kCopy) ? I.fin : I.buf[phase]) + mbase;
+  gptr<double> dst = gmem(I.buf[phase ^ 1]) + mbase;
   const double a = I.a;
   const int len = i1 - i0;
   // global row of march position k (k = -1 and k = len are the halo rows)
   auto row_at = [&](int k) { return DIR > 0 ? i0 + k : i1 - 1 - k; };
   auto load_row = [&](int r, double2 (&raw)[P]) {
     if (MODE == kLift) return;
-    const double* row = src + (long long)ghost_row(r, nx, I.bc) * nv3;
+    gptr<const double> row = src + (long long)ghost_row(r, nx, I.bc) * nv3;
 #pragma unroll
     for (int p = 0; p < P; ++p)
-      raw[p] = e.ok[p] ? *reinterpret_cast<const double2*>(row + e.jofs[p])
+      raw[p] = e.ok[p] ? ld2(row + e.jofs[p])
                        : make_double2(0.0, 0.0);
   };
   auto relax_row = [&](int r, const double2 (&raw)[P], double2 (&out)[P]) {
@@ -1001,7 +1001,7 @@ __device__ __forceinline__ void step2_march(const Inst& I, const double* lds,
     const int r = row_at(k);
     Acc<NS, UNI> acc;
     acc.zero();
-    double* drow = dst + (long long)r * nv3;
+    gptr<double> drow = dst + (long long)r * nv3;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const double nu = UNI ? nuu : e.nu(p);
@@ -1022,7 +1022,7 @@ __device__ __forceinline__ void step2_march(const Inst& I, const double* lds,
 __device__ __forceinline__ void stage_rows(const Inst& I, const double* fac, int b,
                                            int first_row, int rows, double* lds) {
   const int nx = I.nx, nvs = I.nvs;
-  const double* f = fac + (long long)b * nx * nvs;
+  gptr<const double> f = gmem(fac) + (long long)b * nx * nvs;
   for (int idx = threadIdx.x; idx < rows * nvs; idx += kBlock) {
     int rr = idx / nvs;
     int k = idx - rr * nvs;
@@ -1123,8 +1123,8 @@ __device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
   setup_pairs<P, FULL>(I, tile, lane, e);
   const double dvz = I.dv[2];
   const long long mbase = (long long)b * nx * nv3;
-  const double* src = I.buf[phase] + mbase;
-  double* dst = I.buf[phase ^ 1] + mbase;
+  gptr<const double> src = gmem(I.buf[phase]) + mbase;
+  gptr<double> dst = gmem(I.buf[phase ^ 1]) + mbase;
   const double a = I.a;
   const bool neumann = I.bc == 0;
   const int len = i1 - i0;
@@ -1132,10 +1132,10 @@ __device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
   auto outside = [&](int r) { return r < 0 || r >= nx; };
   auto load_row = [&](int r, double2 (&raw)[P]) {
     if (MODE == kLift) return;
-    const double* row = src + (long long)ghost_row(r, nx, I.bc) * nv3;
+    gptr<const double> row = src + (long long)ghost_row(r, nx, I.bc) * nv3;
 #pragma unroll
     for (int p = 0; p < P; ++p)
-      raw[p] = e.ok[p] ? *reinterpret_cast<const double2*>(row + e.jofs[p])
+      raw[p] = e.ok[p] ? ld2(row + e.jofs[p])
                        : make_double2(0.0, 0.0);
   };
   // level 1: rows i0-2 .. i1+1 staged in lds1; level 2: rows i0-1 .. i1 in lds2
@@ -1193,7 +1193,7 @@ __device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
     const int r = row_at(k);
     Acc<15, UNI> acc;
     acc.zero();
-    double* drow = dst + (long long)r * nv3;
+    gptr<double> drow = dst + (long long)r * nv3;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const double nu = UNI ? nuu : e.nu(p);
@@ -1287,8 +1287,8 @@ __device__ __forceinline__ void step3x_march(const Inst& I, const double* lds1,
   setup_pairs<P, true>(I, tile, lane, e);
   const double dvz = I.dv[2];
   const long long mbase = (long long)b * nx * nv3;
-  const double* src = I.buf[phase] + mbase;
-  double* dst = I.buf[phase ^ 1] + mbase;
+  gptr<const double> src = gmem(I.buf[phase]) + mbase;
+  gptr<double> dst = gmem(I.buf[phase ^ 1]) + mbase;
   const double a = I.a;
   const bool neumann = I.bc == 0;
   const int len = i1 - i0;
@@ -1299,9 +1299,9 @@ __device__ __forceinline__ void step3x_march(const Inst& I, const double* lds1,
   };
   auto load_row = [&](int k, double2 (&raw)[P]) {
     if (MODE == kLift) return;
-    const double* row = src + (long long)ghost_row(row_at(k), nx, I.bc) * nv3;
+    gptr<const double> row = src + (long long)ghost_row(row_at(k), nx, I.bc) * nv3;
 #pragma unroll
-    for (int p = 0; p < P; ++p) raw[p] = *reinterpret_cast<const double2*>(row + e.jofs[p]);
+    for (int p = 0; p < P; ++p) raw[p] = ld2(row + e.jofs[p]);
   };
   // level 1 at position k: rows i0-3 .. i1+2 staged in lds1
   auto level1 = [&](int k, const double2 (&raw)[P], double2 (&out)[P]) {
@@ -1377,7 +1377,7 @@ __device__ __forceinline__ void step3x_march(const Inst& I, const double* lds1,
     const int r = row_at(k);
     Acc<15, true> acc;
     acc.zero();
-    double* drow = dst + (long long)r * nv3;
+    gptr<double> drow = dst + (long long)r * nv3;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const double2 g = transport_pair<DIR, SGN>(nuu, l3b[p], l3c[p], l3a[p]);
@@ -1459,8 +1459,8 @@ __global__ __launch_bounds__(kBlock) void k_partials(
   const int i0 = c * chunk, i1 = min(i0 + chunk, nx);
   Elems<E> el;
   setup_elems<E>(I, tile, lane, el);
-  const double* src = I.fin + (long long)b * nx * nv3 + tile * (kWave * E) + lane;
-  double* part = I.part + (((long long)b * nx) * I.part_tiles + tile) * 5;
+  gptr<const double> src = gmem(I.fin) + (long long)b * nx * nv3 + tile * (kWave * E) + lane;
+  gptr<double> part = gmem(I.part) + (((long long)b * nx) * I.part_tiles + tile) * 5;
   for (int i = i0; i < i1; ++i) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
 #pragma unroll
@@ -1480,7 +1480,7 @@ __global__ __launch_bounds__(kBlock) void k_partials(
     s3 = wave_sum_to_last(s3);
     s4 = wave_sum_to_last(s4);
     if (lane == kWave - 1) {
-      double* pp = part + (long long)i * I.part_tiles * 5;
+      gptr<double> pp = part + (long long)i * I.part_tiles * 5;
       pp[0] = s0;
       pp[1] = s1;
       pp[2] = s2;
@@ -1612,11 +1612,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
     const int nx = I.nx;
     const long long b = cl / nx;
     const int i = (int)(cl - b * nx);
-    const double* base = mode == kRedW3x3 ? I.aux2 : I.aux;
+    gptr<const double> base = gmem(mode == kRedW3x3 ? I.aux2 : I.aux);
     const int stride = mode == kRedW3x3 ? kAux2 : kAux;
-    const double* ac = base + cl * stride;
-    const double* am = base + (b * nx + ghost_row(i - 1, nx, I.bc)) * stride;
-    const double* ap = base + (b * nx + ghost_row(i + 1, nx, I.bc)) * stride;
+    gptr<const double> ac = base + cl * stride;
+    gptr<const double> am = base + (b * nx + ghost_row(i - 1, nx, I.bc)) * stride;
+    gptr<const double> ap = base + (b * nx + ghost_row(i + 1, nx, I.bc)) * stride;
     // lane 5 w + c forms component c of the plain (w = 0) moments of T h and,
     // for kRedW2x3, of its nu+ (w = 1) and nu- (w = 2) weighted sums (nu+ nu-
     // = 0: the sums of h weighted by nu+ and nu+^2 at i and i-1, by nu- and
@@ -1659,7 +1659,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
     return;
   }
   const int ns = I.nsum;
-  const double* pp = I.part + cl * I.part_tiles * 5;
+  gptr<const double> pp = gmem(I.part) + cl * I.part_tiles * 5;
   // weight classes of the sums: 1 (and nu+, nu- for W1; and nu+^2, nu-^2
   // for W1x3, which needs compact records)
   constexpr int NW = mode == kRedW1x3 ? 5 : (mode == kRedW1 ? 3 : 1);
@@ -1672,7 +1672,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
     const int nyz = I.nvy * I.nvz;
     for (int t = lane; t < I.nparts; t += kWave) {
       const double vx = vgrid(I, 0, (int)(((long long)t * I.crec) / nyz));
-      const double* q = pp + t * 4;
+      gptr<const double> q = pp + t * 4;
       const double m[5] = {q[0], vx * q[0], q[1], q[2], q[3]};
 #pragma unroll
       for (int c = 0; c < 5; ++c) s[c] += m[c];
@@ -1877,12 +1877,12 @@ __global__ __launch_bounds__(kBlock) void k_relax_out(
   const long long local = blk - begin;
   const long long cl = local / slabs;
   const int slab = (int)(local % slabs);
-  const double* frow = I.fac + cl * I.nvs;
+  gptr<const double> frow = gmem(I.fac) + cl * I.nvs;
   for (int k = threadIdx.x; k < I.nvs; k += kBlock) lds[k] = frow[k];
   __syncthreads();
   const int nyz = I.nvy * I.nvz;
-  const double* g = src_sel >= 0 ? I.buf[src_sel] + cl * I.nv3 : nullptr;
-  double* out = I.fout + cl * I.nv3;
+  gptr<const double> g = src_sel >= 0 ? gmem(I.buf[src_sel]) + cl * I.nv3 : nullptr;
+  gptr<double> out = gmem(I.fout) + cl * I.nv3;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     int j = slab * 4 * kBlock + e * kBlock + threadIdx.x;
