@@ -156,24 +156,43 @@ __device__ __forceinline__ double fac3(const double* row, unsigned off) {
 }
 
 // ------------------------------------------------ lane reductions --
-// Lane exchange with partner lane ^ (1 << STAGE): DPP quad permutations for
-// bits 0-1, ds_swizzle (bit mode, within 32 lanes) for bits 2-4, bpermute for
-// bit 5.
-template <int PATTERN>
-__device__ __forceinline__ double swizzle_d(double v) {
-  int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), PATTERN);
-  int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), PATTERN);
-  return __hiloint2double(hi, lo);
+// Lane exchanges without the LDS pipe (no LDS-counter waits on the row loop's
+// critical path).  Partner lane ^ (1 << STAGE) for bits 0-3 by DPP: quad
+// permutations for bits 0-1; for bit 2 a row shift by 4 (right in lanes with
+// bit 2 set, left in the others); for bit 3 a rotation by 8 inside the row of
+// 16.  Bits 4 and 5 only ever enter sums, v + partner(v): the gfx950 permlane
+// swaps with both operands v leave a lane's own value in one result and its
+// partner's in the other, so the sum of the two results is that sum.
+template <int STAGE>
+__device__ __forceinline__ double xor_lane(double v, int lane) {
+  static_assert(STAGE >= 0 && STAGE <= 3, "bits 4 and 5: sum_across");
+  if (STAGE == 0) return dpp_mov<0xb1, 0xf>(v);  // quad_perm [1,0,3,2]
+  if (STAGE == 1) return dpp_mov<0x4e, 0xf>(v);  // quad_perm [2,3,0,1]
+  if (STAGE == 2) {
+    const double from_below = dpp_mov<0x114, 0xf>(v);  // row_shr:4: lane - 4
+    const double from_above = dpp_mov<0x104, 0xf>(v);  // row_shl:4: lane + 4
+    return (lane & 4) ? from_below : from_above;
+  }
+  return dpp_mov<0x128, 0xf>(v);  // row_ror:8: lane ^ 8 inside the row
 }
 
+// v plus the value of partner lane ^ (1 << STAGE), every lane.
 template <int STAGE>
-__device__ __forceinline__ double xor_lane(double v) {
-  if (STAGE == 0) return dpp_mov<0xb1, 0xf>(v);        // quad_perm [1,0,3,2]
-  if (STAGE == 1) return dpp_mov<0x4e, 0xf>(v);        // quad_perm [2,3,0,1]
-  if (STAGE == 2) return swizzle_d<0x1F | (4 << 10)>(v);
-  if (STAGE == 3) return swizzle_d<0x1F | (8 << 10)>(v);
-  if (STAGE == 4) return swizzle_d<0x1F | (16 << 10)>(v);
-  return __shfl_xor(v, 32, kWave);
+__device__ __forceinline__ double sum_across(double v, int lane) {
+  if constexpr (STAGE <= 3) {
+    return v + xor_lane<STAGE>(v, lane);
+  } else {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    if constexpr (STAGE == 4) {
+      const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+      const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+      return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+    } else {
+      const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+      const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+      return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+    }
+  }
 }
 
 // One reduce-scatter stage: the lanes split by bit STAGE; each keeps one half
@@ -186,7 +205,7 @@ __device__ __forceinline__ void scatter_stage(double (&s)[N], int lane) {
   for (int i = 0; i < H; ++i) {
     const double send = upper ? s[i] : s[i + H];
     const double keep = upper ? s[i + H] : s[i];
-    s[i] = keep + xor_lane<STAGE>(send);
+    s[i] = keep + xor_lane<STAGE>(send, lane);
   }
 }
 
@@ -199,8 +218,8 @@ __device__ __forceinline__ double wave_reduce_scatter16(double (&s)[16], int lan
   scatter_stage<1, 4>(s, lane);
   scatter_stage<2, 2>(s, lane);
   scatter_stage<3, 1>(s, lane);
-  s[0] += xor_lane<4>(s[0]);
-  s[0] += xor_lane<5>(s[0]);
+  s[0] = sum_across<4>(s[0], lane);
+  s[0] = sum_across<5>(s[0], lane);
   return s[0];
 }
 
@@ -317,10 +336,10 @@ __device__ __forceinline__ double wave_reduce_scatter(double (&s)[NSLOT], int la
   scatter_stage<(NSLOT >= 16 ? 2 : (NSLOT >= 8 ? 1 : 0)), 2>(s, lane);
   scatter_stage<(NSLOT >= 16 ? 3 : (NSLOT >= 8 ? 2 : 1)), 1>(s, lane);
   // remaining lane bits: plain sums of the one value each lane holds
-  if (NSLOT <= 8) s[0] += xor_lane<(NSLOT >= 8 ? 3 : 2)>(s[0]);
-  if (NSLOT <= 4) s[0] += xor_lane<3>(s[0]);
-  s[0] += xor_lane<4>(s[0]);
-  s[0] += xor_lane<5>(s[0]);
+  if (NSLOT <= 8) s[0] = sum_across<(NSLOT >= 8 ? 3 : 2)>(s[0], lane);
+  if (NSLOT <= 4) s[0] = sum_across<3>(s[0], lane);
+  s[0] = sum_across<4>(s[0], lane);
+  s[0] = sum_across<5>(s[0], lane);
   return s[0];
 }
 
