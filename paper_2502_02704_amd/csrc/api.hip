@@ -157,20 +157,22 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 512) t.chunk /= 2;
   } else {
     // enough work items to fill 256 CUs several times over.  Three-step
-    // passes (grids whose v_x planes are whole tiles of 4 velocities per
-    // lane) hold three levels of rows: 4 velocities per lane, and 16-cell
-    // chunks to amortise the deeper halo (measured on the 512 x 32^3 x
-    // 64-slice batch)
-    if (pair && g_fuse == 3 && p.nx >= 3 && ((long long)p.nv[1] * p.nv[2]) % (kWave * 4) == 0) {
-      // the longest chunk up to 16 whose three levels of factor rows fit 64 KiB of LDS
+    // passes (grids whose v_x planes are whole tiles of 2 velocities per
+    // lane) hold three levels of rows: 2 velocities per lane (four waves
+    // per SIMD), and chunks up to 24 cells to amortise the deeper halo
+    // (measured on the 512 x 32^3 x 64-slice batch: 8, 16, 24 cells take
+    // 3.98, 3.58, 3.46 ms per pass)
+    if (pair && g_fuse == 3 && p.nx >= 3 && ((long long)p.nv[1] * p.nv[2]) % (kWave * 2) == 0) {
+      // the longest chunk up to 24 whose three levels of factor rows fit 64 KiB of LDS
       const long long nvs = (long long)p.nv[0] + p.nv[1] + p.nv[2];
-      int ch = 16;
+      int ch = 24;
       while (ch > 1 && (3LL * ch + 12) * nvs * (long long)sizeof(double) > 65536) --ch;
-      t = Tiles{4, ch, 1};
+      t = Tiles{2, ch, 1};
     }
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 4096) t.chunk /= 2;
-    if (blocks_for_tiles(p, batch, t) < 2048) t.elems = 4;
-    if (blocks_for_tiles(p, batch, t) < 1024) t.elems = 2;
+    // fewer velocities per lane (more tiles) where blocks are still short
+    if (blocks_for_tiles(p, batch, t) < 2048 && t.elems > 4) t.elems = 4;
+    if (blocks_for_tiles(p, batch, t) < 1024 && t.elems > 2) t.elems = 2;
   }
   if (g_override.elems) t.elems = g_override.elems;
   if (g_override.chunk) t.chunk = g_override.chunk;
@@ -1595,10 +1597,10 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_byt
   Tiles best = {0, 0, 0};
   float best_ms = 1e30f;
   const int Es[3] = {2, 4, 8};
-  const int Cs[6] = {1, 2, 4, 8, 16, 32};
+  const int Cs[7] = {1, 2, 4, 8, 16, 24, 32};
   for (int pr = 0; pr < 2; ++pr)
   for (int ei = 0; ei < 3; ++ei)
-    for (int ci = 0; ci < 6; ++ci) {
+    for (int ci = 0; ci < 7; ++ci) {
       Tiles t = {Es[ei], Cs[ci], pr};
       if (t.chunk > prob->nx || (pr && prob->nv[2] % 2 != 0)) continue;
       Inst I = make_inst(*prob, batch, dt, t, fused_for(t, steps) ? 15 : 5);
