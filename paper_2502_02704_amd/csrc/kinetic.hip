@@ -250,16 +250,6 @@ __device__ __forceinline__ void wave_sum_all_n(double (&v)[N], int lane) {
   }
 }
 
-// Raw rows in flight ahead of the one relaxed, in the two-step march.
-#ifndef BGK_PF2X2
-#define BGK_PF2X2 1
-#endif
-// Minimum waves per SIMD requested for the two-step kernel (0 = compiler's
-// choice).
-#ifndef BGK_WAVES2X2
-#define BGK_WAVES2X2 0
-#endif
-
 // Recompute |v|^2 and nu per use instead of holding them in registers.
 #ifndef BGK_RECOMPUTE_Q
 #define BGK_RECOMPUTE_Q 0
@@ -1688,27 +1678,46 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
   if (I.crec) {
     // compact records (tiles inside one v_x plane): (sum g, sum v_y g,
     // sum v_z g, sum |v|^2 g); v_x and nu are the tile's
-    const int nyz = I.nvy * I.nvz;
-    for (int t = lane; t < I.nparts; t += kWave) {
-      const double vx = vgrid(I, 0, (int)(((long long)t * I.crec) / nyz));
-      gptr<const double> q = pp + t * 4;
-      const double m[5] = {q[0], vx * q[0], q[1], q[2], q[3]};
+    // a record's tile lies in v_x plane t / (tiles per plane); crec divides
+    // nvy nvz, and the 32-bit quotient avoids a 64-bit division per record
+    const unsigned tiles_per_plane = (unsigned)(I.nvy * I.nvz / I.crec);
+    // the records of up to RU tiles per lane are loaded before any is summed
+    // (loads in flight together); summed in tile order as in one pass
+    constexpr int RU = 4;
+    for (int t0 = lane; t0 < I.nparts; t0 += RU * kWave) {
+      double q[RU][4];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) s[c] += m[c];
-      if (NW >= 3) {
-        const double nu = vx * I.r;
-        const double wp = nu > 0.0 ? nu : 0.0, wm = nu < 0.0 ? -nu : 0.0;
+      for (int r = 0; r < RU; ++r) {
+        const int t = t0 + r * kWave;
+        // (records are 8-byte aligned only: part_tiles * 5 may be odd)
+        if (t < I.nparts) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          s[5 + c] += wp * m[c];
-          s[10 + c] += wm * m[c];
+          for (int c = 0; c < 4; ++c) q[r][c] = pp[t * 4 + c];
         }
-        if (NW == 5) {
-          const double wpp = wp * wp, wmm = wm * wm;
+      }
+#pragma unroll
+      for (int r = 0; r < RU; ++r) {
+        const int t = t0 + r * kWave;
+        if (t >= I.nparts) break;
+        const double vx = vgrid(I, 0, (int)((unsigned)t / tiles_per_plane));
+        const double m[5] = {q[r][0], vx * q[r][0], q[r][1], q[r][2], q[r][3]};
+#pragma unroll
+        for (int c = 0; c < 5; ++c) s[c] += m[c];
+        if (NW >= 3) {
+          const double nu = vx * I.r;
+          const double wp = nu > 0.0 ? nu : 0.0, wm = nu < 0.0 ? -nu : 0.0;
 #pragma unroll
           for (int c = 0; c < 5; ++c) {
-            s[15 + c] += wpp * m[c];
-            s[20 + c] += wmm * m[c];
+            s[5 + c] += wp * m[c];
+            s[10 + c] += wm * m[c];
+          }
+          if (NW == 5) {
+            const double wpp = wp * wp, wmm = wm * wm;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+              s[15 + c] += wpp * m[c];
+              s[20 + c] += wmm * m[c];
+            }
           }
         }
       }
