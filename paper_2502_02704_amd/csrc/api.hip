@@ -157,17 +157,18 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 512) t.chunk /= 2;
   } else {
     // enough work items to fill 256 CUs several times over.  Three-step
-    // passes (grids whose v_x planes are whole tiles of 2 velocities per
-    // lane) hold three levels of rows: 2 velocities per lane (four waves
-    // per SIMD), and chunks up to 24 cells to amortise the deeper halo
-    // (measured on the 512 x 32^3 x 64-slice batch: 8, 16, 24 cells take
-    // 3.98, 3.58, 3.46 ms per pass)
-    if (pair && g_fuse == 3 && p.nx >= 3 && ((long long)p.nv[1] * p.nv[2]) % (kWave * 2) == 0) {
+    // passes (grids whose v_x planes are whole tiles) hold three levels of
+    // rows: 4 velocities per lane (non-temporal row loads) where a v_x plane
+    // is whole tiles of 256 velocities, else 2; chunks up to 24 cells to
+    // amortise the deeper halo (measured on the 512 x 32^3 x 64-slice batch:
+    // 4 per lane 3.26 ms per pass over 24-cell chunks, 3.37 over 16, 3.51
+    // over 12; 2 per lane 3.47 ms over 24)
+    if (pair && g_fuse == 3 && p.nx >= 3 && nyz % (kWave * 2) == 0) {
       // the longest chunk up to 24 whose three levels of factor rows fit 64 KiB of LDS
       const long long nvs = (long long)p.nv[0] + p.nv[1] + p.nv[2];
       int ch = 24;
       while (ch > 1 && (3LL * ch + 12) * nvs * (long long)sizeof(double) > 65536) --ch;
-      t = Tiles{2, ch, 1};
+      t = Tiles{nyz % (kWave * 4) == 0 ? 4 : 2, ch, 1};
     }
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 4096) t.chunk /= 2;
     // fewer velocities per lane (more tiles) where blocks are still short

@@ -120,6 +120,11 @@ __device__ __forceinline__ double2 ld2(gptr<const double> p) {
   const bgk_d2 t = *reinterpret_cast<gptr<const bgk_d2>>(p);
   return make_double2(t.x, t.y);
 }
+// The same load marked non-temporal (streamed, not kept in the caches).
+__device__ __forceinline__ double2 ld2_nt(gptr<const double> p) {
+  const bgk_d2 t = __builtin_nontemporal_load(reinterpret_cast<gptr<const bgk_d2>>(p));
+  return make_double2(t.x, t.y);
+}
 __device__ __forceinline__ void st2(gptr<double> p, double x, double y) {
   bgk_d2 t;
   t.x = x;

@@ -1306,11 +1306,15 @@ __device__ __forceinline__ void step3x_march(const Inst& I, const double* lds1,
     const int r = row_at(k);
     return r < 0 || r >= nx;
   };
+  // raw rows: non-temporal loads with two pairs per lane (measured on the
+  // 64-slice 512 x 32^3 batch: 3.26 against 3.47 ms per pass; with one pair
+  // per lane, and in the one- and two-step passes, they are slower)
   auto load_row = [&](int k, double2 (&raw)[P]) {
     if (MODE == kLift) return;
     gptr<const double> row = src + (long long)ghost_row(row_at(k), nx, I.bc) * nv3;
 #pragma unroll
-    for (int p = 0; p < P; ++p) raw[p] = ld2(row + e.jofs[p]);
+    for (int p = 0; p < P; ++p)
+      raw[p] = P == 2 ? ld2_nt(row + e.jofs[p]) : ld2(row + e.jofs[p]);
   };
   // level 1 at position k: rows i0-3 .. i1+2 staged in lds1
   auto level1 = [&](int k, const double2 (&raw)[P], double2 (&out)[P]) {
