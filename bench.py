@@ -302,8 +302,8 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "sharding of the slices is a design, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding the "
+              "slices over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
