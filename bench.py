@@ -196,33 +196,52 @@ def force_throughput(torch, bgk, wl, reps=5):
 
 def uneven_throughput(torch, bgk, wl, span=0.01, reps=3):
     """The uneven multi-instance batch (seeded Riemann problems with Nx in
-    [128, 1024], Nv in [16, 32], eps in [1e-4, 1]) advanced together, one
-    launch per step over all instances that are still stepping.  Instances
-    7, 15 and 29 are left out: their cold states are not resolved on their
-    velocity grids (theta / dv^2 = 0.11, 0.29, 0.33) and their temperatures
-    collapse within the span, in the oracle too."""
+    [128, 1024], Nv in [16, 32], eps in [1e-4, 1]) advanced together: every
+    instance's first step alone, then per round one two-step pass over the
+    instances with two or more steps left and one step for those with one
+    left (the library's built-in setting), and, for comparison, one step per
+    launch.  Instances 7, 15 and 29 are left out: their cold states are not
+    resolved on their velocity grids (theta / dv^2 = 0.11, 0.29, 0.33) and
+    their temperatures collapse within the span, in the oracle too."""
     insts = [w for q, w in enumerate(wl.c5_uneven()) if q not in (7, 15, 29)]
     probs = [w.problem for w in insts]
     fs = [bgk.lift(w.problem, torch.from_numpy(w.W0).cuda()) for w in insts]
     spans = [span] * len(insts)
     outs, steps = bgk.fine_step_batched(probs, fs, spans)
-    torch.cuda.synchronize()
-    bgk.prof_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        bgk.fine_step_batched(probs, fs, spans, outs)
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / reps
-    ms, launches, upd, by = bgk.prof_read(bgk.PROF_ONE_STEP)
-    bgk.prof_enable(False)
-    bgk.check_status()
     n_upd = sum(p.cells * n for p, n in zip(probs, steps))
-    return {"workload": f"uneven_{len(insts)}_instances", "span": span,
+
+    def timed():
+        bgk.fine_step_batched(probs, fs, spans, outs)
+        torch.cuda.synchronize()
+        bgk.prof_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            bgk.fine_step_batched(probs, fs, spans, outs)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        kinds = {name: bgk.prof_read(kind) for name, kind in
+                 (("two_step_pass", bgk.PROF_TWO_STEP), ("one_step", bgk.PROF_ONE_STEP))}
+        bgk.prof_enable(False)
+        bgk.check_status()
+        return el, kinds
+
+    el, kinds = timed()
+    line = {"workload": f"uneven_{len(insts)}_instances", "span": span,
             "steps_min_max": [min(steps), max(steps)],
             "cells": sum(p.cells for p in probs), "updates_per_s": n_upd / el,
-            "ms_per_call": round(el * 1e3, 3),
-            "step_kernel_GBs": round(by / (ms * 1e-3) / 1e9, 1),
-            "step_kernel_avg_us": round(ms * 1e3 / max(launches, 1), 2)}
+            "ms_per_call": round(el * 1e3, 3)}
+    for name, (ms, launches, upd, by) in kinds.items():
+        if launches:
+            line[name + "_GBs"] = round(by / (ms * 1e-3) / 1e9, 1)
+            line[name + "_avg_us"] = round(ms * 1e3 / launches, 2)
+            line[name + "_launches"] = launches
+    bgk.set_step_fusion(1)
+    try:
+        el1, _ = timed()
+    finally:
+        bgk.set_step_fusion(3)
+    line["one_step_per_launch_updates_per_s"] = n_upd / el1
+    return line
 
 
 def adjoint_timing(torch, bgk, wl, reps=3):

@@ -346,6 +346,8 @@ _batched_ws: Dict[tuple, torch.Tensor] = {}
 
 def fine_step_batched(probs: Sequence, fs: Sequence[torch.Tensor], spans: Sequence[float],
                       outs: Sequence[torch.Tensor] | None = None):
+    """Uneven batch: instance q advances fs[q] by spans[q] on its own grid
+    (bgk_fine_step_batched).  Returns (outputs, step counts)."""
     L = _gpu_lib()
     n = len(probs)
     arr = (_Problem * n)(*[problem_struct(p) for p in probs])

@@ -1476,30 +1476,45 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   if (n_steps_out)
     for (int q = 0; q < n; ++q) n_steps_out[q] = steps[q];
   hipStream_t s = (hipStream_t)stream;
-  // one tile shape for all instances; instances sorted by step count
-  // (descending) so that the active ones at any step form a prefix.
-  std::vector<int> order(n);
-  for (int q = 0; q < n; ++q) order[q] = q;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return steps[x] > steps[y]; });
+  // Tile shape: 4 velocities per lane over 8-cell chunks (or the override).
+  // With two or more steps per pass set, the instances whose rows can be
+  // read in 16-byte pairs (nvz even, aligned f_in and f_out) run fused
+  // two-step passes (group A); the others one step per launch (group B, on
+  // paired lanes only if all of its instances allow it).  Each group is
+  // sorted by step count (descending) so that its active instances at any
+  // step form a prefix; group A comes first in the descriptor table.
   Tiles t = {4, 8, 1};
-  for (int q = 0; q < n; ++q) {
-    if (probs[q].nv[2] % 2 != 0) t.pair = 0;
-    t = aligned_tiles(t, probs[q], {f_in[q], f_out[q]});
-  }
   {
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_override.elems) t.elems = g_override.elems;
     if (g_override.chunk) t.chunk = g_override.chunk;
     if (g_override.pair == 0) t.pair = 0;
   }
+  std::vector<char> pairable(n);
+  for (int q = 0; q < n; ++q)
+    pairable[q] = t.pair == 1 && probs[q].nv[2] % 2 == 0 &&
+                  aligned_tiles(t, probs[q], {f_in[q], f_out[q]}).pair == 1;
+  const bool fused = fuse_mode() >= 2;
+  auto in_a = [&](int q) { return fused && pairable[q]; };
+  std::vector<int> order(n);
+  for (int q = 0; q < n; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (in_a(x) != in_a(y)) return in_a(x);
+    return steps[x] > steps[y];
+  });
+  int nA = 0;
+  while (nA < n && in_a(order[nA])) ++nA;
+  Tiles tA = t, tB = t;
+  for (int k = nA; k < n; ++k)
+    if (!pairable[order[k]]) tB.pair = 0;
   std::vector<Inst> h(n);
   long long items = 0;
-  int nvs_max = 0;
+  int nvs_a = 0, nvs_b = 0;
   std::vector<long long> items_prefix(n + 1, 0), cells_prefix(n + 1, 0);
   for (int k = 0; k < n; ++k) {
     const int q = order[k];
-    Inst I = make_inst(probs[q], 1, dts[q], t);
+    // fused passes need the nu-weighted partial sums (15 per record)
+    Inst I = k < nA ? make_inst(probs[q], 1, dts[q], tA, 15) : make_inst(probs[q], 1, dts[q], tB);
     attach_fine(I, ws, L.regions[q], f_out[q]);
     I.fin = f_in[q];
     I.fout = f_out[q];
@@ -1508,43 +1523,119 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
     items += I.items;
     items_prefix[k + 1] = items;
     cells_prefix[k + 1] = cells_prefix[k] + I.nx;
-    nvs_max = std::max(nvs_max, I.nvs);
+    (k < nA ? nvs_a : nvs_b) = std::max(k < nA ? nvs_a : nvs_b, I.nvs);
     h[k] = I;
   }
   Inst* dI = at<Inst>(ws, L.insts);
   int* st = &at<WsHeader>(ws, 0)->status;
-  const int smax = steps[order[0]];
-  auto sequence = [&](hipStream_t q) -> int {
+  auto cells_of = [&](int a, int b) {
+    double c = 0.0;
+    for (int k = a; k < b; ++k) c += (double)h[k].nx * h[k].nv3;
+    return c;
+  };
+  // Group B, entries [nA, n): one step per launch over the instances still
+  // stepping (a launch over entries [a, b) takes the table from entry a).
+  auto sequence_b = [&](hipStream_t q) -> int {
     int r;
-    if ((r = put_insts(dI, h.data(), n, q))) return r;
+    if (nA == n) return BGK_OK;
+    const int smax = h[nA].steps;
     int w_prev = 1;
     for (int k = 1; k <= smax; ++k) {
-      int n_act = 0;
-      while (n_act < n && h[n_act].steps >= k) ++n_act;
+      int e = nA;
+      while (e < n && h[e].steps >= k) ++e;
       const int mode = (k == 1) ? kCopy : kRelax;
       const int phase = w_prev;
-      double cells = 0.0;
-      for (int a = 0; a < n_act; ++a) cells += (double)h[a].nx * h[a].nv3;
       prof_before(q);
-      r = launch_step(dI, n_act, items_prefix[n_act], mode, phase, t,
-                      (t.chunk + 2) * nvs_max, st, q);
-      prof_after(q, cells, 16.0, BGK_PROF_ONE_STEP);
+      r = launch_step(dI + nA, e - nA, items_prefix[e] - items_prefix[nA], mode, phase, tB,
+                      (tB.chunk + 2) * nvs_b, st, q);
+      prof_after(q, cells_of(nA, e), 16.0, BGK_PROF_ONE_STEP);
       if (r) return r;
-      if ((r = launch_reduce(dI, n_act, cells_prefix[n_act], kRedRelaxFactors, 0, st, q)))
+      if ((r = launch_reduce(dI + nA, e - nA, cells_prefix[e] - cells_prefix[nA],
+                             kRedRelaxFactors, 0, st, q)))
         return r;
       w_prev = phase ^ 1;
     }
     // final relaxation, each instance from the buffer its last step wrote:
     // step k writes buf[(k - 1) & 1]
-    for (int k = 0; k < n; ++k) {
+    for (int k = nA; k < n; ++k) {
       const int sel = (h[k].steps - 1) & 1;
       if ((r = launch_relax_out_blocks(dI + k, 1, relax_out_blocks(h[k]), h[k].nvs, sel, q)))
         return r;
     }
     return BGK_OK;
   };
+  // Group A, entries [0, nA): every instance's first step alone (from f_in),
+  // then in each round the instances with two or more steps left (a prefix)
+  // take one two-step pass and those with one left (the next entries) one
+  // step, so all active instances stay in the same buffer phase.
+  auto sequence_a = [&](hipStream_t q) -> int {
+    int r;
+    if (nA == 0) return BGK_OK;
+    std::vector<int> rem(nA), sel(nA, 0);
+    for (int k = 0; k < nA; ++k) rem[k] = h[k].steps;
+    auto prefix = [&](int m) {
+      int c = 0;
+      while (c < nA && rem[c] >= m) ++c;
+      return c;
+    };
+    int phase = 1;  // a pass reads buf[phase] (f_in in copy mode), writes buf[phase ^ 1]
+    auto advance = [&](int a, int b, int by) {
+      for (int k = a; k < b; ++k) {
+        rem[k] -= by;
+        if (rem[k] == 0) sel[k] = phase ^ 1;
+      }
+    };
+    prof_before(q);
+    r = launch_step(dI, nA, items_prefix[nA], kCopy, phase, tA, (tA.chunk + 2) * nvs_a, st, q,
+                    15);
+    prof_after(q, cells_of(0, nA), 16.0, BGK_PROF_ONE_STEP);
+    if (r) return r;
+    advance(0, nA, 1);
+    phase ^= 1;
+    for (;;) {
+      const int n1 = prefix(1), n2 = prefix(2);
+      if (n1 == 0) break;
+      if (n2 > 0) {
+        if ((r = launch_reduce(dI, n2, cells_prefix[n2], kRedW1, 0, st, q))) return r;
+        if ((r = launch_reduce(dI, n2, cells_prefix[n2], kRedW2, 0, st, q))) return r;
+      }
+      if (n1 > n2 &&
+          (r = launch_reduce(dI + n2, n1 - n2, cells_prefix[n1] - cells_prefix[n2],
+                             kRedRelaxFactors, 0, st, q)))
+        return r;
+      if (n2 > 0) {
+        prof_before(q);
+        r = launch_step2x2(dI, n2, items_prefix[n2], kRelax, phase, tA,
+                           (2 * tA.chunk + 6) * nvs_a, false, q);
+        prof_after(q, 2.0 * cells_of(0, n2), 8.0, BGK_PROF_TWO_STEP);
+        if (r) return r;
+      }
+      if (n1 > n2) {
+        prof_before(q);
+        r = launch_step(dI + n2, n1 - n2, items_prefix[n1] - items_prefix[n2], kRelax, phase,
+                        tA, (tA.chunk + 2) * nvs_a, st, q, 15);
+        prof_after(q, cells_of(n2, n1), 16.0, BGK_PROF_ONE_STEP);
+        if (r) return r;
+      }
+      advance(0, n2, 2);
+      advance(n2, n1, 1);
+      phase ^= 1;
+    }
+    // factors of every instance's last field, then its relaxed output
+    if ((r = launch_reduce(dI, nA, cells_prefix[nA], kRedRelaxFactors, 0, st, q))) return r;
+    for (int k = 0; k < nA; ++k)
+      if ((r = launch_relax_out_blocks(dI + k, 1, relax_out_blocks(h[k]), h[k].nvs, sel[k], q)))
+        return r;
+    return BGK_OK;
+  };
+  auto sequence = [&](hipStream_t q) -> int {
+    int r;
+    if ((r = put_insts(dI, h.data(), n, q))) return r;
+    if ((r = sequence_a(q))) return r;
+    return sequence_b(q);
+  };
   // the whole sequence is captured once per (workspace, problems, buffers,
-  // spans, tiles) and replayed
+  // spans, tiles, fusion) and replayed
   std::string key("bat");
   auto add = [&](const void* q, size_t nb) { key.append(static_cast<const char*>(q), nb); };
   add(&ws, sizeof(ws));
@@ -1555,6 +1646,7 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   add(f_out, sizeof(double*) * (size_t)n);
   add(t_span, sizeof(double) * (size_t)n);
   add(&t, sizeof(t));
+  add(&fused, sizeof(fused));
   return run_graph(key, s, sequence);
 }
 

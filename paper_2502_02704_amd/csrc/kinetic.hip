@@ -89,6 +89,9 @@ __device__ __forceinline__ double wave_sum_all(double v) {
   return readlane_d(wave_sum_to_last(v), kWave - 1);
 }
 
+// Instance of a work item.  A launch may take a table that starts inside a
+// batch (its first entry's item_begin > 0): the kernels add that offset to
+// their block's item before the search.
 __device__ __forceinline__ int find_inst(const Inst* insts, int n_inst,
                                          long long item) {
   int q = 0;
@@ -381,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
                                                  int phase) {
   constexpr int H = LIMITED ? 2 : 1;  // stencil half-width in x
   extern __shared__ double lds[];
-  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const long long item = xcd_item(blockIdx.x, gridDim.x) + insts[0].item_begin;
   const int q = find_inst(insts, n_inst, item);
   const Inst& I = insts[q];
   const long long local = item - I.item_begin;
@@ -677,7 +680,7 @@ __global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ i
                                                       int n_inst, int chunk, int phase) {
   constexpr int H = LIMITED ? 2 : 1;
   extern __shared__ double lds[];
-  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const long long item = xcd_item(blockIdx.x, gridDim.x) + insts[0].item_begin;
   const int q = find_inst(insts, n_inst, item);
   const Inst& I = insts[q];
   const long long local = item - I.item_begin;
@@ -1086,7 +1089,7 @@ __global__ __launch_bounds__(kBlock) void k_step2(const Inst* __restrict__ insts
                                                   int n_inst, int chunk,
                                                   int phase) {
   extern __shared__ double lds[];
-  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const long long item = xcd_item(blockIdx.x, gridDim.x) + insts[0].item_begin;
   const int q = find_inst(insts, n_inst, item);
   const Inst& I = insts[q];
   const long long local = item - I.item_begin;
@@ -1238,7 +1241,7 @@ __global__ __launch_bounds__(kBlock) void k_step2x2(const Inst* __restrict__ ins
                                                     int n_inst, int chunk,
                                                     int phase) {
   extern __shared__ double lds[];
-  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const long long item = xcd_item(blockIdx.x, gridDim.x) + insts[0].item_begin;
   const int q = find_inst(insts, n_inst, item);
   const Inst& I = insts[q];
   const long long local = item - I.item_begin;
@@ -1428,7 +1431,7 @@ template <int P, int MODE>
 __global__ __launch_bounds__(kBlock) void k_step3x(const Inst* __restrict__ insts,
                                                    int n_inst, int chunk, int phase) {
   extern __shared__ double lds[];
-  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const long long item = xcd_item(blockIdx.x, gridDim.x) + insts[0].item_begin;
   const int q = find_inst(insts, n_inst, item);
   const Inst& I = insts[q];
   const long long local = item - I.item_begin;
@@ -1458,7 +1461,7 @@ __global__ __launch_bounds__(kBlock) void k_step3x(const Inst* __restrict__ inst
 template <int E>
 __global__ __launch_bounds__(kBlock) void k_partials(
     const Inst* __restrict__ insts, int n_inst, int chunk) {
-  const long long item = xcd_item(blockIdx.x, gridDim.x);
+  const long long item = xcd_item(blockIdx.x, gridDim.x) + insts[0].item_begin;
   const int q = find_inst(insts, n_inst, item);
   const Inst& I = insts[q];
   const long long local = item - I.item_begin;

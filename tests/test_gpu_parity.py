@@ -287,6 +287,57 @@ def test_fine_step_batched_uneven():
         assert rel_f(outs[q].cpu().numpy(), ref) < TOL
 
 
+def test_fine_step_batched_uneven_two_step_passes():
+    """With two or three steps per pass set, the uneven batch takes every
+    instance's first step alone (from f_in), then per round one two-step
+    pass over the instances with two or more steps left and one step for
+    those with one left.  Step counts 1, 2, 3, 4 and 7 (odd and even), both
+    boundary conditions, one grid whose v_x planes are whole tiles (compact
+    records); two instances with odd nvz (no paired rows) take one step per
+    launch in the same call.  Against the oracle, and against one step per
+    pass."""
+    probs = [
+        wl.Problem(nx=9, nv=(6, 4, 8), v_lo=(-5,) * 3, v_hi=(5,) * 3, bc=wl.BC_NEUMANN,
+                   eps=1e-2),
+        wl.Problem(nx=12, nv=(5, 6, 4), v_lo=(-6,) * 3, v_hi=(6,) * 3, bc=wl.BC_PERIODIC,
+                   eps=0.3),
+        wl.Problem(nx=7, nv=(4, 4, 6), v_lo=(-5,) * 3, v_hi=(5,) * 3, bc=wl.BC_PERIODIC,
+                   eps=3e-3),
+        wl.Problem(nx=16, nv=(4, 16, 16), v_lo=(-5,) * 3, v_hi=(5,) * 3, bc=wl.BC_NEUMANN,
+                   eps=1e-1),
+        wl.Problem(nx=5, nv=(6, 6, 2), v_lo=(-4,) * 3, v_hi=(4,) * 3, bc=wl.BC_PERIODIC,
+                   eps=1.0),
+        wl.Problem(nx=10, nv=(5, 5, 5), v_lo=(-5,) * 3, v_hi=(5,) * 3, bc=wl.BC_NEUMANN,
+                   eps=2e-2),
+        wl.Problem(nx=6, nv=(4, 3, 3), v_lo=(-4,) * 3, v_hi=(4,) * 3, bc=wl.BC_PERIODIC,
+                   eps=5e-2),
+    ]
+    want = [7, 1, 4, 3, 2, 5, 2]
+    spans, fs, refs = [], [], []
+    for q, p in enumerate(probs):
+        dv = (p.v_hi[0] - p.v_lo[0]) / p.nv[0]
+        vmax = max(abs(p.v_lo[0] + 0.5 * dv), abs(p.v_hi[0] - 0.5 * dv))
+        span = (want[q] - 0.5) * p.cfl * ((p.x_hi - p.x_lo) / p.nx) / vmax
+        _, f = states(p, 60 + q)
+        spans.append(span)
+        fs.append(cuda(f))
+        refs.append(oracle.fine_step(p, f, span))
+    for fuse in (2, 3):
+        bgk.set_step_fusion(fuse)
+        outs, steps = bgk.fine_step_batched(probs, fs, spans)
+        bgk.check_status()
+        assert steps == want
+        for q in range(len(probs)):
+            ref, nr = refs[q]
+            assert nr == want[q]
+            assert rel_f(outs[q].cpu().numpy(), ref) < TOL, q
+        bgk.set_step_fusion(1)
+        single, _ = bgk.fine_step_batched(probs, fs, spans)
+        bgk.check_status()
+        for q in range(len(probs)):
+            assert rel_f(outs[q].cpu().numpy(), single[q].cpu().numpy()) < 1e-13, q
+
+
 # ------------------------------------------------------------------ adjoint --
 def _adj_case(bc=wl.BC_PERIODIC):
     p = wl.Problem(nx=10, nv=(6, 5, 4), v_lo=(-5,) * 3, v_hi=(5,) * 3, bc=bc, eps=1e-2)
