@@ -109,6 +109,12 @@ static long long blocks_for_tiles(const bgk_problem& p, int batch, Tiles t) {
 
 static int g_fuse = 3;  // IMEX steps per pass (1, 2 or 3) where possible
 
+// LDS and chunk limits of the three-step kernel.  With 4 velocities per lane
+// (233 VGPRs) a CU holds one 8-wave block, which may then take all 160 KB of
+// gfx950's LDS; with 2 (123 VGPRs) two blocks share it.
+static size_t lds3_cap(int elems) { return elems == 4 ? 163840 : 65536; }
+static int lds3_max_chunk(int elems) { return elems == 4 ? 48 : 24; }
+
 // The v_x-column mapping fits a grid whose tiles fit the partial-sum capacity.
 static bool vcol_fits(const bgk_problem& p, Tiles t) {
   return ntiles_of(p, t) <= part_tiles_of(p);
@@ -159,16 +165,18 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
     // enough work items to fill 256 CUs several times over.  Three-step
     // passes (grids whose v_x planes are whole tiles) hold three levels of
     // rows: 4 velocities per lane (non-temporal row loads) where a v_x plane
-    // is whole tiles of 256 velocities, else 2; chunks up to 24 cells to
-    // amortise the deeper halo (measured on the 512 x 32^3 x 64-slice batch:
-    // 4 per lane 3.26 ms per pass over 24-cell chunks, 3.37 over 16, 3.51
-    // over 12; 2 per lane 3.47 ms over 24)
+    // is whole tiles of 256 velocities, else 2; long chunks amortise the
+    // deeper halo (measured with 4 per lane: on the 512 x 32^3 x 64-slice
+    // batch 3.51, 3.37, 3.30, 3.24, 3.21 ms per pass over 12, 16, 24, 32, 48
+    // cells; on 4 slices of 2048 x 48^3 3.17, 3.01, 2.97 ms over 14, 24, 32;
+    // 2 per lane 3.47 ms over 24)
     if (pair && g_fuse == 3 && p.nx >= 3 && nyz % (kWave * 2) == 0) {
-      // the longest chunk up to 24 whose three levels of factor rows fit 64 KiB of LDS
+      // the longest chunk whose three levels of factor rows fit the LDS
+      const int e = nyz % (kWave * 4) == 0 ? 4 : 2;
       const long long nvs = (long long)p.nv[0] + p.nv[1] + p.nv[2];
-      int ch = 24;
-      while (ch > 1 && (3LL * ch + 12) * nvs * (long long)sizeof(double) > 65536) --ch;
-      t = Tiles{nyz % (kWave * 4) == 0 ? 4 : 2, ch, 1};
+      int ch = lds3_max_chunk(e);
+      while (ch > 1 && (size_t)(3LL * ch + 12) * nvs * sizeof(double) > lds3_cap(e)) --ch;
+      t = Tiles{e, ch, 1};
     }
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 4096) t.chunk /= 2;
     // fewer velocities per lane (more tiles) where blocks are still short
@@ -440,7 +448,7 @@ static int fuse_mode() {
 // Three IMEX steps per pass: on when asked for, on grids with compact records
 // (every tile in one v_x plane), nx >= 3 (ghost rows three deep), 2 or 4
 // velocities per lane (three levels of rows in registers) and factor rows of
-// the three levels within 64 KiB of LDS.
+// the three levels within the LDS cap (lds3_cap).
 static bool triple_for(const Inst& h, Tiles t) {
   int fuse;
   {
@@ -448,7 +456,7 @@ static bool triple_for(const Inst& h, Tiles t) {
     fuse = g_fuse;
   }
   return fuse == 3 && h.crec != 0 && h.nsum == 15 && h.nx >= 3 && t.pair && t.elems <= 4 &&
-         (size_t)lds_doubles3(h, t) * sizeof(double) <= 65536;
+         (size_t)lds_doubles3(h, t) * sizeof(double) <= lds3_cap(t.elems);
 }
 
 // Runs `n` relax-then-transport steps on the (uploaded) descriptor d_I.
@@ -1690,10 +1698,10 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_byt
   Tiles best = {0, 0, 0};
   float best_ms = 1e30f;
   const int Es[3] = {2, 4, 8};
-  const int Cs[7] = {1, 2, 4, 8, 16, 24, 32};
+  const int Cs[8] = {1, 2, 4, 8, 16, 24, 32, 48};
   for (int pr = 0; pr < 2; ++pr)
   for (int ei = 0; ei < 3; ++ei)
-    for (int ci = 0; ci < 7; ++ci) {
+    for (int ci = 0; ci < 8; ++ci) {
       Tiles t = {Es[ei], Cs[ci], pr};
       if (t.chunk > prob->nx || (pr && prob->nv[2] % 2 != 0)) continue;
       Inst I = make_inst(*prob, batch, dt, t, fused_for(t, steps) ? 15 : 5);

@@ -57,7 +57,7 @@ def tiles_for(p):
     nyz = p.nv[1] * p.nv[2]
     out = [(2, 1, 1), (2, 2, 1), (2, 5, 1), (2, 24, 1), (2, 64, 1)]
     if nyz % 256 == 0:
-        out += [(4, 3, 1), (4, 8, 1), (4, 24, 1)]
+        out += [(4, 3, 1), (4, 8, 1), (4, 24, 1), (4, 48, 1)]
     return out
 
 
@@ -197,9 +197,10 @@ def test_smooth_periodic_full_batch_three_steps_sampled():
 
 def test_sod_large_full_size_three_step_pass():
     """Nx=2048, 48^3 on [-10,10]^3 (the large Sod workload, 144 factor values
-    per x row, so 14-cell chunks keep three levels of factor rows in 64 KiB of
-    LDS): four steps from the lifted Sod data (one single step, one three-step
-    pass), whole field against the oracle."""
+    per x row: the chunk is as long as three levels of factor rows fit the
+    LDS, more than 64 KiB with four velocities per lane): four steps from the
+    lifted Sod data (one single step, one three-step pass), whole field
+    against the oracle."""
     wk = wl.c3_sod_large()
     p = wk.problem
     n, dt = oracle.n_steps(p, wk.T / wk.n_slices)
