@@ -125,8 +125,9 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
   const int pair = (p.nv[2] % 2 == 0 && !generic) ? 1 : 0;
   // measured best on the 512 x 32^3 x 64-slice batch with 8-wave blocks:
   // fused passes 8 velocities per lane over 8-cell chunks, single steps 8
-  // over short chunks
-  Tiles t = (pair && g_fuse >= 2) ? Tiles{8, 8, 1} : Tiles{8, 4, pair};
+  // over short chunks; fused passes on unpaired lanes (odd nv_z) take 4
+  // (8 spill in their two-step march)
+  Tiles t = g_fuse >= 2 ? (pair ? Tiles{8, 8, 1} : Tiles{4, 8, 0}) : Tiles{8, 4, pair};
   auto it = g_tuned.find({p.nx, p.nv[0], p.nv[1], p.nv[2], batch});
   const long long cells = (long long)batch * p.nx * nv3_of(p);
   // The exterior-force step runs on v_x columns (the v_x neighbours of a
@@ -373,10 +374,12 @@ int launch_prim_to_cons(const double* W, double* V, int n, hipStream_t s) {
   return BGK_OK;
 }
 
-// Two IMEX steps per pass over f (paired lane mapping only); switchable.
+// Two (or three) IMEX steps per pass over f, paired or unpaired lanes;
+// switchable.
 static bool fused_for(const Tiles& t, int n_steps) {
+  (void)t;
   std::lock_guard<std::mutex> lk(g_mu);
-  return g_fuse >= 2 && t.pair && n_steps >= 2;
+  return g_fuse >= 2 && n_steps >= 2;
 }
 
 // Descriptor of B members of one grid advanced with step dt.  ns: sums per
@@ -1485,12 +1488,13 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
     for (int q = 0; q < n; ++q) n_steps_out[q] = steps[q];
   hipStream_t s = (hipStream_t)stream;
   // Tile shape: 4 velocities per lane over 8-cell chunks (or the override).
-  // With two or more steps per pass set, the instances whose rows can be
-  // read in 16-byte pairs (nvz even, aligned f_in and f_out) run fused
-  // two-step passes (group A); the others one step per launch (group B, on
-  // paired lanes only if all of its instances allow it).  Each group is
-  // sorted by step count (descending) so that its active instances at any
-  // step form a prefix; group A comes first in the descriptor table.
+  // With two or more steps per pass set, every instance runs fused two-step
+  // passes: first the instances whose rows can be read in 16-byte pairs
+  // (nvz even, aligned f_in and f_out), then the others on unpaired lanes,
+  // each group with its own tile mapping.  Without fusion all instances take
+  // one step per launch (paired lanes only if every instance allows them).
+  // Within a group the instances are sorted by step count (descending), so
+  // that its active instances at any step form a prefix.
   Tiles t = {4, 8, 1};
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -1503,15 +1507,15 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
     pairable[q] = t.pair == 1 && probs[q].nv[2] % 2 == 0 &&
                   aligned_tiles(t, probs[q], {f_in[q], f_out[q]}).pair == 1;
   const bool fused = fuse_mode() >= 2;
-  auto in_a = [&](int q) { return fused && pairable[q]; };
+  auto first_group = [&](int q) { return fused && pairable[q]; };
   std::vector<int> order(n);
   for (int q = 0; q < n; ++q) order[q] = q;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    if (in_a(x) != in_a(y)) return in_a(x);
+    if (first_group(x) != first_group(y)) return first_group(x);
     return steps[x] > steps[y];
   });
   int nA = 0;
-  while (nA < n && in_a(order[nA])) ++nA;
+  while (nA < n && first_group(order[nA])) ++nA;
   Tiles tA = t, tB = t;
   for (int k = nA; k < n; ++k)
     if (!pairable[order[k]]) tB.pair = 0;
@@ -1522,7 +1526,7 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   for (int k = 0; k < n; ++k) {
     const int q = order[k];
     // fused passes need the nu-weighted partial sums (15 per record)
-    Inst I = k < nA ? make_inst(probs[q], 1, dts[q], tA, 15) : make_inst(probs[q], 1, dts[q], tB);
+    Inst I = make_inst(probs[q], 1, dts[q], k < nA ? tA : tB, fused ? 15 : 5);
     attach_fine(I, ws, L.regions[q], f_out[q]);
     I.fin = f_in[q];
     I.fout = f_out[q];
@@ -1541,106 +1545,112 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
     for (int k = a; k < b; ++k) c += (double)h[k].nx * h[k].nv3;
     return c;
   };
-  // Group B, entries [nA, n): one step per launch over the instances still
-  // stepping (a launch over entries [a, b) takes the table from entry a).
-  auto sequence_b = [&](hipStream_t q) -> int {
+  // Entries [a0, a1) one step per launch over the instances still stepping
+  // (a launch over entries [a, b) takes the table from entry a).
+  auto single_steps = [&](int a0, int a1, Tiles tt, int nvs_m, hipStream_t q) -> int {
     int r;
-    if (nA == n) return BGK_OK;
-    const int smax = h[nA].steps;
+    if (a0 == a1) return BGK_OK;
+    const int smax = h[a0].steps;
     int w_prev = 1;
     for (int k = 1; k <= smax; ++k) {
-      int e = nA;
-      while (e < n && h[e].steps >= k) ++e;
+      int e = a0;
+      while (e < a1 && h[e].steps >= k) ++e;
       const int mode = (k == 1) ? kCopy : kRelax;
       const int phase = w_prev;
       prof_before(q);
-      r = launch_step(dI + nA, e - nA, items_prefix[e] - items_prefix[nA], mode, phase, tB,
-                      (tB.chunk + 2) * nvs_b, st, q);
-      prof_after(q, cells_of(nA, e), 16.0, BGK_PROF_ONE_STEP);
+      r = launch_step(dI + a0, e - a0, items_prefix[e] - items_prefix[a0], mode, phase, tt,
+                      (tt.chunk + 2) * nvs_m, st, q);
+      prof_after(q, cells_of(a0, e), 16.0, BGK_PROF_ONE_STEP);
       if (r) return r;
-      if ((r = launch_reduce(dI + nA, e - nA, cells_prefix[e] - cells_prefix[nA],
+      if ((r = launch_reduce(dI + a0, e - a0, cells_prefix[e] - cells_prefix[a0],
                              kRedRelaxFactors, 0, st, q)))
         return r;
       w_prev = phase ^ 1;
     }
     // final relaxation, each instance from the buffer its last step wrote:
     // step k writes buf[(k - 1) & 1]
-    for (int k = nA; k < n; ++k) {
+    for (int k = a0; k < a1; ++k) {
       const int sel = (h[k].steps - 1) & 1;
       if ((r = launch_relax_out_blocks(dI + k, 1, relax_out_blocks(h[k]), h[k].nvs, sel, q)))
         return r;
     }
     return BGK_OK;
   };
-  // Group A, entries [0, nA): every instance's first step alone (from f_in),
+  // Entries [a0, a1) fused: every instance's first step alone (from f_in),
   // then in each round the instances with two or more steps left (a prefix)
   // take one two-step pass and those with one left (the next entries) one
   // step, so all active instances stay in the same buffer phase.
-  auto sequence_a = [&](hipStream_t q) -> int {
+  auto fused_steps = [&](int a0, int a1, Tiles tt, int nvs_m, hipStream_t q) -> int {
     int r;
-    if (nA == 0) return BGK_OK;
-    std::vector<int> rem(nA), sel(nA, 0);
-    for (int k = 0; k < nA; ++k) rem[k] = h[k].steps;
-    auto prefix = [&](int m) {
-      int c = 0;
-      while (c < nA && rem[c] >= m) ++c;
+    if (a0 == a1) return BGK_OK;
+    std::vector<int> rem(a1 - a0), sel(a1 - a0, 0);
+    for (int k = a0; k < a1; ++k) rem[k - a0] = h[k].steps;
+    auto prefix_end = [&](int m) {
+      int c = a0;
+      while (c < a1 && rem[c - a0] >= m) ++c;
       return c;
     };
     int phase = 1;  // a pass reads buf[phase] (f_in in copy mode), writes buf[phase ^ 1]
     auto advance = [&](int a, int b, int by) {
       for (int k = a; k < b; ++k) {
-        rem[k] -= by;
-        if (rem[k] == 0) sel[k] = phase ^ 1;
+        rem[k - a0] -= by;
+        if (rem[k - a0] == 0) sel[k - a0] = phase ^ 1;
       }
     };
+    auto span_items = [&](int a, int b) { return items_prefix[b] - items_prefix[a]; };
+    auto span_cells = [&](int a, int b) { return cells_prefix[b] - cells_prefix[a]; };
     prof_before(q);
-    r = launch_step(dI, nA, items_prefix[nA], kCopy, phase, tA, (tA.chunk + 2) * nvs_a, st, q,
-                    15);
-    prof_after(q, cells_of(0, nA), 16.0, BGK_PROF_ONE_STEP);
+    r = launch_step(dI + a0, a1 - a0, span_items(a0, a1), kCopy, phase, tt,
+                    (tt.chunk + 2) * nvs_m, st, q, 15);
+    prof_after(q, cells_of(a0, a1), 16.0, BGK_PROF_ONE_STEP);
     if (r) return r;
-    advance(0, nA, 1);
+    advance(a0, a1, 1);
     phase ^= 1;
     for (;;) {
-      const int n1 = prefix(1), n2 = prefix(2);
-      if (n1 == 0) break;
-      if (n2 > 0) {
-        if ((r = launch_reduce(dI, n2, cells_prefix[n2], kRedW1, 0, st, q))) return r;
-        if ((r = launch_reduce(dI, n2, cells_prefix[n2], kRedW2, 0, st, q))) return r;
+      const int e1 = prefix_end(1), e2 = prefix_end(2);
+      if (e1 == a0) break;
+      if (e2 > a0) {
+        if ((r = launch_reduce(dI + a0, e2 - a0, span_cells(a0, e2), kRedW1, 0, st, q)))
+          return r;
+        if ((r = launch_reduce(dI + a0, e2 - a0, span_cells(a0, e2), kRedW2, 0, st, q)))
+          return r;
       }
-      if (n1 > n2 &&
-          (r = launch_reduce(dI + n2, n1 - n2, cells_prefix[n1] - cells_prefix[n2],
-                             kRedRelaxFactors, 0, st, q)))
+      if (e1 > e2 && (r = launch_reduce(dI + e2, e1 - e2, span_cells(e2, e1),
+                                        kRedRelaxFactors, 0, st, q)))
         return r;
-      if (n2 > 0) {
+      if (e2 > a0) {
         prof_before(q);
-        r = launch_step2x2(dI, n2, items_prefix[n2], kRelax, phase, tA,
-                           (2 * tA.chunk + 6) * nvs_a, false, q);
-        prof_after(q, 2.0 * cells_of(0, n2), 8.0, BGK_PROF_TWO_STEP);
+        r = launch_step2x2(dI + a0, e2 - a0, span_items(a0, e2), kRelax, phase, tt,
+                           (2 * tt.chunk + 6) * nvs_m, false, q);
+        prof_after(q, 2.0 * cells_of(a0, e2), 8.0, BGK_PROF_TWO_STEP);
         if (r) return r;
       }
-      if (n1 > n2) {
+      if (e1 > e2) {
         prof_before(q);
-        r = launch_step(dI + n2, n1 - n2, items_prefix[n1] - items_prefix[n2], kRelax, phase,
-                        tA, (tA.chunk + 2) * nvs_a, st, q, 15);
-        prof_after(q, cells_of(n2, n1), 16.0, BGK_PROF_ONE_STEP);
+        r = launch_step(dI + e2, e1 - e2, span_items(e2, e1), kRelax, phase, tt,
+                        (tt.chunk + 2) * nvs_m, st, q, 15);
+        prof_after(q, cells_of(e2, e1), 16.0, BGK_PROF_ONE_STEP);
         if (r) return r;
       }
-      advance(0, n2, 2);
-      advance(n2, n1, 1);
+      advance(a0, e2, 2);
+      advance(e2, e1, 1);
       phase ^= 1;
     }
     // factors of every instance's last field, then its relaxed output
-    if ((r = launch_reduce(dI, nA, cells_prefix[nA], kRedRelaxFactors, 0, st, q))) return r;
-    for (int k = 0; k < nA; ++k)
-      if ((r = launch_relax_out_blocks(dI + k, 1, relax_out_blocks(h[k]), h[k].nvs, sel[k], q)))
+    if ((r = launch_reduce(dI + a0, a1 - a0, span_cells(a0, a1), kRedRelaxFactors, 0, st, q)))
+      return r;
+    for (int k = a0; k < a1; ++k)
+      if ((r = launch_relax_out_blocks(dI + k, 1, relax_out_blocks(h[k]), h[k].nvs,
+                                       sel[k - a0], q)))
         return r;
     return BGK_OK;
   };
   auto sequence = [&](hipStream_t q) -> int {
     int r;
     if ((r = put_insts(dI, h.data(), n, q))) return r;
-    if ((r = sequence_a(q))) return r;
-    return sequence_b(q);
+    if (!fused) return single_steps(0, n, tB, nvs_b, q);
+    if ((r = fused_steps(0, nA, tA, nvs_a, q))) return r;
+    return fused_steps(nA, n, tB, nvs_b, q);
   };
   // the whole sequence is captured once per (workspace, problems, buffers,
   // spans, tiles, fusion) and replayed

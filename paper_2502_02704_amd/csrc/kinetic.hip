@@ -378,7 +378,9 @@ __device__ __forceinline__ double flux2(double vx, double anu, double fm, double
   return vx * (up + c * vl_limited(d1, fp - f0));
 }
 
-template <int E, int MODE, bool FORCE = false, bool LIMITED = false>
+// NS = 15: the records also carry the nu+ and nu- weighted sums (fused
+// passes on grids without paired rows; plain step only).
+template <int E, int MODE, bool FORCE = false, bool LIMITED = false, int NS = 5>
 __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
                                                  int n_inst, int chunk,
                                                  int phase) {
@@ -485,7 +487,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
     for (int e = 0; e < E; ++e)
       fcar[e] = flux2(el.vx[e], fabs(nu[e]), w[0][e], w[1][e], w[2][e], w[3 < 2 * H ? 3 : 0][e]);
   }
-  gptr<double> part = gmem(I.part) + (((long long)b * nx) * I.part_tiles + tile) * 5;
+  static_assert(NS == 5 || (NS == 15 && !FORCE && !LIMITED), "weighted sums: plain step");
+  gptr<double> part = gmem(I.part) + ((long long)b * nx) * I.part_tiles * 5 + (long long)tile * NS;
   for (int i = i0; i < i1; ++i) {
     if (i + 2 <= i1) load_row(i + H + 1, rawn);  // prefetch the next row
     if (FORCE && i + 1 < i1) load_vnb(i + 1, dn_nxt, up_nxt);
@@ -493,6 +496,9 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
     double Ei = 0.0;
     if (FORCE) Ei = gmem(I.efield)[i];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+    double sw[NS == 15 ? 10 : 1];
+#pragma unroll
+    for (int c = 0; c < (NS == 15 ? 10 : 1); ++c) sw[c] = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       double gs;
@@ -527,12 +533,32 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
       s2 = fma(el.vy[e], gs, s2);
       s3 = fma(el.vz[e], gs, s3);
       s4 = fma(vsq, gs, s4);
+      if (NS == 15) {
+        const double cp = nu[e] > 0.0 ? nu[e] : 0.0, cm = nu[e] < 0.0 ? -nu[e] : 0.0;
+        const double m[5] = {gs, el.vx[e] * gs, el.vy[e] * gs, el.vz[e] * gs, vsq * gs};
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          sw[c] = fma(cp, m[c], sw[c]);
+          sw[5 + c] = fma(cm, m[c], sw[5 + c]);
+        }
+      }
     }
-    // the wave's five sums by reduce-scatter: lanes 0..7 hold the totals
-    double t8[8] = {s0, s1, s2, s3, s4, 0.0, 0.0, 0.0};
-    const double tot = wave_reduce_scatter<8>(t8, lane);
-    const int slot = slot_of_lane<8>(lane);
-    if (lane < 8 && slot < 5) part[(long long)i * I.part_tiles * 5 + slot] = tot;
+    if (NS == 15) {
+      // the fifteen sums by reduce-scatter: lanes 0..15 hold the totals
+      double t16[16] = {s0, s1, s2, s3, s4};
+#pragma unroll
+      for (int c = 0; c < 10; ++c) t16[5 + c] = sw[c];
+      t16[15] = 0.0;
+      const double tot = wave_reduce_scatter<16>(t16, lane);
+      const int slot = slot_of_lane<16>(lane);
+      if (lane < 16 && slot < 15) part[(long long)i * I.part_tiles * 5 + slot] = tot;
+    } else {
+      // the wave's five sums by reduce-scatter: lanes 0..7 hold the totals
+      double t8[8] = {s0, s1, s2, s3, s4, 0.0, 0.0, 0.0};
+      const double tot = wave_reduce_scatter<8>(t8, lane);
+      const int slot = slot_of_lane<8>(lane);
+      if (lane < 8 && slot < 5) part[(long long)i * I.part_tiles * 5 + slot] = tot;
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
 #pragma unroll
@@ -1265,6 +1291,141 @@ __global__ __launch_bounds__(kBlock) void k_step2x2(const Inst* __restrict__ ins
     BGK_MARCH_DISPATCH_UNI(Call, I, lds1, lds2, b, tile, lane, i0, i1, phase, vxu, nuu);
   else
     BGK_MARCH_DISPATCH(Call, I, lds1, lds2, b, tile, lane, i0, i1, phase, vxu, nuu);
+}
+
+// ------------------------------- two steps per pass, unpaired lanes --
+// The two-step pass for grids whose rows cannot be read in 16-byte pairs
+// (odd nv_z): E velocities per lane at stride 64 (flat index tile * 64 E +
+// e * 64 + lane, one 8-byte access each), as in the one-step kernel.  Same
+// levels as the paired march: level 1 at rows k .. k+2 from the factors
+// fac, level 2 at rows k-1 .. k+1 from fac2, output row k; every velocity
+// has its own v_x, nu and factors.  Records: the fifteen sums per wave.
+template <int E, int MODE, int DIR>
+__device__ __forceinline__ void step2x2_flat_march(const Inst& I, const double* lds1,
+                                                   const double* lds2, int b, int tile,
+                                                   int lane, int i0, int i1, int phase) {
+  const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
+  Elems<E> el;
+  setup_elems<E>(I, tile, lane, el);
+  double nu[E], q[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    nu[e] = el.vx[e] * I.r;
+    q[e] = el.vx[e] * el.vx[e] + el.vy[e] * el.vy[e] + el.vz[e] * el.vz[e];
+  }
+  const long long mbase = (long long)b * nx * nv3 + (long long)tile * (kWave * E) + lane;
+  gptr<const double> src = gmem(I.buf[phase]) + mbase;
+  gptr<double> dst = gmem(I.buf[phase ^ 1]) + mbase;
+  const double a = I.a;
+  const bool neumann = I.bc == 0;
+  const int len = i1 - i0;
+  auto row_at = [&](int k) { return DIR > 0 ? i0 + k : i1 - 1 - k; };
+  auto outside = [&](int r) { return r < 0 || r >= nx; };
+  auto load_row = [&](int r, double (&raw)[E]) {
+    if (MODE == kLift) return;
+    gptr<const double> row = src + (long long)ghost_row(r, nx, I.bc) * nv3;
+#pragma unroll
+    for (int e = 0; e < E; ++e) raw[e] = el.ok[e] ? row[e * kWave] : 0.0;
+  };
+  // upwind transport of one velocity: centre c, neighbours behind (march
+  // position k-1) and ahead (k+1); the upwind cell is x-1 for v_x > 0
+  auto transport = [&](int e, double bh, double c, double ah) {
+    const double nb = ((nu[e] > 0.0) == (DIR > 0)) ? bh : ah;
+    return fma(fabs(nu[e]), nb - c, c);
+  };
+  // level 1: rows i0-2 .. i1+1 staged in lds1; level 2: rows i0-1 .. i1 in lds2
+  auto relax1 = [&](int r, const double (&raw)[E], double (&out)[E]) {
+    const double* fr = lds1 + (r - (i0 - 2)) * nvs;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double m = fac3(fr, el.off[e]);
+      const double v = MODE == kRelax ? fma(a, raw[e], m) : m;
+      out[e] = el.ok[e] ? v : 0.0;
+    }
+  };
+  auto level2 = [&](int r, const double (&b1)[E], const double (&c1)[E],
+                    const double (&a1)[E], double (&out)[E]) {
+    const double* fr = lds2 + (r - (i0 - 1)) * nvs;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double v = fma(a, transport(e, b1[e], c1[e], a1[e]), fac3(fr, el.off[e]));
+      out[e] = el.ok[e] ? v : 0.0;
+    }
+  };
+  auto copy = [&](double (&d)[E], const double (&s)[E]) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) d[e] = s[e];
+  };
+
+  double f1b[E], f1c[E], f1a[E];  // level 1 at positions k, k+1, k+2
+  double f2b[E], f2c[E], f2a[E];  // level 2 at positions k-1, k, k+1
+  double rcur[E];                 // raw row k+2; refilled with k+3 once used
+  {
+    double ra[E], rb[E], l0[E], l1[E];
+    load_row(row_at(-2), ra);
+    load_row(row_at(-1), rb);
+    relax1(row_at(-2), ra, l0);       // level 1 at -2
+    load_row(row_at(0), ra);
+    relax1(row_at(-1), rb, l1);       // level 1 at -1
+    load_row(row_at(1), rb);
+    relax1(row_at(0), ra, f1b);       // level 1 at 0
+    load_row(row_at(2), rcur);
+    relax1(row_at(1), rb, f1c);       // level 1 at 1
+    level2(row_at(-1), l0, l1, f1b, f2b);  // level 2 at -1
+    level2(row_at(0), l1, f1b, f1c, f2c);  // level 2 at 0
+    if (neumann && outside(row_at(-1))) copy(f2b, f2c);
+  }
+  for (int k = 0; k < len; ++k) {
+    relax1(row_at(k + 2), rcur, f1a);
+    if (k + 3 <= len + 1) load_row(row_at(k + 3), rcur);  // in flight during the rest
+    level2(row_at(k + 1), f1b, f1c, f1a, f2a);
+    if (neumann && outside(row_at(k + 1))) copy(f2a, f2c);
+    const int r = row_at(k);
+    Acc<15, false> acc;
+    acc.zero();
+    gptr<double> drow = dst + (long long)r * nv3;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double g = transport(e, f2b[e], f2c[e], f2a[e]);
+      if (el.ok[e]) __builtin_nontemporal_store(g, drow + e * kWave);
+      // one velocity: the pair accumulation with a zero second member
+      acc.add(make_double2(g, 0.0), el.vx[e], el.vy[e], el.vz[e], 0.0, q[e], 0.0, nu[e]);
+    }
+    acc.store(I, b, r, tile, lane, 0.0, 0.0);
+    copy(f1b, f1c);
+    copy(f1c, f1a);
+    copy(f2b, f2c);
+    copy(f2c, f2a);
+  }
+}
+
+template <int E, int MODE>
+__global__ __launch_bounds__(kBlock) void k_step2x2_flat(const Inst* __restrict__ insts,
+                                                         int n_inst, int chunk, int phase) {
+  extern __shared__ double lds[];
+  const long long item = xcd_item(blockIdx.x, gridDim.x) + insts[0].item_begin;
+  const int q = find_inst(insts, n_inst, item);
+  const Inst& I = insts[q];
+  const long long local = item - I.item_begin;
+  int b, tg, c;
+  decode_item(I, local, b, tg, c);
+  const int i0 = c * chunk;
+  const int i1 = min(i0 + chunk, I.nx);
+  const int len = i1 - i0;
+  double* lds1 = lds;
+  double* lds2 = lds + (len + 4) * I.nvs;
+  stage_rows(I, I.fac, b, i0 - 2, len + 4, lds1);
+  stage_rows(I, I.fac2, b, i0 - 1, len + 2, lds2);
+  __syncthreads();
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int tile = tg * kWavesPerBlock + wave;
+  if (tile >= I.ntiles) return;
+  // neighbouring chunks march in opposite directions (shared halo rows)
+  if (c & 1)
+    step2x2_flat_march<E, MODE, -1>(I, lds1, lds2, b, tile, lane, i0, i1, phase);
+  else
+    step2x2_flat_march<E, MODE, 1>(I, lds1, lds2, b, tile, lane, i0, i1, phase);
 }
 
 // ---------------------------------------------- three steps in one pass --
@@ -2031,6 +2192,16 @@ int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode
     BGK_STEP_CASE((k_step2<4, kCopy, 5>), 8, kCopy)
     BGK_STEP_CASE((k_step2<4, kRelax, 5>), 8, kRelax)
     BGK_STEP_CASE((k_step2<4, kLift, 5>), 8, kLift)
+  } else if (ns == 15) {
+    BGK_STEP_CASE((k_step<2, kCopy, false, false, 15>), 2, kCopy)
+    BGK_STEP_CASE((k_step<2, kRelax, false, false, 15>), 2, kRelax)
+    BGK_STEP_CASE((k_step<2, kLift, false, false, 15>), 2, kLift)
+    BGK_STEP_CASE((k_step<4, kCopy, false, false, 15>), 4, kCopy)
+    BGK_STEP_CASE((k_step<4, kRelax, false, false, 15>), 4, kRelax)
+    BGK_STEP_CASE((k_step<4, kLift, false, false, 15>), 4, kLift)
+    BGK_STEP_CASE((k_step<8, kCopy, false, false, 15>), 8, kCopy)
+    BGK_STEP_CASE((k_step<8, kRelax, false, false, 15>), 8, kRelax)
+    BGK_STEP_CASE((k_step<8, kLift, false, false, 15>), 8, kLift)
   } else {
     BGK_STEP_CASE((k_step<2, kCopy>), 2, kCopy)
     BGK_STEP_CASE((k_step<2, kRelax>), 2, kRelax)
@@ -2049,13 +2220,19 @@ int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode
 int launch_step2x2(const Inst* d_insts, int n_inst, long long total_items, int mode,
                    int phase, Tiles t, int lds_doubles, bool uni_only, hipStream_t s) {
   if (total_items <= 0) return BGK_OK;
-  if (!t.pair) {
-    set_error("two-step passes need the paired lane mapping");
-    return BGK_E_INVALID;
-  }
   dim3 grid(blocks_for(total_items)), block(kBlock);
   size_t lds = (size_t)lds_doubles * sizeof(double);
   const int chunk = t.chunk;
+  if (!t.pair) {
+    BGK_STEP_CASE((k_step2x2_flat<2, kRelax>), 2, kRelax)
+    BGK_STEP_CASE((k_step2x2_flat<2, kLift>), 2, kLift)
+    BGK_STEP_CASE((k_step2x2_flat<4, kRelax>), 4, kRelax)
+    BGK_STEP_CASE((k_step2x2_flat<4, kLift>), 4, kLift)
+    BGK_STEP_CASE((k_step2x2_flat<8, kRelax>), 8, kRelax)
+    BGK_STEP_CASE((k_step2x2_flat<8, kLift>), 8, kLift)
+    set_error("unsupported tile shape");
+    return BGK_E_INVALID;
+  }
   if (uni_only) {
     BGK_STEP_CASE((k_step2x2<1, kRelax, true>), 2, kRelax)
     BGK_STEP_CASE((k_step2x2<1, kLift, true>), 2, kLift)
