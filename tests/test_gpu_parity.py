@@ -293,9 +293,9 @@ def test_fine_step_batched_uneven_two_step_passes():
     pass over the instances with two or more steps left and one step for
     those with one left.  Step counts 1, 2, 3, 4 and 7 (odd and even), both
     boundary conditions, one grid whose v_x planes are whole tiles (compact
-    records); two instances with odd nvz (no paired rows) take one step per
-    launch in the same call.  Against the oracle, and against one step per
-    pass."""
+    records); two instances with odd nvz (no paired rows) run the same
+    schedule on unpaired lanes in the same call.  Against the oracle, and
+    against one step per pass."""
     probs = [
         wl.Problem(nx=9, nv=(6, 4, 8), v_lo=(-5,) * 3, v_hi=(5,) * 3, bc=wl.BC_NEUMANN,
                    eps=1e-2),
