@@ -358,9 +358,11 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws,
  * 3 (default) runs triples (16/3 bytes per update; the third step's moments need the
  * sums weighted by max(nu,0)^2 and max(-nu,0)^2 too) where every velocity tile
  * lies in one v_x plane (nv[1] nv[2] a multiple of 64 times the velocities
- * per lane) and nx >= 3, else pairs; 1 runs one step per pass.  Applies where
- * the paired lane mapping is used (even nv[2], 16-byte aligned f); the
- * uneven batch (bgk_fine_step_batched) always runs one step per pass. */
+ * per lane), nx >= 3 and the paired lane mapping is used (even nv[2],
+ * 16-byte aligned f), else pairs (paired or unpaired lanes); 1 runs one step
+ * per pass.  The exterior-force step and the second-order transport always
+ * run one step per pass; the uneven batch (bgk_fine_step_batched) runs pairs
+ * under 2 and 3. */
 int bgk_set_step_fusion(int32_t steps_per_pass);
 
 /* Launch-bound sequences (each parareal iteration, the serial chain of
