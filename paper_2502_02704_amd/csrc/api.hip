@@ -513,9 +513,14 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
       done += 3;
       return r;
     };
+    // When only the projected moments leave the call, a last single step is
+    // not written out: its moments follow from the weighted sums of the
+    // field before it (linearity of the transport, reductions kRedW1 and
+    // kRedW2Project).  Then n = 1 mod 3 starts with three steps from the lift.
+    const bool last_on_moments = project_last && first_mode == kLift && n >= 4 && n % 3 == 1;
     // the first pass starts from the lift (write-only) or the copy: n mod 3
     // decides whether it takes three, two or one step
-    if (first_mode == kLift && n >= 3 && n % 3 == 0) {
+    if (first_mode == kLift && n >= 3 && (n % 3 == 0 || last_on_moments)) {
       if ((rc = reduce(kRedW2x3))) return rc;
       if ((rc = reduce(kRedW3x3))) return rc;
       if ((rc = triple_pass(kLift))) return rc;
@@ -537,6 +542,12 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
       if ((rc = reduce(kRedW3x3))) return rc;
       if ((rc = triple_pass(kRelax))) return rc;
     }
+    if (n - done == 1 && last_on_moments) {
+      if ((rc = reduce(kRedW1))) return rc;
+      if ((rc = reduce(kRedW2Project))) return rc;
+      *last_sel = phase;  // the last field written (the call returns moments only)
+      return BGK_OK;
+    }
     if (n - done == 1) {
       if ((rc = reduce(kRedRelaxFactors))) return rc;
       if ((rc = single(kRelax))) return rc;
@@ -548,7 +559,10 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
   }
   // An odd step count takes its single step first, from the lift: that pass
   // only writes f (8 bytes per update instead of the 16 of a later single).
-  if (first_mode == kLift && n >= 2 && n % 2 == 0) {
+  // When only the projected moments leave the call, the odd step is the last
+  // one instead, not written out (its moments from the weighted sums).
+  const bool last_on_moments = project_last && first_mode == kLift && n >= 3 && n % 2 == 1;
+  if (first_mode == kLift && n >= 2 && (n % 2 == 0 || last_on_moments)) {
     if ((rc = reduce(kRedW2))) return rc;
     if ((rc = pair_pass(kLift))) return rc;
   } else {
@@ -559,6 +573,12 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
     if ((rc = reduce(kRedW1))) return rc;
     if ((rc = reduce(kRedW2))) return rc;
     if ((rc = pair_pass(kRelax))) return rc;
+  }
+  if (n - done == 1 && last_on_moments) {
+    if ((rc = reduce(kRedW1))) return rc;
+    if ((rc = reduce(kRedW2Project))) return rc;
+    *last_sel = phase;  // the last field written (the call returns moments only)
+    return BGK_OK;
   }
   if (n - done == 1) {
     if ((rc = reduce(kRedRelaxFactors))) return rc;

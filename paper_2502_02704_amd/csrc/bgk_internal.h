@@ -85,6 +85,9 @@ enum ReduceMode : int {
   kRedW2x3 = 7,            // kRedW2 -> fac2, and the weighted sums of the
                            // second-step fields into aux2
   kRedW3x3 = 8,            // kRedW2 on aux2 -> third-step factors fac3
+  kRedW2Project = 9,       // kRedW2's moments of the next field, projected:
+                           // vout = a V + al V(M[U]) (a last step that is not
+                           // written out)
 };
 
 // aux layout per x cell (conserved-moment units, 5 values each):

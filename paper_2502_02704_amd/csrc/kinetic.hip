@@ -1796,7 +1796,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
   long long cl;
   const int q = find_inst_cell(insts, n_inst, cell, &cl);
   const Inst& I = insts[q];
-  if (mode == kRedW2 || mode == kRedW2x3 || mode == kRedW3x3) {
+  if (mode == kRedW2 || mode == kRedW2x3 || mode == kRedW3x3 || mode == kRedW2Project) {
     // moments of the next transported field T(a g + al M[U(g)]) at this cell
     // from the weighted sums of g and M at cells i-1, i, i+1 (upwind
     // transport: T h_i = (1 - nu+ - nu-) h_i + nu+ h_{i-1} + nu- h_{i+1})
@@ -1835,6 +1835,18 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
     cons_to_prim(V, rho, u, th);
     if (lane == 0 && !physical(rho, th)) *status = 1;
     const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
+    if (mode == kRedW2Project) {
+      // the next field's relaxation, projected (as kRedProject does from
+      // records): P f = a V(g) + al V(M[U(g)])
+      double A[15];
+      maxwell_weighted_sums<3>(I, lane, u, th, C0 * I.dv3, A);
+      if (lane == 0) {
+        double* vo = I.vout + cl * 5;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) vo[c] = I.a * V[c] + I.al * A[c];
+      }
+      return;
+    }
     double* fout = (mode == kRedW3x3 ? I.fac3 : I.fac2) + cl * I.nvs;
     if (mode != kRedW2x3) write_factors(I, fout, lane, I.al * C0, u, th);
     if (mode == kRedW2x3) {
@@ -2329,6 +2341,7 @@ int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
     BGK_REDUCE_CASE(kRedW1x3)
     BGK_REDUCE_CASE(kRedW2x3)
     BGK_REDUCE_CASE(kRedW3x3)
+    BGK_REDUCE_CASE(kRedW2Project)
 #undef BGK_REDUCE_CASE
     default:
       set_error("unknown reduction mode");

@@ -107,6 +107,31 @@ def test_three_steps_from_lift(name, span_steps):
             assert rel_V(got[b], oracle.fine_propagate_moments(p, Vin[b], span)) < TOL, tiles
 
 
+@pytest.mark.parametrize("span_steps", [3, 4, 5, 7, 10])
+@pytest.mark.parametrize("name", ["uni_periodic", "uni_neumann", "sod_nx64_nv16"])
+def test_last_step_on_moments(name, span_steps):
+    """Propagation returns projected moments only, so a last single step is
+    not written out (three steps per pass with n = 1 mod 3, two with n odd):
+    its moments follow from the weighted sums of the field before it.
+    Against the oracle (every step on f) and against one step per pass."""
+    p = UNI_GRIDS[name]
+    dv = (p.v_hi[0] - p.v_lo[0]) / p.nv[0]
+    vmax = max(abs(p.v_lo[0] + 0.5 * dv), abs(p.v_hi[0] - 0.5 * dv))
+    span = (span_steps - 0.5) * p.cfl * ((p.x_hi - p.x_lo) / p.nx) / vmax
+    n, _ = oracle.n_steps(p, span)
+    assert n == span_steps
+    Vin = np.stack([conserved(states(p, 330 + b)[0]) for b in range(2)])
+    bgk.set_step_fusion(1)
+    single = bgk.fine_propagate_moments(p, cuda(Vin), span).cpu().numpy()
+    for fuse in (3, 2):
+        bgk.set_step_fusion(fuse)
+        got = bgk.fine_propagate_moments(p, cuda(Vin), span).cpu().numpy()
+        bgk.check_status()
+        for b in range(2):
+            assert rel_V(got[b], oracle.fine_propagate_moments(p, Vin[b], span)) < TOL, fuse
+            assert rel_V(got[b], single[b]) < 1e-13, fuse
+
+
 def test_non_uniform_tiles_fall_back_to_pairs():
     """Grids whose tiles straddle v_x planes run fused pairs under the
     three-step setting: same results as with pairs."""
