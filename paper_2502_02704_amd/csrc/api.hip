@@ -513,14 +513,20 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
       done += 3;
       return r;
     };
-    // When only the projected moments leave the call, a last single step is
-    // not written out: its moments follow from the weighted sums of the
-    // field before it (linearity of the transport, reductions kRedW1 and
-    // kRedW2Project).  Then n = 1 mod 3 starts with three steps from the lift.
-    const bool last_on_moments = project_last && first_mode == kLift && n >= 4 && n % 3 == 1;
+    // When only the projected moments leave the call, the last one or two
+    // steps are not written out: their moments follow from the weighted sums
+    // of the last stored field (linearity of the transport; the reductions
+    // before a three-step pass give the moments of the next two fields).
+    // Then the first pass takes two steps from the lift (cheaper than three),
+    // three-step passes follow, and virt = (n - 2) mod 3 steps close on the
+    // moments.
+    const int virt = (project_last && first_mode == kLift && n >= 4) ? (n - 2) % 3 : 0;
     // the first pass starts from the lift (write-only) or the copy: n mod 3
     // decides whether it takes three, two or one step
-    if (first_mode == kLift && n >= 3 && (n % 3 == 0 || last_on_moments)) {
+    if (virt) {
+      if ((rc = reduce(kRedW2))) return rc;
+      if ((rc = pair_pass(kLift))) return rc;
+    } else if (first_mode == kLift && n >= 3 && n % 3 == 0) {
       if ((rc = reduce(kRedW2x3))) return rc;
       if ((rc = reduce(kRedW3x3))) return rc;
       if ((rc = triple_pass(kLift))) return rc;
@@ -531,21 +537,28 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
       if ((rc = single(first_mode))) return rc;
       done = 1;
     }
-    if ((n - done) % 3 == 2) {
+    if (!virt && (n - done) % 3 == 2) {
       if ((rc = reduce(kRedW1))) return rc;
       if ((rc = reduce(kRedW2))) return rc;
       if ((rc = pair_pass(kRelax))) return rc;
     }
-    while (n - done >= 3) {
+    while (n - done - virt >= 3) {
       if ((rc = reduce(kRedW1x3))) return rc;
       if ((rc = reduce(kRedW2x3))) return rc;
       if ((rc = reduce(kRedW3x3))) return rc;
       if ((rc = triple_pass(kRelax))) return rc;
     }
-    if (n - done == 1 && last_on_moments) {
+    if (virt == 1) {
       if ((rc = reduce(kRedW1))) return rc;
       if ((rc = reduce(kRedW2Project))) return rc;
       *last_sel = phase;  // the last field written (the call returns moments only)
+      return BGK_OK;
+    }
+    if (virt == 2) {
+      if ((rc = reduce(kRedW1x3))) return rc;
+      if ((rc = reduce(kRedW2x3))) return rc;
+      if ((rc = reduce(kRedW3x3Project))) return rc;
+      *last_sel = phase;
       return BGK_OK;
     }
     if (n - done == 1) {

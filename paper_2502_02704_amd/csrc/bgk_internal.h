@@ -88,6 +88,7 @@ enum ReduceMode : int {
   kRedW2Project = 9,       // kRedW2's moments of the next field, projected:
                            // vout = a V + al V(M[U]) (a last step that is not
                            // written out)
+  kRedW3x3Project = 10,    // the same from aux2: the second of two last steps
 };
 
 // aux layout per x cell (conserved-moment units, 5 values each):

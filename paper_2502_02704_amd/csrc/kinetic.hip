@@ -1796,15 +1796,17 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
   long long cl;
   const int q = find_inst_cell(insts, n_inst, cell, &cl);
   const Inst& I = insts[q];
-  if (mode == kRedW2 || mode == kRedW2x3 || mode == kRedW3x3 || mode == kRedW2Project) {
+  if (mode == kRedW2 || mode == kRedW2x3 || mode == kRedW3x3 || mode == kRedW2Project ||
+      mode == kRedW3x3Project) {
     // moments of the next transported field T(a g + al M[U(g)]) at this cell
     // from the weighted sums of g and M at cells i-1, i, i+1 (upwind
     // transport: T h_i = (1 - nu+ - nu-) h_i + nu+ h_{i-1} + nu- h_{i+1})
     const int nx = I.nx;
     const long long b = cl / nx;
     const int i = (int)(cl - b * nx);
-    gptr<const double> base = gmem(mode == kRedW3x3 ? I.aux2 : I.aux);
-    const int stride = mode == kRedW3x3 ? kAux2 : kAux;
+    const bool second = mode == kRedW3x3 || mode == kRedW3x3Project;  // from aux2
+    gptr<const double> base = gmem(second ? I.aux2 : I.aux);
+    const int stride = second ? kAux2 : kAux;
     gptr<const double> ac = base + cl * stride;
     gptr<const double> am = base + (b * nx + ghost_row(i - 1, nx, I.bc)) * stride;
     gptr<const double> ap = base + (b * nx + ghost_row(i + 1, nx, I.bc)) * stride;
@@ -1835,7 +1837,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
     cons_to_prim(V, rho, u, th);
     if (lane == 0 && !physical(rho, th)) *status = 1;
     const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
-    if (mode == kRedW2Project) {
+    if (mode == kRedW2Project || mode == kRedW3x3Project) {
       // the next field's relaxation, projected (as kRedProject does from
       // records): P f = a V(g) + al V(M[U(g)])
       double A[15];
@@ -2342,6 +2344,7 @@ int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
     BGK_REDUCE_CASE(kRedW2x3)
     BGK_REDUCE_CASE(kRedW3x3)
     BGK_REDUCE_CASE(kRedW2Project)
+    BGK_REDUCE_CASE(kRedW3x3Project)
 #undef BGK_REDUCE_CASE
     default:
       set_error("unknown reduction mode");
