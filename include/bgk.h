@@ -131,8 +131,15 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
 
 /* Steps 5-7 of Algorithm 2 for a batch of slices: V_out[b] =
  * P F L(V_in[b]) over t_span (lift, fine propagation, projection), all
- * members in one launch per step.  [device] V_in, V_out [batch][nx][5]
- * conserved; may not overlap. */
+ * members in one launch per pass.  From the Maxwellian lift (order 0), with
+ * no exterior force and first-order transport, the last one or two steps are
+ * not written out as f: (n - 2) mod 3 of them for n >= 4 under triples
+ * (after a first two-step pass from the lift), one for odd n >= 3 under
+ * pairs.  Their moments, and the projection, follow from moment sums of the
+ * last stored field weighted by 1, max(+-nu,0) and their squares (transport
+ * being linear); V_out equals advancing f through every step to rounding.
+ * The same holds for parareal_iterate and bgk_serial_fine.  [device] V_in,
+ * V_out [batch][nx][5] conserved; may not overlap. */
 int bgk_fine_propagate_moments(const bgk_problem* prob, int32_t batch,
                                const double* V_in, double* V_out, double t_span,
                                void* ws, size_t ws_bytes, void* stream);
