@@ -976,7 +976,6 @@ static int propagate_impl(const bgk_problem* prob, const Force& F, int lift_orde
   int rc = check_problem(prob);
   if (rc) return rc;
   if ((rc = check_lift_order(*prob, lift_order))) return rc;
-  if (rc) return rc;
   if (batch < 1) return invalid("batch must be >= 1");
   if (!V_in || !V_out) return invalid("NULL array");
   const size_t vb = (size_t)batch * prob->nx * 5 * sizeof(double);
@@ -1025,7 +1024,6 @@ static int euler_impl(const bgk_problem* prob, const double* E, bool viscous, in
   int rc = check_problem(prob);
   if (rc) return rc;
   if (viscous && !std::isfinite(prob->eps)) return invalid("the Navier-Stokes model needs a finite eps");
-  if (rc) return rc;
   if (batch < 1) return invalid("batch must be >= 1");
   if (!V_in || !V_out) return invalid("NULL array");
   if (!(t_span > 0.0) || !std::isfinite(t_span)) return invalid("t_span must be > 0");
@@ -1191,7 +1189,6 @@ static int serial_impl(const bgk_problem* prob, const Force& F, int lift_order,
   int rc = check_problem(prob);
   if (rc) return rc;
   if ((rc = check_lift_order(*prob, lift_order))) return rc;
-  if (rc) return rc;
   if (!W0 || !V_out) return invalid("NULL array");
   if (n_slices < 1 || !(T > 0.0) || !std::isfinite(T)) return invalid("bad n_slices or T");
   const double span = T / n_slices;

@@ -116,3 +116,31 @@ def test_options_struct_layout():
     assert ctypes.sizeof(bgk._Options) == 32
     assert [f[0] for f in bgk._Options._fields_] == ["E", "e_max", "coarse", "lift_order",
                                                       "fine_order", "reserved"]
+
+
+def test_empty_and_oversized_batches_rejected():
+    """Batch, slice and instance counts below one (and an uneven batch above
+    its 4096-instance limit) are argument errors, found before any device
+    work; the arrays passed here are never read."""
+    lib = bgk.load_library()
+    c1 = wl.c1_sod_small()
+    ps = ctypes.byref(bgk.problem_struct(c1.problem))
+    buf = (ctypes.c_double * 8)()
+    a, b = ctypes.cast(buf, ctypes.c_void_p), ctypes.cast(ctypes.byref(buf, 32), ctypes.c_void_p)
+    for batch in (0, -3):
+        assert lib.bgk_fine_propagate_moments(ps, batch, a, b, 0.1, None, 0, None) == bgk.E_INVALID
+        assert lib.euler_coarse_step(ps, batch, a, b, 0.1, None, None, 0, None) == bgk.E_INVALID
+    err = (ctypes.c_double * 4)()
+    kd = ctypes.c_int32()
+    assert lib.parareal_iterate(ps, a, 0, 0.1, 2, 0.0, b, err, ctypes.byref(kd), None, 0,
+                                None) == bgk.E_INVALID
+    assert lib.parareal_iterate(ps, a, 4, 0.1, -1, 0.0, b, err, ctypes.byref(kd), None, 0,
+                                None) == bgk.E_INVALID
+    assert lib.bgk_serial_fine(ps, a, 0, 0.1, b, None, 0, None) == bgk.E_INVALID
+    probs = (bgk._Problem * 1)(bgk.problem_struct(c1.problem))
+    ptrs = (ctypes.c_void_p * 1)(a.value)
+    outs = (ctypes.c_void_p * 1)(b.value)
+    spans = (ctypes.c_double * 1)(0.1)
+    for n in (0, 4097):
+        assert lib.bgk_fine_step_batched(probs, n, ptrs, outs, spans, None, None, 0,
+                                         None) == bgk.E_INVALID
