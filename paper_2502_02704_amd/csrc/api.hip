@@ -150,11 +150,15 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
     if (vcol_fits(p, c)) return c;
   }
   if (generic) {
-    // the exterior-force step on the flat mapping, and the second-order
-    // step: 2 velocities per lane keep the extra registers unspilled; the
-    // second-order march amortises its 5-row window over 16-cell chunks
-    // (measured on the 512 x 32^3 x 64-slice batch)
-    t = Tiles{2, limited ? 16 : 8, 0};
+    // the exterior-force step on the flat mapping: 2 velocities per lane
+    // keep the extra registers unspilled.  The second-order step without
+    // force is VALU-bound: 4 velocities per lane (170 VGPRs, no spills)
+    // halve the per-update share of the wave's moment reduction, and
+    // 64-cell chunks amortise its 5-row window (measured on the 512 x 32^3
+    // x 64-slice batch: 3.38 ms per step against 3.80 with 2 per lane over
+    // 16 cells; 2 per lane where a tile of 256 velocities would be short)
+    t = (limited && !force && nv3_of(p) >= 4 * kWave * 4) ? Tiles{4, 64, 0}
+                                                          : Tiles{2, limited ? 16 : 8, 0};
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 512) t.chunk /= 2;
   } else if (it != g_tuned.end()) t = it->second;
   else if (pair && g_fuse >= 2 && cells < (1LL << 24)) {
