@@ -100,3 +100,25 @@ def test_eight_elements_per_lane_runs_as_four():
     got = bgk.fine_steps(p, cuda(f), 1e-3, 2, fine_order=2).cpu().numpy()
     bgk.check_status()
     assert rel_f(got, oracle.fine_steps_opts(p, f, 1e-3, 2, fine_order=2)) < TOL
+
+
+def test_smooth_periodic_full_batch_second_order_sampled():
+    """The benchmark batch (64 slices of 512 x 32^3, 25 steps) with the
+    second-order transport in the launch configuration the bench times (the
+    built-in tiles: four velocities per lane, 64-cell chunks, one step per
+    pass); two sampled members against the oracle."""
+    wk = wl.c2_smooth_periodic(eps=1e-2)
+    p = wk.problem
+    B = wk.n_slices
+    x = p.x_centres()
+    V = np.empty((B, p.nx, 5))
+    for b in range(B):
+        rho = 1 + 0.2 * np.sin(2 * np.pi * (x + b / B))
+        u = 0.1 * np.sin(2 * np.pi * (x + b / B))
+        V[b] = np.column_stack([rho, rho * u, 0 * x, 0 * x, 0.5 * rho * u * u + 1.5 * rho])
+    span = wk.T / wk.n_slices
+    got = bgk.fine_propagate_moments(p, cuda(V), span, fine_order=2).cpu().numpy()
+    bgk.check_status()
+    for b in (0, 41):
+        ref = oracle.fine_propagate_moments_opts(p, V[b], span, fine_order=2)
+        assert rel_V(got[b], ref) < TOL

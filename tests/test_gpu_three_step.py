@@ -203,10 +203,11 @@ def test_parareal_and_serial_with_three_step_passes():
 
 
 def test_smooth_periodic_full_batch_three_steps_sampled():
-    """The benchmark batch (64 slices of 512 x 32^3, 25 steps: one single
-    step from the lift, then eight triples) under three-step passes with the
-    built-in tiles (four velocities per lane, 24-cell chunks: a ragged last
-    chunk of 8 cells); two sampled members against the oracle."""
+    """The benchmark batch (64 slices of 512 x 32^3, 25 steps: a two-step
+    pass from the lift, seven triples, and the last two steps evaluated on
+    their moments) under three-step passes with the built-in tiles (two
+    velocity pairs per lane, 48-cell chunks: a ragged last chunk of 32
+    cells); two sampled members against the oracle."""
     wk = wl.c2_smooth_periodic(eps=1e-2)
     p = wk.problem
     B = wk.n_slices
