@@ -192,3 +192,21 @@ def test_parareal_force_lane_mappings(mapping):
     Vr, _, _ = oracle.parareal_iterate(p, W0, wk.n_slices, wk.T, 2, 0.0, E=wk.E)
     assert kd == 2
     assert rel_V(V.cpu().numpy(), Vr) < TOL
+
+
+def test_two_beam_batched_slices_sampled():
+    """The exterior-force propagation in the launch configuration the bench
+    times: all 20 slices of the two-beam test batched (lift, 21 steps, one
+    per pass on v_x columns, projection) with the built-in tiles; the members
+    differ by a density scale; two sampled members against the oracle."""
+    wk = wl.c6_two_beam_force()
+    p, N = wk.problem, wk.n_slices
+    W = wk.U0()
+    V1 = np.column_stack([W[:, 0], W[:, 0:1] * W[:, 1:4],
+                          0.5 * W[:, 0] * (W[:, 1:4] ** 2).sum(1) + 1.5 * W[:, 0] * W[:, 4]])
+    V = np.stack([V1 * (1.0 + 0.01 * b) for b in range(N)])
+    span = wk.T / N
+    got = bgk.fine_propagate_moments(p, cuda(V), span, E=wk.E).cpu().numpy()
+    bgk.check_status()
+    for b in (0, 13):
+        assert rel_V(got[b], oracle.fine_propagate_moments(p, V[b], span, E=wk.E)) < TOL
