@@ -627,3 +627,27 @@ def test_adjoint_graph_replays_match_eager():
         bgk.fine_steps(GRIDS["wide_periodic"], cuda(f), 1e-3, 2)  # eager work between
         torch.cuda.synchronize()
     bgk.check_status()
+
+
+def test_uneven_batch_bench_configuration_sampled():
+    """The uneven batch as the bench times it: the 29 resolved seeded
+    instances (cold instances 7, 15 and 29 left out) over a span of 0.01
+    (26 to 150 steps each), two-step passes on paired lanes (even nv_z) and
+    unpaired lanes (odd nv_z) in one call; the two cheapest instances of
+    each kind against the oracle."""
+    keep = [q for q in range(32) if q not in (7, 15, 29)]
+    all_insts = wl.c5_uneven()
+    insts = [all_insts[q] for q in keep]
+    probs = [w.problem for w in insts]
+    fs = [bgk.lift(w.problem, cuda(w.W0)) for w in insts]
+    bgk.check_status()
+    span = 0.01
+    outs, steps = bgk.fine_step_batched(probs, fs, [span] * len(insts))
+    bgk.check_status()
+    assert min(steps) >= 26 and max(steps) <= 150
+    for q in (21, 30, 2, 24):   # nv_z 18, 28 (paired lanes); 27, 31 (unpaired)
+        w = all_insts[q]
+        k = keep.index(q)
+        ref, nr = oracle.fine_step(w.problem, oracle.lift(w.problem, w.W0), span)
+        assert steps[k] == nr
+        assert rel_f(outs[k].cpu().numpy(), ref) < TOL, q
