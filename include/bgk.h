@@ -328,6 +328,26 @@ int bgk_lift_adjoint_rho(const bgk_problem* prob, const double* W,
 int bgk_density_adjoint(const bgk_problem* prob, const double* rhobar,
                         double* fbar, void* stream);
 
+/* ---------------------------------------------- allocation-free variant --
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  bgk_fine_propagate_moments (same V_in, V_out, batch, t_span
+ * and results, bitwise) with its workspace in a static device array of
+ * BGK_NOALLOC_SCRATCH_BYTES per device, held from the library's first call
+ * on that device until the process ends.  The call allocates nothing and
+ * records no timing events.  Limit: bgk_workspace_bytes(prob,
+ * BGK_OP_PROPAGATE, batch) <= BGK_NOALLOC_SCRATCH_BYTES (for 64 x 16^3
+ * cells, up to 14 members), else BGK_E_WORKSPACE before anything is enqueued.
+ * status [device] (nullable): after the call's kernels, receives BGK_OK or
+ * BGK_E_NONPHYSICAL for the states this call met (the sticky word is cleared
+ * at the start of every call).  All calls on one device share its array:
+ * calls that overlap in time on one device (different streams, threads or
+ * replays in flight together) race and must be serialised by the caller. */
+#define BGK_NOALLOC_SCRATCH_BYTES (64u << 20)
+int bgk_fine_propagate_moments_noalloc(const bgk_problem* prob, int32_t batch,
+                                       const double* V_in, double* V_out,
+                                       double t_span, int32_t* status, void* stream);
+
 /* Synchronises `stream`, returns and clears the sticky device status in ws:
  * BGK_OK, BGK_E_NONPHYSICAL, or BGK_E_INVALID for an exterior force that
  * exceeds e_max or is not finite. */

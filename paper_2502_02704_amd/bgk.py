@@ -34,6 +34,7 @@ EXPORTS = [
     "parareal_iterate_force", "bgk_serial_fine_force", "euler_coarse_step_cns",
     "parareal_iterate_cns", "bgk_lift_ce", "bgk_fine_propagate_moments_opts",
     "parareal_iterate_opts", "bgk_serial_fine_opts", "bgk_fine_steps_opts",
+    "bgk_fine_propagate_moments_noalloc",
 ]
 
 
@@ -126,6 +127,8 @@ def load_library(path: str = LIB_PATH):
                                             Z, V]),
         "bgk_serial_fine_opts": (C.c_int, [P, C.POINTER(_Options), V, C.c_int32, C.c_double,
                                            V, V, Z, V]),
+        "bgk_fine_propagate_moments_noalloc": (C.c_int, [P, C.c_int32, V, V, C.c_double, V,
+                                                         V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -395,6 +398,29 @@ def fine_propagate_moments(p, V_in: torch.Tensor, t_span: float, E=None,
                                                 _dev(V_in, "V_in"), _dev(out, "V_out"),
                                                 t_span, w.data_ptr(), w.numel(), _stream())
     _check(rc, "bgk_fine_propagate_moments")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # BGK_NOALLOC_SCRATCH_BYTES
+
+
+def fine_propagate_moments_noalloc(p, V_in: torch.Tensor, t_span: float,
+                                   out: torch.Tensor | None = None,
+                                   status: torch.Tensor | None = None) -> torch.Tensor:
+    """bgk_fine_propagate_moments_noalloc: the batched P F L of
+    fine_propagate_moments with the library's static scratch instead of a
+    workspace.  `out` ([B][nx][5]) and `status` (int32 device scalar, receives
+    BGK_OK or BGK_E_NONPHYSICAL) are optional caller-owned outputs."""
+    L = _gpu_lib()
+    V_in = V_in.contiguous()
+    B = V_in.shape[0] if V_in.dim() == 3 else 1
+    out = torch.empty_like(V_in) if out is None else out
+    if status is not None and not (status.is_cuda and status.dtype == torch.int32):
+        raise TypeError("status must be an int32 CUDA tensor")
+    _check(L.bgk_fine_propagate_moments_noalloc(
+        C.byref(problem_struct(p)), B, _dev(V_in, "V_in"), _dev(out, "V_out"), t_span,
+        status.data_ptr() if status is not None else None, _stream()),
+        "bgk_fine_propagate_moments_noalloc")
     return out
 
 

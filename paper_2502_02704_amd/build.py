@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbgk.so")
-SOURCES = ["kinetic.hip", "coarse.hip", "adjoint.hip", "lift.hip", "api.hip"]
+SOURCES = ["kinetic.hip", "coarse.hip", "adjoint.hip", "lift.hip", "api.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -669,16 +669,21 @@ static hipEvent_t prof_event() {
   return e;
 }
 
+// Calls that must not create events (the no-allocation entry point) turn
+// timing off for their own thread.
+static thread_local bool t_prof_off = false;
+void prof_suppress(bool off) { t_prof_off = off; }
+
 void prof_before(hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  if (!g_prof_on) return;
+  if (!g_prof_on || t_prof_off) return;
   g_prof_pending = prof_event();
   if (g_prof_pending) (void)hipEventRecord(g_prof_pending, s);
 }
 
 void prof_after(hipStream_t s, double cells, double bytes_per_cell, int kind) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  if (!g_prof_on || !g_prof_pending) return;
+  if (!g_prof_on || t_prof_off || !g_prof_pending) return;
   hipEvent_t e = prof_event();
   if (!e) return;
   (void)hipEventRecord(e, s);
@@ -1006,6 +1011,21 @@ static int propagate_impl(const bgk_problem* prob, const Force& F, int lift_orde
   int last = 0;
   return run_lifted(dI, I, n, lift_order, *prob, t, st, s, &last);
 }
+
+}  // extern "C"
+
+namespace bgk {
+size_t propagate_ws_bytes(const bgk_problem& p, int batch) {
+  return layout_of(p, BGK_OP_PROPAGATE, batch).total;
+}
+int propagate_plain(const bgk_problem* prob, int32_t batch, const double* V_in,
+                    double* V_out, double t_span, void* ws, size_t ws_bytes,
+                    void* stream) {
+  return propagate_impl(prob, Force{}, 0, batch, V_in, V_out, t_span, ws, ws_bytes, stream);
+}
+}  // namespace bgk
+
+extern "C" {
 
 int bgk_fine_propagate_moments(const bgk_problem* prob, int32_t batch,
                                const double* V_in, double* V_out, double t_span,

@@ -162,6 +162,14 @@ struct WsHeader {
   double scratch[30];
 };
 
+// Workspace bytes of bgk_fine_propagate_moments for `batch` members, and
+// that call itself (no force, Maxwellian lift, first-order transport) on a
+// caller-chosen workspace.  propagate_ws_bytes expects a checked problem.
+size_t propagate_ws_bytes(const bgk_problem& p, int batch);
+int propagate_plain(const bgk_problem* prob, int32_t batch, const double* V_in,
+                    double* V_out, double t_span, void* ws, size_t ws_bytes,
+                    void* stream);
+
 // ------------------------------------------------------------ launchers --
 struct Tiles {
   int elems;   // velocity elements per lane
@@ -257,6 +265,8 @@ int launch_lift_adjoint_rho(const Inst* d_inst, const Inst& h_inst,
 constexpr int kAdjElems = 4;  // velocity elements per lane in adjoint kernels
 
 // Timing of the step kernels; kind is one of the BGK_PROF_* tags.
+// prof_suppress(true) turns it off for the calling thread (no events made).
+void prof_suppress(bool off);
 void prof_before(hipStream_t s);
 void prof_after(hipStream_t s, double cells, double bytes_per_cell, int kind);
 

@@ -144,3 +144,21 @@ def test_empty_and_oversized_batches_rejected():
     for n in (0, 4097):
         assert lib.bgk_fine_step_batched(probs, n, ptrs, outs, spans, None, None, 0,
                                          None) == bgk.E_INVALID
+
+
+def test_noalloc_size_limit_checked_on_the_host():
+    """The allocation-free propagation rejects a batch whose workspace would
+    exceed its static scratch, and an empty batch, before any device work
+    (the arrays passed here are never read)."""
+    lib = bgk.load_library()
+    c1 = wl.c1_sod_small()
+    ps = ctypes.byref(bgk.problem_struct(c1.problem))
+    assert bgk.workspace_bytes(c1.problem, bgk.OP_PROPAGATE, 14) <= bgk.NOALLOC_SCRATCH_BYTES
+    assert bgk.workspace_bytes(c1.problem, bgk.OP_PROPAGATE, 15) > bgk.NOALLOC_SCRATCH_BYTES
+    buf = (ctypes.c_double * 8)()
+    a, b = ctypes.cast(buf, ctypes.c_void_p), ctypes.cast(ctypes.byref(buf, 32), ctypes.c_void_p)
+    assert lib.bgk_fine_propagate_moments_noalloc(ps, 15, a, b, 0.0125, None,
+                                                  None) == bgk.E_WORKSPACE
+    assert b"static scratch holds 67108864 bytes" in lib.bgk_last_error()
+    assert lib.bgk_fine_propagate_moments_noalloc(ps, 0, a, b, 0.0125, None,
+                                                  None) == bgk.E_INVALID
