@@ -112,6 +112,19 @@ def c3_sod_large() -> Workload:
                     T=0.15, n_slices=32, k_max=6)
 
 
+def c3_slice_states(wk: Workload | None = None) -> np.ndarray:
+    """Primitive moments [32][2048][5] handed to the 32 slices of the large
+    Sod workload in one batched fine sweep: member b is the Sod data with its
+    discontinuity at x = 0.5 + (b - 16)/256 (a cell face; every member
+    distinct), a stand-in for the Riemann-fan states a parareal iterate
+    carries at the slice starts (the fine solve's cost does not depend on
+    the data)."""
+    wk = wk or c3_sod_large()
+    p = wk.problem
+    return np.stack([riemann_W0(p, SOD_LEFT, SOD_RIGHT, x_split=0.5 + (b - 16) / 256.0)
+                     for b in range(wk.n_slices)])
+
+
 C4_SEED = 250202704
 
 
