@@ -29,18 +29,16 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose: bool = False, jobs: int = 4, out: str = LIB, defines=()) -> str:
-    """Compile all sources and link `out`.  `defines` (e.g. ["X=1"]) are
-    passed as -D options (used to build experimental variants)."""
+def build(verbose: bool = False, out: str = LIB) -> str:
+    """Compile all sources and link `out`."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objdir = os.path.join(HERE, "_build" if not defines else "_build_" + str(abs(hash(tuple(defines)))))
+    objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = ([hipcc, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS +
-               ["-D" + d for d in defines])
+        cmd = [hipcc, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))

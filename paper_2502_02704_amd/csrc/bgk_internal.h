@@ -12,10 +12,7 @@
 namespace bgk {
 
 constexpr int kWave = 64;            // CDNA wavefront
-#ifndef BGK_WAVES_PER_BLOCK
-#define BGK_WAVES_PER_BLOCK 8
-#endif
-constexpr int kWavesPerBlock = BGK_WAVES_PER_BLOCK;  // step kernels: independent waves
+constexpr int kWavesPerBlock = 8;    // step kernels: independent waves
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kMinElems = 2;         // smallest velocity elements per lane
 constexpr int kPartElems = 32;       // fewest velocities behind one partial sum

@@ -19,14 +19,6 @@
 // stages the factor rows of its chunk in LDS.
 #include "bgk_internal.h"
 
-#ifndef BGK_WAVE_REDUCE_DPP
-#define BGK_WAVE_REDUCE_DPP 1
-#endif
-// Non-temporal stores of g (streamed once, read back only by the next step).
-#ifndef BGK_NT_STORE
-#define BGK_NT_STORE 1
-#endif
-
 namespace bgk {
 
 // ------------------------------------------------------------- helpers --
@@ -64,7 +56,6 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // Sum over the 64 lanes of a wave; the total is valid in lane 63.  Fixed
 // combination order, so results are bitwise reproducible.
 __device__ __forceinline__ double wave_sum_to_last(double v) {
-#if BGK_WAVE_REDUCE_DPP
   v += dpp_mov<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
   v += dpp_mov<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
   v += dpp_mov<0x114, 0xf>(v);  // row_shr:4
@@ -72,10 +63,6 @@ __device__ __forceinline__ double wave_sum_to_last(double v) {
   v += dpp_mov<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
   v += dpp_mov<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
   return v;
-#else
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-#endif
 }
 
 // A wave-uniform double moved to scalar registers.
@@ -99,26 +86,15 @@ __device__ __forceinline__ int find_inst(const Inst* insts, int n_inst,
   return q;
 }
 
-// Work item -> (member b, tile group tg, x chunk c).  BGK_TG_FASTEST: tile
-// groups fastest, so the blocks that run together on one XCD cover whole
-// rows of a few x chunks (a compact address window; shared halo rows stay
-// in that XCD's L2); else x chunks fastest.
-#ifndef BGK_TG_FASTEST
-#define BGK_TG_FASTEST 1
-#endif
+// Work item -> (member b, tile group tg, x chunk c), tile groups fastest, so
+// the blocks that run together on one XCD cover whole rows of a few x chunks
+// (a compact address window; shared halo rows stay in that XCD's L2).
 __device__ __forceinline__ void decode_item(const Inst& I, long long local, int& b, int& tg,
                                             int& c) {
-#if BGK_TG_FASTEST
   tg = (int)(local % I.ntg);
   const long long t = local / I.ntg;
   c = (int)(t % I.nchunks);
   b = (int)(t / I.nchunks);
-#else
-  c = (int)(local % I.nchunks);
-  const long long t = local / I.nchunks;
-  tg = (int)(t % I.ntg);
-  b = (int)(t / I.ntg);
-#endif
 }
 
 __device__ __forceinline__ double vgrid(const Inst& I, int a, int j) {
@@ -253,35 +229,19 @@ __device__ __forceinline__ void wave_sum_all_n(double (&v)[N], int lane) {
   }
 }
 
-// Recompute |v|^2 and nu per use instead of holding them in registers.
-#ifndef BGK_RECOMPUTE_Q
-#define BGK_RECOMPUTE_Q 0
-#endif
-
-// Per-pair velocity data of one lane.
+// Per-pair velocity data of one lane: |v|^2 of both velocities of the pair
+// and nu = v_x dt/dx held in registers.
 template <int P>
 struct PairEls {
   int jofs[P];
   unsigned off[P];
   double vx[P], vy[P], vz[P];
-#if !BGK_RECOMPUTE_Q
   double q0_[P], q1_[P], nu_[P];
-#endif
   double r, dvz;
   bool ok[P];
-#if BGK_RECOMPUTE_Q
-  __device__ __forceinline__ double q0(int p) const {
-    return fma(vx[p], vx[p], fma(vy[p], vy[p], vz[p] * vz[p]));
-  }
-  __device__ __forceinline__ double q1(int p) const {
-    return fma(dvz, fma(2.0, vz[p], dvz), q0(p));
-  }
-  __device__ __forceinline__ double nu(int p) const { return vx[p] * r; }
-#else
   __device__ __forceinline__ double q0(int p) const { return q0_[p]; }
   __device__ __forceinline__ double q1(int p) const { return q1_[p]; }
   __device__ __forceinline__ double nu(int p) const { return nu_[p]; }
-#endif
 };
 
 template <int P, bool FULL>
@@ -303,13 +263,11 @@ __device__ __forceinline__ void setup_pairs(const Inst& I, int tile, int lane,
     e.vx[p] = vgrid(I, 0, jx);
     e.vy[p] = vgrid(I, 1, jy);
     e.vz[p] = vgrid(I, 2, jz);
-#if !BGK_RECOMPUTE_Q
     const double vxy = e.vx[p] * e.vx[p] + e.vy[p] * e.vy[p];
     e.q0_[p] = vxy + e.vz[p] * e.vz[p];
     const double vz1 = vgrid(I, 2, jz + 1);
     e.q1_[p] = vxy + vz1 * vz1;
     e.nu_[p] = e.vx[p] * I.r;
-#endif
   }
   e.r = I.r;
   e.dvz = I.dv[2];
@@ -931,13 +889,11 @@ __global__ __launch_bounds__(kBlock) void k_step_vcol(const Inst* __restrict__ i
   }
 }
 
+// Non-temporal store of a pair of g (streamed once, read back only by the
+// next pass).
 __device__ __forceinline__ void store_pair(gptr<double> drow, int jofs, double2 g) {
-#if BGK_NT_STORE
   __builtin_nontemporal_store(g.x, drow + jofs);
   __builtin_nontemporal_store(g.y, drow + jofs + 1);
-#else
-  st2(drow + jofs, g.x, g.y);
-#endif
 }
 
 // One upwind transport of a pair: centre c, its neighbours behind (march
@@ -1459,9 +1415,7 @@ __global__ __launch_bounds__(kBlock) void k_step2x2_flat(const Inst* __restrict_
 // level-2 and level-3 values outside the domain are, for Neumann ends, copies
 // of the boundary row of the same level (the single step's ghost cells).
 // Raw rows in flight in the three-step march.
-#ifndef BGK_PF3X
-#define BGK_PF3X 2
-#endif
+constexpr int kRowsInFlight3x = 2;
 
 template <int P, int MODE, int CASE, int DIR>
 __device__ __forceinline__ void step3x_march(const Inst& I, const double* lds1,
@@ -1521,7 +1475,7 @@ __device__ __forceinline__ void step3x_march(const Inst& I, const double* lds1,
   double2 l3b[P], l3c[P];  // level 3 at k-1, k
   // raw rows in flight: rows k+3 .. k+2+R in R buffers used in turn (the loop
   // is unrolled by R, so no buffer is copied while its load is outstanding)
-  constexpr int R = BGK_PF3X;
+  constexpr int R = kRowsInFlight3x;
   double2 raw[R][P];
   {
     double2 x0[P], x1[P], x2[P], r0[P], r1[P], y0[P], y1[P];
