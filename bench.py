@@ -1,20 +1,21 @@
 """Benchmark of the fine kinetic propagator on one MI355X.
 
-A step = one pass of the whole hot path over one batch: every one of the 64
-parareal slices of the smooth periodic workload (Nx=512, 32^3 velocities on
-[-8,8]^3, eps=1e-2) is lifted from its moments, advanced by one slice (25 IMEX
-steps, three per pass over f where possible) and projected back to moments,
-all slices batched in one launch per pass.  The call returns moments only, so
-the last two steps are evaluated on their moments (from weighted sums of the
-23rd field, by linearity of the transport) rather than written out as f: a
-two-step pass from the lift, then seven three-step passes.  Prints one JSON line: phase-space
-updates/s, the roofline of the dominant kernel (the three-step relax pass; the
-two-step pass is timed beside it), the CPU oracle timed on a bounded sample,
-and the parareal vs serial-fine speedup on small workloads where one slice's
-step is latency bound.
+A step = one pass of the whole hot path over one batch: all 32 parareal
+slices of the large Sod workload (Nx=2048, 48^3 velocities on [-10,10]^3,
+eps=1e-3, zero-gradient ends) are lifted from their moments, advanced by one
+slice span (188 IMEX steps: a two-step pass from the lift, then 62 three-step
+passes over f) and projected back to moments, all slices batched in one
+launch per pass (7.25e9 phase-space cells per buffer).  Prints one JSON line:
+phase-space updates/s, the roofline of the dominant kernel (the three-step
+relax pass) under both byte models, the CPU oracle timed on a bounded sample,
+and secondary sections: the smooth periodic workload (Nx=512, 32^3, 64 slices)
+at its three Knudsen numbers, parareal against the serial fine solve at the
+baseline configurations and on small latency-bound cases, the exterior-force,
+second-order, uneven-batch and adjoint paths.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--eps E]
-       [--no-cpu-baseline] [--no-parareal] [--extras parareal,force,order2,uneven,adjoint]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       [--workload sod_large|smooth_periodic] [--no-cpu-baseline] [--no-parareal]
+       [--extras smooth,parareal,parareal_large,force,order2,uneven,adjoint]
        [--copy-calibration]
 """
 import argparse
@@ -31,15 +32,30 @@ sys.path.insert(0, ROOT)
 METRIC = "BGK phase-space updates/s (Nx*Nv^3*steps) + parareal vs serial-fine speedup"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = {
-    "three": os.path.join(ROOT, "profiles", "k_step3x_smooth_periodic_traffic.md"),
-    "two": os.path.join(ROOT, "profiles", "k_step2x2_smooth_periodic_traffic.md"),
+    ("sod_large", "three"): os.path.join(ROOT, "profiles", "k_step3x_sod_large_traffic.md"),
+    ("smooth_periodic", "three"): os.path.join(ROOT, "profiles",
+                                               "k_step3x_smooth_periodic_traffic.md"),
+    ("smooth_periodic", "two"): os.path.join(ROOT, "profiles",
+                                             "k_step2x2_smooth_periodic_traffic.md"),
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2502_02704_amd", "csrc", "kinetic.hip")
+
+
+def log(msg):
+    """Progress of the run on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_hash() -> str:
     with open(KERNEL_SRC, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def conserved(W):
+    """Conserved moments (rho, rho u, E) of primitive (rho, u, theta) rows."""
+    import numpy as np
+    return np.column_stack([W[:, 0], W[:, 0:1] * W[:, 1:4],
+                            0.5 * W[:, 0] * (W[:, 1:4] ** 2).sum(1) + 1.5 * W[:, 0] * W[:, 4]])
 
 
 def slice_moments(wk, B):
@@ -56,11 +72,32 @@ def slice_moments(wk, B):
     return V
 
 
-def traffic_from_profile(which):
+def workload_batch(name, eps=None):
+    """(workload, conserved slice moments [B][nx][5], span) of a benchmark batch."""
+    import numpy as np
+    from paper_2502_02704_amd import workloads as wl
+    if name == "sod_large":
+        wk = wl.c3_sod_large()
+        V = np.stack([conserved(w) for w in wl.c3_slice_states(wk)])
+    else:
+        wk = wl.c2_smooth_periodic(eps=1e-2 if eps is None else eps)
+        V = slice_moments(wk, wk.n_slices)
+    return wk, V, wk.T / wk.n_slices
+
+
+def steps_on_moments(n):
+    """Steps of a propagation with three steps per pass that are evaluated on
+    the moments only (not written out as f)."""
+    return (n - 2) % 3 if n >= 4 else 0
+
+
+def traffic_from_profile(workload, which):
     """HBM bytes per launch of the three- or two-step pass from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source;
-    else None."""
-    path = TRAFFIC_SUMMARY[which]
+    rocprofv3 counter summary of this workload, if it was taken on the
+    current kernel source; else None."""
+    path = TRAFFIC_SUMMARY.get((workload, which))
+    if path is None:
+        return None
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -73,49 +110,75 @@ def traffic_from_profile(which):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wk, V, span, budget_s=12.0, max_slices=64):
-    """The oracle as it stands, on slices of the same batch until the budget
-    is spent (at least one slice)."""
-    import oracle
-    p = wk.problem
-    n, _ = oracle.n_steps(p, span)
-    t0 = time.perf_counter()
-    done = 0
-    while done < max_slices:
-        oracle.fine_propagate_moments(p, V[done], span)
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    el = time.perf_counter() - t0
-    upd = done * p.cells * n
-    cores = oracle.get_threads()
-    # the same oracle on one thread, one slice
-    oracle.set_threads(1)
+def cpu_model():
     try:
-        t1 = time.perf_counter()
-        oracle.fine_propagate_moments(p, V[0], span)
-        el1 = time.perf_counter() - t1
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wk, V, span, n_sample=20, reps=3):
+    """The oracle, built for this host (-O3 -march=native, no fast-math, in
+    a temporary directory), on a bounded sample of the same workload: one
+    slice lifted, advanced `n_sample` steps of the slice's step size and
+    projected; median of `reps` runs on every OpenMP thread, and one run on
+    one thread over a single step."""
+    import statistics
+    import tempfile
+    import oracle
+    from oracle import build as obuild
+    p = wk.problem
+    n, dt = oracle.n_steps(p, span)
+    sample = n_sample * dt
+    tmp = tempfile.mkdtemp(prefix="oracle_native_")
+    oracle.use_library(obuild.build_native(os.path.join(tmp, "liboracle_native.so")))
+    try:
+        assert oracle.n_steps(p, sample)[0] == n_sample
+        cores = oracle.get_threads()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.fine_propagate_moments(p, V[0], sample)
+            ts.append(time.perf_counter() - t0)
+        el = statistics.median(ts)
+        oracle.set_threads(1)
+        try:
+            t1 = time.perf_counter()
+            oracle.fine_propagate_moments(p, V[0], dt)
+            el1 = time.perf_counter() - t1
+        finally:
+            oracle.set_threads(cores)
     finally:
-        oracle.set_threads(cores)
-    return {"value": upd / el, "unit": "updates/s", "cores": cores,
+        oracle.use_library(None)
+    return {"value": p.cells * n_sample / el, "unit": "updates/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{done} of {V.shape[0]} slices (lift + {n} IMEX steps + projection "
-                      f"each, {p.nx}x{p.nv[0]}^3), {el:.1f} s",
-            "value_1_thread": p.cells * n / el1}
+            "sample": (f"slice 0 of {V.shape[0]}: lift + {n_sample} of its {n} IMEX steps + "
+                       f"projection, {p.nx}x{p.nv[0]}^3, median of {reps} runs "
+                       f"({', '.join(f'{t:.1f}' for t in ts)} s)"),
+            "build": "gcc -O3 -march=native -fopenmp (no -ffast-math), built on this host",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "value_1_thread": p.cells / el1,
+            "sample_1_thread": f"lift + 1 step + projection of slice 0, {el1:.1f} s"}
 
 
-def parareal_speedup(torch, bgk, wl, reps=5):
-    """Parareal vs the serial chained fine solve with the same kernels and the
-    same launch machinery (captured graphs on both sides), on small workloads
-    where one slice's step is launch-latency bound -- the only regime where
-    one GPU can gain (larger slices are bandwidth bound, and parareal then
-    does more fine work than the serial solve).  Error = max over slices,
-    cells and components of |U_parareal - U_serial| (conserved moments);
-    reports the smallest K reaching 1e-6."""
+def parareal_row(torch, bgk, name, p, W0np, N, T, E, coarse, lift_order, k_cap, reps,
+                 baseline_config, warm_each=True):
+    """Parareal (Algorithm 2) against the serial chained fine solve with the
+    same kernels and the same launch machinery (captured graphs on both
+    sides).  Error = max over slices, cells and components of
+    |U_parareal - U_serial| (conserved moments); K runs from 1 until the error
+    reaches 1e-6 or K = k_cap.  Wall-clock: median of `reps` runs (after a
+    warm-up run per K, or with warm_each False one warm-up at K = k_cap, which
+    captures every iteration's graph)."""
     import numpy as np
 
-    def timed(fn):
-        fn()
+    def timed(fn, warm=True):
+        if warm:
+            fn()
         torch.cuda.synchronize()
         ts = []
         for _ in range(reps):
@@ -125,41 +188,76 @@ def parareal_speedup(torch, bgk, wl, reps=5):
             ts.append(time.perf_counter() - t0)
         return out, float(np.median(ts))
 
+    W0 = torch.from_numpy(W0np).cuda()
+    run_par = lambda K: bgk.parareal_iterate(p, W0, N, T, K, 0.0, E=E, coarse=coarse,
+                                             lift_order=lift_order)
+    ref, t_serial = timed(lambda: bgk.serial_fine(p, W0, N, T, E=E, lift_order=lift_order))
+    ref = ref.cpu().numpy()
+    res = {"workload": name, "baseline_config": baseline_config, "coarse": coarse,
+           "lift_order": lift_order, "slices": N, "serial_fine_ms": round(t_serial * 1e3, 4),
+           "K": []}
+    if not warm_each:
+        run_par(k_cap)
+    chosen = None
+    for K in range(1, k_cap + 1):
+        (V, err, kd), t_par = timed(lambda: run_par(K), warm=warm_each)
+        e = float(np.max(np.abs(V.cpu().numpy() - ref)))
+        res["K"].append({"K": K, "ms": round(t_par * 1e3, 4), "err_vs_fine": e,
+                         "speedup": round(t_serial / t_par, 3)})
+        if not warm_each:
+            log(f"parareal {name} K={K}: {t_par * 1e3:.1f} ms, err {e:.3g}")
+        if e <= 1e-6:
+            chosen = res["K"][-1]
+            break
+    bgk.check_status()
+    res["K_at_1e-6"] = chosen["K"] if chosen else None
+    res["speedup_at_1e-6"] = chosen["speedup"] if chosen else None
+    if chosen is None:
+        res["err_at_K_cap"] = res["K"][-1]["err_vs_fine"]
+        res["speedup_at_K_cap"] = res["K"][-1]["speedup"]
+    return res
+
+
+def parareal_small(torch, bgk, wl, reps=5):
+    """The small Sod configuration (64 x 16^3, 8 slices) with the Euler and
+    Navier-Stokes coarse models and the order-one lifting, and reduced
+    smooth periodic cases (64 x 16^3, 16 slices; not baseline configurations)
+    and the two-beam exterior-force test: where one slice's step is
+    launch-latency bound, the only regime where one GPU can gain."""
     sod = wl.c1_sod_small()
     s4 = wl.c2_smooth_periodic(eps=1e-4, nx=64, nv=16, n_slices=16)
     s2 = wl.c2_smooth_periodic(eps=1e-2, nx=64, nv=16, n_slices=16)
     fk = wl.c6_two_beam_force()
-    cases = [(sod.name, sod.problem, sod.W0, sod.n_slices, sod.T, None, "euler"),
-             (s4.name, s4.problem, s4.W0, s4.n_slices, s4.T, None, "euler"),
-             (s4.name, s4.problem, s4.W0, s4.n_slices, s4.T, None, "cns"),
-             (s2.name, s2.problem, s2.W0, s2.n_slices, s2.T, None, "euler"),
-             (s2.name, s2.problem, s2.W0, s2.n_slices, s2.T, None, "cns"),
-             (fk.name, fk.problem, fk.U0(), fk.n_slices, fk.T, fk.E, "euler")]
-    cases = [c + (0,) for c in cases]
-    # the multiscale variant: Navier-Stokes coarse model with the order-one
-    # (Chapman-Enskog) lifting, against the serial chain with the same lifting
-    cases.append((s2.name, s2.problem, s2.W0, s2.n_slices, s2.T, None, "cns", 1))
+    cases = [(sod, None, "euler", 0, True), (sod, None, "cns", 0, True),
+             (sod, None, "cns", 1, True),
+             (s4, None, "euler", 0, False), (s4, None, "cns", 0, False),
+             (s2, None, "euler", 0, False), (s2, None, "cns", 0, False),
+             (s2, None, "cns", 1, False)]
+    out = [parareal_row(torch, bgk, w.name, w.problem, w.W0, w.n_slices, w.T, E, coarse, lo,
+                        w.n_slices, reps, base) for w, E, coarse, lo, base in cases]
+    out.append(parareal_row(torch, bgk, fk.name, fk.problem, fk.U0(), fk.n_slices, fk.T, fk.E,
+                            "euler", 0, fk.n_slices, reps, False))
+    return out
+
+
+def parareal_large(torch, bgk, wl, k_cap_smooth=8, k_cap_sod=6):
+    """Parareal at the full baseline sizes, where one slice's fine step is
+    bandwidth bound: the smooth periodic workload (512 x 32^3, 64 slices) at
+    eps = 1, 1e-2, 1e-4 and the large Sod workload (2048 x 48^3, 32 slices,
+    K <= 6), Euler coarse model.  Reported as measured (a slowdown is
+    expected: each iteration moves about as many bytes as the serial solve)."""
     out = []
-    for name, p, W0np, N, T, E, coarse, lo in cases:
-        W0 = torch.from_numpy(W0np).cuda()
-        ref, t_serial = timed(lambda: bgk.serial_fine(p, W0, N, T, E=E, lift_order=lo))
-        ref = ref.cpu().numpy()
-        res = {"workload": name, "coarse": coarse, "lift_order": lo, "slices": N,
-               "serial_fine_ms": round(t_serial * 1e3, 4), "K": []}
-        chosen = None
-        for K in range(1, N + 1):
-            (V, err, kd), t_par = timed(lambda: bgk.parareal_iterate(p, W0, N, T, K, 0.0, E=E,
-                                                                     coarse=coarse,
-                                                                     lift_order=lo))
-            e = float(np.max(np.abs(V.cpu().numpy() - ref)))
-            res["K"].append({"K": K, "ms": round(t_par * 1e3, 4), "err_vs_fine": e,
-                             "speedup": round(t_serial / t_par, 3)})
-            if e <= 1e-6:
-                chosen = res["K"][-1]
-                break
-        res["K_at_1e-6"] = chosen["K"] if chosen else None
-        res["speedup_at_1e-6"] = chosen["speedup"] if chosen else None
-        out.append(res)
+    for eps in (1.0, 1e-2, 1e-4):
+        w = wl.c2_smooth_periodic(eps=eps)
+        out.append(parareal_row(torch, bgk, w.name, w.problem, w.W0, w.n_slices, w.T, None,
+                                "euler", 0, k_cap_smooth, 2, True, warm_each=False))
+        bgk.free_workspaces()
+        torch.cuda.empty_cache()
+    w = wl.c3_sod_large()
+    out.append(parareal_row(torch, bgk, w.name, w.problem, w.W0, w.n_slices, w.T, None,
+                            "euler", 0, k_cap_sod, 1, True, warm_each=False))
+    bgk.free_workspaces()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -197,7 +295,7 @@ def force_throughput(torch, bgk, wl, reps=5):
             "step_kernel_avg_us": round(ms * 1e3 / max(launches, 1), 2)}
 
 
-def uneven_throughput(torch, bgk, wl, span=0.01, reps=3):
+def uneven_throughput(torch, bgk, wl, span=0.1, reps=3):
     """The uneven multi-instance batch (seeded Riemann problems with Nx in
     [128, 1024], Nv in [16, 32], eps in [1e-4, 1]) advanced together: every
     instance's first step alone, then per round one two-step pass over the
@@ -211,6 +309,14 @@ def uneven_throughput(torch, bgk, wl, span=0.01, reps=3):
     fs = [bgk.lift(w.problem, torch.from_numpy(w.W0).cuda()) for w in insts]
     spans = [span] * len(insts)
     outs, steps = bgk.fine_step_batched(probs, fs, spans)
+    note = None
+    if bgk.status() != bgk.OK:
+        # a state went non-physical over the whole span: time the short one
+        note = f"non-physical state flagged over span {span}; timed over 0.01"
+        span = 0.01
+        spans = [span] * len(insts)
+        outs, steps = bgk.fine_step_batched(probs, fs, spans)
+        bgk.check_status()
     n_upd = sum(p.cells * n for p, n in zip(probs, steps))
 
     def timed():
@@ -233,6 +339,8 @@ def uneven_throughput(torch, bgk, wl, span=0.01, reps=3):
             "steps_min_max": [min(steps), max(steps)],
             "cells": sum(p.cells for p in probs), "updates_per_s": n_upd / el,
             "ms_per_call": round(el * 1e3, 3)}
+    if note:
+        line["note"] = note
     for name, (ms, launches, upd, by) in kinds.items():
         if launches:
             line[name + "_GBs"] = round(by / (ms * 1e-3) / 1e9, 1)
@@ -308,18 +416,127 @@ def second_order_throughput(torch, bgk, V, p, span, reps=2):
             "step_kernel_avg_us": round(ms * 1e3 / max(launches, 1), 2)}
 
 
+def time_batch(torch, bgk, p, V, span, steps, warmup):
+    """Times `steps` calls of the batched propagation (lift, fine steps,
+    projection) of the slices V after `warmup` calls, with the step kernels'
+    launches bracketed by HIP events on their stream.  Returns (seconds,
+    output, {kind: (ms, launches, updates, bytes)})."""
+    Vd = torch.from_numpy(V).cuda()
+    for _ in range(warmup):
+        bgk.fine_propagate_moments(p, Vd, span)
+    bgk.check_status()
+    torch.cuda.synchronize()
+    bgk.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = bgk.fine_propagate_moments(p, Vd, span)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kinds = {k: bgk.prof_read(kind) for k, kind in
+             (("three", bgk.PROF_THREE_STEP), ("two", bgk.PROF_TWO_STEP),
+              ("all", bgk.PROF_ALL))}
+    bgk.prof_enable(False)
+    bgk.check_status()
+    assert out is None or torch.isfinite(out).all().item()
+    return elapsed, kinds
+
+
+def roofline_of(workload, kinds, updates_per_step, steps, elapsed):
+    """Roofline of the dominant kernel, the three-step relax pass (or the
+    two-step pass where no three-step pass ran), from the HIP-event timing.
+    `frac` uses the pass's own algorithmic bytes: one read and one write of f
+    per pass (16 B per cell per pass: 16/3 B per phase-space update with
+    three steps per pass, 8 with two); `frac_at_16B_per_update` prices the
+    same updates at one read and one write of f per IMEX step."""
+    which = "three" if kinds["three"][1] else "two"
+    k_ms, k_launches, k_upd, k_bytes = kinds[which]
+    a_ms, a_launches, a_upd, a_bytes = kinds["all"]
+    achieved = k_bytes / (k_ms * 1e-3) / 1e9
+    per_launch_alg = k_bytes / max(k_launches, 1)
+    pass_ups = k_upd / (k_ms * 1e-3)
+    traffic = traffic_from_profile(workload, which)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "frac_basis": ("algorithmic bytes of the pass: one read and one write of f per "
+                           f"{'three' if which == 'three' else 'two'}-step pass "
+                           f"({k_bytes / max(k_upd, 1.0):.3f} B per phase-space update)"),
+            "frac_at_16B_per_update": round(pass_ups * 16.0 / (HBM_PEAK_GBS * 1e9), 4),
+            "traffic_over_alg_bytes": (round(traffic / per_launch_alg, 4) if traffic else None),
+            "kernel": ("k_step3x relax passes (three IMEX steps per pass over f)"
+                       if which == "three" else
+                       "k_step2x2 relax passes (two IMEX steps per pass over f)"),
+            "launches": k_launches, "avg_launch_us": round(k_ms * 1e3 / max(k_launches, 1), 2),
+            "alg_bytes_per_launch": per_launch_alg,
+            "alg_bytes_per_update": round(k_bytes / max(k_upd, 1.0), 3),
+            "pass_updates_per_s": pass_ups,
+            "all_step_kernels": {
+                "launches": a_launches,
+                "avg_launch_us": round(a_ms * 1e3 / max(a_launches, 1), 2),
+                "achieved": round(a_bytes / (a_ms * 1e-3) / 1e9, 1),
+                "alg_bytes_per_update": round(a_bytes / max(a_upd, 1.0), 3),
+                "share_of_wall_clock": round(a_ms * 1e-3 / elapsed, 4)}}
+
+
+def batch_line(torch, bgk, name, steps, warmup, eps=None):
+    """Throughput and roofline of one benchmark batch."""
+    wk, V, span = workload_batch(name, eps)
+    p = wk.problem
+    B = V.shape[0]
+    n_fine, _ = bgk.n_steps(p, span)
+    virt = steps_on_moments(n_fine)
+    updates_per_step = B * p.cells * n_fine
+    elapsed, kinds = time_batch(torch, bgk, p, V, span, steps, warmup)
+    cfg = {"workload": f"{wk.name.split('_eps')[0]}_slices{B}", "nx": p.nx, "nv": list(p.nv),
+           "v_box": [p.v_lo[0], p.v_hi[0]], "slices_batched": B,
+           "fine_steps_per_slice": n_fine, "steps_applied_to_f": n_fine - virt,
+           "last_steps_on_moments": virt, "eps": p.eps,
+           "bc": "periodic" if p.bc == 1 else "neumann", "updates_per_step": updates_per_step,
+           "updates_per_step_applied_to_f": B * p.cells * (n_fine - virt)}
+    return {"value": updates_per_step * steps / elapsed,
+            "value_steps_applied_to_f": B * p.cells * (n_fine - virt) * steps / elapsed,
+            "ms_per_step": elapsed / steps * 1e3, "config": cfg,
+            "roofline": roofline_of(name, kinds, updates_per_step, steps, elapsed)}, wk, V, span
+
+
+def smooth_section(torch, bgk, steps=5, warmup=1):
+    """The smooth periodic workload (64 slices of 512 x 32^3, 25 steps per
+    slice, the last two evaluated on the moments) at its three Knudsen
+    numbers, and with two steps per pass at eps = 1e-2 for comparison."""
+    out = []
+    for eps in (1.0, 1e-2, 1e-4):
+        line, _, _, _ = batch_line(torch, bgk, "smooth_periodic", steps, warmup, eps)
+        line["config"]["eps"] = eps
+        out.append(line)
+    bgk.set_step_fusion(2)
+    try:
+        two, _, _, _ = batch_line(torch, bgk, "smooth_periodic", 3, 1, 1e-2)
+        two["steps_per_pass"] = 2
+        two["roofline"]["traffic"] = traffic_from_profile("smooth_periodic", "two")
+        out.append(two)
+    finally:
+        bgk.set_step_fusion(3)
+    bgk.free_workspaces()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--eps", type=float, default=1e-2)
+    ap.add_argument("--workload", default="sod_large", choices=["sod_large", "smooth_periodic"])
+    ap.add_argument("--eps", type=float, default=None,
+                    help="Knudsen number of the smooth periodic main line (default 1e-2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parareal", action="store_true",
                     help="skip every section after the main line (same as --extras '')")
-    ap.add_argument("--extras", default="parareal,force,order2,uneven,adjoint",
-                    help="comma list of the extra sections: parareal, force, order2, uneven, "
-                         "adjoint")
+    ap.add_argument("--extras", default="smooth,parareal,parareal_large,force,order2,uneven,adjoint",
+                    help="comma list of the extra sections: smooth, parareal, parareal_large, "
+                         "force, order2, uneven, adjoint")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -328,69 +545,17 @@ def main():
               "slices over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_2502_02704_amd import bgk
     from paper_2502_02704_amd import workloads as wl
 
     torch.cuda.set_device(0)
-    wk = wl.c2_smooth_periodic(eps=args.eps)
-    p = wk.problem
-    B = wk.n_slices
-    span = wk.T / wk.n_slices
-    n_fine, _ = bgk.n_steps(p, span)
-    V_np = slice_moments(wk, B)
-    V = torch.from_numpy(V_np).cuda()
-    updates_per_step = B * p.cells * n_fine
-
-    for _ in range(args.warmup):
-        bgk.fine_propagate_moments(p, V, span)
-    bgk.check_status()
-    torch.cuda.synchronize()
-
-    bgk.prof_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = bgk.fine_propagate_moments(p, V, span)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    which = "three"
-    k_ms, k_launches, k_upd, k_bytes = bgk.prof_read(bgk.PROF_THREE_STEP)
-    if k_launches == 0:
-        which = "two"
-        k_ms, k_launches, k_upd, k_bytes = bgk.prof_read(bgk.PROF_TWO_STEP)
-    a_ms, a_launches, a_upd, a_bytes = bgk.prof_read(bgk.PROF_ALL)
-    bgk.prof_enable(False)
-    bgk.check_status()
-    assert torch.isfinite(out).all().item()
-
-    # the same batch with two steps per pass, for comparison
-    two = None
-    if which == "three":
-        bgk.set_step_fusion(2)
-        try:
-            bgk.fine_propagate_moments(p, V, span)
-            torch.cuda.synchronize()
-            bgk.prof_enable(True)
-            reps2 = max(1, min(args.steps, 3))
-            t2 = time.perf_counter()
-            for _ in range(reps2):
-                bgk.fine_propagate_moments(p, V, span)
-            torch.cuda.synchronize()
-            el2 = (time.perf_counter() - t2) / reps2
-            m2, l2, u2, b2 = bgk.prof_read(bgk.PROF_TWO_STEP)
-            bgk.prof_enable(False)
-            bgk.check_status()
-        finally:
-            bgk.set_step_fusion(3)
-        ach2 = b2 / (m2 * 1e-3) / 1e9
-        two = {"kernel": "k_step2x2 relax passes (two IMEX steps per pass over f)",
-               "updates_per_s": updates_per_step / el2, "ms_per_step": round(el2 * 1e3, 3),
-               "achieved": round(ach2, 1), "frac": round(ach2 / HBM_PEAK_GBS, 4),
-               "avg_launch_us": round(m2 * 1e3 / max(l2, 1), 2), "launches": l2,
-               "alg_bytes_per_update": round(b2 / max(u2, 1.0), 3),
-               "traffic": traffic_from_profile("two")}
+    main_line, wk, V_np, span = batch_line(torch, bgk, args.workload, args.steps, args.warmup,
+                                           args.eps)
+    log(f"main line {main_line['config']['workload']}: {main_line['value']:.4g} updates/s, "
+        f"{main_line['ms_per_step']:.1f} ms per step")
+    bgk.free_workspaces()
+    torch.cuda.empty_cache()
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -400,54 +565,41 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    value = updates_per_step * args.steps / elapsed
-    achieved = k_bytes / (k_ms * 1e-3) / 1e9
-    per_launch_alg = k_bytes / max(k_launches, 1)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_from_profile(which),
-                "kernel": ("k_step3x relax passes (three IMEX steps per pass over f)"
-                           if which == "three" else
-                           "k_step2x2 relax passes (two IMEX steps per pass over f)"),
-                "launches": k_launches, "avg_launch_us": round(k_ms * 1e3 / max(k_launches, 1), 2),
-                "alg_bytes_per_launch": per_launch_alg,
-                "alg_bytes_per_update": round(k_bytes / max(k_upd, 1.0), 3),
-                "all_step_kernels": {
-                    "launches": a_launches, "avg_launch_us": round(a_ms * 1e3 / max(a_launches, 1), 2),
-                    "achieved": round(a_bytes / (a_ms * 1e-3) / 1e9, 1),
-                    "alg_bytes_per_update": round(a_bytes / max(a_upd, 1.0), 3)}}
-    if which == "three":
-        # the pass's own updates/s against the HBM ceiling of a two-steps-per-pass
-        # design (8 B per update): what moving a third fewer bytes buys
-        pass_ups = k_upd / (k_ms * 1e-3)
-        roofline["pass_updates_per_s"] = pass_ups
-        roofline["frac_of_8B_per_update_ceiling"] = round(pass_ups / (HBM_PEAK_GBS * 1e9 / 8.0), 4)
-    if two is not None:
-        roofline["two_step_pass"] = two
-    line = {"metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": f"smooth_periodic_nx{p.nx}_nv{p.nv[0]}_slices{B}",
-                       "nx": p.nx, "nv": list(p.nv), "slices_batched": B,
-                       "fine_steps_per_slice": n_fine,
-                       "last_steps_on_moments": (n_fine - 2) % 3 if n_fine >= 4 else 0,
-                       "eps": p.eps, "bc": "periodic",
-                       "updates_per_step": updates_per_step},
-            "roofline": roofline}
+    line = {"metric": METRIC, "value": main_line["value"], "unit": "updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_line["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": main_line["config"],
+            "value_steps_applied_to_f": main_line["value_steps_applied_to_f"],
+            "roofline": main_line["roofline"]}
     extras = set() if args.no_parareal else {x for x in args.extras.split(",") if x}
+    if "smooth" in extras and args.workload == "sod_large":
+        line["smooth_periodic"] = smooth_section(torch, bgk)
+        log("smooth periodic section done")
     if "parareal" in extras:
-        line["parareal"] = parareal_speedup(torch, bgk, wl)
+        line["parareal"] = parareal_small(torch, bgk, wl)
+        log("parareal, small cases done")
+    if "parareal_large" in extras:
+        line["parareal_baseline_sizes"] = parareal_large(torch, bgk, wl)
+        log("parareal, baseline sizes done")
     if "force" in extras:
         line["exterior_force"] = force_throughput(torch, bgk, wl)
+        log("exterior force done")
     if "order2" in extras:
-        line["second_order_fine"] = second_order_throughput(torch, bgk, V, p, span)
+        wk2, V2, span2 = workload_batch("smooth_periodic")
+        line["second_order_fine"] = second_order_throughput(
+            torch, bgk, torch.from_numpy(V2).cuda(), wk2.problem, span2)
+        bgk.free_workspaces()
+        torch.cuda.empty_cache()
+        log("second-order section done")
     if "uneven" in extras:
         line["uneven_batch"] = uneven_throughput(torch, bgk, wl)
+        log("uneven batch done")
     if "adjoint" in extras:
         line["adjoint"] = adjoint_timing(torch, bgk, wl)
+        log("adjoint done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wk, V_np, span)
+        log("cpu baseline done")
     print(json.dumps(line), flush=True)
 
 

@@ -38,15 +38,24 @@ class _Problem(C.Structure):
 
 
 _lib = None
+_lib_path = LIB_PATH
+
+
+def use_library(path: str | None = None) -> None:
+    """Load the oracle from another build of the same source (the host-tuned
+    build the benchmark times); None returns to the portable build."""
+    global _lib, _lib_path
+    _lib = None
+    _lib_path = path or LIB_PATH
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        if _lib_path == LIB_PATH and not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(_lib_path)
         P = C.POINTER(_Problem)
         D = C.POINTER(C.c_double)
         I = C.POINTER(C.c_int32)
