@@ -19,4 +19,16 @@ def rel_V(got, ref):
     return max(np.max(d[:, 0]) / r, np.max(d[:, 1:4]) / m, np.max(d[:, 4]) / e)
 
 
+def rel_W(got, ref):
+    """Normwise errors of primitive moments [..., 5]: density by max|rho|,
+    velocity by the thermal speed sqrt(max theta), temperature by max theta.
+    Returns (rho, u, theta) errors."""
+    got = np.asarray(got).reshape(-1, 5)
+    ref = np.asarray(ref).reshape(-1, 5)
+    d = np.abs(got - ref)
+    th = np.max(np.abs(ref[:, 4]))
+    return (float(np.max(d[:, 0]) / np.max(np.abs(ref[:, 0]))),
+            float(np.max(d[:, 1:4]) / np.sqrt(th)), float(np.max(d[:, 4]) / th))
+
+
 TOL = 1e-12  # parity bar on f and moments (max norm, normwise relative)

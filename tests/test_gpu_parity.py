@@ -15,7 +15,7 @@ import torch
 import oracle
 from paper_2502_02704_amd import bgk
 from paper_2502_02704_amd import workloads as wl
-from tests.gpu_util import TOL, rel_f, rel_V
+from tests.gpu_util import TOL, rel_f, rel_V, rel_W
 
 pytestmark = pytest.mark.gpu
 
@@ -76,10 +76,12 @@ def test_moments(name):
     _, f = states(p, 2)
     V, W = bgk.moments(p, cuda(f))
     Vr, Wr = oracle.moments(p, f)
-    assert rel_V(V.cpu().numpy(), Vr) < TOL
-    Wg = W.cpu().numpy()
-    assert np.max(np.abs(Wg[:, 0] - Wr[:, 0])) / np.max(Wr[:, 0]) < TOL
-    assert np.max(np.abs(Wg[:, 4] - Wr[:, 4])) / np.max(Wr[:, 4]) < 1e-11
+    ev = rel_V(V.cpu().numpy(), Vr)
+    er, eu, et = rel_W(W.cpu().numpy(), Wr)
+    print(f"{name}: conserved {ev:.2e}; rho {er:.2e}, u {eu:.2e}, theta {et:.2e} "
+          "(theta one-pass on the GPU, two-pass in the oracle)")
+    assert ev < TOL
+    assert er < TOL and eu < TOL and et < TOL
 
 
 # --------------------------------------------------------------- fine step --
@@ -244,6 +246,33 @@ def test_parareal_sod_small_matches_oracle():
     assert kd == kdr == 3
     assert rel_V(V.cpu().numpy(), Vr) < TOL
     assert np.allclose(err, errr, rtol=1e-6, atol=1e-13)
+
+
+def test_parareal_many_slices_kinetic_regime_matches_oracle():
+    """64 slices of 512 x 16^3 at eps = 1 (the smooth periodic profile;
+    every fine sweep batches 64 - k slices through three-step passes): the
+    iterates after K = 1, 2, 3 and their errors against the serial chain,
+    GPU against the oracle.  In this regime the Euler coarse model is far
+    from the kinetic solution and the error against the serial chain need not
+    fall with K before K approaches N (the same in both)."""
+    wk = wl.c2_smooth_periodic(eps=1.0, nx=512, nv=16, n_slices=64)
+    p = wk.problem
+    N, T = wk.n_slices, wk.T
+    S = bgk.serial_fine(p, cuda(wk.W0), N, T).cpu().numpy()
+    Sr = oracle.serial_fine(p, wk.W0, N, T)
+    assert rel_V(S, Sr) < TOL
+    for K in (1, 2, 3):
+        V, err, kd = bgk.parareal_iterate(p, cuda(wk.W0), N, T, K, 0.0)
+        Vr, errr, _ = oracle.parareal_iterate(p, wk.W0, N, T, K, 0.0)
+        bgk.check_status()
+        e = rel_V(V.cpu().numpy(), Vr)
+        d_gpu = float(np.max(np.abs(V.cpu().numpy() - S)))
+        d_ora = float(np.max(np.abs(Vr - Sr)))
+        print(f"K={K}: GPU vs oracle {e:.2e}; error vs serial chain GPU {d_gpu:.3e}, "
+              f"oracle {d_ora:.3e}")
+        assert kd == K and e < TOL
+        assert abs(d_gpu - d_ora) <= 1e-10 * max(d_ora, 1e-300) + 1e-14
+        assert np.allclose(err, errr, rtol=1e-8, atol=1e-14)
 
 
 RESOLVED_RAGGED = wl.Problem(nx=13, nv=(12, 7, 9), v_lo=(-7, -6, -7), v_hi=(7, 6, 7),
@@ -443,8 +472,8 @@ def test_sod_large_full_size_two_steps():
 
 def test_smooth_periodic_full_batch_sampled():
     """Nx=512, 32^3, 64 slices in one batched launch per step (the benchmark
-    workload): every member advances one full slice (25 steps); two sampled
-    members are recomputed by the oracle."""
+    workload): every member advances one full slice (25 steps); eight sampled
+    members (first and last among them) are recomputed by the oracle."""
     wk = wl.c2_smooth_periodic(eps=1e-2)
     p = wk.problem
     B = wk.n_slices
@@ -457,7 +486,7 @@ def test_smooth_periodic_full_batch_sampled():
     span = wk.T / wk.n_slices
     got = bgk.fine_propagate_moments(p, cuda(V), span).cpu().numpy()
     bgk.check_status()
-    for b in (0, 37):
+    for b in (0, 9, 18, 27, 37, 45, 54, 63):
         ref = oracle.fine_propagate_moments(p, V[b], span)
         assert rel_V(got[b], ref) < TOL
 
@@ -532,6 +561,45 @@ def test_adjoint_workload_full_size_gradients():
         fd_dir = (float(loss_fn(r0 + h * d, le)) - float(loss_fn(r0 - h * d, le))) / (2 * h)
     assert abs(g_le - fd_le) < 1e-6 * abs(fd_le)
     assert abs(float(torch.dot(g_rho, d)) - fd_dir) < 1e-6 * abs(fd_dir)
+
+
+def test_adjoint_workload_full_size_against_oracle_adjoint():
+    """The same full-size gradient workload (256 x 24^3, 393 steps, checkpoints
+    every 16) against the oracle's FP64 adjoint: the oracle recomputes its own
+    forward states, target and misfit adjoint, then applies its transposed
+    steps and the lifting's adjoint; the gradients in rho0 (all 256 cells)
+    and log eps agree to 1e-10 normwise."""
+    from dataclasses import replace
+    wk, rho0, eps_t, _ = wl.c4_adjoint()
+    p = wk.problem
+    n, dt = oracle.n_steps(p, wk.T)
+    # GPU: autograd through the library's forward and adjoint kernels
+    r0 = torch.tensor(rho0, dtype=torch.float64, device="cuda", requires_grad=True)
+    le = torch.tensor(np.log(p.eps), dtype=torch.float64, device="cuda", requires_grad=True)
+    with torch.no_grad():
+        target = bgk.kinetic_density(r0.detach(), torch.tensor(np.log(eps_t), dtype=torch.float64,
+                                                               device="cuda"), p, T=wk.T)
+    rho = bgk.kinetic_density(r0, le, p, T=wk.T, ckpt_every=16)
+    (0.5 * (1.0 / p.nx) * torch.sum((rho - target) ** 2)).backward()
+    bgk.check_status()
+    g_rho, g_le = r0.grad.cpu().numpy(), float(le.grad)
+    # oracle: forward with checkpoints, target, density adjoint, fine adjoint,
+    # lifting adjoint
+    W = wk.W0.copy()
+    f0 = oracle.lift(p, W)
+    ck, fT = oracle.checkpoints(p, f0, dt, n, 16)
+    fT_t = oracle.fine_steps(replace(p, eps=eps_t), f0, dt, n)
+    rho_o = oracle.moments(p, fT)[0][:, 0]
+    rho_t = oracle.moments(p, fT_t)[0][:, 0]
+    dx = (p.x_hi - p.x_lo) / p.nx
+    dv3 = np.prod([(p.v_hi[a] - p.v_lo[a]) / p.nv[a] for a in range(3)])
+    fbar_T = np.repeat(((rho_o - rho_t) * dx * dv3)[:, None], p.nv3, axis=1)
+    fb0, dle = oracle.fine_adjoint(p, ck, 16, n, dt, fbar_T)
+    g_ref = oracle.lift_adjoint_rho(p, W, fb0)
+    e_rho = float(np.max(np.abs(g_rho - g_ref)) / np.max(np.abs(g_ref)))
+    e_le = abs(g_le - dle) / abs(dle)
+    print(f"full-size adjoint vs oracle: rho0 gradient {e_rho:.2e}, log eps {e_le:.2e}")
+    assert e_rho < 1e-10 and e_le < 1e-10
 
 
 def test_uneven_batch_full_set_sampled():
