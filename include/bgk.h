@@ -3,10 +3,13 @@
  * the multiscale kinetic/fluid parareal method for the collisional Vlasov-BGK
  * equation in the hyperbolic scaling (Laidin & Rey, arXiv 2502.02704).
  *
- * Model (Section 1, Section 3.1): 1D in x, 3D in v, alpha = 0, no exterior
- * force, BGK operator relaxing at rate 1/eps (tau = 1), IMEX scheme with
- * explicit upwind transport in x and implicit relaxation whose n+1 moments
- * come from conservation.
+ * Model (Section 1, Section 3.1): 1D in x, 3D in v, alpha = 0, BGK operator
+ * relaxing at rate 1/eps (tau = 1), IMEX scheme with explicit upwind
+ * transport in x and implicit relaxation whose n+1 moments come from
+ * conservation.  The calls without a suffix have no exterior force; the
+ * _force calls add one along x (the Test 3 setting of Section 5.3), the
+ * _cns and _opts calls the Navier-Stokes coarse model, the order-one lifting
+ * and second-order transport.
  *
  * Conventions shared by every entry point
  *  - Pointers marked [device] are HIP device pointers; [host] are host
@@ -29,7 +32,12 @@
  *  - Return value: BGK_OK or a negative status.  Arguments are validated on
  *    the host before anything is enqueued; then nothing is launched.
  *    Non-physical states met on the device (rho <= 0, theta <= 0, NaN) raise
- *    a sticky flag in the workspace; bgk_status() reads and clears it.
+ *    a sticky flag in the workspace; bgk_check(stream) reads and clears the
+ *    flags of every workspace used on a stream, bgk_status(ws) one of them.
+ *  - Caches between calls (captured HIP graphs, tuned tile shapes, the
+ *    workspaces each stream used since its last check) live in a plan:
+ *    the library's default plan, or one the caller creates and selects with
+ *    bgk_plan_use (see "plans" below).
  */
 #ifndef BGK_H
 #define BGK_H
@@ -194,6 +202,11 @@ int bgk_serial_fine(const bgk_problem* prob, const double* W0, int32_t n_slices,
  * sizes) and errors otherwise as the functions without _force. */
 int bgk_n_steps_force(const bgk_problem* prob, double e_max, double t_span,
                       int32_t* n_steps, double* dt);
+/* The Rusanov coefficient e_max = max_i |E_i| of a force (NaN if an E_i is
+ * NaN).  E [device] when E_on_device is nonzero (read on `stream`, which is
+ * synchronised), else [host]; [host] e_max. */
+int bgk_force_bound(const bgk_problem* prob, const double* E, int32_t E_on_device,
+                    double* e_max, void* stream);
 int bgk_fine_steps_force(const bgk_problem* prob, const double* E, double e_max,
                          const double* f_in, double* f_out, double dt,
                          int32_t n_steps, void* ws, size_t ws_bytes, void* stream);
@@ -353,6 +366,41 @@ int bgk_fine_propagate_moments_noalloc(const bgk_problem* prob, int32_t batch,
  * exceeds e_max or is not finite. */
 int bgk_status(void* ws, void* stream);
 
+/* Synchronises `stream`, then reads and clears the sticky status of every
+ * workspace that calls of the calling thread's plan enqueued on `stream`
+ * since the last bgk_check(stream), and returns the first non-OK one
+ * (statuses as bgk_status).  Those workspaces must still be allocated: call
+ * it before freeing a workspace that calls on the stream used. */
+int bgk_check(void* stream);
+
+/* ------------------------------------------------------------------ plans --
+ * A plan holds what the library keeps between calls: the HIP graphs captured
+ * for launch-bound sequences (parareal iterations, the serial fine chain,
+ * the uneven batch, the adjoint), the tile shapes bgk_autotune chose, and
+ * the workspaces bgk_check will read.  Every thread starts on the library's
+ * default plan, which lives until the library is unloaded.
+ * bgk_plan_create: a new, empty plan ([host] *plan receives it).
+ * bgk_plan_use: makes `plan` the one the calling thread's later calls use
+ *   (NULL: the default plan again).
+ * bgk_plan_destroy: synchronises the device, destroys the plan's graphs and
+ *   frees it; the calling thread returns to the default plan if it used it;
+ *   other threads must have stopped using it.  NULL is a no-op.
+ * bgk_plan_info: [host] graphs and tuned tile shapes a plan holds (plan NULL:
+ *   the calling thread's plan); outputs nullable.
+ * bgk_plan_save_tiles / bgk_plan_load_tiles: the tuned tile shapes as a JSON
+ *   file, entries keyed by (device architecture, nv[3], nx and batch rounded
+ *   up to powers of two, steps per pass); load merges the entries measured
+ *   on the current device's architecture into the plan (plan NULL: the
+ *   calling thread's plan).  BGK_E_INVALID for a file that cannot be opened
+ *   or parsed. */
+typedef struct bgk_plan bgk_plan;
+int bgk_plan_create(bgk_plan** plan);
+int bgk_plan_use(bgk_plan* plan);
+int bgk_plan_destroy(bgk_plan* plan);
+int bgk_plan_info(const bgk_plan* plan, int32_t* n_graphs, int32_t* n_tiles);
+int bgk_plan_save_tiles(const bgk_plan* plan, const char* path);
+int bgk_plan_load_tiles(bgk_plan* plan, const char* path);
+
 const char* bgk_status_string(int status);
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -370,10 +418,15 @@ const char* bgk_last_error(void);
  * mapping. */
 int bgk_set_tiles(int32_t elems_per_lane, int32_t x_chunk, int32_t pair);
 
-/* Times candidate tile shapes on `prob` with `batch` members (uses ws of
- * BGK_OP_PROPAGATE size; synchronises) and keeps the fastest for problems of
- * the same grid and batch.  [host] best_elems, best_chunk, best_pair
- * (nullable). */
+/* Times candidate tile shapes on `prob` with `batch` members (nine fine
+ * steps from a lift: whole two- and three-step passes; uses ws of
+ * BGK_OP_PROPAGATE size; synchronises) and keeps the fastest in the calling
+ * thread's plan for problems of the same velocity grid, nx and batch
+ * rounded up to powers of two, and steps per pass.  The candidates are the
+ * built-in choice, 2, 4 or 8 velocities per lane by 1 to 48-cell chunks,
+ * paired or not, and the longest three-step chunks the LDS holds; shapes
+ * whose passes need more than 160 KB of LDS are skipped.  [host]
+ * best_elems, best_chunk, best_pair (nullable). */
 int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws,
                  size_t ws_bytes, void* stream, int32_t* best_elems,
                  int32_t* best_chunk, int32_t* best_pair);
@@ -398,11 +451,11 @@ int bgk_set_step_fusion(int32_t steps_per_pass);
  * (default).  Kernel timing (bgk_prof_enable) always launches directly. */
 int bgk_set_graphs(int32_t on);
 
-/* Destroys every cached graph, after synchronising the device (none cached:
- * returns at once, no device call).  The cache is per process, keyed by the
- * workspace, the problem and the launch parameters, so later calls capture
- * again; call it before freeing workspaces to give the graphs' resources
- * back.  [host] */
+/* Destroys every graph cached in the calling thread's plan, after
+ * synchronising the device (none cached: returns at once, no device call).
+ * Graphs are keyed by the workspace, the problem, the launch parameters and
+ * the device pointers they read, so later calls capture again; call it
+ * before freeing workspaces to give the graphs' resources back.  [host] */
 int bgk_release_graphs(void);
 
 /* Kernel timing of the step kernels: when on, every launch of one is

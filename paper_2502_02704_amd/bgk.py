@@ -34,7 +34,9 @@ EXPORTS = [
     "parareal_iterate_force", "bgk_serial_fine_force", "euler_coarse_step_cns",
     "parareal_iterate_cns", "bgk_lift_ce", "bgk_fine_propagate_moments_opts",
     "parareal_iterate_opts", "bgk_serial_fine_opts", "bgk_fine_steps_opts",
-    "bgk_fine_propagate_moments_noalloc",
+    "bgk_fine_propagate_moments_noalloc", "bgk_check", "bgk_plan_create", "bgk_plan_use",
+    "bgk_plan_destroy", "bgk_plan_info", "bgk_plan_save_tiles", "bgk_plan_load_tiles",
+    "bgk_force_bound",
 ]
 
 
@@ -129,6 +131,14 @@ def load_library(path: str = LIB_PATH):
                                            V, V, Z, V]),
         "bgk_fine_propagate_moments_noalloc": (C.c_int, [P, C.c_int32, V, V, C.c_double, V,
                                                          V]),
+        "bgk_check": (C.c_int, [V]),
+        "bgk_plan_create": (C.c_int, [C.POINTER(V)]),
+        "bgk_plan_use": (C.c_int, [V]),
+        "bgk_plan_destroy": (C.c_int, [V]),
+        "bgk_plan_info": (C.c_int, [V, I, I]),
+        "bgk_plan_save_tiles": (C.c_int, [V, C.c_char_p]),
+        "bgk_plan_load_tiles": (C.c_int, [V, C.c_char_p]),
+        "bgk_force_bound": (C.c_int, [P, V, C.c_int32, D, V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -210,17 +220,29 @@ def workspace(p, op: int, batch: int = 1) -> torch.Tensor:
     return w
 
 
+def _drain():
+    """bgk_check on the current stream before workspaces are released (the
+    library reads the status of every workspace a call used since the last
+    check, so none may be freed before it)."""
+    if _lib is not None and torch.cuda.is_available():
+        _lib.bgk_check(C.c_void_p(_stream()))
+
+
 def free_workspaces():
+    _drain()
     _ws.clear()
     _last_ws.clear()
+    _batched_ws.clear()
 
 
 def status(ws: torch.Tensor | None = None) -> int:
-    """Synchronise and return/clear the sticky status of a workspace."""
-    w = ws if ws is not None else (_last_ws[0] if _last_ws else None)
-    if w is None:
-        return OK
-    return int(_gpu_lib().bgk_status(C.c_void_p(w.data_ptr()), C.c_void_p(_stream())))
+    """Synchronise and return/clear the sticky status: of one workspace, or
+    (ws None) of every workspace the calls on the current stream used since
+    the last check (bgk_check)."""
+    L = _gpu_lib()
+    if ws is not None:
+        return int(L.bgk_status(C.c_void_p(ws.data_ptr()), C.c_void_p(_stream())))
+    return int(L.bgk_check(C.c_void_p(_stream())))
 
 
 def check_status(ws: torch.Tensor | None = None):
@@ -231,10 +253,22 @@ def check_status(ws: torch.Tensor | None = None):
 # Functions taking E=None also run the exterior-force variant of the method
 # when E (force at the x centres, [nx], numpy or tensor) is given; its Rusanov
 # coefficient e_max is max |E_i| of those values.
-def _emax(E) -> float:
-    if isinstance(E, torch.Tensor):
-        return float(E.detach().abs().max().item())
-    return float(np.max(np.abs(np.asarray(E, dtype=np.float64))))
+def _emax(p, E) -> float:
+    """The library's Rusanov coefficient max_i |E_i| (bgk_force_bound)."""
+    L = load_library()
+    out = C.c_double()
+    if isinstance(E, torch.Tensor) and E.is_cuda:
+        Ed = E.detach().to(torch.float64).contiguous()
+        rc = L.bgk_force_bound(C.byref(problem_struct(p)), Ed.data_ptr(), 1, C.byref(out),
+                               _stream())
+    else:
+        Eh = np.ascontiguousarray(
+            E.detach().cpu().numpy() if isinstance(E, torch.Tensor) else E, dtype=np.float64)
+        if Eh.shape != (p.nx,):
+            raise ValueError(f"E must have shape ({p.nx},)")
+        rc = L.bgk_force_bound(C.byref(problem_struct(p)), Eh.ctypes.data, 0, C.byref(out), None)
+    _check(rc, "bgk_force_bound")
+    return out.value
 
 
 def _force(p, E):
@@ -242,7 +276,7 @@ def _force(p, E):
     Ed = _f64(E)
     if Ed.shape != (p.nx,):
         raise ValueError(f"E must have shape ({p.nx},)")
-    return Ed, _emax(E)
+    return Ed, _emax(p, Ed)
 
 
 def n_steps(p, t_span: float, E=None) -> Tuple[int, float]:
@@ -251,7 +285,7 @@ def n_steps(p, t_span: float, E=None) -> Tuple[int, float]:
     if E is None:
         rc = L.bgk_n_steps(C.byref(problem_struct(p)), t_span, C.byref(n), C.byref(dt))
     else:
-        rc = L.bgk_n_steps_force(C.byref(problem_struct(p)), _emax(E), t_span, C.byref(n),
+        rc = L.bgk_n_steps_force(C.byref(problem_struct(p)), _emax(p, E), t_span, C.byref(n),
                                  C.byref(dt))
     _check(rc, "bgk_n_steps")
     return n.value, dt.value
@@ -366,6 +400,7 @@ def fine_step_batched(probs: Sequence, fs: Sequence[torch.Tensor], spans: Sequen
     w = _batched_ws.get(key)
     if w is None or w.numel() < nb:
         w = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+        _drain()
         _batched_ws.clear()
         _batched_ws[key] = w
     _last_ws[:] = [w]
@@ -558,6 +593,65 @@ def autotune(p, batch: int = 1) -> Tuple[int, int, int]:
     _check(L.bgk_autotune(C.byref(problem_struct(p)), batch, w.data_ptr(), w.numel(),
                           _stream(), C.byref(e), C.byref(c), C.byref(pr)), "bgk_autotune")
     return e.value, c.value, pr.value
+
+
+class Plan:
+    """A library plan (captured graphs, tuned tiles, the workspace registry
+    of bgk_check); `with Plan() as pl:` makes it the calling thread's plan
+    for the block and destroys it afterwards."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(load_library().bgk_plan_create(C.byref(h)), "bgk_plan_create")
+        self.handle = h
+
+    def use(self):
+        _check(load_library().bgk_plan_use(self.handle), "bgk_plan_use")
+
+    def info(self) -> Tuple[int, int]:
+        g, t = C.c_int32(), C.c_int32()
+        _check(load_library().bgk_plan_info(self.handle, C.byref(g), C.byref(t)),
+               "bgk_plan_info")
+        return g.value, t.value
+
+    def save_tiles(self, path: str):
+        _check(load_library().bgk_plan_save_tiles(self.handle, path.encode()),
+               "bgk_plan_save_tiles")
+
+    def load_tiles(self, path: str):
+        _check(load_library().bgk_plan_load_tiles(self.handle, path.encode()),
+               "bgk_plan_load_tiles")
+
+    def destroy(self):
+        if self.handle:
+            _drain()
+            _check(load_library().bgk_plan_destroy(self.handle), "bgk_plan_destroy")
+            self.handle = None
+
+    def __enter__(self):
+        self.use()
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+        return False
+
+
+def default_plan_info() -> Tuple[int, int]:
+    """(graphs, tuned tile shapes) held by the calling thread's plan."""
+    g, t = C.c_int32(), C.c_int32()
+    _check(load_library().bgk_plan_info(None, C.byref(g), C.byref(t)), "bgk_plan_info")
+    return g.value, t.value
+
+
+def save_tiles(path: str):
+    """The calling thread's plan's tuned tiles as JSON (bgk_plan_save_tiles)."""
+    _check(load_library().bgk_plan_save_tiles(None, path.encode()), "bgk_plan_save_tiles")
+
+
+def load_tiles(path: str):
+    """Merge a tile file into the calling thread's plan (bgk_plan_load_tiles)."""
+    _check(load_library().bgk_plan_load_tiles(None, path.encode()), "bgk_plan_load_tiles")
 
 
 def release_graphs():

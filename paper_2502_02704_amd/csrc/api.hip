@@ -7,15 +7,50 @@
 // operation on the caller's stream.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
+#include <string>
 #include <tuple>
 #include <vector>
 
 #include "bgk_internal.h"
 
 namespace bgk {
+// Tuned tile shape of one grid class: velocity grid, x cells and batch
+// rounded up to powers of two, steps per pass.
+using TileKey = std::tuple<int, int, int, int, int, int>;
+struct Tuned {
+  Tiles t;
+  double ms;         // time of the autotuner's timed sequence
+  std::string arch;  // device architecture it was measured on
+};
+}  // namespace bgk
+
+// What the library keeps between calls (include/bgk.h, plans): captured
+// graphs, tuned tiles, and the workspaces each stream's calls used since its
+// last bgk_check.  Separate locks: a capture (graph lock held) chooses tiles.
+struct bgk_plan {
+  std::mutex graph_mu;
+  std::map<std::string, hipGraphExec_t> graphs;
+  hipStream_t cap_stream = nullptr;  // private stream the graphs are captured on
+  std::mutex tile_mu;
+  std::map<bgk::TileKey, bgk::Tuned> tiles;
+  std::mutex used_mu;
+  std::map<void*, std::set<void*>> used;  // stream -> workspaces
+};
+
+namespace bgk {
+
+static bgk_plan g_default_plan;
+static thread_local bgk_plan* t_plan = nullptr;
+static bgk_plan* cur_plan() { return t_plan ? t_plan : &g_default_plan; }
+
+// Calls made by the allocation-free entry point: no timing events, no
+// workspace registry entries (both would allocate host memory).
+static thread_local bool t_noalloc = false;
 
 // ---------------------------------------------------------------- errors --
 static thread_local std::string g_last_error;
@@ -82,7 +117,15 @@ int n_steps_for(const bgk_problem& p, double t_span, int32_t* n, double* dt, dou
 // ----------------------------------------------------------------- tiles --
 static std::mutex g_mu;
 static Tiles g_override = {0, 0, -1};
-static std::map<std::tuple<int, int, int, int, int>, Tiles> g_tuned;
+
+static int pow2_ceil(long long n) {
+  int v = 1;
+  while (v < n && v < (1 << 30)) v <<= 1;
+  return v;
+}
+static TileKey tile_key(const bgk_problem& p, int batch, int fuse) {
+  return TileKey{p.nv[0], p.nv[1], p.nv[2], pow2_ceil(p.nx), pow2_ceil(batch), fuse};
+}
 
 static long long nv3_of(const bgk_problem& p) {
   return (long long)p.nv[0] * p.nv[1] * p.nv[2];
@@ -112,7 +155,7 @@ static int g_fuse = 3;  // IMEX steps per pass (1, 2 or 3) where possible
 // LDS and chunk limits of the three-step kernel.  With 4 velocities per lane
 // (233 VGPRs) a CU holds one 8-wave block, which may then take all 160 KB of
 // gfx950's LDS; with 2 (123 VGPRs) two blocks share it.
-static size_t lds3_cap(int elems) { return elems == 4 ? 163840 : 65536; }
+static size_t lds3_cap(int elems) { return elems == 4 ? (size_t)kLdsBytes : 65536; }
 static int lds3_max_chunk(int elems) { return elems == 4 ? 48 : 24; }
 
 // The v_x-column mapping fits a grid whose tiles fit the partial-sum capacity.
@@ -128,7 +171,16 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
   // over short chunks; fused passes on unpaired lanes (odd nv_z) take 4
   // (8 spill in their two-step march)
   Tiles t = g_fuse >= 2 ? (pair ? Tiles{8, 8, 1} : Tiles{4, 8, 0}) : Tiles{8, 4, pair};
-  auto it = g_tuned.find({p.nx, p.nv[0], p.nv[1], p.nv[2], batch});
+  bool tuned = false;
+  if (!generic && !force && !limited) {
+    bgk_plan* pl = cur_plan();
+    std::lock_guard<std::mutex> lt(pl->tile_mu);
+    auto it = pl->tiles.find(tile_key(p, batch, g_fuse));
+    if (it != pl->tiles.end() && (it->second.t.pair == 0 || pair)) {
+      t = it->second.t;
+      tuned = true;
+    }
+  }
   const long long cells = (long long)batch * p.nx * nv3_of(p);
   // The exterior-force step runs on v_x columns (the v_x neighbours of a
   // lane's elements in its own registers) when a v_x plane fills a wave, or
@@ -160,8 +212,9 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
     t = (limited && !force && nv3_of(p) >= 4 * kWave * 4) ? Tiles{4, 64, 0}
                                                           : Tiles{2, limited ? 16 : 8, 0};
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 512) t.chunk /= 2;
-  } else if (it != g_tuned.end()) t = it->second;
-  else if (pair && g_fuse >= 2 && cells < (1LL << 24)) {
+  } else if (tuned) {
+    // a shape bgk_autotune measured for this grid class
+  } else if (pair && g_fuse >= 2 && cells < (1LL << 24)) {
     // latency-bound sizes (f fits the last-level cache): short velocity
     // tiles, x chunks as long as the grid keeps about two blocks per CU
     t = Tiles{2, 16, 1};
@@ -193,6 +246,18 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
   if ((g_override.pair == 0 || g_override.pair == 1) && p.nv[2] % 2 == 0 && !generic)
     t.pair = g_override.pair;
   if (limited && t.elems > 4) t.elems = 4;  // second-order flat kernels take 2 or 4
+  // keep the factor rows a step kernel stages within gfx950's 160 KB of LDS
+  // (x-flat mappings: chunk + 2 rows per level, + 4 with the limiter, two
+  // levels of 2 chunk + 6 rows in the fused two-step pass)
+  if (!t.vcol) {
+    const long long nvs = (long long)p.nv[0] + p.nv[1] + p.nv[2];
+    auto rows = [&](int c) -> long long {
+      if (limited) return c + 4;
+      return g_fuse >= 2 ? 2LL * c + 6 : c + 2;
+    };
+    while (t.chunk > 1 && rows(t.chunk) * nvs * (long long)sizeof(double) > kLdsBytes)
+      t.chunk /= 2;
+  }
   return t;
 }
 
@@ -325,6 +390,15 @@ static int check_ws(void* ws, size_t ws_bytes, size_t need) {
     return BGK_E_WORKSPACE;
   }
   return BGK_OK;
+}
+
+// Records that a call enqueued on `stream` uses workspace `ws`, whose sticky
+// status bgk_check(stream) reads.
+static void note_ws(void* ws, void* stream) {
+  if (t_noalloc) return;
+  bgk_plan* pl = cur_plan();
+  std::lock_guard<std::mutex> lk(pl->used_mu);
+  pl->used[stream].insert(ws);
 }
 
 // -------------------------------------------------- descriptor uploads --
@@ -669,21 +743,18 @@ static hipEvent_t prof_event() {
   return e;
 }
 
-// Calls that must not create events (the no-allocation entry point) turn
-// timing off for their own thread.
-static thread_local bool t_prof_off = false;
-void prof_suppress(bool off) { t_prof_off = off; }
+void noalloc_mode(bool on) { t_noalloc = on; }
 
 void prof_before(hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  if (!g_prof_on || t_prof_off) return;
+  if (!g_prof_on || t_noalloc) return;
   g_prof_pending = prof_event();
   if (g_prof_pending) (void)hipEventRecord(g_prof_pending, s);
 }
 
 void prof_after(hipStream_t s, double cells, double bytes_per_cell, int kind) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  if (!g_prof_on || t_prof_off || !g_prof_pending) return;
+  if (!g_prof_on || t_noalloc || !g_prof_pending) return;
   hipEvent_t e = prof_event();
   if (!e) return;
   (void)hipEventRecord(e, s);
@@ -696,11 +767,9 @@ void prof_after(hipStream_t s, double cells, double bytes_per_cell, int kind) {
 // solves) are captured once per (workspace, shape, iteration) on a private
 // capture stream and replayed on the caller's stream.  Everything a captured
 // sequence touches lives in the workspace, so the key names the workspace.
-static std::mutex g_graph_mu;
+static std::mutex g_graph_mu;  // guards g_graphs_on
 static bool g_graphs_on = true;
-static std::map<std::string, hipGraphExec_t> g_graphs;
-static hipStream_t g_cap_stream = nullptr;
-constexpr size_t kMaxGraphs = 512;
+constexpr size_t kMaxGraphs = 512;  // per plan; a full plan is emptied
 
 // The fields of a problem as key bytes (not the struct's own bytes: the
 // padding after bc is whatever the caller left there).
@@ -713,14 +782,19 @@ static void add_problem_key(std::string& k, const bgk_problem& p) {
   k.append(reinterpret_cast<const char*>(v), sizeof(v));
 }
 
+// Key of a captured sequence: its tag, the workspace, the problem, the
+// launch parameters xs and the raw bytes of the device pointers it reads
+// or writes outside the workspace.
 static std::string graph_key(const char* tag, const void* ws, size_t ws_bytes,
-                             const bgk_problem& p, std::initializer_list<double> xs) {
+                             const bgk_problem& p, std::initializer_list<double> xs,
+                             std::initializer_list<const void*> ptrs = {}) {
   std::string k(tag);
   auto add = [&](const void* q, size_t n) { k.append(static_cast<const char*>(q), n); };
   add(&ws, sizeof(ws));
   add(&ws_bytes, sizeof(ws_bytes));
   add_problem_key(k, p);
   for (double x : xs) add(&x, sizeof(x));
+  for (const void* q : ptrs) add(&q, sizeof(q));
   return k;
 }
 
@@ -732,19 +806,21 @@ static int run_graph(const std::string& key, hipStream_t user, F&& enqueue) {
     use = g_graphs_on && !g_prof_on;
   }
   if (!use) return enqueue(user);
-  std::lock_guard<std::mutex> lk(g_graph_mu);
-  auto it = g_graphs.find(key);
-  if (it == g_graphs.end()) {
-    if (g_graphs.size() >= kMaxGraphs) {
+  bgk_plan* pl = cur_plan();
+  std::lock_guard<std::mutex> lk(pl->graph_mu);
+  auto it = pl->graphs.find(key);
+  if (it == pl->graphs.end()) {
+    if (pl->graphs.size() >= kMaxGraphs) {
       BGK_HIP(hipDeviceSynchronize());
-      for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
-      g_graphs.clear();
+      for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+      pl->graphs.clear();
     }
-    if (!g_cap_stream) BGK_HIP(hipStreamCreateWithFlags(&g_cap_stream, hipStreamNonBlocking));
-    BGK_HIP(hipStreamBeginCapture(g_cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue(g_cap_stream);
+    if (!pl->cap_stream)
+      BGK_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+    BGK_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue(pl->cap_stream);
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(g_cap_stream, &g);
+    hipError_t e = hipStreamEndCapture(pl->cap_stream, &g);
     if (rc || e != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
       return rc ? rc : hip_fail(e, "hipStreamEndCapture");
@@ -753,7 +829,7 @@ static int run_graph(const std::string& key, hipStream_t user, F&& enqueue) {
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-    it = g_graphs.emplace(key, ex).first;
+    it = pl->graphs.emplace(key, ex).first;
   }
   BGK_HIP(hipGraphLaunch(it->second, user));
   return BGK_OK;
@@ -851,16 +927,97 @@ int bgk_n_steps(const bgk_problem* prob, double t_span, int32_t* n, double* dt) 
   return BGK_OK;
 }
 
-int bgk_status(void* ws, void* stream) {
-  if (ws == nullptr) return BGK_E_WORKSPACE;
-  hipStream_t s = (hipStream_t)stream;
-  BGK_HIP(hipStreamSynchronize(s));
+}  // extern "C"
+
+namespace bgk {
+// Reads and clears the sticky status word of ws (stream already idle).
+static int take_status(void* ws, hipStream_t s) {
   int st = 0;
   BGK_HIP(hipMemcpy(&st, at<WsHeader>(ws, 0), sizeof(int), hipMemcpyDeviceToHost));
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, &at<WsHeader>(ws, 0)->status, 0);
   BGK_HIP(hipGetLastError());
   BGK_HIP(hipStreamSynchronize(s));
   return status_code(st);
+}
+}  // namespace bgk
+
+extern "C" {
+
+int bgk_status(void* ws, void* stream) {
+  if (ws == nullptr) return BGK_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  BGK_HIP(hipStreamSynchronize(s));
+  return take_status(ws, s);
+}
+
+int bgk_check(void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  BGK_HIP(hipStreamSynchronize(s));
+  std::set<void*> list;
+  {
+    bgk_plan* pl = cur_plan();
+    std::lock_guard<std::mutex> lk(pl->used_mu);
+    auto it = pl->used.find(stream);
+    if (it == pl->used.end()) return BGK_OK;
+    list.swap(it->second);
+    pl->used.erase(it);
+  }
+  int worst = BGK_OK;
+  std::string msg;
+  for (void* ws : list) {
+    const int rc = take_status(ws, s);
+    if (rc != BGK_OK && worst == BGK_OK) {
+      worst = rc;
+      msg = g_last_error;
+    }
+  }
+  if (worst != BGK_OK && worst != BGK_E_HIP) set_error(msg);
+  return worst;
+}
+
+// ------------------------------------------------------------------ plans --
+int bgk_plan_create(bgk_plan** plan) {
+  if (!plan) return invalid("plan is NULL");
+  *plan = new (std::nothrow) bgk_plan();
+  if (!*plan) {
+    set_error("out of host memory for a plan");
+    return BGK_E_INVALID;
+  }
+  return BGK_OK;
+}
+
+int bgk_plan_use(bgk_plan* plan) {
+  t_plan = plan;
+  return BGK_OK;
+}
+
+int bgk_plan_destroy(bgk_plan* plan) {
+  if (!plan) return BGK_OK;
+  if (plan == &g_default_plan) return invalid("the default plan cannot be destroyed");
+  if (t_plan == plan) t_plan = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(plan->graph_mu);
+    if (!plan->graphs.empty() || plan->cap_stream) {
+      BGK_HIP(hipDeviceSynchronize());
+      for (auto& kv : plan->graphs) (void)hipGraphExecDestroy(kv.second);
+      plan->graphs.clear();
+      if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+      plan->cap_stream = nullptr;
+    }
+  }
+  delete plan;
+  return BGK_OK;
+}
+
+int bgk_plan_info(const bgk_plan* plan, int32_t* n_graphs, int32_t* n_tiles) {
+  bgk_plan* pl = plan ? const_cast<bgk_plan*>(plan) : cur_plan();
+  {
+    std::lock_guard<std::mutex> lk(pl->graph_mu);
+    if (n_graphs) *n_graphs = (int32_t)pl->graphs.size();
+  }
+  std::lock_guard<std::mutex> lk(pl->tile_mu);
+  if (n_tiles) *n_tiles = (int32_t)pl->tiles.size();
+  return BGK_OK;
 }
 
 int bgk_lift(const bgk_problem* prob, const double* W, double* f, void* ws,
@@ -870,6 +1027,7 @@ int bgk_lift(const bgk_problem* prob, const double* W, double* f, void* ws,
   if (!W || !f) return invalid("NULL array");
   const Layout L = layout_of(*prob, BGK_OP_LIFT, 1);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  note_ws(ws, stream);
   hipStream_t s = (hipStream_t)stream;
   const Tiles t = choose_tiles(*prob, 1);
   Inst I = make_inst(*prob, 1, 1.0, t);
@@ -889,6 +1047,7 @@ int bgk_moments(const bgk_problem* prob, const double* f, double* V, double* W,
   if (!f) return invalid("NULL array");
   const Layout L = layout_of(*prob, BGK_OP_MOMENTS, 1);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  note_ws(ws, stream);
   hipStream_t s = (hipStream_t)stream;
   Tiles t = choose_tiles(*prob, 1);
   t.pair = 0;  // the moment-partials kernel uses the generic lane mapping
@@ -918,6 +1077,7 @@ static int fine_steps_impl(const bgk_problem* prob, const Force& F, const double
   if (a0 < b0 + fbytes && b0 < a0 + fbytes) return invalid("f_in and f_out overlap");
   const Layout L = layout_of(*prob, BGK_OP_FINE_STEP, 1);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  note_ws(ws, stream);
   hipStream_t s = (hipStream_t)stream;
   if (n_steps == 0) {
     BGK_HIP(hipMemcpyAsync(f_out, f_in, fbytes, hipMemcpyDeviceToDevice, s));
@@ -996,6 +1156,7 @@ static int propagate_impl(const bgk_problem* prob, const Force& F, int lift_orde
   if ((rc = n_steps_for(*prob, t_span, &n, &dt, F.emax))) return rc;
   const Layout L = layout_of(*prob, BGK_OP_PROPAGATE, batch);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  note_ws(ws, stream);
   hipStream_t s = (hipStream_t)stream;
   const Tiles t = fine_tiles(*prob, batch, F);
   Inst I = make_inst(*prob, batch, dt, t, fine_nsum(t, n, F));
@@ -1053,6 +1214,7 @@ static int euler_impl(const bgk_problem* prob, const double* E, bool viscous, in
   if (!(t_span > 0.0) || !std::isfinite(t_span)) return invalid("t_span must be > 0");
   const Layout L = layout_of(*prob, BGK_OP_COARSE, batch);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  note_ws(ws, stream);
   return launch_euler(*prob, batch, V_in, V_out, t_span, n_sub_out,
                       at<double>(ws, L.coarse), &at<WsHeader>(ws, 0)->status,
                       (hipStream_t)stream, E, viscous);
@@ -1099,6 +1261,7 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
   if ((rc = n_steps_for(*prob, span, &n, &dt, F.emax))) return rc;
   const Layout L = layout_of(*prob, BGK_OP_PARAREAL, n_slices);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  note_ws(ws, stream);
   hipStream_t s = (hipStream_t)stream;
   WsHeader* hd = at<WsHeader>(ws, 0);
   int* st = &hd->status;
@@ -1141,8 +1304,9 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
                                   {(double)n_slices, span, (double)k, (double)t.elems,
                                    (double)t.chunk, (double)(t.pair + 2 * t.vcol),
                                    (double)I.nsum, (double)fuse_mode(),
-                                   tol > 0.0 ? 1.0 : 0.0, (double)(uintptr_t)F.E, F.emax,
-                                   viscous ? 1.0 : 0.0, (double)lift_order}),
+                                   tol > 0.0 ? 1.0 : 0.0, F.emax,
+                                   viscous ? 1.0 : 0.0, (double)lift_order},
+                                  {F.E}),
                         s, iteration)))
       return rc;
     cur ^= 1;
@@ -1157,6 +1321,9 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
     BGK_HIP(hipStreamSynchronize(s));
     err_hist[k] = h.err;
     if (h.status) {
+      // reported here: cleared, so that a later check does not report it again
+      hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, st, 0);
+      BGK_HIP(hipGetLastError());
       if (k_done) *k_done = kd;
       set_error("non-physical state during parareal iteration");
       return status_code(h.status);
@@ -1170,6 +1337,8 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
     BGK_HIP(hipMemcpyAsync(&st_h, st, sizeof(int), hipMemcpyDeviceToHost, s));
     BGK_HIP(hipStreamSynchronize(s));
     if (st_h) {
+      hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, st, 0);
+      BGK_HIP(hipGetLastError());
       if (k_done) *k_done = kd;
       set_error("non-physical state during parareal iteration");
       return status_code(st_h);
@@ -1221,6 +1390,7 @@ static int serial_impl(const bgk_problem* prob, const Force& F, int lift_order,
   if ((rc = n_steps_for(*prob, span, &n, &dt, F.emax))) return rc;
   const Layout L = layout_of(*prob, BGK_OP_PARAREAL, n_slices);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  note_ws(ws, stream);
   hipStream_t s = (hipStream_t)stream;
   int* st = &at<WsHeader>(ws, 0)->status;
   const size_t sl = (size_t)prob->nx * 5;
@@ -1248,9 +1418,9 @@ static int serial_impl(const bgk_problem* prob, const Force& F, int lift_order,
   if ((rc = run_graph(graph_key("ser", ws, ws_bytes, *prob,
                                 {(double)n_slices, span, (double)t.elems, (double)t.chunk,
                                  (double)(t.pair + 2 * t.vcol), (double)ns,
-                                 (double)fuse_mode(),
-                                 (double)(uintptr_t)F.E, F.emax,
-                                 (double)lift_order}),
+                                 (double)fuse_mode(), F.emax,
+                                 (double)lift_order},
+                                {F.E}),
                       s, chain)))
     return rc;
   BGK_HIP(hipMemcpyAsync(V_out, U, sl * (n_slices + 1) * sizeof(double),
@@ -1331,6 +1501,7 @@ int bgk_lift_ce(const bgk_problem* prob, const double* W, double* f, void* ws,
   if (!W || !f) return invalid("NULL array");
   const Layout L = layout_of(*prob, BGK_OP_LIFT, 1);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  note_ws(ws, stream);
   hipStream_t s = (hipStream_t)stream;
   const Tiles t = choose_tiles(*prob, 1);
   Inst I = make_inst(*prob, 1, 1.0, t);
@@ -1370,11 +1541,12 @@ int bgk_set_graphs(int32_t on) {
 }
 
 int bgk_release_graphs(void) {
-  std::lock_guard<std::mutex> lk(g_graph_mu);
-  if (g_graphs.empty()) return BGK_OK;
+  bgk_plan* pl = cur_plan();
+  std::lock_guard<std::mutex> lk(pl->graph_mu);
+  if (pl->graphs.empty()) return BGK_OK;
   BGK_HIP(hipDeviceSynchronize());
-  for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
-  g_graphs.clear();
+  for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+  pl->graphs.clear();
   return BGK_OK;
 }
 
@@ -1396,6 +1568,7 @@ int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
   }
   const Layout L = layout_of(*prob, BGK_OP_ADJOINT, ckpt_every);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  note_ws(ws, stream);
   hipStream_t s = (hipStream_t)stream;
   int* st = &at<WsHeader>(ws, 0)->status;
   const Tiles t = choose_tiles(*prob, 1);
@@ -1448,10 +1621,9 @@ int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
   // the whole sequence (about 11 launches per step) is captured once per
   // (workspace, problem, buffers, steps) and replayed
   return run_graph(graph_key("adj", ws, ws_bytes, *prob,
-                             {(double)(uintptr_t)f_ckpt, (double)ckpt_every, (double)n_steps,
-                              dt, (double)(uintptr_t)fbar_T, (double)(uintptr_t)fbar_0,
-                              (double)(uintptr_t)dlog_eps, (double)t.elems, (double)t.chunk,
-                              (double)(t.pair + 2 * t.vcol)}),
+                             {(double)ckpt_every, (double)n_steps, dt, (double)t.elems,
+                              (double)t.chunk, (double)(t.pair + 2 * t.vcol)},
+                             {f_ckpt, fbar_T, fbar_0, dlog_eps}),
                    s, sequence);
 }
 
@@ -1463,6 +1635,7 @@ int bgk_lift_adjoint_rho(const bgk_problem* prob, const double* W,
   if (!W || !fbar || !rhobar) return invalid("NULL array");
   const Layout L = layout_of(*prob, BGK_OP_LIFT, 1);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  note_ws(ws, stream);
   hipStream_t s = (hipStream_t)stream;
   const Tiles t = choose_tiles(*prob, 1);
   Inst I = make_inst(*prob, 1, 1.0, t);
@@ -1538,6 +1711,7 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   }
   const BatchedLayout L = batched_layout(probs, n);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  note_ws(ws, stream);
   if (n_steps_out)
     for (int q = 0; q < n; ++q) n_steps_out[q] = steps[q];
   hipStream_t s = (hipStream_t)stream;
@@ -1733,6 +1907,40 @@ int bgk_set_tiles(int32_t elems, int32_t chunk, int32_t pair) {
   return BGK_OK;
 }
 
+}  // extern "C"
+
+namespace bgk {
+// Architecture name of the current device ("gfx950"), looked up once per
+// device.
+static std::string device_arch() {
+  static std::mutex mu;
+  static std::map<int, std::string> names;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = names.find(dev);
+  if (it != names.end()) return it->second;
+  hipDeviceProp_t prop;
+  std::string name = "unknown";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    name = prop.gcnArchName;
+    const size_t c = name.find(':');
+    if (c != std::string::npos) name = name.substr(0, c);
+  }
+  names[dev] = name;
+  return name;
+}
+
+// LDS bytes of the passes a fused sequence of `steps` steps runs with tiles t.
+static long long seq_lds_bytes(const Inst& h, Tiles t, int steps) {
+  if (fused_for(t, steps) && triple_for(h, t)) return (long long)lds_doubles3(h, t) * 8;
+  if (fused_for(t, steps)) return (long long)lds_doubles2(h, t) * 8;
+  return (long long)lds_doubles(h, t) * 8;
+}
+}  // namespace bgk
+
+extern "C" {
+
 int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_bytes,
                  void* stream, int32_t* best_elems, int32_t* best_chunk,
                  int32_t* best_pair) {
@@ -1741,6 +1949,7 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_byt
   if (batch < 1) return invalid("batch must be >= 1");
   const Layout L = layout_of(*prob, BGK_OP_PROPAGATE, batch);
   if ((rc = check_ws(ws, ws_bytes, L.total))) return rc;
+  note_ws(ws, stream);
   hipStream_t s = (hipStream_t)stream;
   // moments of a smooth state to lift from
   std::vector<double> hV((size_t)batch * prob->nx * 5);
@@ -1753,58 +1962,220 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_byt
     }
   double* Vin = at<double>(ws, L.fine.vg);   // borrow: lifted from before steps
   double* Vout = at<double>(ws, L.fine.vout);
-  // six steps: whole passes both with two and with three steps per pass
-  const int steps = 6;
+  // nine steps: whole passes with three steps per pass (one from the lift,
+  // two reading and writing f) and with two
+  const int steps = 9;
   const double dt = 0.5 * dx_of(*prob) / std::max(std::fabs(prob->v_lo[0]), std::fabs(prob->v_hi[0]));
-  hipEvent_t e0, e1;
-  BGK_HIP(hipEventCreate(&e0));
-  BGK_HIP(hipEventCreate(&e1));
-  Tiles best = {0, 0, 0};
-  float best_ms = 1e30f;
+  const int fuse = fuse_mode();
+  // candidates: the built-in choice (without a tuned entry), a grid of
+  // shapes, and for three-step grids the longest chunks whose factor rows fit
+  // the LDS; shapes whose passes would need more than 160 KB of LDS are left
+  // out
+  std::vector<Tiles> cands;
+  {
+    bgk_plan* pl = cur_plan();
+    std::map<TileKey, Tuned> saved;
+    {
+      std::lock_guard<std::mutex> lk(pl->tile_mu);
+      saved.swap(pl->tiles);
+    }
+    cands.push_back(choose_tiles(*prob, batch));
+    std::lock_guard<std::mutex> lk(pl->tile_mu);
+    for (auto& kv : saved) pl->tiles.emplace(kv.first, kv.second);
+  }
   const int Es[3] = {2, 4, 8};
   const int Cs[8] = {1, 2, 4, 8, 16, 24, 32, 48};
   for (int pr = 0; pr < 2; ++pr)
-  for (int ei = 0; ei < 3; ++ei)
-    for (int ci = 0; ci < 8; ++ci) {
-      Tiles t = {Es[ei], Cs[ci], pr};
-      if (t.chunk > prob->nx || (pr && prob->nv[2] % 2 != 0)) continue;
-      Inst I = make_inst(*prob, batch, dt, t, fused_for(t, steps) ? 15 : 5);
-      attach_fine(I, ws, L.fine, nullptr);
-      I.vin = Vin;
-      I.vout = Vout;
-      Inst* dI = at<Inst>(ws, L.insts);
-      int* st = &at<WsHeader>(ws, 0)->status;
-      float ms = 0.f;
-      for (int rep = 0; rep < 2; ++rep) {
-        BGK_HIP(hipMemcpyAsync(Vin, hV.data(), hV.size() * sizeof(double),
-                               hipMemcpyHostToDevice, s));
-        if ((rc = put_insts(dI, &I, 1, s))) break;
-        BGK_HIP(hipEventRecord(e0, s));
-        int last = 0;
-        if ((rc = lift_and_run(dI, I, steps, false, t, st, s, &last))) break;
-        BGK_HIP(hipEventRecord(e1, s));
-        BGK_HIP(hipEventSynchronize(e1));
-        BGK_HIP(hipEventElapsedTime(&ms, e0, e1));
-      }
-      if (rc) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return rc;
-      }
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = t;
+    for (int ei = 0; ei < 3; ++ei) {
+      for (int ci = 0; ci < 8; ++ci) cands.push_back(Tiles{Es[ei], Cs[ci], pr});
+      if (pr && Es[ei] <= 4) {
+        const long long nvs = (long long)prob->nv[0] + prob->nv[1] + prob->nv[2];
+        int ch = 64;
+        while (ch > 1 && (3LL * ch + 12) * nvs * 8 > (long long)lds3_cap(Es[ei])) --ch;
+        cands.push_back(Tiles{Es[ei], ch, 1});
       }
     }
+  hipEvent_t e0, e1;
+  BGK_HIP(hipEventCreate(&e0));
+  BGK_HIP(hipEventCreate(&e1));
+  Tiles best = cands[0];
+  float best_ms = 1e30f;
+  std::set<std::tuple<int, int, int>> seen;
+  for (const Tiles& t : cands) {
+    if (t.chunk < 1 || t.chunk > prob->nx || (t.pair && prob->nv[2] % 2 != 0)) continue;
+    if (!seen.insert({t.elems, t.chunk, t.pair}).second) continue;
+    Inst I = make_inst(*prob, batch, dt, t, fused_for(t, steps) ? 15 : 5);
+    if (seq_lds_bytes(I, t, steps) > kLdsBytes) continue;
+    attach_fine(I, ws, L.fine, nullptr);
+    I.vin = Vin;
+    I.vout = Vout;
+    Inst* dI = at<Inst>(ws, L.insts);
+    int* st = &at<WsHeader>(ws, 0)->status;
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+      BGK_HIP(hipMemcpyAsync(Vin, hV.data(), hV.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+      if ((rc = put_insts(dI, &I, 1, s))) break;
+      BGK_HIP(hipEventRecord(e0, s));
+      int last = 0;
+      if ((rc = lift_and_run(dI, I, steps, false, t, st, s, &last))) break;
+      BGK_HIP(hipEventRecord(e1, s));
+      BGK_HIP(hipEventSynchronize(e1));
+      BGK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    }
+    if (rc) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return rc;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   {
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_tuned[{prob->nx, prob->nv[0], prob->nv[1], prob->nv[2], batch}] = best;
+    bgk_plan* pl = cur_plan();
+    std::lock_guard<std::mutex> lk(pl->tile_mu);
+    pl->tiles[tile_key(*prob, batch, fuse)] = Tuned{best, (double)best_ms, device_arch()};
   }
   if (best_elems) *best_elems = best.elems;
   if (best_chunk) *best_chunk = best.chunk;
   if (best_pair) *best_pair = best.pair;
+  return BGK_OK;
+}
+
+// Tuned tiles as JSON: {"bgk_tiles": 1, "entries": [{"arch": "gfx950",
+// "nv": [a, b, c], "nx_bucket": n, "batch_bucket": m, "steps_per_pass": k,
+// "elems": e, "chunk": c, "pair": p, "ms": t}, ...]}
+int bgk_plan_save_tiles(const bgk_plan* plan, const char* path) {
+  if (!path) return invalid("path is NULL");
+  bgk_plan* pl = plan ? const_cast<bgk_plan*>(plan) : cur_plan();
+  std::string out = "{\"bgk_tiles\": 1, \"entries\": [";
+  {
+    std::lock_guard<std::mutex> lk(pl->tile_mu);
+    bool first = true;
+    for (auto& kv : pl->tiles) {
+      const TileKey& k = kv.first;
+      const Tuned& v = kv.second;
+      char buf[512];
+      std::snprintf(buf, sizeof(buf),
+                    "%s\n  {\"arch\": \"%s\", \"nv\": [%d, %d, %d], \"nx_bucket\": %d, "
+                    "\"batch_bucket\": %d, \"steps_per_pass\": %d, \"elems\": %d, "
+                    "\"chunk\": %d, \"pair\": %d, \"ms\": %.6g}",
+                    first ? "" : ",", v.arch.c_str(), std::get<0>(k), std::get<1>(k),
+                    std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k),
+                    v.t.elems, v.t.chunk, v.t.pair, v.ms);
+      out += buf;
+      first = false;
+    }
+  }
+  out += "\n]}\n";
+  FILE* fh = std::fopen(path, "w");
+  if (!fh) return invalid("cannot open the tile file for writing");
+  const size_t wr = std::fwrite(out.data(), 1, out.size(), fh);
+  const int cl = std::fclose(fh);
+  if (wr != out.size() || cl != 0) return invalid("cannot write the tile file");
+  return BGK_OK;
+}
+
+}  // extern "C"
+
+namespace bgk {
+// Value text after "name": in one entry object (nullptr if absent).
+static const char* json_field(const std::string& obj, const char* name, size_t* pos) {
+  const std::string k = std::string("\"") + name + "\"";
+  const size_t a = obj.find(k);
+  if (a == std::string::npos) return nullptr;
+  const size_t c = obj.find(':', a + k.size());
+  if (c == std::string::npos) return nullptr;
+  *pos = c + 1;
+  return obj.c_str() + c + 1;
+}
+static bool json_int(const std::string& obj, const char* name, int* v) {
+  size_t pos;
+  const char* t = json_field(obj, name, &pos);
+  return t && std::sscanf(t, " %d", v) == 1;
+}
+}  // namespace bgk
+
+extern "C" {
+
+int bgk_plan_load_tiles(bgk_plan* plan, const char* path) {
+  if (!path) return invalid("path is NULL");
+  FILE* fh = std::fopen(path, "r");
+  if (!fh) return invalid("cannot open the tile file");
+  std::string txt;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof(buf), fh)) > 0) txt.append(buf, n);
+  std::fclose(fh);
+  if (txt.find("\"bgk_tiles\"") == std::string::npos) return invalid("not a tile file");
+  bgk_plan* pl = plan ? plan : cur_plan();
+  std::vector<std::pair<std::string, std::pair<TileKey, Tuned>>> entries;
+  size_t at_ = txt.find('[');
+  if (at_ == std::string::npos) return invalid("tile file has no entries");
+  for (;;) {
+    const size_t a = txt.find('{', at_);
+    if (a == std::string::npos) break;
+    const size_t b = txt.find('}', a);
+    if (b == std::string::npos) return invalid("truncated tile file");
+    const std::string obj = txt.substr(a, b - a + 1);
+    at_ = b + 1;
+    size_t pos;
+    const char* t = json_field(obj, "arch", &pos);
+    char a_name[64] = {0};
+    if (!t || std::sscanf(t, " \"%63[^\"]\"", a_name) != 1) return invalid("tile entry without arch");
+    int nv[3], nxb, bb, fu, e, c, pr;
+    const char* tv = json_field(obj, "nv", &pos);
+    if (!tv || std::sscanf(tv, " [ %d , %d , %d ]", &nv[0], &nv[1], &nv[2]) != 3 ||
+        !json_int(obj, "nx_bucket", &nxb) || !json_int(obj, "batch_bucket", &bb) ||
+        !json_int(obj, "steps_per_pass", &fu) || !json_int(obj, "elems", &e) ||
+        !json_int(obj, "chunk", &c) || !json_int(obj, "pair", &pr))
+      return invalid("malformed tile entry");
+    if (!(e == 2 || e == 4 || e == 8) || c < 1 || c > kMaxChunk || pr < 0 || pr > 1)
+      return invalid("tile entry out of range");
+    double ms = 0.0;
+    const char* tm = json_field(obj, "ms", &pos);
+    if (tm) std::sscanf(tm, " %lf", &ms);
+    entries.push_back({a_name, {TileKey{nv[0], nv[1], nv[2], nxb, bb, fu},
+                                Tuned{Tiles{e, c, pr, 0}, ms, a_name}}});
+  }
+  if (entries.empty()) return BGK_OK;
+  const std::string arch = device_arch();
+  std::lock_guard<std::mutex> lk(pl->tile_mu);
+  for (auto& en : entries)
+    if (en.first == arch) pl->tiles[en.second.first] = en.second.second;  // else another arch
+  return BGK_OK;
+}
+
+// max |E_i| of an exterior force (the Rusanov coefficient of the v_x flux).
+int bgk_force_bound(const bgk_problem* prob, const double* E, int32_t E_on_device,
+                    double* e_max, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!E || !e_max) return invalid("NULL array");
+  std::vector<double> h;
+  const double* src = E;
+  if (E_on_device) {
+    // nx values: read back on the stream rather than reduced on the device
+    h.resize(prob->nx);
+    hipStream_t s = (hipStream_t)stream;
+    BGK_HIP(hipMemcpyAsync(h.data(), E, sizeof(double) * prob->nx, hipMemcpyDeviceToHost, s));
+    BGK_HIP(hipStreamSynchronize(s));
+    src = h.data();
+  }
+  double m = 0.0;
+  for (int i = 0; i < prob->nx; ++i) {
+    const double a = std::fabs(src[i]);
+    if (std::isnan(a)) {
+      m = a;
+      break;
+    }
+    m = std::max(m, a);
+  }
+  *e_max = m;
   return BGK_OK;
 }
 

@@ -19,6 +19,7 @@ constexpr int kPartElems = 32;       // fewest velocities behind one partial sum
 constexpr int kMaxNv = 256;          // per velocity axis
 constexpr int kMaxChunk = 64;        // x cells per work item
 constexpr int kNumXcd = 8;           // MI355X: 8 accelerator complex dies
+constexpr long long kLdsBytes = 163840;  // gfx950 LDS per workgroup (160 KB)
 
 // One problem (or a batch of same-grid members) as the kernels see it.  All
 // members b share the grid; member b's arrays start at b * (member stride).
@@ -262,8 +263,9 @@ int launch_lift_adjoint_rho(const Inst* d_inst, const Inst& h_inst,
 constexpr int kAdjElems = 4;  // velocity elements per lane in adjoint kernels
 
 // Timing of the step kernels; kind is one of the BGK_PROF_* tags.
-// prof_suppress(true) turns it off for the calling thread (no events made).
-void prof_suppress(bool off);
+// noalloc_mode(true): the calling thread's calls make no timing events and
+// no workspace registry entries (the allocation-free entry point).
+void noalloc_mode(bool on);
 void prof_before(hipStream_t s);
 void prof_after(hipStream_t s, double cells, double bytes_per_cell, int kind);
 

@@ -5,8 +5,9 @@
 // per-wave moment partials, Maxwellian factor rows and per-cell sums.  Here
 // that workspace is a file-scope device array of fixed size, so the call
 // itself allocates nothing (no hipMalloc, no library allocation, no timing
-// events) and can run inside HIP graph capture or a loop that must not
-// allocate.  Every call on a device shares that device's array.
+// events, no host-side bookkeeping) and can run inside HIP graph capture or
+// a loop that must not allocate.  Every call on a device shares that
+// device's array.
 #include <mutex>
 
 #include "bgk_internal.h"
@@ -88,10 +89,10 @@ extern "C" int bgk_fine_propagate_moments_noalloc(const bgk_problem* prob, int32
   int* st = &reinterpret_cast<WsHeader*>(ws)->status;
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, st);
   BGK_HIP(hipGetLastError());
-  prof_suppress(true);
+  noalloc_mode(true);
   rc = propagate_plain(prob, batch, V_in, V_out, t_span, ws, (size_t)BGK_NOALLOC_SCRATCH_BYTES,
                        stream);
-  prof_suppress(false);
+  noalloc_mode(false);
   if (rc) return rc;
   if (status) {
     hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, s, st, status);

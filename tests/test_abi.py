@@ -162,3 +162,60 @@ def test_noalloc_size_limit_checked_on_the_host():
     assert b"static scratch holds 67108864 bytes" in lib.bgk_last_error()
     assert lib.bgk_fine_propagate_moments_noalloc(ps, 0, a, b, 0.0125, None,
                                                   None) == bgk.E_INVALID
+
+
+def test_survey_boundary_helpers_exported():
+    """The helper calls of the boundary: workspace sizing, plans, the stream
+    check, status strings and the last error."""
+    lib = bgk.load_library()
+    for name in ("bgk_workspace_bytes", "bgk_plan_create", "bgk_plan_destroy", "bgk_check",
+                 "bgk_status_string", "bgk_last_error", "bgk_plan_use", "bgk_plan_info",
+                 "bgk_plan_save_tiles", "bgk_plan_load_tiles", "bgk_force_bound"):
+        assert hasattr(lib, name), name
+
+
+def test_plans_and_tile_files_on_the_host(tmp_path):
+    """A plan is created, selected, queried and destroyed without device
+    work while it holds no graphs; an empty tile file round-trips; a file
+    that is not a tile file, or an entry out of range, is an argument
+    error."""
+    lib = bgk.load_library()
+    pl = bgk.Plan()
+    assert pl.info() == (0, 0)
+    pl.use()
+    assert bgk.default_plan_info() == (0, 0)
+    path = str(tmp_path / "tiles.json")
+    pl.save_tiles(path)
+    assert '"bgk_tiles": 1' in open(path).read()
+    pl.load_tiles(path)
+    assert pl.info() == (0, 0)
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"something": 1}')
+    assert lib.bgk_plan_load_tiles(pl.handle, str(bad).encode()) == bgk.E_INVALID
+    bad.write_text('{"bgk_tiles": 1, "entries": [{"arch": "gfx950", "nv": [4, 4, 4], '
+                   '"nx_bucket": 8, "batch_bucket": 1, "steps_per_pass": 3, "elems": 3, '
+                   '"chunk": 4, "pair": 0, "ms": 1.0}]}')
+    assert lib.bgk_plan_load_tiles(pl.handle, str(bad).encode()) == bgk.E_INVALID
+    assert lib.bgk_plan_load_tiles(pl.handle, str(tmp_path / "missing.json").encode()) == bgk.E_INVALID
+    assert lib.bgk_plan_use(None) == bgk.OK
+    pl.destroy()
+    assert lib.bgk_plan_destroy(None) == bgk.OK
+    assert lib.bgk_plan_create(None) == bgk.E_INVALID
+
+
+def test_force_bound_of_a_host_array():
+    """bgk_force_bound on a host array: max |E_i| (the Rusanov coefficient),
+    NaN if an entry is NaN."""
+    import numpy as np
+    lib = bgk.load_library()
+    fk = wl.c6_two_beam_force()
+    p = fk.problem
+    assert bgk._emax(p, fk.E) == float(np.max(np.abs(fk.E)))
+    E = fk.E.copy()
+    E[7] = np.nan
+    out = ctypes.c_double()
+    assert lib.bgk_force_bound(ctypes.byref(bgk.problem_struct(p)), E.ctypes.data, 0,
+                               ctypes.byref(out), None) == bgk.OK
+    assert np.isnan(out.value)
+    assert lib.bgk_force_bound(ctypes.byref(bgk.problem_struct(p)), None, 0,
+                               ctypes.byref(out), None) == bgk.E_INVALID
