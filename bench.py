@@ -39,6 +39,7 @@ TRAFFIC_SUMMARY = {
                                              "k_step2x2_smooth_periodic_traffic.md"),
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2502_02704_amd", "csrc", "kinetic.hip")
+TILE_CACHE = os.path.join(ROOT, "paper_2502_02704_amd", "tiles.json")
 
 
 def log(msg):
@@ -480,34 +481,90 @@ def roofline_of(workload, kinds, updates_per_step, steps, elapsed):
                 "share_of_wall_clock": round(a_ms * 1e-3 / elapsed, 4)}}
 
 
-def batch_line(torch, bgk, name, steps, warmup, eps=None):
-    """Throughput and roofline of one benchmark batch."""
+def pow2_ceil(n):
+    v = 1
+    while v < n:
+        v <<= 1
+    return v
+
+
+def tile_entry(path, arch, p, B, fuse=3):
+    """The tile-file entry of this grid class (velocity grid, nx and batch
+    rounded up to powers of two, steps per pass) for `arch`, or None."""
+    if not os.path.exists(path):
+        return None
+    for e in json.load(open(path)).get("entries", []):
+        if (e["arch"] == arch and e["nv"] == list(p.nv) and e["nx_bucket"] == pow2_ceil(p.nx)
+                and e["batch_bucket"] == pow2_ceil(B) and e["steps_per_pass"] == fuse):
+            return e
+    return None
+
+
+def tuned_tiles(torch, bgk, p, B, cache):
+    """Tiles of the grid class from the tile file, else measured now by
+    bgk_autotune (and the file rewritten).  Returns a description for the
+    bench line."""
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    e = tile_entry(cache, arch, p, B)
+    if e is not None:
+        bgk.load_tiles(cache)
+        return {"source": "autotune (tile file)", "elems": e["elems"], "chunk": e["chunk"],
+                "pair": e["pair"], "arch": arch}
+    t0 = time.perf_counter()
+    el, ch, pr = bgk.autotune(p, B)
+    took = time.perf_counter() - t0
+    if os.path.exists(cache):
+        bgk.load_tiles(cache)  # keep the file's other entries
+    bgk.save_tiles(cache)
+    log(f"autotuned {p.nx}x{p.nv} x{B}: elems {el}, chunk {ch}, pair {pr} ({took:.1f} s)")
+    return {"source": "autotune (measured in this run)", "elems": el, "chunk": ch, "pair": pr,
+            "arch": arch, "autotune_s": round(took, 2)}
+
+
+def batch_line(torch, bgk, name, steps, warmup, eps=None, cache=None):
+    """Throughput and roofline of one benchmark batch, with autotuned tiles
+    when a tile file path is given (and the built-in choice timed beside
+    them)."""
     wk, V, span = workload_batch(name, eps)
     p = wk.problem
     B = V.shape[0]
     n_fine, _ = bgk.n_steps(p, span)
     virt = steps_on_moments(n_fine)
     updates_per_step = B * p.cells * n_fine
+    tiles = None
+    if cache:
+        tiles = tuned_tiles(torch, bgk, p, B, cache)
+        # the built-in choice on the same batch: a plan without tuned shapes
+        with bgk.Plan():
+            el_h, _ = time_batch(torch, bgk, p, V, span, max(1, min(steps, 2)), 1)
+        tiles["builtin_ms_per_step"] = round(el_h / max(1, min(steps, 2)) * 1e3, 2)
     elapsed, kinds = time_batch(torch, bgk, p, V, span, steps, warmup)
+    if tiles is not None:
+        tiles["tuned_ms_per_step"] = round(elapsed / steps * 1e3, 2)
     cfg = {"workload": f"{wk.name.split('_eps')[0]}_slices{B}", "nx": p.nx, "nv": list(p.nv),
            "v_box": [p.v_lo[0], p.v_hi[0]], "slices_batched": B,
            "fine_steps_per_slice": n_fine, "steps_applied_to_f": n_fine - virt,
            "last_steps_on_moments": virt, "eps": p.eps,
            "bc": "periodic" if p.bc == 1 else "neumann", "updates_per_step": updates_per_step,
            "updates_per_step_applied_to_f": B * p.cells * (n_fine - virt)}
-    return {"value": updates_per_step * steps / elapsed,
+    line = {"value": updates_per_step * steps / elapsed,
             "value_steps_applied_to_f": B * p.cells * (n_fine - virt) * steps / elapsed,
             "ms_per_step": elapsed / steps * 1e3, "config": cfg,
-            "roofline": roofline_of(name, kinds, updates_per_step, steps, elapsed)}, wk, V, span
+            "roofline": roofline_of(name, kinds, updates_per_step, steps, elapsed)}
+    if tiles is not None:
+        line["tiles"] = tiles
+    return line, wk, V, span
 
 
-def smooth_section(torch, bgk, steps=5, warmup=1):
+def smooth_section(torch, bgk, steps=5, warmup=1, cache=None):
     """The smooth periodic workload (64 slices of 512 x 32^3, 25 steps per
     slice, the last two evaluated on the moments) at its three Knudsen
-    numbers, and with two steps per pass at eps = 1e-2 for comparison."""
+    numbers (autotuned tiles), and with two steps per pass at eps = 1e-2 for
+    comparison."""
     out = []
     for eps in (1.0, 1e-2, 1e-4):
-        line, _, _, _ = batch_line(torch, bgk, "smooth_periodic", steps, warmup, eps)
+        line, _, _, _ = batch_line(torch, bgk, "smooth_periodic", steps, warmup, eps,
+                                   cache=cache if eps == 1e-2 else None)
         line["config"]["eps"] = eps
         out.append(line)
     bgk.set_step_fusion(2)
@@ -539,6 +596,11 @@ def main():
                          "force, order2, uneven, adjoint")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--tile-cache", default=TILE_CACHE,
+                    help="JSON file of autotuned tiles (read, and written when a grid class "
+                         "is tuned in this run)")
+    ap.add_argument("--builtin-tiles", action="store_true",
+                    help="time the built-in tile choice only (no autotuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding the "
@@ -550,8 +612,9 @@ def main():
     from paper_2502_02704_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    cache = None if args.builtin_tiles else args.tile_cache
     main_line, wk, V_np, span = batch_line(torch, bgk, args.workload, args.steps, args.warmup,
-                                           args.eps)
+                                           args.eps, cache=cache)
     log(f"main line {main_line['config']['workload']}: {main_line['value']:.4g} updates/s, "
         f"{main_line['ms_per_step']:.1f} ms per step")
     bgk.free_workspaces()
@@ -571,9 +634,11 @@ def main():
             "data": "synthetic", "config": main_line["config"],
             "value_steps_applied_to_f": main_line["value_steps_applied_to_f"],
             "roofline": main_line["roofline"]}
+    if "tiles" in main_line:
+        line["tiles"] = main_line["tiles"]
     extras = set() if args.no_parareal else {x for x in args.extras.split(",") if x}
     if "smooth" in extras and args.workload == "sod_large":
-        line["smooth_periodic"] = smooth_section(torch, bgk)
+        line["smooth_periodic"] = smooth_section(torch, bgk, cache=cache)
         log("smooth periodic section done")
     if "parareal" in extras:
         line["parareal"] = parareal_small(torch, bgk, wl)
