@@ -601,6 +601,12 @@ def main():
                          "is tuned in this run)")
     ap.add_argument("--builtin-tiles", action="store_true",
                     help="time the built-in tile choice only (no autotuning)")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every kernel directly instead of replaying captured HIP "
+                         "graphs (counter-collection runs)")
+    ap.add_argument("--only", default="",
+                    help="run only these extra sections (comma list, as --extras), without "
+                         "the main line or the CPU baseline (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding the "
@@ -612,14 +618,9 @@ def main():
     from paper_2502_02704_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.no_graphs:
+        bgk.set_graphs(False)
     cache = None if args.builtin_tiles else args.tile_cache
-    main_line, wk, V_np, span = batch_line(torch, bgk, args.workload, args.steps, args.warmup,
-                                           args.eps, cache=cache)
-    log(f"main line {main_line['config']['workload']}: {main_line['value']:.4g} updates/s, "
-        f"{main_line['ms_per_step']:.1f} ms per step")
-    bgk.free_workspaces()
-    torch.cuda.empty_cache()
-
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
@@ -627,6 +628,34 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.only:
+        only = {x for x in args.only.split(",") if x}
+        line = {"metric": METRIC, "only": sorted(only)}
+        sections = {"smooth": ("smooth_periodic", lambda: smooth_section(torch, bgk, cache=cache)),
+                    "parareal": ("parareal", lambda: parareal_small(torch, bgk, wl)),
+                    "parareal_large": ("parareal_baseline_sizes",
+                                       lambda: parareal_large(torch, bgk, wl)),
+                    "force": ("exterior_force", lambda: force_throughput(torch, bgk, wl)),
+                    "uneven": ("uneven_batch", lambda: uneven_throughput(torch, bgk, wl)),
+                    "adjoint": ("adjoint", lambda: adjoint_timing(torch, bgk, wl))}
+        for name in sorted(only):
+            if name == "order2":
+                wk2, V2, span2 = workload_batch("smooth_periodic")
+                line["second_order_fine"] = second_order_throughput(
+                    torch, bgk, torch.from_numpy(V2).cuda(), wk2.problem, span2)
+            else:
+                key, fn = sections[name]
+                line[key] = fn()
+            log(f"{name} done")
+        print(json.dumps(line), flush=True)
+        return
+    main_line, wk, V_np, span = batch_line(torch, bgk, args.workload, args.steps, args.warmup,
+                                           args.eps, cache=cache)
+    log(f"main line {main_line['config']['workload']}: {main_line['value']:.4g} updates/s, "
+        f"{main_line['ms_per_step']:.1f} ms per step")
+    bgk.free_workspaces()
+    torch.cuda.empty_cache()
+
 
     line = {"metric": METRIC, "value": main_line["value"], "unit": "updates/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_line["ms_per_step"],

@@ -1723,11 +1723,17 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   // one step per launch (paired lanes only if every instance allows them).
   // Within a group the instances are sorted by step count (descending), so
   // that its active instances at any step form a prefix.
-  Tiles t = {4, 8, 1};
+  // Built-in shapes, measured on the 29-instance seeded batch: paired lanes
+  // four pairs per lane over 8-cell chunks (5.3 TB/s), unpaired lanes four
+  // velocities per lane over 24-cell chunks (4.0 TB/s; 8-cell chunks 3.3,
+  // eight per lane spill); an override applies to both groups.
+  Tiles t = {8, 8, 1}, tflat = {4, 24, 0};
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (g_override.elems) t.elems = g_override.elems;
-    if (g_override.chunk) t.chunk = g_override.chunk;
+    for (Tiles* x : {&t, &tflat}) {
+      if (g_override.elems) x->elems = g_override.elems;
+      if (g_override.chunk) x->chunk = g_override.chunk;
+    }
     if (g_override.pair == 0) t.pair = 0;
   }
   std::vector<char> pairable(n);
@@ -1746,7 +1752,19 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   while (nA < n && first_group(order[nA])) ++nA;
   Tiles tA = t, tB = t;
   for (int k = nA; k < n; ++k)
-    if (!pairable[order[k]]) tB.pair = 0;
+    if (!pairable[order[k]]) tB = tflat;
+  // factor rows of the group's largest velocity grid within the LDS (two
+  // levels of 2 chunk + 6 rows in a two-step pass, chunk + 2 in one step)
+  for (int grp = 0; grp < 2; ++grp) {
+    Tiles& tt = grp ? tB : tA;
+    long long nvs_m = 0;
+    for (int k = grp ? nA : 0; k < (grp ? n : nA); ++k) {
+      const bgk_problem& pq = probs[order[k]];
+      nvs_m = std::max(nvs_m, (long long)pq.nv[0] + pq.nv[1] + pq.nv[2]);
+    }
+    while (tt.chunk > 1 && (fused ? 2LL * tt.chunk + 6 : tt.chunk + 2LL) * nvs_m * 8 > kLdsBytes)
+      tt.chunk /= 2;
+  }
   std::vector<Inst> h(n);
   long long items = 0;
   int nvs_a = 0, nvs_b = 0;
@@ -1760,6 +1778,7 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
     I.fout = f_out[q];
     I.steps = steps[q];
     I.item_begin = items;
+    I.cell_begin = cells_prefix[k];
     items += I.items;
     items_prefix[k + 1] = items;
     cells_prefix[k + 1] = cells_prefix[k] + I.nx;
@@ -1891,7 +1910,8 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   add(f_in, sizeof(const double*) * (size_t)n);
   add(f_out, sizeof(double*) * (size_t)n);
   add(t_span, sizeof(double) * (size_t)n);
-  add(&t, sizeof(t));
+  add(&tA, sizeof(tA));
+  add(&tB, sizeof(tB));
   add(&fused, sizeof(fused));
   return run_graph(key, s, sequence);
 }

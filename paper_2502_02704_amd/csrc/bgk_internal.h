@@ -32,6 +32,7 @@ struct Inst {
   int steps;                   // steps this instance takes (uneven batches)
   long long item_begin;        // first work item of this instance
   long long items;             // nbatch * ntg * nchunks
+  long long cell_begin;        // first x cell (over all members) of this instance
   int part_tiles;              // partial-sum capacity of `part` per x cell
   int nparts;                  // partial sums per x cell the step writes
   int nsum;                    // values per partial: 5 moments, or 15 with the

@@ -76,14 +76,19 @@ __device__ __forceinline__ double wave_sum_all(double v) {
   return readlane_d(wave_sum_to_last(v), kWave - 1);
 }
 
-// Instance of a work item.  A launch may take a table that starts inside a
-// batch (its first entry's item_begin > 0): the kernels add that offset to
-// their block's item before the search.
+// Instance of a work item: the last entry whose item_begin is <= item
+// (binary search; entries are in item order).  A launch may take a table
+// that starts inside a batch (its first entry's item_begin > 0): the kernels
+// add that offset to their block's item before the search.
 __device__ __forceinline__ int find_inst(const Inst* insts, int n_inst,
                                          long long item) {
-  int q = 0;
-  while (q + 1 < n_inst && insts[q + 1].item_begin <= item) ++q;
-  return q;
+  int lo = 0, hi = n_inst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (insts[mid].item_begin <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 // Work item -> (member b, tile group tg, x chunk c), tile groups fastest, so
@@ -1118,11 +1123,20 @@ __global__ __launch_bounds__(kBlock) void k_step2(const Inst* __restrict__ insts
 // The march keeps level-1 rows k..k+2 and level-2 rows k-1..k+1.  Level-2
 // values outside the domain are ghost copies of the boundary cell (Neumann)
 // or the wrapped cell (periodic), exactly as a single step would see them.
+// Raw rows in flight in the two-step marches: one on paired lanes (a second
+// row spills the 4-pair march: measured 3.3 against 5.3 TB/s on the uneven
+// batch's paired instances), three on unpaired lanes, loaded non-temporally
+// (3.97 TB/s on its unpaired instances against 3.76 with one row, 3.92 with
+// two).
+constexpr int kRowsInFlight2x = 1;
+constexpr int kRowsInFlight2xFlat = 3;
+
 template <int P, int MODE, int CASE, int DIR>
 __device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
                                               const double* lds2, int b, int tile,
                                               int lane, int i0, int i1, int phase,
                                               double vxu, double nuu) {
+  constexpr int R = kRowsInFlight2x;
   constexpr bool FULL = CASE != kTileRagged;
   constexpr bool UNI = CASE == kTilePos || CASE == kTileNeg;
   constexpr int SGN = CASE == kTilePos ? 1 : (CASE == kTileNeg ? -1 : 0);
@@ -1171,7 +1185,8 @@ __device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
 
   double2 f1b[P], f1c[P], f1a[P];  // level 1 at positions k, k+1, k+2
   double2 f2b[P], f2c[P], f2a[P];  // level 2 at positions k-1, k, k+1
-  double2 rcur[P];                 // raw row k+2; refilled with k+3 once used
+  // raw rows in flight: rows k+2 .. k+1+R in R buffers used in turn
+  double2 raw[R][P];
   {
     double2 ra[P], rb[P], l0[P], l1[P];
     load_row(row_at(-2), ra);
@@ -1181,7 +1196,9 @@ __device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
     relax1(row_at(-1), rb, l1);        // level 1 at -1
     load_row(row_at(1), rb);
     relax1(row_at(0), ra, f1b);        // level 1 at 0
-    load_row(row_at(2), rcur);
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (2 + j <= len + 1) load_row(row_at(2 + j), raw[j]);
     relax1(row_at(1), rb, f1c);        // level 1 at 1
     level2(row_at(-1), l0, l1, f1b, f2b);   // level 2 at -1
     level2(row_at(0), l1, f1b, f1c, f2c);   // level 2 at 0
@@ -1190,9 +1207,10 @@ __device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
       for (int p = 0; p < P; ++p) f2b[p] = f2c[p];
     }
   }
-  for (int k = 0; k < len; ++k) {
-    relax1(row_at(k + 2), rcur, f1a);
-    if (k + 3 <= len + 1) load_row(row_at(k + 3), rcur);  // in flight during the rest
+  // output row k; rw holds raw row k+2 and takes the load of row k+2+R
+  auto step = [&](int k, double2 (&rw)[P]) {
+    relax1(row_at(k + 2), rw, f1a);
+    if (k + 2 + R <= len + 1) load_row(row_at(k + 2 + R), rw);  // in flight meanwhile
     level2(row_at(k + 1), f1b, f1c, f1a, f2a);
     if (neumann && outside(row_at(k + 1))) {
 #pragma unroll
@@ -1217,6 +1235,11 @@ __device__ __forceinline__ void step2x2_march(const Inst& I, const double* lds1,
       f2b[p] = f2c[p];
       f2c[p] = f2a[p];
     }
+  };
+  for (int k = 0; k < len; k += R) {
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (k + j < len) step(k + j, raw[j]);
   }
 }
 
@@ -1270,7 +1293,7 @@ __global__ __launch_bounds__(kBlock) void k_step2x2(const Inst* __restrict__ ins
 // levels as the paired march: level 1 at rows k .. k+2 from the factors
 // fac, level 2 at rows k-1 .. k+1 from fac2, output row k; every velocity
 // has its own v_x, nu and factors.  Records: the fifteen sums per wave.
-template <int E, int MODE, int DIR>
+template <int E, int MODE, int DIR, int R>
 __device__ __forceinline__ void step2x2_flat_march(const Inst& I, const double* lds1,
                                                    const double* lds2, int b, int tile,
                                                    int lane, int i0, int i1, int phase) {
@@ -1295,7 +1318,8 @@ __device__ __forceinline__ void step2x2_flat_march(const Inst& I, const double* 
     if (MODE == kLift) return;
     gptr<const double> row = src + (long long)ghost_row(r, nx, I.bc) * nv3;
 #pragma unroll
-    for (int e = 0; e < E; ++e) raw[e] = el.ok[e] ? row[e * kWave] : 0.0;
+    for (int e = 0; e < E; ++e)
+      raw[e] = el.ok[e] ? __builtin_nontemporal_load(row + e * kWave) : 0.0;
   };
   // upwind transport of one velocity: centre c, neighbours behind (march
   // position k-1) and ahead (k+1); the upwind cell is x-1 for v_x > 0
@@ -1329,7 +1353,10 @@ __device__ __forceinline__ void step2x2_flat_march(const Inst& I, const double* 
 
   double f1b[E], f1c[E], f1a[E];  // level 1 at positions k, k+1, k+2
   double f2b[E], f2c[E], f2a[E];  // level 2 at positions k-1, k, k+1
-  double rcur[E];                 // raw row k+2; refilled with k+3 once used
+  // raw rows in flight: rows k+2 .. k+1+R in R buffers used in turn (the
+  // loop is unrolled by R, so no buffer is copied while its load is
+  // outstanding)
+  double raw[R][E];
   {
     double ra[E], rb[E], l0[E], l1[E];
     load_row(row_at(-2), ra);
@@ -1339,15 +1366,18 @@ __device__ __forceinline__ void step2x2_flat_march(const Inst& I, const double* 
     relax1(row_at(-1), rb, l1);       // level 1 at -1
     load_row(row_at(1), rb);
     relax1(row_at(0), ra, f1b);       // level 1 at 0
-    load_row(row_at(2), rcur);
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (2 + j <= len + 1) load_row(row_at(2 + j), raw[j]);
     relax1(row_at(1), rb, f1c);       // level 1 at 1
     level2(row_at(-1), l0, l1, f1b, f2b);  // level 2 at -1
     level2(row_at(0), l1, f1b, f1c, f2c);  // level 2 at 0
     if (neumann && outside(row_at(-1))) copy(f2b, f2c);
   }
-  for (int k = 0; k < len; ++k) {
-    relax1(row_at(k + 2), rcur, f1a);
-    if (k + 3 <= len + 1) load_row(row_at(k + 3), rcur);  // in flight during the rest
+  // output row k; rw holds raw row k+2 and takes the load of row k+2+R
+  auto step = [&](int k, double (&rw)[E]) {
+    relax1(row_at(k + 2), rw, f1a);
+    if (k + 2 + R <= len + 1) load_row(row_at(k + 2 + R), rw);  // in flight meanwhile
     level2(row_at(k + 1), f1b, f1c, f1a, f2a);
     if (neumann && outside(row_at(k + 1))) copy(f2a, f2c);
     const int r = row_at(k);
@@ -1366,6 +1396,11 @@ __device__ __forceinline__ void step2x2_flat_march(const Inst& I, const double* 
     copy(f1c, f1a);
     copy(f2b, f2c);
     copy(f2c, f2a);
+  };
+  for (int k = 0; k < len; k += R) {
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (k + j < len) step(k + j, raw[j]);
   }
 }
 
@@ -1393,9 +1428,11 @@ __global__ __launch_bounds__(kBlock) void k_step2x2_flat(const Inst* __restrict_
   if (tile >= I.ntiles) return;
   // neighbouring chunks march in opposite directions (shared halo rows)
   if (c & 1)
-    step2x2_flat_march<E, MODE, -1>(I, lds1, lds2, b, tile, lane, i0, i1, phase);
+    step2x2_flat_march<E, MODE, -1, kRowsInFlight2xFlat>(I, lds1, lds2, b, tile, lane, i0,
+                                                         i1, phase);
   else
-    step2x2_flat_march<E, MODE, 1>(I, lds1, lds2, b, tile, lane, i0, i1, phase);
+    step2x2_flat_march<E, MODE, 1, kRowsInFlight2xFlat>(I, lds1, lds2, b, tile, lane, i0,
+                                                        i1, phase);
 }
 
 // ---------------------------------------------- three steps in one pass --
@@ -1636,19 +1673,20 @@ __global__ __launch_bounds__(kBlock) void k_partials(
 }
 
 // ------------------------------------------------------- cell reduction --
+// Instance of an x cell counted from the table's first entry, and the cell
+// within that instance (binary search over cell_begin, as find_inst).
 __device__ __forceinline__ int find_inst_cell(const Inst* insts, int n_inst,
                                               long long cell,
                                               long long* cell_local) {
-  long long begin = 0;
-  int q = 0;
-  for (;;) {
-    long long n = (long long)insts[q].nbatch * insts[q].nx;
-    if (cell < begin + n || q + 1 == n_inst) break;
-    begin += n;
-    ++q;
+  cell += insts[0].cell_begin;
+  int lo = 0, hi = n_inst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (insts[mid].cell_begin <= cell) lo = mid;
+    else hi = mid - 1;
   }
-  *cell_local = cell - begin;
-  return q;
+  *cell_local = cell - insts[lo].cell_begin;
+  return lo;
 }
 
 __device__ __forceinline__ bool physical(double rho, double th) {
