@@ -156,7 +156,18 @@ static int g_fuse = 3;  // IMEX steps per pass (1, 2 or 3) where possible
 // (233 VGPRs) a CU holds one 8-wave block, which may then take all 160 KB of
 // gfx950's LDS; with 2 (123 VGPRs) two blocks share it.
 static size_t lds3_cap(int elems) { return elems == 4 ? (size_t)kLdsBytes : 65536; }
-static int lds3_max_chunk(int elems) { return elems == 4 ? 48 : 24; }
+static int lds3_max_chunk(int elems) { return elems == 4 ? 64 : 24; }
+
+// Longest factor row a three-step block stages: Ex of the v_x planes its
+// eight tiles of 64 * elems velocities span, then Ey and Ez.
+static int lds3_row(int nvx, int nvy, int nvz, int elems) {
+  const long long nyz = (long long)nvy * nvz, nv3 = nyz * nvx;
+  const long long span = (long long)kWavesPerBlock * kWave * elems;
+  long long nj = 1;
+  for (long long v0 = 0; v0 < nv3; v0 += span)
+    nj = std::max(nj, (std::min(v0 + span, nv3) - 1) / nyz - v0 / nyz + 1);
+  return (int)nj + nvy + nvz;
+}
 
 // The v_x-column mapping fits a grid whose tiles fit the partial-sum capacity.
 static bool vcol_fits(const bgk_problem& p, Tiles t) {
@@ -231,9 +242,9 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
     if (pair && g_fuse == 3 && p.nx >= 3 && nyz % (kWave * 2) == 0) {
       // the longest chunk whose three levels of factor rows fit the LDS
       const int e = nyz % (kWave * 4) == 0 ? 4 : 2;
-      const long long nvs = (long long)p.nv[0] + p.nv[1] + p.nv[2];
+      const long long rl = lds3_row(p.nv[0], p.nv[1], p.nv[2], e);
       int ch = lds3_max_chunk(e);
-      while (ch > 1 && (size_t)(3LL * ch + 12) * nvs * sizeof(double) > lds3_cap(e)) --ch;
+      while (ch > 1 && (size_t)(3LL * ch + 12) * rl * sizeof(double) > lds3_cap(e)) --ch;
       t = Tiles{e, ch, 1};
     }
     while (t.chunk > 1 && blocks_for_tiles(p, batch, t) < 4096) t.chunk /= 2;
@@ -519,7 +530,9 @@ static int lds_doubles(const Inst& I, Tiles t) {
   return (t.chunk + (I.order == 2 ? 4 : 2)) * I.nvs;
 }
 static int lds_doubles2(const Inst& I, Tiles t) { return (2 * t.chunk + 6) * I.nvs; }
-static int lds_doubles3(const Inst& I, Tiles t) { return (3 * t.chunk + 12) * I.nvs; }
+static int lds_doubles3(const Inst& I, Tiles t) {
+  return (3 * t.chunk + 12) * lds3_row(I.nvx, I.nvy, I.nvz, t.elems);
+}
 
 static int fuse_mode() {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -2009,9 +2022,9 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws, size_t ws_byt
     for (int ei = 0; ei < 3; ++ei) {
       for (int ci = 0; ci < 8; ++ci) cands.push_back(Tiles{Es[ei], Cs[ci], pr});
       if (pr && Es[ei] <= 4) {
-        const long long nvs = (long long)prob->nv[0] + prob->nv[1] + prob->nv[2];
-        int ch = 64;
-        while (ch > 1 && (3LL * ch + 12) * nvs * 8 > (long long)lds3_cap(Es[ei])) --ch;
+        const long long rl = lds3_row(prob->nv[0], prob->nv[1], prob->nv[2], Es[ei]);
+        int ch = lds3_max_chunk(Es[ei]);
+        while (ch > 1 && (3LL * ch + 12) * rl * 8 > (long long)lds3_cap(Es[ei])) --ch;
         cands.push_back(Tiles{Es[ei], ch, 1});
       }
     }

@@ -249,10 +249,15 @@ struct PairEls {
   __device__ __forceinline__ double nu(int p) const { return nu_[p]; }
 };
 
+// Velocity data of a lane's pairs and their offsets into a factor row laid
+// out as [Ex | Ey | Ez]; jx_base and row_nx describe a row holding only the
+// Ex values of v_x planes jx_base .. jx_base + row_nx - 1 (defaults: all).
 template <int P, bool FULL>
 __device__ __forceinline__ void setup_pairs(const Inst& I, int tile, int lane,
-                                            PairEls<P>& e) {
+                                            PairEls<P>& e, int jx_base = 0,
+                                            int row_nx = -1) {
   const int nyz = I.nvy * I.nvz;
+  if (row_nx < 0) row_nx = I.nvx;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const int j = tile * (128 * P) + p * 128 + 2 * lane;
@@ -263,8 +268,8 @@ __device__ __forceinline__ void setup_pairs(const Inst& I, int tile, int lane,
     const int rem = jj - jx * nyz;
     const int jy = rem / I.nvz;
     const int jz = rem - jy * I.nvz;
-    e.off[p] = (unsigned)jx | ((unsigned)(I.nvx + jy) << 10) |
-               ((unsigned)(I.nvx + I.nvy + jz) << 20);
+    e.off[p] = (unsigned)(jx - jx_base) | ((unsigned)(row_nx + jy) << 10) |
+               ((unsigned)(row_nx + I.nvy + jz) << 20);
     e.vx[p] = vgrid(I, 0, jx);
     e.vy[p] = vgrid(I, 1, jy);
     e.vz[p] = vgrid(I, 2, jz);
@@ -1458,11 +1463,13 @@ template <int P, int MODE, int CASE, int DIR>
 __device__ __forceinline__ void step3x_march(const Inst& I, const double* lds1,
                                              const double* lds2, const double* lds3,
                                              int b, int tile, int lane, int i0, int i1,
-                                             int phase, double vxu, double nuu) {
+                                             int phase, double vxu, double nuu,
+                                             int jx_base, int row_nx) {
   constexpr int SGN = CASE == kTilePos ? 1 : -1;
-  const int nx = I.nx, nv3 = I.nv3, nvs = I.nvs;
+  const int nx = I.nx, nv3 = I.nv3;
+  const int nvs = row_nx + I.nvy + I.nvz;  // compact factor rows in LDS
   PairEls<P> e;
-  setup_pairs<P, true>(I, tile, lane, e);
+  setup_pairs<P, true>(I, tile, lane, e, jx_base, row_nx);
   const double dvz = I.dv[2];
   const long long mbase = (long long)b * nx * nv3;
   gptr<const double> src = gmem(I.buf[phase]) + mbase;
@@ -1587,11 +1594,29 @@ struct Step3xCall {
   static __device__ __forceinline__ void run(const Inst& I, const double* lds1,
                                              const double* lds2, const double* lds3, int b,
                                              int tile, int lane, int i0, int i1, int phase,
-                                             double vxu, double nuu) {
+                                             double vxu, double nuu, int jx_base,
+                                             int row_nx) {
     step3x_march<P, MODE, CASE, DIR>(I, lds1, lds2, lds3, b, tile, lane, i0, i1, phase,
-                                     vxu, nuu);
+                                     vxu, nuu, jx_base, row_nx);
   }
 };
+
+// Factor rows of `rows` x cells from first_row on, keeping of Ex only the
+// v_x planes jx_base .. jx_base + row_nx - 1 (the planes the block's tiles
+// lie in): [Ex(jx_base ..) | Ey | Ez], row_nx + nvy + nvz values per row.
+__device__ __forceinline__ void stage_rows_compact(const Inst& I, const double* fac, int b,
+                                                   int first_row, int rows, int jx_base,
+                                                   int row_nx, double* lds) {
+  const int nx = I.nx, nvs = I.nvs;
+  const int rl = row_nx + I.nvy + I.nvz;
+  gptr<const double> f = gmem(fac) + (long long)b * nx * nvs;
+  for (int idx = threadIdx.x; idx < rows * rl; idx += kBlock) {
+    const int rr = idx / rl;
+    const int k = idx - rr * rl;
+    const int src = k < row_nx ? jx_base + k : I.nvx + (k - row_nx);
+    lds[idx] = f[(long long)ghost_row(first_row + rr, nx, I.bc) * nvs + src];
+  }
+}
 
 template <int P, int MODE>
 __global__ __launch_bounds__(kBlock) void k_step3x(const Inst* __restrict__ insts,
@@ -1606,12 +1631,20 @@ __global__ __launch_bounds__(kBlock) void k_step3x(const Inst* __restrict__ inst
   const int i0 = c * chunk;
   const int i1 = min(i0 + chunk, I.nx);
   const int len = i1 - i0;
+  // the v_x planes of the block's tiles (every tile lies in one plane)
+  constexpr int kTileV = 128 * P;
+  const int nyz = I.nvy * I.nvz;
+  const int v_first = tg * kWavesPerBlock * kTileV;
+  const int v_last = min((tg + 1) * kWavesPerBlock * kTileV, I.nv3) - 1;
+  const int jx_base = v_first / nyz;
+  const int row_nx = v_last / nyz - jx_base + 1;
+  const int rl = row_nx + I.nvy + I.nvz;
   double* lds1 = lds;
-  double* lds2 = lds1 + (len + 6) * I.nvs;
-  double* lds3 = lds2 + (len + 4) * I.nvs;
-  stage_rows(I, I.fac, b, i0 - 3, len + 6, lds1);
-  stage_rows(I, I.fac2, b, i0 - 2, len + 4, lds2);
-  stage_rows(I, I.fac3, b, i0 - 1, len + 2, lds3);
+  double* lds2 = lds1 + (len + 6) * rl;
+  double* lds3 = lds2 + (len + 4) * rl;
+  stage_rows_compact(I, I.fac, b, i0 - 3, len + 6, jx_base, row_nx, lds1);
+  stage_rows_compact(I, I.fac2, b, i0 - 2, len + 4, jx_base, row_nx, lds2);
+  stage_rows_compact(I, I.fac3, b, i0 - 1, len + 2, jx_base, row_nx, lds3);
   __syncthreads();
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
@@ -1619,7 +1652,8 @@ __global__ __launch_bounds__(kBlock) void k_step3x(const Inst* __restrict__ inst
   if (tile >= I.ntiles) return;
   double vxu, nuu;
   using Call = Step3xCall<P, MODE>;
-  BGK_MARCH_DISPATCH_UNI(Call, I, lds1, lds2, lds3, b, tile, lane, i0, i1, phase, vxu, nuu);
+  BGK_MARCH_DISPATCH_UNI(Call, I, lds1, lds2, lds3, b, tile, lane, i0, i1, phase, vxu, nuu,
+                         jx_base, row_nx);
 }
 
 // -------------------------------------------- partial sums of a field --

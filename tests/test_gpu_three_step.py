@@ -57,7 +57,7 @@ def tiles_for(p):
     nyz = p.nv[1] * p.nv[2]
     out = [(2, 1, 1), (2, 2, 1), (2, 5, 1), (2, 24, 1), (2, 64, 1)]
     if nyz % 256 == 0:
-        out += [(4, 3, 1), (4, 8, 1), (4, 24, 1), (4, 48, 1)]
+        out += [(4, 3, 1), (4, 8, 1), (4, 24, 1), (4, 48, 1), (4, 64, 1)]
     return out
 
 
