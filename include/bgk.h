@@ -439,10 +439,14 @@ int bgk_autotune(const bgk_problem* prob, int32_t batch, void* ws,
  * sums weighted by max(nu,0)^2 and max(-nu,0)^2 too) where every velocity tile
  * lies in one v_x plane (nv[1] nv[2] a multiple of 64 times the velocities
  * per lane), nx >= 3 and the paired lane mapping is used (even nv[2],
- * 16-byte aligned f), else pairs (paired or unpaired lanes); 1 runs one step
- * per pass.  The exterior-force step and the second-order transport always
- * run one step per pass; the uneven batch (bgk_fine_step_batched) runs pairs
- * under 2 and 3. */
+ * 16-byte aligned f), else pairs (paired or unpaired lanes); 4 runs quads
+ * (4 bytes per update; sums weighted to the third power) on grids where
+ * nv[1] nv[2] is a multiple of 128, nx >= 4 and lanes are paired, with one
+ * velocity pair per lane, else as 3; a call that returns moments closes the
+ * n - 4 mod 4 steps after its last quad on the moments.  1 runs one step per
+ * pass.  The exterior-force step and the second-order transport always run
+ * one step per pass; the uneven batch (bgk_fine_step_batched) runs pairs
+ * under 2, 3 and 4. */
 int bgk_set_step_fusion(int32_t steps_per_pass);
 
 /* Launch-bound sequences (each parareal iteration, the serial chain of
@@ -470,6 +474,8 @@ int bgk_release_graphs(void);
  *   BGK_PROF_THREE_STEP     three IMEX steps per pass, reading and writing f
  *                           (16 algorithmic bytes per cell per pass)
  *   BGK_PROF_THREE_STEP_LIFT three steps from the lifted Maxwellian (8)
+ *   BGK_PROF_FOUR_STEP      four IMEX steps per pass, reading and writing f (16)
+ *   BGK_PROF_FOUR_STEP_LIFT four steps from the lifted Maxwellian (8)
  * bgk_prof_read synchronises and returns, over the launches of `kind`
  * (BGK_PROF_ALL: every kind) since the last bgk_prof_enable(1), the summed
  * milliseconds, the launch count, the phase-space updates (cells times steps)
@@ -481,7 +487,9 @@ enum {
   BGK_PROF_TWO_STEP_LIFT = 2,
   BGK_PROF_ONE_STEP = 3,
   BGK_PROF_THREE_STEP = 4,
-  BGK_PROF_THREE_STEP_LIFT = 5
+  BGK_PROF_THREE_STEP_LIFT = 5,
+  BGK_PROF_FOUR_STEP = 6,
+  BGK_PROF_FOUR_STEP_LIFT = 7
 };
 int bgk_prof_enable(int32_t on);
 int bgk_prof_read(int32_t kind, double* total_ms, int64_t* launches, double* updates,

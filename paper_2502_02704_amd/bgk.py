@@ -665,9 +665,9 @@ def set_graphs(on: bool = True):
 
 
 def set_step_fusion(steps_per_pass: int = 3):
-    """IMEX steps per read-write pass over f: 1, 2 (fused pairs) or 3 (fused
+    """IMEX steps per read-write pass over f: 1, 2 (fused pairs), 3 (fused
     triples where every velocity tile lies in one v_x plane, else pairs;
-    the default)."""
+    the default) or 4 (quads where the grid allows, else as 3)."""
     _check(load_library().bgk_set_step_fusion(steps_per_pass), "bgk_set_step_fusion")
 
 
@@ -677,6 +677,7 @@ def prof_enable(on: bool = True):
 
 PROF_ALL, PROF_TWO_STEP, PROF_TWO_STEP_LIFT, PROF_ONE_STEP = 0, 1, 2, 3
 PROF_THREE_STEP, PROF_THREE_STEP_LIFT = 4, 5
+PROF_FOUR_STEP, PROF_FOUR_STEP_LIFT = 6, 7
 
 
 def prof_read(kind: int = PROF_ALL):

@@ -239,7 +239,14 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic, bool force, bo
     // batch 3.51, 3.37, 3.30, 3.24, 3.21 ms per pass over 12, 16, 24, 32, 48
     // cells; on 4 slices of 2048 x 48^3 3.17, 3.01, 2.97 ms over 14, 24, 32;
     // 2 per lane 3.47 ms over 24)
-    if (pair && g_fuse == 3 && p.nx >= 3 && nyz % (kWave * 2) == 0) {
+    if (pair && g_fuse == 4 && p.nx >= 4 && nyz % (kWave * 2) == 0) {
+      // four levels of rows: one velocity pair per lane (two spill), the
+      // longest chunk whose four levels of factor rows fit the LDS
+      const long long rl = lds3_row(p.nv[0], p.nv[1], p.nv[2], 2);
+      int ch = kMaxChunk;
+      while (ch > 1 && (4LL * ch + 20) * rl * (long long)sizeof(double) > kLdsBytes) --ch;
+      t = Tiles{2, ch, 1};
+    } else if (pair && g_fuse >= 3 && p.nx >= 3 && nyz % (kWave * 2) == 0) {
       // the longest chunk whose three levels of factor rows fit the LDS
       const int e = nyz % (kWave * 4) == 0 ? 4 : 2;
       const long long rl = lds3_row(p.nv[0], p.nv[1], p.nv[2], e);
@@ -298,7 +305,7 @@ struct Carve {
 constexpr int kMaxInst = 4096;
 
 struct FineRegions {  // fine solve of B members of one grid
-  size_t buf0, buf1, part, fac, vg, vout, fac2, aux, fac3, aux2;
+  size_t buf0, buf1, part, fac, vg, vout, fac2, aux, fac3, aux2, fac4, aux3;
 };
 constexpr size_t kNone = ~(size_t)0;  // region not allocated
 
@@ -322,6 +329,8 @@ static FineRegions carve_fine(Carve& c, const bgk_problem& p, int B, int nbufs) 
   r.aux = c.take((size_t)B * p.nx * kAux * sizeof(double));
   r.fac3 = c.take((size_t)B * p.nx * (p.nv[0] + p.nv[1] + p.nv[2]) * sizeof(double));
   r.aux2 = c.take((size_t)B * p.nx * kAux2 * sizeof(double));
+  r.fac4 = c.take((size_t)B * p.nx * (p.nv[0] + p.nv[1] + p.nv[2]) * sizeof(double));
+  r.aux3 = c.take((size_t)B * p.nx * kAux3 * sizeof(double));
   return r;
 }
 
@@ -524,6 +533,8 @@ static void attach_fine(Inst& I, void* ws, const FineRegions& r, double* buf1) {
   I.aux = at<double>(ws, r.aux);
   I.fac3 = at<double>(ws, r.fac3);
   I.aux2 = at<double>(ws, r.aux2);
+  I.fac4 = at<double>(ws, r.fac4);
+  I.aux3 = at<double>(ws, r.aux3);
 }
 
 static int lds_doubles(const Inst& I, Tiles t) {
@@ -532,6 +543,9 @@ static int lds_doubles(const Inst& I, Tiles t) {
 static int lds_doubles2(const Inst& I, Tiles t) { return (2 * t.chunk + 6) * I.nvs; }
 static int lds_doubles3(const Inst& I, Tiles t) {
   return (3 * t.chunk + 12) * lds3_row(I.nvx, I.nvy, I.nvz, t.elems);
+}
+static int lds_doubles4(const Inst& I, Tiles t) {
+  return (4 * t.chunk + 20) * lds3_row(I.nvx, I.nvy, I.nvz, t.elems);
 }
 
 static int fuse_mode() {
@@ -549,8 +563,21 @@ static bool triple_for(const Inst& h, Tiles t) {
     std::lock_guard<std::mutex> lk(g_mu);
     fuse = g_fuse;
   }
-  return fuse == 3 && h.crec != 0 && h.nsum == 15 && h.nx >= 3 && t.pair && t.elems <= 4 &&
+  return fuse >= 3 && h.crec != 0 && h.nsum == 15 && h.nx >= 3 && t.pair && t.elems <= 4 &&
          (size_t)lds_doubles3(h, t) * sizeof(double) <= lds3_cap(t.elems);
+}
+
+// Four IMEX steps per pass: on when asked for, on grids with compact records,
+// nx >= 4 (ghost rows four deep), one velocity pair per lane (four levels of
+// rows in registers) and factor rows of the four levels within the LDS.
+static bool quad_for(const Inst& h, Tiles t) {
+  int fuse;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    fuse = g_fuse;
+  }
+  return fuse == 4 && h.crec != 0 && h.nsum == 15 && h.nx >= 4 && t.pair && t.elems == 2 &&
+         (long long)lds_doubles4(h, t) * (long long)sizeof(double) <= kLdsBytes;
 }
 
 // Runs `n` relax-then-transport steps on the (uploaded) descriptor d_I.
@@ -594,6 +621,78 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
     done += 2;
     return r;
   };
+  if (quad_for(h, t)) {
+    auto quad_pass = [&](int mode) -> int {
+      prof_before(s);
+      int r = launch_step4x(d_I, 1, h.items, mode, phase, t, lds_doubles4(h, t), s);
+      prof_after(s, 4.0 * upd, mode == kLift ? 2.0 : 4.0,
+                 mode == kLift ? BGK_PROF_FOUR_STEP_LIFT : BGK_PROF_FOUR_STEP);
+      phase ^= 1;
+      done += 4;
+      return r;
+    };
+    auto quad_reductions = [&]() -> int {
+      int r;
+      if ((r = reduce(kRedW1x4))) return r;
+      if ((r = reduce(kRedW2x4))) return r;
+      if ((r = reduce(kRedW3x4))) return r;
+      return reduce(kRedW4x4);
+    };
+    // the first pass: four steps from the lift (its weighted sums to the
+    // third power come with the lift factors), or one step from the copy
+    if (first_mode == kLift && n >= 4) {
+      if ((rc = reduce(kRedW2x4))) return rc;
+      if ((rc = reduce(kRedW3x4))) return rc;
+      if ((rc = reduce(kRedW4x4))) return rc;
+      if ((rc = quad_pass(kLift))) return rc;
+    } else {
+      if ((rc = single(first_mode))) return rc;
+      done = 1;
+    }
+    // When only the projected moments leave the call, the n - done mod 4 steps
+    // left after the last four-step pass close on the moments (weighted sums
+    // of the last stored field).
+    const int virt = (project_last && first_mode == kLift && n >= 4) ? (n - done) % 4 : 0;
+    while (n - done - virt >= 4) {
+      if ((rc = quad_reductions())) return rc;
+      if ((rc = quad_pass(kRelax))) return rc;
+    }
+    if (virt == 1) {
+      if ((rc = reduce(kRedW1))) return rc;
+      if ((rc = reduce(kRedW2Project))) return rc;
+      *last_sel = phase;
+      return BGK_OK;
+    }
+    if (virt == 2) {
+      if ((rc = reduce(kRedW1x3))) return rc;
+      if ((rc = reduce(kRedW2x3))) return rc;
+      if ((rc = reduce(kRedW3x3Project))) return rc;
+      *last_sel = phase;
+      return BGK_OK;
+    }
+    if (virt == 3) {
+      if ((rc = reduce(kRedW1x4))) return rc;
+      if ((rc = reduce(kRedW2x4))) return rc;
+      if ((rc = reduce(kRedW3x4))) return rc;
+      if ((rc = reduce(kRedW4x4Project))) return rc;
+      *last_sel = phase;
+      return BGK_OK;
+    }
+    // fewer than four steps left: two-step passes, then one step
+    while (n - done >= 2) {
+      if ((rc = reduce(kRedW1))) return rc;
+      if ((rc = reduce(kRedW2))) return rc;
+      if ((rc = pair_pass(kRelax))) return rc;
+    }
+    if (n - done == 1) {
+      if ((rc = reduce(kRedRelaxFactors))) return rc;
+      if ((rc = single(kRelax))) return rc;
+      done += 1;
+    }
+    if ((rc = reduce(project_last ? kRedProject : kRedRelaxFactors))) return rc;
+    *last_sel = phase;
+    return BGK_OK;
+  }
   if (triple_for(h, t)) {
     auto triple_pass = [&](int mode) -> int {
       prof_before(s);
@@ -699,7 +798,8 @@ static int lift_and_run(const Inst* d_I, const Inst& h, int n, bool project_last
                         int* d_status, hipStream_t s, int* last_sel) {
   // a three-step first pass needs the nu+^2, nu-^2 weighted sums of the lift
   int rc = launch_lift_factors(d_I, 1, (long long)h.nbatch * h.nx, nullptr, d_status, s,
-                               h.nsum == 15 ? (triple_for(h, t) ? 2 : 1) : 0);
+                               h.nsum == 15 ? (quad_for(h, t) ? 3 : (triple_for(h, t) ? 2 : 1))
+                                            : 0);
   if (rc) return rc;
   return run_steps(d_I, h, n, kLift, project_last, t, d_status, s, last_sel);
 }
@@ -1541,7 +1641,8 @@ int bgk_n_steps_force(const bgk_problem* prob, double e_max, double t_span, int3
 }
 
 int bgk_set_step_fusion(int32_t steps_per_pass) {
-  if (steps_per_pass < 1 || steps_per_pass > 3) return invalid("steps_per_pass must be 1, 2 or 3");
+  if (steps_per_pass < 1 || steps_per_pass > 4)
+    return invalid("steps_per_pass must be 1, 2, 3 or 4");
   std::lock_guard<std::mutex> lk(g_mu);
   g_fuse = steps_per_pass;
   return BGK_OK;
@@ -2226,7 +2327,7 @@ int bgk_prof_enable(int32_t on) {
 
 int bgk_prof_read(int32_t kind, double* total_ms, int64_t* launches, double* cells,
                   double* bytes) {
-  if (kind < BGK_PROF_ALL || kind > BGK_PROF_THREE_STEP_LIFT) return invalid("unknown timing kind");
+  if (kind < BGK_PROF_ALL || kind > BGK_PROF_FOUR_STEP_LIFT) return invalid("unknown timing kind");
   std::lock_guard<std::mutex> lk(g_prof_mu);
   double ms = 0.0, c = 0.0, by = 0.0;
   int64_t n = 0;

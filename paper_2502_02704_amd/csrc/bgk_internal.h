@@ -57,6 +57,8 @@ struct Inst {
   double* aux;                 // per-cell weighted sums (fused passes) [..][nx][kAux]
   double* fac3;                // factors of the third step of a pass  [..][nvs]
   double* aux2;                // sums of the second step (three-step) [..][nx][kAux2]
+  double* fac4;                // factors of the fourth step of a pass [..][nvs]
+  double* aux3;                // sums of the third step (four-step)  [..][nx][kAux3]
   const double* efield;        // exterior force E_i at x centres [nx]; null = none
   double emax;                 // Rusanov coefficient of the v_x flux (>= max |E_i|)
   double rv;                   // dt / dv_x
@@ -88,6 +90,11 @@ enum ReduceMode : int {
                            // vout = a V + al V(M[U]) (a last step that is not
                            // written out)
   kRedW3x3Project = 10,    // the same from aux2: the second of two last steps
+  kRedW1x4 = 11,           // kRedW1x3 with the nu+^3, nu-^3 weighted sums too
+  kRedW2x4 = 12,           // kRedW2x3 to the second power: -> fac2, aux2
+  kRedW3x4 = 13,           // from aux2: -> fac3, aux3 (first power)
+  kRedW4x4 = 14,           // from aux3: -> fac4
+  kRedW4x4Project = 15,    // from aux3, projected: the third of three last steps
 };
 
 // aux layout per x cell (conserved-moment units, 5 values each):
@@ -95,10 +102,16 @@ enum ReduceMode : int {
 //   A, A+, A-    the same sums of the Maxwellian M[U(g)]
 //   S++, S--     moments of g weighted by nu+^2, nu-^2   (three-step passes)
 //   A++, A--     the same sums of M[U(g)]                (three-step passes)
-// aux2 (three-step passes) holds the first 30 values of that layout for the
-// pass's second-step field g^{m+1} and its Maxwellian.
-constexpr int kAux = 50;
-constexpr int kAux2 = 30;
+//   S+3, S-3     moments of g weighted by nu+^3, nu-^3   (four-step passes)
+//   A+3, A-3     the same sums of M[U(g)]                (four-step passes)
+// A layout of highest power q holds its first 30 (q = 1), 50 (q = 2) or 70
+// (q = 3) values.  aux2 holds the sums of a pass's second-step field
+// g^{m+1} and its Maxwellian (to the first power in three-step passes, the
+// second in four-step passes), aux3 those of the third-step field (first
+// power, four-step passes).
+constexpr int kAux = 70;
+constexpr int kAux2 = 50;
+constexpr int kAux3 = 30;
 
 // ------------------------------------------------ global-memory pointers --
 // The arrays an Inst points to live in device global memory, but a pointer
@@ -208,6 +221,10 @@ int launch_step2x2(const Inst* d_insts, int n_inst, long long total_items,
 // Three IMEX steps per pass (paired lanes, every tile in one v_x plane,
 // compact records, nx >= 3): mode kRelax or kLift for the first.
 int launch_step3x(const Inst* d_insts, int n_inst, long long total_items, int mode,
+                  int phase, Tiles t, int lds_doubles, hipStream_t s);
+// Four IMEX steps per pass (one velocity pair per lane, every tile in one v_x
+// plane, compact records, nx >= 4): mode kRelax or kLift for the first.
+int launch_step4x(const Inst* d_insts, int n_inst, long long total_items, int mode,
                   int phase, Tiles t, int lds_doubles, hipStream_t s);
 // Partial sums of an arbitrary f (source = fin), no transport.
 int launch_partials(const Inst* d_insts, int n_inst, long long total_items,

@@ -1656,6 +1656,222 @@ __global__ __launch_bounds__(kBlock) void k_step3x(const Inst* __restrict__ inst
                          jx_base, row_nx);
 }
 
+// ----------------------------------------------- four steps in one pass --
+// The three-step pass extended by one level: reads g^m once and writes
+// g^{m+4} once (4 bytes per phase-space update).  The moments of g^{m+1},
+// g^{m+2} and g^{m+3} are known before the pass (reductions kRedW1x4,
+// kRedW2x4, kRedW3x4, kRedW4x4 from sums of g^m and M^m weighted by nu+ and
+// nu- up to the third power).  Output row k takes level 4 at k-1 .. k+1,
+// level 4 at k+1 takes level 3 at k .. k+2, level 3 at k+2 level 2 at
+// k+1 .. k+3, level 2 at k+3 level 1 at k+2 .. k+4.  Four levels of rows fit
+// the registers with one velocity pair per lane (147 VGPRs with two rows in
+// flight; two pairs per lane spill).  With four rows in flight the pass takes
+// 30.9 ms on the 32-slice 2048 x 48^3 batch (47-cell chunks), 7.7 ms per IMEX
+// step against 7.1 for the three-step pass (two pairs per lane): one pair
+// per lane and one block per CU leave too few loads in flight.
+constexpr int kRowsInFlight4x = 4;
+
+template <int P, int MODE, int CASE, int DIR>
+__device__ __forceinline__ void step4x_march(const Inst& I, const double* lds1,
+                                             const double* lds2, const double* lds3,
+                                             const double* lds4, int b, int tile, int lane,
+                                             int i0, int i1, int phase, double vxu,
+                                             double nuu, int jx_base, int row_nx) {
+  constexpr int SGN = CASE == kTilePos ? 1 : -1;
+  const int nx = I.nx, nv3 = I.nv3;
+  const int nvs = row_nx + I.nvy + I.nvz;  // compact factor rows in LDS
+  PairEls<P> e;
+  setup_pairs<P, true>(I, tile, lane, e, jx_base, row_nx);
+  const double dvz = I.dv[2];
+  const long long mbase = (long long)b * nx * nv3;
+  gptr<const double> src = gmem(I.buf[phase]) + mbase;
+  gptr<double> dst = gmem(I.buf[phase ^ 1]) + mbase;
+  const double a = I.a;
+  const bool neumann = I.bc == 0;
+  const int len = i1 - i0;
+  auto row_at = [&](int k) { return DIR > 0 ? i0 + k : i1 - 1 - k; };
+  auto outside = [&](int k) {
+    const int r = row_at(k);
+    return r < 0 || r >= nx;
+  };
+  auto load_row = [&](int k, double2 (&raw)[P]) {
+    if (MODE == kLift) return;
+    gptr<const double> row = src + (long long)ghost_row(row_at(k), nx, I.bc) * nv3;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+      raw[p] = P == 2 ? ld2_nt(row + e.jofs[p]) : ld2(row + e.jofs[p]);
+  };
+  // level 1 at position k: rows i0-4 .. i1+3 staged in lds1
+  auto level1 = [&](int k, const double2 (&raw)[P], double2 (&out)[P]) {
+    const double* fr = lds1 + (row_at(k) - (i0 - 4)) * nvs;
+#pragma unroll
+    for (int p = 0; p < P; ++p) out[p] = relax_pair<MODE>(fr, e.off[p], a, raw[p]);
+  };
+  // level L+1 at position k from level L at k-1, k, k+1 (lds: the factor
+  // rows of level L+1, first row `first`)
+  auto next = [&](const double* lds, int first, int k, const double2 (&bh)[P],
+                  const double2 (&c)[P], const double2 (&ah)[P], double2 (&out)[P]) {
+    const double* fr = lds + (row_at(k) - first) * nvs;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const double2 g = transport_pair<DIR, SGN>(nuu, bh[p], c[p], ah[p]);
+      out[p] = relax_pair<kRelax>(fr, e.off[p], a, g);
+    }
+  };
+  auto copy = [&](double2 (&d)[P], const double2 (&s)[P]) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) d[p] = s[p];
+  };
+
+  double2 l1b[P], l1c[P];  // level 1 at positions k+2, k+3
+  double2 l2b[P], l2c[P];  // level 2 at k+1, k+2
+  double2 l3b[P], l3c[P];  // level 3 at k, k+1
+  double2 l4b[P], l4c[P];  // level 4 at k-1, k
+  constexpr int R = kRowsInFlight4x;
+  double2 raw[R][P];
+  {
+    // level 1 at -4 .. 3 (streamed), level 2 at -3 .. 2, then the Neumann
+    // copies outside the domain, level 3 at -2 .. 1, level 4 at -1 .. 0
+    double2 r0[P], r1[P], x0[P], x1[P], x2[P];
+    double2 m3[P], m2[P], m1[P], z0[P];  // level 2 at -3, -2, -1, 0
+    load_row(-4, r0);
+    load_row(-3, r1);
+    level1(-4, r0, x0);
+    load_row(-2, r0);
+    level1(-3, r1, x1);
+    load_row(-1, r1);
+    level1(-2, r0, x2);
+    next(lds2, i0 - 3, -3, x0, x1, x2, m3);  // level 2 at -3
+    load_row(0, r0);
+    level1(-1, r1, x0);
+    next(lds2, i0 - 3, -2, x1, x2, x0, m2);  // level 2 at -2
+    load_row(1, r1);
+    level1(0, r0, x1);
+    next(lds2, i0 - 3, -1, x2, x0, x1, m1);  // level 2 at -1
+    load_row(2, r0);
+    level1(1, r1, x2);
+    next(lds2, i0 - 3, 0, x0, x1, x2, z0);   // level 2 at 0
+    load_row(3, r1);
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (4 + j <= len + 3) load_row(4 + j, raw[j]);
+    level1(2, r0, x0);
+    next(lds2, i0 - 3, 1, x1, x2, x0, l2b);  // level 2 at 1
+    level1(3, r1, x1);
+    next(lds2, i0 - 3, 2, x2, x0, x1, l2c);  // level 2 at 2
+    copy(l1b, x0);
+    copy(l1c, x1);
+    if (neumann) {
+      if (outside(1)) copy(l2b, z0);
+      if (outside(2)) copy(l2c, l2b);
+      if (outside(-1)) copy(m1, z0);
+      if (outside(-2)) copy(m2, m1);
+      if (outside(-3)) copy(m3, m2);
+    }
+    double2 y2[P], y1[P];                       // level 3 at -2, -1
+    next(lds3, i0 - 2, -2, m3, m2, m1, y2);
+    next(lds3, i0 - 2, -1, m2, m1, z0, y1);
+    next(lds3, i0 - 2, 0, m1, z0, l2b, l3b);    // level 3 at 0
+    next(lds3, i0 - 2, 1, z0, l2b, l2c, l3c);   // level 3 at 1
+    if (neumann) {
+      if (outside(1)) copy(l3c, l3b);
+      if (outside(-1)) copy(y1, l3b);
+      if (outside(-2)) copy(y2, y1);
+    }
+    next(lds4, i0 - 1, -1, y2, y1, l3b, l4b);   // level 4 at -1
+    next(lds4, i0 - 1, 0, y1, l3b, l3c, l4c);   // level 4 at 0
+    if (neumann && outside(-1)) copy(l4b, l4c);
+  }
+  // output row k; rw holds raw row k+4 and takes the load of row k+4+R
+  auto step = [&](int k, double2 (&rw)[P]) {
+    double2 l1a[P], l2a[P], l3a[P], l4a[P];
+    level1(k + 4, rw, l1a);
+    if (k + 4 + R <= len + 3) load_row(k + 4 + R, rw);  // in flight meanwhile
+    next(lds2, i0 - 3, k + 3, l1b, l1c, l1a, l2a);
+    if (neumann && outside(k + 3)) copy(l2a, l2c);
+    next(lds3, i0 - 2, k + 2, l2b, l2c, l2a, l3a);
+    if (neumann && outside(k + 2)) copy(l3a, l3c);
+    next(lds4, i0 - 1, k + 1, l3b, l3c, l3a, l4a);
+    if (neumann && outside(k + 1)) copy(l4a, l4c);
+    const int r = row_at(k);
+    Acc<15, true> acc;
+    acc.zero();
+    gptr<double> drow = dst + (long long)r * nv3;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const double2 g = transport_pair<DIR, SGN>(nuu, l4b[p], l4c[p], l4a[p]);
+      store_pair(drow, e.jofs[p], g);
+      acc.add(g, e.vx[p], e.vy[p], e.vz[p], dvz, e.q0(p), e.q1(p), nuu);
+    }
+    acc.store(I, b, r, tile, lane, vxu, nuu);
+    copy(l1b, l1c);
+    copy(l1c, l1a);
+    copy(l2b, l2c);
+    copy(l2c, l2a);
+    copy(l3b, l3c);
+    copy(l3c, l3a);
+    copy(l4b, l4c);
+    copy(l4c, l4a);
+  };
+  for (int k = 0; k < len; k += R) {
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (k + j < len) step(k + j, raw[j]);
+  }
+}
+
+template <int P, int MODE>
+struct Step4xCall {
+  template <int CASE, int DIR>
+  static __device__ __forceinline__ void run(const Inst& I, const double* lds1,
+                                             const double* lds2, const double* lds3,
+                                             const double* lds4, int b, int tile, int lane,
+                                             int i0, int i1, int phase, double vxu,
+                                             double nuu, int jx_base, int row_nx) {
+    step4x_march<P, MODE, CASE, DIR>(I, lds1, lds2, lds3, lds4, b, tile, lane, i0, i1,
+                                     phase, vxu, nuu, jx_base, row_nx);
+  }
+};
+
+template <int P, int MODE>
+__global__ __launch_bounds__(kBlock) void k_step4x(const Inst* __restrict__ insts,
+                                                   int n_inst, int chunk, int phase) {
+  extern __shared__ double lds[];
+  const long long item = xcd_item(blockIdx.x, gridDim.x) + insts[0].item_begin;
+  const int q = find_inst(insts, n_inst, item);
+  const Inst& I = insts[q];
+  const long long local = item - I.item_begin;
+  int b, tg, c;
+  decode_item(I, local, b, tg, c);
+  const int i0 = c * chunk;
+  const int i1 = min(i0 + chunk, I.nx);
+  const int len = i1 - i0;
+  constexpr int kTileV = 128 * P;
+  const int nyz = I.nvy * I.nvz;
+  const int v_first = tg * kWavesPerBlock * kTileV;
+  const int v_last = min((tg + 1) * kWavesPerBlock * kTileV, I.nv3) - 1;
+  const int jx_base = v_first / nyz;
+  const int row_nx = v_last / nyz - jx_base + 1;
+  const int rl = row_nx + I.nvy + I.nvz;
+  double* lds1 = lds;
+  double* lds2 = lds1 + (len + 8) * rl;
+  double* lds3 = lds2 + (len + 6) * rl;
+  double* lds4 = lds3 + (len + 4) * rl;
+  stage_rows_compact(I, I.fac, b, i0 - 4, len + 8, jx_base, row_nx, lds1);
+  stage_rows_compact(I, I.fac2, b, i0 - 3, len + 6, jx_base, row_nx, lds2);
+  stage_rows_compact(I, I.fac3, b, i0 - 2, len + 4, jx_base, row_nx, lds3);
+  stage_rows_compact(I, I.fac4, b, i0 - 1, len + 2, jx_base, row_nx, lds4);
+  __syncthreads();
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int tile = tg * kWavesPerBlock + wave;
+  if (tile >= I.ntiles) return;
+  double vxu, nuu;
+  using Call = Step4xCall<P, MODE>;
+  BGK_MARCH_DISPATCH_UNI(Call, I, lds1, lds2, lds3, lds4, b, tile, lane, i0, i1, phase, vxu,
+                         nuu, jx_base, row_nx);
+}
+
 // -------------------------------------------- partial sums of a field --
 // Moments of an arbitrary f (source fin), same tiling, no transport.
 template <int E>
@@ -1743,7 +1959,8 @@ __device__ __forceinline__ void write_factors(const Inst& I, double* row,
 
 // Separable moment sums of the Maxwellian with factors exp(-(v-u)^2/(2 theta))
 // per axis (C0 * dv3 applied by the caller): for weights w of v_x in {1, nu+,
-// nu-} (NW = 3) and also nu+^2, nu-^2 (NW = 5), nu = v_x dt/dx, A^w = (rho,
+// nu-} (NW = 3), also nu+^2, nu-^2 (NW = 5) and nu+^3, nu-^3 (NW = 7),
+// nu = v_x dt/dx, A^w = (rho,
 // m_x, m_y, m_z, E) moments of w M, scaled by K = C0 dv3: 5 NW values in that
 // weight order.  All lanes return the same values.
 // row (nullable): also writes the factor row of the same exponentials (Ex
@@ -1774,10 +1991,15 @@ __device__ __forceinline__ void maxwell_weighted_sums(const Inst& I, int lane,
       t[0] += ex; t[1] += e1; t[2] += e2;
       t[3] += wp * ex; t[4] += wp * e1; t[5] += wp * e2;
       t[6] += wm * ex; t[7] += wm * e1; t[8] += wm * e2;
-      if (NW == 5) {
+      if (NW >= 5) {
         const double wpp = wp * wp, wmm = wm * wm;
         t[9] += wpp * ex; t[10] += wpp * e1; t[11] += wpp * e2;
         t[12] += wmm * ex; t[13] += wmm * e1; t[14] += wmm * e2;
+        if (NW == 7) {
+          const double w3p = wpp * wp, w3m = wmm * wm;
+          t[15] += w3p * ex; t[16] += w3p * e1; t[17] += w3p * e2;
+          t[18] += w3m * ex; t[19] += w3m * e1; t[20] += w3m * e2;
+        }
       }
     } else if (ax == 1) {
       t[3 * NW] += ex; t[3 * NW + 1] += e1; t[3 * NW + 2] += e2;
@@ -1809,6 +2031,95 @@ __device__ __forceinline__ void cons_to_prim(const double* V, double& rho, doubl
   th = (2.0 * V[4] / rho - usq) / 3.0;
 }
 
+// Offset of weight class w (0: 1; 2q - 1: nu+^q; 2q: nu-^q) in an aux-style
+// layout, for the sums of g (maxw false) or of its Maxwellian (true).
+__device__ __forceinline__ constexpr int aux_off(int w, bool maxw) {
+  return w == 0 ? (maxw ? 15 : 0)
+                : (w <= 2 ? 5 * w + (maxw ? 15 : 0)
+                          : 30 + 20 * ((w + 1) / 2 - 2) + (w % 2 == 0 ? 5 : 0) +
+                                (maxw ? 10 : 0));
+}
+static_assert(aux_off(0, false) == 0 && aux_off(1, false) == 5 && aux_off(2, false) == 10 &&
+                  aux_off(0, true) == 15 && aux_off(1, true) == 20 && aux_off(2, true) == 25 &&
+                  aux_off(3, false) == 30 && aux_off(4, false) == 35 && aux_off(3, true) == 40 &&
+                  aux_off(4, true) == 45 && aux_off(5, false) == 50 && aux_off(6, false) == 55 &&
+                  aux_off(5, true) == 60 && aux_off(6, true) == 65,
+              "aux layout");
+
+// Moments of the next transported field T(a g + al M[U(g)]) at a cell and its
+// sums weighted by nu+^q, nu-^q up to q = PIN - 1, from the sums of g and M
+// at cells i-1, i, i+1 (input layout of highest power PIN: upwind transport
+// T h_i = (1 - nu+ - nu-) h_i + nu+ h_{i-1} + nu- h_{i+1} with nu+ nu- = 0
+// gives S^0[T h]_i = S^0_i - S^{1+}_i - S^{1-}_i + S^{1+}_{i-1} + S^{1-}_{i+1},
+// S^{q+}[T h]_i = S^{q+}_i - S^{(q+1)+}_i + S^{(q+1)+}_{i-1} and the mirror
+// for q-).  Writes the factor row of the new field's Maxwellian into fac_out
+// and, for PIN >= 2, its sums and the Maxwellian's into out (layout of
+// highest power PIN - 1); with PROJECT instead the projected relaxed moments
+// a V + al V(M) into vout.  One wave per cell; every lane returns.
+template <int PIN, bool PROJECT>
+__device__ __forceinline__ void advance_reduce(const Inst& I, long long cl, int lane,
+                                               const double* in, int in_stride,
+                                               double* fac_out, double* out, int out_stride,
+                                               int* status) {
+  constexpr int NWO = 2 * PIN - 1;  // weight classes of the output
+  const int nx = I.nx;
+  const long long b = cl / nx;
+  const int i = (int)(cl - b * nx);
+  gptr<const double> ac = gmem(in) + cl * in_stride;
+  gptr<const double> am = gmem(in) + (b * nx + ghost_row(i - 1, nx, I.bc)) * in_stride;
+  gptr<const double> ap = gmem(in) + (b * nx + ghost_row(i + 1, nx, I.bc)) * in_stride;
+  double val = 0.0;
+  if (lane < 5 * NWO) {
+    const int w = lane / 5, c = lane - 5 * (lane / 5);
+    double tg, tm;
+    if (w == 0) {
+      tg = ac[c] - ac[5 + c] - ac[10 + c] + am[5 + c] + ap[10 + c];
+      tm = ac[15 + c] - ac[20 + c] - ac[25 + c] + am[20 + c] + ap[25 + c];
+    } else {
+      // class w = (q, sign); the next power of the same sign is class w + 2
+      const bool plus = (w % 2) == 1;
+      const int og = aux_off(w, false), og1 = aux_off(w + 2, false);
+      const int om = aux_off(w, true), om1 = aux_off(w + 2, true);
+      gptr<const double> nb = plus ? am : ap;
+      tg = ac[og + c] - ac[og1 + c] + nb[og1 + c];
+      tm = ac[om + c] - ac[om1 + c] + nb[om1 + c];
+    }
+    val = I.a * tg + I.al * tm;
+  }
+  double V[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) V[c] = readlane_d(val, c);
+  double rho, u[3], th;
+  cons_to_prim(V, rho, u, th);
+  if (lane == 0 && !physical(rho, th)) *status = 1;
+  const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
+  if (PROJECT) {
+    double A[15];
+    maxwell_weighted_sums<3>(I, lane, u, th, C0 * I.dv3, A);
+    if (lane == 0) {
+      double* vo = I.vout + cl * 5;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) vo[c] = I.a * V[c] + I.al * A[c];
+    }
+    return;
+  }
+  double* frow = fac_out + cl * I.nvs;
+  if (NWO == 1) {
+    write_factors(I, frow, lane, I.al * C0, u, th);
+    return;
+  }
+  double A[5 * NWO];
+  maxwell_weighted_sums<NWO>(I, lane, u, th, C0 * I.dv3, A, frow, I.al * C0);
+  double* ax = out + cl * out_stride;
+  if (lane < 5 * NWO) ax[aux_off(lane / 5, false) + lane % 5] = val;
+  if (lane == 0) {
+#pragma unroll
+    for (int w = 0; w < NWO; ++w)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) ax[aux_off(w, true) + c] = A[5 * w + c];
+  }
+}
+
 // One wave per (instance, member, x cell).  The mode is a template argument
 // so that the independent wave reductions are unrolled and interleaved.
 template <int mode>
@@ -1822,6 +2133,22 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
   long long cl;
   const int q = find_inst_cell(insts, n_inst, cell, &cl);
   const Inst& I = insts[q];
+  if (mode == kRedW2x4) {
+    advance_reduce<3, false>(I, cl, lane, I.aux, kAux, I.fac2, I.aux2, kAux2, status);
+    return;
+  }
+  if (mode == kRedW3x4) {
+    advance_reduce<2, false>(I, cl, lane, I.aux2, kAux2, I.fac3, I.aux3, kAux3, status);
+    return;
+  }
+  if (mode == kRedW4x4) {
+    advance_reduce<1, false>(I, cl, lane, I.aux3, kAux3, I.fac4, nullptr, 0, status);
+    return;
+  }
+  if (mode == kRedW4x4Project) {
+    advance_reduce<1, true>(I, cl, lane, I.aux3, kAux3, nullptr, nullptr, 0, status);
+    return;
+  }
   if (mode == kRedW2 || mode == kRedW2x3 || mode == kRedW3x3 || mode == kRedW2Project ||
       mode == kRedW3x3Project) {
     // moments of the next transported field T(a g + al M[U(g)]) at this cell
@@ -1893,10 +2220,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
   gptr<const double> pp = gmem(I.part) + cl * I.part_tiles * 5;
   // weight classes of the sums: 1 (and nu+, nu- for W1; and nu+^2, nu-^2
   // for W1x3, which needs compact records)
-  constexpr int NW = mode == kRedW1x3 ? 5 : (mode == kRedW1 ? 3 : 1);
-  double s[25];
+  constexpr int NW = mode == kRedW1x4 ? 7 : (mode == kRedW1x3 ? 5 : (mode == kRedW1 ? 3 : 1));
+  double s[35];
 #pragma unroll
-  for (int c = 0; c < 25; ++c) s[c] = 0.0;
+  for (int c = 0; c < 35; ++c) s[c] = 0.0;
   if (I.crec) {
     // compact records (tiles inside one v_x plane): (sum g, sum v_y g,
     // sum v_z g, sum |v|^2 g); v_x and nu are the tile's
@@ -1933,12 +2260,20 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
             s[5 + c] += wp * m[c];
             s[10 + c] += wm * m[c];
           }
-          if (NW == 5) {
+          if (NW >= 5) {
             const double wpp = wp * wp, wmm = wm * wm;
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
               s[15 + c] += wpp * m[c];
               s[20 + c] += wmm * m[c];
+            }
+            if (NW == 7) {
+              const double w3p = wpp * wp, w3m = wmm * wm;
+#pragma unroll
+              for (int c = 0; c < 5; ++c) {
+                s[25 + c] += w3p * m[c];
+                s[30 + c] += w3m * m[c];
+              }
             }
           }
         }
@@ -1997,11 +2332,25 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
   }
   const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
   if (mode == kRedRelaxFactors || mode == kRedMaxwellFactors || mode == kRedW1 ||
-      mode == kRedW1x3) {
+      mode == kRedW1x3 || mode == kRedW1x4) {
     // (W1, W1x3: the factor row is written with the weighted sums' exponentials)
     if (mode == kRedRelaxFactors || mode == kRedMaxwellFactors)
       write_factors(I, I.fac + cl * I.nvs, lane,
                     mode == kRedMaxwellFactors ? C0 : I.al * C0, u, th);
+    if (mode == kRedW1x4) {
+      double A[35];
+      maxwell_weighted_sums<7>(I, lane, u, th, C0 * I.dv3, A, I.fac + cl * I.nvs, I.al * C0);
+      if (lane == 0) {
+        double* ax = I.aux + cl * kAux;
+#pragma unroll
+        for (int w = 0; w < 7; ++w)
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            ax[aux_off(w, false) + c] = s[5 * w + c];
+            ax[aux_off(w, true) + c] = A[5 * w + c];
+          }
+      }
+    }
     if (mode == kRedW1x3) {
       double A[25];
       maxwell_weighted_sums<5>(I, lane, u, th, C0 * I.dv3, A, I.fac + cl * I.nvs, I.al * C0);
@@ -2084,6 +2433,20 @@ __global__ __launch_bounds__(kBlock) void k_lift_factors(
         ax[c] = A[c];
         ax[15 + c] = A[c];
       }
+    }
+  } else if (with_aux == 3) {
+    // to the third power, for a four-step first pass
+    double A[35];
+    maxwell_weighted_sums<7>(I, lane, u, th, C0 * I.dv3, A, row, C0);
+    if (lane == 0) {
+      double* ax = I.aux + cl * kAux;
+#pragma unroll
+      for (int w = 0; w < 7; ++w)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          ax[aux_off(w, false) + c] = A[5 * w + c];
+          ax[aux_off(w, true) + c] = A[5 * w + c];
+        }
     }
   } else if (with_aux == 2) {
     // with the nu+^2, nu-^2 weighted sums, for a three-step first pass
@@ -2331,6 +2694,29 @@ int launch_step3x(const Inst* d_insts, int n_inst, long long total_items, int mo
   return BGK_E_INVALID;
 }
 
+int launch_step4x(const Inst* d_insts, int n_inst, long long total_items, int mode,
+                  int phase, Tiles t, int lds_doubles, hipStream_t s) {
+  if (total_items <= 0) return BGK_OK;
+  if (!t.pair || t.elems != 2) {
+    set_error("four-step passes need the paired lane mapping with one pair per lane");
+    return BGK_E_INVALID;
+  }
+  dim3 grid(blocks_for(total_items)), block(kBlock);
+  const size_t lds = (size_t)lds_doubles * sizeof(double);
+  if (mode == kRelax)
+    hipLaunchKernelGGL((k_step4x<1, kRelax>), grid, block, lds, s, d_insts, n_inst, t.chunk,
+                       phase);
+  else if (mode == kLift)
+    hipLaunchKernelGGL((k_step4x<1, kLift>), grid, block, lds, s, d_insts, n_inst, t.chunk,
+                       phase);
+  else {
+    set_error("unsupported mode for a four-step pass");
+    return BGK_E_INVALID;
+  }
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
 int launch_partials(const Inst* d_insts, int n_inst, long long total_items,
                     int elems, int chunk, hipStream_t s) {
   if (total_items <= 0) return BGK_OK;
@@ -2371,6 +2757,11 @@ int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
     BGK_REDUCE_CASE(kRedW3x3)
     BGK_REDUCE_CASE(kRedW2Project)
     BGK_REDUCE_CASE(kRedW3x3Project)
+    BGK_REDUCE_CASE(kRedW1x4)
+    BGK_REDUCE_CASE(kRedW2x4)
+    BGK_REDUCE_CASE(kRedW3x4)
+    BGK_REDUCE_CASE(kRedW4x4)
+    BGK_REDUCE_CASE(kRedW4x4Project)
 #undef BGK_REDUCE_CASE
     default:
       set_error("unknown reduction mode");

@@ -56,14 +56,14 @@ def test_host_only_calls():
     assert lib.bgk_set_tiles(0, 0, -1) == bgk.OK
     # nothing cached in a process that made no GPU call: no device call
     assert lib.bgk_release_graphs() == bgk.OK
-    # steps per pass: 1, 2 or 3 (the default)
-    for bad in (0, 4, -1):
+    # steps per pass: 1, 2, 3 (the default) or 4
+    for bad in (0, 5, -1):
         assert lib.bgk_set_step_fusion(bad) == bgk.E_INVALID
-    for good in (1, 2, 3):
+    for good in (1, 2, 4, 3):
         assert lib.bgk_set_step_fusion(good) == bgk.OK
-    # timing kinds 0 .. BGK_PROF_THREE_STEP_LIFT
-    assert lib.bgk_prof_read(bgk.PROF_THREE_STEP_LIFT, None, None, None, None) == bgk.OK
-    assert lib.bgk_prof_read(bgk.PROF_THREE_STEP_LIFT + 1, None, None, None, None) == bgk.E_INVALID
+    # timing kinds 0 .. BGK_PROF_FOUR_STEP_LIFT
+    assert lib.bgk_prof_read(bgk.PROF_FOUR_STEP_LIFT, None, None, None, None) == bgk.OK
+    assert lib.bgk_prof_read(bgk.PROF_FOUR_STEP_LIFT + 1, None, None, None, None) == bgk.E_INVALID
 
 
 def test_problem_struct_layout_matches_oracle():
