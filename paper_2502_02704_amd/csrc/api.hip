@@ -596,7 +596,8 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
   auto single = [&](int mode) -> int {
     prof_before(s);
     int r = launch_step(d_I, 1, h.items, mode, phase, t, lds_doubles(h, t), d_status, s,
-                        h.nsum, h.efield != nullptr, h.order == 2 ? 2 : 1);
+                        h.nsum, h.efield != nullptr, h.order == 2 ? 2 : 1,
+                        h.order == 2 && h.crec != 0);
     prof_after(s, upd, mode == kLift ? 8.0 : 16.0, BGK_PROF_ONE_STEP);
     phase ^= 1;
     return r;
@@ -976,11 +977,16 @@ static int check_force(const bgk_problem& p, const Force& F, int* d_status, hipS
 }
 
 // Method fields of a descriptor (the v_x flux needs dt / dv_x).
-static void attach_force(Inst& I, const bgk_problem& p, const Force& F, double dt) {
+static void attach_force(Inst& I, const bgk_problem& p, const Force& F, double dt, Tiles t) {
   I.efield = F.E;
   I.emax = F.emax;
   I.rv = dt / dv_of(p, 0);
   I.order = F.order;
+  // the limited step without force on tiles that each lie in one v_x plane
+  // writes compact records
+  if (F.order == 2 && !F.on() && !t.vcol && !t.pair &&
+      ((long long)p.nv[1] * p.nv[2]) % (kWave * t.elems) == 0)
+    I.crec = kWave * t.elems;
 }
 
 // Tiles and sums per partial for a fine solve of `n` steps: the force step
@@ -1199,7 +1205,7 @@ static int fine_steps_impl(const bgk_problem* prob, const Force& F, const double
   const Tiles t = aligned_tiles(fine_tiles(*prob, 1, F), *prob, {f_in, f_out});
   Inst I = make_inst(*prob, 1, dt, t, fine_nsum(t, n_steps, F));
   attach_fine(I, ws, L.fine, f_out);  // ping-pong between ws and f_out
-  attach_force(I, *prob, F, dt);
+  attach_force(I, *prob, F, dt, t);
   I.fin = f_in;
   I.fout = f_out;
   Inst* dI = at<Inst>(ws, L.insts);
@@ -1274,7 +1280,7 @@ static int propagate_impl(const bgk_problem* prob, const Force& F, int lift_orde
   const Tiles t = fine_tiles(*prob, batch, F);
   Inst I = make_inst(*prob, batch, dt, t, fine_nsum(t, n, F));
   attach_fine(I, ws, L.fine, nullptr);
-  attach_force(I, *prob, F, dt);
+  attach_force(I, *prob, F, dt, t);
   prepare_lift(I, lift_order);
   I.vin = V_in;
   I.vout = V_out;
@@ -1398,7 +1404,7 @@ static int parareal_impl(const bgk_problem* prob, const Force& F, bool viscous,
     const Tiles t = fine_tiles(*prob, B, F);
     Inst I = make_inst(*prob, B, dt, t, fine_nsum(t, n, F));
     attach_fine(I, ws, L.fine, nullptr);
-    attach_force(I, *prob, F, dt);
+    attach_force(I, *prob, F, dt, t);
     prepare_lift(I, lift_order);
     I.vin = U[cur] + (size_t)k * sl;        // U^{n-1,k}, n = k+1..N
     I.vout = VF + (size_t)(k + 1) * sl;     // P F L(U^{n-1,k})
@@ -1517,7 +1523,7 @@ static int serial_impl(const bgk_problem* prob, const Force& F, int lift_order,
     int r;
     Inst I = make_inst(*prob, 1, dt, t, ns);
     attach_fine(I, ws, L.fine, nullptr);
-    attach_force(I, *prob, F, dt);
+    attach_force(I, *prob, F, dt, t);
     prepare_lift(I, lift_order);
     for (int m = 1; m <= n_slices; ++m) {
       I.vin = U + (size_t)(m - 1) * sl;

@@ -203,9 +203,12 @@ Tiles choose_tiles(const bgk_problem& p, int batch, bool generic = false,
 // the v_x-column mapping t.vcol).
 // order 2: x transport with the van Leer limited Lax-Wendroff correction
 // (generic lanes, 2 or 4 elements per lane, LDS rows for (chunk + 4) cells).
+// uni: the limited step on tiles that each lie in one v_x plane (compact
+// records; the descriptor's crec set).
 int launch_step(const Inst* d_insts, int n_inst, long long total_items,
                 int mode, int phase, Tiles t, int lds_doubles, int* d_status,
-                hipStream_t s, int ns = 5, bool force = false, int order = 1);
+                hipStream_t s, int ns = 5, bool force = false, int order = 1,
+                bool uni = false);
 // Per-x-cell reduction of partial sums into moments and factors.
 int launch_reduce(const Inst* d_insts, int n_inst, long long total_cells,
                   int mode, int phase, int* d_status, hipStream_t s);

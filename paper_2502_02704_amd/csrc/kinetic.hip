@@ -361,8 +361,12 @@ __device__ __forceinline__ double flux2(double vx, double anu, double fm, double
 }
 
 // NS = 15: the records also carry the nu+ and nu- weighted sums (fused
-// passes on grids without paired rows; plain step only).
-template <int E, int MODE, bool FORCE = false, bool LIMITED = false, int NS = 5>
+// passes on grids without paired rows; plain step only).  UNI (the limited
+// step without force): every tile lies in one v_x plane, so v_x and nu are
+// the wave's, the upwind side is uniform, and the record is compact (sum g,
+// sum v_y g, sum v_z g, sum |v|^2 g; the reduction rebuilds sum v_x g).
+template <int E, int MODE, bool FORCE = false, bool LIMITED = false, int NS = 5,
+          bool UNI = false>
 __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
                                                  int n_inst, int chunk,
                                                  int phase) {
@@ -404,9 +408,16 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
   src += mbase + tile * (kWave * E) + lane;
   dst += mbase + tile * (kWave * E) + lane;
   const double a = I.a;
-  double nu[E];
+  static_assert(!UNI || (LIMITED && !FORCE && NS == 5), "uniform tiles: limited step only");
+  double nu[E], vsq[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) nu[e] = el.vx[e] * I.r;
+  for (int e = 0; e < E; ++e) {
+    nu[e] = el.vx[e] * I.r;
+    vsq[e] = el.vx[e] * el.vx[e] + el.vy[e] * el.vy[e] + el.vz[e] * el.vz[e];
+  }
+  // the tile's v_x and nu (UNI)
+  const double vxu = UNI ? uniform_d(vgrid(I, 0, (tile * kWave * E) / (I.nvy * I.nvz))) : 0.0;
+  const double nuu = vxu * I.r;
 
   // relaxed value of row r (global row index, ghost-mapped) from raw g
   auto relax_row = [&](int r, const double* raw, double* out) {
@@ -467,7 +478,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
   if (LIMITED) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      fcar[e] = flux2(el.vx[e], fabs(nu[e]), w[0][e], w[1][e], w[2][e], w[3 < 2 * H ? 3 : 0][e]);
+      fcar[e] = flux2(UNI ? vxu : el.vx[e], fabs(UNI ? nuu : nu[e]), w[0][e], w[1][e], w[2][e],
+                      w[3 < 2 * H ? 3 : 0][e]);
   }
   static_assert(NS == 5 || (NS == 15 && !FORCE && !LIMITED), "weighted sums: plain step");
   gptr<double> part = gmem(I.part) + ((long long)b * nx) * I.part_tiles * 5 + (long long)tile * NS;
@@ -485,8 +497,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
     for (int e = 0; e < E; ++e) {
       double gs;
       if (LIMITED) {
-        const double fr = flux2(el.vx[e], fabs(nu[e]), w[H - 1][e], w[H][e], w[H + 1][e],
-                                w[H + 2 < 2 * H + 1 ? H + 2 : 2 * H][e]);
+        const double fr = flux2(UNI ? vxu : el.vx[e], fabs(UNI ? nuu : nu[e]), w[H - 1][e],
+                                w[H][e], w[H + 1][e], w[H + 2 < 2 * H + 1 ? H + 2 : 2 * H][e]);
         gs = w[H][e] - I.r * (fr - fcar[e]);
         fcar[e] = fr;
       } else {
@@ -508,16 +520,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
         gs -= I.rv * (g_up - g_down);
       }
       if (el.ok[e]) dst[(long long)i * nv3 + e * kWave] = gs;
-      const double vsq = el.vx[e] * el.vx[e] + el.vy[e] * el.vy[e] +
-                         el.vz[e] * el.vz[e];
       s0 += gs;
-      s1 = fma(el.vx[e], gs, s1);
+      if (!UNI) s1 = fma(el.vx[e], gs, s1);
       s2 = fma(el.vy[e], gs, s2);
       s3 = fma(el.vz[e], gs, s3);
-      s4 = fma(vsq, gs, s4);
+      s4 = fma(vsq[e], gs, s4);
       if (NS == 15) {
         const double cp = nu[e] > 0.0 ? nu[e] : 0.0, cm = nu[e] < 0.0 ? -nu[e] : 0.0;
-        const double m[5] = {gs, el.vx[e] * gs, el.vy[e] * gs, el.vz[e] * gs, vsq * gs};
+        const double m[5] = {gs, el.vx[e] * gs, el.vy[e] * gs, el.vz[e] * gs, vsq[e] * gs};
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
           sw[c] = fma(cp, m[c], sw[c]);
@@ -534,6 +544,12 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
       const double tot = wave_reduce_scatter<16>(t16, lane);
       const int slot = slot_of_lane<16>(lane);
       if (lane < 16 && slot < 15) part[(long long)i * I.part_tiles * 5 + slot] = tot;
+    } else if (UNI) {
+      // compact record: the four totals by reduce-scatter (lanes 0..3)
+      double t4[4] = {s0, s2, s3, s4};
+      const double tot = wave_reduce_scatter<4>(t4, lane);
+      gptr<double> crec = gmem(I.part) + ((long long)b * nx + i) * I.part_tiles * 5 + tile * 4;
+      if (lane < 4) crec[slot_of_lane<4>(lane)] = tot;
     } else {
       // the wave's five sums by reduce-scatter: lanes 0..7 hold the totals
       double t8[8] = {s0, s1, s2, s3, s4, 0.0, 0.0, 0.0};
@@ -2515,7 +2531,7 @@ static int blocks_for(long long n) { return (int)n; }
 
 int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode,
                 int phase, Tiles t, int lds_doubles, int* d_status, hipStream_t s,
-                int ns, bool force, int order) {
+                int ns, bool force, int order, bool uni) {
   (void)d_status;
   if (total_items <= 0) return BGK_OK;
   dim3 grid(blocks_for(total_items)), block(kBlock);
@@ -2567,6 +2583,13 @@ int launch_step(const Inst* d_insts, int n_inst, long long total_items, int mode
       BGK_STEP_CASE((k_step<4, kCopy, true, true>), 4, kCopy)
       BGK_STEP_CASE((k_step<4, kRelax, true, true>), 4, kRelax)
       BGK_STEP_CASE((k_step<4, kLift, true, true>), 4, kLift)
+    } else if (uni) {
+      BGK_STEP_CASE((k_step<2, kCopy, false, true, 5, true>), 2, kCopy)
+      BGK_STEP_CASE((k_step<2, kRelax, false, true, 5, true>), 2, kRelax)
+      BGK_STEP_CASE((k_step<2, kLift, false, true, 5, true>), 2, kLift)
+      BGK_STEP_CASE((k_step<4, kCopy, false, true, 5, true>), 4, kCopy)
+      BGK_STEP_CASE((k_step<4, kRelax, false, true, 5, true>), 4, kRelax)
+      BGK_STEP_CASE((k_step<4, kLift, false, true, 5, true>), 4, kLift)
     } else {
       BGK_STEP_CASE((k_step<2, kCopy, false, true>), 2, kCopy)
       BGK_STEP_CASE((k_step<2, kRelax, false, true>), 2, kRelax)
