@@ -3,9 +3,10 @@
 A step = one pass of the whole hot path over one batch: all 32 parareal
 slices of the large Sod workload (Nx=2048, 48^3 velocities on [-10,10]^3,
 eps=1e-3, zero-gradient ends) are lifted from their moments, advanced by one
-slice span (188 IMEX steps: a two-step pass from the lift, then 62 three-step
-passes over f) and projected back to moments, all slices batched in one
-launch per pass (7.25e9 phase-space cells per buffer).  Prints one JSON line:
+slice span (188 IMEX steps: a three-step pass from the lift, 61 three-step
+passes over f, and the last two steps evaluated on the moments, exactly, from
+weighted sums of the last stored field) and projected back to moments, all
+slices batched in one launch per pass (7.25e9 phase-space cells per buffer).  Prints one JSON line:
 phase-space updates/s, the roofline of the dominant kernel (the three-step
 relax pass) under both byte models, the CPU oracle timed on a bounded sample,
 and secondary sections: the smooth periodic workload (Nx=512, 32^3, 64 slices)
@@ -88,8 +89,11 @@ def workload_batch(name, eps=None):
 
 def steps_on_moments(n):
     """Steps of a propagation with three steps per pass that are evaluated on
-    the moments only (not written out as f)."""
-    return (n - 2) % 3 if n >= 4 else 0
+    the moments only (not written out as f): after a three-step first pass
+    from the lift when n = 2 mod 3, else after a two-step one."""
+    if n < 4:
+        return 0
+    return 2 if n >= 5 and n % 3 == 2 else (n - 2) % 3
 
 
 def traffic_from_profile(workload, which):

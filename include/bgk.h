@@ -140,11 +140,12 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
 /* Steps 5-7 of Algorithm 2 for a batch of slices: V_out[b] =
  * P F L(V_in[b]) over t_span (lift, fine propagation, projection), all
  * members in one launch per pass.  From the Maxwellian lift (order 0), with
- * no exterior force and first-order transport, the last one or two steps are
- * not written out as f: (n - 2) mod 3 of them for n >= 4 under triples
- * (after a first two-step pass from the lift), one for odd n >= 3 under
+ * no exterior force and first-order transport, the last steps are not
+ * written out as f: under triples two for n = 2 mod 3, n >= 5 (after a first
+ * three-step pass from the lift), else (n - 2) mod 3 for n >= 4 (after a
+ * first two-step pass); under quads (n - 4) mod 4; one for odd n >= 3 under
  * pairs.  Their moments, and the projection, follow from moment sums of the
- * last stored field weighted by 1, max(+-nu,0) and their squares (transport
+ * last stored field weighted by 1 and powers of max(+-nu,0) (transport
  * being linear); V_out equals advancing f through every step to rounding.
  * The same holds for parareal_iterate and bgk_serial_fine.  [device] V_in,
  * V_out [batch][nx][5] conserved; may not overlap. */

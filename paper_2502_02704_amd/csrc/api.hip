@@ -711,10 +711,19 @@ static int run_steps(const Inst* d_I, const Inst& h, int n, int first_mode,
     // Then the first pass takes two steps from the lift (cheaper than three),
     // three-step passes follow, and virt = (n - 2) mod 3 steps close on the
     // moments.
-    const int virt = (project_last && first_mode == kLift && n >= 4) ? (n - 2) % 3 : 0;
+    // For n = 2 mod 3 (n >= 5) the first pass takes three steps from the lift
+    // and two steps close on the moments: one relax pass fewer than a
+    // two-step first pass followed by triples.
+    const bool proj_lift = project_last && first_mode == kLift && n >= 4;
+    const bool lift3 = proj_lift && n >= 5 && n % 3 == 2;
+    const int virt = lift3 ? 2 : (proj_lift ? (n - 2) % 3 : 0);
     // the first pass starts from the lift (write-only) or the copy: n mod 3
     // decides whether it takes three, two or one step
-    if (virt) {
+    if (lift3) {
+      if ((rc = reduce(kRedW2x3))) return rc;
+      if ((rc = reduce(kRedW3x3))) return rc;
+      if ((rc = triple_pass(kLift))) return rc;
+    } else if (virt) {
       if ((rc = reduce(kRedW2))) return rc;
       if ((rc = pair_pass(kLift))) return rc;
     } else if (first_mode == kLift && n >= 3 && n % 3 == 0) {
