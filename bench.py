@@ -303,10 +303,11 @@ def force_throughput(torch, bgk, wl, reps=5):
 def uneven_throughput(torch, bgk, wl, span=0.1, reps=3):
     """The uneven multi-instance batch (seeded Riemann problems with Nx in
     [128, 1024], Nv in [16, 32], eps in [1e-4, 1]) advanced together: every
-    instance's first step alone, then per round one two-step pass over the
-    instances with two or more steps left and one step for those with one
-    left (the library's built-in setting), and, for comparison, one step per
-    launch.  Instances 7, 15 and 29 are left out: their cold states are not
+    instance's first step alone, then per round one fused pass over the
+    instances with two or more steps left (three steps for those with paired
+    rows whose v_x planes are whole tiles and three or more steps left, else
+    two) and one step for those with one left (the library's built-in
+    setting), and, for comparison, one step per launch.  Instances 7, 15 and 29 are left out: their cold states are not
     resolved on their velocity grids (theta / dv^2 = 0.11, 0.29, 0.33) and
     their temperatures collapse within the span, in the oracle too."""
     insts = [w for q, w in enumerate(wl.c5_uneven()) if q not in (7, 15, 29)]
@@ -334,7 +335,8 @@ def uneven_throughput(torch, bgk, wl, span=0.1, reps=3):
         torch.cuda.synchronize()
         el = (time.perf_counter() - t0) / reps
         kinds = {name: bgk.prof_read(kind) for name, kind in
-                 (("two_step_pass", bgk.PROF_TWO_STEP), ("one_step", bgk.PROF_ONE_STEP))}
+                 (("three_step_pass", bgk.PROF_THREE_STEP), ("two_step_pass", bgk.PROF_TWO_STEP),
+                  ("one_step", bgk.PROF_ONE_STEP))}
         bgk.prof_enable(False)
         bgk.check_status()
         return el, kinds
@@ -351,6 +353,11 @@ def uneven_throughput(torch, bgk, wl, span=0.1, reps=3):
             line[name + "_GBs"] = round(by / (ms * 1e-3) / 1e9, 1)
             line[name + "_avg_us"] = round(ms * 1e3 / launches, 2)
             line[name + "_launches"] = launches
+    # the fused passes together: algorithmic bytes over their kernel time
+    f_ms = sum(kinds[k][0] for k in ("three_step_pass", "two_step_pass"))
+    f_by = sum(kinds[k][3] for k in ("three_step_pass", "two_step_pass"))
+    if f_ms > 0:
+        line["fused_passes_GBs"] = round(f_by / (f_ms * 1e-3) / 1e9, 1)
     bgk.set_step_fusion(1)
     try:
         el1, _ = timed()
