@@ -1,10 +1,18 @@
-"""Shared helpers of the GPU parity tests (comparison norms)."""
+"""Shared helpers of the GPU parity tests (comparison norms).
+
+Every norm evaluated here is also recorded in ERRORS, so that the test
+session can report, per test, the largest error it measured against the
+bar (the margin of each parity check)."""
 import numpy as np
+
+ERRORS = []  # errors measured by the running test (cleared per test)
 
 
 def rel_f(got, ref):
     """Normwise relative max-norm error of a phase-space field."""
-    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    e = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    ERRORS.append(e)
+    return e
 
 
 def rel_V(got, ref):
@@ -16,7 +24,9 @@ def rel_V(got, ref):
     e = np.max(np.abs(ref[:, 4]))
     m = np.sqrt(r * 2 * e)
     d = np.abs(got - ref)
-    return max(np.max(d[:, 0]) / r, np.max(d[:, 1:4]) / m, np.max(d[:, 4]) / e)
+    err = float(max(np.max(d[:, 0]) / r, np.max(d[:, 1:4]) / m, np.max(d[:, 4]) / e))
+    ERRORS.append(err)
+    return err
 
 
 def rel_W(got, ref):
@@ -27,8 +37,10 @@ def rel_W(got, ref):
     ref = np.asarray(ref).reshape(-1, 5)
     d = np.abs(got - ref)
     th = np.max(np.abs(ref[:, 4]))
-    return (float(np.max(d[:, 0]) / np.max(np.abs(ref[:, 0]))),
+    errs = (float(np.max(d[:, 0]) / np.max(np.abs(ref[:, 0]))),
             float(np.max(d[:, 1:4]) / np.sqrt(th)), float(np.max(d[:, 4]) / th))
+    ERRORS.append(max(errs))
+    return errs
 
 
 TOL = 1e-12  # parity bar on f and moments (max norm, normwise relative)
