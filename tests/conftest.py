@@ -61,7 +61,7 @@ def pytest_terminal_summary(terminalreporter):
     tr = terminalreporter
     tr.section("parity margins")
     rows = sorted(_MARGINS.items(), key=lambda kv: -kv[1][0])
-    n_cmp = sum(c for _, c in rows)
+    n_cmp = sum(c for _, (_, c) in rows)
     tr.write_line(f"{len(rows)} tests, {n_cmp} normwise comparisons; largest errors "
                   f"(fraction of the {TOL:g} bar):")
     for nodeid, (e, c) in rows[:20]:
