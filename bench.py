@@ -303,11 +303,11 @@ def force_throughput(torch, bgk, wl, reps=5):
 def uneven_throughput(torch, bgk, wl, span=0.1, reps=3):
     """The uneven multi-instance batch (seeded Riemann problems with Nx in
     [128, 1024], Nv in [16, 32], eps in [1e-4, 1]) advanced together: every
-    instance's first step alone, then per round one fused pass over the
-    instances with two or more steps left (three steps for those with paired
-    rows whose v_x planes are whole tiles and three or more steps left, else
-    two) and one step for those with one left (the library's built-in
-    setting), and, for comparison, one step per launch.  Instances 7, 15 and 29 are left out: their cold states are not
+    instance's first step alone, then per round one two-step pass over the
+    instances with two or more steps left and one step for those with one
+    left (the library's built-in setting; instances with odd Nv on padded
+    copies), and, for comparison, one step per launch.  Instances 7, 15 and
+    29 are left out: their cold states are not
     resolved on their velocity grids (theta / dv^2 = 0.11, 0.29, 0.33) and
     their temperatures collapse within the span, in the oracle too."""
     insts = [w for q, w in enumerate(wl.c5_uneven()) if q not in (7, 15, 29)]

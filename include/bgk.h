@@ -123,14 +123,18 @@ int bgk_fine_step(const bgk_problem* prob, const double* f_in, double* f_out,
 
 /* Uneven batch of independent problems, batched launches over the instances
  * still stepping: instance q advances f_in[q] -> f_out[q] by t_span[q] with
- * its own grid, eps and step count.  With two or three steps per pass set
+ * its own grid, eps and step count.  With two or more steps per pass set
  * (bgk_set_step_fusion), every instance takes its first step alone and then
- * two steps per pass (one step where one is left): the instances with even
- * nv[2] and 16-byte aligned f_in[q], f_out[q] on paired lanes, the others on
- * unpaired lanes.  With one step per pass set, one step per launch.  The
- * results equal one step per launch to rounding.  [host] probs[n], f_in[n], f_out[n]
- * (arrays of [device] pointers), t_span[n], n_steps_out[n] (nullable).  ws:
- * at least bgk_workspace_bytes_batched(probs, n). */
+ * two steps per pass (one step where one is left) on paired lanes: those
+ * with even nv[2] in place (f_in[q], f_out[q] 16-byte aligned, else on
+ * unpaired lanes), those with odd nv[2] on a copy in the workspace whose z
+ * rows carry one extra point above the box with a zero Maxwellian factor
+ * (f stays zero there; f_out[q] receives the live points only).  With one
+ * step per pass set, one step per launch.  The results equal one step per
+ * launch to rounding.  [host] probs[n], f_in[n], f_out[n] (arrays of
+ * [device] pointers), t_span[n], n_steps_out[n] (nullable).  ws: at least
+ * bgk_workspace_bytes_batched(probs, n) (two padded fields per instance with
+ * odd nv[2], one field per other instance, and per-cell scratch). */
 size_t bgk_workspace_bytes_batched(const bgk_problem* probs, int32_t n);
 int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
                           const double* const* f_in, double* const* f_out,

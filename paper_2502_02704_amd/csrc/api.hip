@@ -501,6 +501,7 @@ static Inst make_inst(const bgk_problem& p, int B, double dt, Tiles t, int ns = 
   if (ns == 15 && t.pair && ((long long)p.nv[1] * p.nv[2]) % (kWave * t.elems) == 0)
     I.crec = kWave * t.elems;
   I.order = 1;
+  I.nvz_live = p.nv[2];
   I.nparts = I.ntiles;  // one partial record per wave tile
   I.nchunks = (p.nx + t.chunk - 1) / t.chunk;
   I.items = (long long)B * I.ntg * I.nchunks;
@@ -1797,6 +1798,22 @@ int bgk_density_adjoint(const bgk_problem* prob, const double* rhobar, double* f
 }
 
 // -------------------------------------------------- uneven batches (C ABI) --
+// A grid with odd nv_z has no 16-byte pairs of z neighbours, and its x rows
+// alternate in alignment.  The fused passes run it on a padded copy instead:
+// each z row gains one point above the box (same spacing) whose Maxwellian
+// factor is zero, so f stays exactly zero there and every sum is unchanged;
+// its fields live in two workspace buffers, filled from f_in with the pad
+// points cleared and written back to f_out without them by the final
+// relaxation.
+static bool batched_padded(const bgk_problem& p) { return p.nv[2] % 2 != 0; }
+
+static bgk_problem padded_problem(const bgk_problem& p) {
+  bgk_problem q = p;
+  q.nv[2] += 1;
+  q.v_hi[2] = p.v_hi[2] + dv_of(p, 2);
+  return q;
+}
+
 struct BatchedLayout {
   size_t header, insts;
   std::vector<FineRegions> regions;
@@ -1808,7 +1825,9 @@ static BatchedLayout batched_layout(const bgk_problem* probs, int n) {
   BatchedLayout L;
   L.header = c.take(sizeof(WsHeader));
   L.insts = c.take(sizeof(Inst) * (size_t)n);
-  for (int q = 0; q < n; ++q) L.regions.push_back(carve_fine(c, probs[q], 1, 1));
+  for (int q = 0; q < n; ++q)
+    L.regions.push_back(batched_padded(probs[q]) ? carve_fine(c, padded_problem(probs[q]), 1, 2)
+                                                 : carve_fine(c, probs[q], 1, 1));
   L.total = c.off;
   return L;
 }
@@ -1847,9 +1866,10 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   // Tile shape: 4 velocities per lane over 8-cell chunks (or the override).
   // With two or more steps per pass set, every instance runs fused two-step
   // passes: first the instances whose rows can be read in 16-byte pairs
-  // (nvz even, aligned f_in and f_out), then the others on unpaired lanes,
-  // each group with its own tile mapping.  Without fusion all instances take
-  // one step per launch (paired lanes only if every instance allows them).
+  // (nvz even with aligned f_in and f_out, or nvz odd on the padded copy),
+  // then the others (even nvz, unaligned f) on unpaired lanes, each group
+  // with its own tile mapping.  Without fusion all instances take one step
+  // per launch (paired lanes only if every instance allows them).
   // Within a group the instances are sorted by step count (descending), so
   // that its active instances at any step form a prefix.
   // Built-in shapes, measured on the 29-instance seeded batch: paired lanes
@@ -1865,11 +1885,16 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
     }
     if (g_override.pair == 0) t.pair = 0;
   }
-  std::vector<char> pairable(n);
-  for (int q = 0; q < n; ++q)
-    pairable[q] = t.pair == 1 && probs[q].nv[2] % 2 == 0 &&
-                  aligned_tiles(t, probs[q], {f_in[q], f_out[q]}).pair == 1;
   const bool fused = fuse_mode() >= 2;
+  std::vector<char> pairable(n), padded(n);
+  for (int q = 0; q < n; ++q) {
+    padded[q] = fused && t.pair == 1 && batched_padded(probs[q]);
+    pairable[q] = t.pair == 1 && (padded[q] || (probs[q].nv[2] % 2 == 0 &&
+                                  aligned_tiles(t, probs[q], {f_in[q], f_out[q]}).pair == 1));
+  }
+  // the grid each instance's kernels run on
+  std::vector<bgk_problem> grid(n);
+  for (int q = 0; q < n; ++q) grid[q] = padded[q] ? padded_problem(probs[q]) : probs[q];
   auto first_group = [&](int q) { return fused && pairable[q]; };
   std::vector<int> order(n);
   for (int q = 0; q < n; ++q) order[q] = q;
@@ -1888,7 +1913,7 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
     Tiles& tt = grp ? tB : tA;
     long long nvs_m = 0;
     for (int k = grp ? nA : 0; k < (grp ? n : nA); ++k) {
-      const bgk_problem& pq = probs[order[k]];
+      const bgk_problem& pq = grid[order[k]];
       nvs_m = std::max(nvs_m, (long long)pq.nv[0] + pq.nv[1] + pq.nv[2]);
     }
     while (tt.chunk > 1 && (fused ? 2LL * tt.chunk + 6 : tt.chunk + 2LL) * nvs_m * 8 > kLdsBytes)
@@ -1901,9 +1926,18 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   for (int k = 0; k < n; ++k) {
     const int q = order[k];
     // fused passes need the nu-weighted partial sums (15 per record)
-    Inst I = make_inst(probs[q], 1, dts[q], k < nA ? tA : tB, fused ? 15 : 5);
-    attach_fine(I, ws, L.regions[q], f_out[q]);
-    I.fin = f_in[q];
+    Inst I = make_inst(grid[q], 1, dts[q], k < nA ? tA : tB, fused ? 15 : 5);
+    if (padded[q]) {
+      // the real grid's spacing and live z points; f_in is copied into buf[1]
+      I.dv[2] = dv_of(probs[q], 2);
+      I.dv3 = I.dv[0] * I.dv[1] * I.dv[2];
+      I.nvz_live = probs[q].nv[2];
+      attach_fine(I, ws, L.regions[q], nullptr);
+      I.fin = I.buf[1];
+    } else {
+      attach_fine(I, ws, L.regions[q], f_out[q]);
+      I.fin = f_in[q];
+    }
     I.fout = f_out[q];
     I.steps = steps[q];
     I.item_begin = items;
@@ -1916,9 +1950,11 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   }
   Inst* dI = at<Inst>(ws, L.insts);
   int* st = &at<WsHeader>(ws, 0)->status;
+  // phase-space cells of entries [a, b) on their own grids (pad points not
+  // counted)
   auto cells_of = [&](int a, int b) {
     double c = 0.0;
-    for (int k = a; k < b; ++k) c += (double)h[k].nx * h[k].nv3;
+    for (int k = a; k < b; ++k) c += (double)h[k].nx * nv3_of(probs[order[k]]);
     return c;
   };
   // Entries [a0, a1) one step per launch over the instances still stepping
@@ -2024,6 +2060,11 @@ int bgk_fine_step_batched(const bgk_problem* probs, int32_t n,
   auto sequence = [&](hipStream_t q) -> int {
     int r;
     if ((r = put_insts(dI, h.data(), n, q))) return r;
+    for (int k = 0; k < n; ++k)
+      if (padded[order[k]] &&
+          (r = launch_pad_rows(f_in[order[k]], h[k].buf[1],
+                               (long long)h[k].nx * h[k].nvx * h[k].nvy, h[k].nvz_live, q)))
+        return r;
     if (!fused) return single_steps(0, n, tB, nvs_b, q);
     if ((r = fused_steps(0, nA, tA, nvs_a, q))) return r;
     return fused_steps(nA, n, tB, nvs_b, q);

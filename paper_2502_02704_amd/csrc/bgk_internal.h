@@ -63,7 +63,9 @@ struct Inst {
   double emax;                 // Rusanov coefficient of the v_x flux (>= max |E_i|)
   double rv;                   // dt / dv_x
   int order;                   // x transport: 1 upwind, 2 van Leer limited
-  int pad2_;
+  int nvz_live;                // v_z points that carry f: nvz, or nvz - 1 where
+                               // each z row ends in one pad point whose
+                               // Maxwellian factor is zero (f stays 0 there)
 };
 
 // Step-kernel source modes.
@@ -262,9 +264,13 @@ int launch_parareal_sweep(const bgk_problem& p, int n_slices, int k,
                           const double* E = nullptr, bool viscous = false);
 int launch_prim_to_cons(const double* W, double* V, int n, hipStream_t s);
 
-// f_out = a g + F from buf[src_sel], or f_out = F (pure lift) if src_sel < 0.
+// f_out = a g + F from buf[src_sel], or f_out = F (pure lift) if src_sel < 0;
+// with pad points (nvz_live < nvz) f_out holds only the live points.
 int launch_relax_out_blocks(const Inst* d_insts, int n_inst, long long blocks,
                             int nvs_max, int src_sel, hipStream_t s);
+// dst[rows][nz_live + 1] = src[rows][nz_live] with a zero pad point per row.
+int launch_pad_rows(const double* src, double* dst, long long rows, int nz_live,
+                    hipStream_t s);
 
 // Adjoint kernels (single instance, nbatch = 1).  g is read from
 // buf[g_sel]; factors in fac are the unscaled Maxwellian of U(g).

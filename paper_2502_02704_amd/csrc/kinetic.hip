@@ -1969,6 +1969,7 @@ __device__ __forceinline__ void write_factors(const Inst& I, double* row,
     int j = k - (ax == 0 ? 0 : (ax == 1 ? I.nvx : I.nvx + I.nvy));
     double d = vgrid(I, ax, j) - u[ax];
     double e = exp(-d * d * inv2t);
+    if (ax == 2 && j >= I.nvz_live) e = 0.0;  // pad points of the z rows
     row[k] = ax == 0 ? C * e : e;
   }
 }
@@ -1998,7 +1999,7 @@ __device__ __forceinline__ void maxwell_weighted_sums(const Inst& I, int lane,
     int j = kk - (ax == 0 ? 0 : (ax == 1 ? I.nvx : I.nvx + I.nvy));
     const double v = vgrid(I, ax, j);
     const double d = v - u[ax];
-    const double ex = exp(-d * d * inv2t);
+    const double ex = (ax == 2 && j >= I.nvz_live) ? 0.0 : exp(-d * d * inv2t);
     if (row != nullptr) row[kk] = ax == 0 ? Cx * ex : ex;
     const double e1 = v * ex, e2 = v * v * ex;
     if (ax == 0) {
@@ -2510,8 +2511,12 @@ __global__ __launch_bounds__(kBlock) void k_relax_out(
   for (int k = threadIdx.x; k < I.nvs; k += kBlock) lds[k] = frow[k];
   __syncthreads();
   const int nyz = I.nvy * I.nvz;
+  // rows with pad points: the output holds only the live ones (nvz_live per
+  // z row, nvx nvy nvz_live per x cell)
+  const int nzl = I.nvz_live;
+  const long long out_nv3 = (long long)I.nvx * I.nvy * nzl;
   gptr<const double> g = src_sel >= 0 ? gmem(I.buf[src_sel]) + cl * I.nv3 : nullptr;
-  gptr<double> out = gmem(I.fout) + cl * I.nv3;
+  gptr<double> out = gmem(I.fout) + cl * out_nv3;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     int j = slab * 4 * kBlock + e * kBlock + threadIdx.x;
@@ -2520,10 +2525,27 @@ __global__ __launch_bounds__(kBlock) void k_relax_out(
     int rem = j - jx * nyz;
     int jy = rem / I.nvz;
     int jz = rem - jy * I.nvz;
+    if (jz >= nzl) continue;
     double F = lds[jx] * lds[I.nvx + jy] * lds[I.nvx + I.nvy + jz];
-    out[j] = g ? fma(I.a, g[j], F) : F;
+    const int jo = nzl == I.nvz ? j : (jx * I.nvy + jy) * nzl + jz;
+    out[jo] = g ? fma(I.a, g[j], F) : F;
   }
   (void)total_cells;
+}
+
+// Rows of f with nz_live values per z row copied into rows of nz_live + 1
+// values, the pad point set to zero: cells x cells, nxy = nvx nvy z rows each.
+__global__ __launch_bounds__(kBlock) void k_pad_rows(const double* __restrict__ src,
+                                                     double* __restrict__ dst,
+                                                     long long rows, int nz_live) {
+  const int nz = nz_live + 1;
+  const long long n = rows * nz;
+  for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < n;
+       t += (long long)gridDim.x * kBlock) {
+    const long long row = t / nz;
+    const int jz = (int)(t - row * nz);
+    dst[t] = jz < nz_live ? src[row * nz_live + jz] : 0.0;
+  }
 }
 
 // ------------------------------------------------------------- launchers --
@@ -2810,6 +2832,17 @@ int launch_relax_out_blocks(const Inst* d_insts, int n_inst, long long blocks,
   hipLaunchKernelGGL(k_relax_out, dim3((unsigned)blocks), dim3(kBlock),
                      (size_t)nvs_max * sizeof(double), s, d_insts, n_inst,
                      (long long)0, src_sel);
+  BGK_HIP(hipGetLastError());
+  return BGK_OK;
+}
+
+int launch_pad_rows(const double* src, double* dst, long long rows, int nz_live,
+                    hipStream_t s) {
+  if (rows <= 0) return BGK_OK;
+  const long long n = rows * (nz_live + 1);
+  const long long blocks = std::min<long long>((n + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)blocks), dim3(kBlock), 0, s, src, dst, rows,
+                     nz_live);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }

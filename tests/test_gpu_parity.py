@@ -322,9 +322,13 @@ def test_fine_step_batched_uneven_two_step_passes():
     pass over the instances with two or more steps left and one step for
     those with one left.  Step counts 1, 2, 3, 4 and 7 (odd and even), both
     boundary conditions, one grid whose v_x planes are whole tiles (compact
-    records); two instances with odd nvz (no paired rows) run the same
-    schedule on unpaired lanes in the same call.  Against the oracle, and
-    against one step per pass."""
+    records); the two instances with odd nvz run the same schedule on padded
+    copies (one zero point appended to each z row), and one instance with
+    even nvz whose f_in and f_out sit 8 bytes off 16-byte alignment runs on
+    unpaired lanes, in the same call.  Against the oracle, and against one
+    step per pass; the outputs are written in place, with sentinels after
+    each one left untouched (the padded copies are written back without
+    their pad points)."""
     probs = [
         wl.Problem(nx=9, nv=(6, 4, 8), v_lo=(-5,) * 3, v_hi=(5,) * 3, bc=wl.BC_NEUMANN,
                    eps=1e-2),
@@ -351,15 +355,27 @@ def test_fine_step_batched_uneven_two_step_passes():
         spans.append(span)
         fs.append(cuda(f))
         refs.append(oracle.fine_step(p, f, span))
+    # instance 2 (nvz = 6): f_in and f_out one double past 16-byte alignment
+    shift = torch.empty(fs[2].numel() + 1, dtype=torch.float64, device="cuda")
+    shift[1:].copy_(fs[2].reshape(-1))
+    fs[2] = shift[1:].view(fs[2].shape)
+    assert fs[2].data_ptr() % 16 == 8
+    sentinel = 4
     for fuse in (2, 3):
         bgk.set_step_fusion(fuse)
-        outs, steps = bgk.fine_step_batched(probs, fs, spans)
+        slabs = [torch.full((f.numel() + 1 + sentinel,), float("nan"), dtype=torch.float64,
+                            device="cuda") for f in fs]
+        outs = [sl[1:1 + f.numel()].view(f.shape) if q == 2 else sl[:f.numel()].view(f.shape)
+                for q, (sl, f) in enumerate(zip(slabs, fs))]
+        _, steps = bgk.fine_step_batched(probs, fs, spans, outs)
         bgk.check_status()
         assert steps == want
         for q in range(len(probs)):
             ref, nr = refs[q]
             assert nr == want[q]
             assert rel_f(outs[q].cpu().numpy(), ref) < TOL, q
+            tail = slabs[q][-sentinel:].cpu().numpy()
+            assert np.isnan(tail).all(), q
         bgk.set_step_fusion(1)
         single, _ = bgk.fine_step_batched(probs, fs, spans)
         bgk.check_status()
@@ -698,11 +714,11 @@ def test_adjoint_graph_replays_match_eager():
 
 
 def test_uneven_batch_bench_configuration_sampled():
-    """The uneven batch as the bench times it: the 29 resolved seeded
-    instances (cold instances 7, 15 and 29 left out) over a span of 0.01
-    (26 to 150 steps each), two-step passes on paired lanes (even nv_z) and
-    unpaired lanes (odd nv_z) in one call; the two cheapest instances of
-    each kind against the oracle."""
+    """The uneven batch as the bench launches it: the 29 resolved seeded
+    instances (cold instances 7, 15 and 29 left out) in one call, two-step
+    passes on paired lanes, in place for even nv_z and on padded copies for
+    odd nv_z, over a tenth of the bench's span (26 to 150 steps each); the
+    two cheapest instances of each kind against the oracle."""
     keep = [q for q in range(32) if q not in (7, 15, 29)]
     all_insts = wl.c5_uneven()
     insts = [all_insts[q] for q in keep]
@@ -713,7 +729,7 @@ def test_uneven_batch_bench_configuration_sampled():
     outs, steps = bgk.fine_step_batched(probs, fs, [span] * len(insts))
     bgk.check_status()
     assert min(steps) >= 26 and max(steps) <= 150
-    for q in (21, 30, 2, 24):   # nv_z 18, 28 (paired lanes); 27, 31 (unpaired)
+    for q in (21, 30, 2, 24):   # nv_z 18, 28 (in place); 27, 31 (padded copies)
         w = all_insts[q]
         k = keep.index(q)
         ref, nr = oracle.fine_step(w.problem, oracle.lift(w.problem, w.W0), span)
