@@ -106,10 +106,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_sums(
   }
 }
 
-// one wave per x cell
+// one wave per x cell; the cell's log-eps term is stored, or added to the
+// terms of the steps already taken (accumulate), and summed over cells once
 __global__ __launch_bounds__(kBlock) void k_adj_reduce(
     const Inst* __restrict__ inst, const double* __restrict__ part6, int ntiles,
-    double* coef, double* dle_cells) {
+    double* coef, double* dle_cells, int accumulate) {
   const Inst& I = *inst;
   const int cell = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (cell >= I.nx) return;
@@ -144,7 +145,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(
   for (int a = 0; a < 3; ++a)
     cf[1 + a] = I.dv3 * (ubar[a] / rho - 2.0 * thbar * u[a] / (3.0 * rho));
   cf[4] = I.dv3 * 0.5 * Etil;
-  dle_cells[cell] = -al * I.a * s[5];
+  const double dle = -al * I.a * s[5];
+  dle_cells[cell] = accumulate ? dle_cells[cell] + dle : dle;
 }
 
 // fbar_prev = T^t gbar; work item = (x chunk, tile group); rows of gbar are
@@ -273,11 +275,12 @@ int launch_adjoint_sums(const Inst* d_inst, const Inst& h, int g_sel,
 }
 
 int launch_adjoint_reduce(const Inst* d_inst, const Inst& h, const double* part6,
-                          double* coef, double* dle_cells, hipStream_t s) {
+                          double* coef, double* dle_cells, bool accumulate, hipStream_t s) {
   const int nt = adj_ntiles(h);
   hipLaunchKernelGGL(k_adj_reduce,
                      dim3((unsigned)((h.nx + kWavesPerBlock - 1) / kWavesPerBlock)),
-                     dim3(kBlock), 0, s, d_inst, part6, nt, coef, dle_cells);
+                     dim3(kBlock), 0, s, d_inst, part6, nt, coef, dle_cells,
+                     accumulate ? 1 : 0);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
 }

@@ -347,7 +347,9 @@ static Layout layout_of(const bgk_problem& p, int op, int batch) {
   Carve c;
   Layout L;
   L.header = c.take(sizeof(WsHeader));
-  L.insts = c.take(sizeof(Inst) * 4);
+  // descriptor table: 4 entries; the adjoint keeps one per step of a
+  // checkpoint segment for the recomputation and one for the backward step
+  L.insts = c.take(sizeof(Inst) * (op == BGK_OP_ADJOINT ? std::max(4, 2 * batch) : 4));
   const size_t f1 = (size_t)p.nx * nv3_of(p) * sizeof(double);
   const size_t sl = (size_t)p.nx * 5 * sizeof(double);
   switch (op) {
@@ -1711,8 +1713,20 @@ int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
   double* dle = at<double>(ws, L.dle);
   Inst* dI = at<Inst>(ws, L.insts);
   const int n_seg = (n_steps + ckpt_every - 1) / ckpt_every;
+  // descriptors by position j in a segment: the recomputation of state j
+  // from state j - 1 (entry j), the backward step from state j (entry
+  // ckpt_every + j); the same for every segment, uploaded once
+  std::vector<Inst> tab(2 * (size_t)ckpt_every, base);
+  for (int j = 0; j < ckpt_every; ++j) {
+    if (j > 0) {
+      tab[j].fin = states + (size_t)(j - 1) * nf;
+      tab[j].fout = states + (size_t)j * nf;
+    }
+    tab[ckpt_every + j].fin = states + (size_t)j * nf;
+  }
   auto sequence = [&](hipStream_t q) -> int {
     int r;
+    if ((r = put_insts(dI, tab.data(), 2 * ckpt_every, q))) return r;
     BGK_HIP(hipMemcpyAsync(fb[0], fbar_T, fbytes, hipMemcpyDeviceToDevice, q));
     int cur = 0;
     for (int c = n_seg - 1; c >= 0; --c) {
@@ -1722,29 +1736,29 @@ int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
                              hipMemcpyDeviceToDevice, q));
       // forward states s0+1 .. s1-1 of the segment (transport, moments, relax)
       for (int k = s0 + 1; k < s1; ++k) {
-        Inst I = base;
-        I.fin = states + (size_t)(k - 1 - s0) * nf;
-        I.fout = states + (size_t)(k - s0) * nf;
-        if ((r = put_insts(dI, &I, 1, q))) return r;
-        if ((r = launch_step(dI, 1, I.items, kCopy, 1, t, lds_doubles(I, t), st, q))) return r;
-        if ((r = launch_reduce(dI, 1, prob->nx, kRedRelaxFactors, 0, st, q))) return r;
-        if ((r = launch_relax_out_blocks(dI, 1, relax_out_blocks(I), I.nvs, 0, q))) return r;
+        const Inst* d = dI + (k - s0);
+        if ((r = launch_step(d, 1, base.items, kCopy, 1, t, lds_doubles(base, t), st, q)))
+          return r;
+        if ((r = launch_reduce(d, 1, prob->nx, kRedRelaxFactors, 0, st, q))) return r;
+        if ((r = launch_relax_out_blocks(d, 1, relax_out_blocks(base), base.nvs, 0, q)))
+          return r;
       }
       for (int k = s1 - 1; k >= s0; --k) {
-        Inst I = base;
-        I.fin = states + (size_t)(k - s0) * nf;
-        if ((r = put_insts(dI, &I, 1, q))) return r;
+        const Inst* d = dI + ckpt_every + (k - s0);
         // g = T f^k into buf[0], moments and the unscaled Maxwellian of U(g)
-        if ((r = launch_step(dI, 1, I.items, kCopy, 1, t, lds_doubles(I, t), st, q))) return r;
-        if ((r = launch_reduce(dI, 1, prob->nx, kRedMaxwellFactors, 0, st, q))) return r;
-        if ((r = launch_adjoint_sums(dI, I, 0, fb[cur], part6, q))) return r;
-        if ((r = launch_adjoint_reduce(dI, I, part6, coef, dle, q))) return r;
-        if ((r = launch_sum_into(dle, prob->nx, dlog_eps, q))) return r;
-        if ((r = launch_adjoint_transpose(dI, I, t.chunk, fb[cur], coef, fb[cur ^ 1], q)))
+        if ((r = launch_step(d, 1, base.items, kCopy, 1, t, lds_doubles(base, t), st, q)))
+          return r;
+        if ((r = launch_reduce(d, 1, prob->nx, kRedMaxwellFactors, 0, st, q))) return r;
+        if ((r = launch_adjoint_sums(d, base, 0, fb[cur], part6, q))) return r;
+        // per-cell log-eps terms summed over the steps, then over the cells
+        if ((r = launch_adjoint_reduce(d, base, part6, coef, dle, k != (int)n_steps - 1, q)))
+          return r;
+        if ((r = launch_adjoint_transpose(d, base, t.chunk, fb[cur], coef, fb[cur ^ 1], q)))
           return r;
         cur ^= 1;
       }
     }
+    if (n_steps > 0 && (r = launch_sum_into(dle, prob->nx, dlog_eps, q))) return r;
     BGK_HIP(hipMemcpyAsync(fbar_0, fb[cur], fbytes, hipMemcpyDeviceToDevice, q));
     return BGK_OK;
   };

@@ -278,7 +278,7 @@ int launch_adjoint_sums(const Inst* d_inst, const Inst& h_inst, int g_sel,
                         const double* fbar_next, double* part6, hipStream_t s);
 int launch_adjoint_reduce(const Inst* d_inst, const Inst& h_inst,
                           const double* part6, double* coef,
-                          double* dle_cells, hipStream_t s);
+                          double* dle_cells, bool accumulate, hipStream_t s);
 int launch_adjoint_transpose(const Inst* d_inst, const Inst& h_inst, int chunk,
                              const double* fbar_next, const double* coef,
                              double* fbar_prev, hipStream_t s);
