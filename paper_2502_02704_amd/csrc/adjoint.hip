@@ -66,6 +66,13 @@ __device__ __forceinline__ El el_of(const Inst& I, int j) {
   return r;
 }
 
+// x row read for row i (ghost rows: periodic wrap, or the boundary row)
+__device__ __forceinline__ int ghost_row_a(int i, int nx, int bc) {
+  if (i < 0) return bc == 1 ? i + nx : 0;
+  if (i >= nx) return bc == 1 ? i - nx : nx - 1;
+  return i;
+}
+
 // grid: nx * ceil(ntiles4 / 4) blocks; block = (cell, tile group)
 __global__ __launch_bounds__(kBlock) void k_adj_sums(
     const Inst* __restrict__ inst, int g_sel, const double* __restrict__ fbar,
@@ -106,8 +113,34 @@ __global__ __launch_bounds__(kBlock) void k_adj_sums(
   }
 }
 
-// one wave per x cell; the cell's log-eps term is stored, or added to the
-// terms of the steps already taken (accumulate), and summed over cells once
+// The cell's coefficients of gbar (rhotil, mtil, Etil/2, times dv^3) and its
+// log-eps term from the sums s = (fbar M, fbar M v, fbar M |v|^2, fbar (M - g))
+// and the moments of g; the log-eps term is stored, or added to the terms of
+// the steps already taken (accumulate).
+__device__ __forceinline__ void adj_coefficients(const Inst& I, double rho, const double u[3],
+                                                 double usq, double th, const double* s,
+                                                 double* cf, double* dle, int accumulate) {
+  const double al = I.al;
+  // sums of w M = al fbar M and its velocity moments
+  const double S0 = s[0], S1[3] = {s[1], s[2], s[3]}, S2 = s[4];
+  const double uS1 = u[0] * S1[0] + u[1] * S1[1] + u[2] * S1[2];
+  const double rhobar = al * S0 / rho;
+  double ubar[3];
+  for (int a = 0; a < 3; ++a) ubar[a] = al * (S1[a] - u[a] * S0) / th;
+  const double c2 = S2 - 2.0 * uS1 + usq * S0;  // sum fbar M |v-u|^2
+  const double thbar = al * (c2 / (2.0 * th * th) - 1.5 * S0 / th);
+  const double ubu = ubar[0] * u[0] + ubar[1] * u[1] + ubar[2] * u[2];
+  const double Etil = 2.0 * thbar / (3.0 * rho);
+  const double rtil = rhobar - ubu / rho + thbar * (usq - 3.0 * th) / (3.0 * rho);
+  cf[0] = I.dv3 * rtil;
+  for (int a = 0; a < 3; ++a)
+    cf[1 + a] = I.dv3 * (ubar[a] / rho - 2.0 * thbar * u[a] / (3.0 * rho));
+  cf[4] = I.dv3 * 0.5 * Etil;
+  const double d = -al * I.a * s[5];
+  *dle = accumulate ? *dle + d : d;
+}
+
+// one wave per x cell
 __global__ __launch_bounds__(kBlock) void k_adj_reduce(
     const Inst* __restrict__ inst, const double* __restrict__ part6, int ntiles,
     double* coef, double* dle_cells, int accumulate) {
@@ -128,25 +161,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(
   const double u[3] = {vg[1] / rho, vg[2] / rho, vg[3] / rho};
   const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const double th = (2.0 * vg[4] / rho - usq) / 3.0;
-  const double al = I.al;
-  // sums of w M = al fbar M and its velocity moments
-  const double S0 = s[0], S1[3] = {s[1], s[2], s[3]}, S2 = s[4];
-  const double uS1 = u[0] * S1[0] + u[1] * S1[1] + u[2] * S1[2];
-  const double rhobar = al * S0 / rho;
-  double ubar[3];
-  for (int a = 0; a < 3; ++a) ubar[a] = al * (S1[a] - u[a] * S0) / th;
-  const double c2 = S2 - 2.0 * uS1 + usq * S0;  // sum fbar M |v-u|^2
-  const double thbar = al * (c2 / (2.0 * th * th) - 1.5 * S0 / th);
-  const double ubu = ubar[0] * u[0] + ubar[1] * u[1] + ubar[2] * u[2];
-  const double Etil = 2.0 * thbar / (3.0 * rho);
-  const double rtil = rhobar - ubu / rho + thbar * (usq - 3.0 * th) / (3.0 * rho);
-  double* cf = coef + (long long)cell * 5;
-  cf[0] = I.dv3 * rtil;
-  for (int a = 0; a < 3; ++a)
-    cf[1 + a] = I.dv3 * (ubar[a] / rho - 2.0 * thbar * u[a] / (3.0 * rho));
-  cf[4] = I.dv3 * 0.5 * Etil;
-  const double dle = -al * I.a * s[5];
-  dle_cells[cell] = accumulate ? dle_cells[cell] + dle : dle;
+  adj_coefficients(I, rho, u, usq, th, s, coef + (long long)cell * 5, dle_cells + cell,
+                   accumulate);
 }
 
 // fbar_prev = T^t gbar; work item = (x chunk, tile group); rows of gbar are
@@ -259,6 +275,166 @@ __global__ __launch_bounds__(kBlock) void k_lift_adj_rho(
   if (threadIdx.x == 0) rhobar[cell] = red[0] / W[(long long)cell * 5];
 }
 
+// ------------------------------------------------ whole-cell adjoint step --
+// One block per x cell holding all of the cell's velocities (EPT per thread),
+// so the per-cell sums are block reductions inside the kernel.  The
+// recomputation of a state (FWD) is then one launch: g = T f^k at the cell,
+// its moments, the Maxwellian factors al M[U(g)] and f^{k+1} = a g + al M.
+// The backward step (BWD) is one launch up to the transposed stencil: g and
+// its moments, the unscaled factors of M[U(g)], the sums of fbar M {1, v,
+// |v|^2} and of fbar (M - g), and from them the cell's coefficients of gbar
+// and its log-eps term.
+constexpr int kCellBlock = 512;
+constexpr int kCellWaves = kCellBlock / kWave;
+
+// Sum over the block of N values per thread (deterministic order: DPP within
+// waves, then the waves in order); every thread receives the sums.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+  for (int c = 0; c < N; ++c) v[c] = wsum_last(v[c]);
+  if (lane == kWave - 1)
+#pragma unroll
+    for (int c = 0; c < N; ++c) red[wave * N + c] = v[c];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    double t = 0.0;
+    for (int w = 0; w < kCellWaves; ++w) t += red[w * N + c];
+    v[c] = t;
+  }
+  __syncthreads();
+}
+
+template <int EPT, bool BWD>
+__global__ __launch_bounds__(kCellBlock) void k_adj_cell(
+    const Inst* __restrict__ inst, const double* __restrict__ f, double* __restrict__ fnext,
+    const double* __restrict__ fbar, double* coef, double* dle_cells, int accumulate,
+    int* status) {
+  // factor row [nvs], the reduction scratch, and the cell's g [nv3]
+  extern __shared__ double lds[];
+  double* red = lds + inst->nvs;
+  double* gl = red + kCellWaves * 6;
+  const Inst& I = *inst;
+  // neighbouring cells on one XCD: the rows i-1 and i+1 a block reads are
+  // its neighbours' own rows, in the same L2
+  const int nx = I.nx, nv3 = I.nv3;
+  const int i = (int)xcd_item(blockIdx.x, (unsigned)nx);
+  const double* fc = f + (long long)i * nv3;
+  const double* fm = f + (long long)ghost_row_a(i - 1, nx, I.bc) * nv3;
+  const double* fp = f + (long long)ghost_row_a(i + 1, nx, I.bc) * nv3;
+  // element j = threadIdx.x + k kCellBlock: its (jx, jy, jz) advance by the
+  // digits of kCellBlock in the (nvx, nvy, nvz) radix, with carries
+  const El el0 = el_of(I, threadIdx.x);
+  const int sz = kCellBlock % I.nvz, sy = (kCellBlock / I.nvz) % I.nvy,
+            sx = kCellBlock / (I.nvz * I.nvy);
+  auto advance = [&](El& el) {
+    el.jz += sz;
+    if (el.jz >= I.nvz) { el.jz -= I.nvz; ++el.jy; }
+    el.jy += sy;
+    if (el.jy >= I.nvy) { el.jy -= I.nvy; ++el.jx; }
+    el.jx += sx;
+  };
+  // loads in batches of KB elements issued together (indices past the cell
+  // clamped to its last element, their values unused)
+  constexpr int KB = EPT < 8 ? EPT : 8;
+  double s[5] = {0, 0, 0, 0, 0};
+  // batches run as a loop (not unrolled), so no per-element value stays live
+  // from one phase into the next
+  El el = el0;
+#pragma unroll 1
+  for (int k0 = 0; k0 < EPT; k0 += KB) {
+    double c[KB], up[KB];
+    El e2 = el;
+#pragma unroll
+    for (int k = k0; k < k0 + KB; ++k) {
+      if (k > k0) advance(e2);
+      const int j = min((int)threadIdx.x + k * kCellBlock, nv3 - 1);
+      c[k - k0] = fc[j];
+      up[k - k0] = (vg_at(I, 0, e2.jx) > 0.0 ? fm : fp)[j];
+    }
+#pragma unroll
+    for (int k = k0; k < k0 + KB; ++k) {
+      if (k > k0) advance(el);
+      const bool live = (int)threadIdx.x + k * kCellBlock < nv3;
+      const double vx = vg_at(I, 0, el.jx), vy = vg_at(I, 1, el.jy), vz = vg_at(I, 2, el.jz);
+      const double nu = vx * I.r;
+      const double cc = c[k - k0];
+      const double g = live ? fma(fabs(nu), up[k - k0] - cc, cc) : 0.0;
+      if (live) gl[threadIdx.x + k * kCellBlock] = g;
+      s[0] += g;
+      s[1] += g * vx;
+      s[2] += g * vy;
+      s[3] += g * vz;
+      s[4] += g * (vx * vx + vy * vy + vz * vz);
+    }
+    // el: element k0 + KB - 1; the next batch starts one element on
+    if (k0 + KB < EPT) advance(el);
+    __builtin_amdgcn_sched_barrier(0);  // batches stay apart (register pressure)
+  }
+  block_sum<5>(s, red);
+  const double rho = s[0] * I.dv3;
+  const double mom[3] = {s[1] * I.dv3, s[2] * I.dv3, s[3] * I.dv3};
+  const double En = 0.5 * s[4] * I.dv3;
+  const double u[3] = {mom[0] / rho, mom[1] / rho, mom[2] / rho};
+  const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const double th = (2.0 * En / rho - usq) / 3.0;
+  if (threadIdx.x == 0 && !(rho > 0.0 && th > 0.0 && isfinite(rho) && isfinite(th)))
+    *status = 1;
+  const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
+  const double inv2t = 1.0 / (2.0 * th);
+  for (int k = threadIdx.x; k < I.nvs; k += kCellBlock) {
+    const int ax = k < I.nvx ? 0 : (k < I.nvx + I.nvy ? 1 : 2);
+    const int jj = k - (ax == 0 ? 0 : (ax == 1 ? I.nvx : I.nvx + I.nvy));
+    const double d = vg_at(I, ax, jj) - u[ax];
+    const double e = exp(-d * d * inv2t);
+    lds[k] = ax == 0 ? (BWD ? C0 : I.al * C0) * e : e;
+  }
+  __syncthreads();
+  if (!BWD) {
+    double* out = fnext + (long long)i * nv3;
+    el = el0;
+#pragma unroll 4
+    for (int k = 0; k < EPT; ++k) {
+      const int j = threadIdx.x + k * kCellBlock;
+      if (k > 0) advance(el);
+      if (j >= nv3) continue;
+      const double M = (lds[el.jx] * lds[I.nvx + el.jy]) * lds[I.nvx + I.nvy + el.jz];
+      out[j] = fma(I.a, gl[j], M);
+    }
+    return;
+  }
+  const double* fb = fbar + (long long)i * nv3;
+  double w[6] = {0, 0, 0, 0, 0, 0};
+  el = el0;
+#pragma unroll 1
+  for (int k0 = 0; k0 < EPT; k0 += KB) {
+    double fbv[KB];
+#pragma unroll
+    for (int k = k0; k < k0 + KB; ++k)
+      fbv[k - k0] = fb[min((int)threadIdx.x + k * kCellBlock, nv3 - 1)];
+#pragma unroll
+    for (int k = k0; k < k0 + KB; ++k) {
+      if (k > 0) advance(el);
+      if ((int)threadIdx.x + k * kCellBlock >= nv3) continue;
+      const double vx = vg_at(I, 0, el.jx), vy = vg_at(I, 1, el.jy), vz = vg_at(I, 2, el.jz);
+      const double M = (lds[el.jx] * lds[I.nvx + el.jy]) * lds[I.nvx + I.nvy + el.jz];
+      const double fmv = fbv[k - k0] * M;
+      w[0] += fmv;
+      w[1] += fmv * vx;
+      w[2] += fmv * vy;
+      w[3] += fmv * vz;
+      w[4] += fmv * (vx * vx + vy * vy + vz * vz);
+      w[5] += fbv[k - k0] * (M - gl[threadIdx.x + k * kCellBlock]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  block_sum<6>(w, red);
+  if (threadIdx.x != 0) return;
+  adj_coefficients(I, rho, u, usq, th, w, coef + (long long)i * 5, dle_cells + i, accumulate);
+}
+
 int adj_ntiles(const Inst& I) { return (I.nv3 + kWave * E - 1) / (kWave * E); }
 
 }  // namespace
@@ -295,6 +471,42 @@ int launch_adjoint_transpose(const Inst* d_inst, const Inst& h, int chunk,
                      fbar_prev);
   BGK_HIP(hipGetLastError());
   return BGK_OK;
+}
+
+int adj_cell_ept(const Inst& h) {
+  // the cell's g is kept in LDS next to the factor row
+  if (((long long)h.nv3 + h.nvs + kCellWaves * 6) * 8 > kLdsBytes) return 0;
+  for (int e = 1; e <= 32; e *= 2)
+    if ((long long)e * kCellBlock >= h.nv3) return e;
+  return 0;
+}
+
+int launch_adj_cell(const Inst* d_inst, const Inst& h, bool backward, const double* f,
+                    double* fnext, const double* fbar, double* coef, double* dle_cells,
+                    bool accumulate, int* status, hipStream_t s) {
+  const int ept = adj_cell_ept(h);
+  const size_t lds = ((size_t)h.nvs + (size_t)kCellWaves * 6 + (size_t)h.nv3) * sizeof(double);
+  const dim3 grid((unsigned)h.nx), block(kCellBlock);
+  const int acc = accumulate ? 1 : 0;
+#define BGK_ADJ_CELL(EE)                                                                  \
+  if (ept == EE) {                                                                        \
+    if (backward)                                                                         \
+      hipLaunchKernelGGL((k_adj_cell<EE, true>), grid, block, lds, s, d_inst, f, fnext, fbar, \
+                         coef, dle_cells, acc, status);                                   \
+    else                                                                                  \
+      hipLaunchKernelGGL((k_adj_cell<EE, false>), grid, block, lds, s, d_inst, f, fnext,  \
+                         fbar, coef, dle_cells, acc, status);                             \
+    BGK_HIP(hipGetLastError());                                                           \
+    return BGK_OK;                                                                        \
+  }
+  BGK_ADJ_CELL(1)
+  BGK_ADJ_CELL(2)
+  BGK_ADJ_CELL(4)
+  BGK_ADJ_CELL(8)
+  BGK_ADJ_CELL(16)
+  BGK_ADJ_CELL(32)
+#undef BGK_ADJ_CELL
+  return BGK_E_INVALID;
 }
 
 int launch_sum_into(const double* cells, int n, double* acc, hipStream_t s) {

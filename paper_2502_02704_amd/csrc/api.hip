@@ -1724,6 +1724,10 @@ int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
     }
     tab[ckpt_every + j].fin = states + (size_t)j * nf;
   }
+  // cells whose velocities fit one block take the whole-cell kernels (one
+  // launch per recomputed state, two per backward step); larger cells the
+  // tiled kernels with separate per-cell reductions
+  const bool whole_cell = adj_cell_ept(base) > 0;
   auto sequence = [&](hipStream_t q) -> int {
     int r;
     if ((r = put_insts(dI, tab.data(), 2 * ckpt_every, q))) return r;
@@ -1737,6 +1741,13 @@ int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
       // forward states s0+1 .. s1-1 of the segment (transport, moments, relax)
       for (int k = s0 + 1; k < s1; ++k) {
         const Inst* d = dI + (k - s0);
+        if (whole_cell) {
+          if ((r = launch_adj_cell(dI, base, false, states + (size_t)(k - 1 - s0) * nf,
+                                   states + (size_t)(k - s0) * nf, nullptr, nullptr, nullptr,
+                                   false, st, q)))
+            return r;
+          continue;
+        }
         if ((r = launch_step(d, 1, base.items, kCopy, 1, t, lds_doubles(base, t), st, q)))
           return r;
         if ((r = launch_reduce(d, 1, prob->nx, kRedRelaxFactors, 0, st, q))) return r;
@@ -1745,14 +1756,21 @@ int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
       }
       for (int k = s1 - 1; k >= s0; --k) {
         const Inst* d = dI + ckpt_every + (k - s0);
-        // g = T f^k into buf[0], moments and the unscaled Maxwellian of U(g)
-        if ((r = launch_step(d, 1, base.items, kCopy, 1, t, lds_doubles(base, t), st, q)))
-          return r;
-        if ((r = launch_reduce(d, 1, prob->nx, kRedMaxwellFactors, 0, st, q))) return r;
-        if ((r = launch_adjoint_sums(d, base, 0, fb[cur], part6, q))) return r;
         // per-cell log-eps terms summed over the steps, then over the cells
-        if ((r = launch_adjoint_reduce(d, base, part6, coef, dle, k != (int)n_steps - 1, q)))
-          return r;
+        const bool acc = k != (int)n_steps - 1;
+        if (whole_cell) {
+          // g = T f^k, its moments and Maxwellian, the sums and coefficients
+          if ((r = launch_adj_cell(dI, base, true, states + (size_t)(k - s0) * nf, nullptr,
+                                   fb[cur], coef, dle, acc, st, q)))
+            return r;
+        } else {
+          // g = T f^k into buf[0], moments and the unscaled Maxwellian of U(g)
+          if ((r = launch_step(d, 1, base.items, kCopy, 1, t, lds_doubles(base, t), st, q)))
+            return r;
+          if ((r = launch_reduce(d, 1, prob->nx, kRedMaxwellFactors, 0, st, q))) return r;
+          if ((r = launch_adjoint_sums(d, base, 0, fb[cur], part6, q))) return r;
+          if ((r = launch_adjoint_reduce(d, base, part6, coef, dle, acc, q))) return r;
+        }
         if ((r = launch_adjoint_transpose(d, base, t.chunk, fb[cur], coef, fb[cur ^ 1], q)))
           return r;
         cur ^= 1;
@@ -1762,8 +1780,8 @@ int bgk_fine_adjoint(const bgk_problem* prob, const double* f_ckpt,
     BGK_HIP(hipMemcpyAsync(fbar_0, fb[cur], fbytes, hipMemcpyDeviceToDevice, q));
     return BGK_OK;
   };
-  // the whole sequence (about 11 launches per step) is captured once per
-  // (workspace, problem, buffers, steps) and replayed
+  // the whole sequence is captured once per (workspace, problem, buffers,
+  // steps) and replayed
   return run_graph(graph_key("adj", ws, ws_bytes, *prob,
                              {(double)ckpt_every, (double)n_steps, dt, (double)t.elems,
                               (double)t.chunk, (double)(t.pair + 2 * t.vcol)},

@@ -68,6 +68,16 @@ struct Inst {
                                // Maxwellian factor is zero (f stays 0 there)
 };
 
+// Bijective block -> work-item map that gives each XCD a contiguous range of
+// work items (blocks are dispatched round-robin over the 8 XCDs), so x-chunk
+// neighbours that share halo rows share an L2.
+__device__ __forceinline__ long long xcd_item(unsigned b, unsigned n) {
+  unsigned per = n / kNumXcd, rem = n % kNumXcd;
+  unsigned x = b % kNumXcd, k = b / kNumXcd;
+  return (x < rem) ? (long long)x * (per + 1) + k
+                   : (long long)rem * (per + 1) + (long long)(x - rem) * per + k;
+}
+
 // Step-kernel source modes.
 enum StepMode : int {
   kCopy = 0,   // f = fin (first step of a plain fine solve)
@@ -283,6 +293,16 @@ int launch_adjoint_transpose(const Inst* d_inst, const Inst& h_inst, int chunk,
                              const double* fbar_next, const double* coef,
                              double* fbar_prev, hipStream_t s);
 int launch_sum_into(const double* cells, int n, double* acc, hipStream_t s);
+// Whole-cell adjoint kernels (one block per x cell, the cell's velocities in
+// the block's registers): elements per thread, 0 where a cell is too large.
+int adj_cell_ept(const Inst& h_inst);
+// backward false: fnext = a T f + al M[U(T f)] (the recomputation of a
+// state); true: from f and fbar (of the next state), the cell coefficients
+// of gbar into coef and the log-eps terms into dle_cells (added if
+// accumulate).  The transposed stencil follows with launch_adjoint_transpose.
+int launch_adj_cell(const Inst* d_inst, const Inst& h_inst, bool backward, const double* f,
+                    double* fnext, const double* fbar, double* coef, double* dle_cells,
+                    bool accumulate, int* status, hipStream_t s);
 int launch_lift_adjoint_rho(const Inst* d_inst, const Inst& h_inst,
                             const double* W, const double* fbar, double* rhobar,
                             hipStream_t s);

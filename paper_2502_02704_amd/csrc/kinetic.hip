@@ -23,15 +23,6 @@ namespace bgk {
 
 // ------------------------------------------------------------- helpers --
 
-// Bijective block -> work-item map that gives each XCD a contiguous range of
-// work items (blocks are dispatched round-robin over the 8 XCDs), so x-chunk
-// neighbours that share halo rows share an L2.
-__device__ __forceinline__ long long xcd_item(unsigned b, unsigned n) {
-  unsigned per = n / kNumXcd, rem = n % kNumXcd;
-  unsigned x = b % kNumXcd, k = b / kNumXcd;
-  return (x < rem) ? (long long)x * (per + 1) + k
-                   : (long long)rem * (per + 1) + (long long)(x - rem) * per + k;
-}
 
 __device__ __forceinline__ int ghost_row(int i, int nx, int bc) {
   if (i < 0) return bc == 1 ? i + nx : 0;

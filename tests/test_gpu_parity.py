@@ -402,6 +402,23 @@ def test_fine_adjoint_matches_oracle(bc):
     assert abs(float(dle.cpu()) - dle_ref) < 1e-11 * abs(dle_ref)
 
 
+@pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_PERIODIC])
+@pytest.mark.parametrize("nv", [(8, 8, 8), (16, 16, 16), (26, 25, 26)])
+def test_fine_adjoint_cell_sizes(bc, nv):
+    """Cells of 512 velocities (one per thread of the whole-cell kernels),
+    4096 (eight per thread) and 16900 (beyond one block: the tiled kernels
+    with separate per-cell reductions), against the oracle's adjoint."""
+    p = wl.Problem(nx=5, nv=nv, v_lo=(-6,) * 3, v_hi=(6,) * 3, bc=bc, eps=3e-2)
+    _, f0 = states(p, 35)
+    dt, n, every = 4e-3, 5, 2
+    ck, _ = oracle.checkpoints(p, f0, dt, n, every)
+    w = np.random.default_rng(36).standard_normal(f0.shape)
+    fb_ref, dle_ref = oracle.fine_adjoint(p, ck, every, n, dt, w)
+    fb, dle = bgk.fine_adjoint(p, cuda(ck), every, n, dt, cuda(w))
+    assert rel_f(fb.cpu().numpy(), fb_ref) < 1e-11
+    assert abs(float(dle.cpu()) - dle_ref) < 1e-11 * abs(dle_ref)
+
+
 def test_lift_and_density_adjoints():
     p, _ = _adj_case()
     W, _ = states(p, 32)
