@@ -432,7 +432,7 @@ def time_batch(torch, bgk, p, V, span, steps, warmup):
     """Times `steps` calls of the batched propagation (lift, fine steps,
     projection) of the slices V after `warmup` calls, with the step kernels'
     launches bracketed by HIP events on their stream.  Returns (seconds,
-    output, {kind: (ms, launches, updates, bytes)})."""
+    {kind: (ms, launches, updates, bytes)})."""
     Vd = torch.from_numpy(V).cuda()
     for _ in range(warmup):
         bgk.fine_propagate_moments(p, Vd, span)
