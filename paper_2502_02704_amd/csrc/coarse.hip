@@ -103,9 +103,12 @@ __device__ double* euler_advance(const CoarseGeo& G, double* cur, double* nxt, d
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
       const double* V = cur + 5 * i;
       const double rho = V[0];
-      const double ux = V[1] / rho, uy = V[2] / rho, uz = V[3] / rho;
+      // one division per cell (the substep loop is one wave's instruction
+      // stream for small grids)
+      const double irho = 1.0 / rho;
+      const double ux = V[1] * irho, uy = V[2] * irho, uz = V[3] * irho;
       const double usq = ux * ux + uy * uy + uz * uz;
-      const double th = (2.0 * V[4] / rho - usq) / 3.0;
+      const double th = (2.0 * V[4] * irho - usq) * (1.0 / 3.0);
       if (!(rho > 0.0 && th > 0.0 && isfinite(rho) && isfinite(th))) bad = 1;
       const double c = sqrt(G.gamma * th);
       const double pr = rho * th;
