@@ -19,6 +19,8 @@
 // stages the factor rows of its chunk in LDS.
 #include "bgk_internal.h"
 
+#include <type_traits>
+
 namespace bgk {
 
 // ------------------------------------------------------------- helpers --
@@ -320,16 +322,18 @@ __device__ __forceinline__ constexpr int lane_of_slot4(int k) {
 // correction limited by van Leer's limiter (five-point stencil, so the march
 // keeps rows i-2 .. i+2 and the ghost cells are two deep).
 // Harmonic-mean slope 2ab/(a+b) of van Leer's limiter, 0 where a b <= 0.
-// The quotient takes the hardware reciprocal of s = a+b refined by two
-// Newton-Raphson steps r <- r + r(1 - s r), then one residual correction of
-// the quotient q <- q + r(n - s q): within an ulp of the rounded division, at
-// fewer instructions (the second-order step is VALU-bound).  s != 0 where the
-// value is used (a b > 0 means a and b have one sign).
+// The quotient takes the hardware reciprocal of s = a+b refined by one
+// Newton-Raphson step r <- r + r(1 - s r), then one residual correction of
+// the quotient q <- q + r(n - s q), at fewer instructions than the division
+// (the second-order step is VALU-bound).  Measured on gfx950 against the
+// rounded division on 4M random same-sign pairs spread over 60 binades:
+// identical in every case (a second Newton step changes nothing; with none,
+// 43 % differ by up to 19 ulp).  s != 0 where the value is used (a b > 0
+// means a and b have one sign).
 __device__ __forceinline__ double vl_limited(double a, double b) {
   const double p = a * b;
   const double s = a + b;
   double r = __builtin_amdgcn_rcp(s);
-  r = fma(r, fma(-s, r, 1.0), r);
   r = fma(r, fma(-s, r, 1.0), r);
   const double n = 2.0 * p;
   double q = n * r;
@@ -349,6 +353,19 @@ __device__ __forceinline__ double flux2(double vx, double anu, double fm, double
   const double h = 0.5 * (1.0 - anu);
   const double c = pos ? h : -h;
   return vx * (up + c * vl_limited(d1, fp - f0));
+}
+
+// flux2 with the sign of v_x known (SGN = +1: v_x > 0, -1: v_x <= 0) for a
+// whole tile, so the upwind side needs no selects; SGN = 0 decides per
+// velocity.
+template <int SGN>
+__device__ __forceinline__ double flux2s(double vx, double anu, double fm, double f0,
+                                         double fp, double fp2) {
+  if (SGN == 0) return flux2(vx, anu, fm, f0, fp, fp2);
+  const double up = SGN > 0 ? f0 : fp;
+  const double d1 = SGN > 0 ? f0 - fm : fp2 - fp;
+  const double h = 0.5 * (1.0 - anu);
+  return vx * (up + (SGN > 0 ? h : -h) * vl_limited(d1, fp - f0));
 }
 
 // NS = 15: the records also carry the nu+ and nu- weighted sums (fused
@@ -411,6 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
   const double nuu = vxu * I.r;
 
   // relaxed value of row r (global row index, ghost-mapped) from raw g
+  // (UNI tiles are whole: a v_x plane holds whole tiles)
   auto relax_row = [&](int r, const double* raw, double* out) {
     const double* frow = lds + (r - rbase) * nvs;
 #pragma unroll
@@ -419,14 +437,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
       if (MODE == kCopy) v = raw[e];
       else if (MODE == kRelax) v = fma(a, raw[e], fac3(frow, el.off[e]));
       else v = fac3(frow, el.off[e]);
-      out[e] = el.ok[e] ? v : 0.0;
+      out[e] = (UNI || el.ok[e]) ? v : 0.0;
     }
   };
   auto load_row = [&](int r, double* raw) {
     if (MODE == kLift) return;
     const long long ro = (long long)ghost_row(r, nx, I.bc) * nv3;
 #pragma unroll
-    for (int e = 0; e < E; ++e) raw[e] = el.ok[e] ? src[ro + e * kWave] : 0.0;
+    for (int e = 0; e < E; ++e) raw[e] = (UNI || el.ok[e]) ? src[ro + e * kWave] : 0.0;
   };
 
   // relaxed rows i-H .. i+H of the march; raw row i+H (rawp) and i+H+1 (rawn)
@@ -474,7 +492,9 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
   }
   static_assert(NS == 5 || (NS == 15 && !FORCE && !LIMITED), "weighted sums: plain step");
   gptr<double> part = gmem(I.part) + ((long long)b * nx) * I.part_tiles * 5 + (long long)tile * NS;
-  for (int i = i0; i < i1; ++i) {
+  // one output row; SG: the tile's sign of v_x (UNI), else 0 (per velocity)
+  auto row = [&](int i, auto sg) {
+    constexpr int SG = decltype(sg)::value;
     if (i + 2 <= i1) load_row(i + H + 1, rawn);  // prefetch the next row
     if (FORCE && i + 1 < i1) load_vnb(i + 1, dn_nxt, up_nxt);
     relax_row(i + H, rawp, w[2 * H]);
@@ -488,8 +508,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
     for (int e = 0; e < E; ++e) {
       double gs;
       if (LIMITED) {
-        const double fr = flux2(UNI ? vxu : el.vx[e], fabs(UNI ? nuu : nu[e]), w[H - 1][e],
-                                w[H][e], w[H + 1][e], w[H + 2 < 2 * H + 1 ? H + 2 : 2 * H][e]);
+        const double fr = flux2s<SG>(UNI ? vxu : el.vx[e], fabs(UNI ? nuu : nu[e]), w[H - 1][e],
+                                     w[H][e], w[H + 1][e], w[H + 2 < 2 * H + 1 ? H + 2 : 2 * H][e]);
         gs = w[H][e] - I.r * (fr - fcar[e]);
         fcar[e] = fr;
       } else {
@@ -510,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
         }
         gs -= I.rv * (g_up - g_down);
       }
-      if (el.ok[e]) dst[(long long)i * nv3 + e * kWave] = gs;
+      if (UNI || el.ok[e]) dst[(long long)i * nv3 + e * kWave] = gs;
       s0 += gs;
       if (!UNI) s1 = fma(el.vx[e], gs, s1);
       s2 = fma(el.vy[e], gs, s2);
@@ -558,6 +578,15 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
         up_cur[e] = up_nxt[e];
       }
     }
+  };
+  // the tile's sign of v_x is uniform (UNI): one loop per sign, no
+  // per-velocity selects of the upwind side
+  if (UNI && vxu > 0.0) {
+    for (int i = i0; i < i1; ++i) row(i, std::integral_constant<int, 1>{});
+  } else if (UNI) {
+    for (int i = i0; i < i1; ++i) row(i, std::integral_constant<int, -1>{});
+  } else {
+    for (int i = i0; i < i1; ++i) row(i, std::integral_constant<int, 0>{});
   }
 }
 
