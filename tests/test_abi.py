@@ -2,6 +2,7 @@
 point that include/bgk.h declares (no compute calls here)."""
 import ctypes
 import os
+from dataclasses import replace
 import re
 
 import pytest
@@ -144,6 +145,26 @@ def test_empty_and_oversized_batches_rejected():
     for n in (0, 4097):
         assert lib.bgk_fine_step_batched(probs, n, ptrs, outs, spans, None, None, 0,
                                          None) == bgk.E_INVALID
+
+
+def test_batched_workspace_holds_padded_copies_for_odd_nvz():
+    """An instance with odd nv_z gets two padded fields in the uneven batch's
+    workspace (each z row one point longer), an instance with even nv_z one
+    field: the odd instance's workspace exceeds the even one's by at least
+    the padded fields' bytes."""
+    lib = bgk.load_library()
+    base = wl.Problem(nx=40, nv=(6, 5, 8), v_lo=(-5,) * 3, v_hi=(5,) * 3, bc=wl.BC_NEUMANN,
+                      eps=1e-2)
+    odd = replace(base, nv=(6, 5, 7))
+
+    def ws(p):
+        arr = (bgk._Problem * 1)(bgk.problem_struct(p))
+        return int(lib.bgk_workspace_bytes_batched(arr, 1))
+
+    f_even = base.nx * 6 * 5 * 8 * 8
+    assert ws(base) >= f_even
+    # odd: two fields of nx * 6 * 5 * (7 + 1) doubles against one of the even grid's size
+    assert ws(odd) - ws(base) >= 2 * f_even - f_even
 
 
 def test_noalloc_size_limit_checked_on_the_host():
