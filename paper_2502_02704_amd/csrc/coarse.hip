@@ -268,7 +268,22 @@ __global__ __launch_bounds__(kCoarseBlock) void k_parareal_sweep(
   const long long sl = 5LL * nx;
   double* cur = scratch;
   double* oth = scratch + 5 * nx;
-  for (long long q = threadIdx.x; q < (k + 1) * sl; q += blockDim.x) U_new[q] = U_old[q];
+  // frozen slices n <= k: eight loads in flight per thread (one wave copies
+  // up to a few thousand values here, so the copy is latency bound)
+  const long long ncopy = (k + 1) * sl;
+  for (long long q0 = threadIdx.x; q0 < ncopy; q0 += 8LL * blockDim.x) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const long long q = q0 + (long long)u * blockDim.x;
+      if (q < ncopy) t[u] = U_old[q];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const long long q = q0 + (long long)u * blockDim.x;
+      if (q < ncopy) U_new[q] = t[u];
+    }
+  }
   for (long long q = threadIdx.x; q < sl; q += blockDim.x) cur[q] = U_old[k * sl + q];
   __syncthreads();
   double lerr = 0.0;
