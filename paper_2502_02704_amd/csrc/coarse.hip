@@ -15,7 +15,9 @@ namespace bgk {
 
 namespace {
 
-constexpr int kCoarseBlock = 256;
+constexpr int kCoarseBlock = 256;      // threads of a cell-per-thread workgroup
+constexpr int kCompWaves = 5;          // grids of up to 64 cells: one wave per
+constexpr int kCompThreads = 64 * kCompWaves;  // conserved component
 constexpr int kMaxSubsteps = 1 << 20;  // hard cap: every loop ends
 
 struct CoarseGeo {
@@ -43,7 +45,7 @@ __device__ __forceinline__ double dpp_get(double v) {
 // DPP row see 0, which is neutral here).  One wave: DPP steps that leave
 // the maximum in lane 63, no LDS and no barrier.  Several waves: one more
 // exchange through LDS between two barriers.
-__device__ double block_max(double v, double* red) {
+__device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_get<0xb1, 0xf>(v));   // quad_perm [1,0,3,2]
   v = fmax(v, dpp_get<0x4e, 0xf>(v));   // quad_perm [2,3,0,1]
   v = fmax(v, dpp_get<0x114, 0xf>(v));  // row_shr:4
@@ -52,7 +54,11 @@ __device__ double block_max(double v, double* red) {
   v = fmax(v, dpp_get<0x143, 0xc>(v));  // row_bcast:31 into rows 2, 3
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-  v = __hiloint2double(hi, lo);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ double block_max(double v, double* red) {
+  v = wave_max(v);
   if (blockDim.x == 64) return v;
   const int w = threadIdx.x / 64;
   __syncthreads();
@@ -81,6 +87,105 @@ __device__ __forceinline__ void visc_flux(const CoarseGeo& G, const double* V,
   D[4] = k * (mu * ((4.0 / 3.0) * uxf * dux + uyf * duy + uzf * duz) + kappa * (pb[3] - pa[3]));
 }
 
+// euler_advance for grids of up to 64 cells on kCompWaves waves: wave c
+// updates conserved component c of every cell (lane = cell).  Each wave
+// computes the primitives, wave speeds and its component's flux of all cells
+// (the same values and the same arithmetic in every wave, so the step size,
+// the substep count and the exits agree), takes the neighbours' values by
+// lane shuffles, and one workgroup barrier per substep publishes the new
+// components.  Same results as the cell-per-thread loop below.
+__device__ double* euler_advance_waves(const CoarseGeo& G, double* cur, double* nxt,
+                                       double span, int* status, int* nsub_out) {
+  const int nx = G.nx;
+  const bool viscous = G.eps > 0.0;
+  const int comp = threadIdx.x / 64, i = threadIdx.x % 64;
+  const bool live = i < nx;
+  const int ic = live ? i : 0;
+  const int L = gh(ic - 1, nx, G.bc), R = gh(ic + 1, nx, G.bc);
+  const double Ei = (G.E != nullptr) ? G.E[ic] : 0.0;
+  const double kv = G.eps / G.dx;
+  double t = 0.0;
+  int nsub = 0;
+  while (span - t > 1e-14 * span) {
+    const double* V = cur + 5 * ic;
+    const double v0 = V[0], v1 = V[1], v2 = V[2], v3 = V[3], v4 = V[4];
+    const double rho = v0;
+    const double irho = 1.0 / rho;
+    const double ux = v1 * irho, uy = v2 * irho, uz = v3 * irho;
+    const double usq = ux * ux + uy * uy + uz * uz;
+    const double th = (2.0 * v4 * irho - usq) * (1.0 / 3.0);
+    const bool bad = live && !(rho > 0.0 && th > 0.0 && isfinite(rho) && isfinite(th));
+    const double cs = sqrt(G.gamma * th);
+    const double pr = rho * th;
+    const double spd = live ? fabs(ux) + cs : 0.0;
+    const double hc = comp == 0 ? rho * ux
+                    : comp == 1 ? rho * ux * ux + pr
+                    : comp == 2 ? rho * ux * uy
+                    : comp == 3 ? rho * ux * uz
+                                : ux * (v4 + pr);
+    const double vc = comp == 0 ? v0 : comp == 1 ? v1 : comp == 2 ? v2 : comp == 3 ? v3 : v4;
+    if (bad) *status = 1;
+    const double smax = wave_max(bad ? INFINITY : spd);
+    if (!(smax > 0.0) || !isfinite(smax) || nsub >= kMaxSubsteps) {
+      *status = 1;
+      break;  // uniform: every wave sees the same smax and nsub
+    }
+    double dt = G.cfl * G.dx / smax;
+    if (viscous) {
+      const double tm = wave_max(bad ? INFINITY : (live ? th : 0.0));
+      const double dt_visc = G.cfl * G.dx * G.dx / (2.0 * G.eps * (5.0 / 3.0) * tm);
+      if (dt_visc < dt) dt = dt_visc;
+    }
+    if (dt > span - t) dt = span - t;
+    const double r = dt / G.dx;
+    const double spdL = __shfl(spd, L), spdR = __shfl(spd, R);
+    const double hL = __shfl(hc, L), hR = __shfl(hc, R);
+    const double cL = __shfl(vc, L), cR = __shfl(vc, R);
+    const double SL = fmax(spdL, spd), SR = fmax(spd, spdR);
+    const double Hr = 0.5 * (hc + hR) - 0.5 * SR * (cR - vc);
+    const double Hl = 0.5 * (hL + hc) - 0.5 * SL * (vc - cL);
+    double nv = vc - r * (Hr - Hl);
+    if (viscous) {
+      // face fluxes (L, i) and (i, R): mu = mean of rho theta, kappa = 5/2 mu
+      const double rL = __shfl(rho, L), rR = __shfl(rho, R);
+      const double xL = __shfl(ux, L), xR = __shfl(ux, R);
+      const double yL = __shfl(uy, L), yR = __shfl(uy, R);
+      const double zL = __shfl(uz, L), zR = __shfl(uz, R);
+      const double tL = __shfl(th, L), tR = __shfl(th, R);
+      auto face = [&](double ra, double xa, double ya, double za, double ta, double rb,
+                      double xb, double yb, double zb, double tb) {
+        const double mu = 0.5 * (ra * ta + rb * tb);
+        const double kappa = 2.5 * mu;
+        const double dux = xb - xa, duy = yb - ya, duz = zb - za;
+        const double uxf = 0.5 * (xa + xb), uyf = 0.5 * (ya + yb), uzf = 0.5 * (za + zb);
+        return comp == 1 ? kv * (4.0 / 3.0) * mu * dux
+             : comp == 2 ? kv * mu * duy
+             : comp == 3 ? kv * mu * duz
+                         : kv * (mu * ((4.0 / 3.0) * uxf * dux + uyf * duy + uzf * duz) +
+                                 kappa * (tb - ta));
+      };
+      if (comp > 0) {
+        const double Dl = face(rL, xL, yL, zL, tL, rho, ux, uy, uz, th);
+        const double Dr = face(rho, ux, uy, uz, th, rR, xR, yR, zR, tR);
+        nv += r * (Dr - Dl);
+      }
+    }
+    if (G.E != nullptr) {
+      if (comp == 1) nv += dt * v0 * Ei;
+      if (comp == 4) nv += dt * v1 * Ei;
+    }
+    if (live) nxt[5 * i + comp] = nv;
+    __syncthreads();
+    double* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    t += dt;
+    ++nsub;
+  }
+  if (nsub_out) *nsub_out = nsub;
+  return cur;
+}
+
 // Advances the state held in `cur` (5*nx doubles) over `span`, ping-ponging
 // with `nxt`; h (5*nx), spd (nx) and prim (4*nx) are flux scratch.  With an
 // exterior force each substep also adds the source (0, rho E, 0, 0,
@@ -93,6 +198,7 @@ __device__ __forceinline__ void visc_flux(const CoarseGeo& G, const double* V,
 __device__ double* euler_advance(const CoarseGeo& G, double* cur, double* nxt, double* h,
                                  double* spd, double* prim, double span, double* red,
                                  int* status, int* nsub_out) {
+  if (blockDim.x == kCompThreads) return euler_advance_waves(G, cur, nxt, span, status, nsub_out);
   const int nx = G.nx;
   const bool viscous = G.eps > 0.0;
   double t = 0.0;
@@ -203,10 +309,10 @@ __device__ __forceinline__ double* coarse_scratch(bool use_lds, double* slab) {
   return use_lds ? lds_scratch : slab;
 }
 
-__global__ __launch_bounds__(kCoarseBlock) void k_euler(
+__global__ __launch_bounds__(kCompThreads) void k_euler(
     CoarseGeo G, const double* __restrict__ Vin, double* Vout, double span,
     int* nsub_out, double* scratch, int* status, int use_lds) {
-  __shared__ double red[kCoarseBlock / 64];
+  __shared__ double red[kCompThreads / 64];
   const long long m = blockIdx.x;
   const long long sl = 5LL * G.nx;
   double* sc = coarse_scratch(use_lds, scratch + m * (long long)kCoarseScratch * G.nx);
@@ -216,10 +322,10 @@ __global__ __launch_bounds__(kCoarseBlock) void k_euler(
 
 // U[0] = V(W0), U[n] = G(U[n-1]) for n = 1..N; Gc[n] = U[n].  The state
 // stays in the workgroup's scratch from one slice to the next.
-__global__ __launch_bounds__(kCoarseBlock) void k_parareal_init(
+__global__ __launch_bounds__(kCompThreads) void k_parareal_init(
     CoarseGeo G, int n_slices, const double* __restrict__ W0, double* U,
     double* Gc, double span, double* scratch_slab, int* status, int use_lds) {
-  __shared__ double red[kCoarseBlock / 64];
+  __shared__ double red[kCompThreads / 64];
   double* scratch = coarse_scratch(use_lds, scratch_slab);
   const int nx = G.nx;
   const long long sl = 5LL * nx;
@@ -258,11 +364,11 @@ __global__ __launch_bounds__(kCoarseBlock) void k_parareal_init(
 // loads VF, Gc and U_old of slice n before propagating into it, so those
 // reads overlap the propagation (requires R * blockDim >= 5 * nx).
 template <int R>
-__global__ __launch_bounds__(kCoarseBlock) void k_parareal_sweep(
+__global__ __launch_bounds__(kCompThreads) void k_parareal_sweep(
     CoarseGeo G, int n_slices, int k, const double* __restrict__ U_old,
     double* U_new, const double* __restrict__ VF, double* Gc, double span,
     double* scratch_slab, double* err, int* status, int use_lds) {
-  __shared__ double red[kCoarseBlock / 64];
+  __shared__ double red[kCompThreads / 64];
   double* scratch = coarse_scratch(use_lds, scratch_slab);
   const int nx = G.nx;
   const long long sl = 5LL * nx;
@@ -340,9 +446,11 @@ CoarseGeo geo_of(const bgk_problem& p, const double* E, bool viscous) {
   return G;
 }
 
-// Threads per coarse workgroup: one per cell up to 256 (whole waves).
+// Threads per coarse workgroup: one wave per conserved component up to 64
+// cells (scratch in LDS: kCoarseScratch nx doubles, at most 10 KB), else one
+// per cell up to 256 (whole waves).
 int coarse_threads(int nx) {
-  return nx <= 64 ? 64 : (nx <= 128 ? 128 : kCoarseBlock);
+  return nx <= 64 ? kCompThreads : (nx <= 128 ? 128 : kCoarseBlock);
 }
 
 // Dynamic LDS bytes for `doubles` of scratch, or 0 if it must stay in HBM.
