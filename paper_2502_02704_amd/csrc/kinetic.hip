@@ -1167,8 +1167,8 @@ __global__ __launch_bounds__(kBlock) void k_step2(const Inst* __restrict__ insts
 // Raw rows in flight in the two-step marches: one on paired lanes (a second
 // row spills the 4-pair march: measured 3.3 against 5.3 TB/s on the uneven
 // batch's paired instances), three on unpaired lanes, loaded non-temporally
-// (3.97 TB/s on its unpaired instances against 3.76 with one row, 3.92 with
-// two).
+// (3.97 TB/s on the batch's odd-nv_z instances run unpaired, against 3.76
+// with one row, 3.92 with two).
 constexpr int kRowsInFlight2x = 1;
 constexpr int kRowsInFlight2xFlat = 3;
 
@@ -1329,7 +1329,7 @@ __global__ __launch_bounds__(kBlock) void k_step2x2(const Inst* __restrict__ ins
 
 // ------------------------------- two steps per pass, unpaired lanes --
 // The two-step pass for grids whose rows cannot be read in 16-byte pairs
-// (odd nv_z): E velocities per lane at stride 64 (flat index tile * 64 E +
+// (odd nv_z, or f off 16-byte alignment): E velocities per lane at stride 64 (flat index tile * 64 E +
 // e * 64 + lane, one 8-byte access each), as in the one-step kernel.  Same
 // levels as the paired march: level 1 at rows k .. k+2 from the factors
 // fac, level 2 at rows k-1 .. k+1 from fac2, output row k; every velocity
