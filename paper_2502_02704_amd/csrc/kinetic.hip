@@ -428,15 +428,19 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
   const double nuu = vxu * I.r;
 
   // relaxed value of row r (global row index, ghost-mapped) from raw g
-  // (UNI tiles are whole: a v_x plane holds whole tiles)
+  // (UNI tiles are whole, a v_x plane holding whole tiles, and share one Ex
+  // factor per row)
   auto relax_row = [&](int r, const double* raw, double* out) {
     const double* frow = lds + (r - rbase) * nvs;
+    const double mxu = (UNI && MODE != kCopy) ? frow[el.off[0] & 1023u] : 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
+      const double m = UNI ? mxu * frow[(el.off[e] >> 10) & 1023u] * frow[el.off[e] >> 20]
+                           : fac3(frow, el.off[e]);
       double v;
       if (MODE == kCopy) v = raw[e];
-      else if (MODE == kRelax) v = fma(a, raw[e], fac3(frow, el.off[e]));
-      else v = fac3(frow, el.off[e]);
+      else if (MODE == kRelax) v = fma(a, raw[e], m);
+      else v = m;
       out[e] = (UNI || el.ok[e]) ? v : 0.0;
     }
   };
@@ -531,11 +535,19 @@ __global__ __launch_bounds__(kBlock) void k_step(const Inst* __restrict__ insts,
         gs -= I.rv * (g_up - g_down);
       }
       if (UNI || el.ok[e]) dst[(long long)i * nv3 + e * kWave] = gs;
-      s0 += gs;
-      if (!UNI) s1 = fma(el.vx[e], gs, s1);
-      s2 = fma(el.vy[e], gs, s2);
-      s3 = fma(el.vz[e], gs, s3);
-      s4 = fma(vsq[e], gs, s4);
+      if (UNI && e == 0) {
+        // the sums start from the first velocity's terms (no additions of 0)
+        s0 = gs;
+        s2 = el.vy[e] * gs;
+        s3 = el.vz[e] * gs;
+        s4 = vsq[e] * gs;
+      } else {
+        s0 += gs;
+        if (!UNI) s1 = fma(el.vx[e], gs, s1);
+        s2 = fma(el.vy[e], gs, s2);
+        s3 = fma(el.vz[e], gs, s3);
+        s4 = fma(vsq[e], gs, s4);
+      }
       if (NS == 15) {
         const double cp = nu[e] > 0.0 ? nu[e] : 0.0, cm = nu[e] < 0.0 ? -nu[e] : 0.0;
         const double m[5] = {gs, el.vx[e] * gs, el.vy[e] * gs, el.vz[e] * gs, vsq[e] * gs};
