@@ -248,14 +248,19 @@ def parareal_small(torch, bgk, wl, reps=5):
 def parareal_large(torch, bgk, wl, k_cap_smooth=8, k_cap_sod=6):
     """Parareal at the full baseline sizes, where one slice's fine step is
     bandwidth bound: the smooth periodic workload (512 x 32^3, 64 slices) at
-    eps = 1, 1e-2, 1e-4 and the large Sod workload (2048 x 48^3, 32 slices,
+    eps = 1, 1e-2, 1e-4 with the Euler coarse model, at eps = 1e-2 and 1e-4
+    also with the Navier-Stokes coarse model and the order-one lifting (at
+    eps = 1 that model is outside its regime: the lifted states leave the
+    physical set), and the large Sod workload (2048 x 48^3, 32 slices,
     K <= 6), Euler coarse model.  Reported as measured (a slowdown is
     expected: each iteration moves about as many bytes as the serial solve)."""
     out = []
     for eps in (1.0, 1e-2, 1e-4):
         w = wl.c2_smooth_periodic(eps=eps)
-        out.append(parareal_row(torch, bgk, w.name, w.problem, w.W0, w.n_slices, w.T, None,
-                                "euler", 0, k_cap_smooth, 2, True, warm_each=False))
+        models = [("euler", 0)] + ([("cns", 1)] if eps < 1.0 else [])
+        for coarse, lo in models:
+            out.append(parareal_row(torch, bgk, w.name, w.problem, w.W0, w.n_slices, w.T, None,
+                                    coarse, lo, k_cap_smooth, 2, True, warm_each=False))
         bgk.free_workspaces()
         torch.cuda.empty_cache()
     w = wl.c3_sod_large()
