@@ -259,8 +259,15 @@ def parareal_large(torch, bgk, wl, k_cap_smooth=8, k_cap_sod=6):
         w = wl.c2_smooth_periodic(eps=eps)
         models = [("euler", 0)] + ([("cns", 1)] if eps < 1.0 else [])
         for coarse, lo in models:
-            out.append(parareal_row(torch, bgk, w.name, w.problem, w.W0, w.n_slices, w.T, None,
-                                    coarse, lo, k_cap_smooth, 2, True, warm_each=False))
+            try:
+                out.append(parareal_row(torch, bgk, w.name, w.problem, w.W0, w.n_slices, w.T,
+                                        None, coarse, lo, k_cap_smooth, 2, True,
+                                        warm_each=False))
+            except bgk.BgkError as e:
+                # a model outside its regime reports a non-physical state
+                bgk.status()
+                out.append({"workload": w.name, "baseline_config": True, "coarse": coarse,
+                            "lift_order": lo, "error": str(e)})
         bgk.free_workspaces()
         torch.cuda.empty_cache()
     w = wl.c3_sod_large()
