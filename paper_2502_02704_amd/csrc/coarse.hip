@@ -15,7 +15,7 @@ namespace bgk {
 
 namespace {
 
-constexpr int kCoarseBlock = 256;      // threads of a cell-per-thread workgroup
+constexpr int kCoarseBlock = 512;      // most threads of a cell-per-thread workgroup
 constexpr int kCompWaves = 5;          // grids of up to 64 cells: one wave per
 constexpr int kCompThreads = 64 * kCompWaves;  // conserved component
 constexpr int kMaxSubsteps = 1 << 20;  // hard cap: every loop ends
@@ -309,10 +309,10 @@ __device__ __forceinline__ double* coarse_scratch(bool use_lds, double* slab) {
   return use_lds ? lds_scratch : slab;
 }
 
-__global__ __launch_bounds__(kCompThreads) void k_euler(
+__global__ __launch_bounds__(kCoarseBlock) void k_euler(
     CoarseGeo G, const double* __restrict__ Vin, double* Vout, double span,
     int* nsub_out, double* scratch, int* status, int use_lds) {
-  __shared__ double red[kCompThreads / 64];
+  __shared__ double red[kCoarseBlock / 64];
   const long long m = blockIdx.x;
   const long long sl = 5LL * G.nx;
   double* sc = coarse_scratch(use_lds, scratch + m * (long long)kCoarseScratch * G.nx);
@@ -322,10 +322,10 @@ __global__ __launch_bounds__(kCompThreads) void k_euler(
 
 // U[0] = V(W0), U[n] = G(U[n-1]) for n = 1..N; Gc[n] = U[n].  The state
 // stays in the workgroup's scratch from one slice to the next.
-__global__ __launch_bounds__(kCompThreads) void k_parareal_init(
+__global__ __launch_bounds__(kCoarseBlock) void k_parareal_init(
     CoarseGeo G, int n_slices, const double* __restrict__ W0, double* U,
     double* Gc, double span, double* scratch_slab, int* status, int use_lds) {
-  __shared__ double red[kCompThreads / 64];
+  __shared__ double red[kCoarseBlock / 64];
   double* scratch = coarse_scratch(use_lds, scratch_slab);
   const int nx = G.nx;
   const long long sl = 5LL * nx;
@@ -364,11 +364,11 @@ __global__ __launch_bounds__(kCompThreads) void k_parareal_init(
 // loads VF, Gc and U_old of slice n before propagating into it, so those
 // reads overlap the propagation (requires R * blockDim >= 5 * nx).
 template <int R>
-__global__ __launch_bounds__(kCompThreads) void k_parareal_sweep(
+__global__ __launch_bounds__(kCoarseBlock) void k_parareal_sweep(
     CoarseGeo G, int n_slices, int k, const double* __restrict__ U_old,
     double* U_new, const double* __restrict__ VF, double* Gc, double span,
     double* scratch_slab, double* err, int* status, int use_lds) {
-  __shared__ double red[kCompThreads / 64];
+  __shared__ double red[kCoarseBlock / 64];
   double* scratch = coarse_scratch(use_lds, scratch_slab);
   const int nx = G.nx;
   const long long sl = 5LL * nx;
@@ -448,15 +448,17 @@ CoarseGeo geo_of(const bgk_problem& p, const double* E, bool viscous) {
 
 // Threads per coarse workgroup: one wave per conserved component up to 64
 // cells (scratch in LDS: kCoarseScratch nx doubles, at most 10 KB), else one
-// per cell up to 256 (whole waves).
+// per cell in whole waves up to 512 (several cells per thread beyond).
 int coarse_threads(int nx) {
-  return nx <= 64 ? kCompThreads : (nx <= 128 ? 128 : kCoarseBlock);
+  if (nx <= 64) return kCompThreads;
+  return nx <= kCoarseBlock ? (nx + 63) / 64 * 64 : kCoarseBlock;
 }
 
-// Dynamic LDS bytes for `doubles` of scratch, or 0 if it must stay in HBM.
+// Dynamic LDS bytes for `doubles` of scratch (grids of up to 960 cells), or
+// 0 if it must stay in an L2-resident global slab.
 size_t coarse_lds(size_t doubles) {
   const size_t bytes = doubles * sizeof(double);
-  return bytes <= 60 * 1024 ? bytes : 0;
+  return bytes <= 150 * 1024 ? bytes : 0;
 }
 
 }  // namespace

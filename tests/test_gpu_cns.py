@@ -30,10 +30,11 @@ def smooth_states(p, seed, B):
 
 @pytest.mark.parametrize("force", [False, True])
 @pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_PERIODIC])
-@pytest.mark.parametrize("nx", [40, 64, 100, 200, 600])
+@pytest.mark.parametrize("nx", [40, 64, 100, 200, 600, 1200])
 def test_cns_coarse_matches_oracle(nx, bc, force):
-    # 40 and 64 cells: one wave per conserved component; 100 (two waves) and
-    # 200 (four): one thread per cell; 600: scratch in global memory
+    # 40 and 64 cells: one wave per conserved component; 100, 200 and 600:
+    # one thread per cell (two, four and ten waves), scratch in LDS; 1200:
+    # several cells per thread, scratch in global memory
     p = wl.small_problem(nx=nx, bc=bc, eps=0.02)
     V = smooth_states(p, nx + bc, 2)
     E = 0.6 * np.sin(2 * np.pi * p.x_centres()) if force else None
