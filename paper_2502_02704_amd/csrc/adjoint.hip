@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kCellBlock) void k_adj_cell(
   const double th = (2.0 * En / rho - usq) / 3.0;
   if (threadIdx.x == 0 && !(rho > 0.0 && th > 0.0 && isfinite(rho) && isfinite(th)))
     *status = 1;
-  const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
+  const double C0 = maxwell_norm(rho, th);
   const double inv2t = 1.0 / (2.0 * th);
   for (int k = threadIdx.x; k < I.nvs; k += kCellBlock) {
     const int ax = k < I.nvx ? 0 : (k < I.nvx + I.nvy ? 1 : 2);

@@ -2070,14 +2070,17 @@ __device__ __forceinline__ void maxwell_weighted_sums(const Inst& I, int lane,
   }
 }
 
+// Primitive (rho, u, theta) from conserved (rho, m, E): one division, the
+// other quotients by its reciprocal.
 __device__ __forceinline__ void cons_to_prim(const double* V, double& rho, double u[3],
                                              double& th) {
   rho = V[0];
-  u[0] = V[1] / rho;
-  u[1] = V[2] / rho;
-  u[2] = V[3] / rho;
+  const double irho = 1.0 / rho;
+  u[0] = V[1] * irho;
+  u[1] = V[2] * irho;
+  u[2] = V[3] * irho;
   const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  th = (2.0 * V[4] / rho - usq) / 3.0;
+  th = (2.0 * V[4] * irho - usq) * (1.0 / 3.0);
 }
 
 // Offset of weight class w (0: 1; 2q - 1: nu+^q; 2q: nu-^q) in an aux-style
@@ -2141,7 +2144,7 @@ __device__ __forceinline__ void advance_reduce(const Inst& I, long long cl, int 
   double rho, u[3], th;
   cons_to_prim(V, rho, u, th);
   if (lane == 0 && !physical(rho, th)) *status = 1;
-  const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
+  const double C0 = maxwell_norm(rho, th);
   if (PROJECT) {
     double A[15];
     maxwell_weighted_sums<3>(I, lane, u, th, C0 * I.dv3, A);
@@ -2238,7 +2241,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
     double rho, u[3], th;
     cons_to_prim(V, rho, u, th);
     if (lane == 0 && !physical(rho, th)) *status = 1;
-    const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
+    const double C0 = maxwell_norm(rho, th);
     if (mode == kRedW2Project || mode == kRedW3x3Project) {
       // the next field's relaxation, projected (as kRedProject does from
       // records): P f = a V(g) + al V(M[U(g)])
@@ -2356,9 +2359,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
   const double rho = s[0];
   const double m[3] = {s[1], s[2], s[3]};
   const double E = s[4];
-  const double u[3] = {m[0] / rho, m[1] / rho, m[2] / rho};
+  const double irho = 1.0 / rho;
+  const double u[3] = {m[0] * irho, m[1] * irho, m[2] * irho};
   const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  const double th = (2.0 * E / rho - usq) / 3.0;
+  const double th = (2.0 * E * irho - usq) * (1.0 / 3.0);
   if (lane == 0) {
     double* vg = I.vg + cl * 5;
     vg[0] = rho;
@@ -2379,7 +2383,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const Inst* __restrict__ inst
     }
     return;
   }
-  const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
+  const double C0 = maxwell_norm(rho, th);
   if (mode == kRedRelaxFactors || mode == kRedMaxwellFactors || mode == kRedW1 ||
       mode == kRedW1x3 || mode == kRedW1x4) {
     // (W1, W1x3: the factor row is written with the weighted sums' exponentials)
@@ -2469,7 +2473,7 @@ __global__ __launch_bounds__(kBlock) void k_lift_factors(
   if (!physical(rho, th) || !isfinite(u[0]) || !isfinite(u[1]) || !isfinite(u[2])) {
     if (lane == 0) *status = 1;
   }
-  const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
+  const double C0 = maxwell_norm(rho, th);
   double* row = I.fac + cl * I.nvs;
   if (!with_aux) write_factors(I, row, lane, C0, u, th);
   if (with_aux == 1) {

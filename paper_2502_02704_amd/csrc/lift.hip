@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_lift_ce(const Inst* __restrict__ ins
   double d[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) d[c] = (wr[c] - wl[c]) / (2.0 * dx);
-  const double C0 = rho * pow(2.0 * M_PI * th, -1.5);
+  const double C0 = maxwell_norm(rho, th);
   const double inv2t = 1.0 / (2.0 * th);
   for (int k = threadIdx.x; k < I.nvs; k += kBlock) {
     const int ax = (k < I.nvx) ? 0 : (k < I.nvx + I.nvy ? 1 : 2);
