@@ -39,7 +39,9 @@ TRAFFIC_SUMMARY = {
     ("smooth_periodic", "two"): os.path.join(ROOT, "profiles",
                                              "k_step2x2_smooth_periodic_traffic.md"),
 }
-KERNEL_SRC = os.path.join(ROOT, "paper_2502_02704_amd", "csrc", "kinetic.hip")
+# sources of the step kernels whose counters the traffic summaries record
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2502_02704_amd", "csrc", n)
+               for n in ("kinetic.hip", "bgk_internal.h")]
 TILE_CACHE = os.path.join(ROOT, "paper_2502_02704_amd", "tiles.json")
 
 
@@ -49,8 +51,13 @@ def log(msg):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """First 16 hex digits of the SHA-256 of the step kernels' sources
+    (concatenated in order)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def conserved(W):
