@@ -1,0 +1,145 @@
+"""Seeded sweep of random grid shapes through the HIP path against the oracle.
+
+The fixed grids of the other parity tests are chosen by hand; here each case
+draws its own: nx in [2, 70] (below three the fused passes fall back to
+pairs), 3 to 14 velocity points per axis on an off-centre box whose spacing
+keeps the Maxwellians resolved (odd and even v_z; every third case with v_x
+planes of whole velocity tiles, which take the three- and four-step
+passes), either boundary condition, eps from 1e-5 to 10 or
+infinite (free transport), one to seven IMEX steps under every step fusion
+setting (1 to 4 steps per pass) and tile shape.  Each case compares moments,
+fine steps and the batched lift-propagate-project call with the oracle at the
+1e-12 bar, and a batch of several drawn grids through the uneven batched call
+(bit-exact step counts).
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2502_02704_amd import bgk
+from paper_2502_02704_amd import workloads as wl
+from tests.gpu_util import TOL, rel_f, rel_V, rel_W
+
+pytestmark = pytest.mark.gpu
+
+SEED = 250202790
+N_CASES = 40
+TILES = [(0, 0, -1), (2, 1, 0), (4, 5, 0), (8, 16, 0), (2, 1, 1), (4, 3, 1), (8, 64, 1)]
+
+
+@pytest.fixture(autouse=True)
+def _reset_tiles():
+    bgk.set_tiles(0, 0, -1)
+    bgk.set_step_fusion(3)
+    yield
+    bgk.set_tiles(0, 0, -1)
+    bgk.set_step_fusion(3)
+
+
+# (v_y, v_z) points whose planes are whole tiles of 128 or 256 velocities:
+# such grids take the three- and four-step passes
+WHOLE_TILE_PLANES = [(8, 16), (16, 8), (16, 16), (4, 32), (32, 4), (8, 32)]
+
+
+def draw_problem(rng, whole_planes=False):
+    """A grid of the sweep: spacing 0.45 to 1.1 per velocity axis around a
+    shifted centre (thermal speed 0.7 to 1.1 stays resolved)."""
+    nx = int(rng.integers(2, 71))
+    nv = tuple(int(rng.integers(3, 15)) for _ in range(3))
+    if whole_planes:
+        nv = (int(rng.integers(3, 11)),) + WHOLE_TILE_PLANES[int(rng.integers(0, 6))]
+    lo, hi = [], []
+    for a in range(3):
+        dv = rng.uniform(0.45, 1.1)
+        c = rng.uniform(-0.6, 0.6)
+        lo.append(c - 0.5 * nv[a] * dv)
+        hi.append(c + 0.5 * nv[a] * dv)
+    bc = int(rng.integers(0, 2))
+    eps = float("inf") if rng.uniform() < 0.1 else float(10.0 ** rng.uniform(-5, 1))
+    return wl.Problem(nx=nx, nv=nv, v_lo=tuple(lo), v_hi=tuple(hi), bc=bc, eps=eps)
+
+
+def draw_states(rng, p):
+    """Primitive moments near (1, 0, 0.8) with their lifted, perturbed field."""
+    W = np.column_stack([rng.uniform(0.4, 1.4, p.nx), rng.uniform(-0.3, 0.3, (p.nx, 3)),
+                         rng.uniform(0.5, 1.2, p.nx)])
+    f = oracle.lift(p, W) * (1 + 0.2 * rng.uniform(-1, 1, (p.nx, p.nv3)))
+    return W, f
+
+
+def conserved(W):
+    return np.column_stack([W[:, 0], W[:, 0:1] * W[:, 1:4],
+                            0.5 * W[:, 0] * (W[:, 1:4] ** 2).sum(1) + 1.5 * W[:, 0] * W[:, 4]])
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("case", range(N_CASES))
+def test_random_grid_matches_oracle(case):
+    rng = np.random.default_rng(SEED + case)
+    p = draw_problem(rng, whole_planes=case % 3 == 0)
+    fusion = int(rng.integers(1, 5))
+    tiles = TILES[int(rng.integers(0, len(TILES)))]
+    n = int(rng.integers(1, 8))
+    W, f = draw_states(rng, p)
+    print(f"case {case}: nx={p.nx} nv={p.nv} bc={p.bc} eps={p.eps:.3g} steps={n} "
+          f"fusion={fusion} tiles={tiles}", flush=True)
+    bgk.set_step_fusion(fusion)
+    bgk.set_tiles(*tiles)
+
+    # moments of the perturbed field
+    V, Wg = bgk.moments(p, cuda(f))
+    bgk.check_status()
+    Vr, Wr = oracle.moments(p, f)
+    assert rel_V(V.cpu().numpy(), Vr) < TOL
+    assert max(rel_W(Wg.cpu().numpy(), Wr)) < TOL
+
+    # n IMEX steps at a step size inside the stability bound
+    n_unit, dt1 = oracle.n_steps(p, 1.0)  # dt1 = 1 / n_unit: at most the stable step
+    dt = 0.9 * dt1
+    got = bgk.fine_steps(p, cuda(f), dt, n).cpu().numpy()
+    bgk.check_status()
+    assert rel_f(got, oracle.fine_steps(p, f, dt, n)) < TOL
+
+    # lift, n steps and projection of a few slices in one batched call
+    B = int(rng.integers(1, 4))
+    Vin = np.stack([conserved(draw_states(rng, p)[0]) for _ in range(B)])
+    span = n * dt1
+    out = bgk.fine_propagate_moments(p, cuda(Vin), span).cpu().numpy()
+    bgk.check_status()
+    for b in range(B):
+        assert rel_V(out[b], oracle.fine_propagate_moments(p, Vin[b], span)) < TOL
+
+
+@pytest.mark.parametrize("batch", range(4))
+def test_random_uneven_batch_matches_oracle(batch):
+    """Several drawn grids (some with odd v_z, some with free transport)
+    advanced over their own spans in one uneven batched call."""
+    rng = np.random.default_rng(SEED + 1000 + batch)
+    fusion = int(rng.integers(1, 5))
+    m = int(rng.integers(2, 7))
+    probs, fs, spans = [], [], []
+    for i in range(m):
+        p = draw_problem(rng, whole_planes=i % 2 == 1)
+        # the batched call takes eps in (0, inf]; keep every instance relaxing
+        # in half the cases
+        if batch % 2 == 0 and p.eps == float("inf"):
+            p = replace(p, eps=1e-2)
+        probs.append(p)
+        fs.append(draw_states(rng, p)[1])
+        _, dt1 = oracle.n_steps(p, 1.0)
+        spans.append(float(rng.integers(1, 9)) * dt1 * rng.uniform(0.7, 1.0))
+    print(f"batch {batch}: fusion={fusion} grids=" +
+          ", ".join(f"{p.nx}x{p.nv}" for p in probs), flush=True)
+    bgk.set_step_fusion(fusion)
+    outs, steps = bgk.fine_step_batched(probs, [cuda(f) for f in fs], spans)
+    bgk.check_status()
+    for q, p in enumerate(probs):
+        ref, n = oracle.fine_step(p, fs[q], spans[q])
+        assert int(steps[q]) == n
+        assert rel_f(outs[q].cpu().numpy(), ref) < TOL
