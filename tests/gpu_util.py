@@ -43,4 +43,11 @@ def rel_W(got, ref):
     return errs
 
 
+def rel_s(got, ref):
+    """Relative error of a scalar."""
+    e = float(abs(float(got) - float(ref)) / abs(float(ref)))
+    ERRORS.append(e)
+    return e
+
+
 TOL = 1e-12  # parity bar on f and moments (max norm, normwise relative)

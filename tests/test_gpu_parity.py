@@ -15,7 +15,7 @@ import torch
 import oracle
 from paper_2502_02704_amd import bgk
 from paper_2502_02704_amd import workloads as wl
-from tests.gpu_util import TOL, rel_f, rel_V, rel_W
+from tests.gpu_util import TOL, rel_f, rel_s, rel_V, rel_W
 
 pytestmark = pytest.mark.gpu
 
@@ -398,8 +398,11 @@ def test_fine_adjoint_matches_oracle(bc):
     w = np.random.default_rng(31).standard_normal(f0.shape)
     fb_ref, dle_ref = oracle.fine_adjoint(p, ck, every, n, dt, w)
     fb, dle = bgk.fine_adjoint(p, cuda(ck), every, n, dt, cuda(w))
-    assert rel_f(fb.cpu().numpy(), fb_ref) < 1e-11
-    assert abs(float(dle.cpu()) - dle_ref) < 1e-11 * abs(dle_ref)
+    e_fb = rel_f(fb.cpu().numpy(), fb_ref)
+    e_le = rel_s(dle.cpu(), dle_ref)
+    print(f"adjoint vs oracle: fbar_0 {e_fb:.2e}, log eps {e_le:.2e}")
+    assert e_fb < TOL
+    assert e_le < TOL
 
 
 @pytest.mark.parametrize("bc", [wl.BC_NEUMANN, wl.BC_PERIODIC])
@@ -415,8 +418,11 @@ def test_fine_adjoint_cell_sizes(bc, nv):
     w = np.random.default_rng(36).standard_normal(f0.shape)
     fb_ref, dle_ref = oracle.fine_adjoint(p, ck, every, n, dt, w)
     fb, dle = bgk.fine_adjoint(p, cuda(ck), every, n, dt, cuda(w))
-    assert rel_f(fb.cpu().numpy(), fb_ref) < 1e-11
-    assert abs(float(dle.cpu()) - dle_ref) < 1e-11 * abs(dle_ref)
+    e_fb = rel_f(fb.cpu().numpy(), fb_ref)
+    e_le = rel_s(dle.cpu(), dle_ref)
+    print(f"adjoint vs oracle: fbar_0 {e_fb:.2e}, log eps {e_le:.2e}")
+    assert e_fb < TOL
+    assert e_le < TOL
 
 
 def test_lift_and_density_adjoints():
@@ -601,7 +607,10 @@ def test_adjoint_workload_full_size_against_oracle_adjoint():
     every 16) against the oracle's FP64 adjoint: the oracle recomputes its own
     forward states, target and misfit adjoint, then applies its transposed
     steps and the lifting's adjoint; the gradients in rho0 (all 256 cells)
-    and log eps agree to 1e-10 normwise."""
+    and log eps agree to 1e-10 normwise.  The bar follows from the 1e-12 one:
+    the adjoint source is the misfit rho(T) - rho*(T) of two forward runs,
+    about 99 times smaller than rho here, so densities agreeing to 1e-12 of
+    rho bound the source and the gradients to about 1e-10."""
     from dataclasses import replace
     wk, rho0, eps_t, _ = wl.c4_adjoint()
     p = wk.problem

@@ -21,7 +21,7 @@ import torch
 import oracle
 from paper_2502_02704_amd import bgk
 from paper_2502_02704_amd import workloads as wl
-from tests.gpu_util import TOL, rel_f, rel_V, rel_W
+from tests.gpu_util import TOL, rel_f, rel_s, rel_V, rel_W
 
 pytestmark = pytest.mark.gpu
 
@@ -143,3 +143,105 @@ def test_random_uneven_batch_matches_oracle(batch):
         ref, n = oracle.fine_step(p, fs[q], spans[q])
         assert int(steps[q]) == n
         assert rel_f(outs[q].cpu().numpy(), ref) < TOL
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_force_and_second_order_match_oracle(case):
+    """Drawn grids with a drawn exterior force (step size from the force's
+    stability bound) under the first- and the second-order (van Leer
+    limited) x transport."""
+    rng = np.random.default_rng(SEED + 2000 + case)
+    p = draw_problem(rng, whole_planes=case % 3 == 0)
+    if p.eps == float("inf"):
+        p = replace(p, eps=1e-3)
+    E = rng.uniform(-2.0, 2.0, p.nx)
+    n = int(rng.integers(1, 7))
+    order = 1 + case % 2
+    use_force = case % 4 != 3
+    _, f = draw_states(rng, p)
+    print(f"case {case}: nx={p.nx} nv={p.nv} bc={p.bc} eps={p.eps:.3g} steps={n} "
+          f"order={order} force={use_force}", flush=True)
+    Ef = E if use_force else None
+    _, dt1 = oracle.n_steps(p, 1.0, E=Ef)
+    dt = 0.9 * dt1
+    got = bgk.fine_steps(p, cuda(f), dt, n, E=Ef, fine_order=order).cpu().numpy()
+    bgk.check_status()
+    ref = oracle.fine_steps_opts(p, f, dt, n, E=Ef, fine_order=order)
+    assert rel_f(got, ref) < TOL
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_coarse_steps_match_oracle(case):
+    """The Euler and Navier-Stokes coarse propagators on drawn grids and
+    drawn two-state data (bit-exact substep counts)."""
+    rng = np.random.default_rng(SEED + 3000 + case)
+    p = draw_problem(rng)
+    p = replace(p, nx=int(rng.integers(2, 1300)) if case % 4 == 0 else p.nx,
+                eps=float(10.0 ** rng.uniform(-5, 0)))
+    coarse = "cns" if case % 2 else "euler"
+    if coarse == "cns":
+        # the viscous step limit cfl dx^2 / (2 eps (5/3) theta) keeps the
+        # substep count in the thousands for eps <= 0.1
+        p = replace(p, eps=min(p.eps, 0.1))
+    B = int(rng.integers(1, 4))
+    Vin = []
+    for _ in range(B):
+        left = (rng.uniform(0.5, 1.5), rng.uniform(-0.3, 0.3), rng.uniform(-0.2, 0.2), 0.0,
+                rng.uniform(0.6, 1.2))
+        right = (rng.uniform(0.1, 0.6), rng.uniform(-0.3, 0.3), 0.0, rng.uniform(-0.2, 0.2),
+                 rng.uniform(0.5, 1.0))
+        Vin.append(conserved(wl.riemann_W0(p, left, right, rng.uniform(0.3, 0.7))))
+    Vin = np.stack(Vin)
+    span = rng.uniform(0.005, 0.05)
+    print(f"case {case}: nx={p.nx} bc={p.bc} eps={p.eps:.3g} batch={B} span={span:.4f} "
+          f"coarse={coarse}", flush=True)
+    got, nsub = bgk.euler_coarse_step(p, cuda(Vin), span, coarse=coarse)
+    bgk.check_status()
+    got, nsub = got.cpu().numpy(), nsub.cpu().numpy()
+    for b in range(B):
+        if coarse == "cns":
+            ref, nr = oracle.cns_coarse_step(p, Vin[b], span)
+        else:
+            ref, nr = oracle.euler_coarse_step(p, Vin[b], span)
+        assert int(nsub[b]) == nr
+        assert rel_V(got[b], ref) < TOL
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_random_lift_order_one_matches_oracle(case):
+    """The order-one (Chapman-Enskog) lifting of drawn moments on drawn grids."""
+    rng = np.random.default_rng(SEED + 4000 + case)
+    p = draw_problem(rng, whole_planes=case % 2 == 0)
+    p = replace(p, eps=float(10.0 ** rng.uniform(-5, -1)))
+    W, _ = draw_states(rng, p)
+    print(f"case {case}: nx={p.nx} nv={p.nv} bc={p.bc} eps={p.eps:.3g}", flush=True)
+    got = bgk.lift_ce(p, cuda(W)).cpu().numpy()
+    bgk.check_status()
+    assert rel_f(got, oracle.lift_ce(p, W)) < TOL
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_random_adjoint_matches_oracle(case):
+    """The adjoint of drawn step sequences (checkpoint intervals 1 to 4) on
+    drawn grids against the oracle's FP64 adjoint: f-bar at step 0 and the
+    log-eps gradient."""
+    rng = np.random.default_rng(SEED + 5000 + case)
+    p = draw_problem(rng, whole_planes=case % 4 == 0)
+    p = replace(p, nx=min(p.nx, 24), eps=float(10.0 ** rng.uniform(-4, 0)))
+    n = int(rng.integers(1, 9))
+    every = int(rng.integers(1, 5))
+    _, f0 = draw_states(rng, p)
+    _, dt1 = oracle.n_steps(p, 1.0)
+    dt = 0.9 * dt1
+    w = rng.standard_normal(f0.shape)
+    print(f"case {case}: nx={p.nx} nv={p.nv} bc={p.bc} eps={p.eps:.3g} steps={n} "
+          f"every={every}", flush=True)
+    ck, _ = oracle.checkpoints(p, f0, dt, n, every)
+    fb_ref, dle_ref = oracle.fine_adjoint(p, ck, every, n, dt, w)
+    fb, dle = bgk.fine_adjoint(p, cuda(ck), every, n, dt, cuda(w))
+    bgk.check_status()
+    e_fb = rel_f(fb.cpu().numpy(), fb_ref)
+    e_le = rel_s(dle.cpu(), dle_ref)
+    print(f"  fbar_0 {e_fb:.2e}, log eps {e_le:.2e}", flush=True)
+    assert e_fb < TOL
+    assert e_le < TOL
