@@ -10,7 +10,9 @@ infinite (free transport), one to seven IMEX steps under every step fusion
 setting (1 to 4 steps per pass) and tile shape.  Each case compares moments,
 fine steps and the batched lift-propagate-project call with the oracle at the
 1e-12 bar, and a batch of several drawn grids through the uneven batched call
-(bit-exact step counts).
+(bit-exact step counts).  Further drawn cases cover the exterior force and the
+second-order transport, the Euler and Navier-Stokes coarse steps (bit-exact
+substep counts), the order-one lifting, the adjoint and parareal.
 """
 from dataclasses import replace
 
@@ -245,3 +247,40 @@ def test_random_adjoint_matches_oracle(case):
     print(f"  fbar_0 {e_fb:.2e}, log eps {e_le:.2e}", flush=True)
     assert e_fb < TOL
     assert e_le < TOL
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_random_parareal_matches_oracle(case):
+    """Algorithm 2 on drawn grids and drawn two-state data: the Euler or
+    Navier-Stokes coarse model, the Maxwellian or order-one lifting, the
+    first- or second-order fine transport, 2 to 6 slices and 1 to 3
+    iterations (iterates at the 1e-12 bar, iteration count exact)."""
+    rng = np.random.default_rng(SEED + 6000 + case)
+    # resolved grids (8 to 14 points per axis over about [-6.5, 6.5]): the
+    # coarse model's states and the order-one lifting stay physical
+    nv = tuple(int(rng.integers(8, 15)) for _ in range(3))
+    if case % 4 == 0:
+        nv = (int(rng.integers(6, 11)), 16, 16)
+    c = rng.uniform(-0.3, 0.3, 3)
+    p = wl.Problem(nx=int(rng.integers(8, 49)), nv=nv, v_lo=tuple(c - 6.5),
+                   v_hi=tuple(c + 6.5), bc=int(rng.integers(0, 2)),
+                   eps=float(10.0 ** rng.uniform(-4, -2)))
+    left = (rng.uniform(0.6, 1.2), rng.uniform(-0.2, 0.2), 0.0, 0.0, rng.uniform(0.7, 1.1))
+    right = (rng.uniform(0.3, 0.7), rng.uniform(-0.2, 0.2), 0.0, 0.0, rng.uniform(0.6, 1.0))
+    W0 = wl.riemann_W0(p, left, right, rng.uniform(0.35, 0.65))
+    N = int(rng.integers(2, 7))
+    T = N * rng.uniform(0.002, 0.006)
+    K = int(rng.integers(1, 4))
+    coarse = "cns" if case % 2 else "euler"
+    lift_order = (case // 2) % 2
+    fine_order = 2 if case in (5, 6) else 1
+    print(f"case {case}: nx={p.nx} nv={p.nv} bc={p.bc} eps={p.eps:.3g} N={N} T={T:.4f} "
+          f"K={K} coarse={coarse} lift={lift_order} order={fine_order}", flush=True)
+    V, err, kd = bgk.parareal_iterate(p, cuda(W0), N, T, K, 0.0, coarse=coarse,
+                                      lift_order=lift_order, fine_order=fine_order)
+    bgk.check_status()
+    Vr, errr, kr = oracle.parareal_iterate_opts(p, W0, N, T, K, 0.0, coarse=coarse,
+                                                lift_order=lift_order, fine_order=fine_order)
+    assert kd == kr == K
+    assert rel_V(V.cpu().numpy(), Vr) < TOL
+    assert np.allclose(err, errr, rtol=1e-6, atol=1e-13)
