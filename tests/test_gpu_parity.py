@@ -156,6 +156,45 @@ def test_relaxation_extremes(eps):
     assert rel_f(got, oracle.fine_steps(p, f, dt, n)) < TOL
 
 
+# One velocity point on an axis (that velocity component is fixed; theta
+# comes from the other axes) and the two-point grid.  The last flag marks the
+# grids whose lifted propagation is well conditioned.  With a single v_y or
+# v_z point the one-point quadrature of that axis's Gaussian has weight
+# dv / sqrt(2 pi theta), not 1, so every lift and relaxation rescales the
+# mass by it; there the density grows to 1e8 within a span of 0.02 and
+# rounding is amplified 35 to 57 times (measured on the oracle), beyond what
+# a 1e-12 comparison can hold.  Moments and steps of a given field are well
+# conditioned on all four (amplification about 1).
+DEGENERATE_V = [((1, 6, 8), (0.2, -6, -7), (1.2, 6, 7), wl.BC_NEUMANN, True),
+                ((6, 1, 5), (-6, -0.5, -6), (6, 0.5, 6), wl.BC_PERIODIC, False),
+                ((5, 6, 1), (-6, -6, -0.3), (6, 6, 0.9), wl.BC_NEUMANN, False),
+                ((2, 2, 2), (-2, -2, -2), (2, 2, 2), wl.BC_PERIODIC, True)]
+
+
+@pytest.mark.parametrize("fusion", [1, 2, 3])
+@pytest.mark.parametrize("grid", range(len(DEGENERATE_V)))
+def test_degenerate_velocity_grids(grid, fusion):
+    nv, lo, hi, bc, lifted = DEGENERATE_V[grid]
+    p = wl.Problem(nx=17, nv=nv, v_lo=lo, v_hi=hi, bc=bc, eps=2e-2)
+    bgk.set_step_fusion(fusion)
+    _, f = states(p, 7)
+    V, W = bgk.moments(p, cuda(f))
+    Vr, Wr = oracle.moments(p, f)
+    assert rel_V(V.cpu().numpy(), Vr) < TOL
+    assert max(rel_W(W.cpu().numpy(), Wr)) < TOL
+    _, dt = oracle.n_steps(p, 0.01)
+    got = bgk.fine_steps(p, cuda(f), dt, 5).cpu().numpy()
+    bgk.check_status()
+    assert rel_f(got, oracle.fine_steps(p, f, dt, 5)) < TOL
+    if not lifted:
+        return
+    Vin = np.stack([V.cpu().numpy(), Vr])
+    out = bgk.fine_propagate_moments(p, cuda(Vin), 0.02).cpu().numpy()
+    bgk.check_status()
+    for b in range(2):
+        assert rel_V(out[b], oracle.fine_propagate_moments(p, Vin[b], 0.02)) < TOL
+
+
 def test_zero_steps_copies():
     p = GRIDS["asym_box"]
     _, f = states(p, 5)
