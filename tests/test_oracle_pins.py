@@ -799,6 +799,30 @@ class TestNavierStokesCoarse:
         rate = (np.log(b) - np.log(a)) / t
         assert abs(rate / (p.eps * lam) - 1) < 2e-3
 
+    def test_heat_flux_coefficient_over_one_substep(self):
+        # gas at rest (rho = 1, u = 0) with theta = 1 + A sin(2 pi x): over a
+        # span shorter than one substep both propagators take the same single
+        # Rusanov step, and the Navier-Stokes run differs only by the heat
+        # flux eps * kappa * d(theta)/dx with kappa = 5/2 rho theta; linearised,
+        # its energy change is -span * eps * (5/2) * lambda_h * A sin(2 pi x)
+        # (lambda_h as above), independent of the discretisation of the
+        # Rusanov part
+        p = wl.small_problem(nx=64, bc=wl.BC_PERIODIC, eps=0.01)
+        x = p.x_centres()
+        A = 1e-4
+        s = np.sin(2 * np.pi * x)
+        V = np.column_stack([1 + 0 * x, 0 * x, 0 * x, 0 * x, 1.5 * (1 + A * s)])
+        span = 1e-4
+        a, na = oracle.cns_coarse_step(p, V, span)
+        b, nb = oracle.euler_coarse_step(p, V, span)
+        assert na == nb == 1
+        dE = (a[:, 4] - b[:, 4]) @ s / (s @ s)
+        dx = 1.0 / p.nx
+        lam = (2 - 2 * np.cos(2 * np.pi * dx)) / dx ** 2
+        assert abs(dE / (-span * p.eps * 2.5 * lam * A) - 1) < 1e-6
+        # no momentum is created at rest
+        assert np.max(np.abs(a[:, 1:4] - b[:, 1:4])) < 1e-15
+
     def test_matches_numpy_substeps(self):
         p = wl.small_problem(nx=14, bc=wl.BC_NEUMANN, eps=0.05)
         x = p.x_centres()
