@@ -823,6 +823,29 @@ class TestNavierStokesCoarse:
         # no momentum is created at rest
         assert np.max(np.abs(a[:, 1:4] - b[:, 1:4])) < 1e-15
 
+    def test_viscous_work_is_the_velocity_times_the_viscous_stress(self):
+        # uniform rho and theta, u = U + small waves in all three components:
+        # over one shared Rusanov substep the Navier-Stokes run differs by the
+        # viscous fluxes only, and to first order in the waves the energy
+        # flux's work term equals U times the momentum fluxes (the stress
+        # (4/3 mu du_x, mu du_y, mu du_z) does work at the face velocity)
+        p = wl.small_problem(nx=64, bc=wl.BC_PERIODIC, eps=0.01)
+        x = p.x_centres()
+        A = 1e-4
+        U = np.array([0.4, -0.3, 0.25])
+        u = np.column_stack([U[0] + A * np.sin(2 * np.pi * x), U[1] + A * np.cos(2 * np.pi * x),
+                             U[2] + A * np.sin(4 * np.pi * x)])
+        rho, th = 1.0, 1.0
+        V = np.column_stack([rho + 0 * x, rho * u, rho * (0.5 * (u ** 2).sum(1) + 1.5 * th)])
+        span = 1e-3
+        a, na = oracle.cns_coarse_step(p, V, span)
+        b, nb = oracle.euler_coarse_step(p, V, span)
+        assert na == nb == 1
+        dm = a[:, 1:4] - b[:, 1:4]
+        dE = a[:, 4] - b[:, 4]
+        assert np.max(np.abs(dE)) > 0 and np.max(np.abs(dm[:, 0])) > 0
+        assert np.max(np.abs(dE - dm @ U)) < 1e-3 * np.max(np.abs(dE))
+
     def test_matches_numpy_substeps(self):
         p = wl.small_problem(nx=14, bc=wl.BC_NEUMANN, eps=0.05)
         x = p.x_centres()
